@@ -1,0 +1,1005 @@
+"""Seeded synthetic workloads for the batched Atari VCS emulator.
+
+This module produces *data only*: cartridge images built by a small 6502
+assembler, initial RAM bytes, joystick action streams, episode lengths and the
+soft-mode leaf tensors (ROM logits, RAM tape, action logits).  It executes no
+6502 code and contains none of the emulator's arithmetic; the reference
+emulator under ``oracle/`` and the GPU library both consume its outputs as plain
+arrays.
+
+The real cartridges the paper measures on (Pong for throughput, 64 ALE titles
+for conformance) are copyrighted and absent; seed-generated programs with the
+same sizes (2K, 4K and F8 bank-switched 8K), the same NTSC frame structure
+(3 VSYNC + 37 VBLANK + 192 kernel + 30 overscan lines of 76 CPU cycles) and the
+same kinds of work (playfield/background colour writes raced against the beam,
+RAM counters, decimal-mode arithmetic, subroutines, input and timer reads)
+stand in for them.
+
+Randomness is SplitMix64 (Steele, Lea & Flood, "Fast splittable pseudorandom
+number generators", OOPSLA 2014) used in counter mode:
+``value(key, i) = mix64(key + (i + 1) * GOLDEN)``; Gaussian noise is Box-Muller
+in float64.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+M64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+
+# --------------------------------------------------------------------------
+# SplitMix64
+# --------------------------------------------------------------------------
+
+
+def mix64(z: int) -> int:
+    """SplitMix64 output function (variant 13 finaliser)."""
+    z &= M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+def mix64_np(z: np.ndarray) -> np.ndarray:
+    z = z.astype(np.uint64, copy=True)
+    with np.errstate(over="ignore"):
+        z ^= z >> np.uint64(30)
+        z *= np.uint64(0xBF58476D1CE4E5B9)
+        z ^= z >> np.uint64(27)
+        z *= np.uint64(0x94D049BB133111EB)
+        z ^= z >> np.uint64(31)
+    return z
+
+
+def stream_key(seed: int, *ids: int) -> int:
+    """Derive an independent stream key from a seed and integer ids."""
+    k = seed & M64
+    for i in ids:
+        k = mix64((k + ((int(i) + 1) * GOLDEN)) & M64)
+    return k
+
+
+def u64_stream(key: int, n: int, start: int = 0) -> np.ndarray:
+    idx = np.arange(start + 1, start + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(key) + idx * np.uint64(GOLDEN)
+    return mix64_np(z)
+
+
+def byte_stream(key: int, n: int) -> np.ndarray:
+    words = u64_stream(key, (n + 7) // 8)
+    return words.view(np.uint8)[:n].copy()  # little-endian bytes of each word
+
+
+def unit_stream(key: int, n: int) -> np.ndarray:
+    """Uniform float64 in [0, 1) from the top 53 bits."""
+    return (u64_stream(key, n) >> np.uint64(11)).astype(np.float64) * (1.0 / (1 << 53))
+
+
+def int_stream(key: int, n: int, hi: int) -> np.ndarray:
+    """Uniform integers in [0, hi) (53-bit float scaling; bias < 2^-40)."""
+    return np.floor(unit_stream(key, n) * hi).astype(np.int64)
+
+
+def normal_stream(key: int, n: int) -> np.ndarray:
+    """Standard normal float64 via Box-Muller (one output per uniform pair)."""
+    u = unit_stream(key, 2 * n)
+    u1 = 1.0 - u[0::2]  # (0, 1]
+    u2 = u[1::2]
+    return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * math.pi * u2)
+
+
+class Rng:
+    """Sequential SplitMix64 for the program generator's decisions."""
+
+    def __init__(self, seed: int):
+        self.state = seed & M64
+
+    def next(self) -> int:
+        self.state = (self.state + GOLDEN) & M64
+        return mix64(self.state)
+
+    def randint(self, lo: int, hi: int) -> int:
+        """Uniform integer in [lo, hi]."""
+        return lo + (self.next() >> 11) * (hi - lo + 1) // (1 << 53)
+
+    def random(self) -> float:
+        return (self.next() >> 11) * (1.0 / (1 << 53))
+
+    def choice(self, seq):
+        return seq[self.randint(0, len(seq) - 1)]
+
+    def weighted(self, items):
+        tot = sum(w for _, w in items)
+        r = self.random() * tot
+        for it, w in items:
+            r -= w
+            if r < 0:
+                return it
+        return items[-1][0]
+
+
+# --------------------------------------------------------------------------
+# Minimal 6502 assembler (encoding only)
+# --------------------------------------------------------------------------
+
+# (mnemonic, addressing mode) -> opcode byte, from the public MOS 6502 opcode
+# matrix.  The last group are the undocumented forms the paper's opcode set
+# includes (LAX, SAX, the NOP family and the $EB alias of SBC #imm).
+_OPC_ROWS = """
+ADC imm 69 zp 65 zpx 75 abs 6D abx 7D aby 79 izx 61 izy 71
+AND imm 29 zp 25 zpx 35 abs 2D abx 3D aby 39 izx 21 izy 31
+ASL acc 0A zp 06 zpx 16 abs 0E abx 1E
+BCC rel 90
+BCS rel B0
+BEQ rel F0
+BMI rel 30
+BNE rel D0
+BPL rel 10
+BVC rel 50
+BVS rel 70
+BIT zp 24 abs 2C
+BRK imp 00
+CLC imp 18
+CLD imp D8
+CLI imp 58
+CLV imp B8
+CMP imm C9 zp C5 zpx D5 abs CD abx DD aby D9 izx C1 izy D1
+CPX imm E0 zp E4 abs EC
+CPY imm C0 zp C4 abs CC
+DEC zp C6 zpx D6 abs CE abx DE
+DEX imp CA
+DEY imp 88
+EOR imm 49 zp 45 zpx 55 abs 4D abx 5D aby 59 izx 41 izy 51
+INC zp E6 zpx F6 abs EE abx FE
+INX imp E8
+INY imp C8
+JMP abs 4C ind 6C
+JSR abs 20
+LDA imm A9 zp A5 zpx B5 abs AD abx BD aby B9 izx A1 izy B1
+LDX imm A2 zp A6 zpy B6 abs AE aby BE
+LDY imm A0 zp A4 zpx B4 abs AC abx BC
+LSR acc 4A zp 46 zpx 56 abs 4E abx 5E
+NOP imp EA
+ORA imm 09 zp 05 zpx 15 abs 0D abx 1D aby 19 izx 01 izy 11
+PHA imp 48
+PHP imp 08
+PLA imp 68
+PLP imp 28
+ROL acc 2A zp 26 zpx 36 abs 2E abx 3E
+ROR acc 6A zp 66 zpx 76 abs 6E abx 7E
+RTI imp 40
+RTS imp 60
+SBC imm E9 zp E5 zpx F5 abs ED abx FD aby F9 izx E1 izy F1
+SEC imp 38
+SED imp F8
+SEI imp 78
+STA zp 85 zpx 95 abs 8D abx 9D aby 99 izx 81 izy 91
+STX zp 86 zpy 96 abs 8E
+STY zp 84 zpx 94 abs 8C
+TAX imp AA
+TAY imp A8
+TSX imp BA
+TXA imp 8A
+TXS imp 9A
+TYA imp 98
+LAX zp A7 zpy B7 abs AF aby BF izx A3 izy B3
+SAX zp 87 zpy 97 abs 8F izx 83
+USBC imm EB
+"""
+
+OPCODES: dict[tuple[str, str], int] = {}
+for _row in _OPC_ROWS.strip().splitlines():
+    _f = _row.split()
+    for _i in range(1, len(_f), 2):
+        OPCODES[(_f[0], _f[_i])] = int(_f[_i + 1], 16)
+
+# Undocumented NOPs by mode (opcode bytes).
+NOP_IMP = [0x1A, 0x3A, 0x5A, 0x7A, 0xDA, 0xFA]
+NOP_IMM = [0x80, 0x82, 0x89, 0xC2, 0xE2]
+NOP_ZP = [0x04, 0x44, 0x64]
+NOP_ZPX = [0x14, 0x34, 0x54, 0x74, 0xD4, 0xF4]
+NOP_ABS = [0x0C]
+NOP_ABX = [0x1C, 0x3C, 0x5C, 0x7C, 0xDC, 0xFC]
+
+_MODE_LEN = {"imp": 1, "acc": 1, "imm": 2, "zp": 2, "zpx": 2, "zpy": 2, "rel": 2,
+             "izx": 2, "izy": 2, "abs": 3, "abx": 3, "aby": 3, "ind": 3}
+
+# Conservative cycle estimates used only to keep each scan line's code inside
+# its 76-cycle budget (upper bounds: page-crossing and taken-branch penalties
+# included).  Exact timing is the emulator's business, not the generator's.
+_RMW = {"ASL", "LSR", "ROL", "ROR", "INC", "DEC"}
+_STORE = {"STA", "STX", "STY", "SAX"}
+
+
+def est_cycles(mn: str, mode: str) -> int:
+    if mode in ("imp", "acc"):
+        return {"PHA": 3, "PHP": 3, "PLA": 4, "PLP": 4, "RTS": 6, "RTI": 6,
+                "BRK": 7}.get(mn, 2)
+    if mode == "rel":
+        return 4
+    if mn == "JSR":
+        return 6
+    if mn == "JMP":
+        return 3 if mode == "abs" else 5
+    if mn in _RMW:
+        return {"zp": 5, "zpx": 6, "abs": 6, "abx": 7}[mode]
+    base = {"imm": 2, "zp": 3, "zpx": 4, "zpy": 4, "abs": 4, "abx": 5, "aby": 5,
+            "izx": 6, "izy": 6}[mode]
+    return base
+
+
+# TIA / RIOT register addresses used by the generated programs.
+VSYNC, VBLANK, WSYNC = 0x00, 0x01, 0x02
+COLUP0, COLUP1, COLUPF, COLUBK, CTRLPF = 0x06, 0x07, 0x08, 0x09, 0x0A
+PF0, PF1, PF2 = 0x0D, 0x0E, 0x0F
+INPT4 = 0x0C
+SWCHA, INTIM, TIM64T = 0x280, 0x284, 0x296
+
+
+class Bank:
+    """One 4 KB (or 2 KB) code window assembled at CPU base address ``base``."""
+
+    def __init__(self, size: int, base: int, fill: bytes):
+        self.size = size
+        self.base = base
+        self.img = bytearray(fill)
+        self.pos = 0
+        self.labels: dict[str, int] = {}
+        self.fix: list[tuple[int, str, str]] = []
+        self.used = bytearray(size)
+
+    # -- placement
+    def at(self, off: int):
+        self.pos = off
+
+    def addr(self) -> int:
+        return self.base + self.pos
+
+    def label(self, name: str):
+        assert name not in self.labels, name
+        self.labels[name] = self.addr()
+
+    def byte(self, *bs: int):
+        for b in bs:
+            assert 0 <= self.pos < self.size, "bank overflow"
+            assert not self.used[self.pos], f"overlap at {self.pos:#x}"
+            self.img[self.pos] = b & 0xFF
+            self.used[self.pos] = 1
+            self.pos += 1
+
+    def ins(self, mn: str, mode: str = "imp", arg=None) -> int:
+        """Emit one instruction; returns the bank offset of its first operand byte."""
+        op = OPCODES[(mn, mode)]
+        self.byte(op)
+        operand_at = self.pos
+        n = _MODE_LEN[mode] - 1
+        if n == 0:
+            return operand_at
+        if isinstance(arg, str):
+            self.fix.append((self.pos, mode, arg))
+            self.byte(*([0] * n))
+        else:
+            v = int(arg)
+            if n == 1:
+                self.byte(v & 0xFF)
+            else:
+                self.byte(v & 0xFF, (v >> 8) & 0xFF)
+        return operand_at
+
+    def raw(self, opcode: int, *operand: int):
+        self.byte(opcode, *operand)
+
+    def link(self, extern: dict[str, int] | None = None):
+        for pos, mode, name in self.fix:
+            tgt = self.labels.get(name)
+            if tgt is None and extern is not None:
+                tgt = extern[name]
+            assert tgt is not None, name
+            if mode == "rel":
+                d = tgt - (self.base + pos + 1)
+                assert -128 <= d <= 127, f"branch out of range to {name}"
+                self.img[pos] = d & 0xFF
+            elif _MODE_LEN[mode] == 2:
+                self.img[pos] = tgt & 0xFF
+            else:
+                self.img[pos] = tgt & 0xFF
+                self.img[pos + 1] = (tgt >> 8) & 0xFF
+
+
+# --------------------------------------------------------------------------
+# Synthetic program generator
+# --------------------------------------------------------------------------
+
+MAPPER_2K, MAPPER_4K, MAPPER_F8 = 0, 1, 2
+MAPPER_OF_SIZE = {2048: MAPPER_2K, 4096: MAPPER_4K, 8192: MAPPER_F8}
+
+LINE_BODY_BUDGET = 56  # cycles of per-line work before STA WSYNC
+
+
+@dataclass
+class Rom:
+    seed: int
+    size: int
+    mapper: int
+    image: np.ndarray                      # uint8 [size]
+    colour_imm: list[int] = field(default_factory=list)  # image offsets of LDA #imm feeding only COLUBK/COLUPF
+    reads_inputs: bool = False
+
+
+class _Gen:
+    def __init__(self, seed: int, size: int, reads_inputs: bool, timer_vblank: bool):
+        self.r = Rng(stream_key(seed, 0x524F4D))
+        self.seed = seed
+        self.size = size
+        self.mapper = MAPPER_OF_SIZE[size]
+        self.inputs = reads_inputs
+        self.timer = timer_vblank
+        self.bank_size = 2048 if size == 2048 else 4096
+        base = 0xF800 if size == 2048 else 0xF000
+        nb = 2 if size == 8192 else 1
+        fill = byte_stream(stream_key(seed, 0x46494C), size)
+        self.banks = [Bank(self.bank_size, base, bytes(fill[i * self.bank_size:(i + 1) * self.bank_size]))
+                      for i in range(nb)]
+        self.colour_imm: list[tuple[int, int]] = []  # (bank, offset)
+        self.n_label = 0
+        # RAM plan: variables in $80-$DF, pointers at $E0-$E3, stack from $FF down.
+        self.vars = sorted({0x80 + self.r.randint(0, 0x5F) for _ in range(24)})
+        self.colour_vars = self.vars[: max(4, len(self.vars) // 3)]
+
+    def lab(self, stem: str) -> str:
+        self.n_label += 1
+        return f"{stem}_{self.n_label}"
+
+    def var(self) -> int:
+        return self.r.choice(self.vars)
+
+    def colour(self) -> int:
+        return self.r.randint(0, 127) * 2
+
+    # -- snippets: each returns (estimated cycles); emits into bank b
+    def snip_kernel(self, b: Bank, bi: int, tables: dict) -> int:
+        r = self.r
+        kind = r.weighted([
+            ("bk_imm", 10), ("pf_imm", 8), ("col_imm", 10), ("pf_tab", 8), ("col_tab", 6),
+            ("col_ram", 8), ("tya_eor", 4), ("incdec", 6), ("adc", 3), ("sbc", 3), ("dec_adc", 3),
+            ("logic", 3), ("shift", 3), ("eor_col", 3), ("branch", 6), ("bit_branch", 3),
+            ("illegal", 4), ("indexed", 3), ("indirect", 3 if "ptr" in tables else 0),
+            ("stack", 2), ("ctrlpf", 3), ("score_col", 2), ("cmp_branch", 2),
+        ])
+        c = 0
+        if kind == "bk_imm" or kind == "col_imm":
+            reg = COLUBK if kind == "bk_imm" else COLUPF
+            off = b.ins("LDA", "imm", self.colour())
+            self.colour_imm.append((bi, off))
+            b.ins("STA", "zp", reg)
+            c = 5
+        elif kind == "pf_imm":
+            b.ins("LDA", "imm", r.randint(0, 255))
+            b.ins("STA", "zp", r.choice([PF0, PF1, PF2]))
+            c = 5
+        elif kind == "pf_tab":
+            b.ins("LDA", "aby", tables["pf"])
+            b.ins("STA", "zp", r.choice([PF0, PF1, PF2]))
+            c = 7
+        elif kind == "col_tab":
+            b.ins("LDA", "aby", tables["col"])
+            b.ins("STA", "zp", r.choice([COLUPF, COLUBK]))
+            c = 7
+        elif kind == "col_ram":
+            b.ins("LDA", "zp", r.choice(self.colour_vars))
+            b.ins("STA", "zp", r.choice([COLUPF, COLUBK]))
+            c = 6
+        elif kind == "tya_eor":
+            b.ins("TYA")
+            b.ins("EOR", "zp", self.var())
+            b.ins("STA", "zp", COLUPF)
+            c = 8
+        elif kind == "incdec":
+            b.ins(r.choice(["INC", "DEC"]), "zp", self.var())
+            c = 5
+        elif kind == "adc":
+            v = self.var()
+            b.ins("LDA", "zp", v)
+            b.ins("CLC")
+            b.ins("ADC", "imm", r.randint(0, 255))
+            b.ins("STA", "zp", v)
+            c = 10
+        elif kind == "sbc":
+            v = self.var()
+            b.ins("SEC")
+            b.ins("LDA", "zp", v)
+            b.ins("SBC", "zp", self.var())
+            b.ins("STA", "zp", v)
+            c = 10
+        elif kind == "dec_adc":
+            v = self.var()
+            b.ins("SED")
+            b.ins(r.choice(["CLC", "SEC"]))
+            b.ins("LDA", "zp", v)
+            if r.random() < 0.5:
+                b.ins("ADC", "imm", r.randint(0, 255))
+            else:
+                b.ins("SBC", "zp", self.var())
+            b.ins("STA", "zp", v)
+            b.ins("CLD")
+            c = 15
+        elif kind == "logic":
+            v = self.var()
+            b.ins("LDA", "zp", v)
+            b.ins("AND", "imm", r.randint(0, 255))
+            b.ins("ORA", "zp", self.var())
+            b.ins("STA", "zp", v)
+            c = 11
+        elif kind == "shift":
+            b.ins(r.choice(["ASL", "LSR", "ROL", "ROR"]), "zp", self.var())
+            c = 5
+        elif kind == "eor_col":
+            b.ins("LDA", "zp", self.var())
+            b.ins("EOR", "imm", r.randint(0, 255))
+            b.ins("STA", "zp", COLUPF)
+            c = 8
+        elif kind == "branch":
+            skip = self.lab("sk")
+            b.ins("LDA", "zp", self.var())
+            b.ins("AND", "imm", 1 << r.randint(0, 7))
+            b.ins(r.choice(["BEQ", "BNE"]), "rel", skip)
+            off = b.ins("LDA", "imm", self.colour())
+            self.colour_imm.append((bi, off))
+            b.ins("STA", "zp", COLUPF)
+            b.label(skip)
+            c = 15
+        elif kind == "bit_branch":
+            skip = self.lab("bb")
+            b.ins("BIT", "zp", self.var())
+            b.ins(r.choice(["BMI", "BPL", "BVC", "BVS"]), "rel", skip)
+            b.ins("INC", "zp", self.var())
+            b.label(skip)
+            c = 12
+        elif kind == "cmp_branch":
+            skip = self.lab("cb")
+            b.ins("LDA", "zp", self.var())
+            b.ins("CMP", "imm", r.randint(0, 255))
+            b.ins(r.choice(["BCC", "BCS"]), "rel", skip)
+            b.ins("DEC", "zp", self.var())
+            b.label(skip)
+            c = 14
+        elif kind == "illegal":
+            sub = r.randint(0, 4)
+            if sub == 0:
+                b.ins("LAX", "zp", self.var())
+                b.ins("STX", "zp", COLUPF)
+                c = 6
+            elif sub == 1:
+                b.ins("LDX", "imm", r.randint(0, 255))
+                b.ins("SAX", "zp", self.var())
+                c = 5
+            elif sub == 2:
+                b.raw(r.choice(NOP_IMP))
+                b.raw(r.choice(NOP_IMM), r.randint(0, 255))
+                c = 4
+            elif sub == 3:
+                b.raw(r.choice(NOP_ZP), self.var())
+                b.raw(r.choice(NOP_ZPX), self.var())
+                c = 7
+            else:
+                b.ins("LDA", "zp", self.var())
+                b.ins("USBC", "imm", r.randint(0, 255))
+                b.ins("STA", "zp", self.var())
+                c = 8
+        elif kind == "indexed":
+            b.ins("LDX", "imm", r.randint(0, 15))
+            b.ins("LDA", "zpx", r.choice(self.colour_vars))
+            b.ins("STA", "zp", r.choice([COLUBK, COLUPF]))
+            c = 9
+        elif kind == "indirect":
+            b.ins("LDA", "izy", 0xE0)
+            b.ins("STA", "zp", r.choice([PF1, PF2]))
+            c = 9
+        elif kind == "stack":
+            b.ins("PHA")
+            b.ins("LDA", "zp", self.var())
+            b.ins("PLA")
+            c = 10
+        elif kind == "ctrlpf":
+            b.ins("LDA", "imm", r.choice([0x00, 0x01, 0x02, 0x03, 0x05]))
+            b.ins("STA", "zp", CTRLPF)
+            c = 5
+        elif kind == "score_col":
+            b.ins("LDA", "imm", self.colour())
+            b.ins("STA", "zp", r.choice([COLUP0, COLUP1]))
+            c = 5
+        return c
+
+    def snip_logic(self, b: Bank, bi: int, budget: int) -> int:
+        """Frame-logic work (VBLANK / overscan); no WSYNC inside."""
+        r = self.r
+        used = 0
+        while True:
+            kinds = [("incdec", 6), ("adc", 4), ("dec_adc", 3), ("logic", 3), ("shift", 3),
+                     ("lax", 1), ("nop", 1), ("colvar", 3)]
+            if self.inputs:
+                kinds += [("swcha", 4), ("inpt4", 4), ("intim", 2)]
+            kind = r.weighted(kinds)
+            cost = {"incdec": 5, "adc": 10, "dec_adc": 15, "logic": 11, "shift": 5, "lax": 6,
+                    "nop": 5, "colvar": 10, "swcha": 12, "inpt4": 12, "intim": 7}[kind]
+            if used + cost > budget:
+                return used
+            used += cost
+            if kind == "incdec":
+                b.ins(r.choice(["INC", "DEC"]), "zp", self.var())
+            elif kind == "adc":
+                v = self.var()
+                b.ins("LDA", "zp", v)
+                b.ins(r.choice(["CLC", "SEC"]))
+                b.ins(r.choice(["ADC", "SBC"]), "imm", r.randint(0, 255))
+                b.ins("STA", "zp", v)
+            elif kind == "dec_adc":
+                v = self.var()
+                b.ins("SED")
+                b.ins("CLC")
+                b.ins("LDA", "zp", v)
+                b.ins(r.choice(["ADC", "SBC"]), "imm", r.randint(0, 255))
+                b.ins("STA", "zp", v)
+                b.ins("CLD")
+            elif kind == "logic":
+                v = self.var()
+                b.ins("LDA", "zp", v)
+                b.ins(r.choice(["AND", "ORA", "EOR"]), "zp", self.var())
+                b.ins(r.choice(["AND", "ORA", "EOR"]), "imm", r.randint(0, 255))
+                b.ins("STA", "zp", v)
+            elif kind == "shift":
+                b.ins(r.choice(["ASL", "LSR", "ROL", "ROR"]), "zp", self.var())
+            elif kind == "lax":
+                b.ins("LAX", "zp", self.var())
+                b.ins("STA", "zp", self.var())
+            elif kind == "nop":
+                b.raw(r.choice(NOP_IMP))
+                b.raw(r.choice(NOP_ZP), self.var())
+            elif kind == "colvar":
+                v = r.choice(self.colour_vars)
+                b.ins("LDA", "zp", v)
+                b.ins("CLC")
+                b.ins("ADC", "imm", 2 * r.randint(1, 8))
+                b.ins("STA", "zp", v)
+            elif kind == "swcha":
+                v = r.choice(self.colour_vars)
+                b.ins("LDA", "abs", SWCHA)
+                b.ins("AND", "imm", 0xF0)
+                b.ins("EOR", "zp", v)
+                b.ins("STA", "zp", v)
+            elif kind == "inpt4":
+                skip = self.lab("f")
+                b.ins("LDA", "zp", INPT4)
+                b.ins("BMI", "rel", skip)
+                b.ins("INC", "zp", r.choice(self.colour_vars))
+                b.label(skip)
+            elif kind == "intim":
+                b.ins("LDA", "abs", INTIM)
+                b.ins("STA", "zp", self.var())
+
+    def build(self) -> Rom:
+        r = self.r
+        nb = len(self.banks)
+        bs = self.bank_size
+        kb = self.banks[0]         # bank holding the kernel, overscan and tables
+        mb = self.banks[-1]        # bank holding the reset target, VSYNC and VBLANK
+        self._pending_subs = []
+        # page-aligned data tables near the top of the kernel bank
+        tables = {}
+        tab_bytes = byte_stream(stream_key(self.seed, 0x544142), 512)
+        tbl_pf_off = bs - 0x300 if bs == 4096 else bs - 0x200
+        kb.at(tbl_pf_off)
+        tables["pf"] = kb.addr()
+        for i in range(256):
+            kb.byte(int(tab_bytes[i]))
+        if bs == 4096:
+            kb.at(bs - 0x200)
+            tables["col"] = kb.addr()
+            for i in range(256):
+                kb.byte(int(tab_bytes[256 + i]) & 0xFE)
+        else:
+            tables["col"] = tables["pf"]
+        if r.random() < 0.6:
+            tables["ptr"] = tables["pf"]
+
+        # fixed offsets near the top of every bank
+        t_to0 = bs - 0x40          # main bank: LDA $1FF8 ; kernel bank at +3: JMP KERNEL
+        t_to1 = bs - 0x30          # kernel bank: LDA $1FF9 ; main bank at +3: JMP FRAME
+        reset_off = bs - 0x20
+        frame_addr = mb.base       # FRAME is assembled at offset 0 of the main bank
+
+        # identical reset stubs in every bank, so the power-on bank is unobservable
+        for b in self.banks:
+            b.at(reset_off)
+            b.label("RESET")
+            b.ins("SEI")
+            b.ins("CLD")
+            b.ins("LDX", "imm", 0xFF)
+            b.ins("TXS")
+            if nb == 2:
+                b.ins("LDA", "abs", 0x1FF9)
+            b.ins("JMP", "abs", frame_addr)
+
+        # ---- main bank: VSYNC + VBLANK
+        b = mb
+        bi = nb - 1
+        b.at(0)
+        b.label("FRAME")
+        assert b.addr() == frame_addr
+        b.ins("LDA", "imm", 0x02)
+        b.ins("STA", "zp", VBLANK)
+        b.ins("STA", "zp", VSYNC)
+        for _ in range(3):
+            b.ins("STA", "zp", WSYNC)
+        b.ins("LDA", "imm", 0x00)
+        b.ins("STA", "zp", VSYNC)
+        for reg in (COLUP0, COLUP1):  # score-mode colours
+            b.ins("LDA", "imm", self.colour())
+            b.ins("STA", "zp", reg)
+        if "ptr" in tables:
+            b.ins("LDA", "imm", tables["ptr"] & 0xFF)
+            b.ins("STA", "zp", 0xE0)
+            b.ins("LDA", "imm", tables["ptr"] >> 8)
+            b.ins("STA", "zp", 0xE1)
+        if self.timer:
+            # INTIM reaches 0 after (44 - 1) * 64 + 64 cycles ~ 36.2 lines
+            b.ins("LDA", "imm", 44)
+            b.ins("STA", "abs", TIM64T)
+            for _ in range(r.randint(6, 14)):
+                self.snip_logic(b, bi, 60)
+            self._extras(b, bi)
+            w = self.lab("w")
+            b.label(w)
+            b.ins("LDA", "abs", INTIM)
+            b.ins("BNE", "rel", w)
+        else:
+            # line 0: the setup above; line 1: subroutine/BRK/indirect extras;
+            # then frame-logic lines, then a WSYNC loop for the rest of VBLANK
+            nlog = r.randint(3, 7)
+            for i in range(nlog):
+                if i == 1:
+                    self._extras(b, bi)
+                elif i > 1:
+                    self.snip_logic(b, bi, 55)
+                b.ins("STA", "zp", WSYNC)
+            b.ins("LDX", "imm", 37 - nlog - 1)
+            lp = self.lab("vbl")
+            b.label(lp)
+            b.ins("STA", "zp", WSYNC)
+            b.ins("DEX")
+            b.ins("BNE", "rel", lp)
+        # the last VBLANK line is ended by the STA WSYNC at KERNEL
+        if nb == 2:
+            b.ins("JMP", "abs", b.base + t_to0)
+            main_end = b.pos
+            b.at(t_to0)
+            b.ins("LDA", "abs", 0x1FF8)
+            kb.at(t_to0 + 3)
+            kb.ins("JMP", "abs", "KERNEL")
+            kb.at(t_to1)
+            kb.ins("LDA", "abs", 0x1FF9)
+            b.at(t_to1 + 3)
+            b.ins("JMP", "abs", frame_addr)
+            k = kb
+            k.at(0)
+        else:
+            main_end = None
+            k = b
+        kbi = 0
+        k.label("KERNEL")
+        k.ins("STA", "zp", WSYNC)
+        k.ins("LDA", "imm", 0x00)
+        k.ins("STA", "zp", VBLANK)
+        # ---- kernel: bands of identical line bodies, 192 lines in total
+        nbands = r.randint(2, 5)
+        cuts = sorted({r.randint(8, 184) for _ in range(nbands - 1)})
+        edges = [0] + cuts + [192]
+        lines = [e1 - e0 for e0, e1 in zip(edges, edges[1:]) if e1 > e0]
+        for n in lines:
+            k.ins("LDY", "imm", n)
+            lp = self.lab("band")
+            k.label(lp)
+            used = 0
+            while True:
+                save = (k.pos, len(k.fix), len(self.colour_imm), self.n_label, dict(k.labels),
+                        bytes(k.used), bytes(k.img))
+                c = self.snip_kernel(k, kbi, tables)
+                if used + c > LINE_BODY_BUDGET:
+                    pos, nf, nc, nl, labs, usedb, imgb = save
+                    k.pos = pos
+                    del k.fix[nf:]
+                    del self.colour_imm[nc:]
+                    self.n_label = nl
+                    k.labels = labs
+                    k.used = bytearray(usedb)
+                    k.img = bytearray(imgb)
+                    break
+                used += c
+                if used > LINE_BODY_BUDGET - 5:
+                    break
+            k.ins("STA", "zp", WSYNC)
+            k.ins("DEY")
+            k.ins("BNE", "rel", lp)
+        # ---- overscan: 30 lines
+        k.ins("LDA", "imm", 0x02)
+        k.ins("STA", "zp", VBLANK)
+        self.snip_logic(k, kbi, 50)
+        k.ins("STA", "zp", WSYNC)
+        k.ins("LDX", "imm", 29)
+        lp = self.lab("os")
+        k.label(lp)
+        k.ins("STA", "zp", WSYNC)
+        k.ins("DEX")
+        k.ins("BNE", "rel", lp)
+        if nb == 2:
+            k.ins("JMP", "abs", k.base + t_to1)
+        else:
+            k.ins("JMP", "abs", frame_addr)
+        # ---- subroutines and the BRK handler after the code of their bank
+        ends = {kbi: k.pos}
+        if main_end is not None:
+            ends[nb - 1] = main_end
+        for bank_i, name, body in self._pending_subs:
+            bb = self.banks[bank_i]
+            bb.at(ends[bank_i])
+            bb.label(name)
+            body(bb)
+            ends[bank_i] = bb.pos
+        # ---- vectors (reset at $FFFC, IRQ/BRK at $FFFE)
+        for bb in self.banks:
+            bb.at(bs - 4)
+            rs = bb.labels["RESET"]
+            bb.byte(rs & 0xFF, rs >> 8)
+            brk = bb.labels.get("BRKH", rs)
+            bb.byte(brk & 0xFF, brk >> 8)
+        for bb in self.banks:
+            bb.link()
+        img = np.frombuffer(b"".join(bytes(bb.img) for bb in self.banks), dtype=np.uint8).copy()
+        assert img.size == self.size
+        offs = [bi2 * bs + off for bi2, off in self.colour_imm]
+        return Rom(seed=self.seed, size=self.size, mapper=self.mapper, image=img,
+                   colour_imm=offs, reads_inputs=self.inputs)
+
+    def _extras(self, b: Bank, bi: int):
+        """Occasional subroutine call, BRK/RTI round trip and indirect jump."""
+        r = self.r
+        if r.random() < 0.8:
+            name = self.lab("sub")
+            v = self.var()
+            inc = r.choice(["INC", "DEC"])
+            acc = self.vars[0]
+
+            def body(bb, v=v, inc=inc, acc=acc):
+                bb.ins(inc, "zp", v)
+                bb.ins("LDA", "zp", v)
+                bb.ins("ROL", "acc")
+                bb.ins("EOR", "zp", acc)
+                bb.ins("STA", "zp", acc)
+                bb.ins("RTS")
+            b.ins("JSR", "abs", name)
+            self._pending_subs.append((bi, name, body))
+        if r.random() < 0.4 and "BRKH" not in b.labels:
+            v = self.var()
+
+            def brk_body(bb, v=v):
+                bb.ins("INC", "zp", v)
+                bb.ins("RTI")
+            b.ins("BRK")
+            b.byte(0xEA)  # padding byte skipped by the pushed return address
+            self._pending_subs.append((bi, "BRKH", brk_body))
+        if r.random() < 0.4:
+            tgt = self.lab("ij")
+            lo_at = b.ins("LDA", "imm", 0)
+            b.ins("STA", "zp", 0xE2)
+            hi_at = b.ins("LDA", "imm", 0)
+            b.ins("STA", "zp", 0xE3)
+            b.ins("JMP", "ind", 0x00E2)
+            b.label(tgt)
+            t = b.labels[tgt]
+            b.img[lo_at] = t & 0xFF
+            b.img[hi_at] = t >> 8
+
+
+def generate_rom(seed: int, size: int = 4096, *, reads_inputs: bool = False,
+                 timer_vblank: bool = False) -> Rom:
+    """Assemble one synthetic cartridge (2048, 4096 or 8192 bytes)."""
+    assert size in (2048, 4096, 8192)
+    return _Gen(seed, size, reads_inputs, timer_vblank).build()
+
+
+def perturb_rom(rom: Rom, seed: int, n: int = 8) -> np.ndarray:
+    """Copy of the image with ``n`` seeded colour immediates replaced by new even bytes.
+
+    Only immediates of ``LDA #imm`` that feed a ``STA COLUBK`` / ``STA COLUPF``
+    are touched, so control flow is unchanged and only colours differ.
+    """
+    img = rom.image.copy()
+    cand = list(rom.colour_imm)
+    r = Rng(stream_key(seed, 0x505254, rom.seed))
+    chosen = []
+    while cand and len(chosen) < n:
+        chosen.append(cand.pop(r.randint(0, len(cand) - 1)))
+    for off in chosen:
+        old = int(img[off])
+        new = old
+        while new == old:
+            new = r.randint(0, 127) * 2
+        img[off] = new
+    return img
+
+
+# --------------------------------------------------------------------------
+# Per-env data
+# --------------------------------------------------------------------------
+
+N_ACTIONS = 18
+
+
+def initial_ram(seed: int, num_envs: int) -> np.ndarray:
+    """Uniform random power-on RAM, uint8 [B][128]."""
+    return byte_stream(stream_key(seed, 0x52414D), num_envs * 128).reshape(num_envs, 128)
+
+
+def action_stream(seed: int, num_envs: int, steps: int) -> np.ndarray:
+    """Uniform joystick actions over the 18 ALE actions, uint8 [B][S]."""
+    return int_stream(stream_key(seed, 0x414354), num_envs * steps, N_ACTIONS).astype(np.uint8).reshape(num_envs, steps)
+
+
+def episode_steps(seed: int, num_envs: int, total_steps: int, frame_skip: int,
+                  mean_frames: float = 1500.0) -> np.ndarray:
+    """Episode lengths in env-steps, uint32 [B][E].
+
+    Frames per episode are Geometric(p = 1/mean_frames) on {1, 2, ...}
+    (inverse-CDF sampling); an episode ends after ceil(L / frame_skip) steps.
+    Enough episodes are drawn for every env to cover ``total_steps``.
+    """
+    p = 1.0 / mean_frames
+    lp = math.log1p(-p)
+    cols = []
+    covered = np.zeros(num_envs, dtype=np.int64)
+    e = 0
+    while (covered < total_steps).any() or e == 0:
+        u = unit_stream(stream_key(seed, 0x455049, e), num_envs)
+        frames = np.maximum(1, np.ceil(np.log1p(-u) / lp)).astype(np.int64)
+        st = (frames + frame_skip - 1) // frame_skip
+        cols.append(st)
+        covered += st
+        e += 1
+    return np.stack(cols, axis=1).astype(np.uint32)
+
+
+# --------------------------------------------------------------------------
+# Soft-mode leaves
+# --------------------------------------------------------------------------
+
+
+def rom_logits(image: np.ndarray, seed: int, sigma: float = 0.1) -> np.ndarray:
+    """float32 [size][256]: one-hot of the ROM bytes plus N(0, sigma^2) noise."""
+    n = image.size
+    noise = normal_stream(stream_key(seed, 0x4C4F47), n * 256).reshape(n, 256) * sigma
+    out = noise
+    out[np.arange(n), image.astype(np.int64)] += 1.0
+    return out.astype(np.float32)
+
+
+def ram_tape(ram0: np.ndarray) -> np.ndarray:
+    """float32 [B][128][256]: one-hot content rows of the initial RAM bytes."""
+    b = ram0.shape[0]
+    t = np.zeros((b, 128, 256), dtype=np.float32)
+    t[np.arange(b)[:, None], np.arange(128)[None, :], ram0.astype(np.int64)] = 1.0
+    return t
+
+
+def action_logits(actions: np.ndarray, seed: int, sigma: float = 0.1) -> np.ndarray:
+    """float32 [B][S][18]: one-hot of the hard actions plus N(0, sigma^2) noise."""
+    b, s = actions.shape
+    noise = normal_stream(stream_key(seed, 0x414C47), b * s * N_ACTIONS).reshape(b, s, N_ACTIONS) * sigma
+    noise[np.arange(b)[:, None], np.arange(s)[None, :], actions.astype(np.int64)] += 1.0
+    return noise.astype(np.float32)
+
+
+# --------------------------------------------------------------------------
+# Workload configurations
+# --------------------------------------------------------------------------
+
+
+@dataclass
+class Workload:
+    name: str
+    roms: list[Rom]
+    env_rom: np.ndarray          # int32 [B]
+    ram0: np.ndarray             # uint8 [B][128]
+    actions: np.ndarray | None   # uint8 [B][S] or None (no input: NOOP)
+    steps: int
+    frame_skip: int
+    episode_steps: np.ndarray | None = None  # uint32 [B][E]
+    seed: int = 0
+
+    @property
+    def num_envs(self) -> int:
+        return int(self.env_rom.size)
+
+    def rom_concat(self) -> np.ndarray:
+        return np.concatenate([r.image for r in self.roms])
+
+    def rom_offsets(self) -> np.ndarray:
+        return np.cumsum([0] + [r.size for r in self.roms])[:-1].astype(np.int64)
+
+    def actions_or_noop(self) -> np.ndarray:
+        if self.actions is not None:
+            return self.actions
+        return np.zeros((self.num_envs, self.steps), dtype=np.uint8)
+
+
+def config_c0() -> Workload:
+    """1 instance, one 4 KB ROM, 60 frames at frame-skip 1, no input."""
+    rom = generate_rom(0, 4096)
+    return Workload("c0_single_4k_60f", [rom], np.zeros(1, np.int32), initial_ram(0, 1),
+                    None, steps=60, frame_skip=1, seed=0)
+
+
+def config_c1(num_envs: int = 4096, steps: int = 500) -> Workload:
+    """4096 instances of one 4 KB ROM, uniform actions, frame-skip 4, 2000 frames."""
+    rom = generate_rom(1, 4096)
+    return Workload("c1_batched_4k", [rom], np.zeros(num_envs, np.int32), initial_ram(1, num_envs),
+                    action_stream(1, num_envs, steps), steps=steps, frame_skip=4, seed=1)
+
+
+def c2_roms(n_roms: int = 64) -> list[Rom]:
+    sizes = [2048] * 21 + [4096] * 22 + [8192] * 21
+    sizes = sizes[:n_roms] if n_roms <= 64 else sizes * (n_roms // 64 + 1)
+    order = np.argsort(unit_stream(stream_key(2, 0x4D4958), len(sizes)), kind="stable")
+    sizes = [sizes[i] for i in order][:n_roms]
+    return [generate_rom(100 + i, sizes[i], reads_inputs=True, timer_vblank=True)
+            for i in range(n_roms)]
+
+
+def config_c2(envs_per_rom: int = 256, steps: int = 500, n_roms: int = 64) -> Workload:
+    """64 mixed ROMs x 256 envs, geometric episode lengths with in-run resets."""
+    roms = c2_roms(n_roms)
+    b = n_roms * envs_per_rom
+    env_rom = np.repeat(np.arange(n_roms, dtype=np.int32), envs_per_rom)
+    perm = np.argsort(unit_stream(stream_key(2, 0x50524D), b), kind="stable")
+    env_rom = env_rom[perm].astype(np.int32)
+    return Workload("c2_hetero_persistent", roms, env_rom, initial_ram(2, b),
+                    action_stream(2, b, steps), steps=steps, frame_skip=4,
+                    episode_steps=episode_steps(2, b, steps, 4), seed=2)
+
+
+def config_c3(num_envs: int = 256) -> Workload:
+    """Soft small: 256 envs of the C1 ROM, 2 frames at frame-skip 1."""
+    rom = generate_rom(1, 4096)
+    return Workload("c3_soft_small", [rom], np.zeros(num_envs, np.int32), initial_ram(3, num_envs),
+                    action_stream(3, num_envs, 2), steps=2, frame_skip=1, seed=3)
+
+
+def config_c4(envs_per_rom: int = 64, steps: int = 60, n_roms: int = 64) -> Workload:
+    """Soft at scale: the heterogeneous ROM mix x 64 envs, 60 frames, no resets."""
+    roms = c2_roms(n_roms)
+    b = n_roms * envs_per_rom
+    env_rom = np.repeat(np.arange(n_roms, dtype=np.int32), envs_per_rom)
+    return Workload("c4_soft_scale", roms, env_rom, initial_ram(4, b),
+                    action_stream(4, b, steps), steps=steps, frame_skip=1, seed=4)
+
+
+@dataclass
+class SoftLeaves:
+    rom_logits: np.ndarray       # float32 [sum sizes][256]
+    ram_tape: np.ndarray         # float32 [B][128][256]
+    action_logits: np.ndarray    # float32 [B][S][18]
+    perturbed_roms: list[np.ndarray]
+
+
+def soft_leaves(w: Workload, seed: int | None = None) -> SoftLeaves:
+    s = w.seed if seed is None else seed
+    logits = np.concatenate([rom_logits(r.image, stream_key(s, 0x4C, i)) for i, r in enumerate(w.roms)])
+    return SoftLeaves(rom_logits=logits, ram_tape=ram_tape(w.ram0),
+                      action_logits=action_logits(w.actions_or_noop(), s),
+                      perturbed_roms=[perturb_rom(r, s) for r in w.roms])
+
+
+CONFIGS = {"c0": config_c0, "c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}

@@ -1,0 +1,315 @@
+"""Pins of the reference emulator's SOFT mode.
+
+Independent checks: the paper's printed gate-derivative values, closed-form
+gradients of hand-assembled programs derived from the surrogate rules by hand,
+structural zeros, numpy softmax statistics, the closed form of the softmax
+Jacobian product, and central finite differences of the SMOOTH relaxation.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_22447_amd import inputs as I
+from tests import asm as A
+
+N_PIX = 210 * 160
+
+
+def lum(c):
+    return (np.asarray(c).astype(np.int64) >> 1) & 7
+
+
+def loss_and_grad(frame_hard, frame_smooth, target):
+    """L = mean((lum - lum_t)^2) with the straight-through luminance: forward
+    lum_h + (c_s - c_h)/2 and d lum / d c = 1/2."""
+    l = lum(frame_hard) + (frame_smooth - frame_hard) / 2.0
+    d = l - lum(target)
+    return float((d ** 2).mean()), (2.0 * d / N_PIX) * 0.5
+
+
+# --------------------------------------------------------------------------
+# gate (Eq. branch) and its derivative: the paper's operating point z = 0.25
+# --------------------------------------------------------------------------
+
+def test_gate_gradient_values_printed_in_the_paper():
+    vals = {a: O.gate_grad(0.25, a) for a in (2, 6, 20)}
+    assert vals[2] == pytest.approx(0.470007, abs=1e-6)
+    assert vals[6] == pytest.approx(0.894879, abs=1e-6)
+    assert vals[20] == pytest.approx(0.132961, abs=1e-6)
+    peak = max(vals.values())
+    # relative peaks printed as 0.53, 1.00, 0.15
+    assert [round(vals[a] / peak, 2) for a in (2, 6, 20)] == [0.53, 1.00, 0.15]
+    # saturation: the gate is the exact hard branch in the alpha -> inf limit
+    assert O.gate(1.0, 200.0) == 1.0 and O.gate(-1.0, 200.0) < 1e-80
+
+
+# --------------------------------------------------------------------------
+# decode statistics vs numpy; epilogue (explicit Jacobian) vs closed forms
+# --------------------------------------------------------------------------
+
+def _softmax(x, tau):
+    z = (x - x.max(axis=-1, keepdims=True)) / tau
+    e = np.exp(z)
+    return e / e.sum(axis=-1, keepdims=True)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.1, 1e-3])
+def test_decode_and_epilogue_closed_forms(tau):
+    rom = I.generate_rom(7, 2048)
+    L = I.rom_logits(rom.image, 11)[:300]
+    hard, ev, mx, z = O.decode_logits(L, tau)
+    w = _softmax(L.astype(np.float64), tau)
+    k = np.arange(256.0)
+    assert (hard == rom.image[:300]).all()
+    assert np.allclose(ev, (w * k).sum(axis=1), rtol=1e-12, atol=1e-9)
+    g = np.linspace(-1.0, 2.0, 300)
+    got = O.epilogue_rom(L, tau, g)
+    closed = g[:, None] * w * (k[None, :] - ev[:, None]) / tau
+    assert np.allclose(got, closed, rtol=1e-9, atol=1e-12 * max(1.0, 1.0 / tau))
+
+    tape = np.random.default_rng(0).random((50, 256)).astype(np.float32)
+    th, tev = O.decode_tape(tape)
+    assert (th == tape.argmax(axis=1)).all() and np.allclose(tev, tape.astype(np.float64) @ k)
+    g0 = np.arange(50.0)
+    assert np.allclose(O.epilogue_tape(g0), g0[:, None] * k[None, :])
+
+    acts = I.action_logits(I.action_stream(5, 6, 7), 5).reshape(-1, 18)
+    ah, es, ei = O.decode_actions(acts, tau)
+    sw = np.array([O.action_ports(a)[0] for a in range(18)], np.float64)
+    ip = np.array([O.action_ports(a)[1] for a in range(18)], np.float64)
+    wa = _softmax(acts.astype(np.float64), tau)
+    assert (ah == acts.argmax(axis=1)).all()
+    assert np.allclose(es, wa @ sw) and np.allclose(ei, wa @ ip)
+    gs, gi = np.linspace(-1, 1, 42), np.linspace(2, -3, 42)
+    got = O.epilogue_action(acts, tau, gs, gi)
+    closed = (wa / tau) * (gs[:, None] * (sw[None, :] - es[:, None]) + gi[:, None] * (ip[None, :] - ei[:, None]))
+    assert np.allclose(got, closed, rtol=1e-9, atol=1e-12 * max(1.0, 1.0 / tau))
+
+
+# --------------------------------------------------------------------------
+# closed-form gradients of straight-line programs
+# --------------------------------------------------------------------------
+
+def _soft_run(rom, ram0_hard, ram0_ev, steps=1, mode="ste", target=None, rom_ev=None, grad_ram=None,
+              actions=None, swcha_ev=None, inpt4_ev=None):
+    rom_ev = rom.astype(np.float64) if rom_ev is None else rom_ev
+    act = np.zeros(steps, np.uint8) if actions is None else actions
+    sw = np.array([O.action_ports(a)[0] for a in act], np.float64) if swcha_ev is None else swcha_ev
+    ip = np.array([O.action_ports(a)[1] for a in act], np.float64) if inpt4_ev is None else inpt4_ev
+    fwd = O.soft_env(rom, rom_ev, 1, ram0_hard, ram0_ev, act, sw, ip, steps, 1, mode=mode)
+    gf = None
+    if target is not None:
+        _, gf = loss_and_grad(fwd["frame"], fwd["frame_smooth"], target)
+    return O.soft_env(rom, rom_ev, 1, ram0_hard, ram0_ev, act, sw, ip, steps, 1, mode=mode, grad_frame=gf,
+                      grad_ram=grad_ram)
+
+
+def test_straight_line_colour_gradient():
+    # LDA #v ; STA COLUBK at the very start: all 33,600 visible pixels are v & $FE,
+    # so dL/d(byte v) = sum over pixels of (lum - lum_t)/N = lum(v) - lum(t).
+    for v, t in ((0x46, 0x1C), (0x0E, 0x0E), (0x80, 0xFE)):
+        rom = A.program(lambda b: (b.ins("LDA", "imm", v), b.ins("STA", "zp", A.COLUBK), b.byte(2)))
+        r = _soft_run(rom, np.zeros(128, np.uint8), np.zeros(128), target=np.full((210, 160), t, np.uint8))
+        assert (r["frame"] == (v & 0xFE)).all()
+        expect = float(lum(v) - lum(t))
+        assert r["g_rom"][1] == pytest.approx(expect, rel=1e-10, abs=1e-12)
+        # structural zeros: opcode bytes and the STA's address operand
+        nz = np.nonzero(r["g_rom"])[0].tolist()
+        assert nz == ([1] if expect != 0 else [])
+
+
+def test_chain_gradients_adc_asl_and_logic():
+    # LDA $80 ; CLC ; ADC #k ; ASL A ; STA COLUBK  -> colour = 2*(RAM0[0] + k) mod 256
+    # every visible pixel shares it, so with S = sum dL/dpixel:
+    #   dL/dRAM0[0] = 2*S and dL/d(byte k) = 2*S (ADC d=1, ASL d=2)
+    k = 0x13
+    rom = A.program(lambda b: (b.ins("LDA", "zp", 0x80), b.ins("CLC"), b.ins("ADC", "imm", k), b.ins("ASL", "acc"),
+                               b.ins("STA", "zp", A.COLUBK), b.byte(2)))
+    ram0 = np.zeros(128, np.uint8)
+    ram0[0] = 0x21
+    target = np.full((210, 160), 0x10, np.uint8)
+    r = _soft_run(rom, ram0, ram0.astype(np.float64), target=target)
+    c = (2 * (0x21 + k)) & 0xFF
+    s = float(lum(c & 0xFE) - lum(0x10))  # sum of dL/dpixel over all pixels
+    assert r["g_ram0"][0] == pytest.approx(2 * s, rel=1e-10)
+    assert r["g_rom"][4] == pytest.approx(2 * s, rel=1e-10)  # ADC's immediate is image byte 4
+
+    # LDA $80 ; AND #m ; EOR $81 ; STA COLUPF with PF on everywhere:
+    #   c = (a & m) ^ b;  STE: dc/da = (m/255) * (255 - 2b)/255, dc/dm = (a/255)(255-2b)/255,
+    #   dc/db = (255 - 2(a&m))/255; the AND immediate is image byte 11
+    m_ = 0x5C
+
+    def body(b):
+        b.ins("LDA", "imm", 0xFF)
+        for reg in (A.PF0, A.PF1, A.PF2):
+            b.ins("STA", "zp", reg)
+        b.ins("LDA", "zp", 0x80)
+        b.ins("AND", "imm", m_)
+        b.ins("EOR", "zp", 0x81)
+        b.ins("STA", "zp", A.COLUPF)
+        b.byte(2)
+    rom = A.program(body)
+    ram0 = np.zeros(128, np.uint8)
+    ram0[0], ram0[1] = 0xB7, 0x3A
+    a, bb = 0xB7, 0x3A
+    c = (a & m_) ^ bb
+    target = np.full((210, 160), 0x00, np.uint8)
+    for mode in ("ste", "smooth"):
+        ev0 = ram0.astype(np.float64)
+        ev0[0] += 0.25 if mode == "smooth" else 0.0
+        r = _soft_run(rom, ram0, ev0, mode=mode, target=target)
+        fr_h, fr_s = r["frame"], r["frame_smooth"]
+        sgrad = (lum(fr_h) + (fr_s - fr_h) / 2.0 - lum(target)).sum() * (2.0 / N_PIX) * 0.5
+        a_val = a + (0.25 if mode == "smooth" else 0.0)
+        am = (a & m_) + (a_val - a) * m_ / 255.0  # smooth value of the AND node: hard + delta
+        d_eor_first = (255.0 - 2 * bb) / 255.0
+        assert r["g_ram0"][0] == pytest.approx(sgrad * (m_ / 255.0) * d_eor_first, rel=1e-12)
+        assert r["g_ram0"][1] == pytest.approx(sgrad * (255.0 - 2 * am) / 255.0, rel=1e-12)
+        assert r["g_rom"][11] == pytest.approx(sgrad * (a_val / 255.0) * d_eor_first, rel=1e-12)
+    assert c != 0
+
+
+def test_overwritten_ram_has_zero_gradient_and_ram_out_gradient():
+    # LDA #5 ; STA $80 ; LDA $80 ; STA COLUBK  -> RAM0[0] is overwritten before
+    # any read: its gradient is a structural zero; the immediate gets it all.
+    rom = A.program(lambda b: (b.ins("LDA", "imm", 5), b.ins("STA", "zp", 0x80), b.ins("LDA", "zp", 0x80),
+                               b.ins("STA", "zp", A.COLUBK), b.byte(2)))
+    ram0 = np.full(128, 9, np.uint8)
+    r = _soft_run(rom, ram0, ram0.astype(np.float64), target=np.full((210, 160), 0x40, np.uint8))
+    assert r["g_ram0"][0] == 0.0 and r["g_rom"][1] == pytest.approx(float(lum(4) - lum(0x40)))
+    # gradient through the RAM output: dL/dRAM_out[0][0] = 1 flows to the immediate,
+    # dL/dRAM_out[0][7] = 1 flows to the untouched RAM0 cell 7
+    gr = np.zeros((1, 128))
+    gr[0, 0] = 1.0
+    gr[0, 7] = 3.0
+    r = _soft_run(rom, ram0, ram0.astype(np.float64), grad_ram=gr)
+    assert r["g_rom"][1] == 1.0 and r["g_ram0"][7] == 3.0 and r["g_ram0"][0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# generated workloads: Theorem 1 in the oracle, STE vs SMOOTH, finite differences
+# --------------------------------------------------------------------------
+
+def _c3_problem(tau, n_steps=2, rom_seed=1, size=4096, inputs=False, env_seed=3):
+    rom = I.generate_rom(rom_seed, size, reads_inputs=inputs, timer_vblank=inputs)
+    L = I.rom_logits(rom.image, I.stream_key(env_seed, 0x4C, 0))
+    ram0 = I.initial_ram(env_seed, 1)[0]
+    tape = I.ram_tape(ram0[None])[0]
+    acts = I.action_stream(env_seed, 1, n_steps)[0]
+    al = I.action_logits(acts[None], env_seed)[0]
+    pert = I.perturb_rom(rom, env_seed)
+    tgt = O.run_env(pert, rom.mapper, ram0, acts, n_steps, 1, frames="last")["frames"][0]
+    return rom, L, tape, al, tgt
+
+
+def _smooth_loss(rom, L, tape, al, tgt, tau, hard_rom, hard_ram, hard_act, n_steps):
+    _, ev, _, _ = O.decode_logits(L, tau)
+    _, ev0 = O.decode_tape(tape)
+    _, es, ei = O.decode_actions(al, tau)
+    r = O.soft_env(hard_rom, ev, rom.mapper, hard_ram, ev0, hard_act, es, ei, n_steps, 1, mode="smooth")
+    return loss_and_grad(r["frame"], r["frame_smooth"], tgt)[0]
+
+
+def _soft_grads(rom, L, tape, al, tgt, tau, mode, n_steps):
+    hard_rom, ev, _, _ = O.decode_logits(L, tau)
+    hard_ram, ev0 = O.decode_tape(tape)
+    hard_act, es, ei = O.decode_actions(al, tau)
+    fwd = O.soft_env(hard_rom, ev, rom.mapper, hard_ram, ev0, hard_act, es, ei, n_steps, 1, mode=mode)
+    _, gf = loss_and_grad(fwd["frame"], fwd["frame_smooth"], tgt)
+    r = O.soft_env(hard_rom, ev, rom.mapper, hard_ram, ev0, hard_act, es, ei, n_steps, 1, mode=mode, grad_frame=gf)
+    g_logits = O.epilogue_rom(L, tau, r["g_rom"])
+    g_tape = O.epilogue_tape(r["g_ram0"])
+    g_act = O.epilogue_action(al, tau, r["g_swcha"], r["g_inpt4"])
+    return r, (hard_rom, hard_ram, hard_act), g_logits, g_tape, g_act
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.1])
+def test_theorem1_soft_forward_equals_hard_in_the_oracle(tau):
+    rom, L, tape, al, tgt = _c3_problem(tau)
+    r, (hr, hm, ha), *_ = _soft_grads(rom, L, tape, al, tgt, tau, "ste", 2)
+    assert (hr == rom.image).all()
+    hard = O.run_env(rom.image, rom.mapper, hm, ha, 2, 1, frames="last")
+    assert (r["ram"] == hard["ram"]).all() and (r["frame"] == hard["frames"][0]).all()
+    assert (r["frame_smooth"] != r["frame"]).any()  # the soft values do differ from the hard ones
+
+
+def test_ste_equals_smooth_as_tau_goes_to_zero():
+    rom, L, tape, al, tgt = _c3_problem(1e-3)
+    ste = _soft_grads(rom, L, tape, al, tgt, 1e-3, "ste", 2)
+    smo = _soft_grads(rom, L, tape, al, tgt, 1e-3, "smooth", 2)
+    for key in ("g_rom", "g_ram0"):
+        a, b = ste[0][key], smo[0][key]
+        assert np.allclose(a, b, rtol=1e-6, atol=1e-9 * np.abs(a).max())
+    assert np.abs(ste[0]["g_rom"]).max() > 0
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.1])
+def test_finite_differences_on_the_smooth_relaxation(tau):
+    rom, L, tape, al, tgt = _c3_problem(tau)
+    r, (hr, hm, ha), gL, gT, gA = _soft_grads(rom, L, tape, al, tgt, tau, "smooth", 2)
+    rows = np.argsort(-np.abs(r["g_rom"]))[:4]
+    assert np.abs(r["g_rom"][rows[0]]) > 0
+    h = 1e-3 if tau == 1.0 else 1e-4
+    checked = 0
+    for a in rows:
+        for k in (int(L[a].argmax()), int(np.argsort(-L[a])[1]), 0):
+            an = gL[a, k]
+            fd = _fd_rom(rom, L, tape, al, tgt, tau, hr, hm, ha, a, k, h)
+            if abs(an) < 1e-9 and abs(fd) < 1e-9:
+                continue
+            assert fd == pytest.approx(an, rel=2e-5, abs=1e-10), (a, k, fd, an)
+            checked += 1
+    assert checked >= 4
+    # RAM tape entries: ev0 = sum_k k P[k] is linear, so FD is exact up to rounding
+    cells = np.argsort(-np.abs(r["g_ram0"]))[:3]
+    for c in cells:
+        if r["g_ram0"][c] == 0:
+            continue
+        for k in (0, 17, 255):
+            fd = _fd_tape(rom, L, tape, al, tgt, tau, hr, hm, ha, c, k, 1e-3)
+            assert fd == pytest.approx(gT[c, k], rel=1e-5, abs=1e-10)
+
+
+def _fd_rom(rom, L, tape, al, tgt, tau, hr, hm, ha, a, k, h):
+    out = []
+    for sgn in (1, -1):
+        Lx = L.copy()
+        Lx[a, k] = np.float32(L[a, k] + sgn * h)
+        step = float(Lx[a, k]) - float(L[a, k])
+        out.append((_smooth_loss(rom, Lx, tape, al, tgt, tau, hr, hm, ha, 2), step))
+    (fp, sp), (fm, sm) = out
+    return (fp - fm) / (sp - sm)
+
+
+def _fd_tape(rom, L, tape, al, tgt, tau, hr, hm, ha, c, k, h):
+    out = []
+    for sgn in (1, -1):
+        T = tape.copy()
+        T[c, k] = np.float32(tape[c, k] + sgn * h)
+        out.append((_smooth_loss(rom, L, T, al, tgt, tau, hr, hm, ha, 2), float(T[c, k]) - float(tape[c, k])))
+    (fp, sp), (fm, sm) = out
+    return (fp - fm) / (sp - sm)
+
+
+def test_finite_differences_on_action_logits():
+    # a ROM that reads SWCHA/INPT4 into its colour variables
+    tau = 1.0
+    for seed in range(100, 110):
+        rom, L, tape, al, tgt = _c3_problem(tau, n_steps=3, rom_seed=seed, size=2048, inputs=True)
+        r, (hr, hm, ha), gL, gT, gA = _soft_grads(rom, L, tape, al, tgt, tau, "smooth", 3)
+        if np.abs(gA).max() > 1e-6:
+            break
+    else:
+        pytest.skip("no generated ROM in the range routes an input to the final frame")
+    s, j = np.unravel_index(np.argmax(np.abs(gA)), gA.shape)
+    h = 1e-3
+    vals = []
+    for sgn in (1, -1):
+        A2 = al.copy()
+        A2[s, j] = np.float32(al[s, j] + sgn * h)
+        vals.append((_smooth_loss(rom, L, tape, A2, tgt, tau, hr, hm, ha, 3), float(A2[s, j]) - float(al[s, j])))
+    fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+    assert fd == pytest.approx(gA[s, j], rel=2e-5)
+    assert math.isfinite(fd)
