@@ -1,0 +1,221 @@
+/*
+ * libvcs -- batched Atari VCS emulation on MI355X (gfx950), hard and soft
+ * (straight-through) forms, behind a plain C ABI.
+ *
+ * The operation is the paper's environment step: state + action -> next
+ * state, RAM and frame ("A Differentiable Atari VCS", Sec. "Building Two
+ * Differentiable VCS Ports" and Sec. "Evaluation Methodology"), for many
+ * independent instances in lockstep.  HARD mode is the bit-exact machine
+ * (Sec. "Hard and Soft Execution"); SOFT mode treats the ROM as a weight
+ * tensor, the RAM as a soft tape and branches as gates joined to the hard
+ * values by the straight-through estimator (Eq. peek, Eq. select, Eq. branch,
+ * Eq. ste), so its forward pass equals HARD (Theorem "Exact forward
+ * equivalence") and its backward pass is the surrogate gradient of the chosen
+ * relaxation (the Corollary after Theorem "Temperature-limit bound").
+ *
+ * Conventions
+ *  - Every function returns a vcs_status (0 = VCS_OK) and never throws.
+ *  - Pointers named d_* are DEVICE pointers (HIP device memory on the current
+ *    device), owned by the caller; the library allocates no device memory.
+ *    Work is enqueued asynchronously on the given stream (NULL = the default
+ *    stream); device buffers must stay valid until that work completes.
+ *    Pointers without the d_ prefix are host pointers, read synchronously.
+ *  - Argument errors are reported synchronously.  HIP launch errors are
+ *    reported as VCS_HIP_ERROR by the call that launched; errors raised while a
+ *    kernel runs surface on a later synchronising call of the caller's.
+ *  - An "env" is one emulated console.  Envs are independent; several envs may
+ *    share a ROM image (selected by env_rom[]).
+ *  - Frame layout: uint8 (hard) or float32 (soft) [210][160] row-major palette
+ *    indices; the visible window is scan lines [ystart, ystart+210) and colour
+ *    clocks 68..227 of each line.  Frames are cycle-framed: frame f covers CPU
+ *    cycles [f*19912, (f+1)*19912) since power-on (262 lines x 76 cycles).
+ *  - An env step applies one action for `frame_skip` frames and ends at the
+ *    first instruction boundary at or after the step's cycle budget.
+ *  - Actions are the 18 standard ALE joystick actions (0 = NOOP ... 17 =
+ *    DOWNLEFTFIRE).
+ */
+#ifndef VCS_H
+#define VCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VCS_ABI_VERSION 1
+
+typedef enum vcs_status {
+    VCS_OK = 0,
+    VCS_INVALID_ARG = -1,        /* a NULL/out-of-range argument or inconsistent sizes */
+    VCS_UNSUPPORTED = -2,        /* a valid request this build does not implement */
+    VCS_WORKSPACE_TOO_SMALL = -3,/* the caller's buffer is smaller than the size query returned */
+    VCS_HIP_ERROR = -4,          /* a HIP runtime call or kernel launch failed */
+    VCS_BAD_STATE_VERSION = -5   /* reserved: state produced by another ABI version */
+} vcs_status;
+
+/* Cartridge formats (Sec. "Building Two Differentiable VCS Ports": 2K, 4K and
+ * the F8 two-bank 8K scheme with hotspots $1FF8/$1FF9). */
+typedef enum vcs_mapper { VCS_MAPPER_2K = 0, VCS_MAPPER_4K = 1, VCS_MAPPER_F8 = 2 } vcs_mapper;
+
+/* Kernel family used for the emulation step. */
+typedef enum vcs_kernel {
+    VCS_KERNEL_AUTO = 0,    /* the tuned kernel (VCS_KERNEL_GROUPED unless told otherwise) */
+    VCS_KERNEL_PLAIN = 1,   /* one env per thread, RAM/ROM in global memory, per-lane dispatch */
+    VCS_KERNEL_GROUPED = 2  /* LDS-staged ROM and RAM, wave-uniform grouped dispatch, lane groups */
+} vcs_kernel;
+
+/* Frame output modes of vcs_step_hard. */
+typedef enum vcs_frames {
+    VCS_FRAMES_NONE = 0,    /* no frame written (d_frame_out may be NULL) */
+    VCS_FRAMES_LAST = 1,    /* d_frame_out is [B][210][160]: last frame of the last step */
+    VCS_FRAMES_ALL = 2      /* d_frame_out is [B][S][210][160]: last frame of every step */
+} vcs_frames;
+
+typedef struct vcs_config {
+    int32_t abi_version;        /* must be VCS_ABI_VERSION */
+    int32_t num_envs;           /* B >= 1 */
+    int32_t num_roms;           /* R >= 1 */
+    const int32_t *rom_size;    /* host [R]: 2048, 4096 or 8192 bytes */
+    const int32_t *rom_mapper;  /* host [R]: vcs_mapper matching the size */
+    const int32_t *env_rom;     /* host [B]: ROM index of each env */
+    int32_t frame_skip;         /* frames per env step, >= 1 */
+    int32_t ystart;             /* first visible scan line, 0..52 (34 is the usual value) */
+    uint64_t seed;              /* SplitMix64 seed of in-run reset RAM */
+    int32_t ckpt_interval;      /* soft backward: hard-state checkpoint every K cycles (>= 64) */
+    int32_t kernel;             /* vcs_kernel */
+    int32_t lanes_per_env;      /* GROUPED kernel: lanes cooperating on one env (1, 4 or 16; 0 = auto) */
+    int32_t block_threads;      /* GROUPED kernel: threads per workgroup (64 or 256; 0 = auto) */
+} vcs_config;
+
+typedef struct vcs_ctx vcs_ctx;
+
+/* Create a host-side context (configuration, launch geometry, env->workgroup
+ * grouping by ROM).  Allocates host memory only.  On error *out is NULL. */
+int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out);
+
+/* Release the context (host memory only).  NULL is accepted. */
+void vcs_destroy(vcs_ctx *ctx);
+
+/* Static text for a status code. */
+const char *vcs_status_string(int32_t status);
+
+/* Sizes of caller-allocated device buffers:
+ *  - state: B opaque 256-byte records (vcs_state_bytes = B*256);
+ *  - roms:  the concatenated ROM images (sum of rom_size[]) as uint8;
+ *  - workspace for op (VCS_OP_*) and S steps;
+ *  - soft residual (saved by the forward, read by the backward) for S steps;
+ *  - soft decode output (float32 statistics, layout in vcs_step_soft_fwd). */
+enum { VCS_OP_HARD = 0, VCS_OP_SOFT_FWD = 1, VCS_OP_SOFT_BWD = 2 };
+int32_t vcs_state_bytes(const vcs_ctx *ctx, size_t *bytes);
+int32_t vcs_rom_bytes(const vcs_ctx *ctx, size_t *bytes);
+int32_t vcs_workspace_bytes(const vcs_ctx *ctx, int32_t op, int32_t steps, size_t *bytes);
+int32_t vcs_residual_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes);
+int32_t vcs_decode_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes);
+
+/* Power-on reset of the envs selected by d_mask (uint8 [B], nonzero = reset;
+ * NULL = all).  RAM comes from d_ram0 (uint8 [B][128], 4-byte aligned) when
+ * given, otherwise from SplitMix64(seed, env, 0).  CPU: A=X=Y=0, S=$FD, P=$24,
+ * TIA registers 0, RIOT timer as if written with 0 at cycle -1 with interval
+ * 1024 and its flag clear, episode and step counters 0.  The PC is loaded from
+ * the reset vector of the power-on bank (bank 1 for F8) by the next step call,
+ * which has the ROM; until then vcs_read_regs shows PC = 0 and status bit 1
+ * (power-on pending).  d_state: [B][256] bytes, 16-byte aligned. */
+int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint8_t *d_ram0, hipStream_t stream);
+
+/* HARD env steps (Sec. "Hard and Soft Execution", hard mode), in place on
+ * d_state:
+ *  d_rom          uint8 [sum rom_size]: ROM images concatenated in ROM order;
+ *  d_state        [B][256] opaque records, updated in place;
+ *  d_actions      uint8 [B][S] action per env step (NULL = NOOP);
+ *  steps          S >= 1;
+ *  d_ram_out      uint8 [B][S][128] RAM after each step (NULL = not written);
+ *  frames, d_frame_out  see vcs_frames;
+ *  d_done         uint8 [B][S]: 1 when the step ended the env's episode
+ *                 (NULL = not written);
+ *  d_episode_steps uint32 [B][E] episode lengths in env steps (NULL = no
+ *                 episodes): when an env has taken d_episode_steps[b][e] steps
+ *                 in episode e < E it is reset in-run (power-on, RAM =
+ *                 SplitMix64(seed, env, e+1)) and the next step starts the new
+ *                 episode;
+ *  d_work         workspace of vcs_workspace_bytes(VCS_OP_HARD). */
+int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                      uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
+                      const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream);
+
+/* SOFT-STE forward of S env steps from power-on (Theorem "Exact forward
+ * equivalence": its values equal HARD at any tau and alpha).
+ *  d_rom_logits    float32 [sum rom_size][256]: ROM as a weight tensor; byte a
+ *                  = STE(sum_k k softmax(L[a]/tau)_k, argmax_k L[a]) (Eq. select
+ *                  over the byte values; lowest index on ties);
+ *  d_ram_tape      float32 [B][128][256]: initial RAM as a soft tape of content
+ *                  rows; cell c = STE(sum_k k P[c][k], argmax_k P[c][k]);
+ *  d_action_logits float32 [B][S][18]: per-step action scores; the ports read
+ *                  STE(E_softmax(l/tau)[port(a)], port(argmax l));
+ *  tau > 0; alpha > 0 is the branch-gate sharpness of Eq. branch (flags carry
+ *  no gradient in this relaxation, so alpha does not change the result);
+ *  d_ram_out       float32 [B][S][128] integer-valued RAM after each step;
+ *  d_frame_out     float32 [B][210][160] integer-valued final frame;
+ *  d_decode_out    float32 statistics (NULL = not written), in order:
+ *                  ROM rows [sum rom_size][3] = (expected byte, softmax max,
+ *                  softmax normaliser); tape [B][128] expected byte; actions
+ *                  [B][S][2] = (E[SWCHA], E[INPT4]);
+ *  d_state_out     [B][256] final hard state (NULL = not written);
+ *  d_residual      vcs_residual_bytes(S): saved for the backward;
+ *  d_work          vcs_workspace_bytes(VCS_OP_SOFT_FWD, S). */
+int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,
+                          const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
+                          float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
+                          void *d_work, hipStream_t stream);
+
+/* SOFT-STE backward: surrogate gradients of a loss given dL/d(final frame)
+ * (float32 [B][210][160]) and optionally dL/d(RAM out) (float32 [B][S][128],
+ * NULL = zero), for the forward whose residual is d_residual (same tau, alpha,
+ * inputs and S).  Recomputes each checkpoint segment from its hard-state
+ * checkpoint, records a tape and sweeps it in reverse; ROM gradients of envs
+ * sharing a ROM are summed in a fixed order (deterministic).
+ *  d_grad_rom_logits    float32 [sum rom_size][256]  (overwritten)
+ *  d_grad_ram_tape      float32 [B][128][256]         (overwritten)
+ *  d_grad_action_logits float32 [B][S][18]            (overwritten)
+ *  d_work               vcs_workspace_bytes(VCS_OP_SOFT_BWD, S). */
+int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_rom_logits,
+                          const float *d_ram_tape, const float *d_action_logits, float tau, float alpha,
+                          int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
+                          float *d_grad_rom_logits, float *d_grad_ram_tape, float *d_grad_action_logits,
+                          void *d_work, hipStream_t stream);
+
+/* Inspect: per-env registers into d_out uint8 [B][16] = A, X, Y, S, P, PCL,
+ * PCH, bank, status (bit0 jammed), INTIM now, TIMINT now, VBLANK, COLUP0,
+ * COLUP1, COLUPF, COLUBK. */
+int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream);
+
+/* Number of soft checkpoints the forward wrote for the largest env (host
+ * value; valid after the stream has completed the forward). */
+int32_t vcs_residual_checkpoints(const vcs_ctx *ctx, int32_t steps, int32_t *count);
+
+/* Soft-backward tape check: after the stream's work completes, *flag (host)
+ * = 1 when a recompute segment needed more tape records than the workspace for
+ * `steps` holds (that backward's gradients are then invalid), else 0.
+ * Synchronises the stream. */
+int32_t vcs_bwd_overflow(const vcs_ctx *ctx, const void *d_work, int32_t steps, hipStream_t stream,
+                         int32_t *flag);
+
+/* Launch geometry chosen at create time (host values; NULL outputs skipped):
+ * kernel family, lanes per env, threads per workgroup, step-kernel workgroups,
+ * soft-backward workgroups. */
+int32_t vcs_launch_info(const vcs_ctx *ctx, int32_t *kernel, int32_t *lanes_per_env, int32_t *block_threads,
+                        int32_t *blocks, int32_t *bwd_blocks);
+
+/* Introspection (host only, no GPU work): the library's decoded opcode table,
+ * out[256] = op class | mode << 6 | base cycles << 10 | page penalty << 13 |
+ * length << 14, with op class 0 for the 67 bytes that jam the CPU. */
+int32_t vcs_decode_table(uint32_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VCS_H */

@@ -1,0 +1,128 @@
+"""ctypes binding of libvcs (the C-ABI declared in ``include/vcs.h``).
+
+Argument marshalling only: every step of the emulation runs in the library's
+HIP kernels.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvcs.so")
+
+VCS_OK = 0
+VCS_MAPPER_2K, VCS_MAPPER_4K, VCS_MAPPER_F8 = 0, 1, 2
+VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED = 0, 1, 2
+VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
+VCS_OP_HARD, VCS_OP_SOFT_FWD, VCS_OP_SOFT_BWD = 0, 1, 2
+ABI_VERSION = 1
+STATE_BYTES = 256
+
+EXPORTED = [
+    "vcs_create", "vcs_destroy", "vcs_status_string", "vcs_state_bytes", "vcs_rom_bytes",
+    "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
+    "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
+    "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table",
+]
+
+
+class VcsConfig(C.Structure):
+    _fields_ = [
+        ("abi_version", C.c_int32), ("num_envs", C.c_int32), ("num_roms", C.c_int32),
+        ("rom_size", C.POINTER(C.c_int32)), ("rom_mapper", C.POINTER(C.c_int32)),
+        ("env_rom", C.POINTER(C.c_int32)), ("frame_skip", C.c_int32), ("ystart", C.c_int32),
+        ("seed", C.c_uint64), ("ckpt_interval", C.c_int32), ("kernel", C.c_int32),
+        ("lanes_per_env", C.c_int32), ("block_threads", C.c_int32),
+    ]
+
+
+class VcsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libvcs.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise VcsError(f"{LIB_PATH} is not built; run `python -m paper_2606_22447_amd.build` "
+                           "(or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, u64, sz = C.c_void_p, C.c_int32, C.c_uint64, C.c_size_t
+        f32 = C.c_float
+        L.vcs_create.argtypes = [C.POINTER(VcsConfig), C.POINTER(vp)]
+        L.vcs_destroy.argtypes = [vp]
+        L.vcs_destroy.restype = None
+        L.vcs_status_string.argtypes = [i32]
+        L.vcs_status_string.restype = C.c_char_p
+        for f in ("vcs_state_bytes", "vcs_rom_bytes"):
+            getattr(L, f).argtypes = [vp, C.POINTER(sz)]
+        L.vcs_workspace_bytes.argtypes = [vp, i32, i32, C.POINTER(sz)]
+        L.vcs_residual_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.vcs_decode_bytes.argtypes = [vp, i32, C.POINTER(sz)]
+        L.vcs_residual_checkpoints.argtypes = [vp, i32, C.POINTER(i32)]
+        L.vcs_reset.argtypes = [vp, vp, vp, vp, vp]
+        L.vcs_step_hard.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp, vp]
+        L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.vcs_step_soft_bwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.vcs_read_regs.argtypes = [vp, vp, vp, vp]
+        L.vcs_bwd_overflow.argtypes = [vp, vp, i32, vp, C.POINTER(i32)]
+        L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5
+        L.vcs_decode_table.argtypes = [C.POINTER(C.c_uint32)]
+        for f in EXPORTED:
+            fn = getattr(L, f)
+            if f not in ("vcs_destroy", "vcs_status_string"):
+                fn.restype = i32
+        del u64
+        _lib = L
+    return _lib
+
+
+def check(rc: int, what: str):
+    if rc != VCS_OK:
+        msg = lib().vcs_status_string(rc).decode()
+        raise VcsError(f"{what} failed: {msg} ({rc})")
+
+
+def ptr(t):
+    """Device (or host) address of a tensor/array, or None."""
+    if t is None:
+        return None
+    if hasattr(t, "data_ptr"):
+        return C.c_void_p(t.data_ptr())
+    return t.ctypes.data_as(C.c_void_p)
+
+
+def decode_table():
+    out = (C.c_uint32 * 256)()
+    check(lib().vcs_decode_table(out), "vcs_decode_table")
+    return list(out)
+
+
+def create(rom_sizes, rom_mappers, env_rom, frame_skip=4, ystart=34, seed=0, ckpt_interval=0,
+           kernel=VCS_KERNEL_AUTO, lanes_per_env=0, block_threads=0):
+    R, B = len(rom_sizes), len(env_rom)
+    sizes = (C.c_int32 * R)(*[int(v) for v in rom_sizes])
+    maps = (C.c_int32 * R)(*[int(v) for v in rom_mappers])
+    envr = (C.c_int32 * B)(*[int(v) for v in env_rom])
+    cfg = VcsConfig(ABI_VERSION, B, R, sizes, maps, envr, frame_skip, ystart, seed, ckpt_interval, kernel,
+                    lanes_per_env, block_threads)
+    h = C.c_void_p()
+    check(lib().vcs_create(C.byref(cfg), C.byref(h)), "vcs_create")
+    return h
+
+
+def size_query(fn, *args) -> int:
+    out = C.c_size_t()
+    check(getattr(lib(), fn)(*args, C.byref(out)), fn)
+    return out.value
+
+
+def launch_info(h):
+    vals = [C.c_int32() for _ in range(5)]
+    check(lib().vcs_launch_info(h, *[C.byref(v) for v in vals]), "vcs_launch_info")
+    return dict(zip(["kernel", "lanes_per_env", "block_threads", "blocks", "bwd_blocks"], [v.value for v in vals]))

@@ -1,0 +1,511 @@
+// C-ABI of libvcs (declared in include/vcs.h): argument validation, launch
+// geometry and the layout of caller-owned device buffers.
+#include <algorithm>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/vcs.h"
+#include "vcs_core.hpp"
+#include "vcs_kernels.hpp"
+
+using namespace vcs;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+}  // namespace
+
+struct vcs_ctx {
+    int32_t B = 0, R = 0, F = 1, ystart = 34, K = 1024, kernel = VCS_KERNEL_GROUPED, G = 1, tpb = 256;
+    uint64_t seed = 0;
+    std::vector<int32_t> rom_size, rom_mapper, env_rom, rom_off;
+    int32_t max_rom = 0, total_rom = 0;
+    int32_t main_E = 0, main_blocks = 0, bwd_blocks = 0;
+    std::vector<int32_t> main_block_rom, main_slot_env;
+    std::vector<int32_t> bwd_block_rom, bwd_slot_env, env_bwd_slot, rom_bwd_begin, rom_bwd_end;
+    StaticHdr hdr{};
+    std::vector<uint8_t> image;  // host image of the static device region
+    uint8_t *pinned = nullptr;   // pinned copy, made on the first upload
+    size_t blob_bytes = 0;
+    ~vcs_ctx() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+namespace {
+
+// Layout of the soft residual for S steps.
+struct ResidualLayout {
+    size_t rom_hard, ram0_hard, act_hard, stats, rom_stats, tape_ev, act_stats, ckpt_count, ckpt, bytes;
+    size_t stats_bytes;
+    int32_t max_ckpt;
+};
+ResidualLayout residual_layout(const vcs_ctx *c, int32_t S) {
+    ResidualLayout L{};
+    size_t o = kAlign;  // header
+    L.rom_hard = o;
+    o = align_up(o + (size_t)c->total_rom);
+    L.ram0_hard = o;
+    o = align_up(o + (size_t)c->B * 128);
+    L.act_hard = o;
+    o = align_up(o + (size_t)c->B * S);
+    L.stats = L.rom_stats = o;
+    L.tape_ev = L.rom_stats + (size_t)c->total_rom * 3 * sizeof(float);
+    L.act_stats = L.tape_ev + (size_t)c->B * 128 * sizeof(float);
+    L.stats_bytes = (size_t)c->total_rom * 3 * sizeof(float) + (size_t)c->B * 128 * sizeof(float) +
+                    (size_t)c->B * S * 2 * sizeof(float);
+    o = align_up(L.rom_stats + L.stats_bytes);
+    L.ckpt_count = o;
+    o = align_up(o + (size_t)c->B * sizeof(int32_t));
+    L.max_ckpt = (int32_t)(((int64_t)S * c->F * kCyclesPerFrame + 256) / c->K + 2);
+    L.ckpt = o;
+    o = align_up(o + (size_t)c->B * L.max_ckpt * sizeof(StateRec));
+    L.bytes = o;
+    return L;
+}
+
+// Layout of the soft-backward workspace (after the static region).
+struct BwdLayout {
+    size_t tape, gpart, gport, g0, overflow, bytes;
+    int32_t max_rec;
+    uint32_t nslots;
+};
+BwdLayout bwd_layout(const vcs_ctx *c, int32_t S) {
+    BwdLayout L{};
+    L.nslots = (uint32_t)c->bwd_blocks * kBwdSlots;
+    L.max_rec = c->K / 2 + 64 + c->K / kCyclesPerFrame + 4;
+    size_t o = align_up(c->blob_bytes);
+    L.tape = o;
+    o = align_up(o + (size_t)L.max_rec * L.nslots * sizeof(TapeRec));
+    L.gpart = o;
+    o = align_up(o + (size_t)c->max_rom * L.nslots * sizeof(float));
+    L.gport = o;
+    o = align_up(o + (size_t)c->B * S * 2 * sizeof(float));
+    L.g0 = o;
+    o = align_up(o + (size_t)c->B * 128 * sizeof(float));
+    L.overflow = o;
+    o = align_up(o + sizeof(int32_t));
+    L.bytes = o;
+    return L;
+}
+
+StaticPtrs static_ptrs(const vcs_ctx *c, const void *d_work) {
+    const uint8_t *b = (const uint8_t *)d_work;
+    const StaticHdr &h = c->hdr;
+    StaticPtrs p;
+    p.rom_off = (const int32_t *)(b + h.off_rom_off);
+    p.rom_size = (const int32_t *)(b + h.off_rom_size);
+    p.rom_mapper = (const int32_t *)(b + h.off_rom_mapper);
+    p.main_block_rom = (const int32_t *)(b + h.off_main_block_rom);
+    p.main_slot_env = (const int32_t *)(b + h.off_main_slot_env);
+    p.bwd_block_rom = (const int32_t *)(b + h.off_bwd_block_rom);
+    p.bwd_slot_env = (const int32_t *)(b + h.off_bwd_slot_env);
+    p.env_bwd_slot = (const int32_t *)(b + h.off_env_bwd_slot);
+    p.rom_bwd_slot_begin = (const int32_t *)(b + h.off_rom_bwd_slot_begin);
+    p.rom_bwd_slot_end = (const int32_t *)(b + h.off_rom_bwd_slot_end);
+    return p;
+}
+
+// Copy the static region (ROM table, env grouping) into the head of the
+// caller's workspace, ordered on the stream before the kernels that read it.
+int32_t upload_static(vcs_ctx *c, void *d_work, hipStream_t stream) {
+    if (!c->pinned) {
+        if (hipHostMalloc((void **)&c->pinned, c->blob_bytes, hipHostMallocDefault) != hipSuccess) {
+            c->pinned = nullptr;
+            return VCS_HIP_ERROR;
+        }
+        std::memcpy(c->pinned, c->image.data(), c->blob_bytes);
+    }
+    if (hipMemcpyAsync(d_work, c->pinned, c->blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return VCS_HIP_ERROR;
+    return VCS_OK;
+}
+
+int32_t hip_status(hipError_t e) { return e == hipSuccess ? VCS_OK : VCS_HIP_ERROR; }
+
+// Envs of every ROM packed into blocks of `per` slots that never mix ROMs.
+void group_by_rom(const vcs_ctx *c, int32_t per, std::vector<int32_t> &block_rom, std::vector<int32_t> &slot_env) {
+    block_rom.clear();
+    slot_env.clear();
+    for (int32_t r = 0; r < c->R; ++r) {
+        std::vector<int32_t> envs;
+        for (int32_t b = 0; b < c->B; ++b)
+            if (c->env_rom[b] == r) envs.push_back(b);
+        for (size_t i = 0; i < envs.size(); i += (size_t)per) {
+            block_rom.push_back(r);
+            for (int32_t j = 0; j < per; ++j)
+                slot_env.push_back(i + (size_t)j < envs.size() ? envs[i + (size_t)j] : -1);
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *vcs_status_string(int32_t status) {
+    switch (status) {
+        case VCS_OK: return "ok";
+        case VCS_INVALID_ARG: return "invalid argument";
+        case VCS_UNSUPPORTED: return "unsupported configuration";
+        case VCS_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case VCS_HIP_ERROR: return "HIP runtime error";
+        case VCS_BAD_STATE_VERSION: return "state record of another ABI version";
+        default: return "unknown status";
+    }
+}
+
+int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
+    if (!out) return VCS_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg || cfg->abi_version != VCS_ABI_VERSION) return VCS_INVALID_ARG;
+    if (cfg->num_envs < 1 || cfg->num_roms < 1 || !cfg->rom_size || !cfg->rom_mapper || !cfg->env_rom)
+        return VCS_INVALID_ARG;
+    if (cfg->frame_skip < 1 || cfg->frame_skip > 1000) return VCS_INVALID_ARG;
+    if (cfg->ystart < 0 || cfg->ystart + kScreenH > kLinesPerFrame) return VCS_INVALID_ARG;
+    if (cfg->ckpt_interval != 0 && (cfg->ckpt_interval < 64 || cfg->ckpt_interval > (1 << 24))) return VCS_INVALID_ARG;
+    vcs_ctx *c = new (std::nothrow) vcs_ctx();
+    if (!c) return VCS_INVALID_ARG;
+    c->B = cfg->num_envs;
+    c->R = cfg->num_roms;
+    c->F = cfg->frame_skip;
+    c->ystart = cfg->ystart;
+    c->seed = cfg->seed;
+    c->K = cfg->ckpt_interval ? cfg->ckpt_interval : 1024;
+    int64_t total = 0;
+    for (int32_t r = 0; r < c->R; ++r) {
+        const int32_t sz = cfg->rom_size[r], mp = cfg->rom_mapper[r];
+        const bool ok = (mp == VCS_MAPPER_2K && sz == 2048) || (mp == VCS_MAPPER_4K && sz == 4096) ||
+                        (mp == VCS_MAPPER_F8 && sz == 8192);
+        if (!ok) {
+            delete c;
+            return VCS_INVALID_ARG;
+        }
+        c->rom_size.push_back(sz);
+        c->rom_mapper.push_back(mp);
+        c->rom_off.push_back((int32_t)total);
+        total += sz;
+        c->max_rom = std::max(c->max_rom, sz);
+    }
+    if (total > (1 << 30)) {
+        delete c;
+        return VCS_INVALID_ARG;
+    }
+    c->total_rom = (int32_t)total;
+    for (int32_t b = 0; b < c->B; ++b) {
+        if (cfg->env_rom[b] < 0 || cfg->env_rom[b] >= c->R) {
+            delete c;
+            return VCS_INVALID_ARG;
+        }
+        c->env_rom.push_back(cfg->env_rom[b]);
+    }
+    // kernel family and lane grouping
+    c->kernel = cfg->kernel == VCS_KERNEL_AUTO ? VCS_KERNEL_GROUPED : cfg->kernel;
+    if (c->kernel != VCS_KERNEL_PLAIN && c->kernel != VCS_KERNEL_GROUPED) {
+        delete c;
+        return VCS_INVALID_ARG;
+    }
+    c->tpb = cfg->block_threads ? cfg->block_threads : 256;
+    if (c->tpb != 64 && c->tpb != 256) {
+        delete c;
+        return VCS_UNSUPPORTED;
+    }
+    if (c->kernel == VCS_KERNEL_PLAIN) {
+        c->G = 1;
+    } else if (cfg->lanes_per_env) {
+        c->G = cfg->lanes_per_env;
+        if (c->G != 1 && c->G != 4 && c->G != 16) {
+            delete c;
+            return VCS_UNSUPPORTED;
+        }
+    } else {
+        // enough lane groups to give every SIMD of the chip (1024 on MI355X) one wave
+        const int64_t lanes = (int64_t)c->B * 16;
+        c->G = lanes <= 1024 * 64 ? 16 : ((int64_t)c->B * 4 <= 1024 * 64 ? 4 : 1);
+    }
+    c->main_E = c->tpb / c->G;
+    group_by_rom(c, c->main_E, c->main_block_rom, c->main_slot_env);
+    c->main_blocks = (int32_t)c->main_block_rom.size();
+    group_by_rom(c, kBwdSlots, c->bwd_block_rom, c->bwd_slot_env);
+    c->bwd_blocks = (int32_t)c->bwd_block_rom.size();
+    c->env_bwd_slot.assign((size_t)c->B, -1);
+    c->rom_bwd_begin.assign((size_t)c->R, 0);
+    c->rom_bwd_end.assign((size_t)c->R, 0);
+    for (int32_t blk = 0; blk < c->bwd_blocks; ++blk) {
+        const int32_t r = c->bwd_block_rom[(size_t)blk];
+        const int32_t first = blk * kBwdSlots;
+        if (blk == 0 || c->bwd_block_rom[(size_t)blk - 1] != r) c->rom_bwd_begin[(size_t)r] = first;
+        c->rom_bwd_end[(size_t)r] = first + kBwdSlots;
+        for (int32_t j = 0; j < kBwdSlots; ++j) {
+            const int32_t e = c->bwd_slot_env[(size_t)first + j];
+            if (e >= 0) c->env_bwd_slot[(size_t)e] = first + j;
+        }
+    }
+    // static device region image
+    StaticHdr &h = c->hdr;
+    h.num_roms = c->R;
+    h.num_envs = c->B;
+    h.main_slots_per_block = c->main_E;
+    h.main_blocks = c->main_blocks;
+    h.bwd_slots_per_block = kBwdSlots;
+    h.bwd_blocks = c->bwd_blocks;
+    h.max_rom_size = c->max_rom;
+    h.total_rom_bytes = c->total_rom;
+    size_t o = align_up(sizeof(StaticHdr));
+    auto place = [&](int64_t &off, size_t n) {
+        off = (int64_t)o;
+        o = align_up(o + n * sizeof(int32_t));
+    };
+    place(h.off_rom_off, (size_t)c->R);
+    place(h.off_rom_size, (size_t)c->R);
+    place(h.off_rom_mapper, (size_t)c->R);
+    place(h.off_main_block_rom, c->main_block_rom.size());
+    place(h.off_main_slot_env, c->main_slot_env.size());
+    place(h.off_bwd_block_rom, c->bwd_block_rom.size());
+    place(h.off_bwd_slot_env, c->bwd_slot_env.size());
+    place(h.off_env_bwd_slot, (size_t)c->B);
+    place(h.off_rom_bwd_slot_begin, (size_t)c->R);
+    place(h.off_rom_bwd_slot_end, (size_t)c->R);
+    h.bytes = (int64_t)o;
+    c->blob_bytes = o;
+    c->image.assign(o, 0);
+    std::memcpy(c->image.data(), &h, sizeof(h));
+    auto put = [&](int64_t off, const std::vector<int32_t> &v) {
+        if (!v.empty()) std::memcpy(c->image.data() + off, v.data(), v.size() * sizeof(int32_t));
+    };
+    put(h.off_rom_off, c->rom_off);
+    put(h.off_rom_size, c->rom_size);
+    put(h.off_rom_mapper, c->rom_mapper);
+    put(h.off_main_block_rom, c->main_block_rom);
+    put(h.off_main_slot_env, c->main_slot_env);
+    put(h.off_bwd_block_rom, c->bwd_block_rom);
+    put(h.off_bwd_slot_env, c->bwd_slot_env);
+    put(h.off_env_bwd_slot, c->env_bwd_slot);
+    put(h.off_rom_bwd_slot_begin, c->rom_bwd_begin);
+    put(h.off_rom_bwd_slot_end, c->rom_bwd_end);
+    *out = c;
+    return VCS_OK;
+}
+
+void vcs_destroy(vcs_ctx *ctx) { delete ctx; }
+
+int32_t vcs_state_bytes(const vcs_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return VCS_INVALID_ARG;
+    *bytes = (size_t)ctx->B * sizeof(StateRec);
+    return VCS_OK;
+}
+
+int32_t vcs_rom_bytes(const vcs_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return VCS_INVALID_ARG;
+    *bytes = (size_t)ctx->total_rom;
+    return VCS_OK;
+}
+
+int32_t vcs_workspace_bytes(const vcs_ctx *ctx, int32_t op, int32_t steps, size_t *bytes) {
+    if (!ctx || !bytes || steps < 1) return VCS_INVALID_ARG;
+    switch (op) {
+        case VCS_OP_HARD:
+        case VCS_OP_SOFT_FWD: *bytes = align_up(ctx->blob_bytes); return VCS_OK;
+        case VCS_OP_SOFT_BWD: *bytes = bwd_layout(ctx, steps).bytes; return VCS_OK;
+        default: return VCS_INVALID_ARG;
+    }
+}
+
+int32_t vcs_residual_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes) {
+    if (!ctx || !bytes || steps < 1) return VCS_INVALID_ARG;
+    *bytes = residual_layout(ctx, steps).bytes;
+    return VCS_OK;
+}
+
+int32_t vcs_decode_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes) {
+    if (!ctx || !bytes || steps < 1) return VCS_INVALID_ARG;
+    *bytes = residual_layout(ctx, steps).stats_bytes;
+    return VCS_OK;
+}
+
+int32_t vcs_residual_checkpoints(const vcs_ctx *ctx, int32_t steps, int32_t *count) {
+    if (!ctx || !count || steps < 1) return VCS_INVALID_ARG;
+    *count = residual_layout(ctx, steps).max_ckpt;
+    return VCS_OK;
+}
+
+int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint8_t *d_ram0, hipStream_t stream) {
+    if (!ctx || !d_state || !aligned16(d_state)) return VCS_INVALID_ARG;
+    if (d_ram0 && ((uintptr_t)d_ram0 & 3u)) return VCS_INVALID_ARG;
+    return hip_status(launch_reset((StateRec *)d_state, ctx->B, d_mask, d_ram0, ctx->seed, stream));
+}
+
+int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                      uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
+                      const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream) {
+    if (!ctx || !d_rom || !d_state || !d_work || steps < 1) return VCS_INVALID_ARG;
+    if (!aligned16(d_rom) || !aligned16(d_state) || !aligned16(d_work)) return VCS_INVALID_ARG;
+    if (frames < VCS_FRAMES_NONE || frames > VCS_FRAMES_ALL) return VCS_INVALID_ARG;
+    if (frames != VCS_FRAMES_NONE && (!d_frame_out || !aligned16(d_frame_out))) return VCS_INVALID_ARG;
+    if (d_ram_out && ((uintptr_t)d_ram_out & 3u)) return VCS_INVALID_ARG;
+    if (d_episode_steps && num_episodes < 1) return VCS_INVALID_ARG;
+    if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
+    const int32_t rc = upload_static(ctx, d_work, stream);
+    if (rc) return rc;
+    StepParams P{};
+    P.st = static_ptrs(ctx, d_work);
+    P.rom = d_rom;
+    P.state = (StateRec *)d_state;
+    P.actions = d_actions;
+    P.steps = steps;
+    P.frame_skip = ctx->F;
+    P.ystart = ctx->ystart;
+    P.frames_mode = frames;
+    P.ram_out = d_ram_out;
+    P.frame_out = frames == VCS_FRAMES_NONE ? nullptr : d_frame_out;
+    P.done = d_done;
+    P.ep_steps = d_episode_steps;
+    P.num_episodes = d_episode_steps ? num_episodes : 0;
+    P.seed = ctx->seed;
+    return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
+                                  stream));
+}
+
+int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,
+                          const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
+                          float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
+                          void *d_work, hipStream_t stream) {
+    if (!ctx || !d_rom_logits || !d_ram_tape || !d_action_logits || !d_residual || !d_work || steps < 1)
+        return VCS_INVALID_ARG;
+    if (!(tau > 0.f) || !(alpha > 0.f)) return VCS_INVALID_ARG;
+    if (!aligned16(d_rom_logits) || !aligned16(d_ram_tape) || ((uintptr_t)d_action_logits & 3u) ||
+        !aligned16(d_residual) || !aligned16(d_work))
+        return VCS_INVALID_ARG;
+    if ((d_ram_out && !aligned16(d_ram_out)) || (d_frame_out && !aligned16(d_frame_out)) ||
+        (d_state_out && !aligned16(d_state_out)) || (d_decode_out && ((uintptr_t)d_decode_out & 3u)))
+        return VCS_INVALID_ARG;
+    if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
+    if (ctx->kernel == VCS_KERNEL_PLAIN) return VCS_UNSUPPORTED;
+    int32_t rc = upload_static(ctx, d_work, stream);
+    if (rc) return rc;
+    const ResidualLayout L = residual_layout(ctx, steps);
+    uint8_t *res = (uint8_t *)d_residual;
+    hipError_t e = launch_decode(d_rom_logits, ctx->total_rom, d_ram_tape, (int64_t)ctx->B * 128, d_action_logits,
+                                 (int64_t)ctx->B * steps, tau, res + L.rom_hard, (float *)(res + L.rom_stats),
+                                 res + L.ram0_hard, (float *)(res + L.tape_ev), res + L.act_hard,
+                                 (float *)(res + L.act_stats), stream);
+    if (e != hipSuccess) return VCS_HIP_ERROR;
+    StepParams P{};
+    P.st = static_ptrs(ctx, d_work);
+    P.rom = res + L.rom_hard;
+    P.state = (StateRec *)d_state_out;
+    P.actions = res + L.act_hard;
+    P.steps = steps;
+    P.frame_skip = ctx->F;
+    P.ystart = ctx->ystart;
+    P.frames_mode = VCS_FRAMES_LAST;
+    P.ram_out_f = d_ram_out;
+    P.frame_out_f = d_frame_out;
+    P.ram0 = res + L.ram0_hard;
+    P.ckpt = (StateRec *)(res + L.ckpt);
+    P.ckpt_count = (int32_t *)(res + L.ckpt_count);
+    P.ckpt_interval = ctx->K;
+    P.max_ckpt = L.max_ckpt;
+    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, stream));
+    if (rc) return rc;
+    if (d_decode_out &&
+        hipMemcpyAsync(d_decode_out, res + L.stats, L.stats_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return VCS_HIP_ERROR;
+    (void)alpha;  // flags carry no gradient in this relaxation, so the gate sharpness drops out
+    return VCS_OK;
+}
+
+int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_rom_logits,
+                          const float *d_ram_tape, const float *d_action_logits, float tau, float alpha,
+                          int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
+                          float *d_grad_rom_logits, float *d_grad_ram_tape, float *d_grad_action_logits,
+                          void *d_work, hipStream_t stream) {
+    if (!ctx || !d_residual || !d_rom_logits || !d_ram_tape || !d_action_logits || !d_grad_frame ||
+        !d_grad_rom_logits || !d_grad_ram_tape || !d_grad_action_logits || !d_work || steps < 1)
+        return VCS_INVALID_ARG;
+    if (!(tau > 0.f) || !(alpha > 0.f)) return VCS_INVALID_ARG;
+    if (!aligned16(d_residual) || !aligned16(d_rom_logits) || !aligned16(d_grad_rom_logits) ||
+        !aligned16(d_grad_ram_tape) || !aligned16(d_work) || ((uintptr_t)d_grad_frame & 3u) ||
+        ((uintptr_t)d_action_logits & 3u) || ((uintptr_t)d_grad_action_logits & 3u) ||
+        (d_grad_ram_out && ((uintptr_t)d_grad_ram_out & 3u)))
+        return VCS_INVALID_ARG;
+    if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
+    int32_t rc = upload_static(ctx, d_work, stream);
+    if (rc) return rc;
+    const ResidualLayout L = residual_layout(ctx, steps);
+    const BwdLayout W = bwd_layout(ctx, steps);
+    const uint8_t *res = (const uint8_t *)d_residual;
+    uint8_t *work = (uint8_t *)d_work;
+    if (launch_fill_zero(work + W.gpart, W.overflow + kAlign - W.gpart, stream) != hipSuccess) return VCS_HIP_ERROR;
+    BwdParams P{};
+    P.st = static_ptrs(ctx, d_work);
+    P.rom = res + L.rom_hard;
+    P.ram0 = res + L.ram0_hard;
+    P.actions = res + L.act_hard;
+    P.ckpt = (const StateRec *)(res + L.ckpt);
+    P.ckpt_count = (const int32_t *)(res + L.ckpt_count);
+    P.max_ckpt = L.max_ckpt;
+    P.steps = steps;
+    P.frame_skip = ctx->F;
+    P.ystart = ctx->ystart;
+    P.ckpt_interval = ctx->K;
+    P.grad_frame = d_grad_frame;
+    P.grad_ram_out = d_grad_ram_out;
+    P.tape = (TapeRec *)(work + W.tape);
+    P.max_rec = W.max_rec;
+    P.gpart = (float *)(work + W.gpart);
+    P.gport = (float *)(work + W.gport);
+    P.g_ram0 = (float *)(work + W.g0);
+    P.overflow = (int32_t *)(work + W.overflow);
+    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, stream));
+    if (rc) return rc;
+    const StaticPtrs sp = static_ptrs(ctx, d_work);
+    return hip_status(launch_epilogue(d_rom_logits, (const float *)(res + L.rom_stats), P.gpart, ctx->total_rom,
+                                      ctx->R, sp.rom_off, sp.rom_size, sp.rom_bwd_slot_begin, sp.rom_bwd_slot_end,
+                                      W.nslots, tau, d_grad_rom_logits, P.g_ram0, (int64_t)ctx->B * 128,
+                                      d_grad_ram_tape, d_action_logits, (const float *)(res + L.act_stats), P.gport,
+                                      (int64_t)ctx->B * steps, d_grad_action_logits, stream));
+}
+
+int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream) {
+    if (!ctx || !d_state || !d_out || !aligned16(d_state)) return VCS_INVALID_ARG;
+    return hip_status(launch_read_regs((const StateRec *)d_state, ctx->B, d_out, stream));
+}
+
+int32_t vcs_decode_table(uint32_t *out) {
+    if (!out) return VCS_INVALID_ARG;
+    constexpr DecodeTable t = make_decode_table();
+    for (int i = 0; i < 256; ++i) out[i] = t.e[i];
+    return VCS_OK;
+}
+
+// Soft-backward workspace check: copies the tape-overflow flag to the host
+// after the stream's work is done (1 = a segment needed more tape records
+// than the workspace holds, so that backward's result is invalid).
+int32_t vcs_bwd_overflow(const vcs_ctx *ctx, const void *d_work, int32_t steps, hipStream_t stream,
+                         int32_t *flag) {
+    if (!ctx || !d_work || !flag || steps < 1) return VCS_INVALID_ARG;
+    const BwdLayout W = bwd_layout(ctx, steps);
+    if (hipMemcpyAsync(flag, (const uint8_t *)d_work + W.overflow, sizeof(int32_t), hipMemcpyDeviceToHost, stream) !=
+        hipSuccess)
+        return VCS_HIP_ERROR;
+    return hip_status(hipStreamSynchronize(stream));
+}
+
+// Launch geometry chosen at create time (host values).
+int32_t vcs_launch_info(const vcs_ctx *ctx, int32_t *kernel, int32_t *lanes_per_env, int32_t *block_threads,
+                        int32_t *blocks, int32_t *bwd_blocks) {
+    if (!ctx) return VCS_INVALID_ARG;
+    if (kernel) *kernel = ctx->kernel;
+    if (lanes_per_env) *lanes_per_env = ctx->G;
+    if (block_threads) *block_threads = ctx->tpb;
+    if (blocks) *blocks = ctx->main_blocks;
+    if (bwd_blocks) *bwd_blocks = ctx->bwd_blocks;
+    return VCS_OK;
+}
+
+}  // extern "C"

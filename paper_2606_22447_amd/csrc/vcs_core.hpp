@@ -1,0 +1,770 @@
+// Per-env machine core of libvcs: 6507 CPU, TIA subset and RIOT, written for
+// one env per lane (or per lane group).  Used by the hard-step, soft-forward
+// and soft-backward kernels; memory placement and side outputs (pixels,
+// checkpoints, tape records) come in through the Mem and Hook policies.
+//
+// Machine semantics (paper: "A Differentiable Atari VCS", Sec. "Why the Atari
+// VCS Is Good Ground Truth", Sec. "Building Two Differentiable VCS Ports"):
+//  - 13-bit bus: A12 set = cartridge; else A7 clear = TIA; else A9 clear = RAM
+//    (128 B, mirrored through the stack page); else RIOT ports/timer.
+//  - 2K images mirror on A11; F8 images switch 4 KB banks on data accesses to
+//    $1FF8/$1FF9 (a hotspot read returns the newly selected bank's byte).
+//  - Loads and stores access memory in an instruction's last cycle; a
+//    read-modify-write reads three cycles before its end; all pushes of an
+//    instruction take effect in its last cycle.
+//  - A TIA write in CPU cycle n shows from colour clock 3n+3; WSYNC resumes the
+//    CPU at cycle 0 of the next line; a pixel is the owning colour register &
+//    0xFE (0 while VBLANK bit 1 is set).
+//  - RIOT timer: after writing V with interval 2^shift at cycle w the timer
+//    underflows at u = w + 1 + V*2^shift; before u INTIM = -1 - floor((t-u)/I),
+//    from u on INTIM = (255 - (t - u)) mod 256; TIMINT bit 7 is set from u
+//    until an INTIM read.
+//  - The 67 opcode bytes outside the paper's set of 189 jam the CPU.
+#pragma once
+
+#include "vcs_internal.hpp"
+
+namespace vcs {
+
+// ---------------------------------------------------------------------------
+// Opcode decode, derived from the regular aaabbbcc structure of the 6502
+// opcode matrix and the documented per-addressing-mode timing rules.
+// ---------------------------------------------------------------------------
+enum Cls : uint32_t {
+    C_JAM = 0, C_LDA, C_LDX, C_LDY, C_LAX, C_STA, C_STX, C_STY, C_SAX,
+    C_ADC, C_SBC, C_AND, C_ORA, C_EOR, C_CMP, C_CPX, C_CPY, C_BIT,
+    C_ASL, C_LSR, C_ROL, C_ROR, C_INC, C_DEC,
+    C_INX, C_INY, C_DEX, C_DEY, C_TAX, C_TAY, C_TXA, C_TYA, C_TSX, C_TXS,
+    C_PHA, C_PHP, C_PLA, C_PLP, C_JMP, C_JSR, C_RTS, C_RTI, C_BRK,
+    C_BRANCH, C_FLAG, C_NOP
+};
+enum Mode : uint32_t { M_IMP, M_ACC, M_IMM, M_ZP, M_ZPX, M_ZPY, M_ABS, M_ABX, M_ABY, M_IZX, M_IZY, M_IND, M_REL };
+
+constexpr uint32_t kFlagC = 0x01, kFlagZ = 0x02, kFlagI = 0x04, kFlagD = 0x08, kFlagB = 0x10, kFlagU = 0x20,
+                   kFlagV = 0x40, kFlagN = 0x80;
+
+constexpr uint32_t mode_len(uint32_t m) {
+    return (m == M_IMP || m == M_ACC) ? 1u : (m == M_ABS || m == M_ABX || m == M_ABY || m == M_IND) ? 3u : 2u;
+}
+
+// entry = class | mode << 6 | cycles << 10 | page penalty << 13 | length << 14 | aux << 16 | set << 24
+constexpr uint32_t enc(uint32_t cls, uint32_t m, uint32_t cyc, uint32_t pen, uint32_t aux = 0, uint32_t set = 0) {
+    return cls | (m << 6) | (cyc << 10) | (pen << 13) | (mode_len(m) << 14) | (aux << 16) | (set << 24);
+}
+// read instructions: +1 cycle when an indexed read crosses a page
+constexpr uint32_t rd_timing(uint32_t cls, uint32_t m) {
+    return m == M_IMM ? enc(cls, m, 2, 0) : m == M_ZP ? enc(cls, m, 3, 0)
+         : (m == M_ZPX || m == M_ZPY) ? enc(cls, m, 4, 0) : m == M_ABS ? enc(cls, m, 4, 0)
+         : (m == M_ABX || m == M_ABY) ? enc(cls, m, 4, 1) : m == M_IZX ? enc(cls, m, 6, 0) : enc(cls, m, 5, 1);
+}
+// write instructions: indexed forms always take the extra cycle
+constexpr uint32_t wr_timing(uint32_t cls, uint32_t m) {
+    return m == M_ZP ? enc(cls, m, 3, 0) : (m == M_ZPX || m == M_ZPY) ? enc(cls, m, 4, 0)
+         : m == M_ABS ? enc(cls, m, 4, 0) : (m == M_ABX || m == M_ABY) ? enc(cls, m, 5, 0) : enc(cls, m, 6, 0);
+}
+// read-modify-write instructions
+constexpr uint32_t rmw_timing(uint32_t cls, uint32_t m) {
+    return m == M_ACC ? enc(cls, m, 2, 0) : m == M_ZP ? enc(cls, m, 5, 0)
+         : (m == M_ZPX || m == M_ABS) ? enc(cls, m, 6, 0) : enc(cls, m, 7, 0);
+}
+
+constexpr uint32_t decode_op(uint32_t op) {
+    const uint32_t aaa = op >> 5, bbb = (op >> 2) & 7u, cc = op & 3u;
+    const uint32_t g1_mode[8] = {M_IZX, M_ZP, M_IMM, M_ABS, M_IZY, M_ZPX, M_ABY, M_ABX};
+    if (cc == 1) {  // ORA AND EOR ADC STA LDA CMP SBC
+        const uint32_t cls[8] = {C_ORA, C_AND, C_EOR, C_ADC, C_STA, C_LDA, C_CMP, C_SBC};
+        if (aaa == 4) return bbb == 2 ? rd_timing(C_NOP, M_IMM) : wr_timing(C_STA, g1_mode[bbb]);
+        return rd_timing(cls[aaa], g1_mode[bbb]);
+    }
+    if (cc == 2) {  // shifts, STX/LDX, DEC/INC and their implied column
+        if (bbb == 4) return 0;
+        if (aaa <= 3) {
+            const uint32_t cls[4] = {C_ASL, C_ROL, C_LSR, C_ROR};
+            switch (bbb) {
+                case 1: return rmw_timing(cls[aaa], M_ZP);
+                case 2: return rmw_timing(cls[aaa], M_ACC);
+                case 3: return rmw_timing(cls[aaa], M_ABS);
+                case 5: return rmw_timing(cls[aaa], M_ZPX);
+                case 6: return enc(C_NOP, M_IMP, 2, 0);
+                case 7: return rmw_timing(cls[aaa], M_ABX);
+                default: return 0;
+            }
+        }
+        if (aaa == 4) {
+            switch (bbb) {
+                case 0: return rd_timing(C_NOP, M_IMM);
+                case 1: return wr_timing(C_STX, M_ZP);
+                case 2: return enc(C_TXA, M_IMP, 2, 0);
+                case 3: return wr_timing(C_STX, M_ABS);
+                case 5: return wr_timing(C_STX, M_ZPY);
+                case 6: return enc(C_TXS, M_IMP, 2, 0);
+                default: return 0;
+            }
+        }
+        if (aaa == 5) {
+            switch (bbb) {
+                case 0: return rd_timing(C_LDX, M_IMM);
+                case 1: return rd_timing(C_LDX, M_ZP);
+                case 2: return enc(C_TAX, M_IMP, 2, 0);
+                case 3: return rd_timing(C_LDX, M_ABS);
+                case 5: return rd_timing(C_LDX, M_ZPY);
+                case 6: return enc(C_TSX, M_IMP, 2, 0);
+                case 7: return rd_timing(C_LDX, M_ABY);
+                default: return 0;
+            }
+        }
+        const uint32_t cls = aaa == 6 ? C_DEC : C_INC;
+        switch (bbb) {
+            case 0: return rd_timing(C_NOP, M_IMM);
+            case 1: return rmw_timing(cls, M_ZP);
+            case 2: return enc(aaa == 6 ? C_DEX : C_NOP, M_IMP, 2, 0);
+            case 3: return rmw_timing(cls, M_ABS);
+            case 5: return rmw_timing(cls, M_ZPX);
+            case 6: return enc(C_NOP, M_IMP, 2, 0);
+            case 7: return rmw_timing(cls, M_ABX);
+            default: return 0;
+        }
+    }
+    if (cc == 0) {
+        if (bbb == 4) {  // Bxx: flag N, V, C, Z by aaa>>1; branch when set if aaa is odd
+            const uint32_t flag[4] = {kFlagN, kFlagV, kFlagC, kFlagZ};
+            return enc(C_BRANCH, M_REL, 2, 0, flag[aaa >> 1], aaa & 1u);
+        }
+        if (bbb == 6) {  // CLC SEC CLI SEI TYA CLV CLD SED
+            if (aaa == 4) return enc(C_TYA, M_IMP, 2, 0);
+            const uint32_t flag[8] = {kFlagC, kFlagC, kFlagI, kFlagI, 0, kFlagV, kFlagD, kFlagD};
+            return enc(C_FLAG, M_IMP, 2, 0, flag[aaa], (aaa & 1u) && aaa != 5);
+        }
+        if (bbb == 2) {  // PHP PLP PHA PLA DEY TAY INY INX
+            const uint32_t cls[8] = {C_PHP, C_PLP, C_PHA, C_PLA, C_DEY, C_TAY, C_INY, C_INX};
+            const uint32_t cyc[8] = {3, 4, 3, 4, 2, 2, 2, 2};
+            return enc(cls[aaa], M_IMP, cyc[aaa], 0);
+        }
+        if (bbb == 0) {
+            switch (aaa) {
+                case 0: return enc(C_BRK, M_IMP, 7, 0);
+                case 1: return enc(C_JSR, M_ABS, 6, 0);
+                case 2: return enc(C_RTI, M_IMP, 6, 0);
+                case 3: return enc(C_RTS, M_IMP, 6, 0);
+                case 4: return rd_timing(C_NOP, M_IMM);
+                case 5: return rd_timing(C_LDY, M_IMM);
+                case 6: return rd_timing(C_CPY, M_IMM);
+                default: return rd_timing(C_CPX, M_IMM);
+            }
+        }
+        if (bbb == 1) {
+            switch (aaa) {
+                case 1: return rd_timing(C_BIT, M_ZP);
+                case 4: return wr_timing(C_STY, M_ZP);
+                case 5: return rd_timing(C_LDY, M_ZP);
+                case 6: return rd_timing(C_CPY, M_ZP);
+                case 7: return rd_timing(C_CPX, M_ZP);
+                default: return rd_timing(C_NOP, M_ZP);
+            }
+        }
+        if (bbb == 3) {
+            switch (aaa) {
+                case 0: return rd_timing(C_NOP, M_ABS);
+                case 1: return rd_timing(C_BIT, M_ABS);
+                case 2: return enc(C_JMP, M_ABS, 3, 0);
+                case 3: return enc(C_JMP, M_IND, 5, 0);
+                case 4: return wr_timing(C_STY, M_ABS);
+                case 5: return rd_timing(C_LDY, M_ABS);
+                case 6: return rd_timing(C_CPY, M_ABS);
+                default: return rd_timing(C_CPX, M_ABS);
+            }
+        }
+        if (bbb == 5) return aaa == 4 ? wr_timing(C_STY, M_ZPX) : aaa == 5 ? rd_timing(C_LDY, M_ZPX)
+                                                                           : rd_timing(C_NOP, M_ZPX);
+        /* bbb == 7 */
+        return aaa == 4 ? 0u : aaa == 5 ? rd_timing(C_LDY, M_ABX) : rd_timing(C_NOP, M_ABX);
+    }
+    // cc == 3: only USBC ($EB), SAX and LAX belong to the set
+    if (op == 0xEB) return rd_timing(C_SBC, M_IMM);
+    if (aaa == 4) {
+        switch (bbb) {
+            case 0: return wr_timing(C_SAX, M_IZX);
+            case 1: return wr_timing(C_SAX, M_ZP);
+            case 3: return wr_timing(C_SAX, M_ABS);
+            case 5: return wr_timing(C_SAX, M_ZPY);
+            default: return 0;
+        }
+    }
+    if (aaa == 5) {
+        switch (bbb) {
+            case 0: return rd_timing(C_LAX, M_IZX);
+            case 1: return rd_timing(C_LAX, M_ZP);
+            case 3: return rd_timing(C_LAX, M_ABS);
+            case 4: return rd_timing(C_LAX, M_IZY);
+            case 5: return rd_timing(C_LAX, M_ZPY);
+            case 7: return rd_timing(C_LAX, M_ABY);
+            default: return 0;
+        }
+    }
+    return 0;
+}
+
+struct DecodeTable {
+    uint32_t e[256];
+};
+constexpr DecodeTable make_decode_table() {
+    DecodeTable t{};
+    for (uint32_t i = 0; i < 256; ++i) t.e[i] = decode_op(i);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood 2014) in counter form, for in-run reset RAM
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint64_t sm64_mix(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+// Word i (0..15) of the reset RAM of (seed, env, episode): 8 little-endian bytes.
+__host__ __device__ __forceinline__ uint64_t reset_ram_word(uint64_t seed, uint64_t env, uint64_t episode, uint32_t i) {
+    uint64_t k = sm64_mix(seed + (env + 1) * kGolden);
+    k = sm64_mix(k + (episode + 1) * kGolden);
+    return sm64_mix(k + (uint64_t)(i + 1) * kGolden);
+}
+
+// ---------------------------------------------------------------------------
+// Playfield geometry: 40 groups of 4 pixels per line, one playfield bit each.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ uint32_t rev8(uint32_t v) {
+    v = ((v & 0xF0u) >> 4) | ((v & 0x0Fu) << 4);
+    v = ((v & 0xCCu) >> 2) | ((v & 0x33u) << 2);
+    return ((v & 0xAAu) >> 1) | ((v & 0x55u) << 1);
+}
+// 20-bit mask, bit i = playfield bit of half-line position i (PF0 b4..b7, PF1 b7..b0, PF2 b0..b7)
+__host__ __device__ __forceinline__ uint32_t pf_mask20(uint32_t pf) {
+    return ((pf >> 4) & 0xFu) | (rev8((pf >> 8) & 0xFFu) << 4) | (((pf >> 16) & 0xFFu) << 12);
+}
+// Owning colour register of 4-pixel group g (0..39): 0 COLUP0, 1 COLUP1, 2 COLUPF, 3 COLUBK.
+__host__ __device__ __forceinline__ uint32_t group_owner(uint32_t g, uint32_t mask20, uint32_t ctrlpf) {
+    const uint32_t i = g < 20 ? g : ((ctrlpf & 1u) ? 39u - g : g - 20u);
+    if (!((mask20 >> i) & 1u)) return 3u;
+    return (ctrlpf & 2u) ? (g < 20 ? 0u : 1u) : 2u;
+}
+
+// Visit the 4-pixel groups of frame-relative colour clocks [from, to) that fall in
+// the visible window; lane `sub` of a group of G lanes takes every G-th group of
+// each line.  f(y, g, xa, xb) gets the row, the group and the covered pixels [xa, xb).
+template <class F>
+__host__ __device__ __forceinline__ void for_each_group(int32_t from, int32_t to, int32_t ystart, uint32_t sub,
+                                                        uint32_t G, F &&f) {
+    const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
+    if (from < vis0) from = vis0;
+    if (to > vis1) to = vis1;
+    while (from < to) {
+        const int32_t rel = from - vis0;
+        const int32_t y = rel / kClocksPerLine;
+        const int32_t h = rel - y * kClocksPerLine;
+        const int32_t line0 = from - h;
+        const int32_t seg_end = to < line0 + kClocksPerLine ? to : line0 + kClocksPerLine;
+        const int32_t x0 = h > kHBlank ? h - kHBlank : 0;
+        const int32_t x1 = seg_end - line0 - kHBlank;
+        if (x1 > x0) {
+            const int32_t g1 = (x1 + 3) >> 2;
+            for (int32_t g = (x0 >> 2) + (int32_t)sub; g < g1; g += (int32_t)G) {
+                const int32_t xa = x0 > 4 * g ? x0 : 4 * g;
+                const int32_t xb = x1 < 4 * g + 4 ? x1 : 4 * g + 4;
+                f(y, g, xa, xb);
+            }
+        }
+        from = seg_end;
+    }
+}
+
+// Write the pixels of [from, to) for the given TIA state into a frame of T.
+template <typename T>
+__host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int32_t to, uint32_t col, uint32_t pf,
+                                                     uint32_t vb, int32_t ystart, uint32_t sub, uint32_t G) {
+    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
+    for_each_group(from, to, ystart, sub, G, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+        const uint32_t c = (vb & 2u) ? 0u : ((col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
+        T *row = frame + y * kScreenW;
+        if (xb - xa == 4) {
+            if constexpr (sizeof(T) == 1) {
+                *reinterpret_cast<uint32_t *>(row + xa) = c * 0x01010101u;
+            } else {
+                const float v = (float)c;
+                *reinterpret_cast<float4 *>(row + xa) = make_float4(v, v, v, v);
+            }
+        } else {
+            for (int32_t x = xa; x < xb; ++x) row[x] = (T)c;
+        }
+    });
+}
+
+// Per-owner sums of dL/dpixel over [from, to) (soft backward): sums[r] for owner r.
+__host__ __device__ __forceinline__ bool pixel_sums(const float *gframe, int32_t from, int32_t to, uint32_t pf,
+                                                    uint32_t vb, int32_t ystart, float sums[4]) {
+    bool any = false;
+    if (vb & 2u) return false;  // blanked pixels are constants
+    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
+    for_each_group(from, to, ystart, 0u, 1u, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+        const float *row = gframe + y * kScreenW;
+        float acc = 0.f;
+        for (int32_t x = xa; x < xb; ++x) acc += row[x];
+        sums[group_owner((uint32_t)g, mask, ctrl)] += acc;
+        any = true;
+    });
+    return any;
+}
+
+// ---------------------------------------------------------------------------
+// Data classes for the soft backward (where a value comes from / goes to)
+// ---------------------------------------------------------------------------
+struct ExecInfo {
+    uint32_t rd_cls, rd_idx, wr_cls, wr_idx, v1, v2, s_before;
+};
+
+// Class of a 13-bit data write target.
+__host__ __device__ __forceinline__ uint32_t write_class(uint32_t addr, uint32_t *idx) {
+    addr &= 0x1FFFu;
+    *idx = 0;
+    if (addr & 0x1000u) return kClsConst;
+    if (!(addr & 0x80u)) {
+        const uint32_t reg = addr & 0x3Fu;
+        if (reg >= 6 && reg <= 9) {
+            *idx = reg - 6;
+            return kClsCol;
+        }
+        return kClsConst;
+    }
+    if (!(addr & 0x200u)) {
+        *idx = addr & 0x7Fu;
+        return kClsRam;
+    }
+    return kClsConst;
+}
+
+// ---------------------------------------------------------------------------
+// The machine
+// ---------------------------------------------------------------------------
+template <class Mem, class Hook>
+struct Cpu {
+    uint32_t a, x, y, s, p, pc, bank, jam;
+    int32_t cyc;                  // frame-relative CPU cycle
+    uint32_t col, pf, vb;         // colour registers, playfield + CTRLPF, VBLANK | VSYNC << 8
+    int32_t tim_u, tim_read;
+    uint32_t tim_shift;
+    uint32_t swcha, inpt4;
+    uint32_t wsync;
+    uint32_t amask, f8;           // cartridge address mask, F8 flag
+    Mem mem;
+    Hook hook;
+
+    __host__ __device__ __forceinline__ uint32_t cart_off(uint32_t addr) const { return (addr & amask) + (bank << 12); }
+
+    __host__ __device__ __forceinline__ uint32_t intim_at(int32_t t) const {
+        const int32_t d = t - tim_u;
+        return d < 0 ? ((uint32_t)(-1 - (d >> tim_shift)) & 0xFFu) : ((uint32_t)(255 - d) & 0xFFu);
+    }
+    __host__ __device__ __forceinline__ uint32_t timint_at(int32_t t) const {
+        return (t >= tim_u && tim_read < tim_u) ? 0x80u : 0u;
+    }
+    __host__ __device__ __forceinline__ uint32_t tia_in(uint32_t addr) const {
+        const uint32_t r = addr & 0xFu;
+        return r == 0xCu ? inpt4 : (r == 0xDu ? 0x80u : 0u);
+    }
+    __host__ __device__ __forceinline__ uint32_t riot_in(uint32_t addr, int32_t t, bool fx) {
+        if (!(addr & 4u)) {
+            const uint32_t r = addr & 3u;
+            return r == 0 ? swcha : (r == 2 ? 0x0Bu : 0u);
+        }
+        if (!(addr & 1u)) {
+            const uint32_t v = intim_at(t);
+            if (fx) tim_read = t;
+            return v;
+        }
+        return timint_at(t);
+    }
+    // fetch-type read: no side effects
+    __host__ __device__ __forceinline__ uint32_t peek(uint32_t addr, int32_t t) {
+        addr &= 0x1FFFu;
+        if (addr & 0x1000u) return mem.rom_byte(cart_off(addr));
+        if (!(addr & 0x80u)) return tia_in(addr);
+        if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
+        return riot_in(addr, t, false);
+    }
+    __host__ __device__ __forceinline__ void hotspot(uint32_t addr) {
+        if (f8 && (addr & 0x1FFEu) == 0x1FF8u) bank = addr & 1u;
+    }
+    // data read in cycle t
+    __host__ __device__ __forceinline__ uint32_t read(uint32_t addr, int32_t t) {
+        addr &= 0x1FFFu;
+        if (addr & 0x1000u) {
+            hotspot(addr);
+            return mem.rom_byte(cart_off(addr));
+        }
+        if (!(addr & 0x80u)) return tia_in(addr);
+        if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
+        return riot_in(addr, t, true);
+    }
+    // class of the value a data read at addr returned (after its side effects)
+    __host__ __device__ __forceinline__ uint32_t read_class(uint32_t addr, uint32_t *idx) const {
+        addr &= 0x1FFFu;
+        *idx = 0;
+        if (addr & 0x1000u) {
+            *idx = cart_off(addr);
+            return kClsRom;
+        }
+        if (!(addr & 0x80u)) return (addr & 0xFu) == 0xCu ? kClsInpt4 : kClsConst;
+        if (!(addr & 0x200u)) {
+            *idx = addr & 0x7Fu;
+            return kClsRam;
+        }
+        return (!(addr & 4u) && !(addr & 3u)) ? kClsSwcha : kClsConst;
+    }
+    __host__ __device__ __forceinline__ void tia_out(uint32_t reg, uint32_t v, int32_t w) {
+        switch (reg) {
+            case 0x00: vb = (vb & 0xFFu) | (v << 8); break;
+            case 0x01: hook.before_pixel_write(*this, w); vb = (vb & 0xFF00u) | v; break;
+            case 0x02: wsync = 1; break;
+            case 0x06: case 0x07: case 0x08: case 0x09: {
+                hook.before_pixel_write(*this, w);
+                const uint32_t sh = (reg - 6u) * 8u;
+                col = (col & ~(0xFFu << sh)) | (v << sh);
+                break;
+            }
+            case 0x0A: hook.before_pixel_write(*this, w); pf = (pf & 0x00FFFFFFu) | (v << 24); break;
+            case 0x0D: case 0x0E: case 0x0F: {
+                hook.before_pixel_write(*this, w);
+                const uint32_t sh = (reg - 0x0Du) * 8u;
+                pf = (pf & ~(0xFFu << sh)) | (v << sh);
+                break;
+            }
+            default: break;  // sprites, audio, motion: outside this subset
+        }
+    }
+    // data write in cycle w
+    __host__ __device__ __forceinline__ void write(uint32_t addr, uint32_t v, int32_t w) {
+        addr &= 0x1FFFu;
+        if (addr & 0x1000u) {
+            hotspot(addr);
+            return;
+        }
+        if (!(addr & 0x80u)) {
+            tia_out(addr & 0x3Fu, v, w);
+            return;
+        }
+        if (!(addr & 0x200u)) {
+            mem.ram_set(addr & 0x7Fu, v);
+            return;
+        }
+        if ((addr & 0x14u) == 0x14u) {  // TIM1T / TIM8T / TIM64T / T1024T
+            const uint32_t k = addr & 3u;
+            const uint32_t sh = k == 0 ? 0u : k == 1 ? 3u : k == 2 ? 6u : 10u;
+            tim_shift = sh;
+            tim_u = w + 1 + (int32_t)(v << sh);
+        }
+    }
+    __host__ __device__ __forceinline__ void set_nz(uint32_t v) {
+        p = (p & ~(kFlagN | kFlagZ)) | (v & kFlagN) | (v ? 0u : kFlagZ);
+    }
+    __host__ __device__ __forceinline__ void push(uint32_t v, int32_t w) {
+        write(0x100u | s, v, w);
+        s = (s - 1u) & 0xFFu;
+    }
+    __host__ __device__ __forceinline__ uint32_t pull(int32_t t) {
+        s = (s + 1u) & 0xFFu;
+        return read(0x100u | s, t);
+    }
+
+    // NMOS ADC, binary and decimal (decimal: B. Clark, "Decimal Mode", App. A)
+    __host__ __device__ __forceinline__ uint32_t adc(uint32_t v) {
+        const uint32_t c = p & kFlagC;
+        const uint32_t sum = a + v + c;
+        if (!(p & kFlagD)) {
+            p = (p & ~(kFlagV | kFlagC)) | ((~(a ^ v) & (a ^ sum) & 0x80u) ? kFlagV : 0u) | (sum > 0xFFu ? kFlagC : 0u);
+            set_nz(sum & 0xFFu);
+            return sum & 0xFFu;
+        }
+        int32_t lo = (int32_t)((a & 0xFu) + (v & 0xFu) + c);
+        if (lo > 9) lo = ((lo + 6) & 0xF) + 0x10;
+        const int32_t hi_s = ((int32_t)((a & 0xF0u) ^ 0x80u) - 128) + ((int32_t)((v & 0xF0u) ^ 0x80u) - 128) + lo;
+        int32_t hi_u = (int32_t)(a & 0xF0u) + (int32_t)(v & 0xF0u) + lo;
+        if (hi_u >= 0xA0) hi_u += 0x60;
+        p &= ~(kFlagN | kFlagZ | kFlagV | kFlagC);
+        p |= ((uint32_t)hi_s & 0x80u) | ((sum & 0xFFu) ? 0u : kFlagZ) | ((hi_s < -128 || hi_s > 127) ? kFlagV : 0u) |
+             (hi_u > 0xFF ? kFlagC : 0u);
+        return (uint32_t)hi_u & 0xFFu;
+    }
+    __host__ __device__ __forceinline__ uint32_t sbc(uint32_t v) {
+        const uint32_t c = p & kFlagC;
+        const int32_t diff = (int32_t)a - (int32_t)v - (int32_t)(1u - c);
+        const uint32_t bin = (uint32_t)diff & 0xFFu;
+        p = (p & ~(kFlagV | kFlagC)) | (((a ^ v) & (a ^ bin) & 0x80u) ? kFlagV : 0u) | (diff >= 0 ? kFlagC : 0u);
+        set_nz(bin);
+        if (!(p & kFlagD)) return bin;
+        int32_t lo = (int32_t)(a & 0xFu) - (int32_t)(v & 0xFu) - (int32_t)(1u - c);
+        if (lo < 0) lo = ((lo - 6) & 0xF) - 0x10;
+        int32_t r = (int32_t)(a & 0xF0u) - (int32_t)(v & 0xF0u) + lo;
+        if (r < 0) r -= 0x60;
+        return (uint32_t)r & 0xFFu;
+    }
+
+    // Execute one instruction whose opcode byte is opc (decode entry d) with
+    // operand bytes lo/hi; `info` receives the data classes when recording.
+    __host__ __device__ __forceinline__ void exec(uint32_t opc, uint32_t d, uint32_t lo, uint32_t hi, ExecInfo &info) {
+        constexpr bool R = Hook::kRecord;
+        const uint32_t cls = d & 63u, mode = (d >> 6) & 15u;
+        const int32_t t0 = cyc;
+        int32_t n = (int32_t)((d >> 10) & 7u);
+        const uint32_t pc0 = pc;
+        pc = (pc0 + ((d >> 14) & 3u)) & 0xFFFFu;
+        if constexpr (R) {
+            info.rd_cls = kClsConst;
+            info.wr_cls = kClsConst;
+            info.rd_idx = info.wr_idx = info.v1 = info.v2 = 0;
+            info.s_before = s;
+        }
+        hook.before_exec(*this);
+        uint32_t ea = 0;
+        switch (mode) {
+            case M_IMM: ea = (pc0 + 1u) & 0xFFFFu; break;
+            case M_ZP: ea = lo; break;
+            case M_ZPX: ea = (lo + x) & 0xFFu; break;
+            case M_ZPY: ea = (lo + y) & 0xFFu; break;
+            case M_ABS: ea = lo | (hi << 8); break;
+            case M_ABX:
+            case M_ABY: {
+                const uint32_t base = lo | (hi << 8);
+                ea = (base + (mode == M_ABX ? x : y)) & 0xFFFFu;
+                n += (int32_t)(((d >> 13) & 1u) & (((base ^ ea) >> 8) != 0u ? 1u : 0u));
+                break;
+            }
+            case M_IZX: {
+                const uint32_t z = (lo + x) & 0xFFu;
+                ea = peek(z, t0) | (peek((z + 1u) & 0xFFu, t0) << 8);
+                break;
+            }
+            case M_IZY: {
+                const uint32_t base = peek(lo, t0) | (peek((lo + 1u) & 0xFFu, t0) << 8);
+                ea = (base + y) & 0xFFFFu;
+                n += (int32_t)(((d >> 13) & 1u) & (((base ^ ea) >> 8) != 0u ? 1u : 0u));
+                break;
+            }
+            case M_IND: {
+                const uint32_t ptr = lo | (hi << 8);
+                const uint32_t ptr_hi = (ptr & 0xFF00u) | ((ptr + 1u) & 0xFFu);
+                ea = peek(ptr, t0) | (peek(ptr_hi, t0) << 8);
+                break;
+            }
+            default: break;
+        }
+        const int32_t tl = t0 + n - 1;  // last cycle of reads/stores (n is final here for them)
+        switch (cls) {
+            case C_LDA: case C_LDX: case C_LDY: case C_LAX:
+            case C_ADC: case C_SBC: case C_AND: case C_ORA: case C_EOR:
+            case C_CMP: case C_CPX: case C_CPY: case C_BIT: {
+                const uint32_t v = mode == M_IMM ? lo : read(ea, tl);
+                if constexpr (R) info.rd_cls = read_class(ea, &info.rd_idx);
+                switch (cls) {
+                    case C_LDA: a = v; set_nz(v); break;
+                    case C_LDX: x = v; set_nz(v); break;
+                    case C_LDY: y = v; set_nz(v); break;
+                    case C_LAX: a = x = v; set_nz(v); break;
+                    case C_ADC: a = adc(v); break;
+                    case C_SBC: a = sbc(v); break;
+                    case C_AND: case C_ORA: case C_EOR:
+                        if constexpr (R) {
+                            info.v1 = a;
+                            info.v2 = v;
+                        }
+                        a = cls == C_AND ? (a & v) : cls == C_ORA ? (a | v) : (a ^ v);
+                        set_nz(a);
+                        break;
+                    case C_BIT:
+                        p = (p & ~(kFlagN | kFlagV | kFlagZ)) | (v & (kFlagN | kFlagV)) | ((a & v) ? 0u : kFlagZ);
+                        break;
+                    default: {  // CMP CPX CPY
+                        const uint32_t r = cls == C_CMP ? a : cls == C_CPX ? x : y;
+                        p = (p & ~kFlagC) | (r >= v ? kFlagC : 0u);
+                        set_nz((r - v) & 0xFFu);
+                        break;
+                    }
+                }
+                break;
+            }
+            case C_STA: case C_STX: case C_STY: case C_SAX: {
+                const uint32_t v = cls == C_STA ? a : cls == C_STX ? x : cls == C_STY ? y : (a & x);
+                if constexpr (R) {
+                    info.wr_cls = write_class(ea, &info.wr_idx);
+                    info.v1 = a;
+                    info.v2 = x;
+                }
+                write(ea, v, tl);
+                break;
+            }
+            case C_ASL: case C_LSR: case C_ROL: case C_ROR: case C_INC: case C_DEC: {
+                uint32_t v;
+                if (mode == M_ACC) {
+                    v = a;
+                    if constexpr (R) info.rd_cls = info.wr_cls = kClsRegA;
+                } else {
+                    v = read(ea, t0 + n - 3);
+                    if constexpr (R) {
+                        info.rd_cls = read_class(ea, &info.rd_idx);
+                        info.wr_cls = write_class(ea, &info.wr_idx);
+                    }
+                }
+                const uint32_t c = p & kFlagC;
+                uint32_t r;
+                switch (cls) {
+                    case C_ASL: p = (p & ~kFlagC) | (v >> 7); r = (v << 1) & 0xFFu; break;
+                    case C_LSR: p = (p & ~kFlagC) | (v & 1u); r = v >> 1; break;
+                    case C_ROL: p = (p & ~kFlagC) | (v >> 7); r = ((v << 1) | c) & 0xFFu; break;
+                    case C_ROR: p = (p & ~kFlagC) | (v & 1u); r = (v >> 1) | (c << 7); break;
+                    case C_INC: r = (v + 1u) & 0xFFu; break;
+                    default: r = (v - 1u) & 0xFFu; break;
+                }
+                set_nz(r);
+                if (mode == M_ACC) a = r;
+                else write(ea, r, tl);
+                break;
+            }
+            case C_INX: x = (x + 1u) & 0xFFu; set_nz(x); break;
+            case C_INY: y = (y + 1u) & 0xFFu; set_nz(y); break;
+            case C_DEX: x = (x - 1u) & 0xFFu; set_nz(x); break;
+            case C_DEY: y = (y - 1u) & 0xFFu; set_nz(y); break;
+            case C_TAX: x = a; set_nz(x); break;
+            case C_TAY: y = a; set_nz(y); break;
+            case C_TXA: a = x; set_nz(a); break;
+            case C_TYA: a = y; set_nz(a); break;
+            case C_TSX: x = s; set_nz(x); break;
+            case C_TXS: s = x; break;
+            case C_PHA:
+                if constexpr (R) info.wr_cls = write_class(0x100u | s, &info.wr_idx);
+                push(a, tl);
+                break;
+            case C_PHP: push(p | kFlagB | kFlagU, tl); break;
+            case C_PLA: {
+                const uint32_t v = pull(tl);
+                if constexpr (R) info.rd_cls = read_class(0x100u | s, &info.rd_idx);
+                a = v;
+                set_nz(v);
+                break;
+            }
+            case C_PLP: p = (pull(tl) & ~kFlagB) | kFlagU; break;
+            case C_JMP: pc = ea; break;
+            case C_JSR: {
+                const uint32_t ret = (pc - 1u) & 0xFFFFu;
+                push(ret >> 8, tl);
+                push(ret & 0xFFu, tl);
+                pc = ea;
+                break;
+            }
+            case C_RTS: {
+                const uint32_t l = pull(tl);
+                const uint32_t h = pull(tl);
+                pc = (((h << 8) | l) + 1u) & 0xFFFFu;
+                break;
+            }
+            case C_BRK: {
+                const uint32_t ret = (pc0 + 2u) & 0xFFFFu;
+                push(ret >> 8, tl);
+                push(ret & 0xFFu, tl);
+                push(p | kFlagB | kFlagU, tl);
+                p |= kFlagI;
+                pc = peek(0x1FFEu, t0) | (peek(0x1FFFu, t0) << 8);
+                break;
+            }
+            case C_RTI: {
+                p = (pull(tl) & ~kFlagB) | kFlagU;
+                const uint32_t l = pull(tl);
+                const uint32_t h = pull(tl);
+                pc = (h << 8) | l;
+                break;
+            }
+            case C_BRANCH: {
+                const uint32_t mask = (d >> 16) & 0xFFu, when_set = (d >> 24) & 1u;
+                if (((p & mask) ? 1u : 0u) == when_set) {
+                    const uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
+                    n += 1 + (((target ^ pc) & 0xFF00u) ? 1 : 0);
+                    pc = target;
+                }
+                break;
+            }
+            case C_FLAG: {
+                const uint32_t mask = (d >> 16) & 0xFFu;
+                p = ((d >> 24) & 1u) ? (p | mask) : (p & ~mask);
+                break;
+            }
+            default: break;  // NOP family (operand reads have no side effects)
+        }
+        cyc = t0 + n;
+        hook.after_exec(*this, opc, t0, cyc, info);
+        if (wsync) {
+            wsync = 0;
+            const int32_t r = cyc % kCyclesPerLine;
+            if (r) cyc += kCyclesPerLine - r;
+        }
+    }
+
+    // Power-on (also the in-run reset): registers, TIA and timer to their
+    // power-on values, PC from the reset vector of the power-on bank.
+    __host__ __device__ __forceinline__ void power_on() {
+        a = x = y = 0;
+        s = 0xFDu;
+        p = kFlagI | kFlagU;
+        bank = f8 ? 1u : 0u;
+        jam = 0;
+        cyc = 0;
+        col = pf = vb = 0;
+        tim_u = 0;
+        tim_read = 0;
+        tim_shift = 10;
+        wsync = 0;
+        pc = peek(0x1FFCu, 0) | (peek(0x1FFDu, 0) << 8);
+    }
+
+    // Frame rollover: cycle counters become relative to the next frame.  Long
+    // underflowed timers are renormalised by multiples of 256 cycles, which
+    // changes no observable value.
+    __host__ __device__ __forceinline__ void next_frame() {
+        cyc -= kCyclesPerFrame;
+        tim_u -= kCyclesPerFrame;
+        tim_read -= kCyclesPerFrame;
+        if (tim_read < tim_u - (1 << 20)) tim_read = tim_u - (1 << 20);
+        if (tim_u < -(1 << 24)) {
+            tim_u += 1 << 24;
+            tim_read += 1 << 24;
+        }
+    }
+
+    __host__ __device__ __forceinline__ void load(const StateRec &r) {
+        a = r.a; x = r.x; y = r.y; s = r.s; p = r.p; pc = r.pc; bank = r.bank; jam = r.status & 1u;
+        cyc = r.cyc; col = r.col; pf = r.pf; vb = r.vblank | ((uint32_t)r.vsync << 8);
+        tim_u = r.tim_u; tim_read = r.tim_read; tim_shift = r.tim_shift; wsync = 0;
+    }
+    __host__ __device__ __forceinline__ void store(StateRec &r) const {
+        r.magic = kMagic;
+        r.a = (uint8_t)a; r.x = (uint8_t)x; r.y = (uint8_t)y; r.s = (uint8_t)s; r.p = (uint8_t)p;
+        r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u);
+        r.cyc = cyc; r.col = col; r.pf = pf; r.vblank = (uint8_t)(vb & 0xFFu); r.vsync = (uint8_t)(vb >> 8);
+        r.tim_u = tim_u; r.tim_read = tim_read; r.tim_shift = (uint8_t)tim_shift;
+    }
+};
+
+// ALE joystick action -> port values (SWCHA, INPT4).  Actions 0..17: NOOP FIRE
+// UP RIGHT LEFT DOWN UPRIGHT UPLEFT DOWNRIGHT DOWNLEFT UPFIRE RIGHTFIRE LEFTFIRE
+// DOWNFIRE UPRIGHTFIRE UPLEFTFIRE DOWNRIGHTFIRE DOWNLEFTFIRE; SWCHA bits 7/6/5/4
+// (right/left/down/up) are cleared while held, INPT4 bit 7 clears on fire.
+__host__ __device__ __forceinline__ void action_ports(uint32_t action, uint32_t *swcha, uint32_t *inpt4) {
+    // direction bits per action: up 1, down 2, left 4, right 8, fire 16
+    constexpr uint8_t dirs[18] = {0, 16, 1, 8, 4, 2, 9, 5, 10, 6, 17, 24, 20, 18, 25, 21, 26, 22};
+    const uint32_t dm = action < 18 ? dirs[action] : 0u;
+    uint32_t v = 0xFFu;
+    if (dm & 8u) v &= ~0x80u;
+    if (dm & 4u) v &= ~0x40u;
+    if (dm & 2u) v &= ~0x20u;
+    if (dm & 1u) v &= ~0x10u;
+    *swcha = v;
+    *inpt4 = (dm & 16u) ? 0x00u : 0x80u;
+}
+
+}  // namespace vcs

@@ -1,0 +1,128 @@
+// Internal layouts shared by the HIP kernels and the C-ABI host code of libvcs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vcs {
+
+constexpr int kCyclesPerLine = 76;
+constexpr int kLinesPerFrame = 262;
+constexpr int kCyclesPerFrame = kCyclesPerLine * kLinesPerFrame;  // 19912
+constexpr int kClocksPerLine = 228;
+constexpr int kClocksPerFrame = kClocksPerLine * kLinesPerFrame;  // 59736
+constexpr int kHBlank = 68;
+constexpr int kScreenW = 160;
+constexpr int kScreenH = 210;
+constexpr int kPixels = kScreenW * kScreenH;  // 33600
+constexpr uint32_t kMagic = 0x31534356u;      // "VCS1"
+
+// One env's machine state in device memory (opaque to callers, 256 bytes).
+// Cycle counters are relative to the start of the current frame so that they
+// stay in 32 bits for arbitrarily long episodes.
+struct alignas(16) StateRec {
+    uint32_t magic;
+    uint8_t a, x, y, s;
+    uint8_t p, bank, status, tim_shift;  // status bit 0: jammed
+    uint16_t pc;
+    uint8_t vblank, vsync;
+    int32_t cyc;          // CPU cycles since the start of frame `frame`
+    uint32_t frame;       // frames since power-on
+    int32_t tim_u;        // first cycle (frame-relative) at which the timer reads as underflowed
+    int32_t tim_read;     // cycle (frame-relative) of the last INTIM read
+    uint32_t col;         // COLUP0 | COLUP1 << 8 | COLUPF << 16 | COLUBK << 24
+    uint32_t pf;          // PF0 | PF1 << 8 | PF2 << 16 | CTRLPF << 24
+    uint32_t episode;     // episodes completed since the last vcs_reset
+    uint32_t ep_step;     // env steps taken in the current episode
+    // soft checkpoints only:
+    int64_t next_ckpt;    // cycle (since power-on) at which the next checkpoint is due
+    int32_t pix_cc;       // frame-relative colour clock of the last instruction's write point
+    uint32_t ckpt_index;  // index of this checkpoint
+    uint32_t pad[16];
+    uint8_t ram[128];
+};
+static_assert(sizeof(StateRec) == 256, "state record must be 256 bytes");
+
+// Static per-context device data (uploaded once per workspace).
+struct StaticHdr {
+    int32_t num_roms, num_envs;
+    int32_t main_slots_per_block, main_blocks;  // hard / soft-forward grouping
+    int32_t bwd_slots_per_block, bwd_blocks;    // soft-backward grouping (one lane per env)
+    int32_t max_rom_size, total_rom_bytes;
+    // byte offsets (from the start of the static region) of the arrays below
+    int64_t off_rom_off, off_rom_size, off_rom_mapper;  // int32 [R]
+    int64_t off_main_block_rom, off_main_slot_env;      // int32 [blocks], [blocks*slots]
+    int64_t off_bwd_block_rom, off_bwd_slot_env;        // int32 [blocks], [blocks*slots]
+    int64_t off_env_bwd_slot;                           // int32 [B]
+    int64_t off_rom_bwd_slot_begin, off_rom_bwd_slot_end;  // int32 [R]
+    int64_t bytes;
+};
+
+struct StaticPtrs {
+    const int32_t *rom_off, *rom_size, *rom_mapper;
+    const int32_t *main_block_rom, *main_slot_env;
+    const int32_t *bwd_block_rom, *bwd_slot_env;
+    const int32_t *env_bwd_slot;
+    const int32_t *rom_bwd_slot_begin, *rom_bwd_slot_end;
+};
+
+// Parameters of the emulation-step kernels (hard steps and the soft forward).
+struct StepParams {
+    StaticPtrs st;
+    const uint8_t *rom;        // concatenated ROM images
+    StateRec *state;           // [B] in/out (NULL for a soft forward without state output)
+    const uint8_t *actions;    // [B][S] or NULL
+    int32_t steps;             // S
+    int32_t frame_skip;        // F
+    int32_t ystart;
+    int32_t frames_mode;       // 0 none, 1 last step, 2 every step
+    uint8_t *ram_out;          // [B][S][128] u8 (hard) or NULL
+    uint8_t *frame_out;        // u8 frames (hard) or NULL
+    float *ram_out_f;          // [B][S][128] f32 (soft) or NULL
+    float *frame_out_f;        // [B][210][160] f32 (soft) or NULL
+    uint8_t *done;             // [B][S] or NULL
+    const uint32_t *ep_steps;  // [B][E] or NULL
+    int32_t num_episodes;
+    uint64_t seed;
+    // soft forward
+    const uint8_t *ram0;       // [B][128]: start every env from power-on with this RAM (NULL: load state)
+    StateRec *ckpt;            // [B][max_ckpt] or NULL
+    int32_t *ckpt_count;       // [B]
+    int32_t ckpt_interval;
+    int32_t max_ckpt;
+};
+
+// One record of the soft backward's recompute tape (32 bytes).
+struct alignas(16) TapeRec {
+    uint32_t w0;  // opcode | rd_class << 8 | wr_class << 12 | kind << 16 | has_pix << 20
+    uint32_t w1;  // rd_idx | wr_idx << 16
+    uint32_t w2;  // v1 | v2 << 8 | s_before << 16
+    uint32_t w3;  // env step of the instruction / marker
+    float pix[4]; // dL/dpixel summed per owning colour register (COLUP0, COLUP1, COLUPF, COLUBK)
+};
+
+enum TapeKind : uint32_t { kRecInstr = 0, kRecStepEnd = 1, kRecPixels = 2 };
+enum ValClass : uint32_t { kClsConst = 0, kClsRam = 1, kClsCol = 2, kClsRom = 3, kClsSwcha = 4, kClsInpt4 = 5, kClsRegA = 6 };
+
+// Parameters of the soft backward kernel.
+struct BwdParams {
+    StaticPtrs st;
+    const uint8_t *rom;          // decoded ROM bytes (concatenated)
+    const uint8_t *ram0;         // [B][128] decoded initial RAM
+    const uint8_t *actions;      // [B][S] decoded actions
+    const StateRec *ckpt;        // [B][max_ckpt]
+    const int32_t *ckpt_count;   // [B]
+    int32_t max_ckpt;
+    int32_t steps, frame_skip, ystart;
+    int32_t ckpt_interval;
+    const float *grad_frame;     // [B][210][160]
+    const float *grad_ram_out;   // [B][S][128] or NULL
+    TapeRec *tape;               // [max_rec][bwd slots]
+    int32_t max_rec;
+    float *gpart;                // [max_rom_size][bwd slots]
+    float *gport;                // [B][S][2]
+    float *g_ram0;               // [B][128]
+    int32_t *overflow;           // set nonzero if a segment needed more than max_rec records
+};
+
+}  // namespace vcs

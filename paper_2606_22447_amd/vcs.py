@@ -1,0 +1,214 @@
+"""Torch-facing wrappers of libvcs: device buffers, streams and autograd.
+
+PyTorch provides device memory and the current HIP stream; every step of the
+emulation, the soft decode, the surrogate backward and its epilogue runs in the
+library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as Bd
+
+_FRAMES = {"none": Bd.VCS_FRAMES_NONE, "last": Bd.VCS_FRAMES_LAST, "all": Bd.VCS_FRAMES_ALL}
+_KERNELS = {"auto": Bd.VCS_KERNEL_AUTO, "plain": Bd.VCS_KERNEL_PLAIN, "grouped": Bd.VCS_KERNEL_GROUPED}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _rom_arrays(roms):
+    imgs, maps = [], []
+    for r in roms:
+        if hasattr(r, "image"):
+            imgs.append(np.asarray(r.image, np.uint8))
+            maps.append(int(r.mapper))
+        else:
+            img, mp = r
+            imgs.append(np.asarray(img, np.uint8))
+            maps.append(int(mp))
+    return imgs, maps
+
+
+class _Ctx:
+    def __init__(self, roms, env_rom, frame_skip, ystart, seed, ckpt_interval, kernel, lanes_per_env,
+                 block_threads, device):
+        imgs, maps = _rom_arrays(roms)
+        self.env_rom = np.asarray(env_rom, np.int32)
+        self.B = int(self.env_rom.size)
+        self.F = int(frame_skip)
+        self.rom_sizes = [int(i.size) for i in imgs]
+        self.h = Bd.create(self.rom_sizes, maps, self.env_rom, frame_skip, ystart, seed, ckpt_interval,
+                           _KERNELS[kernel] if isinstance(kernel, str) else int(kernel), lanes_per_env,
+                           block_threads)
+        self.device = torch.device(device)
+        self.rom = torch.from_numpy(np.concatenate(imgs)).to(self.device)
+        self._ws = {}
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and Bd._lib is not None:
+            Bd.lib().vcs_destroy(h)
+            self.h = None
+
+    def info(self):
+        return Bd.launch_info(self.h)
+
+    def workspace(self, op: int, steps: int) -> torch.Tensor:
+        n = Bd.size_query("vcs_workspace_bytes", self.h, op, steps)
+        key = (op, steps)
+        w = self._ws.get(key)
+        if w is None or w.numel() < n:
+            w = torch.empty(n, dtype=torch.uint8, device=self.device)
+            self._ws = {key: w}
+        return w
+
+
+class VcsBatch(_Ctx):
+    """B independent consoles in HARD mode (bit-exact machine)."""
+
+    def __init__(self, roms, env_rom, frame_skip: int = 4, ystart: int = 34, seed: int = 0,
+                 kernel="auto", lanes_per_env: int = 0, block_threads: int = 0, device="cuda"):
+        super().__init__(roms, env_rom, frame_skip, ystart, seed, 0, kernel, lanes_per_env, block_threads,
+                         device)
+        n = Bd.size_query("vcs_state_bytes", self.h)
+        self.state = torch.zeros(n, dtype=torch.uint8, device=self.device)
+
+    def reset(self, ram0=None, mask=None):
+        r0 = None if ram0 is None else torch.as_tensor(np.asarray(ram0, np.uint8) if not torch.is_tensor(ram0)
+                                                       else ram0, device=self.device).contiguous()
+        mk = None if mask is None else torch.as_tensor(mask, dtype=torch.uint8, device=self.device).contiguous()
+        Bd.check(Bd.lib().vcs_reset(self.h, Bd.ptr(self.state), Bd.ptr(mk), Bd.ptr(r0), _stream()), "vcs_reset")
+
+    def step(self, actions=None, steps: int | None = None, frames: str = "all", episode_steps=None,
+             ram_out=None, frame_out=None, done=None, want_done: bool = True):
+        """Run `steps` env steps in place.  Returns (ram_out [B,S,128] u8, frames, done [B,S] u8)."""
+        B = self.B
+        act = None
+        if actions is not None:
+            act = actions if torch.is_tensor(actions) else torch.from_numpy(np.asarray(actions, np.uint8))
+            act = act.to(self.device, torch.uint8).contiguous()
+            steps = act.shape[1]
+        assert steps is not None and steps >= 1
+        if ram_out is None:
+            ram_out = torch.empty((B, steps, 128), dtype=torch.uint8, device=self.device)
+        mode = _FRAMES[frames]
+        if frame_out is None and mode != Bd.VCS_FRAMES_NONE:
+            shape = (B, steps, 210, 160) if mode == Bd.VCS_FRAMES_ALL else (B, 210, 160)
+            frame_out = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        if done is None and want_done:
+            done = torch.empty((B, steps), dtype=torch.uint8, device=self.device)
+        eps, ne = None, 0
+        if episode_steps is not None:
+            eps = episode_steps if torch.is_tensor(episode_steps) else torch.from_numpy(
+                np.ascontiguousarray(episode_steps, np.uint32).view(np.int32))
+            eps = eps.to(self.device).contiguous()
+            ne = eps.shape[1]
+        work = self.workspace(Bd.VCS_OP_HARD, steps)
+        rc = Bd.lib().vcs_step_hard(self.h, Bd.ptr(self.rom), Bd.ptr(self.state), Bd.ptr(act), steps,
+                                    Bd.ptr(ram_out), mode, Bd.ptr(frame_out), Bd.ptr(done), Bd.ptr(eps), ne,
+                                    Bd.ptr(work), _stream())
+        Bd.check(rc, "vcs_step_hard")
+        return ram_out, frame_out, done
+
+    def regs(self) -> torch.Tensor:
+        out = torch.empty((self.B, 16), dtype=torch.uint8, device=self.device)
+        Bd.check(Bd.lib().vcs_read_regs(self.h, Bd.ptr(self.state), Bd.ptr(out), _stream()), "vcs_read_regs")
+        return out
+
+
+class SoftVcs(_Ctx):
+    """B consoles in SOFT-STE mode: differentiable w.r.t. ROM logits, RAM tape and action logits."""
+
+    def __init__(self, roms, env_rom, frame_skip: int = 1, ystart: int = 34, ckpt_interval: int = 1024,
+                 lanes_per_env: int = 0, block_threads: int = 0, device="cuda"):
+        super().__init__(roms, env_rom, frame_skip, ystart, 0, ckpt_interval, "grouped", lanes_per_env,
+                         block_threads, device)
+
+    def decode_split(self, dec: torch.Tensor, steps: int):
+        total = sum(self.rom_sizes)
+        rom = dec[: total * 3].view(total, 3)
+        tape = dec[total * 3: total * 3 + self.B * 128].view(self.B, 128)
+        act = dec[total * 3 + self.B * 128:].view(self.B, steps, 2)
+        return rom, tape, act
+
+    def forward(self, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0,
+                want_decode: bool = False, want_state: bool = False):
+        B, S = self.B, action_logits.shape[1]
+        dev = self.device
+        ram_out = torch.empty((B, S, 128), dtype=torch.float32, device=dev)
+        frame = torch.empty((B, 210, 160), dtype=torch.float32, device=dev)
+        residual = torch.empty(Bd.size_query("vcs_residual_bytes", self.h, S), dtype=torch.uint8, device=dev)
+        dec = None
+        if want_decode:
+            dec = torch.empty(Bd.size_query("vcs_decode_bytes", self.h, S) // 4, dtype=torch.float32, device=dev)
+        st = torch.empty(B * Bd.STATE_BYTES, dtype=torch.uint8, device=dev) if want_state else None
+        work = self.workspace(Bd.VCS_OP_SOFT_FWD, S)
+        rc = Bd.lib().vcs_step_soft_fwd(self.h, Bd.ptr(rom_logits), Bd.ptr(ram_tape), Bd.ptr(action_logits),
+                                        float(tau), float(alpha), S, Bd.ptr(ram_out), Bd.ptr(frame), Bd.ptr(dec),
+                                        Bd.ptr(st), Bd.ptr(residual), Bd.ptr(work), _stream())
+        Bd.check(rc, "vcs_step_soft_fwd")
+        return ram_out, frame, residual, dec, st
+
+    def backward(self, residual, rom_logits, ram_tape, action_logits, tau: float, alpha: float, grad_frame,
+                 grad_ram_out=None, check_overflow: bool = False):
+        S = action_logits.shape[1]
+        g_rom = torch.empty_like(rom_logits)
+        g_tape = torch.empty_like(ram_tape)
+        g_act = torch.empty_like(action_logits)
+        work = self.workspace(Bd.VCS_OP_SOFT_BWD, S)
+        rc = Bd.lib().vcs_step_soft_bwd(self.h, Bd.ptr(residual), Bd.ptr(rom_logits), Bd.ptr(ram_tape),
+                                        Bd.ptr(action_logits), float(tau), float(alpha), S,
+                                        Bd.ptr(grad_frame.contiguous()),
+                                        Bd.ptr(None if grad_ram_out is None else grad_ram_out.contiguous()),
+                                        Bd.ptr(g_rom), Bd.ptr(g_tape), Bd.ptr(g_act), Bd.ptr(work), _stream())
+        Bd.check(rc, "vcs_step_soft_bwd")
+        if check_overflow:
+            flag = C.c_int32()
+            Bd.check(Bd.lib().vcs_bwd_overflow(self.h, Bd.ptr(work), S, _stream(), C.byref(flag)),
+                     "vcs_bwd_overflow")
+            if flag.value:
+                raise Bd.VcsError("soft backward tape overflow")
+        return g_rom, g_tape, g_act
+
+
+class VcsSoftFunction(torch.autograd.Function):
+    """(rom_logits, ram_tape, action_logits) -> (ram_out [B,S,128], final frame [B,210,160]).
+
+    Forward values equal the hard machine's; the backward is the hand-written
+    surrogate adjoint (recompute from hard-state checkpoints, reverse sweep)."""
+
+    @staticmethod
+    def forward(ctx, rom_logits, ram_tape, action_logits, sim: SoftVcs, tau: float, alpha: float):
+        rom_logits = rom_logits.contiguous()
+        ram_tape = ram_tape.contiguous()
+        action_logits = action_logits.contiguous()
+        ram_out, frame, residual, _, _ = sim.forward(rom_logits, ram_tape, action_logits, tau, alpha)
+        ctx.save_for_backward(rom_logits, ram_tape, action_logits, residual)
+        ctx.sim, ctx.tau, ctx.alpha = sim, tau, alpha
+        return ram_out, frame
+
+    @staticmethod
+    def backward(ctx, g_ram, g_frame):
+        rom_logits, ram_tape, action_logits, residual = ctx.saved_tensors
+        sim = ctx.sim
+        if g_frame is None:
+            g_frame = torch.zeros((sim.B, 210, 160), dtype=torch.float32, device=sim.device)
+        g_rom, g_tape, g_act = sim.backward(residual, rom_logits, ram_tape, action_logits, ctx.tau, ctx.alpha,
+                                            g_frame.float(), None if g_ram is None else g_ram.float())
+        return g_rom, g_tape, g_act, None, None, None
+
+
+def soft_rollout(sim: SoftVcs, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0):
+    return VcsSoftFunction.apply(rom_logits, ram_tape, action_logits, sim, tau, alpha)
+
+
+def ste_luminance(frame: torch.Tensor) -> torch.Tensor:
+    """Luminance (c >> 1) & 7 of palette indices, with d lum / d c = 1/2 (straight-through)."""
+    hard = ((frame.detach().to(torch.int32) >> 1) & 7).to(frame.dtype)
+    soft = frame * 0.5
+    return soft + (hard - soft).detach()

@@ -1,0 +1,176 @@
+"""GPU parity of the HARD path against the oracle (bit-exact RAM, frames, done flags)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_22447_amd import inputs as I
+from tests import asm as A
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = [("plain", 1, 64), ("plain", 1, 256), ("grouped", 1, 64), ("grouped", 1, 256),
+           ("grouped", 4, 64), ("grouped", 4, 256), ("grouped", 16, 64), ("grouped", 16, 256)]
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def oracle_env(w, b, steps=None, frames="all"):
+    rom = w.roms[int(w.env_rom[b])]
+    acts = None if w.actions is None else w.actions[b]
+    eps = None if w.episode_steps is None else w.episode_steps[b]
+    return O.run_env(rom.image, rom.mapper, w.ram0[b], acts, steps or w.steps, w.frame_skip, ep_steps=eps,
+                     seed=w.seed, env_index=b, frames=frames)
+
+
+def gpu_run(w, kernel="grouped", G=0, tpb=0, frames="all", splits=(None,)):
+    import torch
+    from paper_2606_22447_amd.vcs import VcsBatch
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel, lanes_per_env=G,
+                  block_threads=tpb)
+    vb.reset(ram0=w.ram0)
+    acts = w.actions_or_noop()
+    eps = None if w.episode_steps is None else w.episode_steps
+    rams, frs, dones = [], [], []
+    s0 = 0
+    bounds = [s for s in splits if s] + [w.steps]
+    for s1 in bounds:
+        ram, fr, dn = vb.step(actions=acts[:, s0:s1], frames=frames, episode_steps=eps)
+        torch.cuda.synchronize()
+        rams.append(ram.cpu().numpy())
+        dones.append(dn.cpu().numpy())
+        if fr is not None:
+            frs.append(fr.cpu().numpy())
+        s0 = s1
+    ram = np.concatenate(rams, axis=1)
+    done = np.concatenate(dones, axis=1)
+    fr = np.concatenate(frs, axis=1) if frames == "all" else (frs[-1] if frs else None)
+    return ram, fr, done, vb
+
+
+@pytest.mark.parametrize("kernel,G,tpb", KERNELS)
+def test_c0_every_byte(kernel, G, tpb):
+    w = I.config_c0()
+    say("c0", kernel, G, tpb)
+    ref = oracle_env(w, 0)
+    ram, fr, done, _ = gpu_run(w, kernel, G, tpb)
+    assert (ram[0] == ref["ram"]).all()
+    assert (fr[0] == ref["frames"]).all()
+    assert not done.any()
+
+
+@pytest.mark.parametrize("kernel,G,tpb", KERNELS)
+def test_c1_slice_every_byte_across_calls(kernel, G, tpb):
+    w = I.config_c1(num_envs=96, steps=12)
+    say("c1 slice", kernel, G, tpb)
+    ram, fr, done, vb = gpu_run(w, kernel, G, tpb, splits=(5, 6))
+    for b in range(w.num_envs):
+        ref = oracle_env(w, b)
+        assert (ram[b] == ref["ram"]).all(), b
+        assert (fr[b] == ref["frames"]).all(), b
+    # register view of the final state
+    regs = vb.regs().cpu().numpy()
+    for b in (0, 17, 95):
+        r = oracle_env(w, b)["regs"]
+        want = [r[k] for k in ("A", "X", "Y", "S", "P", "PCL", "PCH", "bank")]
+        assert regs[b, :8].tolist() == want
+        assert regs[b, 9] == r["INTIM"] and regs[b, 10] == r["TIMINT"]
+        assert regs[b, 12:16].tolist() == [r["COLUP0"], r["COLUP1"], r["COLUPF"], r["COLUBK"]]
+
+
+@pytest.mark.parametrize("kernel,G,tpb", [("plain", 1, 256), ("grouped", 1, 256), ("grouped", 4, 64),
+                                          ("grouped", 16, 256)])
+def test_heterogeneous_roms_with_episode_resets(kernel, G, tpb):
+    # 2K / 4K / F8 ROMs that read SWCHA, INPT4 and INTIM; short episodes force in-run resets
+    roms = [I.generate_rom(100 + i, sz, reads_inputs=True, timer_vblank=True)
+            for i, sz in enumerate([2048, 4096, 8192, 8192, 2048, 4096])]
+    B, S = 70, 10
+    env_rom = (np.arange(B) * 7 % len(roms)).astype(np.int32)
+    eps = (1 + (np.arange(B)[:, None] * 3 + np.arange(5)[None, :]) % 4).astype(np.uint32)
+    w = I.Workload("hetero_test", roms, env_rom, I.initial_ram(9, B), I.action_stream(9, B, S), S, 4,
+                   episode_steps=eps, seed=4242)
+    say("hetero", kernel, G, tpb)
+    ram, fr, done, _ = gpu_run(w, kernel, G, tpb, splits=(3,))
+    for b in range(B):
+        ref = oracle_env(w, b)
+        assert (done[b] == ref["done"]).all(), b
+        assert (ram[b] == ref["ram"]).all(), b
+        assert (fr[b] == ref["frames"]).all(), b
+
+
+def test_frames_last_and_none_modes():
+    w = I.config_c1(num_envs=8, steps=5)
+    ram_all, fr_all, _, _ = gpu_run(w, "grouped", 4, 256, frames="all")
+    ram_last, fr_last, _, _ = gpu_run(w, "grouped", 4, 256, frames="last")
+    ram_none, fr_none, _, _ = gpu_run(w, "grouped", 4, 256, frames="none")
+    assert (ram_all == ram_last).all() and (ram_all == ram_none).all()
+    assert (fr_last == fr_all[:, -1]).all() and fr_none is None
+
+
+def test_adc_sbc_all_cases_through_the_cpu():
+    # one env per (A, M, carry, decimal, op): LDA $80 ; PLP-style flag load ; ADC/SBC $81 ; PHP ; STA $82
+    def body(b):
+        b.ins("LDX", "imm", 0xFF)
+        b.ins("TXS")
+        b.ins("LDA", "zp", 0x83)      # flags byte (C, D) prepared in RAM
+        b.ins("PHA")
+        b.ins("PLP")
+        b.ins("LDA", "zp", 0x80)
+        b.ins("BIT", "zp", 0x84)      # bit 7 of $84 selects SBC
+        b.ins("BMI", "rel", "SUB")
+        b.ins("ADC", "zp", 0x81)
+        b.ins("JMP", "abs", "OUT")
+        b.label("SUB")
+        b.ins("SBC", "zp", 0x81)
+        b.label("OUT")
+        b.ins("STA", "zp", 0x82)
+        b.ins("PHP")
+        b.ins("PLA")
+        b.ins("STA", "zp", 0x85)
+        b.byte(A.JAM_OPCODE)
+    rom = A.program(body)
+    a, m, c, d, op = np.meshgrid(np.arange(256), np.arange(256), [0, 1], [0, 1], [0, 1], indexing="ij")
+    a, m, c, d, op = (v.reshape(-1) for v in (a, m, c, d, op))
+    B = a.size  # 524,288 envs
+    ram0 = np.zeros((B, 128), np.uint8)
+    ram0[:, 0], ram0[:, 1] = a, m
+    ram0[:, 3] = 0x20 | c | (d << 3)
+    ram0[:, 4] = op << 7
+    w = I.Workload("alu", [I.Rom(0, 4096, 1, rom)], np.zeros(B, np.int32), ram0, None, 1, 1)
+    say("adc/sbc brute force", B)
+    ram, _, _, _ = gpu_run(w, "grouped", 1, 256, frames="none")
+    res, flags = ram[:, 0, 2], ram[:, 0, 5]
+    exp_r = np.zeros(B, np.uint8)
+    exp_p = np.zeros(B, np.uint8)
+    for i in range(B):
+        r, p = O.alu("SBC" if op[i] else "ADC", int(a[i]), int(m[i]), 0x20 | int(c[i]) | (int(d[i]) << 3))
+        exp_r[i], exp_p[i] = r, p | 0x30
+    assert (res == exp_r).all()
+    assert (flags == exp_p).all()
+    # and end to end through the oracle's machine for a sample
+    for i in np.linspace(0, B - 1, 64).astype(int):
+        ref = O.run_env(rom, 1, ram0[i], None, 1, 1, frames="none")
+        assert (ref["ram"][0] == ram[i, 0]).all()
+
+
+def test_jam_and_reset_paths():
+    img = A.program(lambda b: (b.ins("LDA", "imm", 0x2A), b.ins("STA", "zp", A.COLUBK), b.ins("INC", "zp", 0x80),
+                               b.byte(0x02)))
+    w = I.Workload("jam", [I.Rom(0, 4096, 1, img)], np.zeros(5, np.int32), I.initial_ram(5, 5), None, 3, 2,
+                   seed=99)
+    ram, fr, _, vb = gpu_run(w, "grouped", 4, 64)
+    for b in range(5):
+        ref = oracle_env(w, b)
+        assert (ram[b] == ref["ram"]).all() and (fr[b] == ref["frames"]).all()
+    assert (vb.regs().cpu().numpy()[:, 8] & 1).all()  # jammed
+    import torch
+    vb.reset(mask=np.array([1, 0, 1, 0, 0], np.uint8))  # SplitMix64 RAM for the masked envs
+    ram2, _, _ = vb.step(steps=1, frames="none")
+    torch.cuda.synchronize()
+    ram2 = ram2.cpu().numpy()
+    for b in (0, 2):
+        ref = O.run_env(img, 1, O.splitmix_ram(99, b, 0), None, 1, 2, frames="none")
+        assert (ram2[b, 0] == ref["ram"][0]).all()
+    ref1 = oracle_env(w, 1, steps=4)
+    assert (ram2[1, 0] == ref1["ram"][3]).all()
