@@ -538,6 +538,14 @@ static uint8_t bus_read(Orc *m, uint16_t addr, int64_t t) {
     return riot_read(m, addr, t, 1);
 }
 
+/* A write to a TIA register shows from colour clock 3w+3 (R4): render the
+ * pixels before that clock with the current registers and their current
+ * content nodes before anything about the write is applied. */
+static void draw_before_write(Orc *m, uint16_t addr, int64_t w) {
+    addr &= 0x1FFF;
+    if (!(addr & 0x1000) && !(addr & 0x80)) tia_draw_until(m, 3 * (w + 1));
+}
+
 /* Data write at cycle w (R5). */
 static void bus_write(Orc *m, uint16_t addr, uint8_t v, int64_t w) {
     addr &= 0x1FFF;
@@ -656,6 +664,7 @@ void orc_alu(int op, int a, int v, int p_in, int *result, int *p_out) {
 
 static void push(Orc *m, uint8_t v, int64_t w, int32_t node) {
     uint16_t addr = (uint16_t)(0x100 | m->s);
+    draw_before_write(m, addr, w);
     if (m->g) {
         int32_t *sl = write_slot(m, addr);
         if (sl) *sl = node;
@@ -848,6 +857,7 @@ int orc_step_instruction(Orc *m) {
                 val = m->a & m->x;
                 if (g) node = g_logic(g, LOGIC_AND, g->slot_a, m->a, g->slot_x, m->x, val);
             }
+            draw_before_write(m, ea, t0 + n - 1);
             if (g) {
                 int32_t *sl = write_slot(m, ea);
                 if (sl) *sl = node;
@@ -923,6 +933,7 @@ int orc_step_instruction(Orc *m) {
                 m->a = r;
                 if (g) g->slot_a = out_node;
             } else {
+                draw_before_write(m, ea, t0 + n - 1);
                 if (g) {
                     int32_t *sl = write_slot(m, ea);
                     if (sl) *sl = out_node;
