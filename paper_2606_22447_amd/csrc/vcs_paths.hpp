@@ -1,0 +1,557 @@
+// Per-env bodies of libvcs's kernels (memory policies, hooks, the step loop
+// and the soft backward), written for one env per lane or lane group.  They are
+// host/device templates over a wave policy W so that the wave-level
+// operations (ballot, readfirstlane) stay in the kernels.
+#pragma once
+
+#include <type_traits>
+
+#include "vcs_core.hpp"
+
+namespace vcs {
+
+// ---------------------------------------------------------------------------
+// Memory policies
+// ---------------------------------------------------------------------------
+// LDS: ROM image bytes; RAM as words [32][E] so that the 4 bytes of a word
+// belong to one env and neighbouring envs hit neighbouring banks.
+struct LdsMem {
+    const uint8_t *rom;
+    uint8_t *ram;
+    uint32_t E, slot;
+    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off]; }
+    __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const {
+        return ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)];
+    }
+    __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) {
+        ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)] = (uint8_t)v;
+    }
+    __host__ __device__ __forceinline__ uint32_t ram_word(uint32_t w) const {
+        return *reinterpret_cast<const uint32_t *>(ram + ((w * E + slot) << 2));
+    }
+    __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) {
+        *reinterpret_cast<uint32_t *>(ram + ((w * E + slot) << 2)) = v;
+    }
+};
+
+// Global memory: the env's ROM image and its 128 RAM bytes in the state record.
+struct GlobalMem {
+    const uint8_t *rom;
+    uint8_t *ram;
+    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off]; }
+    __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const { return ram[cell]; }
+    __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) { ram[cell] = (uint8_t)v; }
+    __host__ __device__ __forceinline__ uint32_t ram_word(uint32_t w) const { return reinterpret_cast<const uint32_t *>(ram)[w]; }
+    __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) { reinterpret_cast<uint32_t *>(ram)[w] = v; }
+};
+
+// ---------------------------------------------------------------------------
+// Hooks
+// ---------------------------------------------------------------------------
+// Renders the returned frame lazily: before every pixel-register write the
+// pixels up to the write's effect clock are drawn with the old state.
+template <typename T>
+struct RenderHook {
+    static constexpr bool kRecord = false;
+    T *frame;         // frame being rendered, or nullptr
+    int32_t rend_cc;  // frame-relative colour clock rendered up to
+    int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
+    int32_t ystart;
+    uint32_t sub, G;
+    template <class C>
+    __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
+        if (frame) {
+            const int32_t cc = 3 * (w + 1);
+            if (cc > rend_cc) {
+                render_span(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
+                rend_cc = cc;
+            }
+        }
+    }
+    template <class C>
+    __host__ __device__ __forceinline__ void before_exec(C &) {}
+    template <class C>
+    __host__ __device__ __forceinline__ void after_exec(C &, uint32_t, int32_t, int32_t wp, ExecInfo &) {
+        pix_cc = 3 * wp;
+    }
+    template <class C>
+    __host__ __device__ __forceinline__ void finish_frame(C &c) {
+        if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
+    }
+};
+
+// Records the recompute tape of the soft backward.  Pixels of the final frame
+// are attributed to the instruction during whose span [previous write point,
+// this write point) they were drawn, with the state before its write.
+struct TapeHook {
+    static constexpr bool kRecord = true;
+    TapeRec *tape;
+    uint32_t stride;
+    int32_t nrec, max_rec;
+    const float *gframe;  // env's dL/dframe while in the final frame, else nullptr
+    int32_t pix_cc;
+    int32_t ystart;
+    uint32_t step;
+    uint32_t save_pf, save_vb;
+    int32_t *overflow;
+    __host__ __device__ __forceinline__ void emit(const TapeRec &r) {
+        if (nrec < max_rec) tape[(size_t)nrec * stride] = r;
+        else *overflow = 1;
+        ++nrec;
+    }
+    template <class C>
+    __host__ __device__ __forceinline__ void before_pixel_write(C &, int32_t) {}
+    template <class C>
+    __host__ __device__ __forceinline__ void before_exec(C &c) {
+        save_pf = c.pf;
+        save_vb = c.vb;
+    }
+    template <class C>
+    __host__ __device__ __forceinline__ void after_exec(C &, uint32_t opc, int32_t, int32_t wp, ExecInfo &info) {
+        TapeRec r;
+        r.w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16);
+        r.w1 = info.rd_idx | (info.wr_idx << 16);
+        r.w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
+        r.w3 = step;
+        r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
+        if (gframe && pixel_sums(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) r.w0 |= 1u << 20;
+        pix_cc = 3 * wp;
+        emit(r);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Per-env bodies of the kernels.  W is the wave policy: any(v) (is v true in
+// any lane of the wave) and first(v) (v of the first active lane); on the GPU
+// they are a ballot and readfirstlane, and the ROM image must already be
+// staged in LDS by the whole workgroup.
+// ---------------------------------------------------------------------------
+template <class W, int G, bool kSoft, bool kPlain, class Mem>
+__host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
+                                                  Mem mem, const uint32_t *decode) {
+    static_assert(!(kSoft && kPlain), "the soft forward uses the grouped kernel");
+    using T = typename std::conditional<kSoft, float, uint8_t>::type;
+    const bool live = env >= 0;
+    const int32_t S = P.steps, F = P.frame_skip;
+
+    Cpu<Mem, RenderHook<T>> c;
+    c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
+    c.f8 = mapper == 2 ? 1u : 0u;
+    c.mem = mem;
+    c.hook.frame = nullptr;
+    c.hook.rend_cc = 0;
+    c.hook.pix_cc = 0;
+    c.hook.ystart = P.ystart;
+    c.hook.sub = sub;
+    c.hook.G = G;
+    uint32_t frame = 0, episode = 0, ep_step = 0;
+    if (live) {
+        if (P.ram0) {  // soft forward: power-on with the decoded RAM
+            const uint32_t *r0 = reinterpret_cast<const uint32_t *>(P.ram0 + (size_t)env * 128);
+            for (uint32_t w = sub; w < 32; w += G) c.mem.ram_word_set(w, r0[w]);
+            c.power_on();
+        } else {
+            const StateRec &st = P.state[env];
+            c.load(st);
+            c.bank &= c.f8;  // only F8 images have a second bank
+            frame = st.frame;
+            episode = st.episode;
+            ep_step = st.ep_step;
+            if constexpr (!kPlain) {
+                const uint32_t *rw = reinterpret_cast<const uint32_t *>(st.ram);
+                for (uint32_t w = sub; w < 32; w += G) c.mem.ram_word_set(w, rw[w]);
+            }
+            if (st.status & 2u) {  // power-on requested by vcs_reset
+                c.power_on();
+                frame = 0;
+            }
+        }
+    }
+
+    int32_t s_idx = 0, fstep = 0;
+    bool active = live && S > 0;
+    auto set_ports = [&]() {
+        const uint32_t act = P.actions ? P.actions[(size_t)env * S + s_idx] : 0u;
+        action_ports(act, &c.swcha, &c.inpt4);
+    };
+    auto start_frame = [&]() {
+        c.hook.rend_cc = 0;
+        c.hook.frame = nullptr;
+        const bool last_of_step = fstep == F - 1;
+        if constexpr (kSoft) {
+            if (P.frame_out_f && last_of_step && s_idx == S - 1) c.hook.frame = P.frame_out_f + (size_t)env * kPixels;
+        } else {
+            if (P.frame_out && last_of_step) {
+                if (P.frames_mode == 2) c.hook.frame = P.frame_out + ((size_t)env * S + s_idx) * kPixels;
+                else if (P.frames_mode == 1 && s_idx == S - 1) c.hook.frame = P.frame_out + (size_t)env * kPixels;
+            }
+        }
+    };
+    if (active) {
+        set_ports();
+        start_frame();
+    }
+    // soft forward: hard-state checkpoints every K cycles since power-on
+    int64_t next_ckpt = P.ckpt_interval;
+    int32_t nckpt = 0;
+
+    while (W::any(active)) {
+        if (active) {
+            if constexpr (kSoft) {
+                if (P.ckpt) {
+                    const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
+                    if (g >= next_ckpt) {
+                        next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
+                        if (nckpt < P.max_ckpt) {
+                            StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
+                            if (sub == 0) {
+                                c.store(r);
+                                r.frame = frame;
+                                r.episode = 0;
+                                r.ep_step = (uint32_t)s_idx;
+                                r.next_ckpt = next_ckpt;
+                                r.pix_cc = c.hook.pix_cc;
+                                r.ckpt_index = (uint32_t)nckpt;
+                            }
+                            uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
+                            for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
+                        }
+                        ++nckpt;
+                    }
+                }
+            }
+            if (c.jam || c.cyc >= kCyclesPerFrame) {
+                // ---- end of frame
+                if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;  // a jammed CPU lets the cycles elapse
+                c.hook.finish_frame(c);
+                c.next_frame();
+                c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
+                ++frame;
+                if (++fstep == F) {
+                    // ---- end of env step
+                    if constexpr (kSoft) {
+                        if (P.ram_out_f) {
+                            float4 *o = reinterpret_cast<float4 *>(P.ram_out_f + ((size_t)env * S + s_idx) * 128);
+                            for (uint32_t w = sub; w < 32; w += G) {
+                                const uint32_t v = c.mem.ram_word(w);
+                                o[w] = make_float4((float)(v & 0xFFu), (float)((v >> 8) & 0xFFu),
+                                                   (float)((v >> 16) & 0xFFu), (float)(v >> 24));
+                            }
+                        }
+                    } else {
+                        if (P.ram_out) {
+                            uint32_t *o = reinterpret_cast<uint32_t *>(P.ram_out + ((size_t)env * S + s_idx) * 128);
+                            for (uint32_t w = sub; w < 32; w += G) o[w] = c.mem.ram_word(w);
+                        }
+                    }
+                    ++ep_step;
+                    uint32_t done = 0;
+                    if (P.ep_steps && (int32_t)episode < P.num_episodes &&
+                        ep_step >= P.ep_steps[(size_t)env * P.num_episodes + episode]) {
+                        // episode over: in-run reset with SplitMix64 RAM for the next episode
+                        done = 1;
+                        ++episode;
+                        for (uint32_t w = sub; w < 16; w += G) {
+                            const uint64_t v = reset_ram_word(P.seed, (uint64_t)env, episode, w);
+                            c.mem.ram_word_set(2 * w, (uint32_t)v);
+                            c.mem.ram_word_set(2 * w + 1, (uint32_t)(v >> 32));
+                        }
+                        c.power_on();
+                        frame = 0;
+                        ep_step = 0;
+                    }
+                    if (P.done && sub == 0) P.done[(size_t)env * S + s_idx] = (uint8_t)done;
+                    fstep = 0;
+                    if (++s_idx == S) {
+                        active = false;
+                    } else {
+                        set_ports();
+                    }
+                }
+                if (active) start_frame();
+            } else {
+                // ---- one instruction
+                const uint32_t pc = c.pc;
+                const uint32_t opc = c.peek(pc, c.cyc);
+                const uint32_t lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
+                const uint32_t hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+                ExecInfo info;
+                if constexpr (kPlain) {
+                    const uint32_t d = decode[opc];
+                    if (d == 0) c.jam = 1;
+                    else c.exec(opc, d, lo, hi, info);
+                } else {
+                    // waterfall: each pass executes one distinct opcode of the wave
+                    // with a wave-uniform (scalar) decode
+                    for (;;) {
+                        const uint32_t u = W::first(opc);
+                        if (opc == u) {
+                            const uint32_t d = decode[u];
+                            if (d == 0) c.jam = 1;
+                            else c.exec(u, d, lo, hi, info);
+                            break;
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if (live) {
+        if (P.state) {
+            StateRec &st = P.state[env];
+            if (sub == 0) {
+                c.store(st);
+                st.frame = frame;
+                st.episode = episode;
+                st.ep_step = ep_step;
+            }
+            if constexpr (!kPlain) {
+                uint32_t *rw = reinterpret_cast<uint32_t *>(st.ram);
+                for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
+            }
+        }
+        if constexpr (kSoft) {
+            if (P.ckpt_count && sub == 0) P.ckpt_count[env] = nckpt;
+        }
+    }
+}
+
+// Soft backward of one env: segments from last to first are recomputed from
+// their checkpoint into the tape and swept in reverse.  adj_ram is the env's
+// RAM adjoint, float [128] with stride E.
+template <class W>
+__host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
+                                                 int32_t mapper, LdsMem mem, float *adj_ram, uint32_t E,
+                                                 const uint32_t *decode) {
+    const bool live = env >= 0;
+    const int32_t S = P.steps, F = P.frame_skip, K = P.ckpt_interval;
+    for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] = 0.f;
+
+    Cpu<LdsMem, TapeHook> c;
+    c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
+    c.f8 = mapper == 2 ? 1u : 0u;
+    c.mem = mem;
+    c.hook.tape = P.tape + gslot;
+    c.hook.stride = nslots;
+    c.hook.max_rec = P.max_rec;
+    c.hook.ystart = P.ystart;
+    c.hook.overflow = P.overflow;
+
+    float aA = 0.f, aX = 0.f, aY = 0.f;
+    float aC[4] = {0.f, 0.f, 0.f, 0.f};
+    const float *gframe_env = live ? P.grad_frame + (size_t)env * kPixels : nullptr;
+    const int32_t nck = live ? (P.ckpt_count[env] < P.max_ckpt ? P.ckpt_count[env] : P.max_ckpt) : 0;
+    const int32_t nseg = live ? nck + 1 : 0;
+    int32_t seg = nseg - 1;
+
+    auto add_src = [&](uint32_t cls, uint32_t idx, uint32_t step, float t) {
+        switch (cls) {
+            case kClsRam: adj_ram[idx * E] += t; break;
+            case kClsRom: P.gpart[(size_t)idx * nslots + gslot] += t; break;
+            case kClsSwcha: P.gport[((size_t)env * S + step) * 2] += t; break;
+            case kClsInpt4: P.gport[((size_t)env * S + step) * 2 + 1] += t; break;
+            case kClsRegA: aA += t; break;
+            default: break;
+        }
+    };
+    auto take_dst = [&](uint32_t cls, uint32_t idx) -> float {
+        float t = 0.f;
+        if (cls == kClsRam) {
+            t = adj_ram[idx * E];
+            adj_ram[idx * E] = 0.f;
+        } else if (cls == kClsCol) {
+            t = aC[0] * (idx == 0) + aC[1] * (idx == 1) + aC[2] * (idx == 2) + aC[3] * (idx == 3);
+            aC[0] = idx == 0 ? 0.f : aC[0];
+            aC[1] = idx == 1 ? 0.f : aC[1];
+            aC[2] = idx == 2 ? 0.f : aC[2];
+            aC[3] = idx == 3 ? 0.f : aC[3];
+        } else if (cls == kClsRegA) {
+            t = aA;
+            aA = 0.f;
+        }
+        return t;
+    };
+    auto zero_push = [&](uint32_t cell) {
+        uint32_t idx;
+        const uint32_t cls = write_class(0x100u | (cell & 0xFFu), &idx);
+        (void)take_dst(cls, idx);
+    };
+
+    while (W::any(seg >= 0)) {
+        if (seg >= 0) {
+            // ---- restore the segment's starting state
+            int64_t seg_end;
+            uint32_t frame;
+            if (seg == 0) {
+                const uint32_t *r0 = reinterpret_cast<const uint32_t *>(P.ram0 + (size_t)env * 128);
+                for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, r0[w]);
+                c.power_on();
+                frame = 0;
+                c.hook.pix_cc = 0;
+                seg_end = K;
+            } else {
+                const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + (seg - 1)];
+                c.load(r);
+                c.bank &= c.f8;
+                const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
+                for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, rw[w]);
+                frame = r.frame;
+                c.hook.pix_cc = r.pix_cc;
+                seg_end = r.next_ckpt;
+            }
+            if (seg == nseg - 1) seg_end = INT64_MAX;
+            int32_t s_idx = (int32_t)(frame / (uint32_t)F), fstep = (int32_t)(frame % (uint32_t)F);
+            c.hook.nrec = 0;
+            auto set_ports = [&]() {
+                action_ports(P.actions[(size_t)env * S + s_idx], &c.swcha, &c.inpt4);
+                c.hook.step = (uint32_t)s_idx;
+                c.hook.gframe = (s_idx == S - 1 && fstep == F - 1) ? gframe_env : nullptr;
+            };
+            bool rec_active = s_idx < S;
+            if (rec_active) set_ports();
+
+            // ---- recompute the segment, recording the tape
+            while (W::any(rec_active)) {
+                if (rec_active) {
+                    const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
+                    if (g >= seg_end) {
+                        rec_active = false;
+                    } else if (c.jam || c.cyc >= kCyclesPerFrame) {
+                        if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;
+                        if (c.hook.gframe) {  // tail of the final frame
+                            TapeRec r;
+                            r.w0 = kRecPixels << 16;
+                            r.w1 = r.w2 = 0;
+                            r.w3 = (uint32_t)s_idx;
+                            r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
+                            pixel_sums(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.pf, c.vb, c.hook.ystart, r.pix);
+                            c.hook.emit(r);
+                        }
+                        c.next_frame();
+                        c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
+                        ++frame;
+                        if (++fstep == F) {
+                            TapeRec r;
+                            r.w0 = kRecStepEnd << 16;
+                            r.w1 = r.w2 = 0;
+                            r.w3 = (uint32_t)s_idx;
+                            r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
+                            c.hook.emit(r);
+                            fstep = 0;
+                            if (++s_idx == S) rec_active = false;
+                        }
+                        if (rec_active) set_ports();
+                    } else {
+                        const uint32_t pc = c.pc;
+                        const uint32_t opc = c.peek(pc, c.cyc);
+                        const uint32_t lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
+                        const uint32_t hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+                        ExecInfo info;
+                        for (;;) {
+                            const uint32_t u = W::first(opc);
+                            if (opc == u) {
+                                const uint32_t d = decode[u];
+                                if (d == 0) c.jam = 1;
+                                else c.exec(u, d, lo, hi, info);
+                                break;
+                            }
+                        }
+                    }
+                }
+            }
+
+            // ---- reverse sweep of the segment's tape
+            const int32_t nrec = c.hook.nrec < c.hook.max_rec ? c.hook.nrec : c.hook.max_rec;
+            for (int32_t i = nrec - 1; i >= 0; --i) {
+                const TapeRec r = c.hook.tape[(size_t)i * nslots];
+                const uint32_t kind = (r.w0 >> 16) & 15u;
+                const uint32_t step = r.w3;
+                if (kind == kRecStepEnd) {
+                    if (P.grad_ram_out) {
+                        const float *gr = P.grad_ram_out + ((size_t)env * S + step) * 128;
+                        for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] += gr[cidx];
+                    }
+                    continue;
+                }
+                if (kind == kRecPixels) {
+                    aC[0] += r.pix[0];
+                    aC[1] += r.pix[1];
+                    aC[2] += r.pix[2];
+                    aC[3] += r.pix[3];
+                    continue;
+                }
+                const uint32_t opc = r.w0 & 0xFFu;
+                const uint32_t rd = (r.w0 >> 8) & 15u, wr = (r.w0 >> 12) & 15u;
+                const uint32_t rd_idx = r.w1 & 0xFFFFu, wr_idx = r.w1 >> 16;
+                const float v1 = (float)(r.w2 & 0xFFu), v2 = (float)((r.w2 >> 8) & 0xFFu);
+                const uint32_t sb = (r.w2 >> 16) & 0xFFu;
+                const uint32_t d = decode[opc];
+                const uint32_t cls = d & 63u;
+                switch (cls) {
+                    case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
+                    case C_LDX: { const float t = aX; aX = 0.f; add_src(rd, rd_idx, step, t); break; }
+                    case C_LDY: { const float t = aY; aY = 0.f; add_src(rd, rd_idx, step, t); break; }
+                    case C_LAX: { const float t = aA + aX; aA = aX = 0.f; add_src(rd, rd_idx, step, t); break; }
+                    case C_STA: aA += take_dst(wr, wr_idx); break;
+                    case C_STX: aX += take_dst(wr, wr_idx); break;
+                    case C_STY: aY += take_dst(wr, wr_idx); break;
+                    case C_SAX: {  // mem = A & X: d/dA = X/255, d/dX = A/255
+                        const float t = take_dst(wr, wr_idx);
+                        aA += t * (v2 / 255.f);
+                        aX += t * (v1 / 255.f);
+                        break;
+                    }
+                    case C_ADC: add_src(rd, rd_idx, step, aA); break;
+                    case C_SBC: add_src(rd, rd_idx, step, -aA); break;
+                    case C_AND: {  // A' = A & M with v1 = A, v2 = M
+                        const float t = aA;
+                        aA = t * (v2 / 255.f);
+                        add_src(rd, rd_idx, step, t * (v1 / 255.f));
+                        break;
+                    }
+                    case C_ORA: {
+                        const float t = aA;
+                        aA = t * ((255.f - v2) / 255.f);
+                        add_src(rd, rd_idx, step, t * ((255.f - v1) / 255.f));
+                        break;
+                    }
+                    case C_EOR: {
+                        const float t = aA;
+                        aA = t * ((255.f - 2.f * v2) / 255.f);
+                        add_src(rd, rd_idx, step, t * ((255.f - 2.f * v1) / 255.f));
+                        break;
+                    }
+                    case C_ASL: case C_ROL: case C_LSR: case C_ROR: case C_INC: case C_DEC: {
+                        const float k = (cls == C_ASL || cls == C_ROL) ? 2.f : (cls == C_LSR || cls == C_ROR) ? 0.5f : 1.f;
+                        const float t = take_dst(wr, wr_idx) * k;
+                        add_src(rd, rd_idx, step, t);
+                        break;
+                    }
+                    case C_TAX: aA += aX; aX = 0.f; break;
+                    case C_TAY: aA += aY; aY = 0.f; break;
+                    case C_TXA: aX += aA; aA = 0.f; break;
+                    case C_TYA: aY += aA; aA = 0.f; break;
+                    case C_TSX: aX = 0.f; break;
+                    case C_PHA: aA += take_dst(wr, wr_idx); break;
+                    case C_PLA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
+                    case C_PHP: zero_push(sb); break;
+                    case C_JSR: zero_push(sb); zero_push(sb - 1u); break;
+                    case C_BRK: zero_push(sb); zero_push(sb - 1u); zero_push(sb - 2u); break;
+                    default: break;  // flags, compares, branches, jumps, pulls into P/PC: no content
+                }
+                if (r.w0 & (1u << 20)) {  // pixels drawn before this instruction's write
+                    aC[0] += r.pix[0];
+                    aC[1] += r.pix[1];
+                    aC[2] += r.pix[2];
+                    aC[3] += r.pix[3];
+                }
+            }
+            --seg;
+        }
+    }
+    if (live)
+        for (uint32_t cidx = 0; cidx < 128; ++cidx) P.g_ram0[(size_t)env * 128 + cidx] = adj_ram[cidx * E];
+}
+
+}  // namespace vcs
