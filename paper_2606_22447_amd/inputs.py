@@ -435,7 +435,10 @@ class _Gen:
             b.ins("STA", "zp", v)
             c = 11
         elif kind == "shift":
-            b.ins(r.choice(["ASL", "LSR", "ROL", "ROR"]), "zp", self.var())
+            # right shifts only in per-line code: under the straight-through
+            # rule a left shift doubles the gradient, and a variable shifted on
+            # every one of 192 lines would grow its gradient like 2**192
+            b.ins(r.choice(["LSR", "ROR"]), "zp", self.var())
             c = 5
         elif kind == "eor_col":
             b.ins("LDA", "zp", self.var())
@@ -552,7 +555,7 @@ class _Gen:
                 b.ins(r.choice(["AND", "ORA", "EOR"]), "imm", r.randint(0, 255))
                 b.ins("STA", "zp", v)
             elif kind == "shift":
-                b.ins(r.choice(["ASL", "LSR", "ROL", "ROR"]), "zp", self.var())
+                b.ins(r.choice(["LSR", "ROR"]), "zp", self.var())
             elif kind == "lax":
                 b.ins("LAX", "zp", self.var())
                 b.ins("STA", "zp", self.var())
