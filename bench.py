@@ -179,7 +179,7 @@ def _cpu_worker(args):
     return time.perf_counter() - t0, len(envs) * steps, instr
 
 
-def cpu_leg(envs_per_proc=2, steps=120):
+def cpu_leg(envs_per_proc=4, steps=500):
     import multiprocessing as mp
     from oracle import build as obuild
     obuild.build(force=False)

@@ -87,7 +87,7 @@ typedef struct vcs_config {
     uint64_t seed;              /* SplitMix64 seed of in-run reset RAM */
     int32_t ckpt_interval;      /* soft backward: hard-state checkpoint every K cycles (>= 64) */
     int32_t kernel;             /* vcs_kernel */
-    int32_t lanes_per_env;      /* GROUPED kernel: lanes cooperating on one env (1, 4 or 16; 0 = auto) */
+    int32_t lanes_per_env;      /* GROUPED kernel: lanes cooperating on one env (1, 4, 16 or 64; 0 = auto) */
     int32_t block_threads;      /* GROUPED kernel: threads per workgroup (64 or 256; 0 = auto) */
 } vcs_config;
 

@@ -218,14 +218,21 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         c->G = 1;
     } else if (cfg->lanes_per_env) {
         c->G = cfg->lanes_per_env;
-        if (c->G != 1 && c->G != 4 && c->G != 16) {
+        if (c->G != 1 && c->G != 4 && c->G != 16 && c->G != 64) {
             delete c;
             return VCS_UNSUPPORTED;
         }
     } else {
-        // enough lane groups to give every SIMD of the chip (1024 on MI355X) one wave
-        const int64_t lanes = (int64_t)c->B * 16;
-        c->G = lanes <= 1024 * 64 ? 16 : ((int64_t)c->B * 4 <= 1024 * 64 ? 4 : 1);
+        // Each env is a serial chain, so throughput comes from interleaving many
+        // waves per SIMD: take the widest lane group that still fits about four
+        // waves on each of the chip's 1024 SIMDs (256 CUs x 4).
+        const int64_t lanes_budget = 1024LL * 4 * 64;
+        c->G = (int64_t)c->B * 64 <= lanes_budget ? 64 : (int64_t)c->B * 16 <= lanes_budget ? 16
+             : (int64_t)c->B * 4 <= lanes_budget ? 4 : 1;
+    }
+    if (c->tpb < c->G) {
+        delete c;
+        return VCS_UNSUPPORTED;
     }
     c->main_E = c->tpb / c->G;
     group_by_rom(c, c->main_E, c->main_block_rom, c->main_slot_env);
@@ -367,7 +374,7 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
     P.num_episodes = d_episode_steps ? num_episodes : 0;
     P.seed = ctx->seed;
     return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
-                                  stream));
+                                  ctx->max_rom, stream));
 }
 
 int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,
@@ -410,7 +417,7 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *
     P.ckpt_count = (int32_t *)(res + L.ckpt_count);
     P.ckpt_interval = ctx->K;
     P.max_ckpt = L.max_ckpt;
-    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, stream));
+    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, ctx->max_rom, stream));
     if (rc) return rc;
     if (d_decode_out &&
         hipMemcpyAsync(d_decode_out, res + L.stats, L.stats_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)

@@ -25,9 +25,20 @@ __constant__ DecodeTable kDecodeDev = make_decode_table();
 // ---------------------------------------------------------------------------
 // Wave policy of the device bodies
 // ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) uint32_t ConstU32;
+
 struct DeviceWave {
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
     __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+    // entry u (wave-uniform) of a read-only table in constant memory: a scalar
+    // load, so that what is derived from it stays in scalar registers and the
+    // branches on it are scalar branches
+    // (u goes through an empty asm so that the compiler cannot substitute an
+    // equal per-lane value for it and turn the load into a vector load).
+    __device__ static __forceinline__ uint32_t table(const uint32_t *t, uint32_t u) {
+        asm volatile("" : "+s"(u));
+        return __builtin_amdgcn_readfirstlane(((ConstU32 *)t)[u]);
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -37,7 +48,7 @@ struct DeviceWave {
 template <int G, int TPB, bool kSoft, bool kPlain>
 __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     constexpr int E = TPB / G;
-    __shared__ __align__(16) uint8_t rom_lds[kPlain ? 16 : 8192];
+    extern __shared__ __align__(16) uint32_t rom_lds[];  // pre-decoded ROM words, sized to the largest image
     __shared__ __align__(16) uint32_t ram_lds[kPlain ? 4 : 32 * E];
     const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
     const int32_t blk = blockIdx.x;
@@ -49,34 +60,36 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
         GlobalMem m{P.rom + rom_base, env >= 0 ? P.state[env].ram : nullptr};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
     } else {
-        for (int32_t i = (int32_t)tid * 16; i < rom_size; i += TPB * 16)
-            *reinterpret_cast<uint4 *>(rom_lds + i) = *reinterpret_cast<const uint4 *>(P.rom + rom_base + i);
+        for (int32_t i = (int32_t)tid; i < rom_size; i += TPB) rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper);
         __syncthreads();
-        LdsMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
+        LdsWordMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Soft backward: one env per lane, 64 envs of one ROM per workgroup.
+// Soft backward: one env per wave (its first lane), kBwdEnvs envs of one ROM
+// per workgroup.  The recompute-and-reverse chain of an env is serial, so the
+// envs are spread over as many waves as possible to interleave their latency.
 // ---------------------------------------------------------------------------
-constexpr int kBwdTPB = 64;
+constexpr int kBwdTPB = kBwdSlots * 64;
 
 __global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
-    constexpr int E = kBwdTPB;
+    constexpr int E = kBwdSlots;
     __shared__ __align__(16) uint8_t rom_lds[8192];
     __shared__ __align__(16) uint32_t ram_lds[32 * E];
     __shared__ float adj_ram[128 * E];
-    const uint32_t tid = threadIdx.x, slot = tid;
+    const uint32_t tid = threadIdx.x, slot = tid / 64;
     const int32_t blk = blockIdx.x;
     const uint32_t nslots = (uint32_t)gridDim.x * E;
     const uint32_t gslot = (uint32_t)blk * E + slot;
     const int32_t rom_idx = P.st.bwd_block_rom[blk];
-    const int32_t env = P.st.bwd_slot_env[gslot];
     const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
     for (int32_t i = (int32_t)tid * 16; i < rom_size; i += kBwdTPB * 16)
         *reinterpret_cast<uint4 *>(rom_lds + i) = *reinterpret_cast<const uint4 *>(P.rom + rom_base + i);
     __syncthreads();
+    if ((tid & 63u) != 0) return;
+    const int32_t env = P.st.bwd_slot_env[gslot];
     LdsMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
     bwd_env<DeviceWave>(P, env, gslot, nslots, P.st.rom_mapper[rom_idx], m, adj_ram + slot, E, kDecodeDev.e);
 }
@@ -129,6 +142,15 @@ __device__ __forceinline__ RowStats row_stats(const float4 L, float tau, uint32_
     z = wave_sum(z);
     e = wave_sum(e);
     return RowStats{v, z, e / z, idx};
+}
+
+// Offset of the softmax expectation from the argmax, delta = sum_k (k - arg) w_k,
+// accumulated without the cancellation of (k - ev) near the argmax.
+__device__ __forceinline__ float row_delta(const float4 L, float tau, uint32_t lane, float m, float z, int arg) {
+    const float l[4] = {L.x, L.y, L.z, L.w};
+    float d = 0.f;
+    for (int j = 0; j < 4; ++j) d += expf((l[j] - m) / tau) * (float)((int)(lane * 4 + j) - arg);
+    return wave_sum(d) / z;
 }
 
 // ROM rows: one wave per row, 4 rows per block.
@@ -215,13 +237,15 @@ __global__ __launch_bounds__(256) void k_rom_grad(const float *logits, const flo
     for (int32_t i = slot_begin[r] + (int32_t)lane; i < slot_end[r]; i += 64) acc += (double)gpart[a * nslots + i];
     const float g = (float)wave_sum_d(acc);
     const float4 L = reinterpret_cast<const float4 *>(logits + row * 256)[lane];
-    const float ev = stats[row * 3 + 0], m = stats[row * 3 + 1], z = stats[row * 3 + 2];
+    const RowStats rs = row_stats(L, tau, lane);
+    const float delta = row_delta(L, tau, lane, rs.m, rs.z, rs.arg);  // ev - argmax
     const float l[4] = {L.x, L.y, L.z, L.w};
     float o[4];
     for (int j = 0; j < 4; ++j) {
-        const float w = expf((l[j] - m) / tau) / z;
-        o[j] = g * w * ((float)(lane * 4 + j) - ev) / tau;
+        const float w = expf((l[j] - rs.m) / tau) / rs.z;
+        o[j] = g * w * ((float)((int)(lane * 4 + j) - rs.arg) - delta) / tau;
     }
+    (void)stats;
     reinterpret_cast<float4 *>(out + row * 256)[lane] = make_float4(o[0], o[1], o[2], o[3]);
     (void)rom_size;
 }
@@ -242,18 +266,32 @@ __global__ __launch_bounds__(256) void k_act_grad(const float *logits, const flo
     const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (row >= rows) return;
     const float *L = logits + row * 18;
-    float m = L[0];
-    for (int j = 1; j < 18; ++j) m = fmaxf(m, L[j]);
-    float z = 0.f;
-    for (int j = 0; j < 18; ++j) z += expf((L[j] - m) / tau);
-    const float es = stats[row * 2], ei = stats[row * 2 + 1];
+    int best = 0;
+    for (int j = 1; j < 18; ++j)
+        if (L[j] > L[best]) best = j;
+    const float m = L[best];
+    uint32_t sw0, in0;
+    action_ports((uint32_t)best, &sw0, &in0);
+    // expectations relative to the argmax action's port values (no cancellation)
+    float z = 0.f, ds = 0.f, di = 0.f;
+    for (int j = 0; j < 18; ++j) {
+        uint32_t sw, in;
+        action_ports((uint32_t)j, &sw, &in);
+        const float w = expf((L[j] - m) / tau);
+        z += w;
+        ds += w * ((float)sw - (float)sw0);
+        di += w * ((float)in - (float)in0);
+    }
+    ds /= z;
+    di /= z;
     const float gs = gport[row * 2], gi = gport[row * 2 + 1];
     for (int j = 0; j < 18; ++j) {
         uint32_t sw, in;
         action_ports((uint32_t)j, &sw, &in);
         const float w = expf((L[j] - m) / tau) / z;
-        out[row * 18 + j] = (w / tau) * (gs * ((float)sw - es) + gi * ((float)in - ei));
+        out[row * 18 + j] = (w / tau) * (gs * (((float)sw - (float)sw0) - ds) + gi * (((float)in - (float)in0) - di));
     }
+    (void)stats;
 }
 
 // ---------------------------------------------------------------------------
@@ -321,28 +359,31 @@ __global__ void k_fill_zero(uint32_t *p, int64_t n) {
 // Launchers
 // ---------------------------------------------------------------------------
 template <int G, int TPB, bool kSoft, bool kPlain>
-static hipError_t launch_step_t(const StepParams &P, int32_t blocks, hipStream_t stream) {
-    hipLaunchKernelGGL((k_step<G, TPB, kSoft, kPlain>), dim3(blocks), dim3(TPB), 0, stream, P);
+static hipError_t launch_step_t(const StepParams &P, int32_t blocks, size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL((k_step<G, TPB, kSoft, kPlain>), dim3(blocks), dim3(TPB), kPlain ? 0 : lds, stream, P);
     return hipGetLastError();
 }
 
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
-                       hipStream_t stream) {
+                       int32_t max_rom_size, hipStream_t stream) {
+    const size_t lds = (size_t)max_rom_size * sizeof(uint32_t);
     if (plain) {
         if (soft || lanes != 1) return hipErrorInvalidValue;
-        return tpb == 64 ? launch_step_t<1, 64, false, true>(P, blocks, stream)
-                         : launch_step_t<1, 256, false, true>(P, blocks, stream);
+        return tpb == 64 ? launch_step_t<1, 64, false, true>(P, blocks, 0, stream)
+                         : launch_step_t<1, 256, false, true>(P, blocks, 0, stream);
     }
 #define VCS_STEP_CASE(Gv, Tv)                                                                \
     if (lanes == Gv && tpb == Tv)                                                            \
-        return soft ? launch_step_t<Gv, Tv, true, false>(P, blocks, stream)                  \
-                    : launch_step_t<Gv, Tv, false, false>(P, blocks, stream);
+        return soft ? launch_step_t<Gv, Tv, true, false>(P, blocks, lds, stream)             \
+                    : launch_step_t<Gv, Tv, false, false>(P, blocks, lds, stream);
     VCS_STEP_CASE(1, 64)
     VCS_STEP_CASE(1, 256)
     VCS_STEP_CASE(4, 64)
     VCS_STEP_CASE(4, 256)
     VCS_STEP_CASE(16, 64)
     VCS_STEP_CASE(16, 256)
+    VCS_STEP_CASE(64, 64)
+    VCS_STEP_CASE(64, 256)
 #undef VCS_STEP_CASE
     return hipErrorInvalidValue;
 }

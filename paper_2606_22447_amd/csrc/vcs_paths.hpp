@@ -34,6 +34,57 @@ struct LdsMem {
     }
 };
 
+// LDS with a pre-decoded ROM: word[off] = byte(off) | byte(off+1) << 8 |
+// byte(off+2) << 16, the successors taken inside the image's 2K mirror or 4K
+// bank, so one read fetches an opcode and both operand bytes.
+struct LdsWordMem {
+    const uint32_t *rom;
+    uint8_t *ram;
+    uint32_t E, slot;
+    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off] & 0xFFu; }
+    __host__ __device__ __forceinline__ uint32_t rom_word(uint32_t off) const { return rom[off]; }
+    __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const {
+        return ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)];
+    }
+    __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) {
+        ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)] = (uint8_t)v;
+    }
+    __host__ __device__ __forceinline__ uint32_t ram_word(uint32_t w) const {
+        return *reinterpret_cast<const uint32_t *>(ram + ((w * E + slot) << 2));
+    }
+    __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) {
+        *reinterpret_cast<uint32_t *>(ram + ((w * E + slot) << 2)) = v;
+    }
+};
+
+// Successor of ROM offset off inside its 2K mirror (mapper 0) or 4K bank.
+__host__ __device__ __forceinline__ uint32_t rom_next(uint32_t off, int32_t mapper) {
+    return mapper == 0 ? ((off + 1u) & 0x7FFu) : ((off & ~0xFFFu) | ((off + 1u) & 0xFFFu));
+}
+__host__ __device__ __forceinline__ uint32_t rom_word_at(const uint8_t *rom, uint32_t off, int32_t mapper) {
+    const uint32_t o1 = rom_next(off, mapper), o2 = rom_next(o1, mapper);
+    return (uint32_t)rom[off] | ((uint32_t)rom[o1] << 8) | ((uint32_t)rom[o2] << 16);
+}
+
+// Opcode and operand bytes at pc.  Inside $1000-$1FFD the three bytes lie in
+// the cartridge window; a word memory serves them with one read.
+template <class C>
+__host__ __device__ __forceinline__ void fetch3(C &c, uint32_t &opc, uint32_t &lo, uint32_t &hi) {
+    const uint32_t pc = c.pc;
+    if constexpr (std::is_same<decltype(c.mem), LdsWordMem>::value) {
+        if ((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu) {
+            const uint32_t w = c.mem.rom_word(c.cart_off(pc));
+            opc = w & 0xFFu;
+            lo = (w >> 8) & 0xFFu;
+            hi = w >> 16;
+            return;
+        }
+    }
+    opc = c.peek(pc, c.cyc);
+    lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
+    hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+}
+
 // Global memory: the env's ROM image and its 128 RAM bytes in the state record.
 struct GlobalMem {
     const uint8_t *rom;
@@ -122,9 +173,10 @@ struct TapeHook {
 
 // ---------------------------------------------------------------------------
 // Per-env bodies of the kernels.  W is the wave policy: any(v) (is v true in
-// any lane of the wave) and first(v) (v of the first active lane); on the GPU
-// they are a ballot and readfirstlane, and the ROM image must already be
-// staged in LDS by the whole workgroup.
+// any lane of the wave), first(v) (v of the first active lane) and table(t, u)
+// (entry u of a constant table, u the same in every active lane); on the GPU
+// they are a ballot, readfirstlane and a scalar load, and the ROM image must
+// already be staged in LDS by the whole workgroup.
 // ---------------------------------------------------------------------------
 template <class W, int G, bool kSoft, bool kPlain, class Mem>
 __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
@@ -271,10 +323,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                 if (active) start_frame();
             } else {
                 // ---- one instruction
-                const uint32_t pc = c.pc;
-                const uint32_t opc = c.peek(pc, c.cyc);
-                const uint32_t lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
-                const uint32_t hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+                uint32_t opc, lo, hi;
+                fetch3(c, opc, lo, hi);
                 ExecInfo info;
                 if constexpr (kPlain) {
                     const uint32_t d = decode[opc];
@@ -285,8 +335,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     // with a wave-uniform (scalar) decode
                     for (;;) {
                         const uint32_t u = W::first(opc);
+                        const uint32_t d = W::table(decode, u);
                         if (opc == u) {
-                            const uint32_t d = decode[u];
                             if (d == 0) c.jam = 1;
                             else c.exec(u, d, lo, hi, info);
                             break;
@@ -319,7 +369,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 
 // Soft backward of one env: segments from last to first are recomputed from
 // their checkpoint into the tape and swept in reverse.  adj_ram is the env's
-// RAM adjoint, float [128] with stride E.
+// RAM adjoint, float [128] with stride E.  The env's lane must be the only
+// active lane of its wave.
 template <class W>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
                                                  int32_t mapper, LdsMem mem, float *adj_ram, uint32_t E,
@@ -443,15 +494,13 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                         }
                         if (rec_active) set_ports();
                     } else {
-                        const uint32_t pc = c.pc;
-                        const uint32_t opc = c.peek(pc, c.cyc);
-                        const uint32_t lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
-                        const uint32_t hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+                        uint32_t opc, lo, hi;
+                        fetch3(c, opc, lo, hi);
                         ExecInfo info;
                         for (;;) {
                             const uint32_t u = W::first(opc);
+                            const uint32_t d = W::table(decode, u);
                             if (opc == u) {
-                                const uint32_t d = decode[u];
                                 if (d == 0) c.jam = 1;
                                 else c.exec(u, d, lo, hi, info);
                                 break;
@@ -486,7 +535,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                 const uint32_t rd_idx = r.w1 & 0xFFFFu, wr_idx = r.w1 >> 16;
                 const float v1 = (float)(r.w2 & 0xFFu), v2 = (float)((r.w2 >> 8) & 0xFFu);
                 const uint32_t sb = (r.w2 >> 16) & 0xFFu;
-                const uint32_t d = decode[opc];
+                const uint32_t d = W::table(decode, W::first(opc));  // the env's lane is the only one active
                 const uint32_t cls = d & 63u;
                 switch (cls) {
                     case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }

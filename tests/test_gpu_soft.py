@@ -88,7 +88,9 @@ def run_gpu(p: Problem, alpha=6.0, K=1024, G=0, tpb=0, grad_ram=None):
 
 def assert_grad_close(g, ref, name):
     m = np.abs(ref).max()
-    assert m > 0, name
+    if m == 0:  # no path from this leaf to the loss: structural zeros everywhere
+        assert (g == 0).all(), (name, np.abs(g).max())
+        return
     err = np.abs(g.astype(np.float64) - ref)
     assert err.max() <= 1e-4 * m, (name, err.max(), m)
     big = np.abs(ref) >= 1e-3 * m
