@@ -347,6 +347,7 @@ __host__ __device__ __forceinline__ uint32_t write_class(uint32_t addr, uint32_t
 template <class Mem, class Hook>
 struct Cpu {
     uint32_t a, x, y, s, p, pc, bank, jam;
+    uint32_t rn, rz;              // N = bit 7 of rn, Z = (low byte of rz == 0); p holds the other flags
     int32_t cyc;                  // frame-relative CPU cycle
     uint32_t col, pf, vb;         // colour registers, playfield + CTRLPF, VBLANK | VSYNC << 8
     int32_t tim_u, tim_read;
@@ -358,6 +359,17 @@ struct Cpu {
     Hook hook;
 
     __host__ __device__ __forceinline__ uint32_t cart_off(uint32_t addr) const { return (addr & amask) + (bank << 12); }
+
+    // processor status byte (B and U as stored in p)
+    __host__ __device__ __forceinline__ uint32_t flags() const {
+        return (p & ~(kFlagN | kFlagZ)) | (rn & kFlagN) | ((rz & 0xFFu) ? 0u : kFlagZ);
+    }
+    __host__ __device__ __forceinline__ void set_flags(uint32_t v) {
+        p = v;
+        rn = v & kFlagN;
+        rz = (v & kFlagZ) ? 0u : 1u;
+    }
+    __host__ __device__ __forceinline__ void set_nz(uint32_t v) { rn = rz = v; }
 
     __host__ __device__ __forceinline__ uint32_t intim_at(int32_t t) const {
         const int32_t d = t - tim_u;
@@ -403,6 +415,16 @@ struct Cpu {
         if (!(addr & 0x80u)) return tia_in(addr);
         if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
         return riot_in(addr, t, true);
+    }
+    // Page 0 and the stack page decode alike (A12 = A9 = 0): TIA below $80,
+    // RAM from $80.  These are read/write for such addresses (zero-page modes,
+    // zero-page pointers, the stack at $100 | s), with the page bits dropped.
+    __host__ __device__ __forceinline__ uint32_t read_zp(uint32_t a8) {
+        return (a8 & 0x80u) ? mem.ram_byte(a8 & 0x7Fu) : tia_in(a8);
+    }
+    __host__ __device__ __forceinline__ void write_zp(uint32_t a8, uint32_t v, int32_t w) {
+        if (a8 & 0x80u) mem.ram_set(a8 & 0x7Fu, v);
+        else tia_out(a8 & 0x3Fu, v, w);
     }
     // class of the value a data read at addr returned (after its side effects)
     __host__ __device__ __forceinline__ uint32_t read_class(uint32_t addr, uint32_t *idx) const {
@@ -462,16 +484,13 @@ struct Cpu {
             tim_u = w + 1 + (int32_t)(v << sh);
         }
     }
-    __host__ __device__ __forceinline__ void set_nz(uint32_t v) {
-        p = (p & ~(kFlagN | kFlagZ)) | (v & kFlagN) | (v ? 0u : kFlagZ);
-    }
     __host__ __device__ __forceinline__ void push(uint32_t v, int32_t w) {
-        write(0x100u | s, v, w);
+        write_zp(s, v, w);
         s = (s - 1u) & 0xFFu;
     }
-    __host__ __device__ __forceinline__ uint32_t pull(int32_t t) {
+    __host__ __device__ __forceinline__ uint32_t pull() {
         s = (s + 1u) & 0xFFu;
-        return read(0x100u | s, t);
+        return read_zp(s);
     }
 
     // NMOS ADC, binary and decimal (decimal: B. Clark, "Decimal Mode", App. A)
@@ -488,9 +507,9 @@ struct Cpu {
         const int32_t hi_s = ((int32_t)((a & 0xF0u) ^ 0x80u) - 128) + ((int32_t)((v & 0xF0u) ^ 0x80u) - 128) + lo;
         int32_t hi_u = (int32_t)(a & 0xF0u) + (int32_t)(v & 0xF0u) + lo;
         if (hi_u >= 0xA0) hi_u += 0x60;
-        p &= ~(kFlagN | kFlagZ | kFlagV | kFlagC);
-        p |= ((uint32_t)hi_s & 0x80u) | ((sum & 0xFFu) ? 0u : kFlagZ) | ((hi_s < -128 || hi_s > 127) ? kFlagV : 0u) |
-             (hi_u > 0xFF ? kFlagC : 0u);
+        p = (p & ~(kFlagV | kFlagC)) | ((hi_s < -128 || hi_s > 127) ? kFlagV : 0u) | (hi_u > 0xFF ? kFlagC : 0u);
+        rn = (uint32_t)hi_s & 0x80u;  // N from the signed high-digit sum, Z from the binary sum
+        rz = sum & 0xFFu;
         return (uint32_t)hi_u & 0xFFu;
     }
     __host__ __device__ __forceinline__ uint32_t sbc(uint32_t v) {
@@ -509,9 +528,12 @@ struct Cpu {
 
     // Execute one instruction whose opcode byte is opc (decode entry d) with
     // operand bytes lo/hi; `info` receives the data classes when recording.
+    // On the GPU opc and d are the same in every lane that runs this call, so
+    // every branch on the mode and class is a scalar branch.
     __host__ __device__ __forceinline__ void exec(uint32_t opc, uint32_t d, uint32_t lo, uint32_t hi, ExecInfo &info) {
         constexpr bool R = Hook::kRecord;
         const uint32_t cls = d & 63u, mode = (d >> 6) & 15u;
+        const bool zp = mode == M_ZP || mode == M_ZPX || mode == M_ZPY;  // ea lies in page 0
         const int32_t t0 = cyc;
         int32_t n = (int32_t)((d >> 10) & 7u);
         const uint32_t pc0 = pc;
@@ -534,18 +556,18 @@ struct Cpu {
             case M_ABY: {
                 const uint32_t base = lo | (hi << 8);
                 ea = (base + (mode == M_ABX ? x : y)) & 0xFFFFu;
-                n += (int32_t)(((d >> 13) & 1u) & (((base ^ ea) >> 8) != 0u ? 1u : 0u));
+                if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
                 break;
             }
             case M_IZX: {
                 const uint32_t z = (lo + x) & 0xFFu;
-                ea = peek(z, t0) | (peek((z + 1u) & 0xFFu, t0) << 8);
+                ea = read_zp(z) | (read_zp((z + 1u) & 0xFFu) << 8);
                 break;
             }
             case M_IZY: {
-                const uint32_t base = peek(lo, t0) | (peek((lo + 1u) & 0xFFu, t0) << 8);
+                const uint32_t base = read_zp(lo) | (read_zp((lo + 1u) & 0xFFu) << 8);
                 ea = (base + y) & 0xFFFFu;
-                n += (int32_t)(((d >> 13) & 1u) & (((base ^ ea) >> 8) != 0u ? 1u : 0u));
+                if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
                 break;
             }
             case M_IND: {
@@ -557,11 +579,12 @@ struct Cpu {
             default: break;
         }
         const int32_t tl = t0 + n - 1;  // last cycle of reads/stores (n is final here for them)
+        bool writes = false;             // the instruction may have written WSYNC
         switch (cls) {
             case C_LDA: case C_LDX: case C_LDY: case C_LAX:
             case C_ADC: case C_SBC: case C_AND: case C_ORA: case C_EOR:
             case C_CMP: case C_CPX: case C_CPY: case C_BIT: {
-                const uint32_t v = mode == M_IMM ? lo : read(ea, tl);
+                const uint32_t v = mode == M_IMM ? lo : zp ? read_zp(ea) : read(ea, tl);
                 if constexpr (R) info.rd_cls = read_class(ea, &info.rd_idx);
                 switch (cls) {
                     case C_LDA: a = v; set_nz(v); break;
@@ -579,7 +602,9 @@ struct Cpu {
                         set_nz(a);
                         break;
                     case C_BIT:
-                        p = (p & ~(kFlagN | kFlagV | kFlagZ)) | (v & (kFlagN | kFlagV)) | ((a & v) ? 0u : kFlagZ);
+                        p = (p & ~kFlagV) | (v & kFlagV);
+                        rn = v;
+                        rz = a & v;
                         break;
                     default: {  // CMP CPX CPY
                         const uint32_t r = cls == C_CMP ? a : cls == C_CPX ? x : y;
@@ -597,7 +622,9 @@ struct Cpu {
                     info.v1 = a;
                     info.v2 = x;
                 }
-                write(ea, v, tl);
+                if (zp) write_zp(ea, v, tl);
+                else write(ea, v, tl);
+                writes = true;
                 break;
             }
             case C_ASL: case C_LSR: case C_ROL: case C_ROR: case C_INC: case C_DEC: {
@@ -606,7 +633,7 @@ struct Cpu {
                     v = a;
                     if constexpr (R) info.rd_cls = info.wr_cls = kClsRegA;
                 } else {
-                    v = read(ea, t0 + n - 3);
+                    v = zp ? read_zp(ea) : read(ea, t0 + n - 3);
                     if constexpr (R) {
                         info.rd_cls = read_class(ea, &info.rd_idx);
                         info.wr_cls = write_class(ea, &info.wr_idx);
@@ -623,8 +650,13 @@ struct Cpu {
                     default: r = (v - 1u) & 0xFFu; break;
                 }
                 set_nz(r);
-                if (mode == M_ACC) a = r;
-                else write(ea, r, tl);
+                if (mode == M_ACC) {
+                    a = r;
+                } else {
+                    if (zp) write_zp(ea, r, tl);
+                    else write(ea, r, tl);
+                    writes = true;
+                }
                 break;
             }
             case C_INX: x = (x + 1u) & 0xFFu; set_nz(x); break;
@@ -640,27 +672,29 @@ struct Cpu {
             case C_PHA:
                 if constexpr (R) info.wr_cls = write_class(0x100u | s, &info.wr_idx);
                 push(a, tl);
+                writes = true;
                 break;
-            case C_PHP: push(p | kFlagB | kFlagU, tl); break;
+            case C_PHP: push(flags() | kFlagB | kFlagU, tl); writes = true; break;
             case C_PLA: {
-                const uint32_t v = pull(tl);
+                const uint32_t v = pull();
                 if constexpr (R) info.rd_cls = read_class(0x100u | s, &info.rd_idx);
                 a = v;
                 set_nz(v);
                 break;
             }
-            case C_PLP: p = (pull(tl) & ~kFlagB) | kFlagU; break;
+            case C_PLP: set_flags((pull() & ~kFlagB) | kFlagU); break;
             case C_JMP: pc = ea; break;
             case C_JSR: {
                 const uint32_t ret = (pc - 1u) & 0xFFFFu;
                 push(ret >> 8, tl);
                 push(ret & 0xFFu, tl);
                 pc = ea;
+                writes = true;
                 break;
             }
             case C_RTS: {
-                const uint32_t l = pull(tl);
-                const uint32_t h = pull(tl);
+                const uint32_t l = pull();
+                const uint32_t h = pull();
                 pc = (((h << 8) | l) + 1u) & 0xFFFFu;
                 break;
             }
@@ -668,21 +702,24 @@ struct Cpu {
                 const uint32_t ret = (pc0 + 2u) & 0xFFFFu;
                 push(ret >> 8, tl);
                 push(ret & 0xFFu, tl);
-                push(p | kFlagB | kFlagU, tl);
+                push(flags() | kFlagB | kFlagU, tl);
                 p |= kFlagI;
                 pc = peek(0x1FFEu, t0) | (peek(0x1FFFu, t0) << 8);
+                writes = true;
                 break;
             }
             case C_RTI: {
-                p = (pull(tl) & ~kFlagB) | kFlagU;
-                const uint32_t l = pull(tl);
-                const uint32_t h = pull(tl);
+                set_flags((pull() & ~kFlagB) | kFlagU);
+                const uint32_t l = pull();
+                const uint32_t h = pull();
                 pc = (h << 8) | l;
                 break;
             }
             case C_BRANCH: {
                 const uint32_t mask = (d >> 16) & 0xFFu, when_set = (d >> 24) & 1u;
-                if (((p & mask) ? 1u : 0u) == when_set) {
+                const uint32_t f = mask == kFlagN ? (rn >> 7) & 1u
+                                 : mask == kFlagZ ? ((rz & 0xFFu) ? 0u : 1u) : ((p & mask) ? 1u : 0u);
+                if (f == when_set) {
                     const uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
                     n += 1 + (((target ^ pc) & 0xFF00u) ? 1 : 0);
                     pc = target;
@@ -698,7 +735,7 @@ struct Cpu {
         }
         cyc = t0 + n;
         hook.after_exec(*this, opc, t0, cyc, info);
-        if (wsync) {
+        if (writes && wsync) {
             wsync = 0;
             const int32_t r = cyc % kCyclesPerLine;
             if (r) cyc += kCyclesPerLine - r;
@@ -710,7 +747,7 @@ struct Cpu {
     __host__ __device__ __forceinline__ void power_on() {
         a = x = y = 0;
         s = 0xFDu;
-        p = kFlagI | kFlagU;
+        set_flags(kFlagI | kFlagU);
         bank = f8 ? 1u : 0u;
         jam = 0;
         cyc = 0;
@@ -737,13 +774,13 @@ struct Cpu {
     }
 
     __host__ __device__ __forceinline__ void load(const StateRec &r) {
-        a = r.a; x = r.x; y = r.y; s = r.s; p = r.p; pc = r.pc; bank = r.bank; jam = r.status & 1u;
+        a = r.a; x = r.x; y = r.y; s = r.s; set_flags(r.p); pc = r.pc; bank = r.bank; jam = r.status & 1u;
         cyc = r.cyc; col = r.col; pf = r.pf; vb = r.vblank | ((uint32_t)r.vsync << 8);
         tim_u = r.tim_u; tim_read = r.tim_read; tim_shift = r.tim_shift; wsync = 0;
     }
     __host__ __device__ __forceinline__ void store(StateRec &r) const {
         r.magic = kMagic;
-        r.a = (uint8_t)a; r.x = (uint8_t)x; r.y = (uint8_t)y; r.s = (uint8_t)s; r.p = (uint8_t)p;
+        r.a = (uint8_t)a; r.x = (uint8_t)x; r.y = (uint8_t)y; r.s = (uint8_t)s; r.p = (uint8_t)flags();
         r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u);
         r.cyc = cyc; r.col = col; r.pf = pf; r.vblank = (uint8_t)(vb & 0xFFu); r.vsync = (uint8_t)(vb >> 8);
         r.tim_u = tim_u; r.tim_read = tim_read; r.tim_shift = (uint8_t)tim_shift;

@@ -48,7 +48,7 @@ struct DeviceWave {
 template <int G, int TPB, bool kSoft, bool kPlain>
 __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     constexpr int E = TPB / G;
-    extern __shared__ __align__(16) uint32_t rom_lds[];  // pre-decoded ROM words, sized to the largest image
+    extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
     __shared__ __align__(16) uint32_t ram_lds[kPlain ? 4 : 32 * E];
     const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
     const int32_t blk = blockIdx.x;
@@ -60,7 +60,8 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
         GlobalMem m{P.rom + rom_base, env >= 0 ? P.state[env].ram : nullptr};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
     } else {
-        for (int32_t i = (int32_t)tid; i < rom_size; i += TPB) rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper);
+        for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
+            rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
         __syncthreads();
         LdsWordMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
@@ -366,7 +367,7 @@ static hipError_t launch_step_t(const StepParams &P, int32_t blocks, size_t lds,
 
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
                        int32_t max_rom_size, hipStream_t stream) {
-    const size_t lds = (size_t)max_rom_size * sizeof(uint32_t);
+    const size_t lds = (size_t)max_rom_size * sizeof(uint2);
     if (plain) {
         if (soft || lanes != 1) return hipErrorInvalidValue;
         return tpb == 64 ? launch_step_t<1, 64, false, true>(P, blocks, 0, stream)

@@ -34,15 +34,16 @@ struct LdsMem {
     }
 };
 
-// LDS with a pre-decoded ROM: word[off] = byte(off) | byte(off+1) << 8 |
-// byte(off+2) << 16, the successors taken inside the image's 2K mirror or 4K
-// bank, so one read fetches an opcode and both operand bytes.
+// LDS with a pre-decoded ROM: word[off].x = byte(off) | byte(off+1) << 8 |
+// byte(off+2) << 16 (the successors taken inside the image's 2K mirror or 4K
+// bank) and word[off].y = decode entry of byte(off), so one read yields an
+// opcode, both operand bytes and the opcode's decode.
 struct LdsWordMem {
-    const uint32_t *rom;
+    const uint2 *rom;
     uint8_t *ram;
     uint32_t E, slot;
-    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off] & 0xFFu; }
-    __host__ __device__ __forceinline__ uint32_t rom_word(uint32_t off) const { return rom[off]; }
+    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off].x & 0xFFu; }
+    __host__ __device__ __forceinline__ uint2 rom_word(uint32_t off) const { return rom[off]; }
     __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const {
         return ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)];
     }
@@ -61,28 +62,42 @@ struct LdsWordMem {
 __host__ __device__ __forceinline__ uint32_t rom_next(uint32_t off, int32_t mapper) {
     return mapper == 0 ? ((off + 1u) & 0x7FFu) : ((off & ~0xFFFu) | ((off + 1u) & 0xFFFu));
 }
-__host__ __device__ __forceinline__ uint32_t rom_word_at(const uint8_t *rom, uint32_t off, int32_t mapper) {
+__host__ __device__ __forceinline__ uint2 rom_word_at(const uint8_t *rom, uint32_t off, int32_t mapper,
+                                                      const uint32_t *decode) {
     const uint32_t o1 = rom_next(off, mapper), o2 = rom_next(o1, mapper);
-    return (uint32_t)rom[off] | ((uint32_t)rom[o1] << 8) | ((uint32_t)rom[o2] << 16);
+    const uint32_t b = rom[off];
+    uint2 w;
+    w.x = b | ((uint32_t)rom[o1] << 8) | ((uint32_t)rom[o2] << 16);
+    w.y = decode[b];
+    return w;
 }
 
-// Opcode and operand bytes at pc.  Inside $1000-$1FFD the three bytes lie in
-// the cartridge window; a word memory serves them with one read.
+// Opcode and operand bytes at pc (three fetch reads).
 template <class C>
 __host__ __device__ __forceinline__ void fetch3(C &c, uint32_t &opc, uint32_t &lo, uint32_t &hi) {
     const uint32_t pc = c.pc;
-    if constexpr (std::is_same<decltype(c.mem), LdsWordMem>::value) {
-        if ((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu) {
-            const uint32_t w = c.mem.rom_word(c.cart_off(pc));
-            opc = w & 0xFFu;
-            lo = (w >> 8) & 0xFFu;
-            hi = w >> 16;
-            return;
-        }
-    }
     opc = c.peek(pc, c.cyc);
     lo = c.peek((pc + 1u) & 0xFFFFu, c.cyc);
     hi = c.peek((pc + 2u) & 0xFFFFu, c.cyc);
+}
+
+// Opcode, operand bytes and decode entry at pc from a word memory: inside
+// $1000-$1FFD the three bytes lie in the cartridge window and one LDS read
+// serves them; elsewhere three fetch reads and a table lookup.
+template <class C>
+__host__ __device__ __forceinline__ void fetch_word(C &c, const uint32_t *decode, uint32_t &opc, uint32_t &lo,
+                                                    uint32_t &hi, uint32_t &dec) {
+    const uint32_t pc = c.pc;
+    if ((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu) {
+        const uint2 w = c.mem.rom_word(c.cart_off(pc));
+        opc = w.x & 0xFFu;
+        lo = (w.x >> 8) & 0xFFu;
+        hi = w.x >> 16;
+        dec = w.y;
+        return;
+    }
+    fetch3(c, opc, lo, hi);
+    dec = decode[opc];
 }
 
 // Global memory: the env's ROM image and its 128 RAM bytes in the state record.
@@ -243,99 +258,58 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         set_ports();
         start_frame();
     }
-    // soft forward: hard-state checkpoints every K cycles since power-on
+    // soft forward: hard-state checkpoints every K cycles since power-on, taken
+    // at the first instruction boundary (or frame end) at or after each multiple
     int64_t next_ckpt = P.ckpt_interval;
     int32_t nckpt = 0;
-
-    while (W::any(active)) {
-        if (active) {
-            if constexpr (kSoft) {
-                if (P.ckpt) {
-                    const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
-                    if (g >= next_ckpt) {
-                        next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
-                        if (nckpt < P.max_ckpt) {
-                            StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
-                            if (sub == 0) {
-                                c.store(r);
-                                r.frame = frame;
-                                r.episode = 0;
-                                r.ep_step = (uint32_t)s_idx;
-                                r.next_ckpt = next_ckpt;
-                                r.pix_cc = c.hook.pix_cc;
-                                r.ckpt_index = (uint32_t)nckpt;
-                            }
-                            uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
-                            for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
+    auto checkpoint = [&]() {
+        if constexpr (kSoft) {
+            if (P.ckpt) {
+                const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
+                if (g >= next_ckpt) {
+                    next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
+                    if (nckpt < P.max_ckpt) {
+                        StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
+                        if (sub == 0) {
+                            c.store(r);
+                            r.frame = frame;
+                            r.episode = 0;
+                            r.ep_step = (uint32_t)s_idx;
+                            r.next_ckpt = next_ckpt;
+                            r.pix_cc = c.hook.pix_cc;
+                            r.ckpt_index = (uint32_t)nckpt;
                         }
-                        ++nckpt;
+                        uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
+                        for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
                     }
+                    ++nckpt;
                 }
             }
-            if (c.jam || c.cyc >= kCyclesPerFrame) {
-                // ---- end of frame
-                if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;  // a jammed CPU lets the cycles elapse
-                c.hook.finish_frame(c);
-                c.next_frame();
-                c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
-                ++frame;
-                if (++fstep == F) {
-                    // ---- end of env step
-                    if constexpr (kSoft) {
-                        if (P.ram_out_f) {
-                            float4 *o = reinterpret_cast<float4 *>(P.ram_out_f + ((size_t)env * S + s_idx) * 128);
-                            for (uint32_t w = sub; w < 32; w += G) {
-                                const uint32_t v = c.mem.ram_word(w);
-                                o[w] = make_float4((float)(v & 0xFFu), (float)((v >> 8) & 0xFFu),
-                                                   (float)((v >> 16) & 0xFFu), (float)(v >> 24));
-                            }
-                        }
-                    } else {
-                        if (P.ram_out) {
-                            uint32_t *o = reinterpret_cast<uint32_t *>(P.ram_out + ((size_t)env * S + s_idx) * 128);
-                            for (uint32_t w = sub; w < 32; w += G) o[w] = c.mem.ram_word(w);
-                        }
-                    }
-                    ++ep_step;
-                    uint32_t done = 0;
-                    if (P.ep_steps && (int32_t)episode < P.num_episodes &&
-                        ep_step >= P.ep_steps[(size_t)env * P.num_episodes + episode]) {
-                        // episode over: in-run reset with SplitMix64 RAM for the next episode
-                        done = 1;
-                        ++episode;
-                        for (uint32_t w = sub; w < 16; w += G) {
-                            const uint64_t v = reset_ram_word(P.seed, (uint64_t)env, episode, w);
-                            c.mem.ram_word_set(2 * w, (uint32_t)v);
-                            c.mem.ram_word_set(2 * w + 1, (uint32_t)(v >> 32));
-                        }
-                        c.power_on();
-                        frame = 0;
-                        ep_step = 0;
-                    }
-                    if (P.done && sub == 0) P.done[(size_t)env * S + s_idx] = (uint8_t)done;
-                    fstep = 0;
-                    if (++s_idx == S) {
-                        active = false;
-                    } else {
-                        set_ports();
-                    }
-                }
-                if (active) start_frame();
-            } else {
-                // ---- one instruction
+        }
+    };
+
+    while (W::any(active)) {
+        // ---- the instructions of one frame (the hot loop; a lane leaves it at
+        // its frame's end, the wave when every lane has)
+        bool run = active && !c.jam && c.cyc < kCyclesPerFrame;
+        while (run) {
+            {
+                checkpoint();
                 uint32_t opc, lo, hi;
-                fetch3(c, opc, lo, hi);
                 ExecInfo info;
                 if constexpr (kPlain) {
+                    fetch3(c, opc, lo, hi);
                     const uint32_t d = decode[opc];
                     if (d == 0) c.jam = 1;
                     else c.exec(opc, d, lo, hi, info);
                 } else {
-                    // waterfall: each pass executes one distinct opcode of the wave
-                    // with a wave-uniform (scalar) decode
+                    uint32_t dec;
+                    fetch_word(c, decode, opc, lo, hi, dec);
+                    // waterfall: each pass executes one distinct opcode of the
+                    // wave with a wave-uniform (scalar) decode
                     for (;;) {
                         const uint32_t u = W::first(opc);
-                        const uint32_t d = W::table(decode, u);
+                        const uint32_t d = W::first(dec);
                         if (opc == u) {
                             if (d == 0) c.jam = 1;
                             else c.exec(u, d, lo, hi, info);
@@ -343,8 +317,59 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                         }
                     }
                 }
+                run = !c.jam && c.cyc < kCyclesPerFrame;
             }
         }
+        if (!active) continue;
+        checkpoint();
+        // ---- end of frame
+        if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;  // a jammed CPU lets the cycles elapse
+        c.hook.finish_frame(c);
+        c.next_frame();
+        c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
+        ++frame;
+        if (++fstep == F) {
+            // ---- end of env step
+            if constexpr (kSoft) {
+                if (P.ram_out_f) {
+                    float4 *o = reinterpret_cast<float4 *>(P.ram_out_f + ((size_t)env * S + s_idx) * 128);
+                    for (uint32_t w = sub; w < 32; w += G) {
+                        const uint32_t v = c.mem.ram_word(w);
+                        o[w] = make_float4((float)(v & 0xFFu), (float)((v >> 8) & 0xFFu),
+                                           (float)((v >> 16) & 0xFFu), (float)(v >> 24));
+                    }
+                }
+            } else {
+                if (P.ram_out) {
+                    uint32_t *o = reinterpret_cast<uint32_t *>(P.ram_out + ((size_t)env * S + s_idx) * 128);
+                    for (uint32_t w = sub; w < 32; w += G) o[w] = c.mem.ram_word(w);
+                }
+            }
+            ++ep_step;
+            uint32_t done = 0;
+            if (P.ep_steps && (int32_t)episode < P.num_episodes &&
+                ep_step >= P.ep_steps[(size_t)env * P.num_episodes + episode]) {
+                // episode over: in-run reset with SplitMix64 RAM for the next episode
+                done = 1;
+                ++episode;
+                for (uint32_t w = sub; w < 16; w += G) {
+                    const uint64_t v = reset_ram_word(P.seed, (uint64_t)env, episode, w);
+                    c.mem.ram_word_set(2 * w, (uint32_t)v);
+                    c.mem.ram_word_set(2 * w + 1, (uint32_t)(v >> 32));
+                }
+                c.power_on();
+                frame = 0;
+                ep_step = 0;
+            }
+            if (P.done && sub == 0) P.done[(size_t)env * S + s_idx] = (uint8_t)done;
+            fstep = 0;
+            if (++s_idx == S) {
+                active = false;
+            } else {
+                set_ports();
+            }
+        }
+        if (active) start_frame();
     }
 
     if (live) {
