@@ -12,8 +12,12 @@ SOURCES = ["vcs_kernels.hip", "vcs_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # gfx950 only; packed-FP32 instruction selection disabled (see the hipcc flags).
+# The step kernels branch on wave-uniform opcodes and classes; control-flow
+# structurisation is skipped for regions whose branches are all uniform, so
+# such switches stay scalar branch trees instead of chains of flow blocks.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-structurizecfg-skip-uniform-regions=true",
          "-I", os.path.join(HERE, "..", "include")]
 
 

@@ -420,7 +420,8 @@ struct Cpu {
     // RAM from $80.  These are read/write for such addresses (zero-page modes,
     // zero-page pointers, the stack at $100 | s), with the page bits dropped.
     __host__ __device__ __forceinline__ uint32_t read_zp(uint32_t a8) {
-        return (a8 & 0x80u) ? mem.ram_byte(a8 & 0x7Fu) : tia_in(a8);
+        const uint32_t r = mem.ram_byte(a8 & 0x7Fu), t = tia_in(a8);  // both, then select: no branch
+        return (a8 & 0x80u) ? r : t;
     }
     __host__ __device__ __forceinline__ void write_zp(uint32_t a8, uint32_t v, int32_t w) {
         if (a8 & 0x80u) mem.ram_set(a8 & 0x7Fu, v);
@@ -493,47 +494,48 @@ struct Cpu {
         return read_zp(s);
     }
 
-    // NMOS ADC, binary and decimal (decimal: B. Clark, "Decimal Mode", App. A)
+    // NMOS ADC, binary and decimal (decimal: B. Clark, "Decimal Mode", App. A).
+    // Both results are formed and D selects, so no lane branches on D.
     __host__ __device__ __forceinline__ uint32_t adc(uint32_t v) {
         const uint32_t c = p & kFlagC;
         const uint32_t sum = a + v + c;
-        if (!(p & kFlagD)) {
-            p = (p & ~(kFlagV | kFlagC)) | ((~(a ^ v) & (a ^ sum) & 0x80u) ? kFlagV : 0u) | (sum > 0xFFu ? kFlagC : 0u);
-            set_nz(sum & 0xFFu);
-            return sum & 0xFFu;
-        }
+        const uint32_t fb = ((~(a ^ v) & (a ^ sum) & 0x80u) ? kFlagV : 0u) | (sum > 0xFFu ? kFlagC : 0u);
         int32_t lo = (int32_t)((a & 0xFu) + (v & 0xFu) + c);
-        if (lo > 9) lo = ((lo + 6) & 0xF) + 0x10;
+        lo = lo > 9 ? ((lo + 6) & 0xF) + 0x10 : lo;
         const int32_t hi_s = ((int32_t)((a & 0xF0u) ^ 0x80u) - 128) + ((int32_t)((v & 0xF0u) ^ 0x80u) - 128) + lo;
         int32_t hi_u = (int32_t)(a & 0xF0u) + (int32_t)(v & 0xF0u) + lo;
-        if (hi_u >= 0xA0) hi_u += 0x60;
-        p = (p & ~(kFlagV | kFlagC)) | ((hi_s < -128 || hi_s > 127) ? kFlagV : 0u) | (hi_u > 0xFF ? kFlagC : 0u);
-        rn = (uint32_t)hi_s & 0x80u;  // N from the signed high-digit sum, Z from the binary sum
-        rz = sum & 0xFFu;
-        return (uint32_t)hi_u & 0xFFu;
+        hi_u = hi_u >= 0xA0 ? hi_u + 0x60 : hi_u;
+        const uint32_t fd = ((hi_s < -128 || hi_s > 127) ? kFlagV : 0u) | (hi_u > 0xFF ? kFlagC : 0u);
+        const bool dec = (p & kFlagD) != 0u;
+        p = (p & ~(kFlagV | kFlagC)) | (dec ? fd : fb);
+        rz = sum & 0xFFu;                              // Z from the binary sum in both modes
+        rn = dec ? ((uint32_t)hi_s & 0x80u) : (sum & 0xFFu);  // decimal N from the signed high-digit sum
+        return dec ? ((uint32_t)hi_u & 0xFFu) : (sum & 0xFFu);
     }
     __host__ __device__ __forceinline__ uint32_t sbc(uint32_t v) {
         const uint32_t c = p & kFlagC;
         const int32_t diff = (int32_t)a - (int32_t)v - (int32_t)(1u - c);
         const uint32_t bin = (uint32_t)diff & 0xFFu;
         p = (p & ~(kFlagV | kFlagC)) | (((a ^ v) & (a ^ bin) & 0x80u) ? kFlagV : 0u) | (diff >= 0 ? kFlagC : 0u);
-        set_nz(bin);
-        if (!(p & kFlagD)) return bin;
+        set_nz(bin);  // flags follow the binary difference in both modes
         int32_t lo = (int32_t)(a & 0xFu) - (int32_t)(v & 0xFu) - (int32_t)(1u - c);
-        if (lo < 0) lo = ((lo - 6) & 0xF) - 0x10;
+        lo = lo < 0 ? ((lo - 6) & 0xF) - 0x10 : lo;
         int32_t r = (int32_t)(a & 0xF0u) - (int32_t)(v & 0xF0u) + lo;
-        if (r < 0) r -= 0x60;
-        return (uint32_t)r & 0xFFu;
+        r = r < 0 ? r - 0x60 : r;
+        return (p & kFlagD) ? ((uint32_t)r & 0xFFu) : bin;
     }
 
     // Execute one instruction whose opcode byte is opc (decode entry d) with
     // operand bytes lo/hi; `info` receives the data classes when recording.
     // On the GPU opc and d are the same in every lane that runs this call, so
-    // every branch on the mode and class is a scalar branch.
+    // every test of the mode or class is a wave-uniform branch.  Instructions
+    // with one data access run in phases (address, read, operate, write) in
+    // which only the read and the write decode addresses per lane; the
+    // operate phase has no per-lane branch, so its class switch stays a
+    // scalar branch tree.  JSR, RTS, RTI, BRK and JMP (ind) take a separate path.
     __host__ __device__ __forceinline__ void exec(uint32_t opc, uint32_t d, uint32_t lo, uint32_t hi, ExecInfo &info) {
         constexpr bool R = Hook::kRecord;
         const uint32_t cls = d & 63u, mode = (d >> 6) & 15u;
-        const bool zp = mode == M_ZP || mode == M_ZPX || mode == M_ZPY;  // ea lies in page 0
         const int32_t t0 = cyc;
         int32_t n = (int32_t)((d >> 10) & 7u);
         const uint32_t pc0 = pc;
@@ -545,151 +547,190 @@ struct Cpu {
             info.s_before = s;
         }
         hook.before_exec(*this);
-        uint32_t ea = 0;
-        switch (mode) {
-            case M_IMM: ea = (pc0 + 1u) & 0xFFFFu; break;
-            case M_ZP: ea = lo; break;
-            case M_ZPX: ea = (lo + x) & 0xFFu; break;
-            case M_ZPY: ea = (lo + y) & 0xFFu; break;
-            case M_ABS: ea = lo | (hi << 8); break;
-            case M_ABX:
-            case M_ABY: {
-                const uint32_t base = lo | (hi << 8);
-                ea = (base + (mode == M_ABX ? x : y)) & 0xFFFFu;
-                if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
-                break;
-            }
-            case M_IZX: {
-                const uint32_t z = (lo + x) & 0xFFu;
-                ea = read_zp(z) | (read_zp((z + 1u) & 0xFFu) << 8);
-                break;
-            }
-            case M_IZY: {
-                const uint32_t base = read_zp(lo) | (read_zp((lo + 1u) & 0xFFu) << 8);
-                ea = (base + y) & 0xFFFFu;
-                if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
-                break;
-            }
-            case M_IND: {
-                const uint32_t ptr = lo | (hi << 8);
-                const uint32_t ptr_hi = (ptr & 0xFF00u) | ((ptr + 1u) & 0xFFu);
-                ea = peek(ptr, t0) | (peek(ptr_hi, t0) << 8);
-                break;
-            }
-            default: break;
-        }
-        const int32_t tl = t0 + n - 1;  // last cycle of reads/stores (n is final here for them)
-        bool writes = false;             // the instruction may have written WSYNC
-        switch (cls) {
-            case C_LDA: case C_LDX: case C_LDY: case C_LAX:
-            case C_ADC: case C_SBC: case C_AND: case C_ORA: case C_EOR:
-            case C_CMP: case C_CPX: case C_CPY: case C_BIT: {
-                const uint32_t v = mode == M_IMM ? lo : zp ? read_zp(ea) : read(ea, tl);
-                if constexpr (R) info.rd_cls = read_class(ea, &info.rd_idx);
-                switch (cls) {
-                    case C_LDA: a = v; set_nz(v); break;
-                    case C_LDX: x = v; set_nz(v); break;
-                    case C_LDY: y = v; set_nz(v); break;
-                    case C_LAX: a = x = v; set_nz(v); break;
-                    case C_ADC: a = adc(v); break;
-                    case C_SBC: a = sbc(v); break;
-                    case C_AND: case C_ORA: case C_EOR:
-                        if constexpr (R) {
-                            info.v1 = a;
-                            info.v2 = v;
-                        }
-                        a = cls == C_AND ? (a & v) : cls == C_ORA ? (a | v) : (a ^ v);
-                        set_nz(a);
-                        break;
-                    case C_BIT:
-                        p = (p & ~kFlagV) | (v & kFlagV);
-                        rn = v;
-                        rz = a & v;
-                        break;
-                    default: {  // CMP CPX CPY
-                        const uint32_t r = cls == C_CMP ? a : cls == C_CPX ? x : y;
-                        p = (p & ~kFlagC) | (r >= v ? kFlagC : 0u);
-                        set_nz((r - v) & 0xFFu);
-                        break;
-                    }
+        const bool multi = cls == C_JSR || cls == C_RTS || cls == C_RTI || cls == C_BRK || mode == M_IND;
+        bool wr;  // the instruction writes memory (so it may have written WSYNC)
+        if (multi) {
+            wr = cls == C_JSR || cls == C_BRK;
+            exec_multi(cls, mode, pc0, lo, hi, t0, n);
+        } else {
+            const bool stack = cls >= C_PHA && cls <= C_PLP;
+            const bool zpt = mode == M_ZP || mode == M_ZPX || mode == M_ZPY || stack;  // page-0 / stack access
+            const bool load = (cls >= C_LDA && cls <= C_LAX) || (cls >= C_ADC && cls <= C_BIT);
+            const bool rmw = cls >= C_ASL && cls <= C_DEC;
+            const bool store = cls >= C_STA && cls <= C_SAX;
+            const bool rd = (load && mode != M_IMM) || (rmw && mode != M_ACC) || cls == C_PLA || cls == C_PLP;
+            wr = store || (rmw && mode != M_ACC) || cls == C_PHA || cls == C_PHP;
+
+            // ---- address
+            uint32_t ea = 0;
+            switch (mode) {
+                case M_IMM: ea = (pc0 + 1u) & 0xFFFFu; break;
+                case M_ZP: ea = lo; break;
+                case M_ZPX: ea = (lo + x) & 0xFFu; break;
+                case M_ZPY: ea = (lo + y) & 0xFFu; break;
+                case M_ABS: ea = lo | (hi << 8); break;
+                case M_ABX:
+                case M_ABY: {
+                    const uint32_t base = lo | (hi << 8);
+                    ea = (base + (mode == M_ABX ? x : y)) & 0xFFFFu;
+                    if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
+                    break;
                 }
-                break;
-            }
-            case C_STA: case C_STX: case C_STY: case C_SAX: {
-                const uint32_t v = cls == C_STA ? a : cls == C_STX ? x : cls == C_STY ? y : (a & x);
-                if constexpr (R) {
-                    info.wr_cls = write_class(ea, &info.wr_idx);
-                    info.v1 = a;
-                    info.v2 = x;
+                case M_IZX: {
+                    const uint32_t z = (lo + x) & 0xFFu;
+                    ea = read_zp(z) | (read_zp((z + 1u) & 0xFFu) << 8);
+                    break;
                 }
-                if (zp) write_zp(ea, v, tl);
-                else write(ea, v, tl);
-                writes = true;
-                break;
+                case M_IZY: {
+                    const uint32_t base = read_zp(lo) | (read_zp((lo + 1u) & 0xFFu) << 8);
+                    ea = (base + y) & 0xFFFFu;
+                    if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
+                    break;
+                }
+                default: break;
             }
-            case C_ASL: case C_LSR: case C_ROL: case C_ROR: case C_INC: case C_DEC: {
-                uint32_t v;
-                if (mode == M_ACC) {
-                    v = a;
-                    if constexpr (R) info.rd_cls = info.wr_cls = kClsRegA;
-                } else {
-                    v = zp ? read_zp(ea) : read(ea, t0 + n - 3);
-                    if constexpr (R) {
+            if (cls == C_PHA || cls == C_PHP) ea = s;                    // push to $100 | s
+            else if (cls == C_PLA || cls == C_PLP) ea = (s + 1u) & 0xFFu;  // pull from $100 | s+1
+            const int32_t tl = t0 + n - 1;  // last cycle: loads and stores access memory here
+
+            // ---- read (a read-modify-write reads three cycles before its end)
+            uint32_t v = lo;
+            if (rd) {
+                if (zpt) v = read_zp(ea);
+                else v = read(ea, rmw ? t0 + n - 3 : tl);
+            }
+            if constexpr (R) {
+                if (load) {
+                    info.rd_cls = read_class(ea, &info.rd_idx);  // an immediate is a ROM byte
+                } else if (rmw) {
+                    if (mode == M_ACC) {
+                        info.rd_cls = info.wr_cls = kClsRegA;
+                    } else {
                         info.rd_cls = read_class(ea, &info.rd_idx);
                         info.wr_cls = write_class(ea, &info.wr_idx);
                     }
+                } else if (store) {
+                    info.wr_cls = write_class(ea, &info.wr_idx);
+                    info.v1 = a;
+                    info.v2 = x;
+                } else if (cls == C_PHA) {
+                    info.wr_cls = write_class(0x100u | ea, &info.wr_idx);
+                } else if (cls == C_PLA) {
+                    info.rd_cls = read_class(0x100u | ea, &info.rd_idx);
                 }
-                const uint32_t c = p & kFlagC;
-                uint32_t r;
-                switch (cls) {
-                    case C_ASL: p = (p & ~kFlagC) | (v >> 7); r = (v << 1) & 0xFFu; break;
-                    case C_LSR: p = (p & ~kFlagC) | (v & 1u); r = v >> 1; break;
-                    case C_ROL: p = (p & ~kFlagC) | (v >> 7); r = ((v << 1) | c) & 0xFFu; break;
-                    case C_ROR: p = (p & ~kFlagC) | (v & 1u); r = (v >> 1) | (c << 7); break;
-                    case C_INC: r = (v + 1u) & 0xFFu; break;
-                    default: r = (v - 1u) & 0xFFu; break;
+            }
+
+            // ---- operate
+            uint32_t r = 0;  // value to write
+            switch (cls) {
+                case C_LDA: a = v; set_nz(v); break;
+                case C_LDX: x = v; set_nz(v); break;
+                case C_LDY: y = v; set_nz(v); break;
+                case C_LAX: a = x = v; set_nz(v); break;
+                case C_ADC: a = adc(v); break;
+                case C_SBC: a = sbc(v); break;
+                case C_AND: case C_ORA: case C_EOR:
+                    if constexpr (R) {
+                        info.v1 = a;
+                        info.v2 = v;
+                    }
+                    a = cls == C_AND ? (a & v) : cls == C_ORA ? (a | v) : (a ^ v);
+                    set_nz(a);
+                    break;
+                case C_BIT:
+                    p = (p & ~kFlagV) | (v & kFlagV);
+                    rn = v;
+                    rz = a & v;
+                    break;
+                case C_CMP: case C_CPX: case C_CPY: {
+                    const uint32_t q = cls == C_CMP ? a : cls == C_CPX ? x : y;
+                    p = (p & ~kFlagC) | (q >= v ? kFlagC : 0u);
+                    set_nz((q - v) & 0xFFu);
+                    break;
                 }
-                set_nz(r);
-                if (mode == M_ACC) {
-                    a = r;
-                } else {
-                    if (zp) write_zp(ea, r, tl);
-                    else write(ea, r, tl);
-                    writes = true;
+                case C_STA: r = a; break;
+                case C_STX: r = x; break;
+                case C_STY: r = y; break;
+                case C_SAX: r = a & x; break;
+                case C_ASL: case C_LSR: case C_ROL: case C_ROR: case C_INC: case C_DEC: {
+                    const uint32_t src = mode == M_ACC ? a : v;
+                    const uint32_t c = p & kFlagC;
+                    switch (cls) {
+                        case C_ASL: p = (p & ~kFlagC) | (src >> 7); r = (src << 1) & 0xFFu; break;
+                        case C_LSR: p = (p & ~kFlagC) | (src & 1u); r = src >> 1; break;
+                        case C_ROL: p = (p & ~kFlagC) | (src >> 7); r = ((src << 1) | c) & 0xFFu; break;
+                        case C_ROR: p = (p & ~kFlagC) | (src & 1u); r = (src >> 1) | (c << 7); break;
+                        case C_INC: r = (src + 1u) & 0xFFu; break;
+                        default: r = (src - 1u) & 0xFFu; break;
+                    }
+                    set_nz(r);
+                    if (mode == M_ACC) a = r;
+                    break;
                 }
+                case C_INX: x = (x + 1u) & 0xFFu; set_nz(x); break;
+                case C_INY: y = (y + 1u) & 0xFFu; set_nz(y); break;
+                case C_DEX: x = (x - 1u) & 0xFFu; set_nz(x); break;
+                case C_DEY: y = (y - 1u) & 0xFFu; set_nz(y); break;
+                case C_TAX: x = a; set_nz(x); break;
+                case C_TAY: y = a; set_nz(y); break;
+                case C_TXA: a = x; set_nz(a); break;
+                case C_TYA: a = y; set_nz(a); break;
+                case C_TSX: x = s; set_nz(x); break;
+                case C_TXS: s = x; break;
+                case C_PHA: r = a; s = (s - 1u) & 0xFFu; break;
+                case C_PHP: r = flags() | kFlagB | kFlagU; s = (s - 1u) & 0xFFu; break;
+                case C_PLA: a = v; set_nz(v); s = ea; break;
+                case C_PLP: set_flags((v & ~kFlagB) | kFlagU); s = ea; break;
+                case C_JMP: pc = ea; break;
+                case C_BRANCH: {
+                    const uint32_t mask = (d >> 16) & 0xFFu, when_set = (d >> 24) & 1u;
+                    const uint32_t f = mask == kFlagN ? (rn >> 7) & 1u
+                                     : mask == kFlagZ ? ((rz & 0xFFu) ? 0u : 1u) : ((p & mask) ? 1u : 0u);
+                    const uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
+                    const bool taken = f == when_set;
+                    n += taken ? 1 + (((target ^ pc) & 0xFF00u) ? 1 : 0) : 0;
+                    pc = taken ? target : pc;
+                    break;
+                }
+                case C_FLAG: {
+                    const uint32_t mask = (d >> 16) & 0xFFu;
+                    p = ((d >> 24) & 1u) ? (p | mask) : (p & ~mask);
+                    break;
+                }
+                default: break;  // NOP family (operand reads have no side effects)
+            }
+
+            // ---- write
+            if (wr) {
+                if (zpt) write_zp(ea, r, tl);
+                else write(ea, r, tl);
+            }
+        }
+        cyc = t0 + n;
+        hook.after_exec(*this, opc, t0, cyc, info);
+        if (wr && wsync) {
+            wsync = 0;
+            const int32_t q = cyc % kCyclesPerLine;
+            if (q) cyc += kCyclesPerLine - q;
+        }
+    }
+
+    // JSR, RTS, RTI, BRK (several stack accesses, all in the last cycle) and JMP (ind).
+    __host__ __device__ __forceinline__ void exec_multi(uint32_t cls, uint32_t mode, uint32_t pc0, uint32_t lo,
+                                                        uint32_t hi, int32_t t0, int32_t n) {
+        const int32_t tl = t0 + n - 1;
+        switch (cls) {
+            case C_JMP: {  // (ind): the pointer's high byte comes from the same page
+                const uint32_t ptr = lo | (hi << 8);
+                const uint32_t ptr_hi = (ptr & 0xFF00u) | ((ptr + 1u) & 0xFFu);
+                pc = peek(ptr, t0) | (peek(ptr_hi, t0) << 8);
                 break;
             }
-            case C_INX: x = (x + 1u) & 0xFFu; set_nz(x); break;
-            case C_INY: y = (y + 1u) & 0xFFu; set_nz(y); break;
-            case C_DEX: x = (x - 1u) & 0xFFu; set_nz(x); break;
-            case C_DEY: y = (y - 1u) & 0xFFu; set_nz(y); break;
-            case C_TAX: x = a; set_nz(x); break;
-            case C_TAY: y = a; set_nz(y); break;
-            case C_TXA: a = x; set_nz(a); break;
-            case C_TYA: a = y; set_nz(a); break;
-            case C_TSX: x = s; set_nz(x); break;
-            case C_TXS: s = x; break;
-            case C_PHA:
-                if constexpr (R) info.wr_cls = write_class(0x100u | s, &info.wr_idx);
-                push(a, tl);
-                writes = true;
-                break;
-            case C_PHP: push(flags() | kFlagB | kFlagU, tl); writes = true; break;
-            case C_PLA: {
-                const uint32_t v = pull();
-                if constexpr (R) info.rd_cls = read_class(0x100u | s, &info.rd_idx);
-                a = v;
-                set_nz(v);
-                break;
-            }
-            case C_PLP: set_flags((pull() & ~kFlagB) | kFlagU); break;
-            case C_JMP: pc = ea; break;
             case C_JSR: {
                 const uint32_t ret = (pc - 1u) & 0xFFFFu;
                 push(ret >> 8, tl);
                 push(ret & 0xFFu, tl);
-                pc = ea;
-                writes = true;
+                pc = lo | (hi << 8);
                 break;
             }
             case C_RTS: {
@@ -705,41 +746,17 @@ struct Cpu {
                 push(flags() | kFlagB | kFlagU, tl);
                 p |= kFlagI;
                 pc = peek(0x1FFEu, t0) | (peek(0x1FFFu, t0) << 8);
-                writes = true;
                 break;
             }
-            case C_RTI: {
+            default: {  // RTI
                 set_flags((pull() & ~kFlagB) | kFlagU);
                 const uint32_t l = pull();
                 const uint32_t h = pull();
                 pc = (h << 8) | l;
                 break;
             }
-            case C_BRANCH: {
-                const uint32_t mask = (d >> 16) & 0xFFu, when_set = (d >> 24) & 1u;
-                const uint32_t f = mask == kFlagN ? (rn >> 7) & 1u
-                                 : mask == kFlagZ ? ((rz & 0xFFu) ? 0u : 1u) : ((p & mask) ? 1u : 0u);
-                if (f == when_set) {
-                    const uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
-                    n += 1 + (((target ^ pc) & 0xFF00u) ? 1 : 0);
-                    pc = target;
-                }
-                break;
-            }
-            case C_FLAG: {
-                const uint32_t mask = (d >> 16) & 0xFFu;
-                p = ((d >> 24) & 1u) ? (p | mask) : (p & ~mask);
-                break;
-            }
-            default: break;  // NOP family (operand reads have no side effects)
         }
-        cyc = t0 + n;
-        hook.after_exec(*this, opc, t0, cyc, info);
-        if (writes && wsync) {
-            wsync = 0;
-            const int32_t r = cyc % kCyclesPerLine;
-            if (r) cyc += kCyclesPerLine - r;
-        }
+        (void)mode;
     }
 
     // Power-on (also the in-run reset): registers, TIA and timer to their

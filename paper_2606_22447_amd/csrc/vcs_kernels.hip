@@ -29,7 +29,11 @@ typedef const __attribute__((address_space(4))) uint32_t ConstU32;
 
 struct DeviceWave {
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
+    __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
     __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+    // makes v opaque to the optimiser (no instruction): code that uses it cannot be
+    // hoisted out of the loop that contains this call
+    __device__ static __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
     // entry u (wave-uniform) of a read-only table in constant memory: a scalar
     // load, so that what is derived from it stays in scalar registers and the
     // branches on it are scalar branches

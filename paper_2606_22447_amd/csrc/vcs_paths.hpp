@@ -187,11 +187,53 @@ struct TapeHook {
 };
 
 // ---------------------------------------------------------------------------
-// Per-env bodies of the kernels.  W is the wave policy: any(v) (is v true in
-// any lane of the wave), first(v) (v of the first active lane) and table(t, u)
-// (entry u of a constant table, u the same in every active lane); on the GPU
-// they are a ballot, readfirstlane and a scalar load, and the ROM image must
-// already be staged in LDS by the whole workgroup.
+// Dispatch of one instruction whose opcode u (decode d) is the same in every
+// lane of the call.  The opcodes that dominate VCS game code (zero-page and
+// immediate loads and stores, branches, stack, counters, flag ops) each get
+// a copy of the interpreter with its decode entry known at compile time, so
+// the mode/class dispatch and the timing arithmetic fold away; every other
+// opcode goes through the generic path.
+// ---------------------------------------------------------------------------
+template <uint32_t OP, class C>
+__host__ __device__ __forceinline__ void exec_fixed(C &c, uint32_t lo, uint32_t hi, ExecInfo &info) {
+    constexpr uint32_t D = decode_op(OP);
+    static_assert(D != 0, "jam opcodes take the generic path");
+    c.exec(OP, D, lo, hi, info);
+}
+
+template <class C>
+__host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_t d, uint32_t lo, uint32_t hi,
+                                                       ExecInfo &info) {
+#define VCS_FIXED(op) \
+    case op: exec_fixed<op>(c, lo, hi, info); return;
+    switch (u) {
+        VCS_FIXED(0x85) VCS_FIXED(0x86) VCS_FIXED(0x84)                  // STA STX STY zp
+        VCS_FIXED(0xA5) VCS_FIXED(0xA6) VCS_FIXED(0xA4) VCS_FIXED(0xB5)  // LDA LDX LDY zp, LDA zp,X
+        VCS_FIXED(0xA9) VCS_FIXED(0xA2) VCS_FIXED(0xA0)                  // LDA LDX LDY #
+        VCS_FIXED(0xD0) VCS_FIXED(0xF0) VCS_FIXED(0x10) VCS_FIXED(0x30)  // BNE BEQ BPL BMI
+        VCS_FIXED(0x90) VCS_FIXED(0xB0)                                  // BCC BCS
+        VCS_FIXED(0x48) VCS_FIXED(0x68)                                  // PHA PLA
+        VCS_FIXED(0x88) VCS_FIXED(0xCA) VCS_FIXED(0xC8) VCS_FIXED(0xE8)  // DEY DEX INY INX
+        VCS_FIXED(0xE6) VCS_FIXED(0xC6)                                  // INC DEC zp
+        VCS_FIXED(0x38) VCS_FIXED(0x18) VCS_FIXED(0xD8) VCS_FIXED(0xF8)  // SEC CLC CLD SED
+        VCS_FIXED(0x65) VCS_FIXED(0xE5) VCS_FIXED(0x69) VCS_FIXED(0xE9)  // ADC SBC zp, #
+        VCS_FIXED(0x49) VCS_FIXED(0x29) VCS_FIXED(0x09) VCS_FIXED(0xC9)  // EOR AND ORA CMP #
+        VCS_FIXED(0x46) VCS_FIXED(0x4A) VCS_FIXED(0x0A)                  // LSR zp, LSR A, ASL A
+        VCS_FIXED(0xAA) VCS_FIXED(0x8A)                                  // TAX TXA
+        VCS_FIXED(0x4C) VCS_FIXED(0x20) VCS_FIXED(0x60)                  // JMP JSR RTS
+        VCS_FIXED(0x8D) VCS_FIXED(0xAD) VCS_FIXED(0xBD) VCS_FIXED(0xB9)  // STA LDA abs, LDA abs,X / abs,Y
+        default: c.exec(u, d, lo, hi, info); return;
+    }
+#undef VCS_FIXED
+}
+
+// ---------------------------------------------------------------------------
+// Per-env bodies of the kernels.  W is the wave policy: any(v) / all(v) (is v
+// true in any / every active lane of the wave), first(v) (v of the first active
+// lane), table(t, u) (entry u of a constant table, u the same in every active
+// lane) and opaque(v) (hide v from the optimiser); on the GPU they are ballots,
+// readfirstlane, a scalar load and an empty asm, and the ROM image must already
+// be staged in LDS by the whole workgroup.
 // ---------------------------------------------------------------------------
 template <class W, int G, bool kSoft, bool kPlain, class Mem>
 __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
@@ -305,15 +347,31 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                 } else {
                     uint32_t dec;
                     fetch_word(c, decode, opc, lo, hi, dec);
-                    // waterfall: each pass executes one distinct opcode of the
-                    // wave with a wave-uniform (scalar) decode
-                    for (;;) {
-                        const uint32_t u = W::first(opc);
-                        const uint32_t d = W::first(dec);
-                        if (opc == u) {
-                            if (d == 0) c.jam = 1;
-                            else c.exec(u, d, lo, hi, info);
-                            break;
+                    const uint32_t u = W::first(opc);
+                    const uint32_t d = W::first(dec);
+                    if (W::all(opc == u)) {
+                        // the usual case: every running lane has the same opcode
+                        if (d == 0) c.jam = 1;
+                        else exec_dispatch(c, u, d, lo, hi, info);
+                    } else {
+                        // waterfall: each pass executes one distinct opcode of the
+                        // wave with a wave-uniform (scalar) decode.  The operands and
+                        // registers are made opaque per pass so that no case's
+                        // arithmetic is hoisted out of the loop and run for all cases.
+                        for (;;) {
+                            W::opaque(lo);
+                            W::opaque(hi);
+                            W::opaque(c.x);
+                            W::opaque(c.y);
+                            W::opaque(c.a);
+                            W::opaque(c.s);
+                            const uint32_t u2 = W::first(opc);
+                            const uint32_t d2 = W::first(dec);
+                            if (opc == u2) {
+                                if (d2 == 0) c.jam = 1;
+                                else c.exec(u2, d2, lo, hi, info);
+                                break;
+                            }
                         }
                     }
                 }
@@ -522,15 +580,11 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                         uint32_t opc, lo, hi;
                         fetch3(c, opc, lo, hi);
                         ExecInfo info;
-                        for (;;) {
-                            const uint32_t u = W::first(opc);
-                            const uint32_t d = W::table(decode, u);
-                            if (opc == u) {
-                                if (d == 0) c.jam = 1;
-                                else c.exec(u, d, lo, hi, info);
-                                break;
-                            }
-                        }
+                        // the env's lane runs alone, so its opcode is wave-uniform
+                        const uint32_t u = W::first(opc);
+                        const uint32_t d = W::table(decode, u);
+                        if (d == 0) c.jam = 1;
+                        else c.exec(u, d, lo, hi, info);
                     }
                 }
             }
