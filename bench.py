@@ -28,8 +28,42 @@ OPS_PER_INSTRUCTION = 12                       # algorithmic integer ops of one 
 OPS_PER_PIXEL = 1                              # one store per returned pixel
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c1_hbm_traffic.md")
+KERNEL_SOURCES = ["vcs_core.hpp", "vcs_paths.hpp", "vcs_internal.hpp", "vcs_kernels.hpp", "vcs_kernels.hip"]
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_digest() -> str:
+    """SHA-256 of the step kernel's sources and build flags (identifies the measured kernel)."""
+    import hashlib
+    from paper_2606_22447_amd import build as B
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(B.CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(f for f in B.FLAGS if not os.path.isabs(f)).encode())  # flags without local paths
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_step launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    when the kernel has changed since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(":", 1) for line in fh.read().splitlines() if line.startswith("- ") is False
+                      and ":" in line and line.split(":", 1)[0].strip().isidentifier())
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_digest") != kernel_digest():
+        return None
+    try:
+        return int(kv["fetch_bytes_per_launch"]) + int(kv["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -259,7 +293,9 @@ def main():
     if h:
         achieved = h["env_steps_per_s"] * ops_per_step / 1e12
         line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                            "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                            "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
+                            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                            "algorithmic_bytes_per_launch": args.envs * args.chunk * (33600 + 128 + 1 + 1),
                             "ops_per_env_step": ops_per_step, "instructions_per_env_step": ips,
                             "kernel": "k_step (grouped)"}
         line["instructions_per_s"] = h["env_steps_per_s"] * ips

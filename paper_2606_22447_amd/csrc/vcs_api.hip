@@ -223,10 +223,11 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
             return VCS_UNSUPPORTED;
         }
     } else {
-        // Each env is a serial chain, so throughput comes from interleaving many
-        // waves per SIMD: take the widest lane group that still fits about four
-        // waves on each of the chip's 1024 SIMDs (256 CUs x 4).
-        const int64_t lanes_budget = 1024LL * 4 * 64;
+        // Each env is a serial chain whose step latency is set by one wave's
+        // instruction issue; a second wave on a SIMD only competes for the same
+        // VALU.  Take the widest lane group that keeps about one wave per SIMD
+        // (1024 SIMDs = 256 CUs x 4); more envs than that share waves.
+        const int64_t lanes_budget = 1024LL * 64;
         c->G = (int64_t)c->B * 64 <= lanes_budget ? 64 : (int64_t)c->B * 16 <= lanes_budget ? 16
              : (int64_t)c->B * 4 <= lanes_budget ? 4 : 1;
     }

@@ -534,7 +534,34 @@ struct Cpu {
     // operate phase has no per-lane branch, so its class switch stays a
     // scalar branch tree.  JSR, RTS, RTI, BRK and JMP (ind) take a separate path.
     __host__ __device__ __forceinline__ void exec(uint32_t opc, uint32_t d, uint32_t lo, uint32_t hi, ExecInfo &info) {
+        int32_t t0, n;
+        uint32_t ea, r;
+        const bool wr = exec_body<false>(opc, d, lo, hi, info, t0, n, ea, r);
+        finish(opc, info, t0, n, wr);
+    }
+
+    // End of an instruction that started at cycle t0 and took n cycles: the cycle
+    // counter, the hook, and the WSYNC stall of an instruction that wrote memory.
+    __host__ __device__ __forceinline__ void finish(uint32_t opc, ExecInfo &info, int32_t t0, int32_t n, bool wr) {
+        cyc = t0 + n;
+        hook.after_exec(*this, opc, t0, cyc, info);
+        if (wr && wsync) {
+            wsync = 0;
+            const int32_t q = cyc % kCyclesPerLine;
+            if (q) cyc += kCyclesPerLine - q;
+        }
+    }
+
+    // The instruction up to (kDefer) or including its memory write; returns whether it
+    // writes memory.  With kDefer the write (page 0 or stack, at ea with value r, in
+    // the last cycle) is left to the caller, which then calls finish().
+    template <bool kDefer>
+    __host__ __device__ __forceinline__ bool exec_body(uint32_t opc, uint32_t d, uint32_t lo, uint32_t hi,
+                                                       ExecInfo &info, int32_t &t0_out, int32_t &n_out,
+                                                       uint32_t &ea_out, uint32_t &r_out) {
         constexpr bool R = Hook::kRecord;
+        ea_out = r_out = 0;
+        (void)opc;
         const uint32_t cls = d & 63u, mode = (d >> 6) & 15u;
         const int32_t t0 = cyc;
         int32_t n = (int32_t)((d >> 10) & 7u);
@@ -701,18 +728,17 @@ struct Cpu {
             }
 
             // ---- write
-            if (wr) {
+            if constexpr (kDefer) {
+                ea_out = ea;
+                r_out = r;
+            } else if (wr) {
                 if (zpt) write_zp(ea, r, tl);
                 else write(ea, r, tl);
             }
         }
-        cyc = t0 + n;
-        hook.after_exec(*this, opc, t0, cyc, info);
-        if (wr && wsync) {
-            wsync = 0;
-            const int32_t q = cyc % kCyclesPerLine;
-            if (q) cyc += kCyclesPerLine - q;
-        }
+        t0_out = t0;
+        n_out = n;
+        return wr;
     }
 
     // JSR, RTS, RTI, BRK (several stack accesses, all in the last cycle) and JMP (ind).

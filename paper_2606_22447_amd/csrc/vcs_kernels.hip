@@ -34,6 +34,8 @@ struct DeviceWave {
     // makes v opaque to the optimiser (no instruction): code that uses it cannot be
     // hoisted out of the loop that contains this call
     __device__ static __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
+    // the same for a wave-uniform value (kept in a scalar register)
+    __device__ static __forceinline__ void opaque_uniform(uint32_t &v) { asm volatile("" : "+s"(v)); }
     // entry u (wave-uniform) of a read-only table in constant memory: a scalar
     // load, so that what is derived from it stays in scalar registers and the
     // branches on it are scalar branches
@@ -54,6 +56,7 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     constexpr int E = TPB / G;
     extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
     __shared__ __align__(16) uint32_t ram_lds[kPlain ? 4 : 32 * E];
+    __shared__ uint32_t dec_lds[kPlain ? 1 : 256];
     const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
     const int32_t blk = blockIdx.x;
     const int32_t rom_idx = P.st.main_block_rom[blk];
@@ -66,8 +69,9 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     } else {
         for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
             rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
+        for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
         __syncthreads();
-        LdsWordMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
+        LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
     }
 }

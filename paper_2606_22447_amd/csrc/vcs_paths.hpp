@@ -37,9 +37,11 @@ struct LdsMem {
 // LDS with a pre-decoded ROM: word[off].x = byte(off) | byte(off+1) << 8 |
 // byte(off+2) << 16 (the successors taken inside the image's 2K mirror or 4K
 // bank) and word[off].y = decode entry of byte(off), so one read yields an
-// opcode, both operand bytes and the opcode's decode.
+// opcode, both operand bytes and the opcode's decode.  dec is the decode
+// table (256 entries), also in LDS.
 struct LdsWordMem {
     const uint2 *rom;
+    const uint32_t *dec;
     uint8_t *ram;
     uint32_t E, slot;
     __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off].x & 0xFFu; }
@@ -82,22 +84,28 @@ __host__ __device__ __forceinline__ void fetch3(C &c, uint32_t &opc, uint32_t &l
 }
 
 // Opcode, operand bytes and decode entry at pc from a word memory: inside
-// $1000-$1FFD the three bytes lie in the cartridge window and one LDS read
-// serves them; elsewhere three fetch reads and a table lookup.
-template <class C>
-__host__ __device__ __forceinline__ void fetch_word(C &c, const uint32_t *decode, uint32_t &opc, uint32_t &lo,
-                                                    uint32_t &hi, uint32_t &dec) {
+// $1000-$1FFD the three bytes lie in the cartridge window and the LDS word
+// serves them; elsewhere (code in RAM, or an instruction that runs past $1FFF)
+// three fetch reads and the decode table.  The word is read for every lane
+// (its offset is always inside the image); only when some lane of the wave
+// needs the slow fetch does the wave branch.
+template <class W, class C>
+__host__ __device__ __forceinline__ void fetch_word(C &c, uint32_t &opc, uint32_t &lo, uint32_t &hi, uint32_t &dec) {
     const uint32_t pc = c.pc;
-    if ((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu) {
-        const uint2 w = c.mem.rom_word(c.cart_off(pc));
-        opc = w.x & 0xFFu;
-        lo = (w.x >> 8) & 0xFFu;
-        hi = w.x >> 16;
-        dec = w.y;
-        return;
+    uint2 w = c.mem.rom_word(c.cart_off(pc));
+    W::opaque(w.x);  // both halves now: keeps the word one LDS read
+    W::opaque(w.y);
+    opc = w.x & 0xFFu;
+    lo = (w.x >> 8) & 0xFFu;
+    hi = w.x >> 16;
+    dec = w.y;
+    const bool slow = !((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu);
+    if (W::any(slow)) {
+        if (slow) {
+            fetch3(c, opc, lo, hi);
+            dec = c.mem.dec[opc];
+        }
     }
-    fetch3(c, opc, lo, hi);
-    dec = decode[opc];
 }
 
 // Global memory: the env's ROM image and its 128 RAM bytes in the state record.
@@ -188,52 +196,81 @@ struct TapeHook {
 
 // ---------------------------------------------------------------------------
 // Dispatch of one instruction whose opcode u (decode d) is the same in every
-// lane of the call.  The opcodes that dominate VCS game code (zero-page and
-// immediate loads and stores, branches, stack, counters, flag ops) each get
-// a copy of the interpreter with its decode entry known at compile time, so
-// the mode/class dispatch and the timing arithmetic fold away; every other
-// opcode goes through the generic path.
+// lane of the call.  Opcodes whose data accesses all fall in page 0 or the
+// stack (immediate, implied, zero-page, stack and relative forms: most of
+// what VCS game code executes) run a copy of the interpreter with the decode
+// entry known at compile time, with the page-0 read done branch-free and the
+// write, if any, deferred until after the opcode switch.  The switch then has
+// no per-lane branch and compiles to a scalar branch tree.  Every other
+// opcode takes the generic path.
 // ---------------------------------------------------------------------------
-template <uint32_t OP, class C>
-__host__ __device__ __forceinline__ void exec_fixed(C &c, uint32_t lo, uint32_t hi, ExecInfo &info) {
-    constexpr uint32_t D = decode_op(OP);
-    static_assert(D != 0, "jam opcodes take the generic path");
-    c.exec(OP, D, lo, hi, info);
+constexpr bool fast_form(uint32_t op) {
+    const uint32_t d = decode_op(op), cls = d & 63u, mode = (d >> 6) & 15u;
+    if (d == 0 || cls == C_JSR || cls == C_BRK || mode == M_IND) return false;
+    const bool page0 = mode == M_IMP || mode == M_ACC || mode == M_IMM || mode == M_REL || mode == M_ZP ||
+                       mode == M_ZPX || mode == M_ZPY;
+    return page0 || (mode == M_ABS && cls == C_JMP);
 }
 
-template <class C>
+template <uint32_t OP, class C>
+__host__ __device__ __forceinline__ bool exec_fast(C &c, uint32_t lo, uint32_t hi, ExecInfo &info, int32_t &t0,
+                                                   int32_t &n, uint32_t &ea, uint32_t &r) {
+    static_assert(fast_form(OP), "not a page-0 form");
+    constexpr uint32_t D = decode_op(OP);
+    return c.template exec_body<true>(OP, D, lo, hi, info, t0, n, ea, r);
+}
+
+template <class W, class C>
 __host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_t d, uint32_t lo, uint32_t hi,
                                                        ExecInfo &info) {
-#define VCS_FIXED(op) \
-    case op: exec_fixed<op>(c, lo, hi, info); return;
+    bool fast = true, wr = false;
+    int32_t t0 = 0, n = 0;
+    uint32_t ea = 0, r = 0;
+#define VCS_FAST(op) \
+    case op: wr = exec_fast<op>(c, lo, hi, info, t0, n, ea, r); break;
     switch (u) {
-        VCS_FIXED(0x85) VCS_FIXED(0x86) VCS_FIXED(0x84)                  // STA STX STY zp
-        VCS_FIXED(0xA5) VCS_FIXED(0xA6) VCS_FIXED(0xA4) VCS_FIXED(0xB5)  // LDA LDX LDY zp, LDA zp,X
-        VCS_FIXED(0xA9) VCS_FIXED(0xA2) VCS_FIXED(0xA0)                  // LDA LDX LDY #
-        VCS_FIXED(0xD0) VCS_FIXED(0xF0) VCS_FIXED(0x10) VCS_FIXED(0x30)  // BNE BEQ BPL BMI
-        VCS_FIXED(0x90) VCS_FIXED(0xB0)                                  // BCC BCS
-        VCS_FIXED(0x48) VCS_FIXED(0x68)                                  // PHA PLA
-        VCS_FIXED(0x88) VCS_FIXED(0xCA) VCS_FIXED(0xC8) VCS_FIXED(0xE8)  // DEY DEX INY INX
-        VCS_FIXED(0xE6) VCS_FIXED(0xC6)                                  // INC DEC zp
-        VCS_FIXED(0x38) VCS_FIXED(0x18) VCS_FIXED(0xD8) VCS_FIXED(0xF8)  // SEC CLC CLD SED
-        VCS_FIXED(0x65) VCS_FIXED(0xE5) VCS_FIXED(0x69) VCS_FIXED(0xE9)  // ADC SBC zp, #
-        VCS_FIXED(0x49) VCS_FIXED(0x29) VCS_FIXED(0x09) VCS_FIXED(0xC9)  // EOR AND ORA CMP #
-        VCS_FIXED(0x46) VCS_FIXED(0x4A) VCS_FIXED(0x0A)                  // LSR zp, LSR A, ASL A
-        VCS_FIXED(0xAA) VCS_FIXED(0x8A)                                  // TAX TXA
-        VCS_FIXED(0x4C) VCS_FIXED(0x20) VCS_FIXED(0x60)                  // JMP JSR RTS
-        VCS_FIXED(0x8D) VCS_FIXED(0xAD) VCS_FIXED(0xBD) VCS_FIXED(0xB9)  // STA LDA abs, LDA abs,X / abs,Y
-        default: c.exec(u, d, lo, hi, info); return;
+        VCS_FAST(0x85) VCS_FAST(0x86) VCS_FAST(0x84) VCS_FAST(0x95) VCS_FAST(0x94) VCS_FAST(0x96)  // stores
+        VCS_FAST(0xA5) VCS_FAST(0xA6) VCS_FAST(0xA4) VCS_FAST(0xB5) VCS_FAST(0xB4) VCS_FAST(0xB6)  // loads zp
+        VCS_FAST(0xA9) VCS_FAST(0xA2) VCS_FAST(0xA0)                                               // loads #
+        VCS_FAST(0x10) VCS_FAST(0x30) VCS_FAST(0x50) VCS_FAST(0x70)                                // branches
+        VCS_FAST(0x90) VCS_FAST(0xB0) VCS_FAST(0xD0) VCS_FAST(0xF0)
+        VCS_FAST(0x48) VCS_FAST(0x68) VCS_FAST(0x08) VCS_FAST(0x28) VCS_FAST(0x60) VCS_FAST(0x40)  // stack, RTS, RTI
+        VCS_FAST(0x88) VCS_FAST(0xCA) VCS_FAST(0xC8) VCS_FAST(0xE8)                                // DEY DEX INY INX
+        VCS_FAST(0xE6) VCS_FAST(0xC6) VCS_FAST(0xF6) VCS_FAST(0xD6)                                // INC DEC zp, zp,X
+        VCS_FAST(0x38) VCS_FAST(0x18) VCS_FAST(0xD8) VCS_FAST(0xF8) VCS_FAST(0x78) VCS_FAST(0x58)  // flags
+        VCS_FAST(0xB8)
+        VCS_FAST(0x65) VCS_FAST(0xE5) VCS_FAST(0x69) VCS_FAST(0xE9) VCS_FAST(0x75) VCS_FAST(0xF5)  // ADC SBC
+        VCS_FAST(0x29) VCS_FAST(0x09) VCS_FAST(0x49) VCS_FAST(0x25) VCS_FAST(0x05) VCS_FAST(0x45)  // AND ORA EOR
+        VCS_FAST(0xC9) VCS_FAST(0xE0) VCS_FAST(0xC0) VCS_FAST(0xC5) VCS_FAST(0xE4) VCS_FAST(0xC4)  // CMP CPX CPY
+        VCS_FAST(0x24)                                                                             // BIT zp
+        VCS_FAST(0x0A) VCS_FAST(0x4A) VCS_FAST(0x2A) VCS_FAST(0x6A)                                // shifts A
+        VCS_FAST(0x06) VCS_FAST(0x46) VCS_FAST(0x26) VCS_FAST(0x66)                                // shifts zp
+        VCS_FAST(0xAA) VCS_FAST(0xA8) VCS_FAST(0x8A) VCS_FAST(0x98) VCS_FAST(0xBA) VCS_FAST(0x9A)  // transfers
+        VCS_FAST(0xEA) VCS_FAST(0x4C)                                                              // NOP, JMP abs
+        default: fast = false; break;
     }
-#undef VCS_FIXED
+#undef VCS_FAST
+    // The switch's outcome goes through an opaque scalar so that the optimiser
+    // cannot thread the per-lane write below back into the cases (which would
+    // put per-lane branches inside the switch).
+    uint32_t how = (fast ? 1u : 0u) | (wr ? 2u : 0u);
+    W::opaque_uniform(how);
+    if (how & 1u) {
+        if (how & 2u) c.write_zp(ea, r, t0 + n - 1);
+        c.finish(u, info, t0, n, (how & 2u) != 0u);
+    } else {
+        c.exec(u, d, lo, hi, info);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Per-env bodies of the kernels.  W is the wave policy: any(v) / all(v) (is v
 // true in any / every active lane of the wave), first(v) (v of the first active
 // lane), table(t, u) (entry u of a constant table, u the same in every active
-// lane) and opaque(v) (hide v from the optimiser); on the GPU they are ballots,
-// readfirstlane, a scalar load and an empty asm, and the ROM image must already
-// be staged in LDS by the whole workgroup.
+// lane) and opaque(v) / opaque_uniform(v) (hide a per-lane / wave-uniform v from
+// the optimiser); on the GPU they are ballots, readfirstlane, a scalar load and
+// empty asm statements, and the ROM image must already be staged in LDS by the
+// whole workgroup.
 // ---------------------------------------------------------------------------
 template <class W, int G, bool kSoft, bool kPlain, class Mem>
 __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
@@ -346,13 +383,13 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     else c.exec(opc, d, lo, hi, info);
                 } else {
                     uint32_t dec;
-                    fetch_word(c, decode, opc, lo, hi, dec);
+                    fetch_word<W>(c, opc, lo, hi, dec);
                     const uint32_t u = W::first(opc);
                     const uint32_t d = W::first(dec);
                     if (W::all(opc == u)) {
                         // the usual case: every running lane has the same opcode
                         if (d == 0) c.jam = 1;
-                        else exec_dispatch(c, u, d, lo, hi, info);
+                        else exec_dispatch<W>(c, u, d, lo, hi, info);
                     } else {
                         // waterfall: each pass executes one distinct opcode of the
                         // wave with a wave-uniform (scalar) decode.  The operands and
