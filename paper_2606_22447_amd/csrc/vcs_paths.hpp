@@ -220,6 +220,20 @@ __host__ __device__ __forceinline__ bool exec_fast(C &c, uint32_t lo, uint32_t h
     return c.template exec_body<true>(OP, D, lo, hi, info, t0, n, ea, r);
 }
 
+// A page-0 / stack write (address a8 < $100) from every running lane.  When all
+// lanes write the same address (lockstep code: STA WSYNC, STA COLUBK, ...) the
+// RAM/TIA decision and the TIA register switch are taken once, on a scalar.
+template <class W, class C>
+__host__ __device__ __forceinline__ void write_page0(C &c, uint32_t a8, uint32_t v, int32_t w) {
+    const uint32_t u8 = W::first(a8);
+    if (W::all(a8 == u8)) {
+        if (u8 & 0x80u) c.mem.ram_set(u8 & 0x7Fu, v);
+        else c.tia_out(u8 & 0x3Fu, v, w);
+    } else {
+        c.write_zp(a8, v, w);
+    }
+}
+
 template <class W, class C>
 __host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_t d, uint32_t lo, uint32_t hi,
                                                        ExecInfo &info) {
@@ -256,7 +270,7 @@ __host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_
     uint32_t how = (fast ? 1u : 0u) | (wr ? 2u : 0u);
     W::opaque_uniform(how);
     if (how & 1u) {
-        if (how & 2u) c.write_zp(ea, r, t0 + n - 1);
+        if (how & 2u) write_page0<W>(c, ea, r, t0 + n - 1);
         c.finish(u, info, t0, n, (how & 2u) != 0u);
     } else {
         c.exec(u, d, lo, hi, info);
