@@ -80,6 +80,7 @@ def parse():
                     help="comma list of: hard, plain, hetero, soft, cpu")
     ap.add_argument("--soft-k", default="256,1024,4096")
     ap.add_argument("--soft-passes", type=int, default=2)
+    ap.add_argument("--soft-lanes", type=int, default=0, help="lanes per env of the soft forward (0 = auto)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
     return ap.parse_args()
 
@@ -177,7 +178,7 @@ def soft_leg(args):
                        "frame-skip 1, FP32 ROM logits/RAM tape/action logits, tau 1.0, alpha 6",
            "env_steps_per_pass": B * S, "by_ckpt_interval": {}}
     for K in [int(k) for k in args.soft_k.split(",")]:
-        sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=K)
+        sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=K, lanes_per_env=args.soft_lanes)
 
         def one(_i):
             L.grad = T.grad = A.grad = None

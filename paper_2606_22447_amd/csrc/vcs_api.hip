@@ -469,7 +469,7 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     P.gport = (float *)(work + W.gport);
     P.g_ram0 = (float *)(work + W.g0);
     P.overflow = (int32_t *)(work + W.overflow);
-    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, stream));
+    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, ctx->max_rom, stream));
     if (rc) return rc;
     const StaticPtrs sp = static_ptrs(ctx, d_work);
     return hip_status(launch_epilogue(d_rom_logits, (const float *)(res + L.rom_stats), P.gpart, ctx->total_rom,

@@ -308,7 +308,8 @@ __host__ __device__ __forceinline__ bool pixel_sums(const float *gframe, int32_t
         const float *row = gframe + y * kScreenW;
         float acc = 0.f;
         for (int32_t x = xa; x < xb; ++x) acc += row[x];
-        sums[group_owner((uint32_t)g, mask, ctrl)] += acc;
+        const uint32_t o = group_owner((uint32_t)g, mask, ctrl);
+        for (uint32_t k = 0; k < 4; ++k) sums[k] += o == k ? acc : 0.f;  // constant indices: stays in registers
         any = true;
     });
     return any;

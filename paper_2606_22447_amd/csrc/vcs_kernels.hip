@@ -30,6 +30,11 @@ typedef const __attribute__((address_space(4))) uint32_t ConstU32;
 struct DeviceWave {
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
     __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
+    // *p += t without waiting for the result (a no-return atomic add).  Only one lane
+    // adds to a given p, so the additions happen in program order.
+    __device__ static __forceinline__ void accumulate(float *p, float t) {
+        (void)__hip_atomic_fetch_add(p, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
     // makes v opaque to the optimiser (no instruction): code that uses it cannot be
     // hoisted out of the loop that contains this call
@@ -77,15 +82,17 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
 }
 
 // ---------------------------------------------------------------------------
-// Soft backward: one env per wave (its first lane), kBwdEnvs envs of one ROM
-// per workgroup.  The recompute-and-reverse chain of an env is serial, so the
-// envs are spread over as many waves as possible to interleave their latency.
+// Soft backward: one env per wave (its first lane), kBwdSlots envs of one ROM
+// per workgroup sharing the pre-decoded ROM words in LDS.  The
+// recompute-and-reverse chain of an env is serial, so the envs are spread over
+// as many waves as possible to interleave their latency.
 // ---------------------------------------------------------------------------
 constexpr int kBwdTPB = kBwdSlots * 64;
 
 __global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
     constexpr int E = kBwdSlots;
-    __shared__ __align__(16) uint8_t rom_lds[8192];
+    extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
+    __shared__ uint32_t dec_lds[256];
     __shared__ __align__(16) uint32_t ram_lds[32 * E];
     __shared__ float adj_ram[128 * E];
     const uint32_t tid = threadIdx.x, slot = tid / 64;
@@ -94,13 +101,15 @@ __global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
     const uint32_t gslot = (uint32_t)blk * E + slot;
     const int32_t rom_idx = P.st.bwd_block_rom[blk];
     const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
-    for (int32_t i = (int32_t)tid * 16; i < rom_size; i += kBwdTPB * 16)
-        *reinterpret_cast<uint4 *>(rom_lds + i) = *reinterpret_cast<const uint4 *>(P.rom + rom_base + i);
+    const int32_t mapper = P.st.rom_mapper[rom_idx];
+    for (int32_t i = (int32_t)tid; i < rom_size; i += kBwdTPB)
+        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
+    for (int32_t i = (int32_t)tid; i < 256; i += kBwdTPB) dec_lds[i] = kDecodeDev.e[i];
     __syncthreads();
     if ((tid & 63u) != 0) return;
     const int32_t env = P.st.bwd_slot_env[gslot];
-    LdsMem m{rom_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
-    bwd_env<DeviceWave>(P, env, gslot, nslots, P.st.rom_mapper[rom_idx], m, adj_ram + slot, E, kDecodeDev.e);
+    LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
+    bwd_env<DeviceWave>(P, env, gslot, nslots, mapper, m, adj_ram + slot, E, kDecodeDev.e);
 }
 
 // ---------------------------------------------------------------------------
@@ -397,8 +406,8 @@ hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, hipStream_t stream) {
-    hipLaunchKernelGGL(k_soft_bwd, dim3(blocks), dim3(kBwdTPB), 0, stream, P);
+hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream) {
+    hipLaunchKernelGGL(k_soft_bwd, dim3(blocks), dim3(kBwdTPB), (size_t)max_rom_size * sizeof(uint2), stream, P);
     return hipGetLastError();
 }
 

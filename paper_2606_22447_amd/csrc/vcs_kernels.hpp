@@ -7,7 +7,7 @@ namespace vcs {
 
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
                        int32_t max_rom_size, hipStream_t stream);
-hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, hipStream_t stream);
+hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream);
 hipError_t launch_decode(const float *rom_logits, int64_t rom_rows, const float *tape, int64_t tape_rows,
                          const float *act_logits, int64_t act_rows, float tau, uint8_t *rom_hard, float *rom_stats,
                          uint8_t *ram0_hard, float *tape_ev, uint8_t *act_hard, float *act_stats, hipStream_t stream);
@@ -22,6 +22,6 @@ hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const u
 hipError_t launch_read_regs(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 
-constexpr int kBwdSlots = 4;  // envs per soft-backward workgroup (one wave each)
+constexpr int kBwdSlots = 16;  // envs per soft-backward workgroup (one wave each)
 
 }  // namespace vcs

@@ -383,11 +383,23 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 
     while (W::any(active)) {
         // ---- the instructions of one frame (the hot loop; a lane leaves it at
-        // its frame's end, the wave when every lane has)
+        // its frame's end, the wave when every lane has).  A soft forward also
+        // leaves it at its next checkpoint cycle, takes the checkpoint and goes on,
+        // so the hot loop itself tests no checkpoint condition.
         bool run = active && !c.jam && c.cyc < kCyclesPerFrame;
-        while (run) {
-            {
-                checkpoint();
+        for (;;) {
+            int32_t lim = kCyclesPerFrame;  // frame-relative cycle at which the lane stops
+            if constexpr (kSoft) {
+                if (run) {
+                    checkpoint();
+                    if (P.ckpt) {
+                        const int64_t rel = next_ckpt - (int64_t)frame * kCyclesPerFrame;
+                        lim = rel < (int64_t)kCyclesPerFrame ? (int32_t)rel : kCyclesPerFrame;
+                    }
+                }
+            }
+            bool go = run && c.cyc < lim;
+            while (go) {
                 uint32_t opc, lo, hi;
                 ExecInfo info;
                 if constexpr (kPlain) {
@@ -426,8 +438,11 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                         }
                     }
                 }
-                run = !c.jam && c.cyc < kCyclesPerFrame;
+                go = !c.jam && c.cyc < lim;
             }
+            run = active && !c.jam && c.cyc < kCyclesPerFrame;
+            if constexpr (!kSoft) break;
+            if (!W::any(run)) break;
         }
         if (!active) continue;
         checkpoint();
@@ -505,20 +520,20 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 // their checkpoint into the tape and swept in reverse.  adj_ram is the env's
 // RAM adjoint, float [128] with stride E.  The env's lane must be the only
 // active lane of its wave.
-template <class W>
+template <class W, class Mem>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
-                                                 int32_t mapper, LdsMem mem, float *adj_ram, uint32_t E,
+                                                 int32_t mapper, Mem mem, float *adj_ram, uint32_t E,
                                                  const uint32_t *decode) {
     const bool live = env >= 0;
     const int32_t S = P.steps, F = P.frame_skip, K = P.ckpt_interval;
     for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] = 0.f;
 
-    Cpu<LdsMem, TapeHook> c;
+    Cpu<Mem, TapeHook> c;
     c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
     c.f8 = mapper == 2 ? 1u : 0u;
     c.mem = mem;
-    c.hook.tape = P.tape + gslot;
-    c.hook.stride = nslots;
+    c.hook.tape = P.tape + (size_t)gslot * (size_t)P.max_rec;  // the env's records, contiguous
+    c.hook.stride = 1;
     c.hook.max_rec = P.max_rec;
     c.hook.ystart = P.ystart;
     c.hook.overflow = P.overflow;
@@ -533,9 +548,9 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     auto add_src = [&](uint32_t cls, uint32_t idx, uint32_t step, float t) {
         switch (cls) {
             case kClsRam: adj_ram[idx * E] += t; break;
-            case kClsRom: P.gpart[(size_t)idx * nslots + gslot] += t; break;
-            case kClsSwcha: P.gport[((size_t)env * S + step) * 2] += t; break;
-            case kClsInpt4: P.gport[((size_t)env * S + step) * 2 + 1] += t; break;
+            case kClsRom: W::accumulate(&P.gpart[(size_t)idx * nslots + gslot], t); break;
+            case kClsSwcha: W::accumulate(&P.gport[((size_t)env * S + step) * 2], t); break;
+            case kClsInpt4: W::accumulate(&P.gport[((size_t)env * S + step) * 2 + 1], t); break;
             case kClsRegA: aA += t; break;
             default: break;
         }
@@ -628,22 +643,32 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                         }
                         if (rec_active) set_ports();
                     } else {
-                        uint32_t opc, lo, hi;
-                        fetch3(c, opc, lo, hi);
+                        uint32_t opc, lo, hi, dec;
+                        fetch_word<W>(c, opc, lo, hi, dec);
                         ExecInfo info;
                         // the env's lane runs alone, so its opcode is wave-uniform
                         const uint32_t u = W::first(opc);
-                        const uint32_t d = W::table(decode, u);
+                        const uint32_t d = W::first(dec);
                         if (d == 0) c.jam = 1;
-                        else c.exec(u, d, lo, hi, info);
+                        else exec_dispatch<W>(c, u, d, lo, hi, info);
                     }
                 }
             }
 
             // ---- reverse sweep of the segment's tape
             const int32_t nrec = c.hook.nrec < c.hook.max_rec ? c.hook.nrec : c.hook.max_rec;
+            const TapeRec *tp = c.hook.tape;
+            TapeRec nx;  // the next record, read one iteration ahead
+            if (nrec > 0) nx = tp[nrec - 1];
             for (int32_t i = nrec - 1; i >= 0; --i) {
-                const TapeRec r = c.hook.tape[(size_t)i * nslots];
+                TapeRec r = nx;
+                if (i > 0) nx = tp[i - 1];
+                // the env's lane runs alone: its record fields are wave-uniform, so the
+                // sweep's branches on them are scalar branches
+                r.w0 = W::first(r.w0);
+                r.w1 = W::first(r.w1);
+                r.w2 = W::first(r.w2);
+                r.w3 = W::first(r.w3);
                 const uint32_t kind = (r.w0 >> 16) & 15u;
                 const uint32_t step = r.w3;
                 if (kind == kRecStepEnd) {
@@ -665,7 +690,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                 const uint32_t rd_idx = r.w1 & 0xFFFFu, wr_idx = r.w1 >> 16;
                 const float v1 = (float)(r.w2 & 0xFFu), v2 = (float)((r.w2 >> 8) & 0xFFu);
                 const uint32_t sb = (r.w2 >> 16) & 0xFFu;
-                const uint32_t d = W::table(decode, W::first(opc));  // the env's lane is the only one active
+                const uint32_t d = W::table(decode, opc);  // the env's lane is the only one active
                 const uint32_t cls = d & 63u;
                 switch (cls) {
                     case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
