@@ -177,8 +177,18 @@ def soft_leg(args):
     out = {"workload": "c4_soft_scale: 64 ROMs (21x2K, 22x4K, 21xF8) x 64 envs = 4096 envs, 60 frames, "
                        "frame-skip 1, FP32 ROM logits/RAM tape/action logits, tau 1.0, alpha 6",
            "env_steps_per_pass": B * S, "by_ckpt_interval": {}}
+    lanes = args.soft_lanes
+    if lanes == 0:  # autotune the soft forward's lanes per env on a short trial of this workload
+        from paper_2606_22447_amd import autotune
+        tuned = autotune.tune_soft(w.roms, w.env_rom, L.detach(), T.detach(), A.detach(), 1.0, 6.0,
+                                   trial_steps=6, ckpt=(1024,))
+        lanes = tuned["lanes_per_env"]
+        out["autotune"] = {"lanes_per_env": lanes,
+                           "trials": [(r["lanes_per_env"], round(r["env_steps_per_s"])) for r in tuned["table"]]}
+        log("soft autotune", out["autotune"])
+    out["lanes_per_env"] = lanes
     for K in [int(k) for k in args.soft_k.split(",")]:
-        sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=K, lanes_per_env=args.soft_lanes)
+        sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=K, lanes_per_env=lanes)
 
         def one(_i):
             L.grad = T.grad = A.grad = None
@@ -250,8 +260,17 @@ def main():
     log(f"c1: {args.envs} envs x {total_steps} env steps")
     ips = instructions_per_step(w1)
     result = {}
+    tuned = {}
     if "hard" in legs:
-        result["hard"] = hard_leg(args, args.kernel, args.lanes, args.tpb, w1)
+        lanes, tpb = args.lanes, args.tpb
+        if lanes == 0 and args.kernel == "grouped":  # autotune the launch shape on this workload
+            from paper_2606_22447_amd import autotune
+            t = autotune.tune_hard(w1.roms, w1.env_rom, frame_skip=w1.frame_skip, seed=w1.seed, ram0=w1.ram0,
+                                   actions=w1.actions, trial_steps=2)
+            lanes, tpb = t["lanes_per_env"], t["block_threads"]
+            tuned["hard"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"])) for r in t["table"]]
+            log("hard autotune", tuned["hard"])
+        result["hard"] = hard_leg(args, args.kernel, lanes, tpb, w1)
         log("hard", result["hard"])
     if "plain" in legs:
         pa = argparse.Namespace(**vars(args))
@@ -262,7 +281,12 @@ def main():
         ha = argparse.Namespace(**vars(args))
         ha.chunk, ha.steps, ha.warmup = 25, 4, 1
         w2 = I.config_c2(steps=25 * 5)
-        result["hetero"] = hard_leg(ha, args.kernel, 0, 0, w2)
+        from paper_2606_22447_amd import autotune
+        t = autotune.tune_hard(w2.roms, w2.env_rom, frame_skip=w2.frame_skip, seed=w2.seed, ram0=w2.ram0,
+                               actions=w2.actions, trial_steps=2)
+        tuned["hetero"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"])) for r in t["table"]]
+        log("hetero autotune", tuned["hetero"])
+        result["hetero"] = hard_leg(ha, args.kernel, t["lanes_per_env"], t["block_threads"], w2)
         result["hetero"]["workload"] = ("c2_hetero_persistent: 64 ROMs (21x2K, 22x4K, 21xF8, reading SWCHA/INPT4/"
                                         "INTIM) x 256 envs = 16384 envs, frame-skip 4, geometric episodes "
                                         "(mean 1500 frames) with in-run resets")
@@ -308,7 +332,10 @@ def main():
                                 "speedup_of_grouped": h["env_steps_per_s"] / result["plain"]["env_steps_per_s"]}
     if "hetero" in result:
         line["hetero"] = {k: result["hetero"][k] for k in ("env_steps_per_s", "ms_per_call", "parity_sample",
-                                                           "workload")}
+                                                           "workload", "launch")}
+    if tuned:
+        line["autotune"] = {k: {"trials (lanes_per_env, block_threads, env_steps_per_s)": v}
+                            for k, v in tuned.items()}
     if "soft" in result:
         line["soft_fwd_bwd"] = result["soft"]
     line["cpu_baseline"] = cpu

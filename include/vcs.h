@@ -141,7 +141,11 @@ int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint
  *                 in episode e < E it is reset in-run (power-on, RAM =
  *                 SplitMix64(seed, env, e+1)) and the next step starts the new
  *                 episode;
- *  d_work         workspace of vcs_workspace_bytes(VCS_OP_HARD). */
+ *  d_work         workspace of vcs_workspace_bytes(VCS_OP_HARD).
+ * The stream work of a call is one host-to-device copy of the launch tables
+ * into d_work and one kernel, so a call can be captured in a HIP graph once the
+ * context has made a device call (vcs_reset, or an earlier step); a context's
+ * first device call inside a capture returns VCS_UNSUPPORTED. */
 int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
                       uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
                       const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream);

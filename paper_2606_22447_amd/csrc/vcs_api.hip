@@ -110,15 +110,28 @@ StaticPtrs static_ptrs(const vcs_ctx *c, const void *d_work) {
     return p;
 }
 
+// Pinned host copy of the static region, made on the context's first device call.
+int32_t ensure_pinned(vcs_ctx *c) {
+    if (c->pinned) return VCS_OK;
+    if (hipHostMalloc((void **)&c->pinned, c->blob_bytes, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        return VCS_HIP_ERROR;
+    }
+    std::memcpy(c->pinned, c->image.data(), c->blob_bytes);
+    return VCS_OK;
+}
+
 // Copy the static region (ROM table, env grouping) into the head of the
 // caller's workspace, ordered on the stream before the kernels that read it.
+// Inside a stream capture the pinned copy must already exist (allocating host
+// memory would invalidate the capture).
 int32_t upload_static(vcs_ctx *c, void *d_work, hipStream_t stream) {
     if (!c->pinned) {
-        if (hipHostMalloc((void **)&c->pinned, c->blob_bytes, hipHostMallocDefault) != hipSuccess) {
-            c->pinned = nullptr;
-            return VCS_HIP_ERROR;
-        }
-        std::memcpy(c->pinned, c->image.data(), c->blob_bytes);
+        hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(stream, &st) == hipSuccess && st != hipStreamCaptureStatusNone)
+            return VCS_UNSUPPORTED;
+        const int32_t rc = ensure_pinned(c);
+        if (rc != VCS_OK) return rc;
     }
     if (hipMemcpyAsync(d_work, c->pinned, c->blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         return VCS_HIP_ERROR;
@@ -344,6 +357,8 @@ int32_t vcs_residual_checkpoints(const vcs_ctx *ctx, int32_t steps, int32_t *cou
 int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint8_t *d_ram0, hipStream_t stream) {
     if (!ctx || !d_state || !aligned16(d_state)) return VCS_INVALID_ARG;
     if (d_ram0 && ((uintptr_t)d_ram0 & 3u)) return VCS_INVALID_ARG;
+    const int32_t rc = ensure_pinned(ctx);  // so that later step calls can be captured
+    if (rc) return rc;
     return hip_status(launch_reset((StateRec *)d_state, ctx->B, d_mask, d_ram0, ctx->seed, stream));
 }
 

@@ -79,6 +79,7 @@ class VcsBatch(_Ctx):
         self.state = torch.zeros(n, dtype=torch.uint8, device=self.device)
 
     def reset(self, ram0=None, mask=None):
+        self._was_reset = True
         r0 = None if ram0 is None else torch.as_tensor(np.asarray(ram0, np.uint8) if not torch.is_tensor(ram0)
                                                        else ram0, device=self.device).contiguous()
         mk = None if mask is None else torch.as_tensor(mask, dtype=torch.uint8, device=self.device).contiguous()
@@ -115,6 +116,39 @@ class VcsBatch(_Ctx):
         Bd.check(rc, "vcs_step_hard")
         return ram_out, frame_out, done
 
+    def capture(self, actions: torch.Tensor, frames: str = "last", episode_steps=None):
+        """Record one step call of ``actions.shape[1]`` env steps as a HIP graph.
+
+        Returns (graph, ram_out, frame_out, done).  Each ``graph.replay()`` runs
+        those steps again from the current state, reading the device tensor
+        ``actions`` (refill it in place between replays) and writing the returned
+        output tensors.  The call's stream work is one host-to-device copy of the
+        launch tables and one kernel, so the graph holds no memset node.
+        """
+        assert getattr(self, "_was_reset", False), "reset() the batch before capturing its steps"
+        assert torch.is_tensor(actions) and actions.is_cuda and actions.dtype == torch.uint8
+        assert actions.is_contiguous() and actions.shape[0] == self.B
+        B, S = self.B, actions.shape[1]
+        mode = _FRAMES[frames]
+        ram_out = torch.empty((B, S, 128), dtype=torch.uint8, device=self.device)
+        frame_out = None
+        if mode != Bd.VCS_FRAMES_NONE:
+            shape = (B, S, 210, 160) if mode == Bd.VCS_FRAMES_ALL else (B, 210, 160)
+            frame_out = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        done = torch.empty((B, S), dtype=torch.uint8, device=self.device)
+        eps = None
+        if episode_steps is not None:
+            eps = episode_steps if torch.is_tensor(episode_steps) else torch.from_numpy(
+                np.ascontiguousarray(episode_steps, np.uint32).view(np.int32))
+            eps = eps.to(self.device).contiguous()
+        self.workspace(Bd.VCS_OP_HARD, S)  # allocated before capture
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.step(actions=actions, frames=frames, episode_steps=eps, ram_out=ram_out, frame_out=frame_out,
+                      done=done)
+        return graph, ram_out, frame_out, done
+
     def regs(self) -> torch.Tensor:
         out = torch.empty((self.B, 16), dtype=torch.uint8, device=self.device)
         Bd.check(Bd.lib().vcs_read_regs(self.h, Bd.ptr(self.state), Bd.ptr(out), _stream()), "vcs_read_regs")
@@ -128,6 +162,9 @@ class SoftVcs(_Ctx):
                  lanes_per_env: int = 0, block_threads: int = 0, device="cuda"):
         super().__init__(roms, env_rom, frame_skip, ystart, 0, ckpt_interval, "grouped", lanes_per_env,
                          block_threads, device)
+
+    def residual_bytes(self, steps: int) -> int:
+        return Bd.size_query("vcs_residual_bytes", self.h, steps)
 
     def decode_split(self, dec: torch.Tensor, steps: int):
         total = sum(self.rom_sizes)

@@ -73,3 +73,14 @@ def test_create_validates_arguments():
     assert L.vcs_status_string(-3).decode() == "workspace too small"
     L.vcs_destroy(h)
     np.testing.assert_equal(Bd.ABI_VERSION, 1)
+
+
+def test_autotune_candidates_are_valid_launch_shapes():
+    from paper_2606_22447_amd import autotune
+    for B in (1, 64, 4096, 16384, 1 << 20):
+        c = autotune.hard_candidates(B)
+        assert c, B
+        for g, t in c:
+            assert g in (1, 4, 16, 64) and t in (64, 256) and t >= g
+            waves = B * g / 64
+            assert waves <= 1024 * 8 or (g, t) == (1, 64)
