@@ -196,6 +196,18 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
  * COLUP1, COLUPF, COLUBK. */
 int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream);
 
+/* Inspect: a 64-bit fingerprint per env for bulk comparisons (the parity
+ * protocol compares them step by step against the reference emulator).
+ * d_out uint64 [B] (8-byte aligned) = FNV-1a 64 (Fowler/Noll/Vo; offset basis
+ * 0xcbf29ce484222325, prime 0x100000001b3) over, in order: the 16 bytes
+ * vcs_read_regs gives for the env, its 128 RAM bytes ($80..$FF), and, if
+ * d_frame is not NULL, the 33,600 bytes of the env's frame in row-major order
+ * at d_frame + env * frame_stride (4-byte aligned; frame_stride >= 33600 and a
+ * multiple of 4: 33600 for a [B][210][160] frame buffer, S * 33600 to pick one
+ * step of a [B][S][210][160] one). */
+int32_t vcs_hash(vcs_ctx *ctx, const void *d_state, const uint8_t *d_frame, int64_t frame_stride, uint64_t *d_out,
+                 hipStream_t stream);
+
 /* Number of soft checkpoints the forward wrote for the largest env (host
  * value; valid after the stream has completed the forward). */
 int32_t vcs_residual_checkpoints(const vcs_ctx *ctx, int32_t steps, int32_t *count);

@@ -63,7 +63,7 @@ def lib():
         L.orc_gate_grad.argtypes = [C.c_double, C.c_double]
         L.orc_gate_grad.restype = C.c_double
         L.orc_run_env.argtypes = [u8p, C.c_int, C.c_int, u8p, vp, C.c_int, C.c_int, C.c_int, vp, C.c_int,
-                                  C.c_uint64, C.c_int64, u8p, vp, C.c_int, vp, vp, vp]
+                                  C.c_uint64, C.c_int64, u8p, vp, C.c_int, vp, vp, vp, vp]
         L.orc_run_env.restype = C.c_int
         L.orc_decode_logit_rows.argtypes = [f32p, C.c_int64, C.c_int, C.c_double, u8p, f64p, f64p, f64p]
         L.orc_decode_tape_rows.argtypes = [f32p, C.c_int64, u8p, f64p]
@@ -181,8 +181,12 @@ def action_ports(a: int):
 # --------------------------------------------------------------------------
 
 def run_env(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int, frame_skip: int,
-            ystart: int = 34, ep_steps=None, seed: int = 0, env_index: int = 0, frames: str = "all"):
-    """Hard rollout of one env from power-on.  Returns a dict of numpy arrays."""
+            ystart: int = 34, ep_steps=None, seed: int = 0, env_index: int = 0, frames: str = "all",
+            step_state: bool = False):
+    """Hard rollout of one env from power-on.  Returns a dict of numpy arrays
+    (with step_state: "step_state" [steps][144] = after each step, the 16 register
+    bytes A X Y S P PCL PCH bank jammed INTIM TIMINT VBLANK COLUP0 COLUP1 COLUPF
+    COLUBK, then the 128 RAM bytes)."""
     L = lib()
     rom = np.ascontiguousarray(rom, dtype=np.uint8)
     ram0 = np.ascontiguousarray(ram0, dtype=np.uint8)
@@ -195,13 +199,17 @@ def run_env(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int,
     done = np.zeros(steps, np.uint8)
     regs = np.zeros(25, np.int64)
     instr = np.zeros(1, np.uint64)
+    st = np.zeros((steps, 144), np.uint8) if step_state else None
     rc = L.orc_run_env(rom, rom.size, mapper, ram0, _ptr(act), steps, frame_skip, ystart, _ptr(eps),
                        0 if eps is None else eps.size, seed, env_index, ram_out, _ptr(frame_out), mode,
-                       _ptr(done), _ptr(regs), _ptr(instr))
+                       _ptr(done), _ptr(regs), _ptr(instr), _ptr(st))
     if rc:
         raise ValueError("oracle rejected the configuration")
-    return {"ram": ram_out, "frames": frame_out[:nfr], "done": done,
-            "regs": dict(zip(REG_NAMES, regs.tolist())), "instructions": int(instr[0])}
+    out = {"ram": ram_out, "frames": frame_out[:nfr], "done": done,
+           "regs": dict(zip(REG_NAMES, regs.tolist())), "instructions": int(instr[0])}
+    if step_state:
+        out["step_state"] = st
+    return out
 
 
 def decode_logits(rows: np.ndarray, tau: float):

@@ -1127,7 +1127,7 @@ int orc_timint_at(const Orc *m, int64_t t) { return timint_at(m, t); }
 int orc_run_env(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, const uint8_t *actions,
                 int steps, int frame_skip, int ystart, const uint32_t *ep_steps, int n_episodes, uint64_t seed,
                 int64_t env_index, uint8_t *ram_out, uint8_t *frame_out, int frames_mode, uint8_t *done_out,
-                int64_t *final_regs, uint64_t *instructions) {
+                int64_t *final_regs, uint64_t *instructions, uint8_t *step_state) {
     Orc *m = orc_new();
     if (orc_power_on(m, rom, rom_size, mapper, ram0, ystart)) {
         orc_free(m);
@@ -1153,6 +1153,12 @@ int orc_run_env(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram
             orc_splitmix_ram(seed, (uint64_t)env_index, (uint64_t)ep, r);
             orc_power_on(m, rom, rom_size, mapper, r, ystart);
             ep_step = 0;
+        }
+        if (step_state) { /* machine state after the step: the 16 inspection bytes, then RAM */
+            int64_t rg[25];
+            orc_get_regs(m, rg);
+            for (int i = 0; i < 16; i++) step_state[(size_t)s * 144 + i] = (uint8_t)rg[i];
+            memcpy(step_state + (size_t)s * 144 + 16, m->ram, 128);
         }
     }
     total_instr += m->instructions;

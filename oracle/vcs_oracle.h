@@ -37,7 +37,7 @@ double orc_gate_grad(double z, double alpha);
 int orc_run_env(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, const uint8_t *actions,
                 int steps, int frame_skip, int ystart, const uint32_t *ep_steps, int n_episodes, uint64_t seed,
                 int64_t env_index, uint8_t *ram_out, uint8_t *frame_out, int frames_mode, uint8_t *done_out,
-                int64_t *final_regs, uint64_t *instructions);
+                int64_t *final_regs, uint64_t *instructions, uint8_t *step_state);
 
 void orc_decode_logit_rows(const float *rows, int64_t n, int k, double tau, uint8_t *hard, double *ev, double *mx,
                            double *z);

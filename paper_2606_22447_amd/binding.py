@@ -23,7 +23,7 @@ EXPORTED = [
     "vcs_create", "vcs_destroy", "vcs_status_string", "vcs_state_bytes", "vcs_rom_bytes",
     "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
     "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
-    "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table",
+    "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash",
 ]
 
 

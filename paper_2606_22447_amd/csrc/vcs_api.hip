@@ -499,6 +499,13 @@ int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStre
     return hip_status(launch_read_regs((const StateRec *)d_state, ctx->B, d_out, stream));
 }
 
+int32_t vcs_hash(vcs_ctx *ctx, const void *d_state, const uint8_t *d_frame, int64_t frame_stride, uint64_t *d_out,
+                 hipStream_t stream) {
+    if (!ctx || !d_state || !d_out || !aligned16(d_state) || ((uintptr_t)d_out & 7u)) return VCS_INVALID_ARG;
+    if (d_frame && (((uintptr_t)d_frame & 3u) || frame_stride < kPixels || (frame_stride & 3))) return VCS_INVALID_ARG;
+    return hip_status(launch_hash((const StateRec *)d_state, ctx->B, d_frame, frame_stride, d_out, stream));
+}
+
 int32_t vcs_decode_table(uint32_t *out) {
     if (!out) return VCS_INVALID_ARG;
     constexpr DecodeTable t = make_decode_table();

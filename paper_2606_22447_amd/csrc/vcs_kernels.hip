@@ -353,20 +353,56 @@ __global__ __launch_bounds__(256) void k_reset(StateRec *state, int32_t B, const
     r.ckpt_index = 0;
 }
 
-__global__ __launch_bounds__(256) void k_read_regs(const StateRec *state, int32_t B, uint8_t *out) {
-    const int32_t env = blockIdx.x * 256 + threadIdx.x;
-    if (env >= B) return;
-    const StateRec &r = state[env];
+// The 16 inspection bytes of a state record (layout of vcs_read_regs).
+__device__ __forceinline__ void regs16(const StateRec &r, uint8_t o[16]) {
     const int32_t t = r.cyc;
     const int32_t dd = t - r.tim_u;
     const uint32_t intim = dd < 0 ? ((uint32_t)(-1 - (dd >> r.tim_shift)) & 0xFFu) : ((uint32_t)(255 - dd) & 0xFFu);
     const uint32_t timint = (t >= r.tim_u && r.tim_read < r.tim_u) ? 0x80u : 0u;
-    uint8_t *o = out + (size_t)env * 16;
     o[0] = r.a; o[1] = r.x; o[2] = r.y; o[3] = r.s; o[4] = r.p;
     o[5] = (uint8_t)(r.pc & 0xFF); o[6] = (uint8_t)(r.pc >> 8); o[7] = r.bank; o[8] = r.status;
     o[9] = (uint8_t)intim; o[10] = (uint8_t)timint; o[11] = r.vblank;
     o[12] = (uint8_t)(r.col & 0xFF); o[13] = (uint8_t)((r.col >> 8) & 0xFF);
     o[14] = (uint8_t)((r.col >> 16) & 0xFF); o[15] = (uint8_t)(r.col >> 24);
+}
+
+__global__ __launch_bounds__(256) void k_read_regs(const StateRec *state, int32_t B, uint8_t *out) {
+    const int32_t env = blockIdx.x * 256 + threadIdx.x;
+    if (env >= B) return;
+    uint8_t o[16];
+    regs16(state[env], o);
+    for (int i = 0; i < 16; ++i) out[(size_t)env * 16 + i] = o[i];
+}
+
+// FNV-1a, 64-bit (Fowler, Noll, Vo): offset basis 14695981039346656037, prime 2^40 + 2^8 + 0xb3.
+__device__ __forceinline__ uint64_t fnv1a(uint64_t h, uint32_t byte) {
+    return (h ^ (uint64_t)byte) * 0x100000001B3ull;
+}
+
+// One thread per env: hash of the 16 inspection bytes, the 128 RAM bytes and, when
+// given, the env's 210 x 160 frame (rows at frame + env * frame_stride).
+__global__ __launch_bounds__(256) void k_hash(const StateRec *state, int32_t B, const uint8_t *frame,
+                                              int64_t frame_stride, uint64_t *out) {
+    const int32_t env = blockIdx.x * 256 + threadIdx.x;
+    if (env >= B) return;
+    const StateRec &r = state[env];
+    uint8_t o[16];
+    regs16(r, o);
+    uint64_t h = 0xCBF29CE484222325ull;
+    for (int i = 0; i < 16; ++i) h = fnv1a(h, o[i]);
+    const uint32_t *ram = reinterpret_cast<const uint32_t *>(r.ram);
+    for (int w = 0; w < 32; ++w) {
+        const uint32_t v = ram[w];
+        for (int k = 0; k < 4; ++k) h = fnv1a(h, (v >> (8 * k)) & 0xFFu);
+    }
+    if (frame) {
+        const uint32_t *f = reinterpret_cast<const uint32_t *>(frame + (size_t)env * (size_t)frame_stride);
+        for (int w = 0; w < kPixels / 4; ++w) {
+            const uint32_t v = f[w];
+            for (int k = 0; k < 4; ++k) h = fnv1a(h, (v >> (8 * k)) & 0xFFu);
+        }
+    }
+    out[env] = h;
 }
 
 __global__ void k_fill_zero(uint32_t *p, int64_t n) {
@@ -447,6 +483,13 @@ hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const u
 
 hipError_t launch_read_regs(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream) {
     hipLaunchKernelGGL(k_read_regs, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const StateRec *state, int32_t B, const uint8_t *frame, int64_t frame_stride, uint64_t *out,
+                       hipStream_t stream) {
+    hipLaunchKernelGGL(k_hash, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, frame, frame_stride,
+                       out);
     return hipGetLastError();
 }
 

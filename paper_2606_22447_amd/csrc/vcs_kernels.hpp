@@ -20,6 +20,8 @@ hipError_t launch_epilogue(const float *rom_logits, const float *rom_stats, cons
 hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const uint8_t *ram0, uint64_t seed,
                         hipStream_t stream);
 hipError_t launch_read_regs(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream);
+hipError_t launch_hash(const StateRec *state, int32_t B, const uint8_t *frame, int64_t frame_stride, uint64_t *out,
+                       hipStream_t stream);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);
 
 constexpr int kBwdSlots = 16;  // envs per soft-backward workgroup (one wave each)

@@ -149,6 +149,21 @@ class VcsBatch(_Ctx):
                       done=done)
         return graph, ram_out, frame_out, done
 
+    def hash(self, frame: torch.Tensor | None = None, step: int | None = None) -> torch.Tensor:
+        """FNV-1a 64 fingerprint per env of (registers, RAM[, frame]) as int64 [B].
+
+        ``frame`` is a [B, 210, 160] or [B, S, 210, 160] uint8 tensor (then ``step``
+        picks one step's frame)."""
+        fp, stride = None, 0
+        if frame is not None:
+            assert frame.dtype == torch.uint8 and frame.is_contiguous() and frame.shape[0] == self.B
+            stride = frame[0].numel()
+            fp = frame if frame.dim() == 3 else frame[:, step]
+        out = torch.empty(self.B, dtype=torch.int64, device=self.device)
+        rc = Bd.lib().vcs_hash(self.h, Bd.ptr(self.state), Bd.ptr(fp), C.c_int64(stride), Bd.ptr(out), _stream())
+        Bd.check(rc, "vcs_hash")
+        return out
+
     def regs(self) -> torch.Tensor:
         out = torch.empty((self.B, 16), dtype=torch.uint8, device=self.device)
         Bd.check(Bd.lib().vcs_read_regs(self.h, Bd.ptr(self.state), Bd.ptr(out), _stream()), "vcs_read_regs")

@@ -1,128 +1,202 @@
-"""Full-size parity in the benchmark's launch configuration, on outputs the
-oracle can compute one env (or one ROM) at a time."""
+"""Full-size parity in the benchmark's launch configurations.
+
+Protocol: every env step of the full-size hard workloads is fingerprinted on the
+GPU (vcs_hash: FNV-1a 64 of registers, RAM and frame); the oracle runs a sample
+of >= 256 envs (>= 4 per ROM for the heterogeneous workload) and the same
+fingerprints, computed from its outputs with numpy, must match step by step.
+Final states are compared byte for byte for every env (or a 1024-env sample of
+the 16384-env workload), and all steps byte for byte for a few envs.  The soft
+workload's gradients are checked for every env of 8 of its ROMs."""
+import multiprocessing as mp
+import os
+
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2606_22447_amd import inputs as I
+from tests.fnv import fnv1a64
 
 pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 256), (4, 64)]  # the shapes the autotuner picks for the batched workload
 
 
 def say(*a):
     print(*a, flush=True)
 
 
-def run_sampled(w, sample, chunk):
-    """Run the whole workload on the GPU in chunks; keep RAM/frames/done of `sample`."""
+def _pool():
+    return mp.get_context("fork").Pool(max(1, min(16, os.cpu_count() or 1)))
+
+
+# --------------------------------------------------------------------------- oracle workers
+_W = {}
+
+
+def _oracle_env(args):
+    name, b, mode = args
+    w = _W[name]
+    rom = w.roms[int(w.env_rom[b])]
+    ep = None if w.episode_steps is None else w.episode_steps[b]
+    r = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, ep_steps=ep, seed=w.seed,
+                  env_index=b, frames="all" if mode == "steps" else "none", step_state=mode == "steps")
+    if mode == "steps":  # per-step fingerprints of (registers, RAM, frame)
+        msgs = np.concatenate([r["step_state"], r["frames"].reshape(w.steps, -1)], axis=1)
+        return b, fnv1a64(msgs), None
+    regs = np.array([r["regs"][k] for k in O.REG_NAMES[:16]], np.uint8)
+    return b, regs, r["ram"][-1]
+
+
+def oracle_runs(name, w, envs, mode):
+    _W[name] = w
+    with _pool() as pool:
+        return pool.map(_oracle_env, [(name, int(b), mode) for b in envs], chunksize=4)
+
+
+# --------------------------------------------------------------------------- GPU side
+def gpu_step_hashes(w, G, tpb):
+    """Run the whole workload one env step per call; fingerprint every env after every step."""
     import torch
     from paper_2606_22447_amd.vcs import VcsBatch
-    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed)
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel="grouped", lanes_per_env=G,
+                  block_threads=tpb)
     vb.reset(ram0=w.ram0)
     B, S = w.num_envs, w.steps
-    ram_out = torch.empty((B, chunk, 128), dtype=torch.uint8, device="cuda")
-    frame_out = torch.empty((B, chunk, 210, 160), dtype=torch.uint8, device="cuda")
-    done = torch.empty((B, chunk), dtype=torch.uint8, device="cuda")
+    acts = torch.from_numpy(np.ascontiguousarray(w.actions)).cuda()
     eps = None if w.episode_steps is None else torch.from_numpy(w.episode_steps.view(np.int32)).cuda()
-    idx = torch.tensor(sample, device="cuda")
-    rams, frs, dns = [], [], []
-    for s0 in range(0, S, chunk):
-        acts = torch.from_numpy(np.ascontiguousarray(w.actions[:, s0:s0 + chunk])).cuda()
-        vb.step(acts, frames="all", episode_steps=eps, ram_out=ram_out, frame_out=frame_out, done=done)
-        rams.append(ram_out[idx].cpu().numpy())
-        frs.append(frame_out[idx].cpu().numpy())
-        dns.append(done[idx].cpu().numpy())
+    ram_out = torch.empty((B, 1, 128), dtype=torch.uint8, device="cuda")
+    frame = torch.empty((B, 210, 160), dtype=torch.uint8, device="cuda")
+    done = torch.empty((B, 1), dtype=torch.uint8, device="cuda")
+    hashes = torch.empty((S, B), dtype=torch.int64, device="cuda")
+    for s in range(S):
+        vb.step(acts[:, s:s + 1], frames="last", episode_steps=eps, ram_out=ram_out, frame_out=frame, done=done)
+        hashes[s] = vb.hash(frame)
+    regs = vb.regs()
     torch.cuda.synchronize()
-    return np.concatenate(rams, 1), np.concatenate(frs, 1), np.concatenate(dns, 1), vb
+    return hashes.cpu().numpy().view(np.uint64), regs.cpu().numpy(), ram_out[:, 0].cpu().numpy(), vb
 
 
-def check_envs(w, sample, ram, fr, dn):
+def check_workload(w, sample, final_envs, shapes):
+    say(w.name, "oracle: per-step fingerprints of", len(sample), "envs")
+    per_step = {b: (h, r) for b, h, r in oracle_runs(w.name, w, sample, "steps")}
+    say(w.name, "oracle: final states of", len(final_envs), "envs")
+    final = {b: (regs, ram) for b, regs, ram in oracle_runs(w.name, w, final_envs, "final")}
+    for G, tpb in shapes:
+        say(w.name, "gpu", G, tpb)
+        h, regs, ram_last, _ = gpu_step_hashes(w, G, tpb)
+        for b in sample:
+            bad = np.nonzero(h[:, b] != per_step[b][0])[0]
+            assert bad.size == 0, (w.name, G, tpb, "env", b, "first differing step", int(bad[0]))
+        for b in final_envs:
+            assert (regs[b] == final[b][0]).all(), (w.name, G, tpb, "final registers of env", b)
+            assert (ram_last[b] == final[b][1]).all(), (w.name, G, tpb, "final RAM of env", b)
+
+
+def test_batched_hard_full_size_every_step_fingerprinted():
+    w = I.config_c1()  # 4096 envs x 500 env steps, frame-skip 4
+    sample = list(range(0, w.num_envs, 16))  # 256 envs
+    check_workload(w, sample, list(range(w.num_envs)), SHAPES)
+
+
+def test_heterogeneous_full_size_every_step_fingerprinted():
+    w = I.config_c2()  # 16384 envs over 64 ROMs (2K / 4K / F8), in-run episode resets
+    by_rom = [np.nonzero(w.env_rom == r)[0] for r in range(len(w.roms))]
+    sample = sorted(int(e) for envs in by_rom for e in envs[:4])       # 4 per ROM = 256
+    final_envs = sorted(int(e) for envs in by_rom for e in envs[:16])  # 16 per ROM = 1024
+    cum = np.cumsum(w.episode_steps[sample], axis=1)
+    assert (cum[:, 0] < w.steps).sum() >= 64  # many sampled envs cross an episode end
+    check_workload(w, sample, final_envs, [(4, 256)])
+
+
+def test_batched_hard_full_size_bytes_of_sampled_envs():
+    """Every RAM byte, frame byte and done flag of a few envs, in bench.py's call pattern (50 steps/call)."""
+    import torch
+    from paper_2606_22447_amd.vcs import VcsBatch
+    w = I.config_c1()
+    sample = [0, 1, 777, 2048, 4095]
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed)
+    vb.reset(ram0=w.ram0)
+    idx = torch.tensor(sample, device="cuda")
+    rams, frs = [], []
+    for s0 in range(0, w.steps, 50):
+        acts = torch.from_numpy(np.ascontiguousarray(w.actions[:, s0:s0 + 50])).cuda()
+        ram, fr, _ = vb.step(acts, frames="all")
+        rams.append(ram[idx].cpu().numpy())
+        frs.append(fr[idx].cpu().numpy())
+    ram, fr = np.concatenate(rams, 1), np.concatenate(frs, 1)
     for i, b in enumerate(sample):
-        rom = w.roms[int(w.env_rom[b])]
-        ep = None if w.episode_steps is None else w.episode_steps[b]
-        ref = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, ep_steps=ep,
-                        seed=w.seed, env_index=b)
-        assert (ref["done"] == dn[i]).all(), b
+        ref = O.run_env(w.roms[0].image, w.roms[0].mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip)
         assert (ref["ram"] == ram[i]).all(), b
         assert (ref["frames"] == fr[i]).all(), b
 
 
-def test_c1_full_size_sampled_envs():
-    w = I.config_c1()
-    sample = [0, 1, 777, 2048, 4095]
-    say("c1 full: 4096 envs x 500 steps")
-    ram, fr, dn, vb = run_sampled(w, sample, 50)
-    check_envs(w, sample, ram, fr, dn)
+# --------------------------------------------------------------------------- soft
+_S = {}
 
 
-def test_c2_full_size_sampled_envs():
-    w = I.config_c2()
-    # envs on 2K, 4K and F8 ROMs, and envs whose episodes end inside the run
-    mappers = np.array([w.roms[int(r)].mapper for r in w.env_rom])
-    cum = np.cumsum(w.episode_steps, axis=1)
-    resets = (cum[:, 0] < w.steps)
-    sample = []
-    for m in (0, 1, 2):
-        cand = np.nonzero((mappers == m) & resets)[0]
-        sample += [int(cand[0]), int(cand[len(cand) // 2])]
-    say("c2 full: 16384 envs x 500 steps, sample", sample)
-    ram, fr, dn, vb = run_sampled(w, sample, 25)
-    check_envs(w, sample, ram, fr, dn)
-    assert dn.sum() >= len(sample)  # every sampled env crossed an episode end
+def _soft_env(args):
+    r, i = args
+    d = _S["data"]
+    dec_rom, hr0, ev0, ha, es, ei, w = d["dec_rom"][r], d["hr0"], d["ev0"], d["ha"], d["es"], d["ei"], d["w"]
+    b = d["envs"][r][i]
+    mapper = w.roms[r].mapper
+    tgt = O.run_env(d["pert"][r], mapper, hr0[b], ha[b], w.steps, 1, frames="last")["frames"][0]
+    hard = O.run_env(dec_rom[0], mapper, hr0[b], ha[b], w.steps, 1, frames="last")["frames"][0]
+    dl = ((hard.astype(np.int64) >> 1) & 7) - ((tgt.astype(np.int64) >> 1) & 7)
+    gf = ((2.0 * dl / 33600) * 0.5).astype(np.float32)
+    res = O.soft_env(dec_rom[0], dec_rom[1], mapper, hr0[b], ev0[b], ha[b], es[b], ei[b], w.steps, 1, mode="ste",
+                     grad_frame=gf.astype(np.float64))
+    return r, b, gf, res["g_rom"], res["g_ram0"], res["g_swcha"], res["g_inpt4"]
 
 
-def test_c4_full_size_gradients_of_one_rom():
+def test_soft_scale_gradients_of_eight_roms():
     import torch
     from paper_2606_22447_amd.vcs import SoftVcs
-    w = I.config_c4()
+    from tests.test_gpu_soft import assert_grad_close
+    w = I.config_c4()  # 4096 envs over 64 ROMs, 60 frames
     lv = I.soft_leaves(w)
     tau = 1.0
     B, S = w.num_envs, w.steps
     offs = w.rom_offsets()
-    r = 1  # a sampled ROM: every env that runs it enters its gradient
-    envs = np.nonzero(w.env_rom == r)[0]
-    o, n = offs[r], w.roms[r].size
-    dec_rom = O.decode_logits(lv.rom_logits[o:o + n], tau)
-    hard_ram0, ev0 = O.decode_tape(lv.ram_tape[envs].reshape(-1, 256))
-    hard_ram0, ev0 = hard_ram0.reshape(-1, 128), ev0.reshape(-1, 128)
-    ha, es, ei = O.decode_actions(lv.action_logits[envs].reshape(-1, 18), tau)
-    ha, es, ei = ha.reshape(-1, S), es.reshape(-1, S), ei.reshape(-1, S)
+    roms = [0, 9, 21, 30, 42, 51, 60, 63]  # 2K, 4K and F8 images
+    hr0, ev0 = O.decode_tape(lv.ram_tape.reshape(-1, 256))
+    ha, es, ei = O.decode_actions(lv.action_logits.reshape(-1, 18), tau)
+    _S["data"] = {
+        "w": w, "pert": lv.perturbed_roms, "hr0": hr0.reshape(B, 128), "ev0": ev0.reshape(B, 128),
+        "ha": ha.reshape(B, S), "es": es.reshape(B, S), "ei": ei.reshape(B, S),
+        "dec_rom": {r: O.decode_logits(lv.rom_logits[offs[r]:offs[r] + w.roms[r].size], tau) for r in roms},
+        "envs": {r: np.nonzero(w.env_rom == r)[0] for r in roms}}
+    jobs = [(r, i) for r in roms for i in range(len(_S["data"]["envs"][r]))]
+    say("soft oracle:", len(jobs), "envs of ROMs", roms)
+    with _pool() as pool:
+        out = pool.map(_soft_env, jobs, chunksize=2)
     grad_frame = np.zeros((B, 210, 160), np.float32)
-    g_rom = np.zeros(n)
-    g0 = np.zeros((len(envs), 128))
-    gsw, gin = np.zeros((len(envs), S)), np.zeros((len(envs), S))
-    say("c4 oracle: ROM", r, "envs", len(envs))
-    for i, b in enumerate(envs):
-        tgt = O.run_env(lv.perturbed_roms[r], w.roms[r].mapper, hard_ram0[i], ha[i], S, 1, frames="last")["frames"][0]
-        hard = O.run_env(dec_rom[0], w.roms[r].mapper, hard_ram0[i], ha[i], S, 1, frames="last")["frames"][0]
-        d = ((hard.astype(np.int64) >> 1) & 7) - ((tgt.astype(np.int64) >> 1) & 7)
-        grad_frame[b] = (2.0 * d / 33600) * 0.5
-        res = O.soft_env(dec_rom[0], dec_rom[1], w.roms[r].mapper, hard_ram0[i], ev0[i], ha[i], es[i], ei[i], S, 1,
-                         mode="ste", grad_frame=grad_frame[b].astype(np.float64))
-        g_rom += res["g_rom"]
-        g0[i], gsw[i], gin[i] = res["g_ram0"], res["g_swcha"], res["g_inpt4"]
-    ref_rom = O.epilogue_rom(lv.rom_logits[o:o + n], tau, g_rom)
-    ref_tape = O.epilogue_tape(g0.reshape(-1)).reshape(len(envs), 128, 256)
-    ref_act = O.epilogue_action(lv.action_logits[envs].reshape(-1, 18), tau, gsw.reshape(-1),
-                                gin.reshape(-1)).reshape(len(envs), S, 18)
-    say("c4 gpu fwd+bwd at full size")
-    sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=1024)
+    g_rom = {r: np.zeros(w.roms[r].size) for r in roms}
+    g0 = np.zeros((B, 128))
+    gsw, gin = np.zeros((B, S)), np.zeros((B, S))
+    for r, b, gf, gr, g_0, g_s, g_i in out:
+        grad_frame[b] = gf
+        g_rom[r] += gr
+        g0[b], gsw[b], gin[b] = g_0, g_s, g_i
+    say("soft gpu fwd+bwd at full size")
+    sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=1024, lanes_per_env=64)
     L = torch.from_numpy(lv.rom_logits).cuda()
     T = torch.from_numpy(lv.ram_tape).cuda()
-    Aa = torch.from_numpy(lv.action_logits).cuda()
-    _, _, residual, _, _ = sim.forward(L, T, Aa, tau, 6.0)
-    g = sim.backward(residual, L, T, Aa, tau, 6.0, torch.from_numpy(grad_frame).cuda(), check_overflow=True)
+    A = torch.from_numpy(lv.action_logits).cuda()
+    _, _, residual, _, _ = sim.forward(L, T, A, tau, 6.0)
+    g = sim.backward(residual, L, T, A, tau, 6.0, torch.from_numpy(grad_frame).cuda(), check_overflow=True)
     torch.cuda.synchronize()
-    got_rom = g[0][o:o + n].cpu().numpy()
-    got_tape = g[1][torch.from_numpy(envs).cuda()].cpu().numpy()
-    got_act = g[2][torch.from_numpy(envs).cuda()].cpu().numpy()
-    from tests.test_gpu_soft import assert_grad_close
-    assert_grad_close(got_rom, ref_rom, "rom_logits")
-    assert_grad_close(got_tape, ref_tape, "ram_tape")
-    if np.abs(ref_act).max() > 0:
-        assert_grad_close(got_act, ref_act, "action_logits")
-    else:
-        assert (got_act == 0).all()
-    # every other env got a zero frame gradient: their leaves' gradients are exactly zero
-    others = np.nonzero(w.env_rom != r)[0][:64]
-    assert (g[1][torch.from_numpy(others).cuda()] == 0).all().item()
+    got_rom, got_tape, got_act = (x.cpu().numpy() for x in g)
+    for r in roms:
+        o, n = offs[r], w.roms[r].size
+        assert_grad_close(got_rom[o:o + n], O.epilogue_rom(lv.rom_logits[o:o + n], tau, g_rom[r]), f"rom {r}")
+        envs = _S["data"]["envs"][r]
+        assert_grad_close(got_tape[envs], O.epilogue_tape(g0[envs].reshape(-1)).reshape(len(envs), 128, 256),
+                          f"ram_tape of rom {r}")
+        ref_act = O.epilogue_action(lv.action_logits[envs].reshape(-1, 18), tau, gsw[envs].reshape(-1),
+                                    gin[envs].reshape(-1)).reshape(len(envs), S, 18)
+        assert_grad_close(got_act[envs], ref_act, f"action_logits of rom {r}")
+    # every other env got a zero frame gradient: its leaves' gradients are exactly zero
+    others = np.nonzero(~np.isin(w.env_rom, roms))[0][:256]
+    assert (got_tape[others] == 0).all() and (got_act[others] == 0).all()

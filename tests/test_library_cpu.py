@@ -84,3 +84,11 @@ def test_autotune_candidates_are_valid_launch_shapes():
             assert g in (1, 4, 16, 64) and t in (64, 256) and t >= g
             waves = B * g / 64
             assert waves <= 1024 * 8 or (g, t) == (1, 64)
+
+
+def test_fnv1a64_matches_the_published_test_vectors():
+    # FNV-1a 64 reference values published with the algorithm: "" , "a", "foobar"
+    from tests.fnv import fnv1a64
+    assert int(fnv1a64(np.zeros((1, 0), np.uint8))[0]) == 0xCBF29CE484222325
+    assert int(fnv1a64(np.frombuffer(b"a", np.uint8)[None])[0]) == 0xAF63DC4C8601EC8C
+    assert int(fnv1a64(np.frombuffer(b"foobar", np.uint8)[None])[0]) == 0x85944171F73967E8
