@@ -82,6 +82,8 @@ def parse():
     ap.add_argument("--soft-passes", type=int, default=2)
     ap.add_argument("--soft-lanes", type=int, default=0, help="lanes per env of the soft forward (0 = auto)")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time direct vcs_step_hard calls instead of replays of a captured HIP graph")
     return ap.parse_args()
 
 
@@ -124,13 +126,25 @@ def hard_leg(args, kernel, lanes, tpb, w, check=True):
     ncalls = args.warmup + args.steps
     acts = [torch.from_numpy(np.ascontiguousarray(w.actions[:, i * C:(i + 1) * C])).cuda() for i in range(ncalls)]
     eps = None if w.episode_steps is None else torch.from_numpy(w.episode_steps.view(np.int32)).cuda()
-    ram_out = torch.empty((B, C, 128), dtype=torch.uint8, device="cuda")
-    frame_out = torch.empty((B, C, 210, 160), dtype=torch.uint8, device="cuda")
-    done = torch.empty((B, C), dtype=torch.uint8, device="cuda")
     first = {}
+    if getattr(args, "no_graph", False):
+        ram_out = torch.empty((B, C, 128), dtype=torch.uint8, device="cuda")
+        frame_out = torch.empty((B, C, 210, 160), dtype=torch.uint8, device="cuda")
+        done = torch.empty((B, C), dtype=torch.uint8, device="cuda")
+
+        def run(i):
+            vb.step(acts[i], frames="all", episode_steps=eps, ram_out=ram_out, frame_out=frame_out, done=done)
+    else:
+        # one captured call of C env steps, replayed with the next actions copied into its input buffer
+        act_buf = acts[0].clone()
+        graph, ram_out, frame_out, done = vb.capture(act_buf, frames="all", episode_steps=eps)
+
+        def run(i):
+            act_buf.copy_(acts[i])
+            graph.replay()
 
     def call(i):
-        vb.step(acts[i], frames="all", episode_steps=eps, ram_out=ram_out, frame_out=frame_out, done=done)
+        run(i)
         if i == 0 and check:
             torch.cuda.synchronize()
             first["ram"] = ram_out[:2].cpu().numpy()
@@ -152,7 +166,9 @@ def hard_leg(args, kernel, lanes, tpb, w, check=True):
     steps_done = B * C * args.steps
     return {"env_steps_per_s": steps_done / per.sum(), "wall_env_steps_per_s": steps_done / wall,
             "ms_per_call": float(per.mean() * 1e3), "ms_per_call_std": float(per.std() * 1e3),
-            "env_steps": steps_done, "parity_sample": parity, "launch": info}
+            "env_steps": steps_done, "parity_sample": parity, "launch": info,
+            "timing": "HIP events around direct calls" if getattr(args, "no_graph", False)
+            else "HIP events around replays of a captured HIP graph (action refill + replay)"}
 
 
 def soft_leg(args):
@@ -326,6 +342,7 @@ def main():
         line["instructions_per_s"] = h["env_steps_per_s"] * ips
         line["frames_per_s"] = h["env_steps_per_s"] * 4
         line["parity_sample"] = h["parity_sample"]
+        line["timing"] = h["timing"]
         line["ms_per_step_std"] = h["ms_per_call_std"]
     if "plain" in result and h:
         line["plain_kernel"] = {"env_steps_per_s": result["plain"]["env_steps_per_s"],
