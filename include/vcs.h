@@ -65,7 +65,9 @@ typedef enum vcs_mapper { VCS_MAPPER_2K = 0, VCS_MAPPER_4K = 1, VCS_MAPPER_F8 = 
 typedef enum vcs_kernel {
     VCS_KERNEL_AUTO = 0,    /* the tuned kernel (VCS_KERNEL_GROUPED unless told otherwise) */
     VCS_KERNEL_PLAIN = 1,   /* one env per thread, RAM/ROM in global memory, per-lane dispatch */
-    VCS_KERNEL_GROUPED = 2  /* LDS-staged ROM and RAM, wave-uniform grouped dispatch, lane groups */
+    VCS_KERNEL_GROUPED = 2, /* LDS-staged ROM and RAM, wave-uniform grouped dispatch, lane groups */
+    VCS_KERNEL_TRANSLATED = 3 /* GROUPED layout running the ROM images' code translated into
+                                 straight-line HIP at run time (vcs_translate); hard steps only */
 } vcs_kernel;
 
 /* Frame output modes of vcs_step_hard. */
@@ -229,6 +231,47 @@ int32_t vcs_launch_info(const vcs_ctx *ctx, int32_t *kernel, int32_t *lanes_per_
  * out[256] = op class | mode << 6 | base cycles << 10 | page penalty << 13 |
  * length << 14, with op class 0 for the 67 bytes that jam the CPU. */
 int32_t vcs_decode_table(uint32_t *out);
+
+/* Translation of the context's ROM images for VCS_KERNEL_TRANSLATED (the same
+ * machine as the interpreting kernels, bit for bit; Sec. "Hard and Soft
+ * Execution", hard mode).  The code each image executes is found by a short
+ * run of the library's machine core on the host (8 envs x 4 frames, RAM from
+ * the context's seed); its immediate / implied / zero-page / stack / relative
+ * instructions are grouped into basic blocks, at most 256 instruction
+ * positions per context shared over the images by their envs, and emitted as
+ * straight-line HIP with opcodes and operand bytes as compile-time constants;
+ * each block is entered through one wave-wide check (cycle limit, common
+ * page-0 write addresses).  Everything else (other addressing modes, code the
+ * host run did not reach, waves whose envs are at different blocks) runs on
+ * the interpreter, one instruction at a time.  The source is compiled for
+ * gfx950 with hiprtc (cached per process by source text) and, unless flags
+ * has VCS_TRANSLATE_COMPILE_ONLY, loaded as a module on the current device;
+ * vcs_step_hard of this context then launches it (on that device only).
+ *  roms       host uint8 [sum rom_size]: the images, concatenated in ROM order;
+ *             the d_rom of later vcs_step_hard calls must hold the same bytes;
+ *  info       host output (NULL = none);
+ *  log        host buffer for the compiler log (NULL = none), NUL-terminated
+ *             within log_size bytes.
+ * Errors: VCS_UNSUPPORTED if the context's kernel is not TRANSLATED (and from
+ * vcs_step_hard of a TRANSLATED context before a loading vcs_translate on the
+ * current device); VCS_HIP_ERROR if compilation or module loading fails (see
+ * log). */
+enum { VCS_TRANSLATE_COMPILE_ONLY = 1 };
+typedef struct vcs_translate_info {
+    int32_t positions;      /* instruction positions translated over all images */
+    int32_t runs;           /* basic blocks (straight-line runs) they form */
+    int32_t truncated;      /* 1 if an image executed more positions than its share of the budget */
+    int32_t cached;         /* 1 if the code object came from this process's cache */
+    double compile_seconds; /* hiprtc time (0 when cached) */
+    size_t source_bytes, code_bytes;
+} vcs_translate_info;
+int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t flags, vcs_translate_info *info, char *log,
+                      size_t log_size);
+
+/* The HIP source vcs_translate compiles for these images (host only): copies
+ * at most buf_size - 1 bytes and a NUL into buf (NULL = none) and sets *len to
+ * the full length. */
+int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, char *buf, size_t buf_size, size_t *len);
 
 #ifdef __cplusplus
 }

@@ -13,7 +13,8 @@ LIB_PATH = os.path.join(HERE, "libvcs.so")
 
 VCS_OK = 0
 VCS_MAPPER_2K, VCS_MAPPER_4K, VCS_MAPPER_F8 = 0, 1, 2
-VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED = 0, 1, 2
+VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED, VCS_KERNEL_TRANSLATED = 0, 1, 2, 3
+VCS_TRANSLATE_COMPILE_ONLY = 1
 VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
 VCS_OP_HARD, VCS_OP_SOFT_FWD, VCS_OP_SOFT_BWD = 0, 1, 2
 ABI_VERSION = 1
@@ -23,8 +24,16 @@ EXPORTED = [
     "vcs_create", "vcs_destroy", "vcs_status_string", "vcs_state_bytes", "vcs_rom_bytes",
     "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
     "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
-    "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash",
+    "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash", "vcs_translate",
+    "vcs_translated_source",
 ]
+
+
+class VcsTranslateInfo(C.Structure):
+    _fields_ = [
+        ("positions", C.c_int32), ("runs", C.c_int32), ("truncated", C.c_int32), ("cached", C.c_int32),
+        ("compile_seconds", C.c_double), ("source_bytes", C.c_size_t), ("code_bytes", C.c_size_t),
+    ]
 
 
 class VcsConfig(C.Structure):
@@ -73,6 +82,8 @@ def lib():
         L.vcs_bwd_overflow.argtypes = [vp, vp, i32, vp, C.POINTER(i32)]
         L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5
         L.vcs_decode_table.argtypes = [C.POINTER(C.c_uint32)]
+        L.vcs_translate.argtypes = [vp, vp, i32, C.POINTER(VcsTranslateInfo), C.c_char_p, sz]
+        L.vcs_translated_source.argtypes = [vp, vp, C.c_char_p, sz, C.POINTER(sz)]
         for f in EXPORTED:
             fn = getattr(L, f)
             if f not in ("vcs_destroy", "vcs_status_string"):
@@ -126,3 +137,26 @@ def launch_info(h):
     vals = [C.c_int32() for _ in range(5)]
     check(lib().vcs_launch_info(h, *[C.byref(v) for v in vals]), "vcs_launch_info")
     return dict(zip(["kernel", "lanes_per_env", "block_threads", "blocks", "bwd_blocks"], [v.value for v in vals]))
+
+
+def translate(h, roms: "np.ndarray", compile_only: bool = False) -> dict:
+    """vcs_translate on the host image bytes (uint8, concatenated); returns its info."""
+    import numpy as np
+    roms = np.ascontiguousarray(roms, np.uint8)
+    info = VcsTranslateInfo()
+    log = C.create_string_buffer(1 << 16)
+    rc = lib().vcs_translate(h, roms.ctypes.data, VCS_TRANSLATE_COMPILE_ONLY if compile_only else 0,
+                             C.byref(info), log, len(log))
+    if rc != VCS_OK:
+        raise VcsError(f"vcs_translate: {lib().vcs_status_string(rc).decode()}\n{log.value.decode(errors='replace')}")
+    return {k: getattr(info, k) for k, _ in VcsTranslateInfo._fields_}
+
+
+def translated_source(h, roms: "np.ndarray") -> str:
+    import numpy as np
+    roms = np.ascontiguousarray(roms, np.uint8)
+    n = C.c_size_t(0)
+    check(lib().vcs_translated_source(h, roms.ctypes.data, None, 0, C.byref(n)), "vcs_translated_source")
+    buf = C.create_string_buffer(n.value + 1)
+    check(lib().vcs_translated_source(h, roms.ctypes.data, buf, len(buf), C.byref(n)), "vcs_translated_source")
+    return buf.value.decode()

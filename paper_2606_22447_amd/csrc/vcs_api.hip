@@ -7,6 +7,7 @@
 
 #include "../../include/vcs.h"
 #include "vcs_core.hpp"
+#include "vcs_jit.hpp"
 #include "vcs_kernels.hpp"
 
 using namespace vcs;
@@ -31,8 +32,13 @@ struct vcs_ctx {
     std::vector<uint8_t> image;  // host image of the static device region
     uint8_t *pinned = nullptr;   // pinned copy, made on the first upload
     size_t blob_bytes = 0;
+    // translated kernel (VCS_KERNEL_TRANSLATED), loaded on one device
+    hipModule_t tr_module = nullptr;
+    hipFunction_t tr_fn = nullptr;
+    int tr_device = -1;
     ~vcs_ctx() {
         if (pinned) (void)hipHostFree(pinned);
+        if (tr_module) (void)hipModuleUnload(tr_module);
     }
 };
 
@@ -218,7 +224,7 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
     }
     // kernel family and lane grouping
     c->kernel = cfg->kernel == VCS_KERNEL_AUTO ? VCS_KERNEL_GROUPED : cfg->kernel;
-    if (c->kernel != VCS_KERNEL_PLAIN && c->kernel != VCS_KERNEL_GROUPED) {
+    if (c->kernel != VCS_KERNEL_PLAIN && c->kernel != VCS_KERNEL_GROUPED && c->kernel != VCS_KERNEL_TRANSLATED) {
         delete c;
         return VCS_INVALID_ARG;
     }
@@ -389,8 +395,73 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
     P.ep_steps = d_episode_steps;
     P.num_episodes = d_episode_steps ? num_episodes : 0;
     P.seed = ctx->seed;
+    if (ctx->kernel == VCS_KERNEL_TRANSLATED) {
+        int dev = -1;
+        if (!ctx->tr_fn || hipGetDevice(&dev) != hipSuccess || dev != ctx->tr_device) return VCS_UNSUPPORTED;
+        void *args[] = {&P};
+        const size_t lds = (size_t)ctx->max_rom * sizeof(uint2);
+        return hip_status(hipModuleLaunchKernel(ctx->tr_fn, (unsigned)ctx->main_blocks, 1, 1, (unsigned)ctx->tpb, 1,
+                                                1, (unsigned)lds, stream, args, nullptr));
+    }
     return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
                                   ctx->max_rom, stream));
+}
+
+int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, char *buf, size_t buf_size, size_t *len) {
+    if (!ctx || !roms || !len) return VCS_INVALID_ARG;
+    TranslateStats st;
+    const std::string src = translated_source(roms, ctx->rom_off, ctx->rom_size, ctx->rom_mapper, ctx->env_rom, ctx->seed,
+                                              kTranslateBudget, ctx->G, ctx->tpb, st);
+    *len = src.size();
+    if (buf && buf_size) {
+        const size_t n = std::min(buf_size - 1, src.size());
+        std::memcpy(buf, src.data(), n);
+        buf[n] = '\0';
+    }
+    return VCS_OK;
+}
+
+int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t flags, vcs_translate_info *info, char *log,
+                      size_t log_size) {
+    if (!ctx || !roms || (flags & ~VCS_TRANSLATE_COMPILE_ONLY)) return VCS_INVALID_ARG;
+    if (ctx->kernel != VCS_KERNEL_TRANSLATED) return VCS_UNSUPPORTED;
+    if (log && log_size) log[0] = '\0';
+    TranslateStats st;
+    const std::string src = translated_source(roms, ctx->rom_off, ctx->rom_size, ctx->rom_mapper, ctx->env_rom, ctx->seed,
+                                              kTranslateBudget, ctx->G, ctx->tpb, st);
+    std::string code, clog;
+    double secs = 0.0;
+    bool cached = false;
+    int32_t rc = jit_compile(src, code, clog, secs, cached);
+    if (log && log_size) {
+        const size_t n = std::min(log_size - 1, clog.size());
+        std::memcpy(log, clog.data(), n);
+        log[n] = '\0';
+    }
+    if (info) {
+        info->positions = st.positions;
+        info->runs = st.runs;
+        info->truncated = st.truncated;
+        info->cached = cached ? 1 : 0;
+        info->compile_seconds = secs;
+        info->source_bytes = src.size();
+        info->code_bytes = code.size();
+    }
+    if (rc != VCS_OK || (flags & VCS_TRANSLATE_COMPILE_ONLY)) return rc;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return VCS_HIP_ERROR;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    if (hipModuleLoadData(&mod, code.data()) != hipSuccess) return VCS_HIP_ERROR;
+    if (hipModuleGetFunction(&fn, mod, "vcs_tr_step") != hipSuccess) {
+        (void)hipModuleUnload(mod);
+        return VCS_HIP_ERROR;
+    }
+    if (ctx->tr_module) (void)hipModuleUnload(ctx->tr_module);
+    ctx->tr_module = mod;
+    ctx->tr_fn = fn;
+    ctx->tr_device = dev;
+    return VCS_OK;
 }
 
 int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,

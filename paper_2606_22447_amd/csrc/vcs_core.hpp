@@ -543,13 +543,14 @@ struct Cpu {
 
     // End of an instruction that started at cycle t0 and took n cycles: the cycle
     // counter, the hook, and the WSYNC stall of an instruction that wrote memory.
+    // (wr is the same in every lane; the stall itself is a select, so no lane branches)
     __host__ __device__ __forceinline__ void finish(uint32_t opc, ExecInfo &info, int32_t t0, int32_t n, bool wr) {
         cyc = t0 + n;
         hook.after_exec(*this, opc, t0, cyc, info);
-        if (wr && wsync) {
-            wsync = 0;
+        if (wr) {
             const int32_t q = cyc % kCyclesPerLine;
-            if (q) cyc += kCyclesPerLine - q;
+            cyc = (wsync && q) ? cyc + (kCyclesPerLine - q) : cyc;
+            wsync = 0;
         }
     }
 

@@ -1,0 +1,65 @@
+// Device side shared by the precompiled kernels of libvcs and the kernels it
+// generates at run time for translated ROM images: the wave policy of the
+// per-env bodies, the decode table in constant memory and the body of the
+// grouped step kernel.
+#pragma once
+
+#include "vcs_paths.hpp"
+
+namespace vcs {
+
+__constant__ DecodeTable kDecodeDev = make_decode_table();
+
+// ---------------------------------------------------------------------------
+// Wave policy of the device bodies
+// ---------------------------------------------------------------------------
+typedef const __attribute__((address_space(4))) uint32_t ConstU32;
+
+struct DeviceWave {
+    __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
+    __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
+    // *p += t without waiting for the result (a no-return atomic add).  Only one lane
+    // adds to a given p, so the additions happen in program order.
+    __device__ static __forceinline__ void accumulate(float *p, float t) {
+        (void)__hip_atomic_fetch_add(p, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+    // makes v opaque to the optimiser (no instruction): code that uses it cannot be
+    // hoisted out of the loop that contains this call
+    __device__ static __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
+    // the same for a wave-uniform value (kept in a scalar register)
+    __device__ static __forceinline__ void opaque_uniform(uint32_t &v) { asm volatile("" : "+s"(v)); }
+    // entry u (wave-uniform) of a read-only table in constant memory: a scalar
+    // load, so that what is derived from it stays in scalar registers and the
+    // branches on it are scalar branches
+    // (u goes through an empty asm so that the compiler cannot substitute an
+    // equal per-lane value for it and turn the load into a vector load).
+    __device__ static __forceinline__ uint32_t table(const uint32_t *t, uint32_t u) {
+        asm volatile("" : "+s"(u));
+        return __builtin_amdgcn_readfirstlane(((ConstU32 *)t)[u]);
+    }
+};
+
+// Body of the grouped step kernel: one workgroup per ROM group of E = TPB / G
+// envs, G lanes per env; the ROM image (pre-decoded words), the decode table and
+// the envs' RAM staged in LDS.  state_of(rom) gives the executor state of the
+// workgroup's ROM.
+template <int G, int TPB, bool kSoft, class X, class StateOf>
+__device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds, uint32_t *dec_lds,
+                                           StateOf state_of) {
+    constexpr int E = TPB / G;
+    const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
+    const int32_t blk = blockIdx.x;
+    const int32_t rom_idx = P.st.main_block_rom[blk];
+    const int32_t env = P.st.main_slot_env[blk * E + slot];
+    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
+    const int32_t mapper = P.st.rom_mapper[rom_idx];
+    for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
+        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
+    for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
+    __syncthreads();
+    LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
+    step_env<DeviceWave, G, kSoft, false, X>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
+}
+
+}  // namespace vcs

@@ -1,7 +1,11 @@
 // Internal layouts shared by the HIP kernels and the C-ABI host code of libvcs.
 #pragma once
 
+// (run-time compilation of translated ROM code supplies the HIP device
+// definitions itself and has no hip_runtime.h)
+#ifndef __HIPCC_RTC__
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace vcs {

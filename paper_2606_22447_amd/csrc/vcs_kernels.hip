@@ -15,42 +15,10 @@
 //  k_decode_*  STE leaves: argmax bytes and softmax statistics (Eq. select).
 //  k_*_grad    epilogue: fixed-order reduction of per-env ROM partials and the
 //              softmax vector-Jacobian products.
+#include "vcs_device.hpp"
 #include "vcs_kernels.hpp"
-#include "vcs_paths.hpp"
 
 namespace vcs {
-
-__constant__ DecodeTable kDecodeDev = make_decode_table();
-
-// ---------------------------------------------------------------------------
-// Wave policy of the device bodies
-// ---------------------------------------------------------------------------
-typedef const __attribute__((address_space(4))) uint32_t ConstU32;
-
-struct DeviceWave {
-    __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
-    __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
-    // *p += t without waiting for the result (a no-return atomic add).  Only one lane
-    // adds to a given p, so the additions happen in program order.
-    __device__ static __forceinline__ void accumulate(float *p, float t) {
-        (void)__hip_atomic_fetch_add(p, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-    // makes v opaque to the optimiser (no instruction): code that uses it cannot be
-    // hoisted out of the loop that contains this call
-    __device__ static __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
-    // the same for a wave-uniform value (kept in a scalar register)
-    __device__ static __forceinline__ void opaque_uniform(uint32_t &v) { asm volatile("" : "+s"(v)); }
-    // entry u (wave-uniform) of a read-only table in constant memory: a scalar
-    // load, so that what is derived from it stays in scalar registers and the
-    // branches on it are scalar branches
-    // (u goes through an empty asm so that the compiler cannot substitute an
-    // equal per-lane value for it and turn the load into a vector load).
-    __device__ static __forceinline__ uint32_t table(const uint32_t *t, uint32_t u) {
-        asm volatile("" : "+s"(u));
-        return __builtin_amdgcn_readfirstlane(((ConstU32 *)t)[u]);
-    }
-};
 
 // ---------------------------------------------------------------------------
 // Step kernel (hard steps, soft forward): one workgroup per ROM group, G lanes
@@ -62,22 +30,15 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
     __shared__ __align__(16) uint32_t ram_lds[kPlain ? 4 : 32 * E];
     __shared__ uint32_t dec_lds[kPlain ? 1 : 256];
-    const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
-    const int32_t blk = blockIdx.x;
-    const int32_t rom_idx = P.st.main_block_rom[blk];
-    const int32_t env = P.st.main_slot_env[blk * E + slot];
-    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
-    const int32_t mapper = P.st.rom_mapper[rom_idx];
     if constexpr (kPlain) {
-        GlobalMem m{P.rom + rom_base, env >= 0 ? P.state[env].ram : nullptr};
-        step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
+        const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
+        const int32_t blk = blockIdx.x;
+        const int32_t rom_idx = P.st.main_block_rom[blk];
+        const int32_t env = P.st.main_slot_env[blk * E + slot];
+        GlobalMem m{P.rom + P.st.rom_off[rom_idx], env >= 0 ? P.state[env].ram : nullptr};
+        step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, P.st.rom_mapper[rom_idx], m, kDecodeDev.e);
     } else {
-        for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
-            rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
-        for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
-        __syncthreads();
-        LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
-        step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, mapper, m, kDecodeDev.e);
+        step_group<G, TPB, kSoft, InterpExec>(P, rom_lds, ram_lds, dec_lds, [](int32_t) { return InterpExec::State{}; });
     }
 }
 

@@ -122,9 +122,19 @@ struct GlobalMem {
 // ---------------------------------------------------------------------------
 // Hooks
 // ---------------------------------------------------------------------------
-// Renders the returned frame lazily: before every pixel-register write the
-// pixels up to the write's effect clock are drawn with the old state.
+// Pixels of [from, to) drawn out of line (not inlined, so that the caller's
+// control flow holds no per-lane branch); returns the new rendered-up-to clock.
 template <typename T>
+__host__ __device__ __attribute__((noinline)) int32_t render_call(T *frame, int32_t from, int32_t to, uint32_t col,
+                                                                  uint32_t pf, uint32_t vb, int32_t ystart,
+                                                                  uint32_t sub, uint32_t G);
+
+// Renders the returned frame lazily: before every pixel-register write the
+// pixels up to the write's effect clock are drawn with the old state.  With a
+// wave policy W (translated code) the drawing is a call taken when any lane
+// of the wave has pixels to draw.
+struct NoWave {};
+template <typename T, class W = NoWave>
 struct RenderHook {
     static constexpr bool kRecord = false;
     T *frame;         // frame being rendered, or nullptr
@@ -134,12 +144,18 @@ struct RenderHook {
     uint32_t sub, G;
     template <class C>
     __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
-        if (frame) {
-            const int32_t cc = 3 * (w + 1);
-            if (cc > rend_cc) {
-                render_span(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
-                rend_cc = cc;
+        if constexpr (std::is_same<W, NoWave>::value) {
+            if (frame) {
+                const int32_t cc = 3 * (w + 1);
+                if (cc > rend_cc) {
+                    render_span(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
+                    rend_cc = cc;
+                }
             }
+        } else {
+            const int32_t cc = 3 * (w + 1);
+            if (W::any(frame != nullptr && cc > rend_cc))
+                rend_cc = render_call(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
         }
     }
     template <class C>
@@ -153,6 +169,15 @@ struct RenderHook {
         if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
     }
 };
+
+template <typename T>
+__host__ __device__ __attribute__((noinline)) int32_t render_call(T *frame, int32_t from, int32_t to, uint32_t col,
+                                                                  uint32_t pf, uint32_t vb, int32_t ystart,
+                                                                  uint32_t sub, uint32_t G) {
+    if (!frame || to <= from) return from;
+    render_span(frame, from, to, col, pf, vb, ystart, sub, G);
+    return to;
+}
 
 // Records the recompute tape of the soft backward.  Pixels of the final frame
 // are attributed to the instruction during whose span [previous write point,
@@ -277,6 +302,91 @@ __host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_
     }
 }
 
+// One page-0 form instruction whose opcode OP is known at compile time
+// (translated code), run by lanes that agree on its write address (the
+// translated code checks that before it, for the forms whose address is per
+// lane): the phases of exec_dispatch's case for OP with the write taken on the
+// wave-uniform address, so that the code has no per-lane branch.
+template <class W, uint32_t OP, class C>
+__host__ __device__ __forceinline__ void exec_static(C &c, uint32_t lo, uint32_t hi) {
+    constexpr uint32_t D = decode_op(OP);
+    static_assert(D != 0 && fast_form(OP), "a page-0 form");
+    ExecInfo info;
+    int32_t t0 = 0, n = 0;
+    uint32_t ea = 0, r = 0;
+    const bool wr = c.template exec_body<true>(OP, D, lo, hi, info, t0, n, ea, r);
+    if (wr) {
+        const uint32_t u8 = W::first(ea);
+        if (u8 & 0x80u) c.mem.ram_set(u8 & 0x7Fu, r);
+        else c.tia_out(u8 & 0x3Fu, r, t0 + n - 1);
+    }
+    c.finish(OP, info, t0, n, wr);
+}
+
+// One interpreted instruction at each running lane's pc: fetch, decode and a
+// dispatch that is wave-uniform when the lanes share the opcode, else a
+// waterfall over the distinct opcodes of the wave.
+template <class W, bool kPlain, class C>
+__host__ __device__ __forceinline__ void interp_one(C &c, const uint32_t *decode) {
+    uint32_t opc, lo, hi;
+    ExecInfo info;
+    if constexpr (kPlain) {
+        fetch3(c, opc, lo, hi);
+        const uint32_t d = decode[opc];
+        if (d == 0) c.jam = 1;
+        else c.exec(opc, d, lo, hi, info);
+    } else {
+        uint32_t dec;
+        fetch_word<W>(c, opc, lo, hi, dec);
+        const uint32_t u = W::first(opc);
+        const uint32_t d = W::first(dec);
+        if (W::all(opc == u)) {
+            // the usual case: every running lane has the same opcode
+            if (d == 0) c.jam = 1;
+            else exec_dispatch<W>(c, u, d, lo, hi, info);
+        } else {
+            // waterfall: each pass executes one distinct opcode of the
+            // wave with a wave-uniform (scalar) decode.  The operands and
+            // registers are made opaque per pass so that no case's
+            // arithmetic is hoisted out of the loop and run for all cases.
+            for (;;) {
+                W::opaque(lo);
+                W::opaque(hi);
+                W::opaque(c.x);
+                W::opaque(c.y);
+                W::opaque(c.a);
+                W::opaque(c.s);
+                const uint32_t u2 = W::first(opc);
+                const uint32_t d2 = W::first(dec);
+                if (opc == u2) {
+                    if (d2 == 0) c.jam = 1;
+                    else c.exec(u2, d2, lo, hi, info);
+                    break;
+                }
+            }
+        }
+    }
+}
+
+// Executors of the instruction loop of a frame.  The interpreter runs
+// interp_one until the lane reaches its cycle limit or jams; translated code
+// (generated per ROM image, see the translator) keeps the position of the
+// next instruction in its state and runs straight-line code from there.
+struct InterpExec {
+    template <typename T, class W>
+    using Hook = RenderHook<T>;
+    struct State {};
+    template <class C>
+    __host__ __device__ __forceinline__ static void init(C &, State &) {}
+    template <class W, bool kPlain, class C>
+    __host__ __device__ __forceinline__ static void run(C &c, State &, bool go, int32_t lim, const uint32_t *decode) {
+        while (go) {
+            interp_one<W, kPlain>(c, decode);
+            go = !c.jam && c.cyc < lim;
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------
 // Per-env bodies of the kernels.  W is the wave policy: any(v) / all(v) (is v
 // true in any / every active lane of the wave), first(v) (v of the first active
@@ -286,15 +396,16 @@ __host__ __device__ __forceinline__ void exec_dispatch(C &c, uint32_t u, uint32_
 // empty asm statements, and the ROM image must already be staged in LDS by the
 // whole workgroup.
 // ---------------------------------------------------------------------------
-template <class W, int G, bool kSoft, bool kPlain, class Mem>
+template <class W, int G, bool kSoft, bool kPlain, class X = InterpExec, class Mem>
 __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
-                                                  Mem mem, const uint32_t *decode) {
+                                                  Mem mem, const uint32_t *decode,
+                                                  typename X::State xs = typename X::State{}) {
     static_assert(!(kSoft && kPlain), "the soft forward uses the grouped kernel");
     using T = typename std::conditional<kSoft, float, uint8_t>::type;
     const bool live = env >= 0;
     const int32_t S = P.steps, F = P.frame_skip;
 
-    Cpu<Mem, RenderHook<T>> c;
+    Cpu<Mem, typename X::template Hook<T, W>> c;
     c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
     c.f8 = mapper == 2 ? 1u : 0u;
     c.mem = mem;
@@ -327,6 +438,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
             }
         }
     }
+    X::init(c, xs);
 
     int32_t s_idx = 0, fstep = 0;
     bool active = live && S > 0;
@@ -398,48 +510,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     }
                 }
             }
-            bool go = run && c.cyc < lim;
-            while (go) {
-                uint32_t opc, lo, hi;
-                ExecInfo info;
-                if constexpr (kPlain) {
-                    fetch3(c, opc, lo, hi);
-                    const uint32_t d = decode[opc];
-                    if (d == 0) c.jam = 1;
-                    else c.exec(opc, d, lo, hi, info);
-                } else {
-                    uint32_t dec;
-                    fetch_word<W>(c, opc, lo, hi, dec);
-                    const uint32_t u = W::first(opc);
-                    const uint32_t d = W::first(dec);
-                    if (W::all(opc == u)) {
-                        // the usual case: every running lane has the same opcode
-                        if (d == 0) c.jam = 1;
-                        else exec_dispatch<W>(c, u, d, lo, hi, info);
-                    } else {
-                        // waterfall: each pass executes one distinct opcode of the
-                        // wave with a wave-uniform (scalar) decode.  The operands and
-                        // registers are made opaque per pass so that no case's
-                        // arithmetic is hoisted out of the loop and run for all cases.
-                        for (;;) {
-                            W::opaque(lo);
-                            W::opaque(hi);
-                            W::opaque(c.x);
-                            W::opaque(c.y);
-                            W::opaque(c.a);
-                            W::opaque(c.s);
-                            const uint32_t u2 = W::first(opc);
-                            const uint32_t d2 = W::first(dec);
-                            if (opc == u2) {
-                                if (d2 == 0) c.jam = 1;
-                                else c.exec(u2, d2, lo, hi, info);
-                                break;
-                            }
-                        }
-                    }
-                }
-                go = !c.jam && c.cyc < lim;
-            }
+            const bool go = run && c.cyc < lim;
+            X::template run<W, kPlain>(c, xs, go, lim, decode);
             run = active && !c.jam && c.cyc < kCyclesPerFrame;
             if constexpr (!kSoft) break;
             if (!W::any(run)) break;
@@ -482,6 +554,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     c.mem.ram_word_set(2 * w + 1, (uint32_t)(v >> 32));
                 }
                 c.power_on();
+                X::init(c, xs);
                 frame = 0;
                 ep_step = 0;
             }

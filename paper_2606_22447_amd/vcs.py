@@ -14,7 +14,8 @@ import torch
 from . import binding as Bd
 
 _FRAMES = {"none": Bd.VCS_FRAMES_NONE, "last": Bd.VCS_FRAMES_LAST, "all": Bd.VCS_FRAMES_ALL}
-_KERNELS = {"auto": Bd.VCS_KERNEL_AUTO, "plain": Bd.VCS_KERNEL_PLAIN, "grouped": Bd.VCS_KERNEL_GROUPED}
+_KERNELS = {"auto": Bd.VCS_KERNEL_AUTO, "plain": Bd.VCS_KERNEL_PLAIN, "grouped": Bd.VCS_KERNEL_GROUPED,
+            "translated": Bd.VCS_KERNEL_TRANSLATED}
 
 
 def _stream():
@@ -46,8 +47,13 @@ class _Ctx:
                            _KERNELS[kernel] if isinstance(kernel, str) else int(kernel), lanes_per_env,
                            block_threads)
         self.device = torch.device(device)
-        self.rom = torch.from_numpy(np.concatenate(imgs)).to(self.device)
+        host_rom = np.concatenate(imgs)
+        self.rom = torch.from_numpy(host_rom).to(self.device)
         self._ws = {}
+        self.translation = None
+        if (_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)) == Bd.VCS_KERNEL_TRANSLATED:
+            with torch.cuda.device(self.device):
+                self.translation = Bd.translate(self.h, host_rom)
 
     def __del__(self):
         h = getattr(self, "h", None)
