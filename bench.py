@@ -28,8 +28,9 @@ OPS_PER_INSTRUCTION = 12                       # algorithmic integer ops of one 
 OPS_PER_PIXEL = 1                              # one store per returned pixel
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c1_hbm_traffic.md")
-KERNEL_SOURCES = ["vcs_core.hpp", "vcs_paths.hpp", "vcs_internal.hpp", "vcs_kernels.hpp", "vcs_kernels.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vcs_tr_step_c1_hbm_traffic.md")
+KERNEL_SOURCES = ["vcs_core.hpp", "vcs_paths.hpp", "vcs_internal.hpp", "vcs_kernels.hpp", "vcs_kernels.hip",
+                  "vcs_device.hpp", "vcs_jit.hpp", "vcs_jit.cpp"]
 
 
 def log(*a):
@@ -49,7 +50,7 @@ def kernel_digest() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per k_step launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
+    """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None
     when the kernel has changed since those counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
@@ -73,10 +74,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2, help="untimed calls")
     ap.add_argument("--chunk", type=int, default=50, help="env steps per call")
     ap.add_argument("--envs", type=int, default=4096)
-    ap.add_argument("--kernel", default="grouped")
+    ap.add_argument("--kernel", default="translated", help="step kernel of the hard leg: translated, grouped, plain")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--tpb", type=int, default=0)
-    ap.add_argument("--legs", default="hard,plain,hetero,soft,cpu",
+    ap.add_argument("--legs", default="hard,grouped,plain,hetero,soft,cpu",
                     help="comma list of: hard, plain, hetero, soft, cpu")
     ap.add_argument("--soft-k", default="256,1024,4096")
     ap.add_argument("--soft-passes", type=int, default=2)
@@ -166,7 +167,7 @@ def hard_leg(args, kernel, lanes, tpb, w, check=True):
     steps_done = B * C * args.steps
     return {"env_steps_per_s": steps_done / per.sum(), "wall_env_steps_per_s": steps_done / wall,
             "ms_per_call": float(per.mean() * 1e3), "ms_per_call_std": float(per.std() * 1e3),
-            "env_steps": steps_done, "parity_sample": parity, "launch": info,
+            "env_steps": steps_done, "parity_sample": parity, "launch": info, "translation": vb.translation,
             "timing": "HIP events around direct calls" if getattr(args, "no_graph", False)
             else "HIP events around replays of a captured HIP graph (action refill + replay)"}
 
@@ -279,15 +280,20 @@ def main():
     tuned = {}
     if "hard" in legs:
         lanes, tpb = args.lanes, args.tpb
-        if lanes == 0 and args.kernel == "grouped":  # autotune the launch shape on this workload
+        if lanes == 0 and args.kernel in ("grouped", "translated"):  # autotune the launch shape on this workload
             from paper_2606_22447_amd import autotune
             t = autotune.tune_hard(w1.roms, w1.env_rom, frame_skip=w1.frame_skip, seed=w1.seed, ram0=w1.ram0,
-                                   actions=w1.actions, trial_steps=2)
+                                   actions=w1.actions, trial_steps=2, kernel=args.kernel)
             lanes, tpb = t["lanes_per_env"], t["block_threads"]
             tuned["hard"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"])) for r in t["table"]]
             log("hard autotune", tuned["hard"])
         result["hard"] = hard_leg(args, args.kernel, lanes, tpb, w1)
         log("hard", result["hard"])
+    if "grouped" in legs:  # the interpreting kernel on the same workload
+        ga = argparse.Namespace(**vars(args))
+        ga.steps, ga.warmup = max(1, min(args.steps, 3)), 1
+        result["grouped"] = hard_leg(ga, "grouped", 16, 256, w1, check=False)
+        log("grouped", result["grouped"])
     if "plain" in legs:
         pa = argparse.Namespace(**vars(args))
         pa.steps, pa.warmup = max(1, min(args.steps, 3)), 1
@@ -298,11 +304,13 @@ def main():
         ha.chunk, ha.steps, ha.warmup = 25, 4, 1
         w2 = I.config_c2(steps=25 * 5)
         from paper_2606_22447_amd import autotune
+        # the interpreting kernel: these ROMs read the joystick, so envs of a wave diverge and the
+        # translated code (which needs every lane of a wave at one block) mostly falls back to it
         t = autotune.tune_hard(w2.roms, w2.env_rom, frame_skip=w2.frame_skip, seed=w2.seed, ram0=w2.ram0,
                                actions=w2.actions, trial_steps=2)
         tuned["hetero"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"])) for r in t["table"]]
         log("hetero autotune", tuned["hetero"])
-        result["hetero"] = hard_leg(ha, args.kernel, t["lanes_per_env"], t["block_threads"], w2)
+        result["hetero"] = hard_leg(ha, "grouped", t["lanes_per_env"], t["block_threads"], w2)
         result["hetero"]["workload"] = ("c2_hetero_persistent: 64 ROMs (21x2K, 22x4K, 21xF8, reading SWCHA/INPT4/"
                                         "INTIM) x 256 envs = 16384 envs, frame-skip 4, geometric episodes "
                                         "(mean 1500 frames) with in-run resets")
@@ -338,7 +346,8 @@ def main():
                             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                             "algorithmic_bytes_per_launch": args.envs * args.chunk * (33600 + 128 + 1 + 1),
                             "ops_per_env_step": ops_per_step, "instructions_per_env_step": ips,
-                            "kernel": "k_step (grouped)"}
+                            "kernel": {"translated": "vcs_tr_step (translated)", "grouped": "k_step (grouped)",
+                                       "plain": "k_step (plain)"}[args.kernel]}
         line["instructions_per_s"] = h["env_steps_per_s"] * ips
         line["frames_per_s"] = h["env_steps_per_s"] * 4
         line["parity_sample"] = h["parity_sample"]
@@ -346,7 +355,12 @@ def main():
         line["ms_per_step_std"] = h["ms_per_call_std"]
     if "plain" in result and h:
         line["plain_kernel"] = {"env_steps_per_s": result["plain"]["env_steps_per_s"],
-                                "speedup_of_grouped": h["env_steps_per_s"] / result["plain"]["env_steps_per_s"]}
+                                "speedup_of_hard_leg": h["env_steps_per_s"] / result["plain"]["env_steps_per_s"]}
+    if "grouped" in result and h:
+        line["grouped_kernel"] = {"env_steps_per_s": result["grouped"]["env_steps_per_s"],
+                                  "speedup_of_hard_leg": h["env_steps_per_s"] / result["grouped"]["env_steps_per_s"]}
+    if h and h.get("translation"):
+        line["translation"] = h["translation"]
     if "hetero" in result:
         line["hetero"] = {k: result["hetero"][k] for k in ("env_steps_per_s", "ms_per_call", "parity_sample",
                                                            "workload", "launch")}

@@ -237,8 +237,8 @@ int32_t vcs_decode_table(uint32_t *out);
  * Execution", hard mode).  The code each image executes is found by a short
  * run of the library's machine core on the host (8 envs x 4 frames, RAM from
  * the context's seed); its immediate / implied / zero-page / stack / relative
- * instructions are grouped into basic blocks, at most 256 instruction
- * positions per context shared over the images by their envs, and emitted as
+ * instructions are grouped into basic blocks, at most max_positions
+ * instruction positions per context shared over the images by their envs, and emitted as
  * straight-line HIP with opcodes and operand bytes as compile-time constants;
  * each block is entered through one wave-wide check (cycle limit, common
  * page-0 write addresses).  Everything else (other addressing modes, code the
@@ -249,6 +249,8 @@ int32_t vcs_decode_table(uint32_t *out);
  * vcs_step_hard of this context then launches it (on that device only).
  *  roms       host uint8 [sum rom_size]: the images, concatenated in ROM order;
  *             the d_rom of later vcs_step_hard calls must hold the same bytes;
+ *  max_positions  instruction positions translated for the context (0 = 256),
+ *             1..65536; compile time grows with it;
  *  info       host output (NULL = none);
  *  log        host buffer for the compiler log (NULL = none), NUL-terminated
  *             within log_size bytes.
@@ -265,13 +267,15 @@ typedef struct vcs_translate_info {
     double compile_seconds; /* hiprtc time (0 when cached) */
     size_t source_bytes, code_bytes;
 } vcs_translate_info;
-int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t flags, vcs_translate_info *info, char *log,
-                      size_t log_size);
+int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, int32_t flags,
+                      vcs_translate_info *info, char *log, size_t log_size);
 
-/* The HIP source vcs_translate compiles for these images (host only): copies
+/* The HIP source vcs_translate compiles for these images and max_positions
+ * (host only): copies
  * at most buf_size - 1 bytes and a NUL into buf (NULL = none) and sets *len to
  * the full length. */
-int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, char *buf, size_t buf_size, size_t *len);
+int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, char *buf,
+                              size_t buf_size, size_t *len);
 
 #ifdef __cplusplus
 }

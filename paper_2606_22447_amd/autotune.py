@@ -56,8 +56,14 @@ def _time(fn, reps: int) -> float:
     return a.elapsed_time(b) / 1e3 / reps
 
 
+def translated_candidates(num_envs: int):
+    """Launch shapes tried for the TRANSLATED kernel (each one is a compilation):
+    lane groups of 4 and 16, the shapes that keep one or a few waves per SIMD."""
+    return [(g, t) for g, t in hard_candidates(num_envs) if g in (4, 16)] or [(1, 64)]
+
+
 def tune_hard(roms, env_rom, frame_skip: int = 4, seed: int = 0, ram0=None, actions=None, trial_steps: int = 2,
-              reps: int = 2, candidates=None, verbose: bool = False) -> dict:
+              reps: int = 2, candidates=None, verbose: bool = False, kernel: str = "grouped") -> dict:
     """Time `trial_steps` env steps of the given workload for each launch shape.
 
     Returns {"lanes_per_env", "block_threads", "env_steps_per_s", "table"}; the
@@ -67,13 +73,13 @@ def tune_hard(roms, env_rom, frame_skip: int = 4, seed: int = 0, ram0=None, acti
     from .vcs import VcsBatch
     env_rom = np.asarray(env_rom, np.int32)
     B = env_rom.size
-    cands = candidates or hard_candidates(B)
+    cands = candidates or (translated_candidates(B) if kernel == "translated" else hard_candidates(B))
     act = None
     if actions is not None:
         act = torch.as_tensor(np.ascontiguousarray(np.asarray(actions)[:, :trial_steps]), dtype=torch.uint8).cuda()
     table = []
     for g, t in cands:
-        vb = VcsBatch(roms, env_rom, frame_skip=frame_skip, seed=seed, kernel="grouped", lanes_per_env=g,
+        vb = VcsBatch(roms, env_rom, frame_skip=frame_skip, seed=seed, kernel=kernel, lanes_per_env=g,
                       block_threads=t)
         vb.reset(ram0=ram0)
         sec = _time(lambda: vb.step(actions=act, steps=None if act is not None else trial_steps, frames="last"),

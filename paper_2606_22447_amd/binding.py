@@ -82,8 +82,8 @@ def lib():
         L.vcs_bwd_overflow.argtypes = [vp, vp, i32, vp, C.POINTER(i32)]
         L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5
         L.vcs_decode_table.argtypes = [C.POINTER(C.c_uint32)]
-        L.vcs_translate.argtypes = [vp, vp, i32, C.POINTER(VcsTranslateInfo), C.c_char_p, sz]
-        L.vcs_translated_source.argtypes = [vp, vp, C.c_char_p, sz, C.POINTER(sz)]
+        L.vcs_translate.argtypes = [vp, vp, i32, i32, C.POINTER(VcsTranslateInfo), C.c_char_p, sz]
+        L.vcs_translated_source.argtypes = [vp, vp, i32, C.c_char_p, sz, C.POINTER(sz)]
         for f in EXPORTED:
             fn = getattr(L, f)
             if f not in ("vcs_destroy", "vcs_status_string"):
@@ -139,24 +139,26 @@ def launch_info(h):
     return dict(zip(["kernel", "lanes_per_env", "block_threads", "blocks", "bwd_blocks"], [v.value for v in vals]))
 
 
-def translate(h, roms: "np.ndarray", compile_only: bool = False) -> dict:
+def translate(h, roms: "np.ndarray", compile_only: bool = False, max_positions: int = 0) -> dict:
     """vcs_translate on the host image bytes (uint8, concatenated); returns its info."""
     import numpy as np
     roms = np.ascontiguousarray(roms, np.uint8)
     info = VcsTranslateInfo()
     log = C.create_string_buffer(1 << 16)
-    rc = lib().vcs_translate(h, roms.ctypes.data, VCS_TRANSLATE_COMPILE_ONLY if compile_only else 0,
+    rc = lib().vcs_translate(h, roms.ctypes.data, int(max_positions), VCS_TRANSLATE_COMPILE_ONLY if compile_only else 0,
                              C.byref(info), log, len(log))
     if rc != VCS_OK:
         raise VcsError(f"vcs_translate: {lib().vcs_status_string(rc).decode()}\n{log.value.decode(errors='replace')}")
     return {k: getattr(info, k) for k, _ in VcsTranslateInfo._fields_}
 
 
-def translated_source(h, roms: "np.ndarray") -> str:
+def translated_source(h, roms: "np.ndarray", max_positions: int = 0) -> str:
     import numpy as np
     roms = np.ascontiguousarray(roms, np.uint8)
     n = C.c_size_t(0)
-    check(lib().vcs_translated_source(h, roms.ctypes.data, None, 0, C.byref(n)), "vcs_translated_source")
+    check(lib().vcs_translated_source(h, roms.ctypes.data, int(max_positions), None, 0, C.byref(n)),
+          "vcs_translated_source")
     buf = C.create_string_buffer(n.value + 1)
-    check(lib().vcs_translated_source(h, roms.ctypes.data, buf, len(buf), C.byref(n)), "vcs_translated_source")
+    check(lib().vcs_translated_source(h, roms.ctypes.data, int(max_positions), buf, len(buf), C.byref(n)),
+          "vcs_translated_source")
     return buf.value.decode()

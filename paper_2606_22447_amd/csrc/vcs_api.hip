@@ -407,11 +407,12 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
                                   ctx->max_rom, stream));
 }
 
-int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, char *buf, size_t buf_size, size_t *len) {
-    if (!ctx || !roms || !len) return VCS_INVALID_ARG;
+int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, char *buf,
+                              size_t buf_size, size_t *len) {
+    if (!ctx || !roms || !len || max_positions < 0 || max_positions > 65536) return VCS_INVALID_ARG;
     TranslateStats st;
     const std::string src = translated_source(roms, ctx->rom_off, ctx->rom_size, ctx->rom_mapper, ctx->env_rom, ctx->seed,
-                                              kTranslateBudget, ctx->G, ctx->tpb, st);
+                                              max_positions ? max_positions : kTranslateBudget, ctx->G, ctx->tpb, st);
     *len = src.size();
     if (buf && buf_size) {
         const size_t n = std::min(buf_size - 1, src.size());
@@ -421,14 +422,16 @@ int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, char *buf
     return VCS_OK;
 }
 
-int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t flags, vcs_translate_info *info, char *log,
-                      size_t log_size) {
+int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, int32_t flags,
+                      vcs_translate_info *info, char *log, size_t log_size) {
     if (!ctx || !roms || (flags & ~VCS_TRANSLATE_COMPILE_ONLY)) return VCS_INVALID_ARG;
+    if (max_positions < 0 || max_positions > 65536) return VCS_INVALID_ARG;
+    const int budget = max_positions ? max_positions : kTranslateBudget;
     if (ctx->kernel != VCS_KERNEL_TRANSLATED) return VCS_UNSUPPORTED;
     if (log && log_size) log[0] = '\0';
     TranslateStats st;
     const std::string src = translated_source(roms, ctx->rom_off, ctx->rom_size, ctx->rom_mapper, ctx->env_rom, ctx->seed,
-                                              kTranslateBudget, ctx->G, ctx->tpb, st);
+                                              budget, ctx->G, ctx->tpb, st);
     std::string code, clog;
     double secs = 0.0;
     bool cached = false;

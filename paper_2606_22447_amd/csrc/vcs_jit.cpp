@@ -300,12 +300,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "template <class W, class C>\n"
-                  "VCS_TR_FN void loop%d(C &c, uint32_t &blk, bool go, int32_t lim, "
-                  "const uint32_t *decode) {\n"
-                  "  uint32_t fb = 0u;\n"
-                  "  while (go) {\n"
-                  "    const uint32_t u = W::first(blk);\n"
-                  "    if (fb == 0u && u != 0u && W::all(blk == u)) {\n"
+                  "VCS_TR_FN void blocks%d(C &c, uint32_t u, uint32_t &blk, uint32_t &fb, int32_t lim) {\n"
                   "      switch (u) {\n",
                   r);
     s += buf;
@@ -378,17 +373,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
         }
         s += buf;
     }
-    std::snprintf(buf, sizeof buf,
-                  "      default: fb = 1u; break;\n"
-                  "      }\n"
-                  "    } else {\n"
-                  "      interp_one<W, false>(c, decode);\n"
-                  "      blk = lookup%d(c.bank, c.pc);\n"
-                  "      fb = 0u;\n"
-                  "    }\n"
-                  "    go = !c.jam && c.cyc < lim;\n  }\n}\n",
-                  r);
-    s += buf;
+    s += "      default: fb = 1u; break;\n      }\n}\n";
     stats.positions += (int32_t)rc.pos.size();
     stats.runs += (int32_t)runs.size();
     if (rc.truncated) stats.truncated = 1;
@@ -424,24 +409,41 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
         const RomCode rc = select_positions(im, prof[(size_t)r], share);
         emit_rom(s, im, r, rc, stats);
     }
-    s += "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
-         "  struct State { uint32_t rom, blk; };\n"
-         "  template <class C> VCS_TR_FN static void init(C &c, State &s) {\n"
-         "    switch (s.rom) {\n";
+    // one instruction loop for all images: a wave runs its image's blocks when
+    // its lanes agree on the block and the entry check holds, else the
+    // interpreter for one instruction (one copy of it, shared by the images)
     char buf[1024];
+    s += "VCS_TR_FN uint32_t lookup(uint32_t rom, uint32_t bank, uint32_t pc) {\n  switch (rom) {\n";
     for (int r = 0; r < R; ++r) {
-        std::snprintf(buf, sizeof buf, "      case %d: s.blk = lookup%d(c.bank, c.pc); break;\n", r, r);
+        std::snprintf(buf, sizeof buf, "    case %d: return lookup%d(bank, pc);\n", r, r);
         s += buf;
     }
-    s += "      default: s.blk = 0u; break;\n    }\n  }\n"
+    s += "    default: return 0u;\n  }\n}\n"
+         "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
+         "  struct State { uint32_t rom, blk; };\n"
+         "  template <class C> VCS_TR_FN static void init(C &c, State &s) { s.blk = lookup(s.rom, c.bank, c.pc); }\n"
          "  template <class W, bool kPlain, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
-         "    switch (s.rom) {\n";
+         "    uint32_t fb = 0u;\n"
+         "    while (go) {\n"
+         "      const uint32_t u = W::first(s.blk);\n"
+         "      if (fb == 0u && u != 0u && W::all(s.blk == u)) {\n"
+         "        switch (s.rom) {\n";
     for (int r = 0; r < R; ++r) {
-        std::snprintf(buf, sizeof buf, "      case %d: loop%d<W>(c, s.blk, go, lim, decode); break;\n", r, r);
+        std::snprintf(buf, sizeof buf, "          case %d: blocks%d<W>(c, u, s.blk, fb, lim); break;\n", r, r);
         s += buf;
     }
-    s += "      default: break;\n    }\n  }\n};\n}  // namespace tr\n}  // namespace vcs\n#ifndef VCS_TR_NO_KERNEL\n";
+    s += "          default: fb = 1u; break;\n"
+         "        }\n"
+         "      } else {\n"
+         "        interp_one<W, false>(c, decode);\n"
+         "        s.blk = lookup(s.rom, c.bank, c.pc);\n"
+         "        fb = 0u;\n"
+         "      }\n"
+         "      go = !c.jam && c.cyc < lim;\n"
+         "    }\n"
+         "  }\n";
+    s += "};\n}  // namespace tr\n}  // namespace vcs\n#ifndef VCS_TR_NO_KERNEL\n";
     std::snprintf(buf, sizeof buf,
                   "extern \"C\" __global__ __launch_bounds__(%d) void vcs_tr_step(vcs::StepParams P) {\n"
                   "  extern __shared__ __align__(16) uint2 rom_lds[];\n"

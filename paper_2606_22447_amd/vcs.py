@@ -37,7 +37,7 @@ def _rom_arrays(roms):
 
 class _Ctx:
     def __init__(self, roms, env_rom, frame_skip, ystart, seed, ckpt_interval, kernel, lanes_per_env,
-                 block_threads, device):
+                 block_threads, device, max_positions=0):
         imgs, maps = _rom_arrays(roms)
         self.env_rom = np.asarray(env_rom, np.int32)
         self.B = int(self.env_rom.size)
@@ -53,7 +53,7 @@ class _Ctx:
         self.translation = None
         if (_KERNELS[kernel] if isinstance(kernel, str) else int(kernel)) == Bd.VCS_KERNEL_TRANSLATED:
             with torch.cuda.device(self.device):
-                self.translation = Bd.translate(self.h, host_rom)
+                self.translation = Bd.translate(self.h, host_rom, max_positions=max_positions)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -78,9 +78,13 @@ class VcsBatch(_Ctx):
     """B independent consoles in HARD mode (bit-exact machine)."""
 
     def __init__(self, roms, env_rom, frame_skip: int = 4, ystart: int = 34, seed: int = 0,
-                 kernel="auto", lanes_per_env: int = 0, block_threads: int = 0, device="cuda"):
+                 kernel="auto", lanes_per_env: int = 0, block_threads: int = 0, device="cuda",
+                 max_positions: int = 0):
+        """kernel: "auto" / "grouped" (interpreter), "plain", or "translated" (the images'
+        code translated to HIP at construction; max_positions bounds the translation,
+        0 = the library default)."""
         super().__init__(roms, env_rom, frame_skip, ystart, seed, 0, kernel, lanes_per_env, block_threads,
-                         device)
+                         device, max_positions)
         n = Bd.size_query("vcs_state_bytes", self.h)
         self.state = torch.zeros(n, dtype=torch.uint8, device=self.device)
 

@@ -19,7 +19,8 @@ from tests.fnv import fnv1a64
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(16, 256), (4, 64)]  # the shapes the autotuner picks for the batched workload
+# (kernel, lanes per env, threads per workgroup): the shapes the autotuner picks for the batched workload
+SHAPES = [("translated", 16, 256), ("grouped", 16, 256), ("grouped", 4, 64)]
 
 
 def say(*a):
@@ -55,11 +56,11 @@ def oracle_runs(name, w, envs, mode):
 
 
 # --------------------------------------------------------------------------- GPU side
-def gpu_step_hashes(w, G, tpb):
+def gpu_step_hashes(w, kernel, G, tpb):
     """Run the whole workload one env step per call; fingerprint every env after every step."""
     import torch
     from paper_2606_22447_amd.vcs import VcsBatch
-    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel="grouped", lanes_per_env=G,
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel, lanes_per_env=G,
                   block_threads=tpb)
     vb.reset(ram0=w.ram0)
     B, S = w.num_envs, w.steps
@@ -82,15 +83,15 @@ def check_workload(w, sample, final_envs, shapes):
     per_step = {b: (h, r) for b, h, r in oracle_runs(w.name, w, sample, "steps")}
     say(w.name, "oracle: final states of", len(final_envs), "envs")
     final = {b: (regs, ram) for b, regs, ram in oracle_runs(w.name, w, final_envs, "final")}
-    for G, tpb in shapes:
-        say(w.name, "gpu", G, tpb)
-        h, regs, ram_last, _ = gpu_step_hashes(w, G, tpb)
+    for kernel, G, tpb in shapes:
+        say(w.name, "gpu", kernel, G, tpb)
+        h, regs, ram_last, _ = gpu_step_hashes(w, kernel, G, tpb)
         for b in sample:
             bad = np.nonzero(h[:, b] != per_step[b][0])[0]
-            assert bad.size == 0, (w.name, G, tpb, "env", b, "first differing step", int(bad[0]))
+            assert bad.size == 0, (w.name, kernel, G, tpb, "env", b, "first differing step", int(bad[0]))
         for b in final_envs:
-            assert (regs[b] == final[b][0]).all(), (w.name, G, tpb, "final registers of env", b)
-            assert (ram_last[b] == final[b][1]).all(), (w.name, G, tpb, "final RAM of env", b)
+            assert (regs[b] == final[b][0]).all(), (w.name, kernel, G, tpb, "final registers of env", b)
+            assert (ram_last[b] == final[b][1]).all(), (w.name, kernel, G, tpb, "final RAM of env", b)
 
 
 def test_batched_hard_full_size_every_step_fingerprinted():
@@ -106,16 +107,18 @@ def test_heterogeneous_full_size_every_step_fingerprinted():
     final_envs = sorted(int(e) for envs in by_rom for e in envs[:16])  # 16 per ROM = 1024
     cum = np.cumsum(w.episode_steps[sample], axis=1)
     assert (cum[:, 0] < w.steps).sum() >= 64  # many sampled envs cross an episode end
-    check_workload(w, sample, final_envs, [(4, 256)])
+    check_workload(w, sample, final_envs, [("grouped", 4, 256), ("translated", 4, 256)])
 
 
-def test_batched_hard_full_size_bytes_of_sampled_envs():
+@pytest.mark.parametrize("kernel", ["translated", "grouped"])
+def test_batched_hard_full_size_bytes_of_sampled_envs(kernel):
     """Every RAM byte, frame byte and done flag of a few envs, in bench.py's call pattern (50 steps/call)."""
     import torch
     from paper_2606_22447_amd.vcs import VcsBatch
     w = I.config_c1()
     sample = [0, 1, 777, 2048, 4095]
-    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed)
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel, lanes_per_env=16,
+                  block_threads=256)
     vb.reset(ram0=w.ram0)
     idx = torch.tensor(sample, device="cuda")
     rams, frs = [], []

@@ -11,13 +11,14 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_graph_replays_match_eager_steps():
+@pytest.mark.parametrize("kernel", ["grouped", "translated"])
+def test_graph_replays_match_eager_steps(kernel):
     import torch
     from paper_2606_22447_amd.vcs import VcsBatch
     w = I.config_c1(num_envs=64, steps=12)
     chunk = 3
-    eager = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed)
-    graphed = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed)
+    eager = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel)
+    graphed = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel)
     eager.reset(ram0=w.ram0)
     graphed.reset(ram0=w.ram0)
     act = torch.empty((w.num_envs, chunk), dtype=torch.uint8, device="cuda")

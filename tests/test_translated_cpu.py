@@ -35,7 +35,7 @@ def test_translated_source_is_basic_blocks_of_page0_forms():
     src = Bd.translated_source(h, np.concatenate([r.image for r in w.roms]))
     import re
     assert "vcs_tr_step" in src and "exec_static" in src
-    loop = src[src.index("void loop0("):src.index("struct Exec")]
+    loop = src[src.index("void blocks0("):src.index("struct Exec")]
     cases = re.findall(r"^      case \d+: (.*)$", loop, re.M)
     assert 10 < len(cases) < 100  # runs, each one case
     assert src.count("exec_static<W, 0x") > 100  # positions
