@@ -90,7 +90,8 @@ typedef struct vcs_config {
     int32_t ckpt_interval;      /* soft backward: hard-state checkpoint every K cycles (>= 64) */
     int32_t kernel;             /* vcs_kernel */
     int32_t lanes_per_env;      /* GROUPED kernel: lanes cooperating on one env (1, 4, 16 or 64; 0 = auto) */
-    int32_t block_threads;      /* GROUPED kernel: threads per workgroup (64 or 256; 0 = auto) */
+    int32_t block_threads;      /* GROUPED kernel: threads per workgroup (64 or 256; 0 = auto);
+                                   TRANSLATED: block_threads / lanes_per_env <= 64 */
 } vcs_config;
 
 typedef struct vcs_ctx vcs_ctx;

@@ -254,6 +254,12 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         delete c;
         return VCS_UNSUPPORTED;
     }
+    // translated code keeps a pixel-write log per env in LDS: at most 64 envs per workgroup
+    // (with the largest ROM image staged beside it)
+    if (c->kernel == VCS_KERNEL_TRANSLATED && c->tpb / c->G > 64) {
+        delete c;
+        return VCS_UNSUPPORTED;
+    }
     c->main_E = c->tpb / c->G;
     group_by_rom(c, c->main_E, c->main_block_rom, c->main_slot_env);
     c->main_blocks = (int32_t)c->main_block_rom.size();

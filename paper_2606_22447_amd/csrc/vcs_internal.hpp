@@ -20,6 +20,10 @@ constexpr int kScreenW = 160;
 constexpr int kScreenH = 210;
 constexpr int kPixels = kScreenW * kScreenH;  // 33600
 constexpr uint32_t kMagic = 0x31534356u;      // "VCS1"
+// Longest straight-line run of translated code, in instructions; also the
+// length of an env's pixel-write log there (a run writes at most one pixel
+// register per instruction).
+constexpr int kTrMaxRun = 32;
 
 // One env's machine state in device memory (opaque to callers, 256 bytes).
 // Cycle counters are relative to the start of the current frame so that they

@@ -49,6 +49,7 @@ struct RomCode {
     std::vector<Pos> pos;                // index = id - 1
     std::map<uint32_t, uint32_t> id_of;  // key bank << 16 | pc
     std::set<uint32_t> leaders;          // keys of positions entered other than by falling through
+    std::vector<uint64_t> count;         // executions per position in the profile (index = id - 1)
     int banks = 1;
     bool truncated = false;
 };
@@ -209,6 +210,7 @@ RomCode select_positions(const Image &im, const Profile &pr, int budget) {
         p.hi = im.byte(p.bank, (p.pc + 2u) & 0xFFFFu);
         p.d = decode_op(p.op);
         rc.pos.push_back(p);
+        rc.count.push_back(o.first);
         rc.id_of[key(p.bank, p.pc)] = (uint32_t)rc.pos.size();
     }
     return rc;
@@ -224,9 +226,10 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
     // Straight-line runs (basic blocks of the translated positions), each with
     // one entry, its first position.  A run ends at a branch, jump, return or
     // jam, before a position that is entered other than by falling through (a
-    // leader), after a write that may hit WSYNC (its stall is not bounded),
-    // after TXS, before an indexed page-0 write, and at kMaxRun positions.
-    constexpr size_t kMaxRun = 32;
+    // leader), after TXS, before an indexed page-0 write, and at kMaxRun
+    // positions.  A write that may hit WSYNC counts a line (76 cycles) in the
+    // run's cycle bound.
+    constexpr size_t kMaxRun = (size_t)kTrMaxRun;
     auto write_kind = [](const Pos &p) -> int {  // 0 none, 1 constant address, 2 per-lane address, 3 push
         const uint32_t cls = p.d & 63u, mode = (p.d >> 6) & 15u;
         if (cls == C_PHA || cls == C_PHP) return 3;
@@ -255,7 +258,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
             const Pos &p = rc.pos[i];
             uint32_t t;
             if (flow_of(p, im.mapper, t) != kNext) break;
-            if ((p.d & 63u) == C_TXS || (write_kind(p) == 1 && may_stall(p)) || run.size() >= kMaxRun) break;
+            if ((p.d & 63u) == C_TXS || run.size() >= kMaxRun) break;
             const uint32_t nx = id(p.bank, p.pc + ((p.d >> 14) & 3u));
             if (!nx || done[nx - 1] || write_kind(rc.pos[nx - 1]) == 2) break;
             if (rc.leaders.count(key(rc.pos[nx - 1].bank, rc.pos[nx - 1].pc))) break;
@@ -300,8 +303,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
     s += buf;
     std::snprintf(buf, sizeof buf,
                   "template <class W, class C>\n"
-                  "VCS_TR_FN void blocks%d(C &c, uint32_t u, uint32_t &blk, uint32_t &fb, int32_t lim) {\n"
-                  "      switch (u) {\n",
+                  "VCS_TR_FN void blocks%d(C &c, uint32_t u, uint32_t &blk, uint32_t &fb, int32_t lim) {\n",
                   r);
     s += buf;
     // Each run: the entry check, made once by every lane of the wave (the
@@ -310,13 +312,16 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
     // agrees and stays in RAM, an indexed page-0 write, which must start its
     // run, has one address), then the body with no exit until its end.  A
     // failed check sends the wave to the interpreter for one instruction.
+    std::vector<std::pair<uint64_t, std::string>> run_code;  // (entries in the profile, code after the case label)
     for (std::vector<uint32_t> run : runs) {
+        std::string code;
+        const uint64_t entries = rc.count[run[0]];
         const Pos &last = rc.pos[run.back()];
         uint32_t t;
         const Flow f = flow_of(last, im.mapper, t);
         if (f == kJam && run.size() == 1) {
-            std::snprintf(buf, sizeof buf, "      case %u: c.jam = 1; break;\n", run[0] + 1);
-            s += buf;
+            std::snprintf(buf, sizeof buf, "%u|c.jam = 1; break;\n", run[0] + 1);
+            run_code.push_back({0, buf});
             continue;
         }
         if (f == kJam) run.pop_back();  // the jam is then reached through the dispatch
@@ -348,14 +353,13 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
                           p0.lo, ix, p0.lo, ix);
             cond += buf;
         }
-        std::snprintf(buf, sizeof buf, "      case %u: if (!W::all(%s)) { fb = 1u; break; }\n", run[0] + 1,
-                      cond.c_str());
-        s += buf;
+        std::snprintf(buf, sizeof buf, "%u|if (!W::all(%s)) { fb = 1u; break; }\n", run[0] + 1, cond.c_str());
+        code += buf;
         for (uint32_t i : run) {
             const Pos &p = rc.pos[i];
             std::snprintf(buf, sizeof buf, "        c.pc = 0x%04Xu; exec_static<W, 0x%02Xu>(c, 0x%02Xu, 0x%02Xu);\n",
                           p.pc, p.op, p.lo, p.hi);
-            s += buf;
+            code += buf;
         }
         const Pos &e = rc.pos[run.back()];
         const Flow fe = flow_of(e, im.mapper, t);
@@ -371,9 +375,37 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
         } else {
             std::snprintf(buf, sizeof buf, "        blk = %uu; break;\n", sid(e.bank, e.pc + ((e.d >> 14) & 3u)));
         }
-        s += buf;
+        code += buf;
+        run_code.push_back({entries, code});
     }
-    s += "      default: fb = 1u; break;\n      }\n}\n";
+    // The most entered runs are tested first, one compare each, ahead of the
+    // switch's compare tree (each wrapped so that `break` leaves it).
+    constexpr size_t kHotRuns = 4;
+    std::vector<size_t> rank(run_code.size());
+    for (size_t i = 0; i < rank.size(); ++i) rank[i] = i;
+    std::stable_sort(rank.begin(), rank.end(), [&](size_t x, size_t y) { return run_code[x].first > run_code[y].first; });
+    std::vector<char> hot(run_code.size(), 0);
+    for (size_t k = 0; k < rank.size() && k < kHotRuns; ++k) hot[rank[k]] = 1;
+    auto split = [](const std::string &c, std::string &rest) {
+        const size_t bar = c.find('|');
+        rest = c.substr(bar + 1);
+        return c.substr(0, bar);
+    };
+    for (size_t k = 0; k < rank.size() && k < kHotRuns; ++k) {
+        std::string rest;
+        const std::string idtxt = split(run_code[rank[k]].second, rest);
+        s += k ? "      else if (u == " : "      if (u == ";
+        s += idtxt + "u) do {\n        " + rest + "      } while (0);\n";
+    }
+    s += rank.empty() ? "      {\n" : "      else {\n";
+    s += "      switch (u) {\n";
+    for (size_t i = 0; i < run_code.size(); ++i) {
+        if (hot[i]) continue;
+        std::string rest;
+        const std::string idtxt = split(run_code[i].second, rest);
+        s += "      case " + idtxt + ": " + rest;
+    }
+    s += "      default: fb = 1u; break;\n      }\n      }\n}\n";
     stats.positions += (int32_t)rc.pos.size();
     stats.runs += (int32_t)runs.size();
     if (rc.truncated) stats.truncated = 1;
@@ -420,14 +452,19 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     }
     s += "    default: return 0u;\n  }\n}\n"
          "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
-         "  struct State { uint32_t rom, blk; };\n"
-         "  template <class C> VCS_TR_FN static void init(C &c, State &s) { s.blk = lookup(s.rom, c.bank, c.pc); }\n"
+         "  struct State { uint32_t rom, blk; uint4 *log; };\n"
+         "  template <class C> VCS_TR_FN static void init(C &c, State &s) {\n"
+         "    s.blk = lookup(s.rom, c.bank, c.pc);\n"
+         "    c.hook.log = s.log;\n"
+         "    c.hook.nlog = 0u;\n"
+         "  }\n"
          "  template <class W, bool kPlain, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
          "    uint32_t fb = 0u;\n"
          "    while (go) {\n"
-         "      const uint32_t u = W::first(s.blk);\n"
-         "      if (fb == 0u && u != 0u && W::all(s.blk == u)) {\n"
+         "      for (;;) {  // every lane at one block: translated runs back to back, no per-lane loop control\n"
+         "        const uint32_t u = W::first(s.blk);\n"
+         "        if (fb != 0u || u == 0u || !W::all(s.blk == u)) break;\n"
          "        switch (s.rom) {\n";
     for (int r = 0; r < R; ++r) {
         std::snprintf(buf, sizeof buf, "          case %d: blocks%d<W>(c, u, s.blk, fb, lim); break;\n", r, r);
@@ -435,12 +472,17 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     }
     s += "          default: fb = 1u; break;\n"
          "        }\n"
-         "      } else {\n"
-         "        interp_one<W, false>(c, decode);\n"
-         "        s.blk = lookup(s.rom, c.bank, c.pc);\n"
-         "        fb = 0u;\n"
+         "        c.hook.flush(c);\n"
+         "        if (!W::all(!c.jam && c.cyc < lim)) break;\n"
          "      }\n"
          "      go = !c.jam && c.cyc < lim;\n"
+         "      if (go) {  // lanes at different blocks, a failed entry check, or untranslated code\n"
+         "        interp_one<W, false>(c, decode);\n"
+         "        s.blk = lookup(s.rom, c.bank, c.pc);\n"
+         "        c.hook.flush(c);\n"
+         "        go = !c.jam && c.cyc < lim;\n"
+         "      }\n"
+         "      fb = 0u;\n"
          "    }\n"
          "  }\n";
     s += "};\n}  // namespace tr\n}  // namespace vcs\n#ifndef VCS_TR_NO_KERNEL\n";
@@ -449,9 +491,11 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
                   "  extern __shared__ __align__(16) uint2 rom_lds[];\n"
                   "  __shared__ __align__(16) uint32_t ram_lds[32 * %d];\n"
                   "  __shared__ uint32_t dec_lds[256];\n"
+                  "  __shared__ uint4 log_lds[%d * vcs::kTrMaxRun];\n"
+                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::kTrMaxRun;\n"
                   "  vcs::step_group<%d, %d, false, vcs::tr::Exec>(P, rom_lds, ram_lds, dec_lds,\n"
-                  "      [](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u}; });\n}\n",
-                  TPB, TPB / G, G, TPB);
+                  "      [log](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log}; });\n}\n",
+                  TPB, TPB / G, TPB / G, G, G, TPB);
     s += buf;
     s += "#endif\n";
     return s;

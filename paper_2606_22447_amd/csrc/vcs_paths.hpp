@@ -122,17 +122,12 @@ struct GlobalMem {
 // ---------------------------------------------------------------------------
 // Hooks
 // ---------------------------------------------------------------------------
-// Pixels of [from, to) drawn out of line (not inlined, so that the caller's
-// control flow holds no per-lane branch); returns the new rendered-up-to clock.
-template <typename T>
-__host__ __device__ __attribute__((noinline)) int32_t render_call(T *frame, int32_t from, int32_t to, uint32_t col,
-                                                                  uint32_t pf, uint32_t vb, int32_t ystart,
-                                                                  uint32_t sub, uint32_t G);
-
 // Renders the returned frame lazily: before every pixel-register write the
 // pixels up to the write's effect clock are drawn with the old state.  With a
-// wave policy W (translated code) the drawing is a call taken when any lane
-// of the wave has pixels to draw.
+// wave policy W (translated code) a write only appends (effect clock, colour
+// registers, playfield, VBLANK: the state before it) to the env's log in LDS,
+// a store with no branch, and flush(), called between runs where lanes may
+// branch, draws the logged spans.
 struct NoWave {};
 template <typename T, class W = NoWave>
 struct RenderHook {
@@ -142,6 +137,8 @@ struct RenderHook {
     int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
     int32_t ystart;
     uint32_t sub, G;
+    uint4 *log;       // (with W) the env's pixel-write log, kTrMaxRun entries
+    uint32_t nlog;
     template <class C>
     __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
         if constexpr (std::is_same<W, NoWave>::value) {
@@ -153,9 +150,29 @@ struct RenderHook {
                 }
             }
         } else {
-            const int32_t cc = 3 * (w + 1);
-            if (W::any(frame != nullptr && cc > rend_cc))
-                rend_cc = render_call(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
+            const uint32_t i = nlog < (uint32_t)kTrMaxRun ? nlog : (uint32_t)kTrMaxRun - 1u;
+            log[i] = make_uint4((uint32_t)(3 * (w + 1)), c.col, c.pf, c.vb);
+            ++nlog;
+        }
+    }
+    // Draw the logged spans (translated code; a no-op otherwise).  A run
+    // writes at most kTrMaxRun pixel registers, and the log is drawn after
+    // every run.
+    template <class C>
+    __host__ __device__ __forceinline__ void flush(C &) {
+        if constexpr (!std::is_same<W, NoWave>::value) {
+            if (frame) {
+                const uint32_t n = nlog < (uint32_t)kTrMaxRun ? nlog : (uint32_t)kTrMaxRun;
+                for (uint32_t i = 0; i < n; ++i) {
+                    const uint4 e = log[i];
+                    const int32_t cc = (int32_t)e.x;
+                    if (cc > rend_cc) {
+                        render_span(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
+                        rend_cc = cc;
+                    }
+                }
+            }
+            nlog = 0;
         }
     }
     template <class C>
@@ -166,18 +183,10 @@ struct RenderHook {
     }
     template <class C>
     __host__ __device__ __forceinline__ void finish_frame(C &c) {
+        flush(c);
         if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
     }
 };
-
-template <typename T>
-__host__ __device__ __attribute__((noinline)) int32_t render_call(T *frame, int32_t from, int32_t to, uint32_t col,
-                                                                  uint32_t pf, uint32_t vb, int32_t ystart,
-                                                                  uint32_t sub, uint32_t G) {
-    if (!frame || to <= from) return from;
-    render_span(frame, from, to, col, pf, vb, ystart, sub, G);
-    return to;
-}
 
 // Records the recompute tape of the soft backward.  Pixels of the final frame
 // are attributed to the instruction during whose span [previous write point,
@@ -319,8 +328,12 @@ __host__ __device__ __forceinline__ void exec_static(C &c, uint32_t lo, uint32_t
         const uint32_t u8 = W::first(ea);
         if (u8 & 0x80u) c.mem.ram_set(u8 & 0x7Fu, r);
         else c.tia_out(u8 & 0x3Fu, r, t0 + n - 1);
+        // only a WSYNC write ($02 or its mirror $42) can have set the stall flag
+        // (it is clear between instructions); for a constant address this folds
+        c.finish(OP, info, t0, n, (u8 & 0xBFu) == 0x02u);
+    } else {
+        c.finish(OP, info, t0, n, false);
     }
-    c.finish(OP, info, t0, n, wr);
 }
 
 // One interpreted instruction at each running lane's pc: fetch, decode and a
