@@ -196,6 +196,7 @@ RomCode select_positions(const Image &im, const Profile &pr, int budget) {
         if (decode_op(op) == 0 || fast_form(op)) order.push_back({kv.second, kv.first});  // others: interpreter
     }
     std::stable_sort(order.begin(), order.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    budget = std::min(budget, 4095);  // ids fit the lookup table's 12-bit field
     if ((int)order.size() > budget) {
         order.resize((size_t)std::max(budget, 0));
         rc.truncated = true;
@@ -216,7 +217,8 @@ RomCode select_positions(const Image &im, const Profile &pr, int budget) {
     return rc;
 }
 
-void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, TranslateStats &stats) {
+void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, TranslateStats &stats,
+              std::vector<uint16_t> &table) {
     char buf[1024];
     const int nb = rc.banks;
     auto id = [&](uint32_t bank, uint32_t pc) -> uint32_t {
@@ -272,38 +274,19 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
         const uint32_t i = id(bank, pc);
         return i && starts[i - 1] ? i : 0u;
     };
-    // lookup table: (bank, pc & 0xFFF) -> run start id, verified against the full pc
-    std::vector<uint32_t> tab((size_t)nb * 4096, 0);
+    // lookup table: (bank, pc & 0xFFF) -> run start id | pc >> 12 << 12 (the id
+    // counts only when the pc's high bits match)
+    table.assign((size_t)nb * 4096, 0);
     for (size_t i = 0; i < rc.pos.size(); ++i) {
         if (!starts[i]) continue;
         const Pos &p = rc.pos[i];
-        uint32_t &slot = tab[((size_t)p.bank << 12) | (p.pc & 0xFFFu)];
-        if (!slot) slot = (uint32_t)(i + 1);
+        uint16_t &slot = table[((size_t)p.bank << 12) | (p.pc & 0xFFFu)];
+        if (!slot) slot = (uint16_t)((i + 1) | ((p.pc >> 12) << 12));
     }
-    std::snprintf(buf, sizeof buf, "VCS_TR_TABLE uint16_t kTab%d[%d] = {", r, nb * 4096);
-    s += buf;
-    for (size_t i = 0; i < tab.size(); ++i) {
-        std::snprintf(buf, sizeof buf, "%u,", tab[i]);
-        s += buf;
-    }
-    s += "};\n";
-    std::snprintf(buf, sizeof buf, "VCS_TR_TABLE uint16_t kPc%d[%zu] = {0xFFFF,", r, rc.pos.size() + 1);
-    s += buf;
-    for (const Pos &p : rc.pos) {
-        std::snprintf(buf, sizeof buf, "%u,", p.pc);
-        s += buf;
-    }
-    s += "};\n";
-    std::snprintf(buf, sizeof buf,
-                  "VCS_TR_FN uint32_t lookup%d(uint32_t bank, uint32_t pc) {\n"
-                  "  if (!((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu)) return 0u;\n"
-                  "  const uint32_t i = kTab%d[((bank & %du) << 12) | (pc & 0xFFFu)];\n"
-                  "  return kPc%d[i] == pc ? i : 0u;\n}\n",
-                  r, r, nb - 1, r);
-    s += buf;
     std::snprintf(buf, sizeof buf,
                   "template <class W, class C>\n"
-                  "VCS_TR_FN void blocks%d(C &c, uint32_t u, uint32_t &blk, uint32_t &fb, int32_t lim) {\n",
+                  "VCS_TR_FN void blocks%d(C &c, uint32_t u, uint32_t &blk, uint32_t &fb, int32_t lim, "
+                  "const uint16_t *tab) {\n",
                   r);
     s += buf;
     // Each run: the entry check, made once by every lane of the wave (the
@@ -371,7 +354,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
         } else if (fe == kStatic) {
             std::snprintf(buf, sizeof buf, "        blk = %uu; break;\n", sid(e.bank, t));
         } else if (fe == kDynamic) {
-            std::snprintf(buf, sizeof buf, "        blk = lookup%d(c.bank, c.pc); break;\n", r);
+            std::snprintf(buf, sizeof buf, "        blk = lookup(tab, c.bank, c.pc); break;\n");
         } else {
             std::snprintf(buf, sizeof buf, "        blk = %uu; break;\n", sid(e.bank, e.pc + ((e.d >> 14) & 3u)));
         }
@@ -435,26 +418,50 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
         weight[(size_t)r] = envs * (double)(prof[(size_t)r].count.size() ? 1 : 0);
         wsum += weight[(size_t)r];
     }
+    // block lookup: (bank, pc) -> run start id, from the image's table (staged in LDS)
+    s += "VCS_TR_FN uint32_t lookup(const uint16_t *tab, uint32_t bank, uint32_t pc) {\n"
+         "  if (!((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu)) return 0u;\n"
+         "  const uint32_t e = tab[(bank << 12) | (pc & 0xFFFu)];\n"
+         "  return (e >> 12) == (pc >> 12) ? (e & 0xFFFu) : 0u;\n}\n";
+    std::vector<uint16_t> all_tables;
+    std::vector<uint32_t> tab_off, tab_banks;
     for (int r = 0; r < R; ++r) {
         const Image im{roms + rom_off[(size_t)r], rom_size[(size_t)r], rom_mapper[(size_t)r]};
         const int share = wsum > 0 ? (int)((double)budget * weight[(size_t)r] / wsum) : 0;
         const RomCode rc = select_positions(im, prof[(size_t)r], share);
-        emit_rom(s, im, r, rc, stats);
+        std::vector<uint16_t> table;
+        emit_rom(s, im, r, rc, stats, table);
+        tab_off.push_back((uint32_t)all_tables.size());
+        tab_banks.push_back((uint32_t)rc.banks);
+        all_tables.insert(all_tables.end(), table.begin(), table.end());
     }
+    char tbuf[64];
+    uint32_t max_banks = 1;
+    s += "VCS_TR_TABLE uint16_t kTabAll[] = {";
+    for (uint16_t v : all_tables) {
+        std::snprintf(tbuf, sizeof tbuf, "%u,", v);
+        s += tbuf;
+    }
+    s += "};\nVCS_TR_TABLE uint32_t kTabOff[] = {";
+    for (uint32_t v : tab_off) {
+        std::snprintf(tbuf, sizeof tbuf, "%u,", v);
+        s += tbuf;
+    }
+    s += "};\nVCS_TR_TABLE uint32_t kTabBanks[] = {";
+    for (uint32_t v : tab_banks) {
+        std::snprintf(tbuf, sizeof tbuf, "%u,", v);
+        s += tbuf;
+        max_banks = std::max(max_banks, v);
+    }
+    s += "};\n";
     // one instruction loop for all images: a wave runs its image's blocks when
     // its lanes agree on the block and the entry check holds, else the
     // interpreter for one instruction (one copy of it, shared by the images)
-    char buf[1024];
-    s += "VCS_TR_FN uint32_t lookup(uint32_t rom, uint32_t bank, uint32_t pc) {\n  switch (rom) {\n";
-    for (int r = 0; r < R; ++r) {
-        std::snprintf(buf, sizeof buf, "    case %d: return lookup%d(bank, pc);\n", r, r);
-        s += buf;
-    }
-    s += "    default: return 0u;\n  }\n}\n"
-         "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
-         "  struct State { uint32_t rom, blk; uint4 *log; };\n"
+    char buf[4096];
+    s += "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
+         "  struct State { uint32_t rom, blk; uint4 *log; const uint16_t *tab; };\n"
          "  template <class C> VCS_TR_FN static void init(C &c, State &s) {\n"
-         "    s.blk = lookup(s.rom, c.bank, c.pc);\n"
+         "    s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "    c.hook.log = s.log;\n"
          "    c.hook.nlog = 0u;\n"
          "  }\n"
@@ -467,7 +474,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "        if (fb != 0u || u == 0u || !W::all(s.blk == u)) break;\n"
          "        switch (s.rom) {\n";
     for (int r = 0; r < R; ++r) {
-        std::snprintf(buf, sizeof buf, "          case %d: blocks%d<W>(c, u, s.blk, fb, lim); break;\n", r, r);
+        std::snprintf(buf, sizeof buf, "          case %d: blocks%d<W>(c, u, s.blk, fb, lim, s.tab); break;\n", r, r);
         s += buf;
     }
     s += "          default: fb = 1u; break;\n"
@@ -478,7 +485,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "      go = !c.jam && c.cyc < lim;\n"
          "      if (go) {  // lanes at different blocks, a failed entry check, or untranslated code\n"
          "        interp_one<W, false>(c, decode);\n"
-         "        s.blk = lookup(s.rom, c.bank, c.pc);\n"
+         "        s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "        c.hook.flush(c);\n"
          "        go = !c.jam && c.cyc < lim;\n"
          "      }\n"
@@ -492,10 +499,16 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
                   "  __shared__ __align__(16) uint32_t ram_lds[32 * %d];\n"
                   "  __shared__ uint32_t dec_lds[256];\n"
                   "  __shared__ uint4 log_lds[%d * vcs::kTrMaxRun];\n"
+                  "  __shared__ uint16_t tab_lds[%u * 4096];\n"
                   "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::kTrMaxRun;\n"
+                  "  {\n"
+                  "    const int32_t rom = P.st.main_block_rom[blockIdx.x];\n"
+                  "    const uint16_t *src = vcs::tr::kTabAll + vcs::tr::kTabOff[rom];\n"
+                  "    for (uint32_t i = threadIdx.x; i < vcs::tr::kTabBanks[rom] * 4096u; i += %d) tab_lds[i] = src[i];\n"
+                  "  }\n"
                   "  vcs::step_group<%d, %d, false, vcs::tr::Exec>(P, rom_lds, ram_lds, dec_lds,\n"
-                  "      [log](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log}; });\n}\n",
-                  TPB, TPB / G, TPB / G, G, G, TPB);
+                  "      [log](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log, tab_lds}; });\n}\n",
+                  TPB, TPB / G, TPB / G, max_banks, G, TPB, G, TPB);
     s += buf;
     s += "#endif\n";
     return s;

@@ -167,7 +167,8 @@ struct RenderHook {
                     const uint4 e = log[i];
                     const int32_t cc = (int32_t)e.x;
                     if (cc > rend_cc) {
-                        render_span(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
+                        if constexpr (sizeof(T) == 1) render_span_u8(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
+                        else render_span(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
                         rend_cc = cc;
                     }
                 }

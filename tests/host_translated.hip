@@ -51,7 +51,8 @@ extern "C" int host_translated(int rom_index, const uint8_t *rom, int rom_size, 
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
     std::vector<uint4> log((size_t)kTrMaxRun);
-    step_env<OneLane, 1, false, false, tr::Exec>(P, env, 0, mapper, m, kHostDecode.e,
-                                                 tr::Exec::State{(uint32_t)rom_index, 0u, log.data()});
+    step_env<OneLane, 1, false, false, tr::Exec>(
+        P, env, 0, mapper, m, kHostDecode.e,
+        tr::Exec::State{(uint32_t)rom_index, 0u, log.data(), tr::kTabAll + tr::kTabOff[rom_index]});
     return 0;
 }
