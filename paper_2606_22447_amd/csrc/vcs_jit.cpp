@@ -336,7 +336,8 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
                           p0.lo, ix, p0.lo, ix);
             cond += buf;
         }
-        std::snprintf(buf, sizeof buf, "%u|if (!W::all(%s)) { fb = 1u; break; }\n", run[0] + 1, cond.c_str());
+        std::snprintf(buf, sizeof buf, "%u|E%u: if (!W::all(%s)) { fb = 1u; break; }\n", run[0] + 1, run[0] + 1,
+                      cond.c_str());
         code += buf;
         for (uint32_t i : run) {
             const Pos &p = rc.pos[i];
@@ -349,8 +350,26 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
         if (f == kJam) {
             std::snprintf(buf, sizeof buf, "        blk = %uu; break;\n", id(last.bank, last.pc));
         } else if (fe == kBranch) {
-            std::snprintf(buf, sizeof buf, "        blk = c.pc == 0x%04Xu ? %uu : %uu; break;\n", t, sid(e.bank, t),
-                          sid(e.bank, e.pc + 2u));
+            const uint32_t me = run[0] + 1, bt = sid(e.bank, t), bf = sid(e.bank, e.pc + 2u);
+            if (bt == me || bf == me) {
+                // a loop onto itself: while every lane takes it, go straight back to
+                // the run's entry check, as long as the pixel-write log has room for
+                // another pass (it is drained between dispatches) or no lane draws
+                int32_t writes = 0;  // pixel-register writes a pass may log (TIA writes)
+                for (uint32_t i : run) {
+                    const Pos &q = rc.pos[i];
+                    const int wk = write_kind(q);
+                    if (wk == 2 || (wk == 1 && q.lo < 0x80u)) ++writes;
+                }
+                std::snprintf(buf, sizeof buf,
+                              "        blk = c.pc == 0x%04Xu ? %uu : %uu;\n"
+                              "        if (W::all(blk == %uu) && (W::all(c.hook.frame == nullptr) || "
+                              "W::all(c.hook.nlog + %du <= (uint32_t)kTrMaxRun))) goto E%u;\n"
+                              "        break;\n",
+                              t, bt, bf, me, writes, me);
+            } else {
+                std::snprintf(buf, sizeof buf, "        blk = c.pc == 0x%04Xu ? %uu : %uu; break;\n", t, bt, bf);
+            }
         } else if (fe == kStatic) {
             std::snprintf(buf, sizeof buf, "        blk = %uu; break;\n", sid(e.bank, t));
         } else if (fe == kDynamic) {

@@ -36,11 +36,11 @@ def test_translated_source_is_basic_blocks_of_page0_forms():
     import re
     assert "vcs_tr_step" in src and "exec_static" in src
     loop = src[src.index("void blocks0("):src.index("struct Exec")]
-    cases = re.findall(r"^      case \d+: (.*)$", loop, re.M)
+    cases = re.findall(r"^      case \d+: (.*)$", loop, re.M) + re.findall(r"^      (?:else )?if \(u == \d+u\) do \{\n\s+(.*)$", loop, re.M)
     assert 10 < len(cases) < 100  # runs, each one case
     assert src.count("exec_static<W, 0x") > 100  # positions
     # every run is entered through one wave-wide check (or is a lone jam)
-    assert all(c.startswith("if (!W::all(c.cyc + ") or c.startswith("c.jam = 1") for c in cases)
+    assert all(re.match(r"(E\d+: )?if \(!W::all\(c\.cyc \+ ", c) or c.startswith("c.jam = 1") for c in cases)
     # only page-0 forms are translated (no absolute / indexed-absolute / indirect opcodes)
     dec = Bd.decode_table()
     for op in {int(x, 16) for x in __import__("re").findall(r"exec_static<W, 0x([0-9A-F]{2})u>", src)}:
