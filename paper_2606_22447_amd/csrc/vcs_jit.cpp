@@ -364,7 +364,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
                 std::snprintf(buf, sizeof buf,
                               "        blk = c.pc == 0x%04Xu ? %uu : %uu;\n"
                               "        if (W::all(blk == %uu) && (W::all(c.hook.frame == nullptr) || "
-                              "W::all(c.hook.nlog + %du <= (uint32_t)kTrMaxRun))) goto E%u;\n"
+                              "W::all(c.hook.nlog + %du <= (uint32_t)kTrLogCap))) goto E%u;\n"
                               "        break;\n",
                               t, bt, bf, me, writes, me);
             } else {
@@ -477,17 +477,21 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     // its lanes agree on the block and the entry check holds, else the
     // interpreter for one instruction (one copy of it, shared by the images)
     char buf[4096];
-    s += "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W>;\n"
+    std::snprintf(buf, sizeof buf, "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W, %d>;\n", G);
+    s += buf;
+    s += ""
          "  struct State { uint32_t rom, blk; uint4 *log; const uint16_t *tab; };\n"
          "  template <class C> VCS_TR_FN static void init(C &c, State &s) {\n"
          "    s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "    c.hook.log = s.log;\n"
          "    c.hook.nlog = 0u;\n"
+         "    c.hook.acc_row = -1;\n"
          "  }\n"
          "  template <class W, bool kPlain, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
          "    uint32_t fb = 0u;\n"
          "    while (go) {\n"
+         "      bool interp = true;\n"
          "      for (;;) {  // every lane at one block: translated runs back to back, no per-lane loop control\n"
          "        const uint32_t u = W::first(s.blk);\n"
          "        if (fb != 0u || u == 0u || !W::all(s.blk == u)) break;\n"
@@ -498,11 +502,15 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     }
     s += "          default: fb = 1u; break;\n"
          "        }\n"
-         "        c.hook.flush(c);\n"
+         "        if (fb != 0u) break;\n"
+         "        interp = false;\n"
          "        if (!W::all(!c.jam && c.cyc < lim)) break;\n"
+         "        if (W::any(c.hook.nlog > (uint32_t)(kTrLogCap - kTrMaxRun))) break;  // drain the pixel log\n"
+         "        interp = true;\n"
          "      }\n"
+         "      c.hook.flush(c);\n"
          "      go = !c.jam && c.cyc < lim;\n"
-         "      if (go) {  // lanes at different blocks, a failed entry check, or untranslated code\n"
+         "      if (go && interp) {  // lanes at different blocks, a failed entry check, or untranslated code\n"
          "        interp_one<W, false>(c, decode);\n"
          "        s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "        c.hook.flush(c);\n"
@@ -517,9 +525,9 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
                   "  extern __shared__ __align__(16) uint2 rom_lds[];\n"
                   "  __shared__ __align__(16) uint32_t ram_lds[32 * %d];\n"
                   "  __shared__ uint32_t dec_lds[256];\n"
-                  "  __shared__ uint4 log_lds[%d * vcs::kTrMaxRun];\n"
+                  "  __shared__ uint4 log_lds[%d * vcs::kTrLogCap];\n"
                   "  __shared__ uint16_t tab_lds[%u * 4096];\n"
-                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::kTrMaxRun;\n"
+                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::kTrLogCap;\n"
                   "  {\n"
                   "    const int32_t rom = P.st.main_block_rom[blockIdx.x];\n"
                   "    const uint16_t *src = vcs::tr::kTabAll + vcs::tr::kTabOff[rom];\n"

@@ -122,23 +122,33 @@ struct GlobalMem {
 // ---------------------------------------------------------------------------
 // Hooks
 // ---------------------------------------------------------------------------
+// Pixel-write log of an env in translated code, in entries (one more holds the
+// frame's end).
+constexpr int kTrLogCap = 2 * kTrMaxRun;
+
 // Renders the returned frame lazily: before every pixel-register write the
 // pixels up to the write's effect clock are drawn with the old state.  With a
 // wave policy W (translated code) a write only appends (effect clock, colour
 // registers, playfield, VBLANK: the state before it) to the env's log in LDS,
 // a store with no branch, and flush(), called between runs where lanes may
-// branch, draws the logged spans.
+// branch, draws the logged spans through draw_log.
 struct NoWave {};
-template <typename T, class W = NoWave>
+template <typename T, class W = NoWave, int GL = 1>
 struct RenderHook {
     static constexpr bool kRecord = false;
+    static constexpr int kGroups = (40 + GL - 1) / GL;  // (with W) pixel groups of a row per lane
     T *frame;         // frame being rendered, or nullptr
     int32_t rend_cc;  // frame-relative colour clock rendered up to
     int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
     int32_t ystart;
     uint32_t sub, G;
-    uint4 *log;       // (with W) the env's pixel-write log, kTrMaxRun entries
+    uint4 *log;       // (with W) the env's pixel-write log, kTrLogCap entries
     uint32_t nlog;
+    // (with W, GL lanes per env) the visible row being drawn and this lane's
+    // groups sub, sub + GL, ... of it, merged span by span in registers and
+    // stored when drawing moves to another row
+    int32_t acc_row;
+    uint32_t acc[kGroups];
     template <class C>
     __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
         if constexpr (std::is_same<W, NoWave>::value) {
@@ -149,26 +159,70 @@ struct RenderHook {
                     rend_cc = cc;
                 }
             }
-        } else {
-            const uint32_t i = nlog < (uint32_t)kTrMaxRun ? nlog : (uint32_t)kTrMaxRun - 1u;
+        } else if (W::any(frame != nullptr)) {  // (wave-uniform) only while some lane draws
+            const uint32_t i = nlog < (uint32_t)kTrLogCap ? nlog : (uint32_t)kTrLogCap - 1u;
             log[i] = make_uint4((uint32_t)(3 * (w + 1)), c.col, c.pf, c.vb);
             ++nlog;
         }
     }
-    // Draw the logged spans (translated code; a no-op otherwise).  A run
-    // writes at most kTrMaxRun pixel registers, and the log is drawn after
-    // every run.
+    // (with W) Store the accumulated row.
+    __host__ __device__ __forceinline__ void store_row() {
+        if (acc_row >= 0) {
+            T *row = frame + acc_row * kScreenW;
+#pragma unroll
+            for (int j = 0; j < kGroups; ++j) {
+                const uint32_t g = sub + (uint32_t)(j * GL);
+                if (g < 40u) *reinterpret_cast<uint32_t *>(row + 4 * g) = acc[j];
+            }
+        }
+    }
+    // (with W) Draw [a, b) with one TIA state into the row accumulators: per
+    // group, the covered pixels' bytes take the group's colour (a byte mask,
+    // no branch).  Rows outside the visible window are skipped.
+    __host__ __device__ __forceinline__ void span(int32_t a, int32_t b, uint32_t col, uint32_t pf, uint32_t vb) {
+        const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
+        if (a < vis0) a = vis0;
+        if (b > vis1) b = vis1;
+        if (a >= b) return;
+        const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
+        while (a < b) {
+            const int32_t y = (a - vis0) / kClocksPerLine;
+            const int32_t line0 = vis0 + y * kClocksPerLine;
+            const int32_t seg = b < line0 + kClocksPerLine ? b : line0 + kClocksPerLine;
+            if (y != acc_row) {
+                store_row();
+                acc_row = y;
+            }
+#pragma unroll
+            for (int j = 0; j < kGroups; ++j) {
+                const uint32_t g = sub + (uint32_t)(j * GL);
+                const int32_t k0 = line0 + kHBlank + 4 * (int32_t)g;
+                int32_t lo = a - k0, hi = seg - k0;  // covered bytes [lo, hi) of the group
+                lo = lo < 0 ? 0 : (lo > 3 ? 3 : lo);
+                const bool any = hi > lo && a < k0 + 4;
+                hi = hi > 4 ? 4 : (hi < 1 ? 1 : hi);
+                const uint32_t m = any ? ((0xFFFFFFFFu << (8 * lo)) & (0xFFFFFFFFu >> (8 * (4 - hi)))) : 0u;
+                const uint32_t c = (vb & 2u) ? 0u : ((col >> (8 * group_owner(g < 40u ? g : 0u, mask, ctrl))) & 0xFEu);
+                acc[j] = (acc[j] & ~m) | ((c * 0x01010101u) & m);
+            }
+            a = seg;
+        }
+    }
+    // Draw the logged spans (translated code; a no-op otherwise).  The log is
+    // drawn before it could overflow: between runs once it holds more than
+    // kTrLogCap - kTrMaxRun entries (a run writes at most kTrMaxRun pixel
+    // registers).
     template <class C>
     __host__ __device__ __forceinline__ void flush(C &) {
         if constexpr (!std::is_same<W, NoWave>::value) {
+            static_assert(sizeof(T) == 1, "translated code returns u8 frames");
             if (frame) {
-                const uint32_t n = nlog < (uint32_t)kTrMaxRun ? nlog : (uint32_t)kTrMaxRun;
+                const uint32_t n = nlog < (uint32_t)kTrLogCap ? nlog : (uint32_t)kTrLogCap;
                 for (uint32_t i = 0; i < n; ++i) {
                     const uint4 e = log[i];
                     const int32_t cc = (int32_t)e.x;
                     if (cc > rend_cc) {
-                        if constexpr (sizeof(T) == 1) render_span_u8(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
-                        else render_span(frame, rend_cc, cc, e.y, e.z, e.w, ystart, sub, G);
+                        span(rend_cc, cc, e.y, e.z, e.w);
                         rend_cc = cc;
                     }
                 }
@@ -184,8 +238,16 @@ struct RenderHook {
     }
     template <class C>
     __host__ __device__ __forceinline__ void finish_frame(C &c) {
-        flush(c);
-        if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
+        if constexpr (std::is_same<W, NoWave>::value) {
+            if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
+        } else {
+            flush(c);
+            if (frame) {  // the rest of the frame with the current state
+                span(rend_cc, kClocksPerFrame, c.col, c.pf, c.vb);
+                store_row();
+            }
+            acc_row = -1;
+        }
     }
 };
 
