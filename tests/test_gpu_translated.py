@@ -55,3 +55,32 @@ def test_translated_jam():
         ref = oracle_env(w, b)
         assert (ram[b] == ref["ram"]).all() and (fr[b] == ref["frames"]).all()
     assert (vb.regs().cpu().numpy()[:, 8] & 1).all()  # jammed
+
+
+@pytest.mark.parametrize("max_positions", [8, 48])
+def test_translated_small_budget_mixes_blocks_and_interpreter(max_positions):
+    # most of the code is not translated: waves move between blocks and the interpreter all the time
+    w = I.config_c1(num_envs=64, steps=8)
+    import torch
+    from paper_2606_22447_amd.vcs import VcsBatch
+    say("translated budget", max_positions)
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel="translated", lanes_per_env=16,
+                  block_threads=256, max_positions=max_positions)
+    assert vb.translation["positions"] <= max_positions and vb.translation["truncated"]
+    vb.reset(ram0=w.ram0)
+    ram, fr, _ = vb.step(actions=w.actions, frames="all")
+    torch.cuda.synchronize()
+    ram, fr = ram.cpu().numpy(), fr.cpu().numpy()
+    for b in range(w.num_envs):
+        ref = oracle_env(w, b)
+        assert (ram[b] == ref["ram"]).all(), b
+        assert (fr[b] == ref["frames"]).all(), b
+
+
+def test_translated_frames_last_and_none_modes():
+    w = I.config_c1(num_envs=8, steps=5)
+    ram_all, fr_all, _, _ = gpu_run(w, "translated", 16, 256, frames="all")
+    ram_last, fr_last, _, _ = gpu_run(w, "translated", 16, 256, frames="last")
+    ram_none, fr_none, _, _ = gpu_run(w, "translated", 16, 256, frames="none")
+    assert (ram_all == ram_last).all() and (ram_all == ram_none).all()
+    assert (fr_last == fr_all[:, -1]).all() and fr_none is None

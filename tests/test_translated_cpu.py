@@ -98,3 +98,19 @@ def test_translate_rejects_other_kernels():
                   Bd.VCS_KERNEL_GROUPED, 16, 256)
     with pytest.raises(Bd.VcsError):
         Bd.translate(h, np.concatenate([r.image for r in w.roms]), compile_only=True)
+
+
+def test_translate_arguments_and_budget():
+    w = I.config_c1(num_envs=8, steps=2)
+    h = _ctx(w, 16, 256)
+    roms = np.concatenate([r.image for r in w.roms])
+    with pytest.raises(Bd.VcsError):
+        Bd.translate(h, roms, compile_only=True, max_positions=-1)
+    with pytest.raises(Bd.VcsError):
+        Bd.translate(h, roms, compile_only=True, max_positions=70000)
+    src = Bd.translated_source(h, roms, max_positions=10)
+    assert src.count("exec_static<W, 0x") <= 10
+    # the translated kernel keeps at most 64 envs per workgroup (the pixel logs live in LDS)
+    with pytest.raises(Bd.VcsError):
+        Bd.create([r.size for r in w.roms], [r.mapper for r in w.roms], w.env_rom, 4, 34, 0, 0,
+                  Bd.VCS_KERNEL_TRANSLATED, 1, 256)
