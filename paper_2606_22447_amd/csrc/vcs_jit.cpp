@@ -364,7 +364,7 @@ void emit_rom(std::string &s, const Image &im, int r, const RomCode &rc, Transla
                 std::snprintf(buf, sizeof buf,
                               "        blk = c.pc == 0x%04Xu ? %uu : %uu;\n"
                               "        if (W::all(blk == %uu) && (W::all(c.hook.frame == nullptr) || "
-                              "W::all(c.hook.nlog + %du <= (uint32_t)kTrLogCap))) goto E%u;\n"
+                              "W::all(c.hook.nlog + %du <= (uint32_t)kLogCap))) goto E%u;\n"
                               "        break;\n",
                               t, bt, bf, me, writes, me);
             } else {
@@ -424,6 +424,13 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     s.reserve(1 << 20);
     s += "#include \"vcs_device.hpp\"\n#ifndef VCS_TR_FN\n#define VCS_TR_FN __device__ __forceinline__\n"
          "#define VCS_TR_TABLE __device__ const\n#endif\nnamespace vcs {\nnamespace tr {\n";
+    {  // the env's pixel-write log: up to 256 entries, 64 KB of LDS per workgroup
+        int log_cap = 256;
+        while (log_cap > kTrLogCap && (TPB / G) * log_cap * 16 > 65536) log_cap /= 2;
+        char cbuf[64];
+        std::snprintf(cbuf, sizeof cbuf, "constexpr int kLogCap = %d;\n", log_cap);
+        s += cbuf;
+    }
     const int R = (int)rom_off.size();
     // the position budget is shared out over the images in proportion to
     // their envs' share of the executed instructions
@@ -477,7 +484,8 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     // its lanes agree on the block and the entry check holds, else the
     // interpreter for one instruction (one copy of it, shared by the images)
     char buf[4096];
-    std::snprintf(buf, sizeof buf, "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W, %d>;\n", G);
+    std::snprintf(buf, sizeof buf,
+                  "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W, %d, kLogCap>;\n", G);
     s += buf;
     s += ""
          "  struct State { uint32_t rom, blk; uint4 *log; const uint16_t *tab; };\n"
@@ -485,7 +493,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "    s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "    c.hook.log = s.log;\n"
          "    c.hook.nlog = 0u;\n"
-         "    c.hook.acc_row = -1;\n"
+         "    c.hook.row_lo = 0;\n"
          "  }\n"
          "  template <class W, bool kPlain, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
@@ -505,7 +513,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "        if (fb != 0u) break;\n"
          "        interp = false;\n"
          "        if (!W::all(!c.jam && c.cyc < lim)) break;\n"
-         "        if (W::any(c.hook.nlog > (uint32_t)(kTrLogCap - kTrMaxRun))) break;  // drain the pixel log\n"
+         "        if (W::any(c.hook.nlog > (uint32_t)(kLogCap - kTrMaxRun))) break;  // drain the pixel log\n"
          "        interp = true;\n"
          "      }\n"
          "      c.hook.flush(c);\n"
@@ -525,9 +533,9 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
                   "  extern __shared__ __align__(16) uint2 rom_lds[];\n"
                   "  __shared__ __align__(16) uint32_t ram_lds[32 * %d];\n"
                   "  __shared__ uint32_t dec_lds[256];\n"
-                  "  __shared__ uint4 log_lds[%d * vcs::kTrLogCap];\n"
+                  "  __shared__ uint4 log_lds[%d * vcs::tr::kLogCap];\n"
                   "  __shared__ uint16_t tab_lds[%u * 4096];\n"
-                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::kTrLogCap;\n"
+                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::tr::kLogCap;\n"
                   "  {\n"
                   "    const int32_t rom = P.st.main_block_rom[blockIdx.x];\n"
                   "    const uint16_t *src = vcs::tr::kTabAll + vcs::tr::kTabOff[rom];\n"

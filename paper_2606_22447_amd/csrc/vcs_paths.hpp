@@ -122,33 +122,31 @@ struct GlobalMem {
 // ---------------------------------------------------------------------------
 // Hooks
 // ---------------------------------------------------------------------------
-// Pixel-write log of an env in translated code, in entries (one more holds the
-// frame's end).
+// Smallest pixel-write log of an env in translated code, in entries: room for
+// one run's writes on top of the entries one row can hold.
 constexpr int kTrLogCap = 2 * kTrMaxRun;
 
 // Renders the returned frame lazily: before every pixel-register write the
 // pixels up to the write's effect clock are drawn with the old state.  With a
 // wave policy W (translated code) a write only appends (effect clock, colour
-// registers, playfield, VBLANK: the state before it) to the env's log in LDS,
-// a store with no branch, and flush(), called between runs where lanes may
-// branch, draws the logged spans through draw_log.
+// registers, playfield, VBLANK: the state before it) to the env's log of CAP
+// entries in LDS, a store with no branch, and flush(), called between runs
+// where lanes may branch, draws the visible rows the log covers once it is
+// nearly full: the env's GL lanes share the rows out, each lane writing whole
+// rows, and the entries of the row not yet covered stay in the log.
 struct NoWave {};
-template <typename T, class W = NoWave, int GL = 1>
+template <typename T, class W = NoWave, int GL = 1, int CAP = kTrLogCap>
 struct RenderHook {
+    static_assert(CAP >= kTrLogCap, "the log holds a row's writes and a run's");
     static constexpr bool kRecord = false;
-    static constexpr int kGroups = (40 + GL - 1) / GL;  // (with W) pixel groups of a row per lane
     T *frame;         // frame being rendered, or nullptr
     int32_t rend_cc;  // frame-relative colour clock rendered up to
     int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
     int32_t ystart;
     uint32_t sub, G;
-    uint4 *log;       // (with W) the env's pixel-write log, kTrLogCap entries
+    uint4 *log;       // (with W) the env's pixel-write log, CAP entries
     uint32_t nlog;
-    // (with W, GL lanes per env) the visible row being drawn and this lane's
-    // groups sub, sub + GL, ... of it, merged span by span in registers and
-    // stored when drawing moves to another row
-    int32_t acc_row;
-    uint32_t acc[kGroups];
+    int32_t row_lo;   // (with W) first visible row of the frame not drawn yet
     template <class C>
     __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
         if constexpr (std::is_same<W, NoWave>::value) {
@@ -160,74 +158,98 @@ struct RenderHook {
                 }
             }
         } else if (W::any(frame != nullptr)) {  // (wave-uniform) only while some lane draws
-            const uint32_t i = nlog < (uint32_t)kTrLogCap ? nlog : (uint32_t)kTrLogCap - 1u;
+            const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
             log[i] = make_uint4((uint32_t)(3 * (w + 1)), c.col, c.pf, c.vb);
             ++nlog;
         }
     }
-    // (with W) Store the accumulated row.
-    __host__ __device__ __forceinline__ void store_row() {
-        if (acc_row >= 0) {
-            T *row = frame + acc_row * kScreenW;
+    // (with W) Draw the visible rows [row_lo, y_hi) from log entries [0, n),
+    // whose last entry lies past the last pixel of row y_hi - 1: the pixel at
+    // colour clock k shows the state of the first entry with an effect clock
+    // > k (an entry holds the state before its write).  Lane sub takes rows
+    // row_lo + sub, row_lo + sub + GL, ...; a row's first entry is found by
+    // bisection and the row is walked with the entry pointer, a 4-pixel group
+    // at a time (one colour unless a write takes effect inside the group),
+    // 16 pixels per store.
+    __host__ __device__ __forceinline__ void draw_rows(int32_t y_hi, uint32_t n) {
+        const int32_t vis0 = ystart * kClocksPerLine + kHBlank;  // clock of pixel (0, 0)
+        for (int32_t y = row_lo + (int32_t)sub; y < y_hi; y += GL) {
+            const int32_t k_row = vis0 + y * kClocksPerLine;
+            uint32_t lo = 0, hi = n - 1u;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((int32_t)log[mid].x > k_row) hi = mid;
+                else lo = mid + 1u;
+            }
+            uint32_t p = lo;
+            uint4 e = log[p];
+            uint32_t mask = pf_mask20(e.z);
+            auto advance_past = [&](int32_t k) {  // to the first entry with clock > k
+                while ((int32_t)e.x <= k && p + 1u < n) {
+                    e = log[++p];
+                    mask = pf_mask20(e.z);
+                }
+            };
+            auto colour = [&](uint32_t g) {
+                return (e.w & 2u) ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
+            };
+            T *row = frame + y * kScreenW;
+            for (int32_t q = 0; q < kScreenW / 16; ++q) {
+                uint32_t wd[4];
 #pragma unroll
-            for (int j = 0; j < kGroups; ++j) {
-                const uint32_t g = sub + (uint32_t)(j * GL);
-                if (g < 40u) *reinterpret_cast<uint32_t *>(row + 4 * g) = acc[j];
-            }
-        }
-    }
-    // (with W) Draw [a, b) with one TIA state into the row accumulators: per
-    // group, the covered pixels' bytes take the group's colour (a byte mask,
-    // no branch).  Rows outside the visible window are skipped.
-    __host__ __device__ __forceinline__ void span(int32_t a, int32_t b, uint32_t col, uint32_t pf, uint32_t vb) {
-        const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
-        if (a < vis0) a = vis0;
-        if (b > vis1) b = vis1;
-        if (a >= b) return;
-        const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
-        while (a < b) {
-            const int32_t y = (a - vis0) / kClocksPerLine;
-            const int32_t line0 = vis0 + y * kClocksPerLine;
-            const int32_t seg = b < line0 + kClocksPerLine ? b : line0 + kClocksPerLine;
-            if (y != acc_row) {
-                store_row();
-                acc_row = y;
-            }
-#pragma unroll
-            for (int j = 0; j < kGroups; ++j) {
-                const uint32_t g = sub + (uint32_t)(j * GL);
-                const int32_t k0 = line0 + kHBlank + 4 * (int32_t)g;
-                int32_t lo = a - k0, hi = seg - k0;  // covered bytes [lo, hi) of the group
-                lo = lo < 0 ? 0 : (lo > 3 ? 3 : lo);
-                const bool any = hi > lo && a < k0 + 4;
-                hi = hi > 4 ? 4 : (hi < 1 ? 1 : hi);
-                const uint32_t m = any ? ((0xFFFFFFFFu << (8 * lo)) & (0xFFFFFFFFu >> (8 * (4 - hi)))) : 0u;
-                const uint32_t c = (vb & 2u) ? 0u : ((col >> (8 * group_owner(g < 40u ? g : 0u, mask, ctrl))) & 0xFEu);
-                acc[j] = (acc[j] & ~m) | ((c * 0x01010101u) & m);
-            }
-            a = seg;
-        }
-    }
-    // Draw the logged spans (translated code; a no-op otherwise).  The log is
-    // drawn before it could overflow: between runs once it holds more than
-    // kTrLogCap - kTrMaxRun entries (a run writes at most kTrMaxRun pixel
-    // registers).
-    template <class C>
-    __host__ __device__ __forceinline__ void flush(C &) {
-        if constexpr (!std::is_same<W, NoWave>::value) {
-            static_assert(sizeof(T) == 1, "translated code returns u8 frames");
-            if (frame) {
-                const uint32_t n = nlog < (uint32_t)kTrLogCap ? nlog : (uint32_t)kTrLogCap;
-                for (uint32_t i = 0; i < n; ++i) {
-                    const uint4 e = log[i];
-                    const int32_t cc = (int32_t)e.x;
-                    if (cc > rend_cc) {
-                        span(rend_cc, cc, e.y, e.z, e.w);
-                        rend_cc = cc;
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t g = (uint32_t)(4 * q + j);
+                    const int32_t k0 = k_row + 4 * (int32_t)g;
+                    advance_past(k0);
+                    if ((int32_t)e.x > k0 + 3) {
+                        wd[j] = colour(g) * 0x01010101u;
+                    } else {  // a write takes effect inside the group
+                        uint32_t v = 0u;
+                        for (int b = 0; b < 4; ++b) {
+                            advance_past(k0 + b);
+                            v |= colour(g) << (8 * b);
+                        }
+                        wd[j] = v;
                     }
                 }
+                *reinterpret_cast<uint4 *>(row + 16 * q) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
             }
-            nlog = 0;
+        }
+        if (y_hi > row_lo) row_lo = y_hi;
+    }
+    // (with W) Draw what the log covers once it is nearly full (some run could
+    // not fit) or `all` (frame end, where the caller has appended the state at
+    // the frame's end), then keep only the entries still needed: those past
+    // the first pixel of the first row not drawn.  A row's pixels span 160
+    // clocks and a write takes at least 9, so at most 18 entries stay.
+    template <class C>
+    __host__ __device__ __forceinline__ void flush(C &, bool all = false) {
+        if constexpr (!std::is_same<W, NoWave>::value) {
+            static_assert(sizeof(T) == 1, "translated code returns u8 frames");
+            const uint32_t n = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP;
+            if (!frame) {
+                nlog = 0;
+            } else if (n > 0u && (all || n > (uint32_t)(CAP - kTrMaxRun))) {
+                const int32_t vis0 = ystart * kClocksPerLine + kHBlank;
+                // rows whose last pixel lies before the last entry's clock
+                const int32_t t = (int32_t)log[n - 1u].x - vis0 - (kScreenW - 1);
+                int32_t y_hi = t <= 0 ? 0 : (t + kClocksPerLine - 1) / kClocksPerLine;
+                y_hi = y_hi < kScreenH ? y_hi : kScreenH;
+                draw_rows(y_hi, n);
+                uint32_t keep0 = n;  // first entry past the first pixel of row y_hi
+                if (y_hi < kScreenH) {
+                    const int32_t cut = vis0 + y_hi * kClocksPerLine;
+                    keep0 = 0u;
+                    while (keep0 < n && (int32_t)log[keep0].x <= cut) ++keep0;
+                }
+                // move the kept entries to the front; the env's lanes run this
+                // loop together, so every read of an iteration precedes its writes
+                for (uint32_t i = sub; i < n - keep0; i += (uint32_t)GL) {
+                    const uint4 e = log[keep0 + i];
+                    log[i] = e;
+                }
+                nlog = n - keep0;
+            }
         }
     }
     template <class C>
@@ -241,12 +263,15 @@ struct RenderHook {
         if constexpr (std::is_same<W, NoWave>::value) {
             if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
         } else {
-            flush(c);
-            if (frame) {  // the rest of the frame with the current state
-                span(rend_cc, kClocksPerFrame, c.col, c.pf, c.vb);
-                store_row();
+            if (W::any(frame != nullptr)) {  // the rest of the frame with the current state
+                flush(c);
+                const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
+                log[i] = make_uint4((uint32_t)kClocksPerFrame, c.col, c.pf, c.vb);
+                nlog = i + 1u;
+                flush(c, true);
             }
-            acc_row = -1;
+            nlog = 0;
+            row_lo = 0;
         }
     }
 };

@@ -50,7 +50,7 @@ extern "C" int host_translated(int rom_index, const uint8_t *rom, int rom_size, 
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-    std::vector<uint4> log((size_t)kTrLogCap);
+    std::vector<uint4> log((size_t)tr::kLogCap);
     step_env<OneLane, 1, false, false, tr::Exec>(
         P, env, 0, mapper, m, kHostDecode.e,
         tr::Exec::State{(uint32_t)rom_index, 0u, log.data(), tr::kTabAll + tr::kTabOff[rom_index]});

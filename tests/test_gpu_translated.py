@@ -44,6 +44,19 @@ def test_translated_heterogeneous_roms_with_episode_resets():
         assert (fr[b] == ref["frames"]).all(), b
 
 
+@pytest.mark.parametrize("G,tpb", [(16, 256), (64, 256)])
+def test_translated_same_clock_tia_writes(G, tpb):
+    # JSR pushes onto CTRLPF and COLUBK: two pixel-register writes at one clock,
+    # at every pixel alignment, drawn by rows shared over the env's lanes
+    from tests.test_translated_cpu import tia_pushes_workload
+    w = tia_pushes_workload(B=40, S=4)
+    say("translated tia pushes", G, tpb)
+    ram, fr, _, vb = gpu_run(w, "translated", G, tpb)
+    for b in range(w.num_envs):
+        ref = oracle_env(w, b)
+        assert (ram[b] == ref["ram"]).all() and (fr[b] == ref["frames"]).all(), b
+
+
 def test_translated_jam():
     from tests import asm as A
     img = A.program(lambda b: (b.ins("LDA", "imm", 0x2A), b.ins("STA", "zp", A.COLUBK), b.ins("INC", "zp", 0x80),

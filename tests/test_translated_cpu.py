@@ -48,9 +48,43 @@ def test_translated_source_is_basic_blocks_of_page0_forms():
         assert mode in (0, 1, 2, 3, 4, 5, 12) or op == 0x4C, hex(op)
 
 
-@pytest.mark.parametrize("name", ["c1", "hetero"])
+def tia_pushes_workload(B: int = 3, S: int = 3) -> I.Workload:
+    """A program whose JSRs push onto CTRLPF and COLUBK (stack pointer $0A): two
+    pixel-register writes at the same clock.  The two call sites push different
+    return addresses, so COLUBK changes at every call, and the 45-cycle loop
+    drifts through every pixel alignment of the writes."""
+    from tests import asm as A
+
+    def body(b):
+        b.ins("LDX", "imm", 0x0A)
+        b.ins("TXS")
+        for reg, v in ((A.PF0, 0xF0), (A.PF1, 0xAA), (A.PF2, 0x55)):
+            b.ins("LDA", "imm", v)
+            b.ins("STA", "zp", reg)
+        b.label("LOOP")
+        b.ins("INC", "zp", 0x80)
+        b.ins("LDA", "zp", 0x80)
+        b.ins("STA", "zp", A.COLUPF)
+        b.ins("INC", "zp", 0x81)
+        b.ins("JSR", "abs", "SUBA")
+        b.label("BACKA")
+        b.ins("JSR", "abs", "SUBB")
+        b.label("BACKB")
+        b.ins("JMP", "abs", "LOOP")
+        for name, back in (("SUBA", "BACKA"), ("SUBB", "BACKB")):
+            b.label(name)
+            b.ins("LDX", "imm", 0x0A)
+            b.ins("TXS")
+            b.ins("JMP", "abs", back)
+
+    img = A.program(body)
+    return I.Workload("tia_pushes", [I.Rom(0, 4096, 1, img)], np.zeros(B, np.int32), I.initial_ram(21, B),
+                      np.zeros((B, S), np.uint8), S, 2, seed=7)
+
+
+@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes"])
 def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
-    w = I.config_c1(num_envs=6, steps=6) if name == "c1" else _hetero()
+    w = {"c1": lambda: I.config_c1(num_envs=6, steps=6), "hetero": _hetero, "tia_pushes": tia_pushes_workload}[name]()
     h = _ctx(w)
     src = Bd.translated_source(h, np.concatenate([r.image for r in w.roms]))
     gen = tmp_path / "translated.hip"
