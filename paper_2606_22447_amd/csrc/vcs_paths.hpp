@@ -236,11 +236,15 @@ struct RenderHook {
                 int32_t y_hi = t <= 0 ? 0 : (t + kClocksPerLine - 1) / kClocksPerLine;
                 y_hi = y_hi < kScreenH ? y_hi : kScreenH;
                 draw_rows(y_hi, n);
-                uint32_t keep0 = n;  // first entry past the first pixel of row y_hi
+                uint32_t keep0 = n;  // first entry past the first pixel of row y_hi (bisection)
                 if (y_hi < kScreenH) {
                     const int32_t cut = vis0 + y_hi * kClocksPerLine;
-                    keep0 = 0u;
-                    while (keep0 < n && (int32_t)log[keep0].x <= cut) ++keep0;
+                    uint32_t lo = 0u;
+                    while (lo < keep0) {
+                        const uint32_t mid = (lo + keep0) >> 1;
+                        if ((int32_t)log[mid].x > cut) keep0 = mid;
+                        else lo = mid + 1u;
+                    }
                 }
                 // move the kept entries to the front; the env's lanes run this
                 // loop together, so every read of an iteration precedes its writes
