@@ -298,41 +298,6 @@ __host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int
     });
 }
 
-// The same pixels as render_span for a u8 frame, written with fewer branches:
-// per line segment each of the G lanes takes every G-th 4-pixel group, a whole
-// group as one 32-bit store and a partial group as up to four byte stores.
-__host__ __device__ __forceinline__ void render_span_u8(uint8_t *frame, int32_t from, int32_t to, uint32_t col,
-                                                        uint32_t pf, uint32_t vb, int32_t ystart, uint32_t sub,
-                                                        uint32_t G) {
-    const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
-    if (from < vis0) from = vis0;
-    if (to > vis1) to = vis1;
-    if (from >= to) return;
-    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
-    while (from < to) {
-        const int32_t y = (from - vis0) / kClocksPerLine;
-        const int32_t line0 = vis0 + y * kClocksPerLine;
-        const int32_t seg_end = to < line0 + kClocksPerLine ? to : line0 + kClocksPerLine;
-        const int32_t x0 = from - line0 - kHBlank > 0 ? from - line0 - kHBlank : 0;
-        const int32_t x1 = seg_end - line0 - kHBlank;
-        uint8_t *row = frame + y * kScreenW;
-        for (int32_t g = (x0 >> 2) + (int32_t)sub; 4 * g < x1; g += (int32_t)G) {
-            const uint32_t c = (vb & 2u) ? 0u : ((col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
-            const int32_t a = x0 - 4 * g, b = x1 - 4 * g;  // covered pixels of the group: [max(a,0), min(b,4))
-            uint8_t *q = row + 4 * g;
-            if (a <= 0 && b >= 4) {
-                *reinterpret_cast<uint32_t *>(q) = c * 0x01010101u;
-            } else {
-                if (a <= 0 && b > 0) q[0] = (uint8_t)c;
-                if (a <= 1 && b > 1) q[1] = (uint8_t)c;
-                if (a <= 2 && b > 2) q[2] = (uint8_t)c;
-                if (a <= 3 && b > 3) q[3] = (uint8_t)c;
-            }
-        }
-        from = seg_end;
-    }
-}
-
 // Per-owner sums of dL/dpixel over [from, to) (soft backward): sums[r] for owner r.
 __host__ __device__ __forceinline__ bool pixel_sums(const float *gframe, int32_t from, int32_t to, uint32_t pf,
                                                     uint32_t vb, int32_t ystart, float sums[4]) {
