@@ -44,13 +44,15 @@ def test_translated_heterogeneous_roms_with_episode_resets():
         assert (fr[b] == ref["frames"]).all(), b
 
 
+@pytest.mark.parametrize("prog", ["tia_pushes", "playfield_modes"])
 @pytest.mark.parametrize("G,tpb", [(16, 256), (64, 256)])
-def test_translated_same_clock_tia_writes(G, tpb):
-    # JSR pushes onto CTRLPF and COLUBK: two pixel-register writes at one clock,
-    # at every pixel alignment, drawn by rows shared over the env's lanes
-    from tests.test_translated_cpu import tia_pushes_workload
-    w = tia_pushes_workload(B=40, S=4)
-    say("translated tia pushes", G, tpb)
+def test_translated_hand_assembled_tia_programs(prog, G, tpb):
+    # JSR pushes onto CTRLPF and COLUBK (two pixel-register writes at one clock, at
+    # every pixel alignment), and CTRLPF cycled through reflected and score modes:
+    # drawn by rows shared over the env's lanes
+    from tests import test_translated_cpu as T
+    w = {"tia_pushes": T.tia_pushes_workload, "playfield_modes": T.playfield_modes_workload}[prog](B=40, S=4)
+    say("translated", prog, G, tpb)
     ram, fr, _, vb = gpu_run(w, "translated", G, tpb)
     for b in range(w.num_envs):
         ref = oracle_env(w, b)

@@ -82,9 +82,36 @@ def tia_pushes_workload(B: int = 3, S: int = 3) -> I.Workload:
                       np.zeros((B, S), np.uint8), S, 2, seed=7)
 
 
-@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes"])
+def playfield_modes_workload(B: int = 3, S: int = 3) -> I.Workload:
+    """A program that cycles CTRLPF through plain, reflected, score and score +
+    reflected playfields in a loop that drifts across the line, with COLUP0,
+    COLUP1, COLUPF and COLUBK all different and changing: every owner of a
+    playfield group shows up on both halves of the screen."""
+    from tests import asm as A
+
+    def body(b):
+        for reg, v in ((A.PF0, 0xA0), (A.PF1, 0x96), (A.PF2, 0x3C), (A.COLUP0, 0x44), (A.COLUP1, 0x88),
+                       (A.COLUPF, 0xCC), (A.COLUBK, 0x22)):
+            b.ins("LDA", "imm", v)
+            b.ins("STA", "zp", reg)
+        b.label("LOOP")
+        for mode in (0x00, 0x01, 0x02, 0x03):
+            b.ins("LDA", "imm", mode)
+            b.ins("STA", "zp", A.CTRLPF)
+            b.ins("INC", "zp", 0x80)
+        b.ins("LDA", "zp", 0x80)
+        b.ins("STA", "zp", A.COLUP1)
+        b.ins("JMP", "abs", "LOOP")
+
+    img = A.program(body)
+    return I.Workload("playfield_modes", [I.Rom(0, 4096, 1, img)], np.zeros(B, np.int32), I.initial_ram(22, B),
+                      np.zeros((B, S), np.uint8), S, 2, seed=8)
+
+
+@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes", "playfield_modes"])
 def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
-    w = {"c1": lambda: I.config_c1(num_envs=6, steps=6), "hetero": _hetero, "tia_pushes": tia_pushes_workload}[name]()
+    w = {"c1": lambda: I.config_c1(num_envs=6, steps=6), "hetero": _hetero, "tia_pushes": tia_pushes_workload,
+         "playfield_modes": playfield_modes_workload}[name]()
     h = _ctx(w)
     src = Bd.translated_source(h, np.concatenate([r.image for r in w.roms]))
     gen = tmp_path / "translated.hip"
