@@ -203,13 +203,14 @@ struct RenderHook {
                     advance_past(k0);
                     if ((int32_t)e.x > k0 + 3) {
                         wd[j] = colour(g) * 0x01010101u;
-                    } else {  // a write takes effect inside the group
-                        uint32_t v = 0u;
-                        for (int b = 0; b < 4; ++b) {
-                            advance_past(k0 + b);
-                            v |= colour(g) << (8 * b);
-                        }
-                        wd[j] = v;
+                    } else {  // a write takes effect inside the group, at clock e.x
+                        // Effect clocks are multiples of 3, so every entry past those at
+                        // e.x lies beyond the group: the pixels before e.x show e, the
+                        // rest the first entry past e.x (writes at one clock: the last).
+                        const uint32_t c0 = colour(g);
+                        const uint32_t m = (1u << (8 * ((int32_t)e.x - k0))) - 1u;  // 1..3 bytes
+                        advance_past((int32_t)e.x);
+                        wd[j] = ((c0 * 0x01010101u) & m) | ((colour(g) * 0x01010101u) & ~m);
                     }
                 }
                 *reinterpret_cast<uint4 *>(row + 16 * q) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
