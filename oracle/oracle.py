@@ -24,6 +24,7 @@ f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
 f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
 u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
 
 
 def lib():
@@ -51,6 +52,7 @@ def lib():
         L.orc_frame.argtypes = [vp]
         L.orc_frame.restype = C.POINTER(C.c_uint8)
         L.orc_poke_ram.argtypes = [vp, C.c_int, C.c_int]
+        L.orc_op_stats.argtypes = [vp, u64p]
         L.orc_intim_at.argtypes = [vp, C.c_int64]
         L.orc_timint_at.argtypes = [vp, C.c_int64]
         L.orc_opcode_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4
@@ -129,6 +131,12 @@ class Machine:
 
     def poke(self, cell: int, v: int):
         self.L.orc_poke_ram(self.h, cell, v)
+
+    def op_stats(self):
+        """(executions, page-crossing executions, taken branches) per opcode byte since power-on."""
+        out = np.zeros(768, np.uint64)
+        self.L.orc_op_stats(self.h, out)
+        return out[:256], out[256:512], out[512:]
 
     def intim_at(self, t: int) -> int:
         return self.L.orc_intim_at(self.h, t)
@@ -210,6 +218,15 @@ def run_env(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int,
     if step_state:
         out["step_state"] = st
     return out
+
+
+def op_stats(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int, frame_skip: int):
+    """Hard rollout of one env from power-on (no resets); returns the opcode
+    statistics of Machine.op_stats."""
+    m = Machine(rom, mapper, ram0)
+    for s in range(steps):
+        m.env_step(0 if actions is None else int(actions[s]), frame_skip, s, store_frame=False)
+    return m.op_stats()
 
 
 def decode_logits(rows: np.ndarray, tau: float):

@@ -364,6 +364,9 @@ struct Orc {
     int ystart;
     uint8_t frame[SCREEN_H * SCREEN_W];
     uint64_t instructions;
+    /* executions per opcode byte; of them, indexed accesses that crossed a page
+     * (or taken branches that crossed one), and taken branches */
+    uint64_t op_count[256], op_cross[256], op_taken[256];
     /* soft */
     Graph *g;
     int step;
@@ -1039,8 +1042,10 @@ int orc_step_instruction(Orc *m) {
         case BEQ: {
             if (branch_taken(m, op)) {
                 uint16_t target = (uint16_t)(m->pc + (int8_t)lo);
-                n += 1 + ((target & 0xFF00) != (m->pc & 0xFF00));
+                crossed = (target & 0xFF00) != (m->pc & 0xFF00);
+                n += 1 + crossed;
                 m->pc = target;
+                m->op_taken[opc]++;
             }
             break;
         }
@@ -1054,6 +1059,8 @@ int orc_step_instruction(Orc *m) {
         if (r) m->cycle += CYCLES_PER_LINE - r;
     }
     m->instructions++;
+    m->op_count[opc]++;
+    if (crossed) m->op_cross[opc]++;
     return 0;
 }
 
@@ -1113,6 +1120,17 @@ void orc_get_regs(const Orc *m, int64_t *out) {
     out[20] = m->vsync;
     out[21] = m->cycle;
     out[22] = (int64_t)m->instructions;
+}
+
+/* Opcode statistics since power-on: out[0..255] executions per opcode byte,
+ * out[256..511] of them with a page crossing (indexed address or taken branch),
+ * out[512..767] taken branches. */
+void orc_op_stats(const Orc *m, uint64_t *out) {
+    for (int i = 0; i < 256; i++) {
+        out[i] = m->op_count[i];
+        out[256 + i] = m->op_cross[i];
+        out[512 + i] = m->op_taken[i];
+    }
 }
 
 const uint8_t *orc_ram(const Orc *m) { return m->ram; }

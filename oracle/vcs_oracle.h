@@ -20,6 +20,7 @@ void orc_set_action(Orc *m, int action);
 void orc_set_draw_frame(Orc *m, int64_t frame);
 void orc_env_step(Orc *m, int action, int frame_skip, int64_t step_index, int store_frame);
 void orc_get_regs(const Orc *m, int64_t *out);
+void orc_op_stats(const Orc *m, uint64_t *out);
 const uint8_t *orc_ram(const Orc *m);
 const uint8_t *orc_frame(const Orc *m);
 void orc_poke_ram(Orc *m, int cell, int v);

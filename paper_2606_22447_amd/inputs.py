@@ -1006,3 +1006,625 @@ def soft_leaves(w: Workload, seed: int | None = None) -> SoftLeaves:
 
 
 CONFIGS = {"c0": config_c0, "c1": config_c1, "c2": config_c2, "c3": config_c3, "c4": config_c4}
+
+
+# --------------------------------------------------------------------------
+# Opcode-sweep programs: every byte of the instruction set, every addressing
+# form, page crossings, read-modify-write on RAM / TIA / RIOT, every timer
+# interval, code in RAM.  A parity workload, not a performance one.
+# --------------------------------------------------------------------------
+
+def instruction_set() -> dict[int, tuple[str, str]]:
+    """opcode byte -> (mnemonic, mode) for the 189 bytes of the paper's set."""
+    ops = {op: mm for mm, op in OPCODES.items()}
+    for lst, mode in ((NOP_IMP, "imp"), (NOP_IMM, "imm"), (NOP_ZP, "zp"), (NOP_ZPX, "zpx"), (NOP_ABS, "abs"),
+                      (NOP_ABX, "abx")):
+        for op in lst:
+            ops[op] = ("NOP", mode)
+    return ops
+
+
+# RIOT registers (13-bit addresses; A2 = timer, A0 = TIMINT on reads, A4 = timer write)
+TIM1T, TIM8T, T1024T, TIMINT = 0x294, 0x295, 0x297, 0x285
+
+
+class _SweepGen:
+    """One seeded opcode-sweep program.
+
+    RAM plan: $80-$9F chain variables (the initial RAM, rewritten by the
+    results), $A0-$A7 four pointers, $A8-$C7 a window for indexed writes,
+    $C8-$CF flag accumulators, $D0-$D7 code written at run time, $D8-$FF the
+    stack.  Values loaded from the variables steer the index registers, so
+    envs with different RAM take different addresses, page crossings and
+    branch directions; results are folded back into the variables, so an
+    error anywhere reaches the RAM and the frame."""
+
+    VAR0, NVAR, PTR, WIN, ACC, RAMCODE = 0x80, 32, 0xA0, 0xA8, 0xC8, 0xD0
+
+    def __init__(self, seed: int, size: int, soft_safe: bool):
+        self.r = Rng(stream_key(seed, 0x535750))
+        self.seed, self.size, self.soft_safe = seed, size, soft_safe
+        self.bank_size = 2048 if size == 2048 else 4096
+        self.base = 0xF800 if size == 2048 else 0xF000
+        self.n_label = 0
+
+    # ---- helpers
+    def lab(self, stem: str) -> str:
+        self.n_label += 1
+        return f"{stem}_{self.n_label}"
+
+    def var(self) -> int:
+        return self.VAR0 + self.r.randint(0, self.NVAR - 1)
+
+    def acc(self) -> int:
+        return self.ACC + self.r.randint(0, 7)
+
+    def idx_reg(self, b: Bank, reg: str, lo: int, span: int):
+        """Load X or Y with lo + (a variable & (span-1)): per-env values in [lo, lo+span)."""
+        b.ins("LDA", "zp", self.var())
+        b.ins("AND", "imm", span - 1)
+        if lo:
+            b.ins("ORA", "imm", lo) if (lo & (span - 1)) == 0 else b.ins("ADC", "imm", lo)
+        b.ins("TAX" if reg == "X" else "TAY")
+
+    def setup_flags(self, b: Bank, decimal_ok: bool = True):
+        r = self.r
+        b.ins(r.choice(["CLC", "SEC"]))
+        if decimal_ok and r.random() < 0.3:
+            b.ins("SED")
+        else:
+            b.ins("CLD")
+
+    def fold_flags(self, b: Bank):
+        """Fold the status byte into an accumulator cell (no decimal adds: EOR)."""
+        if self.r.random() < 0.5:
+            return
+        a = self.acc()
+        b.ins("PHP")
+        b.ins("PLA")
+        b.ins("EOR", "zp", a)
+        b.ins("STA", "zp", a)
+
+    def save_a(self, b: Bank):
+        b.ins("STA", "zp", self.var())
+
+    def set_ptr(self, b: Bank, k: int, addr: int):
+        b.ins("LDA", "imm", addr & 0xFF)
+        b.ins("STA", "zp", self.PTR + 2 * k)
+        b.ins("LDA", "imm", (addr >> 8) & 0xFF)
+        b.ins("STA", "zp", self.PTR + 2 * k + 1)
+
+    def op(self, b: Bank, opc: int, operand: int | None, mode: str):
+        n = _MODE_LEN[mode] - 1
+        if n == 0:
+            b.raw(opc)
+        elif n == 1:
+            b.raw(opc, operand & 0xFF)
+        else:
+            b.raw(opc, operand & 0xFF, (operand >> 8) & 0xFF)
+
+    # ---- operands by access kind: (address or operand, needs index setup)
+    def read_target_zp(self) -> int:
+        r = self.r
+        k = r.weighted([("var", 7), ("tia", 2), ("win", 1)])
+        if k == "var":
+            return self.var()
+        if k == "win":
+            return self.WIN + r.randint(0, 31)
+        return r.choice([INPT4, 0x0D, 0x3C, 0x2D, 0x00, 0x07, 0x1C])  # INPT4/5, mirrors, collisions
+
+    def write_target_zp(self) -> int:
+        r = self.r
+        k = r.weighted([("var", 5), ("win", 2), ("tia", 3)])
+        if k == "var":
+            return self.var()
+        if k == "win":
+            return self.WIN + r.randint(0, 31)
+        return r.choice([COLUBK, COLUPF, COLUP0, COLUP1, PF0, PF1, PF2, CTRLPF, WSYNC, 0x49, 0x48, 0x03, 0x1F])
+
+    def read_target_abs(self, tables) -> int:
+        r = self.r
+        k = r.weighted([("ram", 3), ("mirror", 1), ("tia", 1), ("riot", 3), ("rom", 3)])
+        if k == "ram":
+            return self.var()
+        if k == "mirror":
+            return 0x100 | self.var()           # the stack page mirrors RAM
+        if k == "tia":
+            return r.choice([0x000C, 0x010C, 0x003D, 0x0105, 0x0040])
+        if k == "riot":
+            return r.choice([SWCHA, 0x281, 0x282, 0x283, INTIM, TIMINT, 0x286, 0x287, 0x2A4, 0x285])
+        return tables[r.randint(0, len(tables) - 1)] + r.randint(0, 255)
+
+    def write_target_abs(self) -> int:
+        r = self.r
+        k = r.weighted([("ram", 3), ("mirror", 1), ("tia", 3), ("riot", 2), ("rom", 1)])
+        if k == "ram":
+            return self.var()
+        if k == "mirror":
+            return 0x100 | (self.WIN + r.randint(0, 31))
+        if k == "tia":
+            return r.choice([0x0009, 0x0008, 0x0108, 0x004E, 0x000D, 0x000F, 0x0002, 0x0006])
+        if k == "riot":
+            return r.choice([TIM1T, TIM8T, TIM64T, T1024T, 0x29C, 0x29F, 0x280, 0x281])
+        return self.base + r.randint(0, 0x7FF)  # cartridge: no effect
+
+    # ---- one instruction of the set, with its operand set up and its result folded
+    def emit(self, b: Bank, opc: int, mn: str, mode: str, tables, cross: bool | None = None):
+        """cross (indexed forms): True = an address range some envs cross a page
+        in, False = one no env crosses in, None = either."""
+        r = self.r
+        load = mn in ("LDA", "LDX", "LDY", "LAX", "ADC", "SBC", "AND", "ORA", "EOR", "CMP", "CPX", "CPY", "BIT",
+                      "USBC") or (mn == "NOP" and mode != "imp")
+        store = mn in ("STA", "STX", "STY", "SAX")
+        rmw = mn in ("ASL", "LSR", "ROL", "ROR", "INC", "DEC")
+        if mode == "rel":
+            return self.emit_branch(b, opc, mn)
+        if mode in ("imp", "acc") or mn in ("JMP", "JSR"):
+            return self.emit_implied(b, opc, mn, mode)
+        # registers the instruction reads besides the operand
+        if mn in ("ADC", "SBC", "USBC"):
+            self.setup_flags(b)
+        elif mn in ("ROL", "ROR"):
+            self.setup_flags(b, decimal_ok=False)
+        # the address
+        operand = 0
+        if mode == "imm":
+            operand = r.randint(0, 255)
+        elif mode == "zp":
+            operand = self.write_target_zp() if (store or rmw) else self.read_target_zp()
+        elif mode in ("zpx", "zpy"):
+            reg = "X" if mode == "zpx" else "Y"
+            if r.random() < 0.35:  # wraps inside page 0, onto TIA registers $00-$0F (reads: collisions, INPT4)
+                self.idx_reg(b, reg, 0x10, 16)
+                operand = 0xF0
+            else:
+                self.idx_reg(b, reg, 0, 32)
+                operand = (self.WIN if (store or rmw) else self.VAR0)
+        elif mode == "abs":
+            operand = self.write_target_abs() if (store or rmw) else self.read_target_abs(tables)
+        elif mode in ("abx", "aby"):
+            reg = "X" if mode == "abx" else "Y"
+            kinds = [("ram", 3 if cross is not True else 0), ("cross_tia", 2 if cross is not False else 0),
+                     ("rom", 3 if not (store or rmw) and cross is not False else 0),
+                     ("riot", 1 if not rmw and cross is not True else 0)]
+            kind = r.weighted(kinds)
+            if kind == "ram":      # $A8 + [0, 32): no crossing
+                self.idx_reg(b, reg, 0, 32)
+                operand = self.WIN if (store or rmw) else self.VAR0
+            elif kind == "cross_tia":
+                # $F8 + [0, 16): some envs cross into $0100-$0107 (TIA mirror).  Between
+                # snippets the stack is empty (S = $FF), so $F8-$FF hold nothing live.
+                self.idx_reg(b, reg, 0, 16)
+                operand = 0x00F8
+            elif kind == "rom":    # a table near a page end: some envs cross
+                self.idx_reg(b, reg, 0, 64)
+                operand = tables[0] + r.randint(0xE0, 0xF0)
+            else:                  # RIOT registers $0280-$0287 (ports, INTIM, TIMINT) or timer writes
+                self.idx_reg(b, reg, 0, 8)
+                operand = 0x0290 if store else 0x0280
+        elif mode in ("izx", "izy"):
+            targets = [self.var(), self.read_target_abs(tables) if not (store or rmw) else self.write_target_abs(),
+                       self.WIN + r.randint(0, 8), r.choice([INTIM, COLUBK, COLUPF, SWCHA])]
+            if mode == "izx":
+                for k in range(4):
+                    self.set_ptr(b, k, targets[k])
+                b.ins("LDA", "zp", self.var())
+                b.ins("AND", "imm", 3)
+                b.ins("ASL", "acc")
+                b.ins("TAX")
+                operand = self.PTR
+            else:
+                k = r.randint(0, 3)
+                kind = r.weighted([("rom", 3 if not store and cross is not False else 0),
+                                   ("win", 2 if cross is not True else 0), ("cross", 1 if cross is not False else 0)])
+                if kind == "rom":
+                    self.set_ptr(b, k, tables[0] + r.randint(0xE0, 0xF0))
+                    self.idx_reg(b, "Y", 0, 64)
+                elif kind == "win":
+                    self.set_ptr(b, k, self.WIN)
+                    self.idx_reg(b, "Y", 0, 32)
+                else:  # $F8 + Y: some envs cross into the TIA mirror $0100-$0107
+                    self.set_ptr(b, k, 0x00F8)
+                    self.idx_reg(b, "Y", 0, 16)
+                operand = self.PTR + 2 * k
+        # the accumulator / X operand of the instruction
+        if mn in ("STX", "CPX"):
+            if mode in ("abx", "zpx", "izx"):
+                pass
+            elif mode in ("zpy", "aby", "izy"):
+                b.ins("LDX", "zp", self.var())
+            else:
+                b.ins("LDX", "zp", self.var())
+        elif mn in ("STY", "CPY"):
+            if mode not in ("zpy", "aby", "izy", "zpx", "abx", "izx"):
+                b.ins("LDY", "zp", self.var())
+        if mn not in ("LDA", "LAX", "LDX", "LDY") and not (rmw and mode == "acc"):
+            b.ins("LDA", "zp", self.var())
+        if mn == "SAX" and mode in ("zp", "abs"):
+            b.ins("LDX", "zp", self.var())
+        self.op(b, opc, operand, mode)
+        # fold the results back
+        if mn in ("LDA", "LAX", "ADC", "SBC", "USBC", "AND", "ORA", "EOR"):
+            self.save_a(b)
+        if mn in ("LDX", "LAX"):
+            b.ins("STX", "zp", self.var())
+        if mn == "LDY":
+            b.ins("STY", "zp", self.var())
+        if mn in ("ADC", "SBC", "USBC"):
+            b.ins("CLD")
+        if not store:
+            self.fold_flags(b)
+
+    def branch_cond(self, b: Bank, mn: str):
+        """Flags for branch mn from a variable: taken for some envs, not for others."""
+        r = self.r
+        flag = {"BPL": "N", "BMI": "N", "BVC": "V", "BVS": "V", "BCC": "C", "BCS": "C", "BNE": "Z", "BEQ": "Z"}[mn]
+        v = self.var()
+        if flag == "N":
+            b.ins("LDA", "zp", v)
+        elif flag == "Z":
+            b.ins("LDA", "zp", v)
+            b.ins("AND", "imm", 1 << r.randint(0, 7))
+        elif flag == "C":
+            b.ins("LDA", "zp", v)
+            b.ins("CMP", "imm", r.randint(0, 255))
+        else:
+            b.ins("BIT", "zp", v)
+
+    def emit_branch(self, b: Bank, opc: int, mn: str):
+        r = self.r
+        self.branch_cond(b, mn)
+        skip = self.lab("br")
+        b.raw(opc, 0)
+        b.fix.append((b.pos - 1, "rel", skip))
+        b.ins("INC", "zp", self.var())
+        b.label(skip)
+
+    def page_end(self, b: Bank):
+        """Near a page end, a branch across it: forward (a data-dependent
+        condition; the taken path lands in the next page) or backward (a count
+        loop whose head lies in the previous page)."""
+        r = self.r
+        if (b.pos & 0xFF) < 0xE0 or (b.pos & 0xFF) > 0xF5:
+            return
+        if r.random() < 0.8:
+            mn = ["BPL", "BMI", "BVC", "BVS", "BCC", "BCS", "BNE", "BEQ"][self.n_cross % 8]
+            self.n_cross += 1
+            self.branch_cond(b, mn)
+            while (b.pos & 0xFF) != 0xFC:
+                b.byte(0xEA)
+            b.ins(mn, "rel", 0)
+            b.img[b.pos - 1] = 0x02  # over the next two bytes, into the next page
+            b.ins("INC", "zp", self.var())
+        else:
+            b.ins("LDA", "zp", self.var())
+            b.ins("AND", "imm", 7)
+            b.ins("TAX")
+            b.ins("INX")
+            while (b.pos & 0xFF) != 0xFE:
+                b.byte(0xEA)
+            b.ins("DEX")  # the loop head, last byte of the page
+            b.ins("NOP")
+            b.ins("BNE", "rel", 0)
+            b.img[b.pos - 1] = (-4) & 0xFF  # back to the DEX, across the page boundary
+            b.ins("STX", "zp", self.var())
+
+    def emit_implied(self, b: Bank, opc: int, mn: str, mode: str):
+        r = self.r
+        if mn in ("ASL", "LSR", "ROL", "ROR"):  # accumulator forms
+            b.ins("LDA", "zp", self.var())
+            if mn in ("ROL", "ROR"):
+                self.setup_flags(b, decimal_ok=False)
+            b.raw(opc)
+            self.save_a(b)
+            self.fold_flags(b)
+        elif mn in ("TAX", "TAY"):
+            b.ins("LDA", "zp", self.var())
+            b.raw(opc)
+            b.ins("STX" if mn == "TAX" else "STY", "zp", self.var())
+            self.fold_flags(b)
+        elif mn in ("TXA", "TYA"):
+            b.ins("LDX" if mn == "TXA" else "LDY", "zp", self.var())
+            b.raw(opc)
+            self.save_a(b)
+            self.fold_flags(b)
+        elif mn in ("INX", "DEX", "INY", "DEY"):
+            reg = "X" if mn in ("INX", "DEX") else "Y"
+            b.ins("LDX" if reg == "X" else "LDY", "zp", self.var())
+            b.raw(opc)
+            b.ins("STX" if reg == "X" else "STY", "zp", self.var())
+            self.fold_flags(b)
+        elif mn in ("CLC", "SEC", "CLD", "SED", "CLI", "SEI", "CLV", "NOP"):
+            if mn == "CLV":  # set V first: BIT of a byte with bit 6 set
+                b.ins("BIT", "abs", 0x0282 if r.random() < 0.5 else SWCHA)
+            b.raw(opc)
+            self.fold_flags(b)
+            if mn == "SED":
+                b.ins("CLD")
+        elif mn == "TSX":
+            b.raw(opc)
+            b.ins("STX", "zp", self.var())
+        elif mn == "TXS":
+            # move the stack into $F0-$FF, push and pull there, then onto the TIA
+            # colour registers ($06-$09: pushes draw), and back
+            b.ins("TSX")
+            b.ins("STX", "zp", self.ACC + 7)
+            b.ins("LDA", "zp", self.var())
+            b.ins("ORA", "imm", 0xF0)
+            b.ins("TAX")
+            b.raw(opc)
+            b.ins("LDA", "zp", self.var())
+            b.ins("PHA")
+            b.ins("PLA")
+            b.ins("LDX", "imm", r.choice([0x07, 0x08, 0x09]))
+            b.raw(opc)
+            b.ins("LDA", "zp", self.var())
+            b.ins("PHA")
+            b.ins("PHP")
+            b.ins("LDX", "zp", self.ACC + 7)
+            b.raw(opc)
+        elif mn == "PHA":
+            b.ins("LDA", "zp", self.var())
+            b.raw(opc)
+            b.ins("LDA", "zp", self.var())
+            b.ins("PLA")
+            self.save_a(b)
+        elif mn == "PLA":
+            b.ins("LDA", "zp", self.var())
+            b.ins("PHA")
+            b.ins("LDA", "imm", r.randint(0, 255))
+            b.raw(opc)
+            self.save_a(b)
+            self.fold_flags(b)
+        elif mn == "PHP":
+            b.ins("LDA", "zp", self.var())  # N, Z from a variable
+            b.raw(opc)
+            b.ins("PLA")
+            self.save_a(b)
+        elif mn == "PLP":
+            b.ins("LDA", "zp", self.var())
+            b.ins("PHA")
+            b.raw(opc)            # any flags, D and I included
+            self.fold_flags(b)
+            b.ins("CLD")
+        elif mn == "JMP" and mode == "abs":
+            t = self.lab("jmp")
+            b.raw(opc, 0, 0)
+            b.fix.append((b.pos - 2, "abs", t))
+            b.ins("INC", "zp", self.var())  # skipped
+            b.label(t)
+        elif mn == "JMP":  # (ind): through a RAM pointer, and through the table's page-wrapping pair
+            t1, t2 = self.lab("ji"), self.lab("jw")
+            b.ins("LDA", "imm", 0)
+            lo_at = b.pos - 1
+            b.ins("STA", "zp", self.PTR + 6)
+            b.ins("LDA", "imm", 0)
+            hi_at = b.pos - 1
+            b.ins("STA", "zp", self.PTR + 7)
+            b.raw(opc, self.PTR + 6, 0x00)
+            b.ins("INC", "zp", self.var())  # skipped
+            b.label(t1)
+            self._late.append((lo_at, hi_at, t1))
+            if self.wrap_page is not None:
+                b.raw(opc, 0xFF, (self.wrap_page >> 8) & 0xFF)  # JMP ($xxFF): high byte from $xx00
+                b.ins("INC", "zp", self.var())  # skipped
+                b.label(t2)
+                self.wrap_target = t2
+        elif mn == "JSR":
+            b.raw(opc, 0, 0)
+            b.fix.append((b.pos - 2, "abs", "SUB"))
+            self.fold_flags(b)
+            # and a call of code written into RAM: LDA #v ; RTS
+            b.ins("LDA", "imm", 0xA9)
+            b.ins("STA", "zp", self.RAMCODE)
+            b.ins("LDA", "zp", self.var())
+            b.ins("STA", "zp", self.RAMCODE + 1)
+            b.ins("LDA", "imm", 0x60)
+            b.ins("STA", "zp", self.RAMCODE + 2)
+            b.raw(opc, self.RAMCODE, 0x00)
+            self.save_a(b)
+        elif mn == "RTS":  # a computed jump: push target - 1, return
+            t = self.lab("rts")
+            b.ins("LDA", "imm", 0)
+            hi_at = b.pos - 1
+            b.ins("PHA")
+            b.ins("LDA", "imm", 0)
+            lo_at = b.pos - 1
+            b.ins("PHA")
+            b.raw(opc)
+            b.ins("INC", "zp", self.var())  # skipped
+            b.label(t)
+            self._late.append((lo_at, hi_at, t, -1))
+        elif mn == "RTI":  # a pushed frame: PCH, PCL, P
+            t = self.lab("rti")
+            b.ins("LDA", "imm", 0)
+            hi_at = b.pos - 1
+            b.ins("PHA")
+            b.ins("LDA", "imm", 0)
+            lo_at = b.pos - 1
+            b.ins("PHA")
+            b.ins("LDA", "zp", self.var())
+            b.ins("AND", "imm", 0xF7)  # D clear
+            b.ins("PHA")
+            b.raw(opc)
+            b.ins("INC", "zp", self.var())  # skipped
+            b.label(t)
+            self._late.append((lo_at, hi_at, t))
+            self.fold_flags(b)
+        elif mn == "BRK":
+            b.ins("LDA", "zp", self.var())
+            b.raw(opc)
+            b.byte(0xEA)  # skipped by the pushed return address
+            self.fold_flags(b)
+        else:
+            raise AssertionError((mn, mode))
+
+    def build(self, ops: list[int]) -> Rom:
+        r = self.r
+        bs, base = self.bank_size, self.base
+        nb = 2 if self.size == 8192 else 1
+        fill = byte_stream(stream_key(self.seed, 0x535746), self.size)
+        banks = [Bank(bs, base, bytes(fill[i * bs:(i + 1) * bs])) for i in range(nb)]
+        # data tables at the top of each bank (different bytes per bank): a full
+        # page, then (4K banks) 192 bytes below the vectors.  Indexed reads near
+        # a table's end cross into the next page, or past $FFFF into page 0.
+        tab0 = bs - (0x100 if bs == 2048 else 0x200)
+        tab_len = [0xC0] if bs == 2048 else [0x100, 0xC0]
+        tables = [base + tab0 + 256 * i for i in range(len(tab_len))]
+        self.wrap_page = tables[0] if bs == 4096 else None
+        for bi, b in enumerate(banks):
+            tb = byte_stream(stream_key(self.seed, 0x544142, bi), sum(tab_len))
+            b.at(tab0)
+            for v in tb[:tab_len[0]]:
+                b.byte(int(v))
+            if len(tab_len) > 1:
+                b.at(tab0 + 0x100)
+                for v in tb[tab_len[0]:]:
+                    b.byte(int(v))
+        info = instruction_set()
+        # the same code in every bank: a bank switch keeps the flow, the tables differ
+        img_code = None
+        for bi, b in enumerate(banks):
+            self.r = Rng(stream_key(self.seed, 0x535750))  # identical decisions per bank
+            self._late = []
+            self.wrap_target = None
+            self.n_cross = self.seed
+            self.n_label = 0
+            b.at(0)
+            b.label("START")
+            b.ins("SEI")
+            b.ins("CLD")
+            b.ins("LDX", "imm", 0xFF)
+            b.ins("TXS")
+            b.label("MAIN")
+            order = list(ops)
+            for i in range(len(order) - 1, 0, -1):  # seeded shuffle
+                j = self.r.randint(0, i)
+                order[i], order[j] = order[j], order[i]
+            for k, opc in enumerate(order):
+                mn, mode = info[opc]
+                if mode in ("abx", "aby", "izy"):  # with and without page crossings
+                    self.emit(b, opc, mn, mode, tables, cross=False)
+                    self.emit(b, opc, mn, mode, tables, cross=True)
+                else:
+                    self.emit(b, opc, mn, mode, tables)
+                self.page_end(b)
+                if k % 16 == 15:  # a line boundary now and then
+                    b.ins("STA", "zp", WSYNC)
+                if nb == 2 and k % 40 == 20:  # bank switches on data accesses of every kind
+                    self.emit_hotspot(b)
+            # every timer interval, INTIM and TIMINT read back
+            for reg in (TIM1T, TIM8T, TIM64T, T1024T):
+                b.ins("LDA", "zp", self.var())
+                b.ins("AND", "imm", 0x3F)
+                b.ins("STA", "abs", reg)
+                for _ in range(self.r.randint(0, 3)):
+                    b.ins("NOP")
+                b.ins("LDA", "abs", INTIM)
+                self.save_a(b)
+                b.ins("BIT", "abs", TIMINT)
+                self.fold_flags(b)
+            b.ins("LDA", "zp", self.var())
+            b.ins("STA", "zp", COLUBK)
+            b.ins("JMP", "abs", "MAIN")
+            # subroutine and BRK handler
+            b.label("SUB")
+            b.ins("LDA", "zp", self.var())
+            b.ins("EOR", "imm", self.r.randint(0, 255))
+            b.ins("STA", "zp", self.var())
+            b.ins("RTS")
+            b.label("BRKH")
+            b.ins("TSX")
+            b.ins("LDA", "abx", 0x0101)   # the pushed status byte, through the stack page
+            b.ins("EOR", "zp", self.ACC)
+            b.ins("STA", "zp", self.ACC)
+            b.ins("INC", "zp", self.var())
+            b.ins("RTI")
+            assert b.pos <= tab0, "sweep program overflows its bank"
+            code_end = b.pos
+            b.link()
+            for item in self._late:
+                lo_at, hi_at, t = item[:3]
+                a = b.labels[t] + (item[3] if len(item) > 3 else 0)
+                b.img[lo_at] = a & 0xFF
+                b.img[hi_at] = (a >> 8) & 0xFF
+            if self.wrap_target is not None:  # JMP ($xxFF) pair: low byte at $xxFF, high at $xx00
+                a = b.labels[self.wrap_target]
+                b.img[tab0 + 0xFF] = a & 0xFF
+                b.img[tab0] = (a >> 8) & 0xFF
+            # vectors: reset at $FFFC, IRQ/BRK at $FFFE
+            b.at(bs - 4)
+            st, brk = b.labels["START"], b.labels["BRKH"]
+            b.byte(st & 0xFF, st >> 8, brk & 0xFF, brk >> 8)
+            code = bytes(b.img[:code_end])
+            assert img_code is None or img_code == code
+            img_code = code
+        img = np.frombuffer(b"".join(bytes(bb.img) for bb in banks), dtype=np.uint8).copy()
+        return Rom(seed=self.seed, size=self.size, mapper=MAPPER_OF_SIZE[self.size], image=img, reads_inputs=True)
+
+    def emit_hotspot(self, b: Bank):
+        r = self.r
+        kind = r.choice(["lda", "sta", "bit", "abx", "izy", "inc"])
+        hs = 0x1FF8 + r.randint(0, 1)
+        if kind == "lda":
+            b.ins("LDA", "abs", hs)
+            self.save_a(b)
+        elif kind == "sta":
+            b.ins("STA", "abs", hs | 0xE000)
+        elif kind == "bit":
+            b.ins("BIT", "abs", hs)
+        elif kind == "abx":
+            b.ins("LDA", "zp", self.var())
+            b.ins("AND", "imm", 1)
+            b.ins("TAX")
+            b.ins("LDA", "abx", 0xFFF8)
+            self.save_a(b)
+        elif kind == "izy":
+            self.set_ptr(b, 1, 0x1FF8)
+            b.ins("LDA", "zp", self.var())
+            b.ins("AND", "imm", 1)
+            b.ins("TAY")
+            b.ins("LDA", "izy", self.PTR + 2)
+            self.save_a(b)
+        else:
+            b.ins("INC", "abs", hs)
+
+
+def generate_sweep_rom(seed: int, size: int = 4096, *, soft_safe: bool = False) -> Rom:
+    """A seeded program that executes every byte of the 189-opcode set (a 2K
+    image holds a seeded 80 of them), in every addressing form, with indexed
+    accesses that cross pages for some envs and not for others, read-modify-
+    write on RAM, TIA and RIOT registers, all four timer intervals, TIMINT
+    reads, the JMP ($xxFF) page wrap, BRK/RTI, computed RTS/RTI jumps, code run
+    from RAM, pushes onto TIA registers and, for F8 images, bank switches on
+    every kind of data access (the code is the same in both banks, the data
+    tables differ)."""
+    assert size in (2048, 4096, 8192)
+    g = _SweepGen(seed, size, soft_safe)
+    ops = sorted(instruction_set())
+    if size == 2048:
+        sel = Rng(stream_key(seed, 0x32304B))
+        for i in range(len(ops) - 1, 0, -1):  # a seeded choice of 80 of them
+            j = sel.randint(0, i)
+            ops[i], ops[j] = ops[j], ops[i]
+        ops = sorted(ops[:80])
+    return g.build(ops)
+
+
+SWEEP_ROMS = ((4, 4096), (1, 4096), (0, 8192), (7, 8192), (1, 2048), (7, 2048))
+
+
+def config_sweep(envs_per_rom: int = 8, steps: int = 4, frame_skip: int = 2, episodes: bool = True) -> Workload:
+    """Parity workload over the opcode-sweep family: 4K, F8 and 2K sweep images,
+    random RAM and joystick inputs, short geometric-free episodes (1-3 steps)
+    for every other env so that in-run resets land mid-sweep."""
+    roms = [generate_sweep_rom(s, sz) for s, sz in SWEEP_ROMS]
+    b = len(roms) * envs_per_rom
+    env_rom = np.repeat(np.arange(len(roms), dtype=np.int32), envs_per_rom)
+    eps = None
+    if episodes:
+        lens = 1 + int_stream(stream_key(5, 0x455053), b * 8, 3).reshape(b, 8)
+        lens[::2] = 1 << 20  # every other env: one long episode
+        eps = lens.astype(np.uint32)
+    return Workload("sweep", roms, env_rom, initial_ram(5, b), action_stream(5, b, steps), steps=steps,
+                    frame_skip=frame_skip, episode_steps=eps, seed=5)

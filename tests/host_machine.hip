@@ -1,0 +1,134 @@
+// Test harness: the library's per-env machine core and kernel bodies built for
+// the host with a one-lane wave policy, so that CPU tests can compare them
+// with the oracle (no GPU involved).
+#include <cstring>
+#include <vector>
+#include "vcs_paths.hpp"
+
+using namespace vcs;
+
+namespace {
+struct OneLane {  // wave policy of a one-lane wave
+    static bool any(bool v) { return v; }
+    static bool all(bool v) { return v; }
+    static void opaque(uint32_t &) {}
+    static void opaque_uniform(uint32_t &) {}
+    static void accumulate(float *p, float t) { *p += t; }
+    static uint32_t first(uint32_t v) { return v; }
+    static uint32_t table(const uint32_t *t, uint32_t u) { return t[u]; }
+};
+constexpr DecodeTable kHostDecode = make_decode_table();
+}  // namespace
+
+// One env from power-on with RAM ram0 for S steps of F frames through the
+// GROUPED interpreter's body (plain = 0: ROM as pre-decoded words, RAM in the
+// word layout, wave-uniform dispatch) or the PLAIN kernel's body (plain = 1:
+// ROM and RAM in global memory, per-lane switch).  Outputs per step: RAM
+// [S][128], frame [S][210][160], done [S]; regs[16] = the inspection bytes
+// after the last step (vcs_read_regs layout).
+extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0,
+                           const uint8_t *actions, int S, int F, const uint32_t *ep_steps, int num_eps,
+                           unsigned long long seed, uint8_t *ram_out, uint8_t *frame_out, uint8_t *done,
+                           uint8_t *regs) {
+    StateRec st{};
+    st.status = 2;
+    st.tim_shift = 10;
+    std::memcpy(st.ram, ram0, 128);
+    StepParams P{};
+    P.state = &st;
+    P.actions = actions;
+    P.steps = S;
+    P.frame_skip = F;
+    P.ystart = 34;
+    P.frames_mode = 2;
+    P.ram_out = ram_out;
+    P.frame_out = frame_out;
+    P.done = done;
+    P.ep_steps = ep_steps;
+    P.num_episodes = num_eps;
+    P.seed = seed;
+    if (plain) {
+        GlobalMem m{rom, st.ram};
+        step_env<OneLane, 1, false, true>(P, 0, 0, mapper, m, kHostDecode.e);
+    } else {
+        std::vector<uint2> words(8192);
+        for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
+        std::vector<uint32_t> ram_lds(32, 0);
+        LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+        step_env<OneLane, 1, false, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    }
+    // inspection bytes, as vcs_read_regs forms them
+    const int32_t t = st.cyc, dd = t - st.tim_u;
+    regs[0] = st.a; regs[1] = st.x; regs[2] = st.y; regs[3] = st.s; regs[4] = st.p;
+    regs[5] = (uint8_t)(st.pc & 0xFF); regs[6] = (uint8_t)(st.pc >> 8); regs[7] = st.bank; regs[8] = st.status;
+    regs[9] = (uint8_t)(dd < 0 ? (-1 - (dd >> st.tim_shift)) : (255 - dd));
+    regs[10] = (uint8_t)((t >= st.tim_u && st.tim_read < st.tim_u) ? 0x80 : 0);
+    regs[11] = st.vblank;
+    for (int i = 0; i < 4; ++i) regs[12 + i] = (uint8_t)(st.col >> (8 * i));
+    return 0;
+}
+
+// SOFT-STE forward and the surrogate backward of one env on the host, through
+// the soft kernels' bodies: forward from power-on on the decoded leaves (rom:
+// decoded bytes, ram0, actions [S]) with a hard-state checkpoint every K
+// cycles, then the backward from dL/dframe [210][160] and dL/dRAM_out [S][128]
+// (NULL = zero).  Outputs: ram_out [S][128] and frame [210][160] as floats,
+// the per-byte ROM value gradient g_rom [rom_size], g_ram0 [128] and the port
+// gradients g_port [S][2] (SWCHA, INPT4), before the softmax epilogue.
+// Returns the number of checkpoints, or -1 if the tape overflowed.
+extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, const uint8_t *actions,
+                         int S, int F, int K, const float *grad_frame, const float *grad_ram, float *ram_out,
+                         float *frame_out, float *g_rom, float *g_ram0, float *g_port) {
+    std::vector<uint2> words(8192);
+    for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
+    const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 2);
+    std::vector<StateRec> ckpt((size_t)max_ckpt);
+    int32_t nck = 0;
+    {
+        StepParams P{};
+        P.rom = rom;
+        P.actions = actions;
+        P.steps = S;
+        P.frame_skip = F;
+        P.ystart = 34;
+        P.frames_mode = 1;
+        P.ram_out_f = ram_out;
+        P.frame_out_f = frame_out;
+        P.ram0 = ram0;
+        P.ckpt = ckpt.data();
+        P.ckpt_count = &nck;
+        P.ckpt_interval = K;
+        P.max_ckpt = max_ckpt;
+        std::vector<uint32_t> ram_lds(32, 0);
+        LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+        step_env<OneLane, 1, true, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    }
+    BwdParams Q{};
+    Q.rom = rom;
+    Q.ram0 = ram0;
+    Q.actions = actions;
+    Q.ckpt = ckpt.data();
+    Q.ckpt_count = &nck;
+    Q.max_ckpt = max_ckpt;
+    Q.steps = S;
+    Q.frame_skip = F;
+    Q.ystart = 34;
+    Q.ckpt_interval = K;
+    Q.grad_frame = grad_frame;
+    Q.grad_ram_out = grad_ram;
+    Q.max_rec = K / 2 + 64 + K / kCyclesPerFrame + 4;
+    std::vector<TapeRec> tape((size_t)Q.max_rec);
+    Q.tape = tape.data();
+    for (int i = 0; i < rom_size; ++i) g_rom[i] = 0.f;
+    for (int i = 0; i < 2 * S; ++i) g_port[i] = 0.f;
+    Q.gpart = g_rom;
+    Q.gport = g_port;
+    Q.g_ram0 = g_ram0;
+    int32_t overflow = 0;
+    Q.overflow = &overflow;
+    std::vector<uint32_t> ram_lds(32, 0);
+    std::vector<float> adj(128, 0.f);
+    LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+    bwd_env<OneLane>(Q, 0, 0, 1, mapper, m, adj.data(), 1, kHostDecode.e);
+    return overflow ? -1 : nck;
+}

@@ -1,0 +1,128 @@
+"""The opcode-sweep workload on the CPU: it reaches the whole instruction set,
+and the library's machine core built for the host (the interpreter of the
+GROUPED kernel and the PLAIN kernel's body) matches the oracle on it byte for
+byte."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_22447_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_2606_22447_amd", "csrc")
+
+
+def test_sweep_workload_covers_the_instruction_set():
+    """Every one of the 189 opcode bytes runs; every indexed-read/-write form runs
+    both with and without a page crossing; every branch is taken and not taken,
+    and taken across a page."""
+    w = I.config_sweep(episodes=False)
+    info = I.instruction_set()
+    cnt = np.zeros(256, np.uint64)
+    crs = np.zeros(256, np.uint64)
+    tk = np.zeros(256, np.uint64)
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        c, x, t = O.op_stats(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip)
+        cnt += c
+        crs += x
+        tk += t
+    seen = {op for op in range(256) if cnt[op]}
+    assert seen == set(info), sorted(hex(o) for o in set(info) ^ seen)
+    assert len(seen) == 189
+    for op, (mn, mode) in info.items():
+        if mode in ("abx", "aby", "izy"):
+            assert 0 < crs[op] < cnt[op], (hex(op), mn, mode, int(crs[op]), int(cnt[op]))
+        if mode == "rel":
+            assert 0 < tk[op] < cnt[op], (hex(op), mn)
+            assert crs[op] > 0, (hex(op), mn)
+    assert not any(O.op_stats(w.roms[int(w.env_rom[b])].image, w.roms[int(w.env_rom[b])].mapper, w.ram0[b],
+                              w.actions[b], 1, 1)[0][0x02] for b in range(0, w.num_envs, 7))  # no jam byte
+
+
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
+    so = tmp_path_factory.mktemp("host") / "libhost_machine.so"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC", "-shared",
+                           "-w", "-I", CSRC, os.path.join(HERE, "host_machine.hip"), "-o", str(so)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return C.CDLL(str(so))
+
+
+def _host_run(H, plain, rom, ram0, actions, S, F, ep, seed, env):
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    ram = np.zeros((S, 128), np.uint8)
+    fr = np.zeros((S, 210, 160), np.uint8)
+    dn = np.zeros(S, np.uint8)
+    regs = np.zeros(16, np.uint8)
+    # the env index only keys the reset RAM: pass it through the seed's stream as the oracle does
+    H.host_interp(plain, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper, ptr(np.ascontiguousarray(ram0)),
+                  ptr(np.ascontiguousarray(actions)), S, F, ptr(ep), 0 if ep is None else ep.size,
+                  C.c_ulonglong(seed), ptr(ram), ptr(fr), ptr(dn), ptr(regs))
+    return ram, fr, dn, regs
+
+
+@pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
+def test_host_core_matches_oracle_on_the_sweep(host_lib, plain):
+    w = I.config_sweep(envs_per_rom=3, steps=4, frame_skip=2, episodes=False)
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        ref = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, seed=w.seed,
+                        env_index=b)
+        ram, fr, dn, regs = _host_run(host_lib, plain, rom, w.ram0[b], w.actions[b], w.steps, w.frame_skip, None,
+                                      w.seed, b)
+        assert (ram == ref["ram"]).all(), (b, plain)
+        assert (fr == ref["frames"]).all(), (b, plain)
+        rr = ref["regs"]
+        want = [rr[k] for k in O.REG_NAMES[:16]]
+        assert regs.tolist() == want, (b, plain, regs.tolist(), want)
+
+
+def _close(g, ref, name):
+    m = np.abs(ref).max()
+    if m == 0:
+        assert (g == 0).all(), (name, np.abs(g).max())
+        return
+    err = np.abs(g.astype(np.float64) - ref)
+    assert err.max() <= 1e-4 * m, (name, err.max(), m)
+    big = np.abs(ref) >= 1e-3 * m
+    assert (err[big] / np.abs(ref[big])).max() <= 1e-4, name
+    assert (g[ref == 0] == 0).all(), name
+
+
+@pytest.mark.parametrize("K", [256, 4096])
+def test_host_soft_backward_matches_oracle_on_the_sweep(host_lib, K):
+    """The soft forward (= hard) and the surrogate backward of the library, built
+    for the host, against the FP64 oracle on every sweep image: raw gradients of
+    the ROM byte values, the initial RAM and the port reads."""
+    w = I.config_sweep(envs_per_rom=2, steps=2, frame_skip=1, episodes=False)
+    rng = np.random.default_rng(11)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    S = w.steps
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        gf = (rng.standard_normal((210, 160)) * 1e-3).astype(np.float32)
+        gr = (rng.standard_normal((S, 128)) * 1e-2).astype(np.float32)
+        sw = np.array([O.action_ports(int(a))[0] for a in w.actions[b]], np.float64)
+        inp = np.array([O.action_ports(int(a))[1] for a in w.actions[b]], np.float64)
+        ref = O.soft_env(rom.image, rom.image.astype(np.float64), rom.mapper, w.ram0[b],
+                         w.ram0[b].astype(np.float64), w.actions[b], sw, inp, S, 1, mode="ste",
+                         grad_frame=gf.astype(np.float64), grad_ram=gr.astype(np.float64))
+        ram = np.zeros((S, 128), np.float32)
+        fr = np.zeros((210, 160), np.float32)
+        g_rom = np.zeros(rom.size, np.float32)
+        g0 = np.zeros(128, np.float32)
+        gp = np.zeros((S, 2), np.float32)
+        n = host_lib.host_soft(ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                               ptr(np.ascontiguousarray(w.ram0[b])), ptr(np.ascontiguousarray(w.actions[b])), S, 1, K,
+                               ptr(gf), ptr(gr), ptr(ram), ptr(fr), ptr(g_rom), ptr(g0), ptr(gp))
+        assert n >= 0, "tape overflow"
+        assert (ram == ref["ram"]).all() and (fr == ref["frame"]).all(), b
+        _close(g_rom, ref["g_rom"], f"rom env {b}")
+        _close(g0, ref["g_ram0"], f"ram0 env {b}")
+        _close(gp[:, 0], ref["g_swcha"], f"swcha env {b}")
+        _close(gp[:, 1], ref["g_inpt4"], f"inpt4 env {b}")

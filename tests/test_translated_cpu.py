@@ -108,10 +108,11 @@ def playfield_modes_workload(B: int = 3, S: int = 3) -> I.Workload:
                       np.zeros((B, S), np.uint8), S, 2, seed=8)
 
 
-@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes", "playfield_modes"])
+@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes", "playfield_modes", "sweep"])
 def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
     w = {"c1": lambda: I.config_c1(num_envs=6, steps=6), "hetero": _hetero, "tia_pushes": tia_pushes_workload,
-         "playfield_modes": playfield_modes_workload}[name]()
+         "playfield_modes": playfield_modes_workload,
+         "sweep": lambda: I.config_sweep(envs_per_rom=2, steps=3, frame_skip=2)}[name]()
     h = _ctx(w)
     src = Bd.translated_source(h, np.concatenate([r.image for r in w.roms]))
     gen = tmp_path / "translated.hip"
