@@ -1301,11 +1301,18 @@ void orc_epilogue_action(const float *logits, int64_t n, double tau, const doubl
 /* ------------------------------------------------------------------------ */
 /* Soft rollout of one env (SOFT-STE forward = hard; surrogate backward)      */
 /* ------------------------------------------------------------------------ */
-int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, int mapper, const uint8_t *ram0_hard,
-                 const double *ram0_ev, const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev,
-                 int steps, int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
-                 uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
-                 double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
+/* The soft rollout may start mid-episode: the machine first takes pre_steps
+ * HARD env steps from power-on (actions pre_actions, no graph), and the soft
+ * steps continue from that state (the paper's env step, state + action -> next
+ * state).  The registers and RAM of that state are then constants of the
+ * graph (no RAM0 leaves: g_ram0 is 0) and the soft steps' frames keep their
+ * place on the frame grid. */
+int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_size, int mapper,
+                      const uint8_t *ram0_hard, const double *ram0_ev, int pre_steps, const uint8_t *pre_actions,
+                      const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev, int steps,
+                      int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
+                      uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
+                      double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
     Graph *g = (Graph *)calloc(1, sizeof(Graph));
     g->rom_size = rom_size;
     g->rom_hard = rom_hard;
@@ -1323,21 +1330,24 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
     g->ramout_node = (int32_t *)malloc(sizeof(int32_t) * (size_t)steps * 128);
     g->slot_a = g->slot_x = g->slot_y = -1; /* power-on registers are constants */
     for (int i = 0; i < 4; i++) g->slot_col[i] = -1;
-    for (int c = 0; c < 128; c++) g->slot_ram[c] = g->ram0_leaf[c] = g_new(g, -1, 0, 0, -1, 0, 0, ram0_ev[c], ram0_hard[c]);
+    for (int c = 0; c < 128; c++)
+        g->slot_ram[c] = g->ram0_leaf[c] =
+            pre_steps > 0 ? -1 : g_new(g, -1, 0, 0, -1, 0, 0, ram0_ev[c], ram0_hard[c]);
     for (int s = 0; s < steps; s++) {
         g->swcha_leaf[s] = g_new(g, -1, 0, 0, -1, 0, 0, swcha_ev[s], orc_action_swcha(act_hard[s]));
         g->inpt4_leaf[s] = g_new(g, -1, 0, 0, -1, 0, 0, inpt4_ev[s], orc_action_inpt4(act_hard[s]));
     }
 
     Orc *m = orc_new();
-    m->g = g;
     if (orc_power_on(m, rom_hard, rom_size, mapper, ram0_hard, ystart)) {
         orc_free(m);
         return -1;
     }
+    for (int s = 0; s < pre_steps; s++) orc_env_step(m, pre_actions ? pre_actions[s] : 0, frame_skip, s, 0);
+    m->g = g;
     for (int s = 0; s < steps; s++) {
         m->step = s;
-        orc_env_step(m, act_hard[s], frame_skip, s, s == steps - 1);
+        orc_env_step(m, act_hard[s], frame_skip, pre_steps + s, s == steps - 1);
         for (int c = 0; c < 128; c++) {
             g->ramout_node[s * 128 + c] = g->slot_ram[c];
             if (ram_out) ram_out[s * 128 + c] = m->ram[c];
@@ -1366,7 +1376,7 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
     }
     for (int a = 0; a < rom_size; a++)
         if (g->rom_leaf[a] >= 0) g_rom[a] += adj[g->rom_leaf[a]];
-    for (int c = 0; c < 128; c++) g_ram0[c] = adj[g->ram0_leaf[c]];
+    for (int c = 0; c < 128; c++) g_ram0[c] = g->ram0_leaf[c] >= 0 ? adj[g->ram0_leaf[c]] : 0.0;
     for (int s = 0; s < steps; s++) {
         g_swcha[s] = adj[g->swcha_leaf[s]];
         g_inpt4[s] = adj[g->inpt4_leaf[s]];
@@ -1383,4 +1393,14 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
     free(g->ramout_node);
     free(g);
     return 0;
+}
+
+int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, int mapper, const uint8_t *ram0_hard,
+                 const double *ram0_ev, const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev,
+                 int steps, int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
+                 uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
+                 double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
+    return orc_soft_env_from(rom_hard, rom_ev, rom_size, mapper, ram0_hard, ram0_ev, 0, NULL, act_hard, swcha_ev,
+                             inpt4_ev, steps, frame_skip, ystart, mode, grad_frame, grad_ram, ram_out, frame_out,
+                             ram_smooth, frame_smooth, g_rom, g_ram0, g_swcha, g_inpt4, n_nodes);
 }

@@ -346,3 +346,75 @@ def test_finite_differences_on_action_logits():
     fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
     assert fd == pytest.approx(gA[s, j], rel=2e-5)
     assert math.isfinite(fd)
+
+
+# --------------------------------------------------------------------------
+# soft steps continuing a hard rollout (state + action -> next state)
+# --------------------------------------------------------------------------
+
+def _mid_problem(tau, pre=3, n_steps=2, rom_seed=104, size=4096):
+    rom, L, tape, al, _ = _c3_problem(tau, n_steps=n_steps, rom_seed=rom_seed, size=size, inputs=True)
+    ram0 = O.decode_tape(tape)[0]
+    pre_acts = I.action_stream(77, 1, pre)[0]
+    acts = O.decode_actions(al, tau)[0]
+    full = np.concatenate([pre_acts, acts])
+    pert = I.perturb_rom(rom, 3)
+    tgt = O.run_env(pert, rom.mapper, ram0, full, pre + n_steps, 1, frames="last")["frames"][0]
+    return rom, L, tape, al, tgt, pre_acts
+
+
+def _mid_run(rom, L, tape, al, tau, pre_acts, n_steps, mode, gf=None):
+    hard_rom, ev, _, _ = O.decode_logits(L, tau)
+    hard_ram, ev0 = O.decode_tape(tape)
+    hard_act, es, ei = O.decode_actions(al, tau)
+    return O.soft_env(hard_rom, ev, rom.mapper, hard_ram, ev0, hard_act, es, ei, n_steps, 1, mode=mode,
+                      grad_frame=gf, pre_actions=pre_acts)
+
+
+def test_soft_steps_from_a_hard_state_equal_the_hard_rollout():
+    tau = 1.0
+    rom, L, tape, al, tgt, pre = _mid_problem(tau)
+    r = _mid_run(rom, L, tape, al, tau, pre, 2, "ste")
+    ram0 = O.decode_tape(tape)[0]
+    full = np.concatenate([pre, O.decode_actions(al, tau)[0]])
+    hard = O.run_env(rom.image, rom.mapper, ram0, full, len(full), 1, frames="last")
+    assert (r["ram"] == hard["ram"][len(pre):]).all() and (r["frame"] == hard["frames"][0]).all()
+    assert (r["frame_smooth"] != r["frame"]).any()
+    # without pre-steps the function is the power-on rollout
+    r0 = _mid_run(rom, L, tape, al, tau, np.zeros(0, np.uint8), 2, "ste")
+    ref = O.soft_env(*[x for x in (O.decode_logits(L, tau)[0], O.decode_logits(L, tau)[1])], rom.mapper,
+                     O.decode_tape(tape)[0], O.decode_tape(tape)[1], *O.decode_actions(al, tau), 2, 1)
+    assert (r0["ram"] == ref["ram"]).all() and np.array_equal(r0["frame_smooth"], ref["frame_smooth"])
+
+
+def test_soft_steps_from_a_hard_state_gradients():
+    """The initial RAM of a mid-episode start is a constant (zero tape gradient);
+    ROM and action-logit gradients of the SMOOTH relaxation match central
+    finite differences."""
+    tau = 1.0
+    rom, L, tape, al, tgt, pre = _mid_problem(tau)
+    fwd = _mid_run(rom, L, tape, al, tau, pre, 2, "smooth")
+    _, gf = loss_and_grad(fwd["frame"], fwd["frame_smooth"], tgt)
+    r = _mid_run(rom, L, tape, al, tau, pre, 2, "smooth", gf)
+    assert (r["g_ram0"] == 0).all()
+    gL = O.epilogue_rom(L, tau, r["g_rom"])
+    assert np.abs(r["g_rom"]).max() > 0
+
+    def loss(Lx, Ax):
+        f = _mid_run(rom, Lx, tape, Ax, tau, pre, 2, "smooth")
+        return loss_and_grad(f["frame"], f["frame_smooth"], tgt)[0]
+
+    checked = 0
+    for a in np.argsort(-np.abs(r["g_rom"]))[:3]:
+        for k in (int(L[a].argmax()), int(np.argsort(-L[a])[1])):
+            vals = []
+            for sgn in (1, -1):
+                Lx = L.copy()
+                Lx[a, k] = np.float32(L[a, k] + sgn * 1e-3)
+                vals.append((loss(Lx, al), float(Lx[a, k]) - float(L[a, k])))
+            fd = (vals[0][0] - vals[1][0]) / (vals[0][1] - vals[1][1])
+            if abs(fd) < 1e-9 and abs(gL[a, k]) < 1e-9:
+                continue
+            assert fd == pytest.approx(gL[a, k], rel=2e-5, abs=1e-10), (a, k)
+            checked += 1
+    assert checked >= 2
