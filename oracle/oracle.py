@@ -53,6 +53,13 @@ def lib():
         L.orc_frame.restype = C.POINTER(C.c_uint8)
         L.orc_poke_ram.argtypes = [vp, C.c_int, C.c_int]
         L.orc_op_stats.argtypes = [vp, u64p]
+        L.orc_set_relax.argtypes = [vp, C.c_int, C.c_double, C.c_double]
+        L.orc_relax_ndiv.argtypes = [vp]
+        L.orc_relax_ndiv.restype = C.c_int64
+        L.orc_relax_fails.argtypes = [vp]
+        L.orc_relax_fails.restype = C.c_uint64
+        L.orc_relax_last_dev.argtypes = [vp, f64p]
+        L.orc_dispatch_deviation.argtypes = [vp, f64p, C.c_double] + [C.POINTER(C.c_double)] * 3
         L.orc_intim_at.argtypes = [vp, C.c_int64]
         L.orc_timint_at.argtypes = [vp, C.c_int64]
         L.orc_opcode_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4
@@ -141,6 +148,31 @@ class Machine:
         out = np.zeros(768, np.uint64)
         self.L.orc_op_stats(self.h, out)
         return out[:256], out[256:512], out[512:]
+
+    def set_relax(self, alpha: float, T: float, on: bool = True, track: bool = False):
+        """FULL relaxed mode: sigmoid branches and distance-softmax reads cast to integers
+        (track: also record each instruction's float64 pre-cast deviations)."""
+        self.L.orc_set_relax(self.h, int(on) | (2 if track else 0), float(alpha), float(T))
+
+    def relax_ndiv(self) -> int:
+        return int(self.L.orc_relax_ndiv(self.h))
+
+    def relax_fails(self) -> int:
+        return int(self.L.orc_relax_fails(self.h))
+
+    def relax_last_dev(self):
+        """(summed read deviation, number of relaxed reads, branch deviation) of the last
+        instruction, float64 before the casts."""
+        out = np.zeros(3)
+        self.L.orc_relax_last_dev(self.h, out)
+        return float(out[0]), int(out[1]), float(out[2])
+
+    def dispatch_deviation(self, logits: np.ndarray, T: float):
+        """(dev, spread, w_star) of the relaxed dispatch of the next instruction."""
+        d, sp, ws = C.c_double(), C.c_double(), C.c_double()
+        self.L.orc_dispatch_deviation(self.h, np.ascontiguousarray(logits, np.float64), float(T), C.byref(d),
+                                      C.byref(sp), C.byref(ws))
+        return d.value, sp.value, ws.value
 
     def intim_at(self, t: int) -> int:
         return self.L.orc_intim_at(self.h, t)
@@ -231,6 +263,25 @@ def op_stats(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int
     for s in range(steps):
         m.env_step(0 if actions is None else int(actions[s]), frame_skip, s, store_frame=False)
     return m.op_stats()
+
+
+def run_relaxed(rom: np.ndarray, mapper: int, ram0: np.ndarray, actions, steps: int, frame_skip: int,
+                alpha: float, T: float, frames: str = "all"):
+    """FULL relaxed rollout of one env from power-on (no episodes): RAM [S][128]
+    and frames after each step, the first diverging instruction (-1: none) and the
+    number of casts that differed."""
+    m = Machine(rom, mapper, ram0)
+    m.set_relax(alpha, T)
+    ram = np.zeros((steps, 128), np.uint8)
+    fr = np.zeros((steps if frames == "all" else 1, 210, 160), np.uint8)
+    for s in range(steps):
+        store = frames == "all" or (frames == "last" and s == steps - 1)
+        m.env_step(0 if actions is None else int(actions[s]), frame_skip, s, store_frame=store)
+        ram[s] = m.ram()
+        if store:
+            fr[s if frames == "all" else 0] = m.frame()
+    return {"ram": ram, "frames": fr, "ndiv": m.relax_ndiv(), "fails": m.relax_fails(),
+            "regs": m.regs()}
 
 
 def decode_logits(rows: np.ndarray, tau: float):

@@ -337,6 +337,34 @@ static int32_t g_logic(Graph *g, int kind, int32_t pa, int ha, int32_t pb, int h
 }
 
 /* ------------------------------------------------------------------------ */
+/* FULL relaxed mode (Table s-modes): the sigmoid branch of Eq. s-branch and  */
+/* the distance-softmax read of Eq. s-read WITHOUT the straight-through      */
+/* correction, each result cast back to an integer (Sec. "Forward            */
+/* Bit-Exactness Under Full Relaxation").  Dispatch stays saturated in the    */
+/* rollouts: the cast-margin model of that section has branch and read casts  */
+/* only; the relaxed dispatch of Eq. s-select is evaluated by the one-step    */
+/* deviation function below (Theorem "Temperature-limit bound").             */
+/* Precision: float32 as the paper's soft mode; weights e^{-|k|/T} are       */
+/* formed in double and stored as float; reads blend the neighbours          */
+/* |k| <= RELAX_WINDOW inside the memory array (ROM image or the 128 RAM      */
+/* cells), normalised over those; casts round to nearest, ties to even.      */
+/* ------------------------------------------------------------------------ */
+enum { RELAX_WINDOW = 8 };
+typedef struct {
+    int on;
+    float u[RELAX_WINDOW + 1];   /* u[k] = e^{-k/T} (u[0] = 1) */
+    float g_taken, g_not;        /* sigma(alpha), sigma(-alpha): the gate for z = +1 / -1 */
+    int64_t ndiv;                /* first instruction whose cast differed from the exact value (-1: none) */
+    uint64_t fails;              /* casts that differed */
+    double T, alpha;
+    /* the last instruction's pre-cast deviations in float64, each read blended over
+     * its whole memory array (Theorem "Temperature-limit bound"): the sum over its
+     * reads, their number, and the branch's */
+    double dev_read, dev_branch;
+    int nread, track;
+} Relax;
+
+/* ------------------------------------------------------------------------ */
 /* Machine                                                                  */
 /* ------------------------------------------------------------------------ */
 struct Orc {
@@ -370,6 +398,9 @@ struct Orc {
     /* soft */
     Graph *g;
     int step;
+    /* FULL relaxed mode (kept across power-on) */
+    Relax rx;
+    int rx_active;     /* an instruction is executing: its reads and branch are relaxed */
 };
 
 Orc *orc_new(void) {
@@ -513,12 +544,55 @@ static void riot_write(Orc *m, uint16_t addr, uint8_t v, int64_t w) {
 
 /* ---- bus ------------------------------------------------------------------ */
 
+static void relax_note(Orc *m) {
+    if (m->rx.ndiv < 0) m->rx.ndiv = (int64_t)m->instructions;
+    m->rx.fails++;
+}
+
+/* Eq. s-read on the memory array r[0..n) at index a, cast to a byte. */
+static uint8_t relaxed_read(Orc *m, const uint8_t *r, int n, int a) {
+    if (m->rx.track) { /* float64 deviation of the read over the whole array, before the cast */
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < n; i++) {
+            const double w = exp(-fabs((double)(i - a)) / m->rx.T);
+            num += w * (double)r[i];
+            den += w;
+        }
+        m->rx.dev_read += fabs(num / den - (double)r[a]);
+        m->rx.nread++;
+    }
+    const float ra = (float)r[a];
+    float num = 0.0f, den = 1.0f;
+    for (int k = 1; k <= RELAX_WINDOW; k++) {
+        const float u = m->rx.u[k];
+        if (a + k < n) {
+            num = num + u * ((float)r[a + k] - ra);
+            den = den + u;
+        }
+        if (a - k >= 0) {
+            num = num + u * ((float)r[a - k] - ra);
+            den = den + u;
+        }
+    }
+    const int v = (int)rintf(ra + num / den);
+    if (v != r[a]) relax_note(m);
+    return (uint8_t)v;
+}
+
+static uint8_t rom_value(Orc *m, int off) {
+    return (m->rx.on && m->rx_active) ? relaxed_read(m, m->rom, m->rom_size, off) : m->rom[off];
+}
+
+static uint8_t ram_value(Orc *m, int cell) {
+    return (m->rx.on && m->rx_active) ? relaxed_read(m, m->ram, 128, cell) : m->ram[cell];
+}
+
 /* Fetch-type read: no side effects (opcode/operand fetches, pointers, NOP reads). */
 static uint8_t bus_peek(Orc *m, uint16_t addr, int64_t t) {
     addr &= 0x1FFF;
-    if (addr & 0x1000) return m->rom[cart_offset(m, addr)];
+    if (addr & 0x1000) return rom_value(m, cart_offset(m, addr));
     if (!(addr & 0x80)) return tia_read(m, addr);
-    if (!(addr & 0x200)) return m->ram[addr & 0x7F];
+    if (!(addr & 0x200)) return ram_value(m, addr & 0x7F);
     return riot_read(m, addr, t, 0);
 }
 
@@ -534,10 +608,10 @@ static uint8_t bus_read(Orc *m, uint16_t addr, int64_t t) {
     addr &= 0x1FFF;
     if (addr & 0x1000) {
         hotspot(m, addr);
-        return m->rom[cart_offset(m, addr)];
+        return rom_value(m, cart_offset(m, addr));
     }
     if (!(addr & 0x80)) return tia_read(m, addr);
-    if (!(addr & 0x200)) return m->ram[addr & 0x7F];
+    if (!(addr & 0x200)) return ram_value(m, addr & 0x7F);
     return riot_read(m, addr, t, 1);
 }
 
@@ -690,8 +764,10 @@ static uint8_t pull(Orc *m, int64_t t, int32_t *node) {
 int orc_power_on(Orc *m, const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int ystart) {
     ops_init();
     Graph *g = m->g;
+    Relax rx = m->rx;
     memset(m, 0, sizeof *m);
     m->g = g;
+    m->rx = rx;
     if (ystart < 0 || ystart + SCREEN_H > LINES_PER_FRAME) return -1;
     if (!((mapper == ORC_MAPPER_2K && rom_size == 2048) || (mapper == ORC_MAPPER_4K && rom_size == 4096) ||
           (mapper == ORC_MAPPER_F8 && rom_size == 8192)))
@@ -749,10 +825,14 @@ int orc_step_instruction(Orc *m) {
     Graph *g = m->g;
     const int64_t t0 = m->cycle;
     const uint16_t pc = m->pc;
+    m->rx_active = 1;
+    m->rx.dev_read = m->rx.dev_branch = 0.0;
+    m->rx.nread = 0;
     const uint8_t opc = bus_peek(m, pc, t0);
     const OpRow info = OPS[opc];
     if (info.op == JAM) {
         m->jammed = 1;
+        m->rx_active = 0;
         return 1;
     }
     const uint16_t a1 = (uint16_t)(pc + 1);
@@ -1040,7 +1120,24 @@ int orc_step_instruction(Orc *m) {
         case BCS:
         case BNE:
         case BEQ: {
-            if (branch_taken(m, op)) {
+            const int taken = branch_taken(m, op);
+            if (m->rx.on) {
+                /* Eq. s-branch without STE: the flag is crisp, so z = +1 (taken) or -1 and
+                 * pc = round(pc_fallthrough + sigma(alpha z) * delta); the cycle penalties
+                 * follow the flag and the page of the pc reached */
+                const double gd = 1.0 / (1.0 + exp(-m->rx.alpha * (taken ? 1.0 : -1.0)));
+                m->rx.dev_branch = fabs(gd * (double)(int8_t)lo - (taken ? (double)(int8_t)lo : 0.0));
+                const float gz = taken ? m->rx.g_taken : m->rx.g_not;
+                const uint16_t cast = (uint16_t)(int)rintf((float)m->pc + gz * (float)(int8_t)lo);
+                const uint16_t hard = taken ? (uint16_t)(m->pc + (int8_t)lo) : m->pc;
+                if (cast != hard) relax_note(m);
+                if (taken) {
+                    crossed = (cast & 0xFF00) != (m->pc & 0xFF00);
+                    n += 1 + crossed;
+                    m->op_taken[opc]++;
+                }
+                m->pc = cast;
+            } else if (taken) {
                 uint16_t target = (uint16_t)(m->pc + (int8_t)lo);
                 crossed = (target & 0xFF00) != (m->pc & 0xFF00);
                 n += 1 + crossed;
@@ -1052,6 +1149,7 @@ int orc_step_instruction(Orc *m) {
         default: break;
     }
 #undef LOAD_OPERAND
+    m->rx_active = 0;
     m->cycle = t0 + n;
     if (m->wsync) { /* R6 */
         m->wsync = 0;
@@ -1121,6 +1219,91 @@ void orc_get_regs(const Orc *m, int64_t *out) {
     out[21] = m->cycle;
     out[22] = (int64_t)m->instructions;
 }
+
+/* FULL relaxed mode on (bit 0 of on; bit 1: also record the float64 pre-cast
+ * deviations) at (alpha, T), or off; resets the divergence record. */
+void orc_set_relax(Orc *m, int on, double alpha, double T) {
+    m->rx.on = on & 1;
+    m->rx.track = (on >> 1) & 1;
+    m->rx.u[0] = 1.0f;
+    for (int k = 1; k <= RELAX_WINDOW; k++) m->rx.u[k] = (float)exp(-(double)k / T);
+    m->rx.g_taken = (float)(1.0 / (1.0 + exp(-alpha)));
+    m->rx.g_not = (float)(1.0 / (1.0 + exp(alpha)));
+    m->rx.ndiv = -1;
+    m->rx.fails = 0;
+    m->rx.T = T;
+    m->rx.alpha = alpha;
+}
+
+/* The last instruction's float64 pre-cast deviations: out[0] = summed read
+ * deviation, out[1] = number of relaxed reads, out[2] = branch deviation. */
+void orc_relax_last_dev(const Orc *m, double *out) {
+    out[0] = m->rx.dev_read;
+    out[1] = m->rx.nread;
+    out[2] = m->rx.dev_branch;
+}
+
+/* State vector of Theorem "Temperature-limit bound" (registers, RAM, RIOT, TIA,
+ * frame buffer, time); returns its length. */
+static int state_vector(const Orc *m, double *v) {
+    int n = 0;
+    v[n++] = m->a; v[n++] = m->x; v[n++] = m->y; v[n++] = m->s; v[n++] = m->p; v[n++] = m->pc;
+    v[n++] = m->bank; v[n++] = m->jammed; v[n++] = (double)m->cycle;
+    v[n++] = (double)m->tim_write; v[n++] = m->tim_value; v[n++] = m->tim_interval; v[n++] = (double)m->tim_read;
+    v[n++] = m->vsync; v[n++] = m->vblank; v[n++] = m->colup0; v[n++] = m->colup1; v[n++] = m->colupf;
+    v[n++] = m->colubk; v[n++] = m->ctrlpf; v[n++] = m->pf0; v[n++] = m->pf1; v[n++] = m->pf2;
+    for (int i = 0; i < 128; i++) v[n++] = m->ram[i];
+    for (int i = 0; i < SCREEN_H * SCREEN_W; i++) v[n++] = m->frame[i];
+    return n;
+}
+
+/* Relaxed dispatch of Eq. s-select for the instruction at the machine's pc:
+ * every handler k = 0..255 runs (hard) from the current state on a copy whose
+ * opcode byte is k, giving the state vector V_k; with w = softmax(logits/T),
+ * dev = max_i |sum_k w_k V_k[i] - V_k*[i]| for the argmax k*, spread =
+ * max_k max_i |V_k[i] - V_k*[i]| and w_star = w_k*.  The machine is not
+ * changed. */
+void orc_dispatch_deviation(const Orc *m, const double *logits, double T, double *dev, double *spread,
+                            double *w_star) {
+    enum { NV = 23 + 128 + SCREEN_H * SCREEN_W };
+    double *V = (double *)malloc(sizeof(double) * 256 * NV);
+    Orc *c = (Orc *)malloc(sizeof(Orc));
+    const int off = cart_offset(m, m->pc);
+    int best = 0;
+    for (int k = 0; k < 256; k++) {
+        *c = *m;
+        c->g = NULL;
+        c->rx.on = 0;
+        if (m->pc & 0x1000) c->rom[off] = (uint8_t)k;
+        orc_step_instruction(c);
+        state_vector(c, V + (size_t)k * NV);
+        if (logits[k] > logits[best]) best = k;
+    }
+    double w[256], z = 0.0;
+    for (int k = 0; k < 256; k++) z += (w[k] = exp((logits[k] - logits[best]) / T));
+    for (int k = 0; k < 256; k++) w[k] /= z;
+    double d = 0.0, sp = 0.0;
+    const double *vs = V + (size_t)best * NV;
+    for (int i = 0; i < NV; i++) {
+        double acc = 0.0;
+        for (int k = 0; k < 256; k++) {
+            acc += w[k] * V[(size_t)k * NV + i];
+            const double e = fabs(V[(size_t)k * NV + i] - vs[i]);
+            if (e > sp) sp = e;
+        }
+        if (fabs(acc - vs[i]) > d) d = fabs(acc - vs[i]);
+    }
+    *dev = d;
+    *spread = sp;
+    *w_star = w[best];
+    free(V);
+    free(c);
+}
+
+/* First instruction (counted from power-on) whose cast differed from the exact
+ * value, or -1; and the number of such casts. */
+int64_t orc_relax_ndiv(const Orc *m) { return m->rx.ndiv; }
+uint64_t orc_relax_fails(const Orc *m) { return m->rx.fails; }
 
 /* Opcode statistics since power-on: out[0..255] executions per opcode byte,
  * out[256..511] of them with a page crossing (indexed address or taken branch),

@@ -21,6 +21,12 @@ void orc_set_draw_frame(Orc *m, int64_t frame);
 void orc_env_step(Orc *m, int action, int frame_skip, int64_t step_index, int store_frame);
 void orc_get_regs(const Orc *m, int64_t *out);
 void orc_op_stats(const Orc *m, uint64_t *out);
+void orc_set_relax(Orc *m, int on, double alpha, double T);
+int64_t orc_relax_ndiv(const Orc *m);
+uint64_t orc_relax_fails(const Orc *m);
+void orc_relax_last_dev(const Orc *m, double *out);
+void orc_dispatch_deviation(const Orc *m, const double *logits, double T, double *dev, double *spread,
+                            double *w_star);
 const uint8_t *orc_ram(const Orc *m);
 const uint8_t *orc_frame(const Orc *m);
 void orc_poke_ram(Orc *m, int cell, int v);
