@@ -153,6 +153,26 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
                       uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
                       const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream);
 
+/* vcs_step_hard for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same arguments without d_work.  The launch tables go to a static device
+ * array of the library (1 MiB on each device it runs on, held until the
+ * process ends) instead of a caller workspace, and the call allocates
+ * nothing: no device, host or pinned memory.
+ *  - The context's tables must fit: VCS_WORKSPACE_TOO_SMALL when
+ *    vcs_workspace_bytes(VCS_OP_HARD) exceeds 1 MiB (about 80,000 envs).
+ *  - The context must have made its pinned host copy of the tables (vcs_reset
+ *    does; so does an earlier vcs_step_hard): VCS_UNSUPPORTED otherwise.
+ *  - All calls on one device share the array, and each call rewrites the
+ *    whole of what it uses (nothing in it needs to start at zero): calls whose
+ *    stream work overlaps on one device (different streams, no ordering
+ *    between them) race on it and must not be issued.
+ * Everything else, including results, is as for vcs_step_hard. */
+int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions,
+                             int32_t steps, uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out,
+                             uint8_t *d_done, const uint32_t *d_episode_steps, int32_t num_episodes,
+                             hipStream_t stream);
+
 /* SOFT-STE forward of S env steps from power-on (Theorem "Exact forward
  * equivalence": its values equal HARD at any tau and alpha).
  *  d_rom_logits    float32 [sum rom_size][256]: ROM as a weight tensor; byte a

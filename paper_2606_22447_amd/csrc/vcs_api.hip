@@ -2,6 +2,7 @@
 // geometry and the layout of caller-owned device buffers.
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -145,6 +146,32 @@ int32_t upload_static(vcs_ctx *c, void *d_work, hipStream_t stream) {
 }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? VCS_OK : VCS_HIP_ERROR; }
+
+// Launch tables of vcs_step_hard_static: a fixed device array, so that the
+// entry point needs no caller workspace and allocates nothing.  Every device
+// the library runs on holds its own copy until the process ends; host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device (the array's name is not a device address in host code).
+constexpr size_t kScratchBytes = size_t(1) << 20;
+__device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int32_t scratch_on_current_device(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return VCS_HIP_ERROR;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return VCS_HIP_ERROR;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return VCS_OK;
+}
 
 // Envs of every ROM packed into blocks of `per` slots that never mix ROMs.
 void group_by_rom(const vcs_ctx *c, int32_t per, std::vector<int32_t> &block_rom, std::vector<int32_t> &slot_env) {
@@ -374,20 +401,30 @@ int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint
     return hip_status(launch_reset((StateRec *)d_state, ctx->B, d_mask, d_ram0, ctx->seed, stream));
 }
 
-int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
-                      uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
-                      const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream) {
-    if (!ctx || !d_rom || !d_state || !d_work || steps < 1) return VCS_INVALID_ARG;
-    if (!aligned16(d_rom) || !aligned16(d_state) || !aligned16(d_work)) return VCS_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+int32_t check_step_hard_args(const vcs_ctx *ctx, const uint8_t *d_rom, const void *d_state, int32_t steps,
+                             const uint8_t *d_ram_out, int32_t frames, const uint8_t *d_frame_out,
+                             const uint32_t *d_episode_steps, int32_t num_episodes) {
+    if (!ctx || !d_rom || !d_state || steps < 1) return VCS_INVALID_ARG;
+    if (!aligned16(d_rom) || !aligned16(d_state)) return VCS_INVALID_ARG;
     if (frames < VCS_FRAMES_NONE || frames > VCS_FRAMES_ALL) return VCS_INVALID_ARG;
     if (frames != VCS_FRAMES_NONE && (!d_frame_out || !aligned16(d_frame_out))) return VCS_INVALID_ARG;
     if (d_ram_out && ((uintptr_t)d_ram_out & 3u)) return VCS_INVALID_ARG;
     if (d_episode_steps && num_episodes < 1) return VCS_INVALID_ARG;
     if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
-    const int32_t rc = upload_static(ctx, d_work, stream);
-    if (rc) return rc;
+    return VCS_OK;
+}
+
+// The hard step's launch: the launch tables are already (in stream order) at d_tables.
+int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                         uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
+                         const uint32_t *d_episode_steps, int32_t num_episodes, const void *d_tables,
+                         hipStream_t stream) {
     StepParams P{};
-    P.st = static_ptrs(ctx, d_work);
+    P.st = static_ptrs(ctx, d_tables);
     P.rom = d_rom;
     P.state = (StateRec *)d_state;
     P.actions = d_actions;
@@ -411,6 +448,44 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
     }
     return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
                                   ctx->max_rom, stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                      uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
+                      const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream) {
+    int32_t rc = check_step_hard_args(ctx, d_rom, d_state, steps, d_ram_out, frames, d_frame_out, d_episode_steps,
+                                      num_episodes);
+    if (rc) return rc;
+    if (!d_work || !aligned16(d_work)) return VCS_INVALID_ARG;
+    rc = upload_static(ctx, d_work, stream);
+    if (rc) return rc;
+    return launch_step_hard(ctx, d_rom, d_state, d_actions, steps, d_ram_out, frames, d_frame_out, d_done,
+                            d_episode_steps, num_episodes, d_work, stream);
+}
+
+// vcs_step_hard with the launch tables in the library's static device array
+// instead of a caller workspace; no allocation of any kind.  The context's
+// pinned host copy of the tables must exist already (vcs_reset makes it).
+int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions,
+                             int32_t steps, uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out,
+                             uint8_t *d_done, const uint32_t *d_episode_steps, int32_t num_episodes,
+                             hipStream_t stream) {
+    int32_t rc = check_step_hard_args(ctx, d_rom, d_state, steps, d_ram_out, frames, d_frame_out, d_episode_steps,
+                                      num_episodes);
+    if (rc) return rc;
+    if (ctx->blob_bytes > kScratchBytes) return VCS_WORKSPACE_TOO_SMALL;
+    if (!ctx->pinned) return VCS_UNSUPPORTED;  // making it would allocate: vcs_reset first
+    void *tables = nullptr;
+    rc = scratch_on_current_device(&tables);
+    if (rc) return rc;
+    if (hipMemcpyAsync(tables, ctx->pinned, ctx->blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return VCS_HIP_ERROR;
+    return launch_step_hard(ctx, d_rom, d_state, d_actions, steps, d_ram_out, frames, d_frame_out, d_done,
+                            d_episode_steps, num_episodes, tables, stream);
 }
 
 int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, char *buf,
