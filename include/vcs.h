@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define VCS_ABI_VERSION 1
+#define VCS_ABI_VERSION 2  /* 2: vcs_step_soft_fwd takes a starting state */
 
 typedef enum vcs_status {
     VCS_OK = 0,
@@ -119,8 +119,12 @@ int32_t vcs_workspace_bytes(const vcs_ctx *ctx, int32_t op, int32_t steps, size_
 int32_t vcs_residual_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes);
 int32_t vcs_decode_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes);
 
-/* Power-on reset of the envs selected by d_mask (uint8 [B], nonzero = reset;
- * NULL = all).  RAM comes from d_ram0 (uint8 [B][128], 4-byte aligned) when
+/* Power-on of the envs selected by d_mask (uint8 [B], nonzero = reset; NULL =
+ * all): the console and environment wrapper the paper ports (Sec. "Building
+ * Two Differentiable VCS Ports") start an episode from a powered-on machine;
+ * the ALE boot sequence of Sec. "Evaluation Methodology" (no-op frames and
+ * console resets) is not applied here: the caller's steps follow directly.
+ * RAM comes from d_ram0 (uint8 [B][128], 4-byte aligned) when
  * given, otherwise from SplitMix64(seed, env, 0).  CPU: A=X=Y=0, S=$FD, P=$24,
  * TIA registers 0, RIOT timer as if written with 0 at cycle -1 with interval
  * 1024 and its flag clear, episode and step counters 0.  The PC is loaded from
@@ -173,8 +177,15 @@ int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, 
                              uint8_t *d_done, const uint32_t *d_episode_steps, int32_t num_episodes,
                              hipStream_t stream);
 
-/* SOFT-STE forward of S env steps from power-on (Theorem "Exact forward
- * equivalence": its values equal HARD at any tau and alpha).
+/* SOFT-STE forward of S env steps (Theorem "Exact forward equivalence": its
+ * values equal HARD at any tau and alpha), the paper's env step state + action
+ * -> next state (Sec. "Building Two Differentiable VCS Ports") taken softly:
+ *  d_state_in      [B][256] state records to start from (NULL = power-on with
+ *                  the tape's RAM).  From a given state (e.g. after hard steps,
+ *                  or a vcs_reset) its registers and RAM are constants of the
+ *                  relaxation: the tape is not read (it may be NULL) and its
+ *                  gradient is zero.  Frames keep their place on the state's
+ *                  frame grid.  May equal d_state_out;
  *  d_rom_logits    float32 [sum rom_size][256]: ROM as a weight tensor; byte a
  *                  = STE(sum_k k softmax(L[a]/tau)_k, argmax_k L[a]) (Eq. select
  *                  over the byte values; lowest index on ties);
@@ -189,11 +200,12 @@ int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, 
  *  d_decode_out    float32 statistics (NULL = not written), in order:
  *                  ROM rows [sum rom_size][3] = (expected byte, softmax max,
  *                  softmax normaliser); tape [B][128] expected byte; actions
- *                  [B][S][2] = (E[SWCHA], E[INPT4]);
+ *                  [B][S][2] = (E[SWCHA], E[INPT4]); the tape rows are zero
+ *                  when the forward starts from d_state_in;
  *  d_state_out     [B][256] final hard state (NULL = not written);
  *  d_residual      vcs_residual_bytes(S): saved for the backward;
  *  d_work          vcs_workspace_bytes(VCS_OP_SOFT_FWD, S). */
-int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,
+int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_rom_logits, const float *d_ram_tape,
                           const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
                           float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
                           void *d_work, hipStream_t stream);
@@ -201,11 +213,18 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *
 /* SOFT-STE backward: surrogate gradients of a loss given dL/d(final frame)
  * (float32 [B][210][160]) and optionally dL/d(RAM out) (float32 [B][S][128],
  * NULL = zero), for the forward whose residual is d_residual (same tau, alpha,
- * inputs and S).  Recomputes each checkpoint segment from its hard-state
- * checkpoint, records a tape and sweeps it in reverse; ROM gradients of envs
- * sharing a ROM are summed in a fixed order (deterministic).
+ * inputs and S).  The gradient is the straight-through surrogate of the
+ * relaxation (Sec. "Hard and Soft Execution": stored switches, round and
+ * clamp with identity backward, straight-through branches; the Corollary after
+ * Theorem "Temperature-limit bound": STE as a surrogate-gradient estimator;
+ * softmax Jacobians of Eq. select for the leaves).  Recomputes each
+ * checkpoint segment from its hard-state checkpoint, records a tape and
+ * sweeps it in reverse; ROM gradients of envs sharing a ROM are summed in a
+ * fixed order (deterministic).
+ *  d_ram_tape           unused (may be NULL): dL/dP[c][k] = k dL/dcell[c]
  *  d_grad_rom_logits    float32 [sum rom_size][256]  (overwritten)
- *  d_grad_ram_tape      float32 [B][128][256]         (overwritten)
+ *  d_grad_ram_tape      float32 [B][128][256]         (overwritten; NULL = not
+ *                       written; zero for a forward from d_state_in)
  *  d_grad_action_logits float32 [B][S][18]            (overwritten)
  *  d_work               vcs_workspace_bytes(VCS_OP_SOFT_BWD, S). */
 int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_rom_logits,
@@ -241,6 +260,12 @@ int32_t vcs_residual_checkpoints(const vcs_ctx *ctx, int32_t steps, int32_t *cou
  * Synchronises the stream. */
 int32_t vcs_bwd_overflow(const vcs_ctx *ctx, const void *d_work, int32_t steps, hipStream_t stream,
                          int32_t *flag);
+
+/* Where the soft backward keeps that flag: *offset = byte offset of an int32
+ * in the VCS_OP_SOFT_BWD workspace for `steps` (nonzero after a backward
+ * whose tape overflowed), so that callers can test it on the device without
+ * synchronising (host only). */
+int32_t vcs_bwd_overflow_offset(const vcs_ctx *ctx, int32_t steps, size_t *offset);
 
 /* Launch geometry chosen at create time (host values; NULL outputs skipped):
  * kernel family, lanes per env, threads per workgroup, step-kernel workgroups,

@@ -17,7 +17,7 @@ VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED, VCS_KERNEL_TRANSLATED = 0
 VCS_TRANSLATE_COMPILE_ONLY = 1
 VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
 VCS_OP_HARD, VCS_OP_SOFT_FWD, VCS_OP_SOFT_BWD = 0, 1, 2
-ABI_VERSION = 1
+ABI_VERSION = 2
 STATE_BYTES = 256
 
 EXPORTED = [
@@ -25,7 +25,7 @@ EXPORTED = [
     "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
     "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
     "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash", "vcs_translate",
-    "vcs_translated_source", "vcs_step_hard_static",
+    "vcs_translated_source", "vcs_step_hard_static", "vcs_bwd_overflow_offset",
 ]
 
 
@@ -77,10 +77,11 @@ def lib():
         L.vcs_reset.argtypes = [vp, vp, vp, vp, vp]
         L.vcs_step_hard.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp, vp]
         L.vcs_step_hard_static.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp]
-        L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.vcs_step_soft_bwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.vcs_read_regs.argtypes = [vp, vp, vp, vp]
         L.vcs_bwd_overflow.argtypes = [vp, vp, i32, vp, C.POINTER(i32)]
+        L.vcs_bwd_overflow_offset.argtypes = [vp, i32, C.POINTER(sz)]
         L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5
         L.vcs_decode_table.argtypes = [C.POINTER(C.c_uint32)]
         L.vcs_translate.argtypes = [vp, vp, i32, i32, C.POINTER(VcsTranslateInfo), C.c_char_p, sz]

@@ -68,7 +68,8 @@ ResidualLayout residual_layout(const vcs_ctx *c, int32_t S) {
     o = align_up(L.rom_stats + L.stats_bytes);
     L.ckpt_count = o;
     o = align_up(o + (size_t)c->B * sizeof(int32_t));
-    L.max_ckpt = (int32_t)(((int64_t)S * c->F * kCyclesPerFrame + 256) / c->K + 2);
+    // the starting state, one per K cycles, and slack for a start inside a frame
+    L.max_ckpt = (int32_t)(((int64_t)S * c->F * kCyclesPerFrame + 256) / c->K + 3);
     L.ckpt = o;
     o = align_up(o + (size_t)c->B * L.max_ckpt * sizeof(StateRec));
     L.bytes = o;
@@ -548,15 +549,16 @@ int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, 
     return VCS_OK;
 }
 
-int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *d_ram_tape,
+int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_rom_logits, const float *d_ram_tape,
                           const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
                           float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
                           void *d_work, hipStream_t stream) {
-    if (!ctx || !d_rom_logits || !d_ram_tape || !d_action_logits || !d_residual || !d_work || steps < 1)
+    if (!ctx || !d_rom_logits || (!d_ram_tape && !d_state_in) || !d_action_logits || !d_residual || !d_work ||
+        steps < 1)
         return VCS_INVALID_ARG;
     if (!(tau > 0.f) || !(alpha > 0.f)) return VCS_INVALID_ARG;
-    if (!aligned16(d_rom_logits) || !aligned16(d_ram_tape) || ((uintptr_t)d_action_logits & 3u) ||
-        !aligned16(d_residual) || !aligned16(d_work))
+    if (!aligned16(d_rom_logits) || (d_ram_tape && !aligned16(d_ram_tape)) || ((uintptr_t)d_action_logits & 3u) ||
+        !aligned16(d_residual) || !aligned16(d_work) || (d_state_in && !aligned16(d_state_in)))
         return VCS_INVALID_ARG;
     if ((d_ram_out && !aligned16(d_ram_out)) || (d_frame_out && !aligned16(d_frame_out)) ||
         (d_state_out && !aligned16(d_state_out)) || (d_decode_out && ((uintptr_t)d_decode_out & 3u)))
@@ -567,15 +569,20 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const float *d_rom_logits, const float *
     if (rc) return rc;
     const ResidualLayout L = residual_layout(ctx, steps);
     uint8_t *res = (uint8_t *)d_residual;
-    hipError_t e = launch_decode(d_rom_logits, ctx->total_rom, d_ram_tape, (int64_t)ctx->B * 128, d_action_logits,
-                                 (int64_t)ctx->B * steps, tau, res + L.rom_hard, (float *)(res + L.rom_stats),
-                                 res + L.ram0_hard, (float *)(res + L.tape_ev), res + L.act_hard,
-                                 (float *)(res + L.act_stats), stream);
+    // (from a given state the tape is not read: its statistics are zero)
+    hipError_t e = d_ram_tape ? hipSuccess
+                              : launch_fill_zero(res + L.tape_ev, (size_t)ctx->B * 128 * sizeof(float), stream);
+    if (e != hipSuccess) return VCS_HIP_ERROR;
+    e = launch_decode(d_rom_logits, ctx->total_rom, d_ram_tape, d_ram_tape ? (int64_t)ctx->B * 128 : 0,
+                      d_action_logits, (int64_t)ctx->B * steps, tau, res + L.rom_hard, (float *)(res + L.rom_stats),
+                      res + L.ram0_hard, (float *)(res + L.tape_ev), res + L.act_hard, (float *)(res + L.act_stats),
+                      stream);
     if (e != hipSuccess) return VCS_HIP_ERROR;
     StepParams P{};
     P.st = static_ptrs(ctx, d_work);
     P.rom = res + L.rom_hard;
     P.state = (StateRec *)d_state_out;
+    P.state_in = (const StateRec *)d_state_in;
     P.actions = res + L.act_hard;
     P.steps = steps;
     P.frame_skip = ctx->F;
@@ -602,12 +609,13 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
                           int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
                           float *d_grad_rom_logits, float *d_grad_ram_tape, float *d_grad_action_logits,
                           void *d_work, hipStream_t stream) {
-    if (!ctx || !d_residual || !d_rom_logits || !d_ram_tape || !d_action_logits || !d_grad_frame ||
-        !d_grad_rom_logits || !d_grad_ram_tape || !d_grad_action_logits || !d_work || steps < 1)
+    (void)d_ram_tape;  // dL/dP0[c,k] = k g0[c] needs no tape values
+    if (!ctx || !d_residual || !d_rom_logits || !d_action_logits || !d_grad_frame || !d_grad_rom_logits ||
+        !d_grad_action_logits || !d_work || steps < 1)
         return VCS_INVALID_ARG;
     if (!(tau > 0.f) || !(alpha > 0.f)) return VCS_INVALID_ARG;
     if (!aligned16(d_residual) || !aligned16(d_rom_logits) || !aligned16(d_grad_rom_logits) ||
-        !aligned16(d_grad_ram_tape) || !aligned16(d_work) || ((uintptr_t)d_grad_frame & 3u) ||
+        (d_grad_ram_tape && !aligned16(d_grad_ram_tape)) || !aligned16(d_work) || ((uintptr_t)d_grad_frame & 3u) ||
         ((uintptr_t)d_action_logits & 3u) || ((uintptr_t)d_grad_action_logits & 3u) ||
         (d_grad_ram_out && ((uintptr_t)d_grad_ram_out & 3u)))
         return VCS_INVALID_ARG;
@@ -622,7 +630,6 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     BwdParams P{};
     P.st = static_ptrs(ctx, d_work);
     P.rom = res + L.rom_hard;
-    P.ram0 = res + L.ram0_hard;
     P.actions = res + L.act_hard;
     P.ckpt = (const StateRec *)(res + L.ckpt);
     P.ckpt_count = (const int32_t *)(res + L.ckpt_count);
@@ -644,8 +651,8 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     const StaticPtrs sp = static_ptrs(ctx, d_work);
     return hip_status(launch_epilogue(d_rom_logits, (const float *)(res + L.rom_stats), P.gpart, ctx->total_rom,
                                       ctx->R, sp.rom_off, sp.rom_size, sp.rom_bwd_slot_begin, sp.rom_bwd_slot_end,
-                                      W.nslots, tau, d_grad_rom_logits, P.g_ram0, (int64_t)ctx->B * 128,
-                                      d_grad_ram_tape, d_action_logits, (const float *)(res + L.act_stats), P.gport,
+                                      W.nslots, tau, d_grad_rom_logits, P.g_ram0,
+                                      d_grad_ram_tape ? (int64_t)ctx->B * 128 : 0, d_grad_ram_tape, d_action_logits, (const float *)(res + L.act_stats), P.gport,
                                       (int64_t)ctx->B * steps, d_grad_action_logits, stream));
 }
 
@@ -679,6 +686,13 @@ int32_t vcs_bwd_overflow(const vcs_ctx *ctx, const void *d_work, int32_t steps, 
         hipSuccess)
         return VCS_HIP_ERROR;
     return hip_status(hipStreamSynchronize(stream));
+}
+
+// Byte offset of the soft backward's int32 tape-overflow flag in its workspace.
+int32_t vcs_bwd_overflow_offset(const vcs_ctx *ctx, int32_t steps, size_t *offset) {
+    if (!ctx || !offset || steps < 1) return VCS_INVALID_ARG;
+    *offset = bwd_layout(ctx, steps).overflow;
+    return VCS_OK;
 }
 
 // Launch geometry chosen at create time (host values).

@@ -43,10 +43,11 @@ struct alignas(16) StateRec {
     uint32_t episode;     // episodes completed since the last vcs_reset
     uint32_t ep_step;     // env steps taken in the current episode
     // soft checkpoints only:
-    int64_t next_ckpt;    // cycle (since power-on) at which the next checkpoint is due
+    int64_t next_ckpt;    // cycle (since the soft call's start) at which the next checkpoint is due
     int32_t pix_cc;       // frame-relative colour clock of the last instruction's write point
     uint32_t ckpt_index;  // index of this checkpoint
-    uint32_t pad[16];
+    uint32_t from_tape;   // (checkpoint 0) 1: the RAM came from the soft tape at power-on; 0: a given state
+    uint32_t pad[15];
     uint8_t ram[128];
 };
 static_assert(sizeof(StateRec) == 256, "state record must be 256 bytes");
@@ -93,8 +94,9 @@ struct StepParams {
     int32_t num_episodes;
     uint64_t seed;
     // soft forward
-    const uint8_t *ram0;       // [B][128]: start every env from power-on with this RAM (NULL: load state)
-    StateRec *ckpt;            // [B][max_ckpt] or NULL
+    const StateRec *state_in;  // [B]: start every env from this state (NULL: power-on with ram0)
+    const uint8_t *ram0;       // [B][128]: decoded RAM of the power-on start
+    StateRec *ckpt;            // [B][max_ckpt] or NULL; checkpoint 0 is the starting state
     int32_t *ckpt_count;       // [B]
     int32_t ckpt_interval;
     int32_t max_ckpt;
@@ -116,9 +118,8 @@ enum ValClass : uint32_t { kClsConst = 0, kClsRam = 1, kClsCol = 2, kClsRom = 3,
 struct BwdParams {
     StaticPtrs st;
     const uint8_t *rom;          // decoded ROM bytes (concatenated)
-    const uint8_t *ram0;         // [B][128] decoded initial RAM
     const uint8_t *actions;      // [B][S] decoded actions
-    const StateRec *ckpt;        // [B][max_ckpt]
+    const StateRec *ckpt;        // [B][max_ckpt]: segment i starts from checkpoint i (0 = the start)
     const int32_t *ckpt_count;   // [B]
     int32_t max_ckpt;
     int32_t steps, frame_skip, ystart;

@@ -521,14 +521,17 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     c.hook.ystart = P.ystart;
     c.hook.sub = sub;
     c.hook.G = G;
-    uint32_t frame = 0, episode = 0, ep_step = 0;
+    // frame counts frames since power-on (hard) or since the call's start (soft;
+    // frame0 then holds the starting state's count)
+    uint32_t frame = 0, frame0 = 0, episode = 0, ep_step = 0;
+    const StateRec *src = kSoft ? P.state_in : P.state;
     if (live) {
-        if (P.ram0) {  // soft forward: power-on with the decoded RAM
+        if (kSoft && !src) {  // soft forward: power-on with the decoded RAM
             const uint32_t *r0 = reinterpret_cast<const uint32_t *>(P.ram0 + (size_t)env * 128);
             for (uint32_t w = sub; w < 32; w += G) c.mem.ram_word_set(w, r0[w]);
             c.power_on();
         } else {
-            const StateRec &st = P.state[env];
+            const StateRec &st = src[env];
             c.load(st);
             c.bank &= c.f8;  // only F8 images have a second bank
             frame = st.frame;
@@ -540,6 +543,10 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
             }
             if (st.status & 2u) {  // power-on requested by vcs_reset
                 c.power_on();
+                frame = 0;
+            }
+            if constexpr (kSoft) {
+                frame0 = frame;
                 frame = 0;
             }
         }
@@ -569,35 +576,43 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         set_ports();
         start_frame();
     }
-    // soft forward: hard-state checkpoints every K cycles since power-on, taken
-    // at the first instruction boundary (or frame end) at or after each multiple
+    // soft forward: hard-state checkpoints, the first at the start, then every K
+    // cycles since the start, each taken at the first instruction boundary (or
+    // frame end) at or after its multiple of K
     int64_t next_ckpt = P.ckpt_interval;
     int32_t nckpt = 0;
+    auto save_checkpoint = [&](int64_t g) {
+        if constexpr (kSoft) {
+            next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
+            if (nckpt < P.max_ckpt) {
+                StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
+                if (sub == 0) {
+                    c.store(r);
+                    r.frame = frame;
+                    r.episode = 0;
+                    r.ep_step = (uint32_t)s_idx;
+                    r.next_ckpt = next_ckpt;
+                    r.pix_cc = c.hook.pix_cc;
+                    r.ckpt_index = (uint32_t)nckpt;
+                    r.from_tape = src ? 0u : 1u;
+                }
+                uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
+                for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
+            }
+            ++nckpt;
+        }
+    };
     auto checkpoint = [&]() {
         if constexpr (kSoft) {
             if (P.ckpt) {
                 const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
-                if (g >= next_ckpt) {
-                    next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
-                    if (nckpt < P.max_ckpt) {
-                        StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
-                        if (sub == 0) {
-                            c.store(r);
-                            r.frame = frame;
-                            r.episode = 0;
-                            r.ep_step = (uint32_t)s_idx;
-                            r.next_ckpt = next_ckpt;
-                            r.pix_cc = c.hook.pix_cc;
-                            r.ckpt_index = (uint32_t)nckpt;
-                        }
-                        uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
-                        for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
-                    }
-                    ++nckpt;
-                }
+                if (g >= next_ckpt) save_checkpoint(g);
             }
         }
     };
+    if constexpr (kSoft) {
+        if (P.ckpt && active) save_checkpoint((int64_t)c.cyc);
+    }
 
     while (W::any(active)) {
         // ---- the instructions of one frame (the hot loop; a lane leaves it at
@@ -680,7 +695,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
             StateRec &st = P.state[env];
             if (sub == 0) {
                 c.store(st);
-                st.frame = frame;
+                st.frame = frame0 + frame;
                 st.episode = episode;
                 st.ep_step = ep_step;
             }
@@ -704,7 +719,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                                                  int32_t mapper, Mem mem, float *adj_ram, uint32_t E,
                                                  const uint32_t *decode) {
     const bool live = env >= 0;
-    const int32_t S = P.steps, F = P.frame_skip, K = P.ckpt_interval;
+    const int32_t S = P.steps, F = P.frame_skip;
     for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] = 0.f;
 
     Cpu<Mem, TapeHook> c;
@@ -720,8 +735,8 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     float aA = 0.f, aX = 0.f, aY = 0.f;
     float aC[4] = {0.f, 0.f, 0.f, 0.f};
     const float *gframe_env = live ? P.grad_frame + (size_t)env * kPixels : nullptr;
-    const int32_t nck = live ? (P.ckpt_count[env] < P.max_ckpt ? P.ckpt_count[env] : P.max_ckpt) : 0;
-    const int32_t nseg = live ? nck + 1 : 0;
+    // segment i starts from checkpoint i (checkpoint 0: the forward's starting state)
+    const int32_t nseg = live ? (P.ckpt_count[env] < P.max_ckpt ? P.ckpt_count[env] : P.max_ckpt) : 0;
     int32_t seg = nseg - 1;
 
     auto add_src = [&](uint32_t cls, uint32_t idx, uint32_t step, float t) {
@@ -760,26 +775,14 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     while (W::any(seg >= 0)) {
         if (seg >= 0) {
             // ---- restore the segment's starting state
-            int64_t seg_end;
-            uint32_t frame;
-            if (seg == 0) {
-                const uint32_t *r0 = reinterpret_cast<const uint32_t *>(P.ram0 + (size_t)env * 128);
-                for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, r0[w]);
-                c.power_on();
-                frame = 0;
-                c.hook.pix_cc = 0;
-                seg_end = K;
-            } else {
-                const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + (seg - 1)];
-                c.load(r);
-                c.bank &= c.f8;
-                const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
-                for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, rw[w]);
-                frame = r.frame;
-                c.hook.pix_cc = r.pix_cc;
-                seg_end = r.next_ckpt;
-            }
-            if (seg == nseg - 1) seg_end = INT64_MAX;
+            const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + seg];
+            c.load(r);
+            c.bank &= c.f8;
+            const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
+            for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, rw[w]);
+            uint32_t frame = r.frame;
+            c.hook.pix_cc = r.pix_cc;
+            const int64_t seg_end = seg == nseg - 1 ? INT64_MAX : r.next_ckpt;
             int32_t s_idx = (int32_t)(frame / (uint32_t)F), fstep = (int32_t)(frame % (uint32_t)F);
             c.hook.nrec = 0;
             auto set_ports = [&]() {
@@ -933,8 +936,13 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             --seg;
         }
     }
-    if (live)
-        for (uint32_t cidx = 0; cidx < 128; ++cidx) P.g_ram0[(size_t)env * 128 + cidx] = adj_ram[cidx * E];
+    // the RAM adjoint at the start reaches the tape only when the forward started
+    // from power-on with the tape's RAM; a given starting state is a constant
+    if (live) {
+        const bool tape = nseg > 0 && P.ckpt[(size_t)env * P.max_ckpt].from_tape != 0u;
+        for (uint32_t cidx = 0; cidx < 128; ++cidx)
+            P.g_ram0[(size_t)env * 128 + cidx] = tape ? adj_ram[cidx * E] : 0.f;
+    }
 }
 
 }  // namespace vcs

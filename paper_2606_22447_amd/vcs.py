@@ -47,6 +47,8 @@ class _Ctx:
                            _KERNELS[kernel] if isinstance(kernel, str) else int(kernel), lanes_per_env,
                            block_threads)
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:  # "cuda" = the current device
+            self.device = torch.device("cuda", torch.cuda.current_device())
         host_rom = np.concatenate(imgs)
         self.rom = torch.from_numpy(host_rom).to(self.device)
         self._ws = {}
@@ -65,12 +67,14 @@ class _Ctx:
         return Bd.launch_info(self.h)
 
     def workspace(self, op: int, steps: int) -> torch.Tensor:
+        """The context's workspace for op, grown when a call needs more.  A
+        workspace that a captured graph uses is also held by that graph, so
+        replacing it here never frees memory a graph reads."""
         n = Bd.size_query("vcs_workspace_bytes", self.h, op, steps)
-        key = (op, steps)
-        w = self._ws.get(key)
+        w = self._ws.get(op)
         if w is None or w.numel() < n:
             w = torch.empty(n, dtype=torch.uint8, device=self.device)
-            self._ws = {key: w}
+            self._ws[op] = w
         return w
 
 
@@ -133,7 +137,10 @@ class VcsBatch(_Ctx):
         those steps again from the current state, reading the device tensor
         ``actions`` (refill it in place between replays) and writing the returned
         output tensors.  The call's stream work is one host-to-device copy of the
-        launch tables and one kernel, so the graph holds no memset node.
+        launch tables and one kernel, so the graph holds no memset node.  The
+        graph holds references to everything it reads or writes (this batch and
+        its context, the workspace, the episode lengths, the actions and the
+        outputs), so none of it is freed while the graph exists.
         """
         assert getattr(self, "_was_reset", False), "reset() the batch before capturing its steps"
         assert torch.is_tensor(actions) and actions.is_cuda and actions.dtype == torch.uint8
@@ -151,12 +158,13 @@ class VcsBatch(_Ctx):
             eps = episode_steps if torch.is_tensor(episode_steps) else torch.from_numpy(
                 np.ascontiguousarray(episode_steps, np.uint32).view(np.int32))
             eps = eps.to(self.device).contiguous()
-        self.workspace(Bd.VCS_OP_HARD, S)  # allocated before capture
+        work = self.workspace(Bd.VCS_OP_HARD, S)  # allocated before capture
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
             self.step(actions=actions, frames=frames, episode_steps=eps, ram_out=ram_out, frame_out=frame_out,
                       done=done)
+        graph._vcs_keep_alive = (self, work, eps, actions, self.state, self.rom, ram_out, frame_out, done)
         return graph, ram_out, frame_out, done
 
     def hash(self, frame: torch.Tensor | None = None, step: int | None = None) -> torch.Tensor:
@@ -181,12 +189,20 @@ class VcsBatch(_Ctx):
 
 
 class SoftVcs(_Ctx):
-    """B consoles in SOFT-STE mode: differentiable w.r.t. ROM logits, RAM tape and action logits."""
+    """B consoles in SOFT-STE mode: differentiable w.r.t. ROM logits, RAM tape and action logits.
+
+    strict=True checks the backward's tape-overflow flag after every backward
+    (a host synchronisation); otherwise the flags are summed on the device and
+    raise_if_overflowed() checks them.  The tape is sized so that no segment
+    can fill it (every instruction takes at least two cycles), so the flag is a
+    safety net."""
 
     def __init__(self, roms, env_rom, frame_skip: int = 1, ystart: int = 34, ckpt_interval: int = 1024,
-                 lanes_per_env: int = 0, block_threads: int = 0, device="cuda"):
+                 lanes_per_env: int = 0, block_threads: int = 0, device="cuda", strict: bool = False):
         super().__init__(roms, env_rom, frame_skip, ystart, 0, ckpt_interval, "grouped", lanes_per_env,
                          block_threads, device)
+        self.strict = strict
+        self._overflow = torch.zeros(1, dtype=torch.int32, device=self.device)
 
     def residual_bytes(self, steps: int) -> int:
         return Bd.size_query("vcs_residual_bytes", self.h, steps)
@@ -198,10 +214,35 @@ class SoftVcs(_Ctx):
         act = dec[total * 3 + self.B * 128:].view(self.B, steps, 2)
         return rom, tape, act
 
+    def _check(self, t, shape, name, dtype=torch.float32):
+        """The kernels read exactly this layout: refuse anything else before launching."""
+        if not torch.is_tensor(t) or t.dtype != dtype or t.device != self.device or not t.is_contiguous() \
+                or tuple(t.shape) != tuple(shape):
+            got = (tuple(t.shape), t.dtype, str(t.device), t.is_contiguous()) if torch.is_tensor(t) else type(t)
+            raise Bd.VcsError(f"{name}: expected a contiguous {dtype} tensor of shape {tuple(shape)} on "
+                              f"{self.device}, got {got}")
+
+    def _check_leaves(self, rom_logits, ram_tape, action_logits, state_in=None):
+        B = self.B
+        S = action_logits.shape[1] if torch.is_tensor(action_logits) and action_logits.dim() == 3 else -1
+        self._check(rom_logits, (sum(self.rom_sizes), 256), "rom_logits")
+        if ram_tape is not None or state_in is None:
+            self._check(ram_tape, (B, 128, 256), "ram_tape")
+        self._check(action_logits, (B, S, 18), "action_logits")
+        if S < 1:
+            raise Bd.VcsError("action_logits: need at least one step")
+        if state_in is not None:
+            self._check(state_in, (B * Bd.STATE_BYTES,), "state_in", torch.uint8)
+        return S
+
     def forward(self, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0,
-                want_decode: bool = False, want_state: bool = False):
-        B, S = self.B, action_logits.shape[1]
-        dev = self.device
+                want_decode: bool = False, want_state: bool = False, state_in=None):
+        """Soft forward of S = action_logits.shape[1] env steps, from power-on with the
+        tape's RAM or (state_in: a [B * 256] uint8 state, e.g. VcsBatch.state after hard
+        steps) from that state, whose registers and RAM are then constants (ram_tape may
+        be None).  Returns (ram_out, frame, residual, decode stats or None, state or None)."""
+        S = self._check_leaves(rom_logits, ram_tape, action_logits, state_in)
+        B, dev = self.B, self.device
         ram_out = torch.empty((B, S, 128), dtype=torch.float32, device=dev)
         frame = torch.empty((B, 210, 160), dtype=torch.float32, device=dev)
         residual = torch.empty(Bd.size_query("vcs_residual_bytes", self.h, S), dtype=torch.uint8, device=dev)
@@ -210,32 +251,48 @@ class SoftVcs(_Ctx):
             dec = torch.empty(Bd.size_query("vcs_decode_bytes", self.h, S) // 4, dtype=torch.float32, device=dev)
         st = torch.empty(B * Bd.STATE_BYTES, dtype=torch.uint8, device=dev) if want_state else None
         work = self.workspace(Bd.VCS_OP_SOFT_FWD, S)
-        rc = Bd.lib().vcs_step_soft_fwd(self.h, Bd.ptr(rom_logits), Bd.ptr(ram_tape), Bd.ptr(action_logits),
-                                        float(tau), float(alpha), S, Bd.ptr(ram_out), Bd.ptr(frame), Bd.ptr(dec),
-                                        Bd.ptr(st), Bd.ptr(residual), Bd.ptr(work), _stream())
+        rc = Bd.lib().vcs_step_soft_fwd(self.h, Bd.ptr(state_in), Bd.ptr(rom_logits), Bd.ptr(ram_tape),
+                                        Bd.ptr(action_logits), float(tau), float(alpha), S, Bd.ptr(ram_out),
+                                        Bd.ptr(frame), Bd.ptr(dec), Bd.ptr(st), Bd.ptr(residual), Bd.ptr(work),
+                                        _stream())
         Bd.check(rc, "vcs_step_soft_fwd")
         return ram_out, frame, residual, dec, st
 
     def backward(self, residual, rom_logits, ram_tape, action_logits, tau: float, alpha: float, grad_frame,
                  grad_ram_out=None, check_overflow: bool = False):
-        S = action_logits.shape[1]
+        """Surrogate gradients (rom_logits, ram_tape, action_logits) of the forward whose
+        residual is given; the RAM-tape gradient is None when ram_tape is None (a forward
+        from a given state, where it would be zero)."""
+        S = action_logits.shape[1] if torch.is_tensor(action_logits) and action_logits.dim() == 3 else -1
+        self._check(rom_logits, (sum(self.rom_sizes), 256), "rom_logits")
+        if ram_tape is not None:
+            self._check(ram_tape, (self.B, 128, 256), "ram_tape")
+        self._check(action_logits, (self.B, S, 18), "action_logits")
+        self._check(residual, (Bd.size_query("vcs_residual_bytes", self.h, S),), "residual", torch.uint8)
+        self._check(grad_frame, (self.B, 210, 160), "grad_frame")
+        if grad_ram_out is not None:
+            self._check(grad_ram_out, (self.B, S, 128), "grad_ram_out")
         g_rom = torch.empty_like(rom_logits)
-        g_tape = torch.empty_like(ram_tape)
+        g_tape = None if ram_tape is None else torch.empty_like(ram_tape)
         g_act = torch.empty_like(action_logits)
         work = self.workspace(Bd.VCS_OP_SOFT_BWD, S)
         rc = Bd.lib().vcs_step_soft_bwd(self.h, Bd.ptr(residual), Bd.ptr(rom_logits), Bd.ptr(ram_tape),
-                                        Bd.ptr(action_logits), float(tau), float(alpha), S,
-                                        Bd.ptr(grad_frame.contiguous()),
-                                        Bd.ptr(None if grad_ram_out is None else grad_ram_out.contiguous()),
-                                        Bd.ptr(g_rom), Bd.ptr(g_tape), Bd.ptr(g_act), Bd.ptr(work), _stream())
+                                        Bd.ptr(action_logits), float(tau), float(alpha), S, Bd.ptr(grad_frame),
+                                        Bd.ptr(grad_ram_out), Bd.ptr(g_rom), Bd.ptr(g_tape), Bd.ptr(g_act),
+                                        Bd.ptr(work), _stream())
         Bd.check(rc, "vcs_step_soft_bwd")
-        if check_overflow:
-            flag = C.c_int32()
-            Bd.check(Bd.lib().vcs_bwd_overflow(self.h, Bd.ptr(work), S, _stream(), C.byref(flag)),
-                     "vcs_bwd_overflow")
-            if flag.value:
-                raise Bd.VcsError("soft backward tape overflow")
+        off = Bd.size_query("vcs_bwd_overflow_offset", self.h, S)
+        self._overflow += work[off:off + 4].view(torch.int32)  # on the stream, no host sync
+        if check_overflow or self.strict:
+            self.raise_if_overflowed()
         return g_rom, g_tape, g_act
+
+    def raise_if_overflowed(self):
+        """Synchronise and raise if any backward since the last check overflowed its tape."""
+        n = int(self._overflow.item())
+        self._overflow.zero_()
+        if n:
+            raise Bd.VcsError("soft backward tape overflow: those gradients are invalid")
 
 
 class VcsSoftFunction(torch.autograd.Function):
@@ -245,11 +302,12 @@ class VcsSoftFunction(torch.autograd.Function):
     surrogate adjoint (recompute from hard-state checkpoints, reverse sweep)."""
 
     @staticmethod
-    def forward(ctx, rom_logits, ram_tape, action_logits, sim: SoftVcs, tau: float, alpha: float):
+    def forward(ctx, rom_logits, ram_tape, action_logits, sim: SoftVcs, tau: float, alpha: float, state_in=None):
         rom_logits = rom_logits.contiguous()
-        ram_tape = ram_tape.contiguous()
+        ram_tape = None if ram_tape is None else ram_tape.contiguous()
         action_logits = action_logits.contiguous()
-        ram_out, frame, residual, _, _ = sim.forward(rom_logits, ram_tape, action_logits, tau, alpha)
+        ram_out, frame, residual, _, _ = sim.forward(rom_logits, ram_tape, action_logits, tau, alpha,
+                                                     state_in=state_in)
         ctx.save_for_backward(rom_logits, ram_tape, action_logits, residual)
         ctx.sim, ctx.tau, ctx.alpha = sim, tau, alpha
         return ram_out, frame
@@ -261,12 +319,15 @@ class VcsSoftFunction(torch.autograd.Function):
         if g_frame is None:
             g_frame = torch.zeros((sim.B, 210, 160), dtype=torch.float32, device=sim.device)
         g_rom, g_tape, g_act = sim.backward(residual, rom_logits, ram_tape, action_logits, ctx.tau, ctx.alpha,
-                                            g_frame.float(), None if g_ram is None else g_ram.float())
-        return g_rom, g_tape, g_act, None, None, None
+                                            g_frame.float().contiguous(),
+                                            None if g_ram is None else g_ram.float().contiguous())
+        return g_rom, g_tape, g_act, None, None, None, None
 
 
-def soft_rollout(sim: SoftVcs, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0):
-    return VcsSoftFunction.apply(rom_logits, ram_tape, action_logits, sim, tau, alpha)
+def soft_rollout(sim: SoftVcs, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0, state_in=None):
+    """Differentiable rollout (ram_out, final frame); from power-on with the tape's RAM, or
+    from state_in (then ram_tape may be None and gets no gradient)."""
+    return VcsSoftFunction.apply(rom_logits, ram_tape, action_logits, sim, tau, alpha, state_in)
 
 
 def ste_luminance(frame: torch.Tensor) -> torch.Tensor:

@@ -69,21 +69,40 @@ extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapp
 }
 
 // SOFT-STE forward and the surrogate backward of one env on the host, through
-// the soft kernels' bodies: forward from power-on on the decoded leaves (rom:
-// decoded bytes, ram0, actions [S]) with a hard-state checkpoint every K
-// cycles, then the backward from dL/dframe [210][160] and dL/dRAM_out [S][128]
-// (NULL = zero).  Outputs: ram_out [S][128] and frame [210][160] as floats,
-// the per-byte ROM value gradient g_rom [rom_size], g_ram0 [128] and the port
-// gradients g_port [S][2] (SWCHA, INPT4), before the softmax epilogue.
-// Returns the number of checkpoints, or -1 if the tape overflowed.
-extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, const uint8_t *actions,
-                         int S, int F, int K, const float *grad_frame, const float *grad_ram, float *ram_out,
-                         float *frame_out, float *g_rom, float *g_ram0, float *g_port) {
+// the soft kernels' bodies: forward on the decoded leaves (rom: decoded bytes,
+// actions [S]) with a hard-state checkpoint every K cycles, from power-on with
+// RAM ram0 (pre_steps = 0) or from the state after pre_steps hard env steps of
+// pre_actions from power-on with ram0 (then the state is a constant and
+// g_ram0 is zero); then the backward from dL/dframe [210][160] and
+// dL/dRAM_out [S][128] (NULL = zero).  Outputs: ram_out [S][128] and frame
+// [210][160] as floats, the per-byte ROM value gradient g_rom [rom_size],
+// g_ram0 [128] and the port gradients g_port [S][2] (SWCHA, INPT4), before the
+// softmax epilogue.  Returns the number of checkpoints, or -1 if the tape
+// overflowed.
+extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
+                         const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
+                         const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
+                         float *g_rom, float *g_ram0, float *g_port) {
     std::vector<uint2> words(8192);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
-    const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 2);
+    const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 3);
     std::vector<StateRec> ckpt((size_t)max_ckpt);
     int32_t nck = 0;
+    StateRec st{};
+    if (pre_steps > 0) {  // hard steps from power-on, through the hard interpreter's body
+        st.status = 2;
+        st.tim_shift = 10;
+        std::memcpy(st.ram, ram0, 128);
+        StepParams P{};
+        P.state = &st;
+        P.actions = pre_actions;
+        P.steps = pre_steps;
+        P.frame_skip = F;
+        P.ystart = 34;
+        std::vector<uint32_t> ram_lds(32, 0);
+        LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+        step_env<OneLane, 1, false, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    }
     {
         StepParams P{};
         P.rom = rom;
@@ -95,6 +114,7 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
         P.ram_out_f = ram_out;
         P.frame_out_f = frame_out;
         P.ram0 = ram0;
+        P.state_in = pre_steps > 0 ? &st : nullptr;
         P.ckpt = ckpt.data();
         P.ckpt_count = &nck;
         P.ckpt_interval = K;
@@ -105,7 +125,6 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
     }
     BwdParams Q{};
     Q.rom = rom;
-    Q.ram0 = ram0;
     Q.actions = actions;
     Q.ckpt = ckpt.data();
     Q.ckpt_count = &nck;

@@ -150,12 +150,12 @@ def _soft_env(args):
     gf = ((2.0 * dl / 33600) * 0.5).astype(np.float32)
     res = O.soft_env(dec_rom[0], dec_rom[1], mapper, hr0[b], ev0[b], ha[b], es[b], ei[b], w.steps, 1, mode="ste",
                      grad_frame=gf.astype(np.float64))
-    return r, b, gf, res["g_rom"], res["g_ram0"], res["g_swcha"], res["g_inpt4"]
+    return r, b, gf, res["g_rom"], res["g_ram0"], res["g_swcha"], res["g_inpt4"], res["ram"], res["frame"]
 
 
 def test_soft_scale_gradients_of_eight_roms():
     import torch
-    from paper_2606_22447_amd.vcs import SoftVcs
+    from paper_2606_22447_amd.vcs import SoftVcs, VcsBatch
     from tests.test_gpu_soft import assert_grad_close
     w = I.config_c4()  # 4096 envs over 64 ROMs, 60 frames
     lv = I.soft_leaves(w)
@@ -178,19 +178,33 @@ def test_soft_scale_gradients_of_eight_roms():
     g_rom = {r: np.zeros(w.roms[r].size) for r in roms}
     g0 = np.zeros((B, 128))
     gsw, gin = np.zeros((B, S)), np.zeros((B, S))
-    for r, b, gf, gr, g_0, g_s, g_i in out:
+    ref_fwd = {}
+    for r, b, gf, gr, g_0, g_s, g_i, ram_o, fr_o in out:
         grad_frame[b] = gf
         g_rom[r] += gr
         g0[b], gsw[b], gin[b] = g_0, g_s, g_i
+        ref_fwd[b] = (ram_o, fr_o)
     say("soft gpu fwd+bwd at full size")
     sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=1024, lanes_per_env=64)
     L = torch.from_numpy(lv.rom_logits).cuda()
     T = torch.from_numpy(lv.ram_tape).cuda()
     A = torch.from_numpy(lv.action_logits).cuda()
-    _, _, residual, _, _ = sim.forward(L, T, A, tau, 6.0)
+    ram_s, frame_s, residual, _, _ = sim.forward(L, T, A, tau, 6.0)
     g = sim.backward(residual, L, T, A, tau, 6.0, torch.from_numpy(grad_frame).cuda(), check_overflow=True)
     torch.cuda.synchronize()
     got_rom, got_tape, got_act = (x.cpu().numpy() for x in g)
+    # forward outputs: every env's RAM after every step and final frame equal the hard kernel's on the
+    # decoded leaves (Theorem "Exact forward equivalence"), and the oracle's for the envs of the 8 ROMs
+    say("soft forward vs hard kernel, every env")
+    dec_all = O.decode_logits(lv.rom_logits, tau)[0]
+    imgs = [(dec_all[offs[r]:offs[r] + w.roms[r].size], w.roms[r].mapper) for r in range(len(w.roms))]
+    vh = VcsBatch(imgs, w.env_rom, frame_skip=1, kernel="grouped", lanes_per_env=64)
+    vh.reset(ram0=_S["data"]["hr0"])
+    ram_h, frame_h, _ = vh.step(actions=_S["data"]["ha"], frames="last", want_done=False)
+    assert torch.equal(ram_s, ram_h.float()) and torch.equal(frame_s, frame_h.float())
+    ram_s, frame_s = ram_s.cpu().numpy(), frame_s.cpu().numpy()
+    for b, (ram_o, fr_o) in ref_fwd.items():
+        assert (ram_s[b] == ram_o).all() and (frame_s[b] == fr_o).all(), b
     for r in roms:
         o, n = offs[r], w.roms[r].size
         assert_grad_close(got_rom[o:o + n], O.epilogue_rom(lv.rom_logits[o:o + n], tau, g_rom[r]), f"rom {r}")

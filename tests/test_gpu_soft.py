@@ -50,6 +50,11 @@ class Problem:
         self.loss = float((d.astype(np.float64) ** 2).mean(axis=(1, 2)).sum())
 
     def oracle_grads(self):
+        if getattr(self, "_grads", None) is None:
+            self._grads = self._oracle_grads()
+        return self._grads
+
+    def _oracle_grads(self):
         w, B, S = self.w, self.w.num_envs, self.w.steps
         g_rom = np.zeros(self.logits.shape[0])
         g0 = np.zeros((B, 128))
@@ -102,7 +107,8 @@ def assert_grad_close(g, ref, name):
 
 @pytest.fixture(scope="module", params=[1.0, 0.1])
 def c3(request):
-    w = I.config_c3(num_envs=32)
+    w = I.config_c3()  # the small soft workload at its size: 256 envs, 2 frames
+    assert w.num_envs == 256
     return Problem(w, request.param)
 
 
@@ -206,3 +212,122 @@ def test_autograd_function_end_to_end(c3):
     ref = p.oracle_grads()
     assert_grad_close(L.grad.cpu().numpy(), ref[0], "rom_logits")
     assert_grad_close(T.grad.cpu().numpy(), ref[1], "ram_tape")
+
+
+def test_soft_forward_continues_a_hard_state():
+    """The env step state + action -> next state taken softly: hard steps first
+    (the interpreting kernel), then the soft forward from the state they left,
+    on input-reading 2K/4K/F8 ROMs.  Forward = the oracle's hard rollout of all
+    steps; gradients = the oracle's, with the state a constant (no tape
+    gradient); the same through the autograd function."""
+    import torch
+    from paper_2606_22447_amd.vcs import SoftVcs, VcsBatch, soft_rollout
+    roms = [I.generate_rom(100 + i, sz, reads_inputs=True, timer_vblank=True)
+            for i, sz in enumerate([2048, 8192, 4096])]
+    B, PRE, S, tau = 12, 3, 2, 1.0
+    env_rom = (np.arange(B) % 3).astype(np.int32)
+    ram0 = I.initial_ram(22, B)
+    pre_act = I.action_stream(23, B, PRE)
+    w = I.Workload("soft_from_state", roms, env_rom, ram0, I.action_stream(24, B, S), S, 1, seed=22)
+    lv = I.soft_leaves(w, 9)
+    offs = w.rom_offsets()
+    dr = O.decode_logits(lv.rom_logits, tau)
+    da = O.decode_actions(lv.action_logits, tau)
+    hard_act = da[0].reshape(B, S)
+    rng = np.random.default_rng(4)
+    gf = (rng.standard_normal((B, 210, 160)) * 1e-3).astype(np.float32)
+    gr = (rng.standard_normal((B, S, 128)) * 1e-2).astype(np.float32)
+    # the hard steps run on the decoded ROM bytes: the soft steps continue the same machine
+    imgs = [(dr[0][offs[r]:offs[r] + roms[r].size], roms[r].mapper) for r in range(3)]
+    say("soft from state: hard pre-steps", PRE)
+    vb = VcsBatch(imgs, env_rom, frame_skip=1, kernel="grouped")
+    vb.reset(ram0=ram0)
+    vb.step(actions=pre_act, frames="none")
+    g_rom = np.zeros(lv.rom_logits.shape[0])
+    gsw, gin = np.zeros((B, S)), np.zeros((B, S))
+    refs = []
+    for b in range(B):
+        r = int(env_rom[b])
+        o, n = offs[r], roms[r].size
+        res = O.soft_env(dr[0][o:o + n], dr[1][o:o + n], roms[r].mapper, ram0[b], ram0[b].astype(np.float64),
+                         hard_act[b], da[1].reshape(B, S)[b], da[2].reshape(B, S)[b], S, 1, mode="ste",
+                         grad_frame=gf[b].astype(np.float64), grad_ram=gr[b].astype(np.float64),
+                         pre_actions=pre_act[b])
+        assert (res["g_ram0"] == 0).all()
+        full = O.run_env(dr[0][o:o + n], roms[r].mapper, ram0[b], np.concatenate([pre_act[b], hard_act[b]]),
+                         PRE + S, 1, frames="last")
+        assert (res["ram"] == full["ram"][PRE:]).all() and (res["frame"] == full["frames"][0]).all()
+        g_rom[o:o + n] += res["g_rom"]
+        gsw[b], gin[b] = res["g_swcha"], res["g_inpt4"]
+        refs.append(res)
+    ref_rom = O.epilogue_rom(lv.rom_logits, tau, g_rom)
+    ref_act = O.epilogue_action(lv.action_logits, tau, gsw.reshape(-1), gin.reshape(-1)).reshape(B, S, 18)
+    for G in (64, 4):
+        say("soft from state, lanes per env", G)
+        sim = SoftVcs(roms, env_rom, frame_skip=1, ckpt_interval=512, lanes_per_env=G, block_threads=256)
+        L = torch.from_numpy(lv.rom_logits).cuda()
+        A = torch.from_numpy(lv.action_logits).cuda()
+        state = vb.state.clone()
+        ram, frame, residual, _, st = sim.forward(L, None, A, tau, 6.0, want_state=True, state_in=state)
+        g = sim.backward(residual, L, None, A, tau, 6.0, torch.from_numpy(gf).cuda(), torch.from_numpy(gr).cuda(),
+                         check_overflow=True)
+        torch.cuda.synchronize()
+        ram, frame = ram.cpu().numpy(), frame.cpu().numpy()
+        for b in range(B):
+            assert (ram[b] == refs[b]["ram"]).all() and (frame[b] == refs[b]["frame"]).all(), b
+        assert g[1] is None
+        assert_grad_close(g[0].cpu().numpy(), ref_rom, "rom_logits")
+        assert_grad_close(g[2].cpu().numpy(), ref_act, "action_logits")
+        # the soft call's final state is the hard machine's after PRE + S steps
+        vh = VcsBatch(imgs, env_rom, frame_skip=1, kernel="grouped")
+        vh.reset(ram0=ram0)
+        vh.step(actions=np.concatenate([pre_act, hard_act], axis=1), frames="none")
+        assert torch.equal(vh.regs(), _regs_of(vh, st)) and torch.equal(vh.hash(), _hash_of(vh, st))
+    # autograd: the tape gets no gradient, the ROM and action logits get the oracle's
+    Lg = torch.from_numpy(lv.rom_logits).cuda().requires_grad_()
+    Ag = torch.from_numpy(lv.action_logits).cuda().requires_grad_()
+    ram, frame = soft_rollout(sim, Lg, None, Ag, tau, 6.0, state_in=vb.state.clone())
+    ((frame * torch.from_numpy(gf).cuda()).sum() + (ram * torch.from_numpy(gr).cuda()).sum()).backward()
+    assert_grad_close(Lg.grad.cpu().numpy(), ref_rom, "rom_logits (autograd)")
+    assert_grad_close(Ag.grad.cpu().numpy(), ref_act, "action_logits (autograd)")
+
+
+def _regs_of(vb, state):
+    saved = vb.state
+    vb.state = state
+    try:
+        return vb.regs()
+    finally:
+        vb.state = saved
+
+
+def _hash_of(vb, state):
+    saved = vb.state
+    vb.state = state
+    try:
+        return vb.hash()
+    finally:
+        vb.state = saved
+
+
+def test_soft_api_refuses_wrong_leaves():
+    """Leaves of the wrong dtype, shape, device or layout are refused before any launch."""
+    import torch
+    from paper_2606_22447_amd import binding as Bd
+    from paper_2606_22447_amd.vcs import SoftVcs
+    w = I.config_c3(num_envs=2)
+    lv = I.soft_leaves(w)
+    sim = SoftVcs(w.roms, w.env_rom, frame_skip=1)
+    L = torch.from_numpy(lv.rom_logits).cuda()
+    T = torch.from_numpy(lv.ram_tape).cuda()
+    A = torch.from_numpy(lv.action_logits).cuda()
+    for bad in (L.double(), L[:-1], L.cpu(), L.t().contiguous().t()):
+        with pytest.raises(Bd.VcsError):
+            sim.forward(bad, T, A, 1.0)
+    with pytest.raises(Bd.VcsError):
+        sim.forward(L, T[:, :64], A, 1.0)
+    with pytest.raises(Bd.VcsError):
+        sim.forward(L, None, A, 1.0)  # no tape and no starting state
+    _, _, res, _, _ = sim.forward(L, T, A, 1.0)
+    with pytest.raises(Bd.VcsError):
+        sim.backward(res, L, T, A, 1.0, 6.0, torch.zeros((2, 210, 161), device="cuda"))

@@ -65,3 +65,42 @@ def test_autotuner_picks_a_measured_shape_and_it_is_exact():
         torch.cuda.synchronize()
         outs.append((ram.cpu().numpy(), fr.cpu().numpy()))
     assert (outs[0][0] == outs[1][0]).all() and (outs[0][1] == outs[1][1]).all()
+
+
+def test_graph_keeps_what_it_reads_alive():
+    """A graph captured with host (numpy) episode lengths keeps its device copy,
+    the workspace and the batch alive: eager steps of another length on the same
+    batch between replays, and fresh allocations that would reuse freed memory,
+    change nothing."""
+    import gc
+    import torch
+    from paper_2606_22447_amd.vcs import VcsBatch
+    w = I.config_c2(envs_per_rom=4, steps=20, n_roms=4)
+    eps = np.minimum(w.episode_steps, 3 + np.arange(w.episode_steps.size).reshape(w.episode_steps.shape) % 4)
+    chunk, other = 3, 2
+    eager = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel="grouped")
+    graphed = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel="grouped")
+    eager.reset(ram0=w.ram0)
+    graphed.reset(ram0=w.ram0)
+    act = torch.from_numpy(np.ascontiguousarray(w.actions[:, :chunk])).cuda()
+    g, ram_g, fr_g, dn_g = graphed.capture(act, frames="last", episode_steps=eps.copy())
+    gc.collect()
+    col = 0
+    for k in range(3):
+        say("replay", k)
+        a_k = torch.from_numpy(np.ascontiguousarray(w.actions[:, col:col + chunk])).cuda()
+        act.copy_(a_k)
+        g.replay()
+        ram_e, fr_e, dn_e = eager.step(actions=a_k, frames="last", episode_steps=eps)
+        torch.cuda.synchronize()
+        assert torch.equal(ram_g, ram_e) and torch.equal(fr_g, fr_e) and torch.equal(dn_g, dn_e), k
+        col += chunk
+        # eager steps of another length on the graphed batch, then allocations over freed memory
+        a_o = np.ascontiguousarray(w.actions[:, col:col + other])
+        graphed.step(actions=a_o, frames="none", episode_steps=eps)
+        eager.step(actions=a_o, frames="none", episode_steps=eps)
+        junk = [torch.full((1 << 20,), 0xA5, dtype=torch.uint8, device="cuda") for _ in range(8)]
+        torch.cuda.synchronize()
+        del junk
+        col += other
+    assert torch.equal(graphed.hash(), eager.hash())

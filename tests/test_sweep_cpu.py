@@ -94,33 +94,39 @@ def _close(g, ref, name):
     assert (g[ref == 0] == 0).all(), name
 
 
-@pytest.mark.parametrize("K", [256, 4096])
-def test_host_soft_backward_matches_oracle_on_the_sweep(host_lib, K):
+@pytest.mark.parametrize("K,pre", [(256, 0), (4096, 0), (512, 2)])
+def test_host_soft_backward_matches_oracle_on_the_sweep(host_lib, K, pre):
     """The soft forward (= hard) and the surrogate backward of the library, built
     for the host, against the FP64 oracle on every sweep image: raw gradients of
-    the ROM byte values, the initial RAM and the port reads."""
-    w = I.config_sweep(envs_per_rom=2, steps=2, frame_skip=1, episodes=False)
+    the ROM byte values, the initial RAM and the port reads; from power-on, and
+    (pre > 0) continuing the state reached by `pre` hard env steps, whose RAM is
+    then a constant."""
+    w = I.config_sweep(envs_per_rom=2, steps=2 + pre, frame_skip=1, episodes=False)
     rng = np.random.default_rng(11)
     ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
-    S = w.steps
+    S = 2
     for b in range(w.num_envs):
         rom = w.roms[int(w.env_rom[b])]
+        pre_act, act = np.ascontiguousarray(w.actions[b, :pre]), np.ascontiguousarray(w.actions[b, pre:])
         gf = (rng.standard_normal((210, 160)) * 1e-3).astype(np.float32)
         gr = (rng.standard_normal((S, 128)) * 1e-2).astype(np.float32)
-        sw = np.array([O.action_ports(int(a))[0] for a in w.actions[b]], np.float64)
-        inp = np.array([O.action_ports(int(a))[1] for a in w.actions[b]], np.float64)
+        sw = np.array([O.action_ports(int(a))[0] for a in act], np.float64)
+        inp = np.array([O.action_ports(int(a))[1] for a in act], np.float64)
         ref = O.soft_env(rom.image, rom.image.astype(np.float64), rom.mapper, w.ram0[b],
-                         w.ram0[b].astype(np.float64), w.actions[b], sw, inp, S, 1, mode="ste",
-                         grad_frame=gf.astype(np.float64), grad_ram=gr.astype(np.float64))
+                         w.ram0[b].astype(np.float64), act, sw, inp, S, 1, mode="ste",
+                         grad_frame=gf.astype(np.float64), grad_ram=gr.astype(np.float64),
+                         pre_actions=pre_act if pre else None)
         ram = np.zeros((S, 128), np.float32)
         fr = np.zeros((210, 160), np.float32)
         g_rom = np.zeros(rom.size, np.float32)
         g0 = np.zeros(128, np.float32)
         gp = np.zeros((S, 2), np.float32)
         n = host_lib.host_soft(ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
-                               ptr(np.ascontiguousarray(w.ram0[b])), ptr(np.ascontiguousarray(w.actions[b])), S, 1, K,
+                               ptr(np.ascontiguousarray(w.ram0[b])), pre, ptr(pre_act), ptr(act), S, 1, K,
                                ptr(gf), ptr(gr), ptr(ram), ptr(fr), ptr(g_rom), ptr(g0), ptr(gp))
         assert n >= 0, "tape overflow"
+        if pre:
+            assert (g0 == 0).all()
         assert (ram == ref["ram"]).all() and (fr == ref["frame"]).all(), b
         _close(g_rom, ref["g_rom"], f"rom env {b}")
         _close(g0, ref["g_ram0"], f"ram0 env {b}")
