@@ -177,6 +177,29 @@ int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, 
                              uint8_t *d_done, const uint32_t *d_episode_steps, int32_t num_episodes,
                              hipStream_t stream);
 
+/* FULL relaxed hard steps: vcs_step_hard (same arguments and outputs, no
+ * episodes) with the relaxation applied without the straight-through
+ * correction (Table s-modes, "full"; Sec. "Forward Bit-Exactness Under Full
+ * Relaxation").  While an instruction executes, every read of a ROM byte or a
+ * RAM cell (opcode and the two bytes after it, operands, pointers, pulls)
+ * returns the distance-softmax read of Eq. s-read over the byte and its
+ * neighbours |k| <= 8 in the same array (ROM image or the 128 RAM cells), with
+ * weights e^{-|k|/T} normalised over those, cast back to a byte; every branch
+ * moves the pc by sigma(alpha z) times its offset (Eq. s-branch, z = +1
+ * taken, -1 not) and is cast.  Sums in float32 without fused multiply-adds,
+ * weights e^{-k/T} and sigma(+-alpha) computed in double and stored as float,
+ * casts round to nearest (ties to even).  The machine runs on the cast values.
+ *  alpha > 0, T > 0   branch sharpness and read temperature;
+ *  d_relax_out        int64 [B][2] (8-byte aligned): the first instruction
+ *                     (counted from the call's start, 0-based) whose cast
+ *                     differed from the exact value, -1 if none (N_div); and
+ *                     the number of such casts.
+ * The launch geometry is the context's (its lanes per env and threads per
+ * workgroup; the interpreter runs whatever the context's kernel). */
+int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                         uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, double alpha, double T,
+                         int64_t *d_relax_out, void *d_work, hipStream_t stream);
+
 /* SOFT-STE forward of S env steps (Theorem "Exact forward equivalence": its
  * values equal HARD at any tau and alpha), the paper's env step state + action
  * -> next state (Sec. "Building Two Differentiable VCS Ports") taken softly:

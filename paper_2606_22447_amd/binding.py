@@ -25,7 +25,7 @@ EXPORTED = [
     "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
     "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
     "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash", "vcs_translate",
-    "vcs_translated_source", "vcs_step_hard_static", "vcs_bwd_overflow_offset",
+    "vcs_translated_source", "vcs_step_hard_static", "vcs_bwd_overflow_offset", "vcs_step_relaxed",
 ]
 
 
@@ -77,6 +77,7 @@ def lib():
         L.vcs_reset.argtypes = [vp, vp, vp, vp, vp]
         L.vcs_step_hard.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp, vp]
         L.vcs_step_hard_static.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp]
+        L.vcs_step_relaxed.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, C.c_double, C.c_double, vp, vp, vp]
         L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.vcs_step_soft_bwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.vcs_read_regs.argtypes = [vp, vp, vp, vp]

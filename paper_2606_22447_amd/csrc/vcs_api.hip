@@ -1,6 +1,7 @@
 // C-ABI of libvcs (declared in include/vcs.h): argument validation, launch
 // geometry and the layout of caller-owned device buffers.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -487,6 +488,37 @@ int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, 
         return VCS_HIP_ERROR;
     return launch_step_hard(ctx, d_rom, d_state, d_actions, steps, d_ram_out, frames, d_frame_out, d_done,
                             d_episode_steps, num_episodes, tables, stream);
+}
+
+// FULL relaxed hard steps: the launch of vcs_step_hard with the relaxing kernel.
+int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
+                         uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, double alpha, double T,
+                         int64_t *d_relax_out, void *d_work, hipStream_t stream) {
+    int32_t rc = check_step_hard_args(ctx, d_rom, d_state, steps, d_ram_out, frames, d_frame_out, nullptr, 0);
+    if (rc) return rc;
+    if (!d_work || !aligned16(d_work) || !d_relax_out || ((uintptr_t)d_relax_out & 7u)) return VCS_INVALID_ARG;
+    if (!(alpha > 0.0) || !(T > 0.0) || !std::isfinite(alpha) || !std::isfinite(T)) return VCS_INVALID_ARG;
+    rc = upload_static(ctx, d_work, stream);
+    if (rc) return rc;
+    StepParams P{};
+    P.st = static_ptrs(ctx, d_work);
+    P.rom = d_rom;
+    P.state = (StateRec *)d_state;
+    P.actions = d_actions;
+    P.steps = steps;
+    P.frame_skip = ctx->F;
+    P.ystart = ctx->ystart;
+    P.frames_mode = frames;
+    P.ram_out = d_ram_out;
+    P.frame_out = frames == VCS_FRAMES_NONE ? nullptr : d_frame_out;
+    P.seed = ctx->seed;
+    // the weights and gates in double, stored as float (the kernel sums in float)
+    P.relax_u[0] = 1.0f;
+    for (int k = 1; k <= 8; ++k) P.relax_u[k] = (float)std::exp(-(double)k / T);
+    P.relax_g_taken = (float)(1.0 / (1.0 + std::exp(-alpha)));
+    P.relax_g_not = (float)(1.0 / (1.0 + std::exp(alpha)));
+    P.relax_out = d_relax_out;
+    return hip_status(launch_step_relaxed(P, ctx->main_blocks, ctx->G, ctx->tpb, ctx->max_rom, stream));
 }
 
 int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, char *buf,

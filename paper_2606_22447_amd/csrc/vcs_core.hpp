@@ -298,23 +298,6 @@ __host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int
     });
 }
 
-// Per-owner sums of dL/dpixel over [from, to) (soft backward): sums[r] for owner r.
-__host__ __device__ __forceinline__ bool pixel_sums(const float *gframe, int32_t from, int32_t to, uint32_t pf,
-                                                    uint32_t vb, int32_t ystart, float sums[4]) {
-    bool any = false;
-    if (vb & 2u) return false;  // blanked pixels are constants
-    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
-    for_each_group(from, to, ystart, 0u, 1u, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
-        const float *row = gframe + y * kScreenW;
-        float acc = 0.f;
-        for (int32_t x = xa; x < xb; ++x) acc += row[x];
-        const uint32_t o = group_owner((uint32_t)g, mask, ctrl);
-        for (uint32_t k = 0; k < 4; ++k) sums[k] += o == k ? acc : 0.f;  // constant indices: stays in registers
-        any = true;
-    });
-    return any;
-}
-
 // ---------------------------------------------------------------------------
 // Data classes for the soft backward (where a value comes from / goes to)
 // ---------------------------------------------------------------------------
@@ -421,8 +404,12 @@ struct Cpu {
     // RAM from $80.  These are read/write for such addresses (zero-page modes,
     // zero-page pointers, the stack at $100 | s), with the page bits dropped.
     __host__ __device__ __forceinline__ uint32_t read_zp(uint32_t a8) {
-        const uint32_t r = mem.ram_byte(a8 & 0x7Fu), t = tia_in(a8);  // both, then select: no branch
-        return (a8 & 0x80u) ? r : t;
+        if constexpr (Mem::kRelax) {  // a relaxed RAM read happens only for a RAM address
+            return (a8 & 0x80u) ? mem.ram_byte(a8 & 0x7Fu) : tia_in(a8);
+        } else {
+            const uint32_t r = mem.ram_byte(a8 & 0x7Fu), t = tia_in(a8);  // both, then select: no branch
+            return (a8 & 0x80u) ? r : t;
+        }
     }
     __host__ __device__ __forceinline__ void write_zp(uint32_t a8, uint32_t v, int32_t w) {
         if (a8 & 0x80u) mem.ram_set(a8 & 0x7Fu, v);
@@ -715,10 +702,11 @@ struct Cpu {
                     const uint32_t mask = (d >> 16) & 0xFFu, when_set = (d >> 24) & 1u;
                     const uint32_t f = mask == kFlagN ? (rn >> 7) & 1u
                                      : mask == kFlagZ ? ((rz & 0xFFu) ? 0u : 1u) : ((p & mask) ? 1u : 0u);
-                    const uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
                     const bool taken = f == when_set;
+                    uint32_t target = (pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu;
+                    if constexpr (Mem::kRelax) target = mem.branch(pc, lo, taken);  // relaxed and cast
                     n += taken ? 1 + (((target ^ pc) & 0xFF00u) ? 1 : 0) : 0;
-                    pc = taken ? target : pc;
+                    pc = (taken || Mem::kRelax) ? target : pc;
                     break;
                 }
                 case C_FLAG: {

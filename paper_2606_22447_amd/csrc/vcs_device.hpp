@@ -16,6 +16,24 @@ __constant__ DecodeTable kDecodeDev = make_decode_table();
 typedef const __attribute__((address_space(4))) uint32_t ConstU32;
 
 struct DeviceWave {
+    static constexpr uint32_t kWidth = 64;  // lanes of a wave
+    __device__ static __forceinline__ uint32_t lane() { return __lane_id(); }
+    // value of v in lane j (j the same in every lane: a scalar)
+    __device__ static __forceinline__ uint32_t readlane(uint32_t v, uint32_t j) {
+        return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)j);
+    }
+    __device__ static __forceinline__ float readlane(float v, uint32_t j) {
+        return __uint_as_float(readlane(__float_as_uint(v), j));
+    }
+    // v with lane j's element replaced by x (x and j the same in every lane)
+    __device__ static __forceinline__ float writelane(float v, float x, uint32_t j) {
+        return lane() == j ? x : v;
+    }
+    // sum of v over the wave's lanes (every lane gets it)
+    __device__ static __forceinline__ float sum(float v) {
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        return v;
+    }
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
     __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
     // *p += t without waiting for the result (a no-return atomic add).  Only one lane
@@ -60,6 +78,36 @@ __device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, 
     __syncthreads();
     LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
     step_env<DeviceWave, G, kSoft, false, X>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
+}
+
+// Body of the FULL relaxed step kernel: the grouped kernel's layout with the
+// relaxing memory policy (hard steps, interpreter only).
+template <int G, int TPB>
+__device__ __forceinline__ void step_group_relaxed(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds,
+                                                   uint32_t *dec_lds) {
+    constexpr int E = TPB / G;
+    const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
+    const int32_t blk = blockIdx.x;
+    const int32_t rom_idx = P.st.main_block_rom[blk];
+    const int32_t env = P.st.main_slot_env[blk * E + slot];
+    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
+    const int32_t mapper = P.st.rom_mapper[rom_idx];
+    for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
+        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
+    for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
+    __syncthreads();
+    RelaxMem<LdsWordMem> m;
+    static_cast<LdsWordMem &>(m) = LdsWordMem{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E,
+                                              slot};
+    for (int k = 0; k < 9; ++k) m.rc.u[k] = P.relax_u[k];
+    m.rc.g_taken = P.relax_g_taken;
+    m.rc.g_not = P.relax_g_not;
+    m.rom_n = (uint32_t)rom_size;
+    m.active = false;
+    m.ninstr = 0;
+    m.ndiv = -1;
+    m.fails = 0;
+    step_env<DeviceWave, G, false, false, InterpExec>(P, env, sub, mapper, m, kDecodeDev.e);
 }
 
 }  // namespace vcs

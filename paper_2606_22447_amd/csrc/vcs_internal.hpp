@@ -100,6 +100,10 @@ struct StepParams {
     int32_t *ckpt_count;       // [B]
     int32_t ckpt_interval;
     int32_t max_ckpt;
+    // FULL relaxed mode (vcs_step_relaxed)
+    float relax_u[9];          // e^{-k/T}, k = 0..8
+    float relax_g_taken, relax_g_not;
+    int64_t *relax_out;        // [B][2]: first diverging instruction (-1: none), casts that differed
 };
 
 // One record of the soft backward's recompute tape (32 bytes).

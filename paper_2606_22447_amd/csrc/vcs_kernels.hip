@@ -42,8 +42,19 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
     }
 }
 
+// FULL relaxed hard steps (vcs_step_relaxed): the grouped layout with every ROM
+// and RAM read and every branch relaxed and cast (Table s-modes).
+template <int G, int TPB>
+__global__ __launch_bounds__(TPB) void k_step_relaxed(StepParams P) {
+    constexpr int E = TPB / G;
+    extern __shared__ __align__(16) uint2 rom_lds[];
+    __shared__ __align__(16) uint32_t ram_lds[32 * E];
+    __shared__ uint32_t dec_lds[256];
+    step_group_relaxed<G, TPB>(P, rom_lds, ram_lds, dec_lds);
+}
+
 // ---------------------------------------------------------------------------
-// Soft backward: one env per wave (its first lane), kBwdSlots envs of one ROM
+// Soft backward: one env per wave (all its lanes), kBwdSlots envs of one ROM
 // per workgroup sharing the pre-decoded ROM words in LDS.  The
 // recompute-and-reverse chain of an env is serial, so the envs are spread over
 // as many waves as possible to interleave their latency.
@@ -55,8 +66,8 @@ __global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
     extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
     __shared__ uint32_t dec_lds[256];
     __shared__ __align__(16) uint32_t ram_lds[32 * E];
-    __shared__ float adj_ram[128 * E];
-    const uint32_t tid = threadIdx.x, slot = tid / 64;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(tid / 64);  // the wave's env slot (a scalar)
     const int32_t blk = blockIdx.x;
     const uint32_t nslots = (uint32_t)gridDim.x * E;
     const uint32_t gslot = (uint32_t)blk * E + slot;
@@ -67,10 +78,9 @@ __global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
         rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
     for (int32_t i = (int32_t)tid; i < 256; i += kBwdTPB) dec_lds[i] = kDecodeDev.e[i];
     __syncthreads();
-    if ((tid & 63u) != 0) return;
     const int32_t env = P.st.bwd_slot_env[gslot];
     LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
-    bwd_env<DeviceWave>(P, env, gslot, nslots, mapper, m, adj_ram + slot, E, kDecodeDev.e);
+    bwd_env<DeviceWave>(P, env, gslot, nslots, mapper, m, kDecodeDev.e);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,6 +410,26 @@ hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32
     VCS_STEP_CASE(64, 64)
     VCS_STEP_CASE(64, 256)
 #undef VCS_STEP_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, int32_t max_rom_size,
+                               hipStream_t stream) {
+    const size_t lds = (size_t)max_rom_size * sizeof(uint2);
+#define VCS_RELAX_CASE(Gv, Tv)                                                                          \
+    if (lanes == Gv && tpb == Tv) {                                                                     \
+        hipLaunchKernelGGL((k_step_relaxed<Gv, Tv>), dim3(blocks), dim3(Tv), lds, stream, P);           \
+        return hipGetLastError();                                                                       \
+    }
+    VCS_RELAX_CASE(1, 64)
+    VCS_RELAX_CASE(1, 256)
+    VCS_RELAX_CASE(4, 64)
+    VCS_RELAX_CASE(4, 256)
+    VCS_RELAX_CASE(16, 64)
+    VCS_RELAX_CASE(16, 256)
+    VCS_RELAX_CASE(64, 64)
+    VCS_RELAX_CASE(64, 256)
+#undef VCS_RELAX_CASE
     return hipErrorInvalidValue;
 }
 

@@ -7,6 +7,8 @@ namespace vcs {
 
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
                        int32_t max_rom_size, hipStream_t stream);
+hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, int32_t max_rom_size,
+                               hipStream_t stream);
 hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream);
 hipError_t launch_decode(const float *rom_logits, int64_t rom_rows, const float *tape, int64_t tape_rows,
                          const float *act_logits, int64_t act_rows, float tau, uint8_t *rom_hard, float *rom_stats,

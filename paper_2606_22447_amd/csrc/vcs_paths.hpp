@@ -16,6 +16,7 @@ namespace vcs {
 // LDS: ROM image bytes; RAM as words [32][E] so that the 4 bytes of a word
 // belong to one env and neighbouring envs hit neighbouring banks.
 struct LdsMem {
+    static constexpr bool kRelax = false;
     const uint8_t *rom;
     uint8_t *ram;
     uint32_t E, slot;
@@ -40,6 +41,7 @@ struct LdsMem {
 // opcode, both operand bytes and the opcode's decode.  dec is the decode
 // table (256 entries), also in LDS.
 struct LdsWordMem {
+    static constexpr bool kRelax = false;
     const uint2 *rom;
     const uint32_t *dec;
     uint8_t *ram;
@@ -110,6 +112,7 @@ __host__ __device__ __forceinline__ void fetch_word(C &c, uint32_t &opc, uint32_
 
 // Global memory: the env's ROM image and its 128 RAM bytes in the state record.
 struct GlobalMem {
+    static constexpr bool kRelax = false;
     const uint8_t *rom;
     uint8_t *ram;
     __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off]; }
@@ -117,6 +120,80 @@ struct GlobalMem {
     __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) { ram[cell] = (uint8_t)v; }
     __host__ __device__ __forceinline__ uint32_t ram_word(uint32_t w) const { return reinterpret_cast<const uint32_t *>(ram)[w]; }
     __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) { reinterpret_cast<uint32_t *>(ram)[w] = v; }
+};
+
+// FULL relaxed mode (the paper's relaxation without the straight-through
+// correction, Table s-modes; Sec. "Forward Bit-Exactness Under Full
+// Relaxation"): while an instruction executes, every read of a ROM byte or a
+// RAM cell returns the distance-softmax blend of Eq. s-read over the byte and
+// its neighbours |k| <= 8 inside the same array (ROM image or the 128 RAM
+// cells), with weights e^{-|k|/T}, cast back to a byte (round to nearest,
+// ties to even); the branch of Eq. s-branch moves the pc by sigma(alpha z)
+// times its offset and is cast likewise (see Cpu::exec_body).  Float32 sums in
+// a fixed order without fused multiply-adds, so the casts are those of a
+// plain float32 evaluation.  The first instruction whose cast differed from
+// the exact value (ndiv, counted from the call's start; -1: none) and the
+// number of such casts are recorded; the machine then runs on the cast
+// values.  A policy over a memory policy Base, selected at compile time: the
+// exact kernels never see it.
+struct RelaxConst {
+    float u[9];            // u[k] = e^{-k/T} (u[0] = 1)
+    float g_taken, g_not;  // sigma(alpha), sigma(-alpha)
+};
+template <class Base>
+struct RelaxMem : Base {
+    static constexpr bool kRelax = true;
+    RelaxConst rc;
+    uint32_t rom_n;   // bytes of the image
+    bool active;      // an instruction is executing
+    int64_t ninstr;   // instructions completed since the call's start
+    int64_t ndiv;
+    uint32_t fails;
+    __host__ __device__ __forceinline__ void note() {
+        if (ndiv < 0) ndiv = ninstr;
+        ++fails;
+    }
+    // Eq. s-read at index a of an array of n bytes read by get(i)
+    template <class Get>
+    __host__ __device__ __forceinline__ uint32_t blend(Get get, uint32_t a, uint32_t n) {
+#pragma clang fp contract(off)
+        const uint32_t exact = get(a);
+        const float ra = (float)exact;
+        float num = 0.f, den = 1.f;
+        for (uint32_t k = 1; k <= 8; ++k) {
+            const float u = rc.u[k];
+            if (a + k < n) {
+                num = num + u * ((float)get(a + k) - ra);
+                den = den + u;
+            }
+            if (a >= k) {
+                num = num + u * ((float)get(a - k) - ra);
+                den = den + u;
+            }
+        }
+        const int32_t v = (int32_t)__builtin_rintf(ra + num / den);
+        if (v != (int32_t)exact) note();
+        return (uint32_t)v & 0xFFu;
+    }
+    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) {
+        if (!active) return Base::rom_byte(off);
+        return blend([&](uint32_t i) { return Base::rom_byte(i); }, off, rom_n);
+    }
+    __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) {
+        if (!active) return Base::ram_byte(cell);
+        return blend([&](uint32_t i) { return Base::ram_byte(i); }, cell, 128u);
+    }
+    // Eq. s-branch without the straight-through correction: the flag is crisp
+    // (z = +1 taken, -1 not), pc' = round(pc + sigma(alpha z) delta)
+    __host__ __device__ __forceinline__ uint32_t branch(uint32_t pc, uint32_t lo, bool taken) {
+#pragma clang fp contract(off)
+        const float gz = taken ? rc.g_taken : rc.g_not;
+        const int32_t cast = (int32_t)__builtin_rintf((float)pc + gz * (float)(int32_t)(int8_t)lo);
+        const uint32_t hard = taken ? ((pc + (uint32_t)(int32_t)(int8_t)lo) & 0xFFFFu) : pc;
+        const uint32_t got = (uint32_t)cast & 0xFFFFu;
+        if (got != hard) note();
+        return got;
+    }
 };
 
 // ---------------------------------------------------------------------------
@@ -281,13 +358,40 @@ struct RenderHook {
     }
 };
 
+// Per-owner sums of dL/dpixel over [from, to) by the lanes of a wave (the soft
+// backward runs one env per wave): lane l takes every kWidth-th 4-pixel group of
+// each line, then the wave sums the four partial sums.  Returns (the same in
+// every lane) whether any visible pixel lies in the span.
+template <class W>
+__host__ __device__ __forceinline__ bool pixel_sums_wave(const float *gframe, int32_t from, int32_t to, uint32_t pf,
+                                                         uint32_t vb, int32_t ystart, float sums[4]) {
+    if (vb & 2u) return false;  // blanked pixels are constants
+    const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
+    if (to <= vis0 || from >= vis1) return false;
+    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
+    float part[4] = {0.f, 0.f, 0.f, 0.f};
+    bool any = false;
+    for_each_group(from, to, ystart, W::lane(), W::kWidth, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+        const float *row = gframe + y * kScreenW;
+        float acc = 0.f;
+        for (int32_t x = xa; x < xb; ++x) acc += row[x];
+        const uint32_t o = group_owner((uint32_t)g, mask, ctrl);
+        for (uint32_t k = 0; k < 4; ++k) part[k] += o == k ? acc : 0.f;  // constant indices: stays in registers
+        any = true;
+    });
+    if (!W::any(any)) return false;
+    for (uint32_t k = 0; k < 4; ++k) sums[k] += W::sum(part[k]);
+    return true;
+}
+
 // Records the recompute tape of the soft backward.  Pixels of the final frame
 // are attributed to the instruction during whose span [previous write point,
-// this write point) they were drawn, with the state before its write.
+// this write point) they were drawn, with the state before its write.  Every
+// lane of the env's wave runs the recompute; lane 0 stores the records.
+template <class W>
 struct TapeHook {
     static constexpr bool kRecord = true;
     TapeRec *tape;
-    uint32_t stride;
     int32_t nrec, max_rec;
     const float *gframe;  // env's dL/dframe while in the final frame, else nullptr
     int32_t pix_cc;
@@ -295,9 +399,13 @@ struct TapeHook {
     uint32_t step;
     uint32_t save_pf, save_vb;
     int32_t *overflow;
+    bool lead;            // the lane that stores
     __host__ __device__ __forceinline__ void emit(const TapeRec &r) {
-        if (nrec < max_rec) tape[(size_t)nrec * stride] = r;
-        else *overflow = 1;
+        if (nrec < max_rec) {
+            if (lead) tape[nrec] = r;
+        } else if (lead) {
+            *overflow = 1;
+        }
         ++nrec;
     }
     template <class C>
@@ -315,10 +423,41 @@ struct TapeHook {
         r.w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
         r.w3 = step;
         r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
-        if (gframe && pixel_sums(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) r.w0 |= 1u << 20;
+        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) r.w0 |= 1u << 20;
         pix_cc = 3 * wp;
         emit(r);
     }
+};
+
+// The soft backward's RAM adjoint, 128 floats held across the lanes of the
+// env's wave: cell c is element c / kWidth of lane c % kWidth.  Cells are
+// addressed by wave-uniform indices (read and written with readlane /
+// writelane), so the reverse sweep touches no memory for them.
+template <class W>
+struct RamAdjoint {
+    static constexpr uint32_t NW = W::kWidth, CPL = 128 / NW;
+    float v[CPL];
+    __host__ __device__ __forceinline__ void zero() {
+        for (uint32_t i = 0; i < CPL; ++i) v[i] = 0.f;
+    }
+    __host__ __device__ __forceinline__ float get(uint32_t c) const {
+        if constexpr (NW == 1) {
+            return v[c];
+        } else {
+            float r = v[0];
+            for (uint32_t i = 1; i < CPL; ++i) r = (c / NW == i) ? v[i] : r;
+            return W::readlane(r, c % NW);
+        }
+    }
+    __host__ __device__ __forceinline__ void set(uint32_t c, float x) {
+        if constexpr (NW == 1) {
+            v[c] = x;
+        } else {
+            for (uint32_t i = 0; i < CPL; ++i)
+                if (c / NW == i) v[i] = W::writelane(v[i], x, c % NW);
+        }
+    }
+    // element i of this lane is cell lane + NW * i
 };
 
 // ---------------------------------------------------------------------------
@@ -436,7 +575,30 @@ template <class W, bool kPlain, class C>
 __host__ __device__ __forceinline__ void interp_one(C &c, const uint32_t *decode) {
     uint32_t opc, lo, hi;
     ExecInfo info;
-    if constexpr (kPlain) {
+    if constexpr (std::decay_t<decltype(c.mem)>::kRelax) {
+        // FULL relaxed mode: the opcode and both bytes after it are read (relaxed) for
+        // every instruction that does not jam, then the lanes' opcodes run one per pass
+        c.mem.active = true;
+        opc = c.peek(c.pc, c.cyc);
+        const uint32_t dj = decode[opc];
+        if (dj == 0) {
+            c.jam = 1;
+        } else {
+            lo = c.peek((c.pc + 1u) & 0xFFFFu, c.cyc);
+            hi = c.peek((c.pc + 2u) & 0xFFFFu, c.cyc);
+        }
+        for (bool more = dj != 0; W::any(more);) {
+            if (more) {
+                const uint32_t u2 = W::first(opc);
+                if (opc == u2) {
+                    c.exec(u2, W::first(dj), lo, hi, info);
+                    ++c.mem.ninstr;
+                    more = false;
+                }
+            }
+        }
+        c.mem.active = false;
+    } else if constexpr (kPlain) {
         fetch3(c, opc, lo, hi);
         const uint32_t d = decode[opc];
         if (d == 0) c.jam = 1;
@@ -707,44 +869,57 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         if constexpr (kSoft) {
             if (P.ckpt_count && sub == 0) P.ckpt_count[env] = nckpt;
         }
+        if constexpr (Mem::kRelax) {
+            if (P.relax_out && sub == 0) {
+                P.relax_out[(size_t)env * 2] = c.mem.ndiv;
+                P.relax_out[(size_t)env * 2 + 1] = (int64_t)c.mem.fails;
+            }
+        }
     }
 }
 
-// Soft backward of one env: segments from last to first are recomputed from
-// their checkpoint into the tape and swept in reverse.  adj_ram is the env's
-// RAM adjoint, float [128] with stride E.  The env's lane must be the only
-// active lane of its wave.
+// Soft backward of one env, run by every lane of its wave: segments from last
+// to first are recomputed from their checkpoint into the tape (the env's
+// records, contiguous) and swept in reverse.  The sweep reads the records a
+// wave-width at a time (lane l loads one record; the next batch is in flight
+// while the current one is processed) and takes each one's fields from its lane
+// with readlane, so its branches are scalar and no record load waits in the
+// loop; the RAM adjoint lives in the lanes' registers (RamAdjoint).  ROM and
+// port gradients are accumulated by lane 0 with no-return atomic adds (one
+// lane per address: program order, deterministic).
 template <class W, class Mem>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
-                                                 int32_t mapper, Mem mem, float *adj_ram, uint32_t E,
-                                                 const uint32_t *decode) {
+                                                 int32_t mapper, Mem mem, const uint32_t *decode) {
+    constexpr uint32_t NW = W::kWidth;
+    const uint32_t lane = W::lane();
+    const bool lead = lane == 0;
     const bool live = env >= 0;
     const int32_t S = P.steps, F = P.frame_skip;
-    for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] = 0.f;
+    RamAdjoint<W> adj;
+    adj.zero();
 
-    Cpu<Mem, TapeHook> c;
+    Cpu<Mem, TapeHook<W>> c;
     c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
     c.f8 = mapper == 2 ? 1u : 0u;
     c.mem = mem;
     c.hook.tape = P.tape + (size_t)gslot * (size_t)P.max_rec;  // the env's records, contiguous
-    c.hook.stride = 1;
     c.hook.max_rec = P.max_rec;
     c.hook.ystart = P.ystart;
     c.hook.overflow = P.overflow;
+    c.hook.lead = lead;
 
     float aA = 0.f, aX = 0.f, aY = 0.f;
     float aC[4] = {0.f, 0.f, 0.f, 0.f};
     const float *gframe_env = live ? P.grad_frame + (size_t)env * kPixels : nullptr;
     // segment i starts from checkpoint i (checkpoint 0: the forward's starting state)
     const int32_t nseg = live ? (P.ckpt_count[env] < P.max_ckpt ? P.ckpt_count[env] : P.max_ckpt) : 0;
-    int32_t seg = nseg - 1;
 
     auto add_src = [&](uint32_t cls, uint32_t idx, uint32_t step, float t) {
         switch (cls) {
-            case kClsRam: adj_ram[idx * E] += t; break;
-            case kClsRom: W::accumulate(&P.gpart[(size_t)idx * nslots + gslot], t); break;
-            case kClsSwcha: W::accumulate(&P.gport[((size_t)env * S + step) * 2], t); break;
-            case kClsInpt4: W::accumulate(&P.gport[((size_t)env * S + step) * 2 + 1], t); break;
+            case kClsRam: adj.set(idx, adj.get(idx) + t); break;
+            case kClsRom: if (lead) W::accumulate(&P.gpart[(size_t)idx * nslots + gslot], t); break;
+            case kClsSwcha: if (lead) W::accumulate(&P.gport[((size_t)env * S + step) * 2], t); break;
+            case kClsInpt4: if (lead) W::accumulate(&P.gport[((size_t)env * S + step) * 2 + 1], t); break;
             case kClsRegA: aA += t; break;
             default: break;
         }
@@ -752,8 +927,8 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     auto take_dst = [&](uint32_t cls, uint32_t idx) -> float {
         float t = 0.f;
         if (cls == kClsRam) {
-            t = adj_ram[idx * E];
-            adj_ram[idx * E] = 0.f;
+            t = adj.get(idx);
+            adj.set(idx, 0.f);
         } else if (cls == kClsCol) {
             t = aC[0] * (idx == 0) + aC[1] * (idx == 1) + aC[2] * (idx == 2) + aC[3] * (idx == 3);
             aC[0] = idx == 0 ? 0.f : aC[0];
@@ -771,177 +946,185 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
         const uint32_t cls = write_class(0x100u | (cell & 0xFFu), &idx);
         (void)take_dst(cls, idx);
     };
-
-    while (W::any(seg >= 0)) {
-        if (seg >= 0) {
-            // ---- restore the segment's starting state
-            const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + seg];
-            c.load(r);
-            c.bank &= c.f8;
-            const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
-            for (uint32_t w = 0; w < 32; ++w) c.mem.ram_word_set(w, rw[w]);
-            uint32_t frame = r.frame;
-            c.hook.pix_cc = r.pix_cc;
-            const int64_t seg_end = seg == nseg - 1 ? INT64_MAX : r.next_ckpt;
-            int32_t s_idx = (int32_t)(frame / (uint32_t)F), fstep = (int32_t)(frame % (uint32_t)F);
-            c.hook.nrec = 0;
-            auto set_ports = [&]() {
-                action_ports(P.actions[(size_t)env * S + s_idx], &c.swcha, &c.inpt4);
-                c.hook.step = (uint32_t)s_idx;
-                c.hook.gframe = (s_idx == S - 1 && fstep == F - 1) ? gframe_env : nullptr;
-            };
-            bool rec_active = s_idx < S;
-            if (rec_active) set_ports();
-
-            // ---- recompute the segment, recording the tape
-            while (W::any(rec_active)) {
-                if (rec_active) {
-                    const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
-                    if (g >= seg_end) {
-                        rec_active = false;
-                    } else if (c.jam || c.cyc >= kCyclesPerFrame) {
-                        if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;
-                        if (c.hook.gframe) {  // tail of the final frame
-                            TapeRec r;
-                            r.w0 = kRecPixels << 16;
-                            r.w1 = r.w2 = 0;
-                            r.w3 = (uint32_t)s_idx;
-                            r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
-                            pixel_sums(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.pf, c.vb, c.hook.ystart, r.pix);
-                            c.hook.emit(r);
-                        }
-                        c.next_frame();
-                        c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
-                        ++frame;
-                        if (++fstep == F) {
-                            TapeRec r;
-                            r.w0 = kRecStepEnd << 16;
-                            r.w1 = r.w2 = 0;
-                            r.w3 = (uint32_t)s_idx;
-                            r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
-                            c.hook.emit(r);
-                            fstep = 0;
-                            if (++s_idx == S) rec_active = false;
-                        }
-                        if (rec_active) set_ports();
-                    } else {
-                        uint32_t opc, lo, hi, dec;
-                        fetch_word<W>(c, opc, lo, hi, dec);
-                        ExecInfo info;
-                        // the env's lane runs alone, so its opcode is wave-uniform
-                        const uint32_t u = W::first(opc);
-                        const uint32_t d = W::first(dec);
-                        if (d == 0) c.jam = 1;
-                        else exec_dispatch<W>(c, u, d, lo, hi, info);
-                    }
-                }
+    // the reverse-sweep rule of one record (fields already wave-uniform)
+    auto sweep_one = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t step, const float pix[4]) {
+        const uint32_t kind = (w0 >> 16) & 15u;
+        if (kind == kRecStepEnd) {
+            if (P.grad_ram_out) {
+                const float *gr = P.grad_ram_out + ((size_t)env * S + step) * 128;
+                for (uint32_t i = 0; i < RamAdjoint<W>::CPL; ++i) adj.v[i] += gr[lane + NW * i];
             }
-
-            // ---- reverse sweep of the segment's tape
-            const int32_t nrec = c.hook.nrec < c.hook.max_rec ? c.hook.nrec : c.hook.max_rec;
-            const TapeRec *tp = c.hook.tape;
-            TapeRec nx;  // the next record, read one iteration ahead
-            if (nrec > 0) nx = tp[nrec - 1];
-            for (int32_t i = nrec - 1; i >= 0; --i) {
-                TapeRec r = nx;
-                if (i > 0) nx = tp[i - 1];
-                // the env's lane runs alone: its record fields are wave-uniform, so the
-                // sweep's branches on them are scalar branches
-                r.w0 = W::first(r.w0);
-                r.w1 = W::first(r.w1);
-                r.w2 = W::first(r.w2);
-                r.w3 = W::first(r.w3);
-                const uint32_t kind = (r.w0 >> 16) & 15u;
-                const uint32_t step = r.w3;
-                if (kind == kRecStepEnd) {
-                    if (P.grad_ram_out) {
-                        const float *gr = P.grad_ram_out + ((size_t)env * S + step) * 128;
-                        for (uint32_t cidx = 0; cidx < 128; ++cidx) adj_ram[cidx * E] += gr[cidx];
-                    }
-                    continue;
-                }
-                if (kind == kRecPixels) {
-                    aC[0] += r.pix[0];
-                    aC[1] += r.pix[1];
-                    aC[2] += r.pix[2];
-                    aC[3] += r.pix[3];
-                    continue;
-                }
-                const uint32_t opc = r.w0 & 0xFFu;
-                const uint32_t rd = (r.w0 >> 8) & 15u, wr = (r.w0 >> 12) & 15u;
-                const uint32_t rd_idx = r.w1 & 0xFFFFu, wr_idx = r.w1 >> 16;
-                const float v1 = (float)(r.w2 & 0xFFu), v2 = (float)((r.w2 >> 8) & 0xFFu);
-                const uint32_t sb = (r.w2 >> 16) & 0xFFu;
-                const uint32_t d = W::table(decode, opc);  // the env's lane is the only one active
-                const uint32_t cls = d & 63u;
-                switch (cls) {
-                    case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
-                    case C_LDX: { const float t = aX; aX = 0.f; add_src(rd, rd_idx, step, t); break; }
-                    case C_LDY: { const float t = aY; aY = 0.f; add_src(rd, rd_idx, step, t); break; }
-                    case C_LAX: { const float t = aA + aX; aA = aX = 0.f; add_src(rd, rd_idx, step, t); break; }
-                    case C_STA: aA += take_dst(wr, wr_idx); break;
-                    case C_STX: aX += take_dst(wr, wr_idx); break;
-                    case C_STY: aY += take_dst(wr, wr_idx); break;
-                    case C_SAX: {  // mem = A & X: d/dA = X/255, d/dX = A/255
-                        const float t = take_dst(wr, wr_idx);
-                        aA += t * (v2 / 255.f);
-                        aX += t * (v1 / 255.f);
-                        break;
-                    }
-                    case C_ADC: add_src(rd, rd_idx, step, aA); break;
-                    case C_SBC: add_src(rd, rd_idx, step, -aA); break;
-                    case C_AND: {  // A' = A & M with v1 = A, v2 = M
-                        const float t = aA;
-                        aA = t * (v2 / 255.f);
-                        add_src(rd, rd_idx, step, t * (v1 / 255.f));
-                        break;
-                    }
-                    case C_ORA: {
-                        const float t = aA;
-                        aA = t * ((255.f - v2) / 255.f);
-                        add_src(rd, rd_idx, step, t * ((255.f - v1) / 255.f));
-                        break;
-                    }
-                    case C_EOR: {
-                        const float t = aA;
-                        aA = t * ((255.f - 2.f * v2) / 255.f);
-                        add_src(rd, rd_idx, step, t * ((255.f - 2.f * v1) / 255.f));
-                        break;
-                    }
-                    case C_ASL: case C_ROL: case C_LSR: case C_ROR: case C_INC: case C_DEC: {
-                        const float k = (cls == C_ASL || cls == C_ROL) ? 2.f : (cls == C_LSR || cls == C_ROR) ? 0.5f : 1.f;
-                        const float t = take_dst(wr, wr_idx) * k;
-                        add_src(rd, rd_idx, step, t);
-                        break;
-                    }
-                    case C_TAX: aA += aX; aX = 0.f; break;
-                    case C_TAY: aA += aY; aY = 0.f; break;
-                    case C_TXA: aX += aA; aA = 0.f; break;
-                    case C_TYA: aY += aA; aA = 0.f; break;
-                    case C_TSX: aX = 0.f; break;
-                    case C_PHA: aA += take_dst(wr, wr_idx); break;
-                    case C_PLA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
-                    case C_PHP: zero_push(sb); break;
-                    case C_JSR: zero_push(sb); zero_push(sb - 1u); break;
-                    case C_BRK: zero_push(sb); zero_push(sb - 1u); zero_push(sb - 2u); break;
-                    default: break;  // flags, compares, branches, jumps, pulls into P/PC: no content
-                }
-                if (r.w0 & (1u << 20)) {  // pixels drawn before this instruction's write
-                    aC[0] += r.pix[0];
-                    aC[1] += r.pix[1];
-                    aC[2] += r.pix[2];
-                    aC[3] += r.pix[3];
-                }
+            return;
+        }
+        if (kind == kRecPixels) {
+            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix[k];
+            return;
+        }
+        const uint32_t opc = w0 & 0xFFu;
+        const uint32_t rd = (w0 >> 8) & 15u, wr = (w0 >> 12) & 15u;
+        const uint32_t rd_idx = w1 & 0xFFFFu, wr_idx = w1 >> 16;
+        const float v1 = (float)(w2 & 0xFFu), v2 = (float)((w2 >> 8) & 0xFFu);
+        const uint32_t sb = (w2 >> 16) & 0xFFu;
+        const uint32_t d = W::table(decode, opc);
+        const uint32_t cls = d & 63u;
+        switch (cls) {
+            case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
+            case C_LDX: { const float t = aX; aX = 0.f; add_src(rd, rd_idx, step, t); break; }
+            case C_LDY: { const float t = aY; aY = 0.f; add_src(rd, rd_idx, step, t); break; }
+            case C_LAX: { const float t = aA + aX; aA = aX = 0.f; add_src(rd, rd_idx, step, t); break; }
+            case C_STA: aA += take_dst(wr, wr_idx); break;
+            case C_STX: aX += take_dst(wr, wr_idx); break;
+            case C_STY: aY += take_dst(wr, wr_idx); break;
+            case C_SAX: {  // mem = A & X: d/dA = X/255, d/dX = A/255
+                const float t = take_dst(wr, wr_idx);
+                aA += t * (v2 / 255.f);
+                aX += t * (v1 / 255.f);
+                break;
             }
-            --seg;
+            case C_ADC: add_src(rd, rd_idx, step, aA); break;
+            case C_SBC: add_src(rd, rd_idx, step, -aA); break;
+            case C_AND: {  // A' = A & M with v1 = A, v2 = M
+                const float t = aA;
+                aA = t * (v2 / 255.f);
+                add_src(rd, rd_idx, step, t * (v1 / 255.f));
+                break;
+            }
+            case C_ORA: {
+                const float t = aA;
+                aA = t * ((255.f - v2) / 255.f);
+                add_src(rd, rd_idx, step, t * ((255.f - v1) / 255.f));
+                break;
+            }
+            case C_EOR: {
+                const float t = aA;
+                aA = t * ((255.f - 2.f * v2) / 255.f);
+                add_src(rd, rd_idx, step, t * ((255.f - 2.f * v1) / 255.f));
+                break;
+            }
+            case C_ASL: case C_ROL: case C_LSR: case C_ROR: case C_INC: case C_DEC: {
+                const float k = (cls == C_ASL || cls == C_ROL) ? 2.f : (cls == C_LSR || cls == C_ROR) ? 0.5f : 1.f;
+                const float t = take_dst(wr, wr_idx) * k;
+                add_src(rd, rd_idx, step, t);
+                break;
+            }
+            case C_TAX: aA += aX; aX = 0.f; break;
+            case C_TAY: aA += aY; aY = 0.f; break;
+            case C_TXA: aX += aA; aA = 0.f; break;
+            case C_TYA: aY += aA; aA = 0.f; break;
+            case C_TSX: aX = 0.f; break;
+            case C_PHA: aA += take_dst(wr, wr_idx); break;
+            case C_PLA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
+            case C_PHP: zero_push(sb); break;
+            case C_JSR: zero_push(sb); zero_push(sb - 1u); break;
+            case C_BRK: zero_push(sb); zero_push(sb - 1u); zero_push(sb - 2u); break;
+            default: break;  // flags, compares, branches, jumps, pulls into P/PC: no content
+        }
+        if (w0 & (1u << 20)) {  // pixels drawn before this instruction's write
+            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix[k];
+        }
+    };
+
+    for (int32_t seg = nseg - 1; seg >= 0; --seg) {
+        // ---- restore the segment's starting state
+        const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + seg];
+        c.load(r);
+        c.bank &= c.f8;
+        const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
+        for (uint32_t w = lane; w < 32; w += NW) c.mem.ram_word_set(w, rw[w]);
+        uint32_t frame = r.frame;
+        c.hook.pix_cc = r.pix_cc;
+        const int64_t seg_end = seg == nseg - 1 ? INT64_MAX : r.next_ckpt;
+        int32_t s_idx = (int32_t)(frame / (uint32_t)F), fstep = (int32_t)(frame % (uint32_t)F);
+        c.hook.nrec = 0;
+        auto set_ports = [&]() {
+            action_ports(P.actions[(size_t)env * S + s_idx], &c.swcha, &c.inpt4);
+            c.hook.step = (uint32_t)s_idx;
+            c.hook.gframe = (s_idx == S - 1 && fstep == F - 1) ? gframe_env : nullptr;
+        };
+        bool rec_active = s_idx < S;
+        if (rec_active) set_ports();
+
+        // ---- recompute the segment, recording the tape
+        while (rec_active) {
+            const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
+            if (g >= seg_end) {
+                rec_active = false;
+            } else if (c.jam || c.cyc >= kCyclesPerFrame) {
+                if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;
+                if (c.hook.gframe) {  // tail of the final frame
+                    TapeRec t;
+                    t.w0 = kRecPixels << 16;
+                    t.w1 = t.w2 = 0;
+                    t.w3 = (uint32_t)s_idx;
+                    t.pix[0] = t.pix[1] = t.pix[2] = t.pix[3] = 0.f;
+                    pixel_sums_wave<W>(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.pf, c.vb, c.hook.ystart, t.pix);
+                    c.hook.emit(t);
+                }
+                c.next_frame();
+                c.hook.pix_cc = c.hook.pix_cc > kClocksPerFrame ? c.hook.pix_cc - kClocksPerFrame : 0;
+                ++frame;
+                if (++fstep == F) {
+                    TapeRec t;
+                    t.w0 = kRecStepEnd << 16;
+                    t.w1 = t.w2 = 0;
+                    t.w3 = (uint32_t)s_idx;
+                    t.pix[0] = t.pix[1] = t.pix[2] = t.pix[3] = 0.f;
+                    c.hook.emit(t);
+                    fstep = 0;
+                    if (++s_idx == S) rec_active = false;
+                }
+                if (rec_active) set_ports();
+            } else {
+                uint32_t opc, lo, hi, dec;
+                fetch_word<W>(c, opc, lo, hi, dec);
+                ExecInfo info;
+                // the wave runs one env, so its opcode is wave-uniform
+                const uint32_t u = W::first(opc);
+                const uint32_t d = W::first(dec);
+                if (d == 0) c.jam = 1;
+                else exec_dispatch<W>(c, u, d, lo, hi, info);
+            }
+        }
+
+        // ---- reverse sweep of the segment's tape, a batch of NW records at a time
+        const int32_t nrec = c.hook.nrec < c.hook.max_rec ? c.hook.nrec : c.hook.max_rec;
+        const TapeRec *tp = c.hook.tape;
+        auto load_batch = [&](int32_t top, uint4 &a, float4 &b) {  // lane l: record top - NW + l
+            const int32_t i = top - (int32_t)NW + (int32_t)lane;
+            if (i >= 0) {
+                a = reinterpret_cast<const uint4 *>(tp + i)[0];
+                b = reinterpret_cast<const float4 *>(tp + i)[1];
+            } else {
+                a = make_uint4(0u, 0u, 0u, 0u);
+                b = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        uint4 ca;
+        float4 cb;
+        load_batch(nrec, ca, cb);
+        for (int32_t top = nrec; top > 0; top -= (int32_t)NW) {
+            const int32_t base = top - (int32_t)NW;  // lane l holds record base + l
+            uint4 na;
+            float4 nb;
+            load_batch(base, na, nb);  // the next batch, in flight during this one
+            const int32_t lo_i = base > 0 ? base : 0;
+            for (int32_t i = top - 1; i >= lo_i; --i) {
+                const uint32_t j = (uint32_t)(i - base);
+                const float pix[4] = {W::readlane(cb.x, j), W::readlane(cb.y, j), W::readlane(cb.z, j),
+                                      W::readlane(cb.w, j)};
+                sweep_one(W::readlane(ca.x, j), W::readlane(ca.y, j), W::readlane(ca.z, j), W::readlane(ca.w, j),
+                          pix);
+            }
+            ca = na;
+            cb = nb;
         }
     }
     // the RAM adjoint at the start reaches the tape only when the forward started
     // from power-on with the tape's RAM; a given starting state is a constant
     if (live) {
         const bool tape = nseg > 0 && P.ckpt[(size_t)env * P.max_ckpt].from_tape != 0u;
-        for (uint32_t cidx = 0; cidx < 128; ++cidx)
-            P.g_ram0[(size_t)env * 128 + cidx] = tape ? adj_ram[cidx * E] : 0.f;
+        for (uint32_t i = 0; i < RamAdjoint<W>::CPL; ++i)
+            P.g_ram0[(size_t)env * 128 + lane + NW * i] = tape ? adj.v[i] : 0.f;
     }
 }
 

@@ -130,6 +130,31 @@ class VcsBatch(_Ctx):
         Bd.check(rc, "vcs_step_hard")
         return ram_out, frame_out, done
 
+    def step_relaxed(self, alpha: float, T: float, actions=None, steps: int | None = None, frames: str = "all"):
+        """FULL relaxed env steps (every ROM/RAM read and branch relaxed and cast, no
+        straight-through correction), in place.  Returns (ram_out [B,S,128] u8, frames,
+        relax [B,2] int64 = (first diverging instruction or -1, casts that differed))."""
+        B = self.B
+        act = None
+        if actions is not None:
+            act = actions if torch.is_tensor(actions) else torch.from_numpy(np.asarray(actions, np.uint8))
+            act = act.to(self.device, torch.uint8).contiguous()
+            steps = act.shape[1]
+        assert steps is not None and steps >= 1
+        ram_out = torch.empty((B, steps, 128), dtype=torch.uint8, device=self.device)
+        mode = _FRAMES[frames]
+        frame_out = None
+        if mode != Bd.VCS_FRAMES_NONE:
+            shape = (B, steps, 210, 160) if mode == Bd.VCS_FRAMES_ALL else (B, 210, 160)
+            frame_out = torch.empty(shape, dtype=torch.uint8, device=self.device)
+        relax = torch.empty((B, 2), dtype=torch.int64, device=self.device)
+        work = self.workspace(Bd.VCS_OP_HARD, steps)
+        rc = Bd.lib().vcs_step_relaxed(self.h, Bd.ptr(self.rom), Bd.ptr(self.state), Bd.ptr(act), steps,
+                                       Bd.ptr(ram_out), mode, Bd.ptr(frame_out), float(alpha), float(T),
+                                       Bd.ptr(relax), Bd.ptr(work), _stream())
+        Bd.check(rc, "vcs_step_relaxed")
+        return ram_out, frame_out, relax
+
     def capture(self, actions: torch.Tensor, frames: str = "last", episode_steps=None):
         """Record one step call of ``actions.shape[1]`` env steps as a HIP graph.
 

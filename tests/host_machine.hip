@@ -1,6 +1,7 @@
 // Test harness: the library's per-env machine core and kernel bodies built for
 // the host with a one-lane wave policy, so that CPU tests can compare them
 // with the oracle (no GPU involved).
+#include <cmath>
 #include <cstring>
 #include <vector>
 #include "vcs_paths.hpp"
@@ -9,6 +10,12 @@ using namespace vcs;
 
 namespace {
 struct OneLane {  // wave policy of a one-lane wave
+    static constexpr uint32_t kWidth = 1;
+    static uint32_t lane() { return 0; }
+    static uint32_t readlane(uint32_t v, uint32_t) { return v; }
+    static float readlane(float v, uint32_t) { return v; }
+    static float writelane(float, float x, uint32_t) { return x; }
+    static float sum(float v) { return v; }
     static bool any(bool v) { return v; }
     static bool all(bool v) { return v; }
     static void opaque(uint32_t &) {}
@@ -146,8 +153,51 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
     int32_t overflow = 0;
     Q.overflow = &overflow;
     std::vector<uint32_t> ram_lds(32, 0);
-    std::vector<float> adj(128, 0.f);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-    bwd_env<OneLane>(Q, 0, 0, 1, mapper, m, adj.data(), 1, kHostDecode.e);
+    bwd_env<OneLane>(Q, 0, 0, 1, mapper, m, kHostDecode.e);
     return overflow ? -1 : nck;
+}
+
+// FULL relaxed rollout of one env from power-on with RAM ram0 (S steps of F
+// frames) through the relaxed kernel's body: the grouped interpreter with the
+// relaxing memory policy.  u[0..8] and the gates as vcs_step_relaxed forms them
+// (in double, stored as float).  Outputs: RAM [S][128], frames [S][210][160],
+// relax[2] = (first diverging instruction or -1, casts that differed).
+extern "C" int host_relaxed(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0,
+                            const uint8_t *actions, int S, int F, double alpha, double T, uint8_t *ram_out,
+                            uint8_t *frame_out, long long *relax) {
+    StateRec st{};
+    st.status = 2;
+    st.tim_shift = 10;
+    std::memcpy(st.ram, ram0, 128);
+    int64_t out[2] = {0, 0};
+    StepParams P{};
+    P.state = &st;
+    P.actions = actions;
+    P.steps = S;
+    P.frame_skip = F;
+    P.ystart = 34;
+    P.frames_mode = 2;
+    P.ram_out = ram_out;
+    P.frame_out = frame_out;
+    P.relax_out = out;
+    std::vector<uint2> words(8192);
+    for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
+    std::vector<uint32_t> ram_lds(32, 0);
+    RelaxMem<LdsWordMem> m;
+    static_cast<LdsWordMem &>(m) = LdsWordMem{words.data(), kHostDecode.e,
+                                              reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+    m.rc.u[0] = 1.0f;
+    for (int k = 1; k <= 8; ++k) m.rc.u[k] = (float)std::exp(-(double)k / T);
+    m.rc.g_taken = (float)(1.0 / (1.0 + std::exp(-alpha)));
+    m.rc.g_not = (float)(1.0 / (1.0 + std::exp(alpha)));
+    m.rom_n = (uint32_t)rom_size;
+    m.active = false;
+    m.ninstr = 0;
+    m.ndiv = -1;
+    m.fails = 0;
+    step_env<OneLane, 1, false, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    relax[0] = out[0];
+    relax[1] = out[1];
+    return 0;
 }
