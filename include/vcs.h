@@ -89,8 +89,10 @@ typedef struct vcs_config {
     uint64_t seed;              /* SplitMix64 seed of in-run reset RAM */
     int32_t ckpt_interval;      /* soft backward: hard-state checkpoint every K cycles (>= 64) */
     int32_t kernel;             /* vcs_kernel */
-    int32_t lanes_per_env;      /* GROUPED kernel: lanes cooperating on one env (1, 4, 16 or 64; 0 = auto) */
-    int32_t block_threads;      /* GROUPED kernel: threads per workgroup (64 or 256; 0 = auto);
+    int32_t lanes_per_env;      /* lanes cooperating on one env (1, 4, 16 or 64, and 32 for TRANSLATED;
+                                   0 = auto) */
+    int32_t block_threads;      /* threads per workgroup: 64, 256, or 1024 (GROUPED with 64 lanes per
+                                   env only); 0 = 1024 for GROUPED with 64 lanes per env, else 256;
                                    TRANSLATED: block_threads / lanes_per_env <= 64 */
 } vcs_config;
 

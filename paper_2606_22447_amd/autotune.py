@@ -36,7 +36,7 @@ def hard_candidates(num_envs: int):
         waves = num_envs * g / 64.0
         if waves < 16 or waves > 1024 * 8:
             continue
-        for t in THREADS:
+        for t in THREADS + ((1024,) if g == 64 else ()):  # one env per wave: 16 envs share a workgroup
             if t >= g:
                 out.append((g, t))
     return out or [(1, 64)]
@@ -58,8 +58,12 @@ def _time(fn, reps: int) -> float:
 
 def translated_candidates(num_envs: int):
     """Launch shapes tried for the TRANSLATED kernel (each one is a compilation):
-    lane groups of 4 and 16, the shapes that keep one or a few waves per SIMD."""
-    return [(g, t) for g, t in hard_candidates(num_envs) if g in (4, 16)] or [(1, 64)]
+    lane groups of 4, 16 and 32 (two envs per wave: twice the waves of 16 to
+    hide latency), the shapes that keep one or a few waves per SIMD."""
+    out = [(g, t) for g, t in hard_candidates(num_envs) if g in (4, 16) and t <= 256]
+    if 1024 <= num_envs * 32 / 64.0 <= 1024 * 8:
+        out += [(32, 64), (32, 256)]
+    return out or [(1, 64)]
 
 
 def tune_hard(roms, env_rom, frame_skip: int = 4, seed: int = 0, ram0=None, actions=None, trial_steps: int = 2,

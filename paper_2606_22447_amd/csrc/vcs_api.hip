@@ -257,8 +257,8 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         delete c;
         return VCS_INVALID_ARG;
     }
-    c->tpb = cfg->block_threads ? cfg->block_threads : 256;
-    if (c->tpb != 64 && c->tpb != 256) {
+    c->tpb = cfg->block_threads;
+    if (c->tpb != 0 && c->tpb != 64 && c->tpb != 256 && c->tpb != 1024) {
         delete c;
         return VCS_UNSUPPORTED;
     }
@@ -266,7 +266,8 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         c->G = 1;
     } else if (cfg->lanes_per_env) {
         c->G = cfg->lanes_per_env;
-        if (c->G != 1 && c->G != 4 && c->G != 16 && c->G != 64) {
+        // 32 lanes (two envs per wave) only for translated code, which is compiled per shape
+        if (c->G != 1 && c->G != 4 && c->G != 16 && c->G != 64 && !(c->G == 32 && c->kernel == VCS_KERNEL_TRANSLATED)) {
             delete c;
             return VCS_UNSUPPORTED;
         }
@@ -279,7 +280,12 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         c->G = (int64_t)c->B * 64 <= lanes_budget ? 64 : (int64_t)c->B * 16 <= lanes_budget ? 16
              : (int64_t)c->B * 4 <= lanes_budget ? 4 : 1;
     }
-    if (c->tpb < c->G) {
+    // One env per wave (64 lanes) runs 16 envs per workgroup by default: they share
+    // the workgroup's staged ROM image, so a large image does not cap the waves a
+    // CU holds.  Otherwise 256 threads.  1024 only with one env per wave and the
+    // interpreting kernel.
+    if (c->tpb == 0) c->tpb = (c->G == 64 && c->kernel == VCS_KERNEL_GROUPED) ? 1024 : 256;
+    if (c->tpb < c->G || (c->tpb == 1024 && (c->G != 64 || c->kernel != VCS_KERNEL_GROUPED))) {
         delete c;
         return VCS_UNSUPPORTED;
     }

@@ -302,7 +302,7 @@ __host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int
 // Data classes for the soft backward (where a value comes from / goes to)
 // ---------------------------------------------------------------------------
 struct ExecInfo {
-    uint32_t rd_cls, rd_idx, wr_cls, wr_idx, v1, v2, s_before;
+    uint32_t op_cls, rd_cls, rd_idx, wr_cls, wr_idx, v1, v2, s_before;
 };
 
 // Class of a 13-bit data write target.
@@ -557,6 +557,7 @@ struct Cpu {
         const uint32_t pc0 = pc;
         pc = (pc0 + ((d >> 14) & 3u)) & 0xFFFFu;
         if constexpr (R) {
+            info.op_cls = cls;
             info.rd_cls = kClsConst;
             info.wr_cls = kClsConst;
             info.rd_idx = info.wr_idx = info.v1 = info.v2 = 0;

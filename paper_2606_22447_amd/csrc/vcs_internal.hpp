@@ -108,7 +108,7 @@ struct StepParams {
 
 // One record of the soft backward's recompute tape (32 bytes).
 struct alignas(16) TapeRec {
-    uint32_t w0;  // opcode | rd_class << 8 | wr_class << 12 | kind << 16 | has_pix << 20
+    uint32_t w0;  // opcode | rd_class << 8 | wr_class << 12 | kind << 16 | has_pix << 20 | op class << 24
     uint32_t w1;  // rd_idx | wr_idx << 16
     uint32_t w2;  // v1 | v2 << 8 | s_before << 16
     uint32_t w3;  // env step of the instruction / marker

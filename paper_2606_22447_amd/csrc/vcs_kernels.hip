@@ -409,6 +409,7 @@ hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32
     VCS_STEP_CASE(16, 256)
     VCS_STEP_CASE(64, 64)
     VCS_STEP_CASE(64, 256)
+    VCS_STEP_CASE(64, 1024)
 #undef VCS_STEP_CASE
     return hipErrorInvalidValue;
 }
@@ -429,6 +430,7 @@ hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lane
     VCS_RELAX_CASE(16, 256)
     VCS_RELAX_CASE(64, 64)
     VCS_RELAX_CASE(64, 256)
+    VCS_RELAX_CASE(64, 1024)
 #undef VCS_RELAX_CASE
     return hipErrorInvalidValue;
 }

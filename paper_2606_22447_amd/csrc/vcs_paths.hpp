@@ -415,17 +415,31 @@ struct TapeHook {
         save_pf = c.pf;
         save_vb = c.vb;
     }
+    // Instructions whose reverse-sweep rule is the identity need no record unless
+    // pixels are attributed to them: branches, flag changes, compares, BIT, NOPs,
+    // jumps, returns, PLP, TXS, and stores to registers that carry no content
+    // (WSYNC, VBLANK, the timer, ...).
+    static constexpr uint64_t kNoContent =
+        (1ull << C_BRANCH) | (1ull << C_FLAG) | (1ull << C_CMP) | (1ull << C_CPX) | (1ull << C_CPY) |
+        (1ull << C_BIT) | (1ull << C_NOP) | (1ull << C_JMP) | (1ull << C_RTS) | (1ull << C_RTI) |
+        (1ull << C_PLP) | (1ull << C_TXS);
+    static constexpr uint64_t kStores = (1ull << C_STA) | (1ull << C_STX) | (1ull << C_STY) | (1ull << C_SAX);
     template <class C>
     __host__ __device__ __forceinline__ void after_exec(C &, uint32_t opc, int32_t, int32_t wp, ExecInfo &info) {
         TapeRec r;
-        r.w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16);
+        r.w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16) | (info.op_cls << 24);
         r.w1 = info.rd_idx | (info.wr_idx << 16);
         r.w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
         r.w3 = step;
         r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
-        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) r.w0 |= 1u << 20;
+        bool keep = !(((kNoContent >> info.op_cls) & 1u) ||
+                      (((kStores >> info.op_cls) & 1u) && info.wr_cls == kClsConst));
+        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) {
+            r.w0 |= 1u << 20;
+            keep = true;
+        }
         pix_cc = 3 * wp;
-        emit(r);
+        if (keep) emit(r);
     }
 };
 
@@ -891,6 +905,7 @@ template <class W, class Mem>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
                                                  int32_t mapper, Mem mem, const uint32_t *decode) {
     constexpr uint32_t NW = W::kWidth;
+    (void)decode;  // the tape records carry the opcode class
     const uint32_t lane = W::lane();
     const bool lead = lane == 0;
     const bool live = env >= 0;
@@ -946,8 +961,9 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
         const uint32_t cls = write_class(0x100u | (cell & 0xFFu), &idx);
         (void)take_dst(cls, idx);
     };
-    // the reverse-sweep rule of one record (fields already wave-uniform)
-    auto sweep_one = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t step, const float pix[4]) {
+    // the reverse-sweep rule of one record (fields already wave-uniform; pix(k) gives
+    // its pixel sums, read only by the records that carry them)
+    auto sweep_one = [&](uint32_t w0, uint32_t w1, uint32_t w2, uint32_t step, auto pix) {
         const uint32_t kind = (w0 >> 16) & 15u;
         if (kind == kRecStepEnd) {
             if (P.grad_ram_out) {
@@ -957,16 +973,14 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             return;
         }
         if (kind == kRecPixels) {
-            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix[k];
+            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix(k);
             return;
         }
-        const uint32_t opc = w0 & 0xFFu;
         const uint32_t rd = (w0 >> 8) & 15u, wr = (w0 >> 12) & 15u;
         const uint32_t rd_idx = w1 & 0xFFFFu, wr_idx = w1 >> 16;
         const float v1 = (float)(w2 & 0xFFu), v2 = (float)((w2 >> 8) & 0xFFu);
         const uint32_t sb = (w2 >> 16) & 0xFFu;
-        const uint32_t d = W::table(decode, opc);
-        const uint32_t cls = d & 63u;
+        const uint32_t cls = (w0 >> 24) & 63u;  // the opcode's class, recorded with it
         switch (cls) {
             case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
             case C_LDX: { const float t = aX; aX = 0.f; add_src(rd, rd_idx, step, t); break; }
@@ -1020,7 +1034,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             default: break;  // flags, compares, branches, jumps, pulls into P/PC: no content
         }
         if (w0 & (1u << 20)) {  // pixels drawn before this instruction's write
-            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix[k];
+            for (uint32_t k = 0; k < 4; ++k) aC[k] += pix(k);
         }
     };
 
@@ -1046,10 +1060,24 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
 
         // ---- recompute the segment, recording the tape
         while (rec_active) {
+            // the instructions of this frame that start before the segment's end run
+            // in a tight loop; the frame and segment bookkeeping sits outside it
+            const int64_t rel = seg_end - (int64_t)frame * kCyclesPerFrame;  // segment end, frame-relative
+            const int32_t lim = rel < (int64_t)kCyclesPerFrame ? (int32_t)rel : kCyclesPerFrame;
+            while (!c.jam && c.cyc < lim) {
+                uint32_t opc, lo, hi, dec;
+                fetch_word<W>(c, opc, lo, hi, dec);
+                ExecInfo info;
+                // the wave runs one env, so its opcode is wave-uniform
+                const uint32_t u = W::first(opc);
+                const uint32_t d = W::first(dec);
+                if (d == 0) c.jam = 1;
+                else exec_dispatch<W>(c, u, d, lo, hi, info);
+            }
             const int64_t g = (int64_t)frame * kCyclesPerFrame + c.cyc;
             if (g >= seg_end) {
                 rec_active = false;
-            } else if (c.jam || c.cyc >= kCyclesPerFrame) {
+            } else {  // the frame is over (or the CPU jammed): its end
                 if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;
                 if (c.hook.gframe) {  // tail of the final frame
                     TapeRec t;
@@ -1074,15 +1102,6 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                     if (++s_idx == S) rec_active = false;
                 }
                 if (rec_active) set_ports();
-            } else {
-                uint32_t opc, lo, hi, dec;
-                fetch_word<W>(c, opc, lo, hi, dec);
-                ExecInfo info;
-                // the wave runs one env, so its opcode is wave-uniform
-                const uint32_t u = W::first(opc);
-                const uint32_t d = W::first(dec);
-                if (d == 0) c.jam = 1;
-                else exec_dispatch<W>(c, u, d, lo, hi, info);
             }
         }
 
@@ -1110,8 +1129,9 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             const int32_t lo_i = base > 0 ? base : 0;
             for (int32_t i = top - 1; i >= lo_i; --i) {
                 const uint32_t j = (uint32_t)(i - base);
-                const float pix[4] = {W::readlane(cb.x, j), W::readlane(cb.y, j), W::readlane(cb.z, j),
-                                      W::readlane(cb.w, j)};
+                auto pix = [&](uint32_t k) {
+                    return W::readlane(k == 0 ? cb.x : k == 1 ? cb.y : k == 2 ? cb.z : cb.w, j);
+                };
                 sweep_one(W::readlane(ca.x, j), W::readlane(ca.y, j), W::readlane(ca.z, j), W::readlane(ca.w, j),
                           pix);
             }

@@ -20,7 +20,7 @@ from tests.fnv import fnv1a64
 pytestmark = pytest.mark.gpu
 
 # (kernel, lanes per env, threads per workgroup): the shapes the autotuner picks for the batched workload
-SHAPES = [("translated", 16, 256), ("grouped", 16, 256), ("grouped", 4, 64)]
+SHAPES = [("translated", 16, 256), ("translated", 32, 256), ("grouped", 16, 256), ("grouped", 4, 64)]
 
 
 def say(*a):
@@ -110,15 +110,15 @@ def test_heterogeneous_full_size_every_step_fingerprinted():
     check_workload(w, sample, final_envs, [("grouped", 4, 256), ("translated", 4, 256)])
 
 
-@pytest.mark.parametrize("kernel", ["translated", "grouped"])
-def test_batched_hard_full_size_bytes_of_sampled_envs(kernel):
+@pytest.mark.parametrize("kernel,G,tpb", [("translated", 16, 256), ("translated", 32, 256), ("grouped", 16, 256)])
+def test_batched_hard_full_size_bytes_of_sampled_envs(kernel, G, tpb):
     """Every RAM byte, frame byte and done flag of a few envs, in bench.py's call pattern (50 steps/call)."""
     import torch
     from paper_2606_22447_amd.vcs import VcsBatch
     w = I.config_c1()
     sample = [0, 1, 777, 2048, 4095]
-    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel, lanes_per_env=16,
-                  block_threads=256)
+    vb = VcsBatch(w.roms, w.env_rom, frame_skip=w.frame_skip, seed=w.seed, kernel=kernel, lanes_per_env=G,
+                  block_threads=tpb)
     vb.reset(ram0=w.ram0)
     idx = torch.tensor(sample, device="cuda")
     rams, frs = [], []

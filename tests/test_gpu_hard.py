@@ -10,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 KERNELS = [("plain", 1, 64), ("plain", 1, 256), ("grouped", 1, 64), ("grouped", 1, 256),
            ("grouped", 4, 64), ("grouped", 4, 256), ("grouped", 16, 64), ("grouped", 16, 256),
-           ("grouped", 64, 64), ("grouped", 64, 256)]
+           ("grouped", 64, 64), ("grouped", 64, 256), ("grouped", 64, 1024)]
 
 
 def say(*a):
@@ -81,7 +81,7 @@ def test_c1_slice_every_byte_across_calls(kernel, G, tpb):
 
 
 @pytest.mark.parametrize("kernel,G,tpb", [("plain", 1, 256), ("grouped", 1, 256), ("grouped", 4, 64),
-                                          ("grouped", 16, 256), ("grouped", 64, 256)])
+                                          ("grouped", 16, 256), ("grouped", 64, 256), ("grouped", 64, 1024)])
 def test_heterogeneous_roms_with_episode_resets(kernel, G, tpb):
     # 2K / 4K / F8 ROMs that read SWCHA, INPT4 and INTIM; short episodes force in-run resets
     roms = [I.generate_rom(100 + i, sz, reads_inputs=True, timer_vblank=True)

@@ -27,7 +27,7 @@ def reference(w):
     return _REF["hard"]
 
 
-@pytest.mark.parametrize("kernel,G,tpb", KERNELS + [("translated", 4, 256), ("translated", 64, 64)])
+@pytest.mark.parametrize("kernel,G,tpb", KERNELS + [("translated", 4, 256), ("translated", 32, 256), ("translated", 64, 64)])
 def test_sweep_every_byte(kernel, G, tpb):
     w = sweep_workload()
     say("sweep", kernel, G, tpb, "envs", w.num_envs)

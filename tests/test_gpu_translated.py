@@ -8,7 +8,7 @@ from tests.test_gpu_hard import gpu_run, oracle_env, say
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("G,tpb", [(16, 256), (4, 64)])
+@pytest.mark.parametrize("G,tpb", [(16, 256), (4, 64), (32, 256)])
 def test_translated_c1_slice_every_byte_across_calls(G, tpb):
     w = I.config_c1(num_envs=96, steps=12)
     say("translated c1 slice", G, tpb)
@@ -45,7 +45,7 @@ def test_translated_heterogeneous_roms_with_episode_resets():
 
 
 @pytest.mark.parametrize("prog", ["tia_pushes", "playfield_modes"])
-@pytest.mark.parametrize("G,tpb", [(16, 256), (64, 256)])
+@pytest.mark.parametrize("G,tpb", [(16, 256), (32, 64), (64, 256)])
 def test_translated_hand_assembled_tia_programs(prog, G, tpb):
     # JSR pushes onto CTRLPF and COLUBK (two pixel-register writes at one clock, at
     # every pixel alignment), and CTRLPF cycled through reflected and score modes:
