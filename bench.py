@@ -26,9 +26,13 @@ METRIC = "env-steps/sec (hard fwd; soft fwd+bwd) at B envs, bit-exact vs oracle"
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12   # int32 lane-ops/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 OPS_PER_INSTRUCTION = 12                       # algorithmic integer ops of one emulated 6507 instruction
 OPS_PER_PIXEL = 1                              # one store per returned pixel
+OPS_PER_SWEEP = 6                              # reverse-sweep ops of one emulated instruction (soft backward)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "vcs_tr_step_c1_hbm_traffic.md")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "vcs_tr_step_c1_hbm_traffic.md")
+HBM_PEAK_GBPS = 8000.0                         # MI355X HBM3E
+SIMDS, CLOCK_HZ = 1024, 2.4e9                  # 256 CUs x 4 SIMDs; a wave64 VALU instruction takes 4 cycles
 KERNEL_SOURCES = ["vcs_core.hpp", "vcs_paths.hpp", "vcs_internal.hpp", "vcs_kernels.hpp", "vcs_kernels.hip",
                   "vcs_device.hpp", "vcs_jit.hpp", "vcs_jit.cpp"]
 
@@ -47,6 +51,51 @@ def kernel_digest() -> str:
             h.update(fh.read())
     h.update(" ".join(f for f in B.FLAGS if not os.path.isabs(f)).encode())  # flags without local paths
     return h.hexdigest()[:16]
+
+
+def profile_figures(name: str):
+    """The machine-readable figures (``key: value`` lines) of a committed rocprofv3
+    summary under profiles/, or None when the kernel has changed since they were taken."""
+    try:
+        with open(os.path.join(PROFILES, name)) as fh:
+            lines = fh.read().splitlines()
+    except OSError:
+        return None
+    kv = {}
+    for line in lines:
+        k, sep, v = line.partition(": ")
+        if sep and k.strip() == k and k.replace("_", "").isalnum() and " " not in v.strip():
+            kv[k] = v.strip()
+    if kv.get("kernel_digest") != kernel_digest():
+        return None
+    out = {"_file": "profiles/" + name}
+    for k, v in kv.items():
+        try:
+            out[k] = float(v) if k != "kernel_digest" else v
+        except ValueError:
+            out[k] = v
+    return out
+
+
+def counter_fractions(fig, prefix: str, launch_s: float):
+    """VALU-issue fraction of a kernel from committed counters (instructions per launch,
+    scaled to this run's launch time): SQ_INSTS_VALU x 4 cycles / (1024 SIMDs x clock x t),
+    and the measured lane utilisation."""
+    if not fig or f"{prefix}_sq_insts_valu_per_launch" not in fig or not launch_s:
+        return None
+    valu = fig[f"{prefix}_sq_insts_valu_per_launch"]
+    issue = valu * 4.0 / (SIMDS * CLOCK_HZ * launch_s)
+    out = {"source": "rocprofv3 SQ counters, " + fig.get("_file", ""), "sq_insts_valu_per_launch": valu,
+           "valu_issue_frac": issue}
+    for k in ("sq_insts_salu", "sq_insts_lds", "sq_insts_branch", "sq_insts_mfma", "sq_waves"):
+        if f"{prefix}_{k}_per_launch" in fig:
+            out[f"{k}_per_launch"] = fig[f"{prefix}_{k}_per_launch"]
+    for k in ("valu_busy_pct", "valu_utilization_pct"):
+        if f"{prefix}_{k}" in fig:
+            out[k] = fig[f"{prefix}_{k}"]
+    if "valu_utilization_pct" in out:
+        out["valu_lane_op_frac"] = issue * out["valu_utilization_pct"] / 100.0
+    return out
 
 
 def measured_traffic():
@@ -81,7 +130,14 @@ def parse():
                     help="comma list of: hard, plain, hetero, soft, cpu")
     ap.add_argument("--soft-k", default="256,1024,4096")
     ap.add_argument("--soft-passes", type=int, default=2)
+    ap.add_argument("--soft-warmup", type=int, default=1)
     ap.add_argument("--soft-lanes", type=int, default=0, help="lanes per env of the soft forward (0 = auto)")
+    ap.add_argument("--hetero-lanes", type=int, default=0, help="lanes per env of the heterogeneous leg (0 = auto)")
+    ap.add_argument("--hetero-tpb", type=int, default=256)
+    ap.add_argument("--hetero-calls", type=int, default=4, help="timed calls of 25 env steps")
+    ap.add_argument("--hetero-warmup", type=int, default=1)
+    ap.add_argument("--cpu-soft-envs", type=int, default=256,
+                    help="envs of the small soft workload in the single-core FP64 fwd+bwd oracle sample")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
     ap.add_argument("--no-graph", action="store_true",
                     help="time direct vcs_step_hard calls instead of replays of a captured HIP graph")
@@ -105,11 +161,12 @@ def timed_calls(fn, warmup, steps):
     return wall, per
 
 
-def instructions_per_step(w, envs=2, steps=4):
-    """Oracle-counted 6507 instructions per env step of this workload (sample)."""
+def instructions_per_step(w, envs=2, steps=4, stride=1):
+    """Oracle-counted 6507 instructions per env step of this workload (sample of
+    `envs` envs, every `stride`-th, over their first `steps` steps)."""
     from oracle import oracle as O
     tot = 0
-    for b in range(envs):
+    for b in range(0, envs * stride, stride):
         rom = w.roms[int(w.env_rom[b])]
         r = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions_or_noop()[b, :steps], steps, w.frame_skip,
                       frames="none")
@@ -206,25 +263,55 @@ def soft_leg(args):
     out["lanes_per_env"] = lanes
     for K in [int(k) for k in args.soft_k.split(",")]:
         sim = SoftVcs(w.roms, w.env_rom, frame_skip=1, ckpt_interval=K, lanes_per_env=lanes)
+        marks = []
 
         def one(_i):
             L.grad = T.grad = A.grad = None
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            ev[0].record()
             ram, frame = soft_rollout(sim, L, T, A, 1.0, 6.0)
             loss = ((ste_luminance(frame) - lum_t) ** 2).mean(dim=(1, 2)).sum()
+            ev[1].record()
             loss.backward()
+            ev[2].record()
+            marks.append(ev)
 
         torch.cuda.reset_peak_memory_stats()
-        wall, per = timed_calls(one, 1, args.soft_passes)
+        wall, per = timed_calls(one, args.soft_warmup, args.soft_passes)
+        sim.raise_if_overflowed()
+        timed = marks[args.soft_warmup:]
+        fwd_s = float(np.mean([a.elapsed_time(b) for a, b, _ in timed])) / 1e3
+        bwd_s = float(np.mean([b.elapsed_time(c) for _, b, c in timed])) / 1e3
         res_b = Bd.size_query("vcs_residual_bytes", sim.h, S)
         ws_b = Bd.size_query("vcs_workspace_bytes", sim.h, Bd.VCS_OP_SOFT_BWD, S)
         out["by_ckpt_interval"][str(K)] = {
             "env_steps_per_s": B * S / per.mean(), "ms_per_pass": float(per.mean() * 1e3),
+            "ms_forward": fwd_s * 1e3, "ms_backward": bwd_s * 1e3,
             "residual_bytes_per_env": res_b / B, "bwd_workspace_bytes_per_env": ws_b / B,
             "peak_mem_bytes_per_env": torch.cuda.max_memory_allocated() / B}
         del sim
     best = max(out["by_ckpt_interval"].items(), key=lambda kv: kv[1]["env_steps_per_s"])
     out["best_ckpt_interval"] = int(best[0])
     out["env_steps_per_s"] = best[1]["env_steps_per_s"]
+    out["instructions_per_env_step"] = instructions_per_step(w, envs=8, steps=6, stride=B // 8)
+    out["instructions_per_s"] = out["env_steps_per_s"] * out["instructions_per_env_step"]
+    # roofline of the pass: forward (12 ops per instruction), backward recompute (12) and reverse
+    # sweep (6: record read, class decode, two adjoint multiply-adds, two adjoint moves), plus the
+    # returned frame drawn in the forward and its pixel gradients summed in the backward
+    ops = out["instructions_per_env_step"] * (2 * OPS_PER_INSTRUCTION + OPS_PER_SWEEP) + 2 * 33600 / S
+    achieved = out["env_steps_per_s"] * ops / 1e12
+    fig = profile_figures("soft_c4_sq_counters.md")
+    bk = best[1]
+    out["roofline"] = {
+        "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+        "frac": achieved / VALU_PEAK_TOPS, "ops_per_env_step": ops,
+        "ops_model": f"{2 * OPS_PER_INSTRUCTION + OPS_PER_SWEEP} integer ops per emulated instruction "
+                     "(forward 12, recompute 12, sweep 6) + 2 per returned pixel",
+        "kernel": "k_soft_bwd (dominant) and k_step<soft>",
+        "k_soft_bwd": counter_fractions(fig, "k_soft_bwd", bk["ms_backward"] / 1e3),
+        "k_step_soft": counter_fractions(fig, "k_step_soft", bk["ms_forward"] / 1e3),
+        "timing": "HIP events on the current stream around the forward (autograd forward + loss) and the "
+                  "backward (loss backward + vcs_step_soft_bwd) of each timed pass"}
     return out
 
 
@@ -241,11 +328,50 @@ def _cpu_worker(args):
     return time.perf_counter() - t0, len(envs) * steps, instr
 
 
-def cpu_leg(envs_per_proc=4, steps=500):
+def _cpu_soft_worker(args):
+    """Single-core FP64 soft forward + backward of the oracle on envs of the small soft workload
+    (leaf decode, then per env the soft rollout with its reverse sweep), `reps` times."""
+    from oracle import oracle as O
+    from paper_2606_22447_amd import inputs as I
+    n_envs, tau, reps = args
+    w = I.config_c3()
+    lv = I.soft_leaves(w)
+    B, S = w.num_envs, w.steps
+    gf = np.full((210, 160), 1e-4)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dr = O.decode_logits(lv.rom_logits, tau)
+        hr0, ev0 = O.decode_tape(lv.ram_tape[:n_envs].reshape(-1, 256))
+        ha, es, ei = O.decode_actions(lv.action_logits[:n_envs].reshape(-1, 18), tau)
+        for b in range(n_envs):
+            O.soft_env(dr[0], dr[1], w.roms[0].mapper, hr0.reshape(-1, 128)[b], ev0.reshape(-1, 128)[b],
+                       ha.reshape(-1, S)[b], es.reshape(-1, S)[b], ei.reshape(-1, S)[b], S, 1, mode="ste",
+                       grad_frame=gf)
+    return time.perf_counter() - t0, reps * n_envs * S
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(envs_per_proc=4, steps=500, soft_envs=16):
     import multiprocessing as mp
     from oracle import build as obuild
     obuild.build(force=False)
-    cores = min(os.cpu_count() or 1, 16)
+    nproc = os.cpu_count() or 1
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = nproc
+    # one process per usable core, at most 16 (the share of one GPU's host cores on the GPU machines)
+    cores = max(1, min(usable, 16))
     jobs = [list(range(i * envs_per_proc, (i + 1) * envs_per_proc)) for i in range(cores)]
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(cores) as pool:
@@ -253,10 +379,19 @@ def cpu_leg(envs_per_proc=4, steps=500):
     wall = time.perf_counter() - t0
     n = sum(r[1] for r in res)
     cpu_s = sum(r[0] for r in res)
+    soft_reps = 10
+    with mp.get_context("fork").Pool(1) as pool:  # the soft oracle on one core
+        soft_s, soft_n = pool.map(_cpu_soft_worker, [(soft_envs, 1.0, soft_reps)])[0]
     return {"value": n / wall, "unit": "env-steps/s", "cores": cores, "kind": "oracle",
             "sample": f"batched hard-forward workload, {cores} processes x {envs_per_proc} envs x {steps} env steps "
                       f"(frame-skip 4, every frame rendered and stored), {cpu_s:.1f} s of CPU work",
-            "single_core_env_steps_per_s": n / cpu_s, "instructions_per_s": sum(r[2] for r in res) / wall}
+            "nproc": nproc, "usable_cores": usable, "process_cap": 16, "cpu_model": cpu_model(),
+            "single_core_env_steps_per_s": n / cpu_s, "instructions_per_s": sum(r[2] for r in res) / wall,
+            "soft_fp64_fwd_bwd_single_core": {
+                "env_steps_per_s": soft_n / soft_s, "seconds": soft_s,
+                "sample": f"small soft workload (1 ROM, frame-skip 1): {soft_envs} envs x 2 env steps, FP64 "
+                          f"SOFT-STE forward + reverse sweep + leaf decode, tau 1.0, one process, {soft_reps} "
+                          "repetitions"}}
 
 
 def main():
@@ -301,16 +436,22 @@ def main():
         log("plain", result["plain"])
     if "hetero" in legs:
         ha = argparse.Namespace(**vars(args))
-        ha.chunk, ha.steps, ha.warmup = 25, 4, 1
-        w2 = I.config_c2(steps=25 * 5)
-        from paper_2606_22447_amd import autotune
+        ha.chunk, ha.steps, ha.warmup = 25, args.hetero_calls, args.hetero_warmup
+        w2 = I.config_c2(steps=25 * (args.hetero_calls + args.hetero_warmup))
         # the interpreting kernel: these ROMs read the joystick, so envs of a wave diverge and the
         # translated code (which needs every lane of a wave at one block) mostly falls back to it
-        t = autotune.tune_hard(w2.roms, w2.env_rom, frame_skip=w2.frame_skip, seed=w2.seed, ram0=w2.ram0,
-                               actions=w2.actions, trial_steps=2)
-        tuned["hetero"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"])) for r in t["table"]]
-        log("hetero autotune", tuned["hetero"])
-        result["hetero"] = hard_leg(ha, "grouped", t["lanes_per_env"], t["block_threads"], w2)
+        hl, ht = args.hetero_lanes, args.hetero_tpb
+        if hl == 0:
+            from paper_2606_22447_amd import autotune
+            t = autotune.tune_hard(w2.roms, w2.env_rom, frame_skip=w2.frame_skip, seed=w2.seed, ram0=w2.ram0,
+                                   actions=w2.actions, trial_steps=2)
+            tuned["hetero"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"]))
+                               for r in t["table"]]
+            log("hetero autotune", tuned["hetero"])
+            hl, ht = t["lanes_per_env"], t["block_threads"]
+        result["hetero"] = hard_leg(ha, "grouped", hl, ht, w2)
+        result["hetero"]["instructions_per_env_step"] = instructions_per_step(w2, envs=8, steps=4,
+                                                                              stride=w2.num_envs // 8)
         result["hetero"]["workload"] = ("c2_hetero_persistent: 64 ROMs (21x2K, 22x4K, 21xF8, reading SWCHA/INPT4/"
                                         "INTIM) x 256 envs = 16384 envs, frame-skip 4, geometric episodes "
                                         "(mean 1500 frames) with in-run resets")
@@ -324,30 +465,44 @@ def main():
         for _ in range(3):
             y.copy_(x)
         torch.cuda.synchronize()
-    cpu = cpu_leg() if "cpu" in legs else None
+    cpu = cpu_leg(soft_envs=args.cpu_soft_envs) if "cpu" in legs else None
 
     h = result.get("hard")
     value = h["env_steps_per_s"] if h else None
     ops_per_step = ips * OPS_PER_INSTRUCTION + 33600 * OPS_PER_PIXEL
+    timed_steps = args.chunk * args.steps
     line = {
         "metric": METRIC, "value": value, "unit": "env-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": h["ms_per_call"] if h else None, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "c1_batched_hard: 4096 envs of one seed-generated 4 KB ROM, uniform actions over "
-                               "the 18 ALE actions, frame-skip 4, 2000 frames = 500 env steps, RAM (128 B) and "
-                               "frame (210x160 u8) written for every env step",
+        "config": {"workload": f"c1_batched_hard: {args.envs} envs of one seed-generated 4 KB ROM, uniform actions "
+                               "over the 18 ALE actions, frame-skip 4, RAM (128 B) and frame (210x160 u8) written "
+                               f"for every env step; each timed call = {args.chunk} env steps, {args.steps} timed "
+                               f"calls = {timed_steps} env steps ({4 * timed_steps} frames) per env after "
+                               f"{args.chunk * args.warmup} warm-up env steps",
                    "envs": args.envs, "env_steps_per_call": args.chunk, "frame_skip": 4,
                    "launch": h["launch"] if h else None},
     }
     if h:
+        launch_s = h["ms_per_call"] / 1e3
         achieved = h["env_steps_per_s"] * ops_per_step / 1e12
+        alg_bytes = args.envs * args.chunk * (33600 + 128 + 1 + 1)
+        kname = {"translated": "vcs_tr_step", "grouped": "k_step_grouped", "plain": "k_step_plain"}[args.kernel]
         line["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                             "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(),
                             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                            "algorithmic_bytes_per_launch": args.envs * args.chunk * (33600 + 128 + 1 + 1),
+                            "algorithmic_bytes_per_launch": alg_bytes,
                             "ops_per_env_step": ops_per_step, "instructions_per_env_step": ips,
+                            "ops_model": f"{OPS_PER_INSTRUCTION} integer ops per emulated 6507 instruction (opcode "
+                                         "fetch, operand fetch, decode, address, bus decode, access, ALU, N/Z, C/V, "
+                                         "PC, cycles, loop test) + 1 store per returned pixel: an algorithmic model",
                             "kernel": {"translated": "vcs_tr_step (translated)", "grouped": "k_step (grouped)",
-                                       "plain": "k_step (plain)"}[args.kernel]}
+                                       "plain": "k_step (plain)"}[args.kernel],
+                            "valu_issue": counter_fractions(profile_figures(f"{kname}_c1_sq_counters.md"), kname,
+                                                            launch_s),
+                            "hbm": {"achieved_GBps": alg_bytes / launch_s / 1e9, "peak_GBps": HBM_PEAK_GBPS,
+                                    "frac": alg_bytes / launch_s / 1e9 / HBM_PEAK_GBPS,
+                                    "note": "algorithmic bytes (frames, RAM, done, actions) per launch / launch time"}}
         line["instructions_per_s"] = h["env_steps_per_s"] * ips
         line["frames_per_s"] = h["env_steps_per_s"] * 4
         line["parity_sample"] = h["parity_sample"]
@@ -362,8 +517,18 @@ def main():
     if h and h.get("translation"):
         line["translation"] = h["translation"]
     if "hetero" in result:
-        line["hetero"] = {k: result["hetero"][k] for k in ("env_steps_per_s", "ms_per_call", "parity_sample",
-                                                           "workload", "launch")}
+        r2 = result["hetero"]
+        line["hetero"] = {k: r2[k] for k in ("env_steps_per_s", "ms_per_call", "parity_sample", "workload", "launch",
+                                             "instructions_per_env_step")}
+        ips2 = r2["instructions_per_env_step"]
+        ops2 = ips2 * OPS_PER_INSTRUCTION + 33600 * OPS_PER_PIXEL
+        ach2 = r2["env_steps_per_s"] * ops2 / 1e12
+        line["hetero"]["instructions_per_s"] = r2["env_steps_per_s"] * ips2
+        line["hetero"]["roofline"] = {
+            "bound": "alu", "achieved": ach2, "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach2 / VALU_PEAK_TOPS,
+            "ops_per_env_step": ops2, "kernel": "k_step (grouped, heterogeneous)",
+            "valu_issue": counter_fractions(profile_figures("k_step_c2_hetero_sq_counters.md"), "k_step_hetero",
+                                            r2["ms_per_call"] / 1e3)}
     if tuned:
         line["autotune"] = {k: {"trials (lanes_per_env, block_threads, env_steps_per_s)": v}
                             for k, v in tuned.items()}
