@@ -15,6 +15,12 @@ from . import build as _build
 _lib = None
 
 SCREEN = (210, 160)
+# cartridge formats (the oracle's numbering, shared with the library's C ABI)
+MAPPER_2K, MAPPER_4K, MAPPER_F8, MAPPER_F6, MAPPER_F4, MAPPER_F8SC, MAPPER_F6SC, MAPPER_F4SC, MAPPER_E0 = range(9)
+MAPPER_SIZE = {MAPPER_2K: 2048, MAPPER_4K: 4096, MAPPER_F8: 8192, MAPPER_F6: 16384, MAPPER_F4: 32768,
+               MAPPER_F8SC: 8192, MAPPER_F6SC: 16384, MAPPER_F4SC: 32768, MAPPER_E0: 8192}
+ACTION_RESET = 18  # the console RESET switch held, joystick idle
+
 REG_NAMES = ["A", "X", "Y", "S", "P", "PCL", "PCH", "bank", "jammed", "INTIM", "TIMINT", "VBLANK",
              "COLUP0", "COLUP1", "COLUPF", "COLUBK", "CTRLPF", "PF0", "PF1", "PF2", "VSYNC", "cycle",
              "instructions", "episode", "ep_step"]
@@ -65,6 +71,10 @@ def lib():
         L.orc_opcode_info.argtypes = [C.c_int] + [C.POINTER(C.c_int)] * 4
         L.orc_alu.argtypes = [C.c_int] * 4 + [C.POINTER(C.c_int)] * 2
         L.orc_splitmix_ram.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, u8p]
+        L.orc_splitmix_sc_ram.argtypes = [C.c_uint64, C.c_uint64, C.c_uint64, u8p]
+        L.orc_set_sc_ram.argtypes = [vp, u8p]
+        L.orc_sc_ram.argtypes = [vp]
+        L.orc_sc_ram.restype = C.POINTER(C.c_uint8)
         L.orc_splitmix_next.argtypes = [C.POINTER(C.c_uint64)]
         L.orc_splitmix_next.restype = C.c_uint64
         L.orc_gate.argtypes = [C.c_double, C.c_double]
@@ -128,6 +138,12 @@ class Machine:
 
     def env_step(self, action: int, frame_skip: int, step_index: int, store_frame: bool = True):
         self.L.orc_env_step(self.h, action, frame_skip, step_index, int(store_frame))
+
+    def set_sc_ram(self, v):
+        self.L.orc_set_sc_ram(self.h, np.ascontiguousarray(v, dtype=np.uint8))
+
+    def sc_ram(self) -> np.ndarray:
+        return np.ctypeslib.as_array(self.L.orc_sc_ram(self.h), shape=(128,)).copy()
 
     def regs(self) -> dict:
         out = np.zeros(25, np.int64)
@@ -196,6 +212,13 @@ def alu(op: str, a: int, v: int, p: int):
 def splitmix_ram(seed: int, env: int, episode: int) -> np.ndarray:
     out = np.zeros(128, np.uint8)
     lib().orc_splitmix_ram(seed, env, episode, out)
+    return out
+
+
+def splitmix_sc_ram(seed: int, env: int, episode: int) -> np.ndarray:
+    """Seeded Superchip RAM of (seed, env, episode)."""
+    out = np.zeros(128, np.uint8)
+    lib().orc_splitmix_sc_ram(seed, env, episode, out)
     return out
 
 

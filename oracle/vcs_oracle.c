@@ -369,8 +369,10 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 struct Orc {
     /* cartridge */
-    uint8_t rom[8192];
+    uint8_t rom[32768];
     int rom_size, mapper, bank;
+    int slice[4];         /* E0: the 1 KB slice mapped at each quarter of the cartridge window */
+    uint8_t sc_ram[128];  /* Superchip RAM (F8SC, F6SC, F4SC) */
     /* 6507 */
     uint8_t a, x, y, s, p;
     uint16_t pc;
@@ -381,7 +383,7 @@ struct Orc {
     int tim_value;     /* V */
     int tim_interval;  /* I */
     int64_t tim_read;  /* cycle of the last INTIM read */
-    uint8_t swcha, inpt4;
+    uint8_t swcha, inpt4, swchb;
     /* TIA */
     uint8_t vsync, vblank, colup0, colup1, colupf, colubk, ctrlpf, pf0, pf1, pf2;
     int wsync;
@@ -411,10 +413,38 @@ Orc *orc_new(void) {
 
 void orc_free(Orc *m) { free(m); }
 
+/* Cartridge formats beyond 2K/4K (Sec. "Building Two Differentiable VCS Ports":
+ * F8, F6, F4, their Superchip variants, E0).  F8/F6/F4 switch the whole 4 KB
+ * window among 2/4/8 banks on a data access to one of their hotspots
+ * ($1FF8-9, $1FF6-9, $1FF4-B); E0 maps 1 KB slices into the window's
+ * first three quarters on accesses to $1FE0-7, $1FE8-F, $1FF0-7 (the last
+ * quarter is slice 7).  Superchip carts add 128 bytes of RAM written through
+ * $1000-$107F and read through $1080-$10FF. */
+static int mapper_banks(int mapper) {
+    switch (mapper) {
+        case ORC_MAPPER_F8: case ORC_MAPPER_F8SC: return 2;
+        case ORC_MAPPER_F6: case ORC_MAPPER_F6SC: return 4;
+        case ORC_MAPPER_F4: case ORC_MAPPER_F4SC: return 8;
+        default: return 1;
+    }
+}
+static int mapper_size(int mapper) {
+    switch (mapper) {
+        case ORC_MAPPER_2K: return 2048;
+        case ORC_MAPPER_4K: return 4096;
+        case ORC_MAPPER_E0: return 8192;
+        default: return 4096 * mapper_banks(mapper);
+    }
+}
+static int mapper_sc(int mapper) {
+    return mapper == ORC_MAPPER_F8SC || mapper == ORC_MAPPER_F6SC || mapper == ORC_MAPPER_F4SC;
+}
+
 static int cart_offset(const Orc *m, uint16_t addr) {
     switch (m->mapper) {
         case ORC_MAPPER_2K: return addr & 0x7FF;
         case ORC_MAPPER_4K: return addr & 0xFFF;
+        case ORC_MAPPER_E0: return m->slice[(addr >> 10) & 3] * 1024 + (addr & 0x3FF);
         default: return m->bank * 4096 + (addr & 0xFFF);
     }
 }
@@ -520,7 +550,7 @@ static uint8_t riot_read(Orc *m, uint16_t addr, int64_t t, int side_effects) {
     if (!(addr & 0x04)) {
         switch (addr & 0x03) {
             case 0: return m->swcha;
-            case 2: return 0x0B; /* SWCHB: colour, difficulty B, no switch pressed */
+            case 2: return m->swchb; /* SWCHB: colour, difficulty B; RESET (bit 0) low while held */
             default: return 0x00; /* data-direction registers: all inputs */
         }
     }
@@ -590,6 +620,7 @@ static uint8_t ram_value(Orc *m, int cell) {
 /* Fetch-type read: no side effects (opcode/operand fetches, pointers, NOP reads). */
 static uint8_t bus_peek(Orc *m, uint16_t addr, int64_t t) {
     addr &= 0x1FFF;
+    if (mapper_sc(m->mapper) && (addr & 0x1F80) == 0x1080) return m->sc_ram[addr & 0x7F];
     if (addr & 0x1000) return rom_value(m, cart_offset(m, addr));
     if (!(addr & 0x80)) return tia_read(m, addr);
     if (!(addr & 0x200)) return ram_value(m, addr & 0x7F);
@@ -597,15 +628,21 @@ static uint8_t bus_peek(Orc *m, uint16_t addr, int64_t t) {
 }
 
 static void hotspot(Orc *m, uint16_t addr) {
-    if (m->mapper == ORC_MAPPER_F8) {
-        if (addr == 0x1FF8) m->bank = 0;
-        if (addr == 0x1FF9) m->bank = 1;
+    if (m->mapper == ORC_MAPPER_E0) {
+        if (addr >= 0x1FE0 && addr <= 0x1FF7) m->slice[(addr - 0x1FE0) >> 3] = addr & 7;
+        return;
+    }
+    const int n = mapper_banks(m->mapper);
+    if (n > 1) { /* F8: $1FF8-9, F6: $1FF6-9, F4: $1FF4-B */
+        const int first = n == 2 ? 0x1FF8 : n == 4 ? 0x1FF6 : 0x1FF4;
+        if (addr >= first && addr < first + n) m->bank = addr - first;
     }
 }
 
 /* Data read at cycle t (R5). */
 static uint8_t bus_read(Orc *m, uint16_t addr, int64_t t) {
     addr &= 0x1FFF;
+    if (mapper_sc(m->mapper) && (addr & 0x1F80) == 0x1080) return m->sc_ram[addr & 0x7F];
     if (addr & 0x1000) {
         hotspot(m, addr);
         return rom_value(m, cart_offset(m, addr));
@@ -626,6 +663,10 @@ static void draw_before_write(Orc *m, uint16_t addr, int64_t w) {
 /* Data write at cycle w (R5). */
 static void bus_write(Orc *m, uint16_t addr, uint8_t v, int64_t w) {
     addr &= 0x1FFF;
+    if (mapper_sc(m->mapper) && (addr & 0x1F80) == 0x1000) {
+        m->sc_ram[addr & 0x7F] = v;
+        return;
+    }
     if (addr & 0x1000) {
         hotspot(m, addr);
         return;
@@ -769,13 +810,16 @@ int orc_power_on(Orc *m, const uint8_t *rom, int rom_size, int mapper, const uin
     m->g = g;
     m->rx = rx;
     if (ystart < 0 || ystart + SCREEN_H > LINES_PER_FRAME) return -1;
-    if (!((mapper == ORC_MAPPER_2K && rom_size == 2048) || (mapper == ORC_MAPPER_4K && rom_size == 4096) ||
-          (mapper == ORC_MAPPER_F8 && rom_size == 8192)))
-        return -1;
+    if (mapper < 0 || mapper >= ORC_MAPPER_COUNT || rom_size != mapper_size(mapper)) return -1;
     memcpy(m->rom, rom, (size_t)rom_size);
     m->rom_size = rom_size;
     m->mapper = mapper;
-    m->bank = mapper == ORC_MAPPER_F8 ? 1 : 0;
+    /* power-on banks: F8 (and F8SC) bank 1, F6/F4 bank 0, E0 slices 4, 5, 6 (7 fixed) */
+    m->bank = (mapper == ORC_MAPPER_F8 || mapper == ORC_MAPPER_F8SC) ? 1 : 0;
+    m->slice[0] = 4;
+    m->slice[1] = 5;
+    m->slice[2] = 6;
+    m->slice[3] = 7;
     memcpy(m->ram, ram0, 128);
     m->a = m->x = m->y = 0;
     m->s = 0xFD;
@@ -786,6 +830,7 @@ int orc_power_on(Orc *m, const uint8_t *rom, int rom_size, int mapper, const uin
     m->tim_read = 0;
     m->swcha = 0xFF;
     m->inpt4 = 0x80;
+    m->swchb = 0x0B;
     m->ystart = ystart;
     m->draw_frame = -1;
     uint16_t lo = bus_peek(m, 0x1FFC, 0), hi = bus_peek(m, 0x1FFD, 0);
@@ -1174,9 +1219,24 @@ static void run_until(Orc *m, int64_t budget) {
     tia_draw_until(m, 3 * m->cycle);
 }
 
+/* Actions 0..17: the joystick; ORC_ACTION_RESET: the console's RESET switch held
+ * with the joystick idle (the boot sequence's RESET frames). */
 void orc_set_action(Orc *m, int action) {
-    m->swcha = (uint8_t)orc_action_swcha(action);
-    m->inpt4 = (uint8_t)orc_action_inpt4(action);
+    const int joy = action == ORC_ACTION_RESET ? 0 : action;
+    m->swcha = (uint8_t)orc_action_swcha(joy);
+    m->inpt4 = (uint8_t)orc_action_inpt4(joy);
+    m->swchb = action == ORC_ACTION_RESET ? 0x0A : 0x0B;
+}
+
+/* Superchip RAM contents (for the formats that have it). */
+void orc_set_sc_ram(Orc *m, const uint8_t *v) { memcpy(m->sc_ram, v, 128); }
+const uint8_t *orc_sc_ram(const Orc *m) { return m->sc_ram; }
+
+/* Seeded Superchip RAM of (seed, env, episode): its own SplitMix64 stream, the
+ * RAM stream's with the seed offset by ORC_SC_SEED (the paper pins this RAM's
+ * contents deterministically; Sec. Discussion). */
+void orc_splitmix_sc_ram(uint64_t seed, uint64_t env, uint64_t episode, uint8_t *out) {
+    orc_splitmix_ram(seed ^ ORC_SC_SEED, env, episode, out);
 }
 
 /* One env step of `frame_skip` frames; `step_index` counts steps since power-on
@@ -1334,6 +1394,9 @@ int orc_run_env(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram
         orc_free(m);
         return -1;
     }
+    uint8_t sc[128];
+    orc_splitmix_sc_ram(seed, (uint64_t)env_index, 0, sc);
+    orc_set_sc_ram(m, sc);
     int64_t ep = 0, ep_step = 0;
     uint64_t total_instr = 0;
     for (int s = 0; s < steps; s++) {
@@ -1353,6 +1416,8 @@ int orc_run_env(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram
             uint8_t r[128];
             orc_splitmix_ram(seed, (uint64_t)env_index, (uint64_t)ep, r);
             orc_power_on(m, rom, rom_size, mapper, r, ystart);
+            orc_splitmix_sc_ram(seed, (uint64_t)env_index, (uint64_t)ep, sc);
+            orc_set_sc_ram(m, sc);
             ep_step = 0;
         }
         if (step_state) { /* machine state after the step: the 16 inspection bytes, then RAM */
@@ -1496,6 +1561,8 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
                       int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
                       uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
                       double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
+    /* the soft value graph has no content nodes for Superchip RAM: those formats run hard only */
+    if (mapper < 0 || mapper >= ORC_MAPPER_COUNT || mapper_sc(mapper)) return -1;
     Graph *g = (Graph *)calloc(1, sizeof(Graph));
     g->rom_size = rom_size;
     g->rom_hard = rom_hard;

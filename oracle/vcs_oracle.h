@@ -7,7 +7,14 @@
 #define VCS_ORACLE_H
 #include <stdint.h>
 
-enum { ORC_MAPPER_2K = 0, ORC_MAPPER_4K = 1, ORC_MAPPER_F8 = 2 };
+enum {
+    ORC_MAPPER_2K = 0, ORC_MAPPER_4K = 1, ORC_MAPPER_F8 = 2, ORC_MAPPER_F6 = 3, ORC_MAPPER_F4 = 4,
+    ORC_MAPPER_F8SC = 5, ORC_MAPPER_F6SC = 6, ORC_MAPPER_F4SC = 7, ORC_MAPPER_E0 = 8, ORC_MAPPER_COUNT = 9
+};
+
+/* action code of the console RESET switch held (joystick idle); 0..17 are the joystick actions */
+enum { ORC_ACTION_RESET = 18 };
+#define ORC_SC_SEED 0x5343534352414D00ull /* "SCSCRAM\0": seed offset of the Superchip RAM stream */
 
 typedef struct Orc Orc;
 
@@ -37,6 +44,9 @@ void orc_alu(int op, int a, int v, int p_in, int *result, int *p_out);
 int orc_action_swcha(int action);
 int orc_action_inpt4(int action);
 void orc_splitmix_ram(uint64_t seed, uint64_t env, uint64_t episode, uint8_t *out);
+void orc_splitmix_sc_ram(uint64_t seed, uint64_t env, uint64_t episode, uint8_t *out);
+void orc_set_sc_ram(Orc *m, const uint8_t *v);
+const uint8_t *orc_sc_ram(const Orc *m);
 uint64_t orc_splitmix_next(uint64_t *state);
 double orc_gate(double z, double alpha);
 double orc_gate_grad(double z, double alpha);
