@@ -32,7 +32,9 @@
  *  - An env step applies one action for `frame_skip` frames and ends at the
  *    first instruction boundary at or after the step's cycle budget.
  *  - Actions are the 18 standard ALE joystick actions (0 = NOOP ... 17 =
- *    DOWNLEFTFIRE).
+ *    DOWNLEFTFIRE) and, for hard steps, 18 = the console RESET switch held
+ *    (SWCHB bit 0 low, joystick idle): the boot sequence's RESET frames (Table
+ *    s-params: 60 NOOP + 4 RESET frames).
  */
 #ifndef VCS_H
 #define VCS_H
@@ -57,9 +59,26 @@ typedef enum vcs_status {
     VCS_BAD_STATE_VERSION = -5   /* reserved: state produced by another ABI version */
 } vcs_status;
 
-/* Cartridge formats (Sec. "Building Two Differentiable VCS Ports": 2K, 4K and
- * the F8 two-bank 8K scheme with hotspots $1FF8/$1FF9). */
-typedef enum vcs_mapper { VCS_MAPPER_2K = 0, VCS_MAPPER_4K = 1, VCS_MAPPER_F8 = 2 } vcs_mapper;
+/* Cartridge formats (Sec. "Building Two Differentiable VCS Ports": 2K, 4K, F8,
+ * F6, F4, their Superchip variants and E0).
+ *  - 2K (2048 bytes, mirrored) and 4K (4096);
+ *  - F8 / F6 / F4 (8 / 16 / 32 KB): 4 KB banks selected by a data access (read
+ *    or write) to $1FF8-9 / $1FF6-9 / $1FF4-B; power-on bank 1 for F8, 0 for
+ *    F6 and F4; a hotspot read returns the newly selected bank's byte;
+ *  - F8SC / F6SC / F4SC: the same plus 128 bytes of Superchip RAM written at
+ *    $1000-$107F and read at $1080-$10FF (a read of the write port returns the
+ *    ROM byte); vcs_reset and in-run resets seed it with SplitMix64 on the seed
+ *    XOR 0x5343534352414D00 (env, episode), as RAM;
+ *  - E0 (8 KB, eight 1 KB slices): $1FE0-7 / $1FE8-F / $1FF0-7 select the
+ *    slice of the window's first / second / third quarter (power-on slices 4,
+ *    5, 6); the last quarter is slice 7.
+ * Images larger than 16 KB (F4, F4SC) need VCS_KERNEL_PLAIN: the LDS-staged
+ * kernels hold an image as 8-byte pre-decoded words in one CU's LDS.  The
+ * soft path takes no Superchip format; TRANSLATED takes 2K, 4K and F8. */
+typedef enum vcs_mapper {
+    VCS_MAPPER_2K = 0, VCS_MAPPER_4K = 1, VCS_MAPPER_F8 = 2, VCS_MAPPER_F6 = 3, VCS_MAPPER_F4 = 4,
+    VCS_MAPPER_F8SC = 5, VCS_MAPPER_F6SC = 6, VCS_MAPPER_F4SC = 7, VCS_MAPPER_E0 = 8
+} vcs_mapper;
 
 /* Kernel family used for the emulation step. */
 typedef enum vcs_kernel {
@@ -81,7 +100,7 @@ typedef struct vcs_config {
     int32_t abi_version;        /* must be VCS_ABI_VERSION */
     int32_t num_envs;           /* B >= 1 */
     int32_t num_roms;           /* R >= 1 */
-    const int32_t *rom_size;    /* host [R]: 2048, 4096 or 8192 bytes */
+    const int32_t *rom_size;    /* host [R]: the size of the format (2048 ... 32768 bytes) */
     const int32_t *rom_mapper;  /* host [R]: vcs_mapper matching the size */
     const int32_t *env_rom;     /* host [B]: ROM index of each env */
     int32_t frame_skip;         /* frames per env step, >= 1 */
@@ -109,7 +128,8 @@ void vcs_destroy(vcs_ctx *ctx);
 const char *vcs_status_string(int32_t status);
 
 /* Sizes of caller-allocated device buffers:
- *  - state: B opaque 256-byte records (vcs_state_bytes = B*256);
+ *  - state: B opaque 256-byte records, followed (when some image is a
+ *    Superchip format) by B 128-byte Superchip RAM blocks (vcs_state_bytes);
  *  - roms:  the concatenated ROM images (sum of rom_size[]) as uint8;
  *  - workspace for op (VCS_OP_*) and S steps;
  *  - soft residual (saved by the forward, read by the backward) for S steps;
@@ -291,6 +311,16 @@ int32_t vcs_bwd_overflow(const vcs_ctx *ctx, const void *d_work, int32_t steps, 
  * whose tape overflowed), so that callers can test it on the device without
  * synchronising (host only). */
 int32_t vcs_bwd_overflow_offset(const vcs_ctx *ctx, int32_t steps, size_t *offset);
+
+/* Content-based format detection (host only; the paper's ports auto-detect
+ * the mapper from the image, Sec. "Building Two Differentiable VCS Ports"):
+ * 2 KB -> 2K, 4 KB -> 4K; 8 KB -> E0 when the image makes more absolute
+ * accesses (LDA/LDX/LDY/STA/STX/STY/BIT/CMP) to the E0 hotspots $xFE0-$xFF7
+ * than to the F8 ones $xFF8-9, else F8; 16 KB -> F6, 32 KB -> F4; a banked
+ * format is its Superchip variant when the first 256 bytes of every 4 KB bank
+ * (the RAM window) hold one repeated value.  *mapper = a vcs_mapper;
+ * VCS_INVALID_ARG for other sizes.  A heuristic: an image may defeat it. */
+int32_t vcs_detect_mapper(const uint8_t *image, size_t size, int32_t *mapper);
 
 /* Launch geometry chosen at create time (host values; NULL outputs skipped):
  * kernel family, lanes per env, threads per workgroup, step-kernel workgroups,

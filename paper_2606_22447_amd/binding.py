@@ -12,7 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvcs.so")
 
 VCS_OK = 0
-VCS_MAPPER_2K, VCS_MAPPER_4K, VCS_MAPPER_F8 = 0, 1, 2
+(VCS_MAPPER_2K, VCS_MAPPER_4K, VCS_MAPPER_F8, VCS_MAPPER_F6, VCS_MAPPER_F4, VCS_MAPPER_F8SC, VCS_MAPPER_F6SC,
+ VCS_MAPPER_F4SC, VCS_MAPPER_E0) = range(9)
+ACTION_RESET = 18  # the console RESET switch held (hard steps)
 VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED, VCS_KERNEL_TRANSLATED = 0, 1, 2, 3
 VCS_TRANSLATE_COMPILE_ONLY = 1
 VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
@@ -26,6 +28,7 @@ EXPORTED = [
     "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
     "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash", "vcs_translate",
     "vcs_translated_source", "vcs_step_hard_static", "vcs_bwd_overflow_offset", "vcs_step_relaxed",
+    "vcs_detect_mapper",
 ]
 
 
@@ -85,6 +88,7 @@ def lib():
         L.vcs_bwd_overflow_offset.argtypes = [vp, i32, C.POINTER(sz)]
         L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5
         L.vcs_decode_table.argtypes = [C.POINTER(C.c_uint32)]
+        L.vcs_detect_mapper.argtypes = [vp, sz, C.POINTER(i32)]
         L.vcs_translate.argtypes = [vp, vp, i32, i32, C.POINTER(VcsTranslateInfo), C.c_char_p, sz]
         L.vcs_translated_source.argtypes = [vp, vp, i32, C.c_char_p, sz, C.POINTER(sz)]
         for f in EXPORTED:
@@ -109,6 +113,15 @@ def ptr(t):
     if hasattr(t, "data_ptr"):
         return C.c_void_p(t.data_ptr())
     return t.ctypes.data_as(C.c_void_p)
+
+
+def detect_mapper(image) -> int:
+    """vcs_detect_mapper on a host image (uint8 array)."""
+    import numpy as np
+    img = np.ascontiguousarray(image, np.uint8)
+    out = C.c_int32()
+    check(lib().vcs_detect_mapper(img.ctypes.data, img.size, C.byref(out)), "vcs_detect_mapper")
+    return out.value
 
 
 def decode_table():

@@ -17,6 +17,7 @@ using namespace vcs;
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS of one CU on gfx950
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -27,6 +28,7 @@ struct vcs_ctx {
     uint64_t seed = 0;
     std::vector<int32_t> rom_size, rom_mapper, env_rom, rom_off;
     int32_t max_rom = 0, total_rom = 0;
+    bool any_sc = false;         // some image is a Superchip format: its RAM follows the state records
     int32_t main_E = 0, main_blocks = 0, bwd_blocks = 0;
     std::vector<int32_t> main_block_rom, main_slot_env;
     std::vector<int32_t> bwd_block_rom, bwd_slot_env, env_bwd_slot, rom_bwd_begin, rom_bwd_end;
@@ -149,6 +151,23 @@ int32_t upload_static(vcs_ctx *c, void *d_work, hipStream_t stream) {
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? VCS_OK : VCS_HIP_ERROR; }
 
+// Whether the LDS-staged step kernels fit the context's images and launch shape.
+bool lds_fits(const vcs_ctx *c) {
+    const size_t E = (size_t)(c->tpb / c->G);
+    return (size_t)c->max_rom * 8 + E * 128 * (c->any_sc ? 2 : 1) + 1024 <= kLdsBytes;
+}
+
+// The Superchip RAM of a context with a Superchip image: [B][128] after the state records.
+uint8_t *sc_state(const vcs_ctx *c, const void *d_state) {
+    return c->any_sc ? (uint8_t *)d_state + (size_t)c->B * sizeof(StateRec) : nullptr;
+}
+
+// Dynamic LDS of the grouped step kernels: the image's pre-decoded words, then
+// (with a Superchip image) the workgroup's Superchip RAM.
+size_t step_lds(const vcs_ctx *c) {
+    return (size_t)c->max_rom * sizeof(uint2) + (c->any_sc ? (size_t)(c->tpb / c->G) * 128 : 0);
+}
+
 // Launch tables of vcs_step_hard_static: a fixed device array, so that the
 // entry point needs no caller workspace and allocates nothing.  Every device
 // the library runs on holds its own copy until the process ends; host code
@@ -227,12 +246,11 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
     int64_t total = 0;
     for (int32_t r = 0; r < c->R; ++r) {
         const int32_t sz = cfg->rom_size[r], mp = cfg->rom_mapper[r];
-        const bool ok = (mp == VCS_MAPPER_2K && sz == 2048) || (mp == VCS_MAPPER_4K && sz == 4096) ||
-                        (mp == VCS_MAPPER_F8 && sz == 8192);
-        if (!ok) {
+        if (mp < 0 || mp >= kMapperCount || sz != mapper_size(mp)) {
             delete c;
             return VCS_INVALID_ARG;
         }
+        c->any_sc = c->any_sc || mapper_sc(mp);
         c->rom_size.push_back(sz);
         c->rom_mapper.push_back(mp);
         c->rom_off.push_back((int32_t)total);
@@ -290,8 +308,19 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         return VCS_UNSUPPORTED;
     }
     // translated code keeps a pixel-write log per env in LDS: at most 64 envs per workgroup
-    // (with the largest ROM image staged beside it)
-    if (c->kernel == VCS_KERNEL_TRANSLATED && c->tpb / c->G > 64) {
+    // (with the largest ROM image staged beside it); its translator handles 2K, 4K and F8
+    if (c->kernel == VCS_KERNEL_TRANSLATED) {
+        bool ok = c->tpb / c->G <= 64;
+        for (int32_t mp : c->rom_mapper) ok = ok && (mp == kMapper2K || mp == kMapper4K || mp == kMapperF8);
+        if (!ok) {
+            delete c;
+            return VCS_UNSUPPORTED;
+        }
+    }
+    // the LDS-staged kernels hold the image as 8-byte pre-decoded words, the envs' RAM
+    // and Superchip RAM and the decode table in one CU's 160 KB; the plain kernel reads
+    // global memory
+    if (c->kernel != VCS_KERNEL_PLAIN && !lds_fits(c)) {
         delete c;
         return VCS_UNSUPPORTED;
     }
@@ -363,7 +392,7 @@ void vcs_destroy(vcs_ctx *ctx) { delete ctx; }
 
 int32_t vcs_state_bytes(const vcs_ctx *ctx, size_t *bytes) {
     if (!ctx || !bytes) return VCS_INVALID_ARG;
-    *bytes = (size_t)ctx->B * sizeof(StateRec);
+    *bytes = (size_t)ctx->B * (sizeof(StateRec) + (ctx->any_sc ? 128 : 0));
     return VCS_OK;
 }
 
@@ -406,7 +435,8 @@ int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint
     if (d_ram0 && ((uintptr_t)d_ram0 & 3u)) return VCS_INVALID_ARG;
     const int32_t rc = ensure_pinned(ctx);  // so that later step calls can be captured
     if (rc) return rc;
-    return hip_status(launch_reset((StateRec *)d_state, ctx->B, d_mask, d_ram0, ctx->seed, stream));
+    return hip_status(launch_reset((StateRec *)d_state, ctx->B, d_mask, d_ram0, ctx->seed, sc_state(ctx, d_state),
+                                   stream));
 }
 
 }  // extern "C"
@@ -446,6 +476,8 @@ int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
     P.ep_steps = d_episode_steps;
     P.num_episodes = d_episode_steps ? num_episodes : 0;
     P.seed = ctx->seed;
+    P.sc_state = sc_state(ctx, d_state);
+    P.rom_words = ctx->max_rom;
     if (ctx->kernel == VCS_KERNEL_TRANSLATED) {
         int dev = -1;
         if (!ctx->tr_fn || hipGetDevice(&dev) != hipSuccess || dev != ctx->tr_device) return VCS_UNSUPPORTED;
@@ -455,7 +487,7 @@ int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
                                                 1, (unsigned)lds, stream, args, nullptr));
     }
     return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
-                                  ctx->max_rom, stream));
+                                  step_lds(ctx), stream));
 }
 
 }  // namespace
@@ -518,13 +550,16 @@ int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
     P.ram_out = d_ram_out;
     P.frame_out = frames == VCS_FRAMES_NONE ? nullptr : d_frame_out;
     P.seed = ctx->seed;
+    P.sc_state = sc_state(ctx, d_state);
+    P.rom_words = ctx->max_rom;
     // the weights and gates in double, stored as float (the kernel sums in float)
     P.relax_u[0] = 1.0f;
     for (int k = 1; k <= 8; ++k) P.relax_u[k] = (float)std::exp(-(double)k / T);
     P.relax_g_taken = (float)(1.0 / (1.0 + std::exp(-alpha)));
     P.relax_g_not = (float)(1.0 / (1.0 + std::exp(alpha)));
     P.relax_out = d_relax_out;
-    return hip_status(launch_step_relaxed(P, ctx->main_blocks, ctx->G, ctx->tpb, ctx->max_rom, stream));
+    if (!lds_fits(ctx)) return VCS_UNSUPPORTED;  // the relaxed kernel stages the image in LDS
+    return hip_status(launch_step_relaxed(P, ctx->main_blocks, ctx->G, ctx->tpb, step_lds(ctx), stream));
 }
 
 int32_t vcs_translated_source(const vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, char *buf,
@@ -602,7 +637,7 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
         (d_state_out && !aligned16(d_state_out)) || (d_decode_out && ((uintptr_t)d_decode_out & 3u)))
         return VCS_INVALID_ARG;
     if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
-    if (ctx->kernel == VCS_KERNEL_PLAIN) return VCS_UNSUPPORTED;
+    if (ctx->kernel == VCS_KERNEL_PLAIN || ctx->any_sc) return VCS_UNSUPPORTED;  // no Superchip RAM in the soft graph
     int32_t rc = upload_static(ctx, d_work, stream);
     if (rc) return rc;
     const ResidualLayout L = residual_layout(ctx, steps);
@@ -633,7 +668,8 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
     P.ckpt_count = (int32_t *)(res + L.ckpt_count);
     P.ckpt_interval = ctx->K;
     P.max_ckpt = L.max_ckpt;
-    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, ctx->max_rom, stream));
+    P.rom_words = ctx->max_rom;
+    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, step_lds(ctx), stream));
     if (rc) return rc;
     if (d_decode_out &&
         hipMemcpyAsync(d_decode_out, res + L.stats, L.stats_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
@@ -658,6 +694,7 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
         (d_grad_ram_out && ((uintptr_t)d_grad_ram_out & 3u)))
         return VCS_INVALID_ARG;
     if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
+    if (ctx->any_sc || (size_t)ctx->max_rom * 8 + 16 * 128 + 1024 > kLdsBytes) return VCS_UNSUPPORTED;
     int32_t rc = upload_static(ctx, d_work, stream);
     if (rc) return rc;
     const ResidualLayout L = residual_layout(ctx, steps);
@@ -704,6 +741,32 @@ int32_t vcs_hash(vcs_ctx *ctx, const void *d_state, const uint8_t *d_frame, int6
     if (!ctx || !d_state || !d_out || !aligned16(d_state) || ((uintptr_t)d_out & 7u)) return VCS_INVALID_ARG;
     if (d_frame && (((uintptr_t)d_frame & 3u) || frame_stride < kPixels || (frame_stride & 3))) return VCS_INVALID_ARG;
     return hip_status(launch_hash((const StateRec *)d_state, ctx->B, d_frame, frame_stride, d_out, stream));
+}
+
+int32_t vcs_detect_mapper(const uint8_t *image, size_t size, int32_t *mapper) {
+    if (!image || !mapper) return VCS_INVALID_ARG;
+    if (size == 2048) return *mapper = VCS_MAPPER_2K, VCS_OK;
+    if (size == 4096) return *mapper = VCS_MAPPER_4K, VCS_OK;
+    if (size != 8192 && size != 16384 && size != 32768) return VCS_INVALID_ARG;
+    // absolute accesses (loads, stores, BIT, CMP) to the E0 slice hotspots vs the F8 ones
+    size_t e0 = 0, f8 = 0;
+    for (size_t i = 0; i + 2 < size; ++i) {
+        const uint8_t op = image[i], lo = image[i + 1], hi = image[i + 2];
+        const bool abs = op == 0xAD || op == 0x8D || op == 0x2C || op == 0xAE || op == 0xAC || op == 0x8E ||
+                         op == 0x8C || op == 0xCD;
+        if (!abs || (hi & 0x1F) != 0x1F) continue;
+        if (lo >= 0xE0 && lo <= 0xF7) ++e0;
+        if (lo == 0xF8 || lo == 0xF9) ++f8;
+    }
+    if (size == 8192 && e0 > f8) return *mapper = VCS_MAPPER_E0, VCS_OK;
+    // Superchip: the first 256 bytes of every bank (the RAM window) hold one repeated value
+    bool sc = true;
+    for (size_t b = 0; b < size && sc; b += 4096)
+        for (size_t i = 1; i < 256 && sc; ++i) sc = image[b + i] == image[b];
+    const int32_t base = size == 8192 ? VCS_MAPPER_F8 : size == 16384 ? VCS_MAPPER_F6 : VCS_MAPPER_F4;
+    const int32_t with_sc = size == 8192 ? VCS_MAPPER_F8SC : size == 16384 ? VCS_MAPPER_F6SC : VCS_MAPPER_F4SC;
+    *mapper = sc ? with_sc : base;
+    return VCS_OK;
 }
 
 int32_t vcs_decode_table(uint32_t *out) {

@@ -336,13 +336,36 @@ struct Cpu {
     uint32_t col, pf, vb;         // colour registers, playfield + CTRLPF, VBLANK | VSYNC << 8
     int32_t tim_u, tim_read;
     uint32_t tim_shift;
-    uint32_t swcha, inpt4;
+    uint32_t swcha, inpt4, swchb;
     uint32_t wsync;
-    uint32_t amask, f8;           // cartridge address mask, F8 flag
+    // cartridge format (set_cart): address mask, hotspot range of the 4 KB bank
+    // switch, E0 slices (4 bits per quarter of the window), Superchip RAM
+    uint32_t amask, hot_lo, hot_n, e0, slices, sc;
+    uint32_t fetch_mask, fetch_lim;  // an instruction whose bytes lie in one bank/slice: (pc & mask) <= lim
     Mem mem;
     Hook hook;
 
-    __host__ __device__ __forceinline__ uint32_t cart_off(uint32_t addr) const { return (addr & amask) + (bank << 12); }
+    // Cartridge formats (Sec. "Building Two Differentiable VCS Ports": 2K, 4K, F8,
+    // F6, F4, their Superchip variants, E0).  F8/F6/F4 select a 4 KB bank on a
+    // data access to $1FF8-9 / $1FF6-9 / $1FF4-B; E0 maps 1 KB slices into the
+    // window's first three quarters through $1FE0-7 / $1FE8-F / $1FF0-7 (the last
+    // quarter is slice 7); Superchip formats add 128 bytes of RAM written at
+    // $1000-$107F and read at $1080-$10FF (a read of the write port returns ROM).
+    __host__ __device__ __forceinline__ void set_cart(int32_t mapper) {
+        amask = mapper == kMapper2K ? 0x7FFu : 0xFFFu;
+        const uint32_t nb = mapper_banks(mapper);
+        hot_n = nb > 1 ? nb : 0u;
+        hot_lo = nb == 2 ? 0x1FF8u : nb == 4 ? 0x1FF6u : 0x1FF4u;
+        e0 = mapper == kMapperE0 ? 1u : 0u;
+        sc = mapper_sc(mapper) ? 1u : 0u;
+        fetch_mask = e0 ? 0x3FFu : 0xFFFu;
+        fetch_lim = fetch_mask - 2u;
+    }
+    __host__ __device__ __forceinline__ uint32_t cart_off(uint32_t addr) const {
+        const uint32_t banked = (addr & amask) + (bank << 12);
+        const uint32_t sliced = (((slices >> (4u * ((addr >> 10) & 3u))) & 7u) << 10) | (addr & 0x3FFu);
+        return e0 ? sliced : banked;
+    }
 
     // processor status byte (B and U as stored in p)
     __host__ __device__ __forceinline__ uint32_t flags() const {
@@ -369,7 +392,7 @@ struct Cpu {
     __host__ __device__ __forceinline__ uint32_t riot_in(uint32_t addr, int32_t t, bool fx) {
         if (!(addr & 4u)) {
             const uint32_t r = addr & 3u;
-            return r == 0 ? swcha : (r == 2 ? 0x0Bu : 0u);
+            return r == 0 ? swcha : (r == 2 ? swchb : 0u);
         }
         if (!(addr & 1u)) {
             const uint32_t v = intim_at(t);
@@ -381,17 +404,23 @@ struct Cpu {
     // fetch-type read: no side effects
     __host__ __device__ __forceinline__ uint32_t peek(uint32_t addr, int32_t t) {
         addr &= 0x1FFFu;
+        if (sc && (addr & 0x1F80u) == 0x1080u) return mem.sc_byte(addr & 0x7Fu);
         if (addr & 0x1000u) return mem.rom_byte(cart_off(addr));
         if (!(addr & 0x80u)) return tia_in(addr);
         if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
         return riot_in(addr, t, false);
     }
     __host__ __device__ __forceinline__ void hotspot(uint32_t addr) {
-        if (f8 && (addr & 0x1FFEu) == 0x1FF8u) bank = addr & 1u;
+        if (addr - hot_lo < hot_n) bank = addr - hot_lo;
+        if (e0 && addr - 0x1FE0u < 24u) {
+            const uint32_t sh = 4u * ((addr - 0x1FE0u) >> 3);
+            slices = (slices & ~(0xFu << sh)) | ((addr & 7u) << sh);
+        }
     }
     // data read in cycle t
     __host__ __device__ __forceinline__ uint32_t read(uint32_t addr, int32_t t) {
         addr &= 0x1FFFu;
+        if (sc && (addr & 0x1F80u) == 0x1080u) return mem.sc_byte(addr & 0x7Fu);
         if (addr & 0x1000u) {
             hotspot(addr);
             return mem.rom_byte(cart_off(addr));
@@ -454,6 +483,10 @@ struct Cpu {
     // data write in cycle w
     __host__ __device__ __forceinline__ void write(uint32_t addr, uint32_t v, int32_t w) {
         addr &= 0x1FFFu;
+        if (sc && (addr & 0x1F80u) == 0x1000u) {
+            mem.sc_set(addr & 0x7Fu, v);
+            return;
+        }
         if (addr & 0x1000u) {
             hotspot(addr);
             return;
@@ -782,7 +815,8 @@ struct Cpu {
         a = x = y = 0;
         s = 0xFDu;
         set_flags(kFlagI | kFlagU);
-        bank = f8 ? 1u : 0u;
+        bank = hot_n == 2u ? 1u : 0u;            // F8 (and F8SC) start in bank 1, F6/F4 in bank 0
+        slices = 4u | (5u << 4) | (6u << 8) | (7u << 12);  // E0: slices 4, 5, 6 and the fixed 7
         jam = 0;
         cyc = 0;
         col = pf = vb = 0;
@@ -808,14 +842,16 @@ struct Cpu {
     }
 
     __host__ __device__ __forceinline__ void load(const StateRec &r) {
-        a = r.a; x = r.x; y = r.y; s = r.s; set_flags(r.p); pc = r.pc; bank = r.bank; jam = r.status & 1u;
+        a = r.a; x = r.x; y = r.y; s = r.s; set_flags(r.p); pc = r.pc; jam = r.status & 1u;
+        bank = hot_n ? (r.bank < hot_n ? r.bank : 0u) : 0u;  // only the banked formats have banks
+        slices = r.slices;
         cyc = r.cyc; col = r.col; pf = r.pf; vb = r.vblank | ((uint32_t)r.vsync << 8);
         tim_u = r.tim_u; tim_read = r.tim_read; tim_shift = r.tim_shift; wsync = 0;
     }
     __host__ __device__ __forceinline__ void store(StateRec &r) const {
         r.magic = kMagic;
         r.a = (uint8_t)a; r.x = (uint8_t)x; r.y = (uint8_t)y; r.s = (uint8_t)s; r.p = (uint8_t)flags();
-        r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u);
+        r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u); r.slices = (uint16_t)slices;
         r.cyc = cyc; r.col = col; r.pf = pf; r.vblank = (uint8_t)(vb & 0xFFu); r.vsync = (uint8_t)(vb >> 8);
         r.tim_u = tim_u; r.tim_read = tim_read; r.tim_shift = (uint8_t)tim_shift;
     }
@@ -825,7 +861,10 @@ struct Cpu {
 // UP RIGHT LEFT DOWN UPRIGHT UPLEFT DOWNRIGHT DOWNLEFT UPFIRE RIGHTFIRE LEFTFIRE
 // DOWNFIRE UPRIGHTFIRE UPLEFTFIRE DOWNRIGHTFIRE DOWNLEFTFIRE; SWCHA bits 7/6/5/4
 // (right/left/down/up) are cleared while held, INPT4 bit 7 clears on fire.
-__host__ __device__ __forceinline__ void action_ports(uint32_t action, uint32_t *swcha, uint32_t *inpt4) {
+__host__ __device__ __forceinline__ void action_ports(uint32_t action, uint32_t *swcha, uint32_t *inpt4,
+                                                      uint32_t *swchb = nullptr) {
+    // action 18: the console RESET switch held (SWCHB bit 0 low), joystick idle
+    if (swchb) *swchb = action == kActionReset ? 0x0Au : 0x0Bu;
     // direction bits per action: up 1, down 2, left 4, right 8, fire 16
     constexpr uint8_t dirs[18] = {0, 16, 1, 8, 4, 2, 9, 5, 10, 6, 17, 24, 20, 18, 25, 21, 26, 22};
     const uint32_t dm = action < 18 ? dirs[action] : 0u;

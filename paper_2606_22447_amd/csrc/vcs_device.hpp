@@ -77,6 +77,8 @@ __device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, 
     for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
     __syncthreads();
     LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
+    // Superchip RAM: [32 words][E] in LDS after the staged image
+    if (mapper_sc(mapper)) m.sc = reinterpret_cast<uint8_t *>(rom_lds + P.rom_words);
     step_env<DeviceWave, G, kSoft, false, X>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
 }
 
@@ -99,6 +101,7 @@ __device__ __forceinline__ void step_group_relaxed(const StepParams &P, uint2 *r
     RelaxMem<LdsWordMem> m;
     static_cast<LdsWordMem &>(m) = LdsWordMem{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E,
                                               slot};
+    if (mapper_sc(mapper)) m.sc = reinterpret_cast<uint8_t *>(rom_lds + P.rom_words);
     for (int k = 0; k < 9; ++k) m.rc.u[k] = P.relax_u[k];
     m.rc.g_taken = P.relax_g_taken;
     m.rc.g_not = P.relax_g_not;

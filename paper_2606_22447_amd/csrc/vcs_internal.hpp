@@ -25,6 +25,24 @@ constexpr uint32_t kMagic = 0x31534356u;      // "VCS1"
 // register per instruction).
 constexpr int kTrMaxRun = 32;
 
+// Cartridge formats (the numbering of vcs_mapper in include/vcs.h).
+constexpr int32_t kMapper2K = 0, kMapper4K = 1, kMapperF8 = 2, kMapperF6 = 3, kMapperF4 = 4, kMapperF8SC = 5,
+                  kMapperF6SC = 6, kMapperF4SC = 7, kMapperE0 = 8, kMapperCount = 9;
+__host__ __device__ constexpr uint32_t mapper_banks(int32_t m) {
+    return (m == kMapperF8 || m == kMapperF8SC) ? 2u : (m == kMapperF6 || m == kMapperF6SC) ? 4u
+         : (m == kMapperF4 || m == kMapperF4SC) ? 8u : 1u;
+}
+__host__ __device__ constexpr bool mapper_sc(int32_t m) {
+    return m == kMapperF8SC || m == kMapperF6SC || m == kMapperF4SC;
+}
+__host__ __device__ constexpr int32_t mapper_size(int32_t m) {
+    return m == kMapper2K ? 2048 : m == kMapper4K ? 4096 : m == kMapperE0 ? 8192 : 4096 * (int32_t)mapper_banks(m);
+}
+// Action code of the console RESET switch held (joystick idle); 0..17 are the joystick.
+constexpr uint32_t kActionReset = 18;
+// Seed offset of the Superchip RAM's SplitMix64 stream ("SCSCRAM\0").
+constexpr uint64_t kScSeed = 0x5343534352414D00ull;
+
 // One env's machine state in device memory (opaque to callers, 256 bytes).
 // Cycle counters are relative to the start of the current frame so that they
 // stay in 32 bits for arbitrarily long episodes.
@@ -47,7 +65,9 @@ struct alignas(16) StateRec {
     int32_t pix_cc;       // frame-relative colour clock of the last instruction's write point
     uint32_t ckpt_index;  // index of this checkpoint
     uint32_t from_tape;   // (checkpoint 0) 1: the RAM came from the soft tape at power-on; 0: a given state
-    uint32_t pad[15];
+    uint16_t slices;      // E0: the slice of each quarter of the cartridge window, 4 bits each
+    uint16_t pad16;
+    uint32_t pad[14];
     uint8_t ram[128];
 };
 static_assert(sizeof(StateRec) == 256, "state record must be 256 bytes");
@@ -80,6 +100,8 @@ struct StepParams {
     StaticPtrs st;
     const uint8_t *rom;        // concatenated ROM images
     StateRec *state;           // [B] in/out (NULL for a soft forward without state output)
+    uint8_t *sc_state;         // [B][128] Superchip RAM after the state records, or NULL (no Superchip image)
+    int32_t rom_words;         // LDS words staged for the ROM image; Superchip RAM follows them in LDS
     const uint8_t *actions;    // [B][S] or NULL
     int32_t steps;             // S
     int32_t frame_skip;        // F

@@ -144,9 +144,8 @@ Profile profile(const Image &im, uint64_t seed) {
             for (int k = 0; k < 8; ++k) ram[8 * w + k] = (uint8_t)(v >> (8 * k));
         }
         Cpu<GlobalMem, RenderHook<uint8_t>> c;
-        c.amask = im.mapper == 0 ? 0x7FFu : 0xFFFu;
-        c.f8 = im.mapper == 2 ? 1u : 0u;
-        c.mem = GlobalMem{im.img, ram};
+        c.set_cart(im.mapper);  // 2K, 4K or F8 (the formats the translator takes)
+        c.mem = GlobalMem{im.img, ram, nullptr};
         c.hook.frame = nullptr;
         c.hook.rend_cc = c.hook.pix_cc = 0;
         c.hook.ystart = 34;
@@ -157,7 +156,7 @@ Profile profile(const Image &im, uint64_t seed) {
         int64_t n = 0;
         uint32_t expect = 0xFFFFFFFFu;  // key of the fall-through successor of the last instruction
         for (int f = 0; f < kProfileFrames && !c.jam && n < kProfileMaxInstructions; ++f) {
-            action_ports((uint32_t)(e * 7 + f) % 18u, &c.swcha, &c.inpt4);
+            action_ports((uint32_t)(e * 7 + f) % 18u, &c.swcha, &c.inpt4, &c.swchb);
             while (!c.jam && c.cyc < kCyclesPerFrame && n < kProfileMaxInstructions) {
                 const uint32_t k = key(c.bank, c.pc);
                 if (translatable(c.pc)) {

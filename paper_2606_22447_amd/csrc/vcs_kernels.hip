@@ -35,7 +35,8 @@ __global__ __launch_bounds__(TPB) void k_step(StepParams P) {
         const int32_t blk = blockIdx.x;
         const int32_t rom_idx = P.st.main_block_rom[blk];
         const int32_t env = P.st.main_slot_env[blk * E + slot];
-        GlobalMem m{P.rom + P.st.rom_off[rom_idx], env >= 0 ? P.state[env].ram : nullptr};
+        GlobalMem m{P.rom + P.st.rom_off[rom_idx], env >= 0 ? P.state[env].ram : nullptr,
+                    (env >= 0 && P.sc_state) ? P.sc_state + (size_t)env * 128 : nullptr};
         step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, P.st.rom_mapper[rom_idx], m, kDecodeDev.e);
     } else {
         step_group<G, TPB, kSoft, InterpExec>(P, rom_lds, ram_lds, dec_lds, [](int32_t) { return InterpExec::State{}; });
@@ -287,10 +288,18 @@ __global__ __launch_bounds__(256) void k_act_grad(const float *logits, const flo
 // Reset and inspection
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_reset(StateRec *state, int32_t B, const uint8_t *mask, const uint8_t *ram0,
-                                               uint64_t seed) {
+                                               uint64_t seed, uint8_t *sc_state) {
     const int32_t env = blockIdx.x * 256 + threadIdx.x;
     if (env >= B) return;
     if (mask && !mask[env]) return;
+    if (sc_state) {  // Superchip RAM from its own SplitMix64 stream
+        uint32_t *sw = reinterpret_cast<uint32_t *>(sc_state + (size_t)env * 128);
+        for (uint32_t w = 0; w < 16; ++w) {
+            const uint64_t v = reset_ram_word(seed ^ kScSeed, (uint64_t)env, 0, w);
+            sw[2 * w] = (uint32_t)v;
+            sw[2 * w + 1] = (uint32_t)(v >> 32);
+        }
+    }
     StateRec &r = state[env];
     uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
     if (ram0) {
@@ -322,6 +331,7 @@ __global__ __launch_bounds__(256) void k_reset(StateRec *state, int32_t B, const
     r.next_ckpt = 0;
     r.pix_cc = 0;
     r.ckpt_index = 0;
+    r.slices = 4u | (5u << 4) | (6u << 8) | (7u << 12);
 }
 
 // The 16 inspection bytes of a state record (layout of vcs_read_regs).
@@ -390,8 +400,7 @@ static hipError_t launch_step_t(const StepParams &P, int32_t blocks, size_t lds,
 }
 
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
-                       int32_t max_rom_size, hipStream_t stream) {
-    const size_t lds = (size_t)max_rom_size * sizeof(uint2);
+                       size_t lds, hipStream_t stream) {
     if (plain) {
         if (soft || lanes != 1) return hipErrorInvalidValue;
         return tpb == 64 ? launch_step_t<1, 64, false, true>(P, blocks, 0, stream)
@@ -414,9 +423,8 @@ hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, int32_t max_rom_size,
+hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
                                hipStream_t stream) {
-    const size_t lds = (size_t)max_rom_size * sizeof(uint2);
 #define VCS_RELAX_CASE(Gv, Tv)                                                                          \
     if (lanes == Gv && tpb == Tv) {                                                                     \
         hipLaunchKernelGGL((k_step_relaxed<Gv, Tv>), dim3(blocks), dim3(Tv), lds, stream, P);           \
@@ -469,8 +477,9 @@ hipError_t launch_epilogue(const float *rom_logits, const float *rom_stats, cons
 }
 
 hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const uint8_t *ram0, uint64_t seed,
-                        hipStream_t stream) {
-    hipLaunchKernelGGL(k_reset, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, mask, ram0, seed);
+                        uint8_t *sc_state, hipStream_t stream) {
+    hipLaunchKernelGGL(k_reset, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, mask, ram0, seed,
+                       sc_state);
     return hipGetLastError();
 }
 

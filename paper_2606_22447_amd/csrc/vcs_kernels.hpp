@@ -5,9 +5,10 @@
 
 namespace vcs {
 
+// lds: bytes of dynamic LDS (the staged ROM image, then Superchip RAM)
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
-                       int32_t max_rom_size, hipStream_t stream);
-hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, int32_t max_rom_size,
+                       size_t lds, hipStream_t stream);
+hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
                                hipStream_t stream);
 hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream);
 hipError_t launch_decode(const float *rom_logits, int64_t rom_rows, const float *tape, int64_t tape_rows,
@@ -20,7 +21,7 @@ hipError_t launch_epilogue(const float *rom_logits, const float *rom_stats, cons
                            const float *act_logits, const float *act_stats, const float *gport, int64_t act_rows,
                            float *grad_act, hipStream_t stream);
 hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const uint8_t *ram0, uint64_t seed,
-                        hipStream_t stream);
+                        uint8_t *sc_state, hipStream_t stream);
 hipError_t launch_read_regs(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream);
 hipError_t launch_hash(const StateRec *state, int32_t B, const uint8_t *frame, int64_t frame_stride, uint64_t *out,
                        hipStream_t stream);

@@ -13,28 +13,6 @@ namespace vcs {
 // ---------------------------------------------------------------------------
 // Memory policies
 // ---------------------------------------------------------------------------
-// LDS: ROM image bytes; RAM as words [32][E] so that the 4 bytes of a word
-// belong to one env and neighbouring envs hit neighbouring banks.
-struct LdsMem {
-    static constexpr bool kRelax = false;
-    const uint8_t *rom;
-    uint8_t *ram;
-    uint32_t E, slot;
-    __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off]; }
-    __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const {
-        return ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)];
-    }
-    __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) {
-        ram[(((cell >> 2) * E + slot) << 2) | (cell & 3u)] = (uint8_t)v;
-    }
-    __host__ __device__ __forceinline__ uint32_t ram_word(uint32_t w) const {
-        return *reinterpret_cast<const uint32_t *>(ram + ((w * E + slot) << 2));
-    }
-    __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) {
-        *reinterpret_cast<uint32_t *>(ram + ((w * E + slot) << 2)) = v;
-    }
-};
-
 // LDS with a pre-decoded ROM: word[off].x = byte(off) | byte(off+1) << 8 |
 // byte(off+2) << 16 (the successors taken inside the image's 2K mirror or 4K
 // bank) and word[off].y = decode entry of byte(off), so one read yields an
@@ -46,6 +24,7 @@ struct LdsWordMem {
     const uint32_t *dec;
     uint8_t *ram;
     uint32_t E, slot;
+    uint8_t *sc = nullptr;  // Superchip RAM, in the RAM's layout (NULL: no Superchip image)
     __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off].x & 0xFFu; }
     __host__ __device__ __forceinline__ uint2 rom_word(uint32_t off) const { return rom[off]; }
     __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const {
@@ -59,6 +38,18 @@ struct LdsWordMem {
     }
     __host__ __device__ __forceinline__ void ram_word_set(uint32_t w, uint32_t v) {
         *reinterpret_cast<uint32_t *>(ram + ((w * E + slot) << 2)) = v;
+    }
+    __host__ __device__ __forceinline__ uint32_t sc_byte(uint32_t cell) const {
+        return sc[(((cell >> 2) * E + slot) << 2) | (cell & 3u)];
+    }
+    __host__ __device__ __forceinline__ void sc_set(uint32_t cell, uint32_t v) {
+        sc[(((cell >> 2) * E + slot) << 2) | (cell & 3u)] = (uint8_t)v;
+    }
+    __host__ __device__ __forceinline__ uint32_t sc_word(uint32_t w) const {
+        return *reinterpret_cast<const uint32_t *>(sc + ((w * E + slot) << 2));
+    }
+    __host__ __device__ __forceinline__ void sc_word_set(uint32_t w, uint32_t v) {
+        *reinterpret_cast<uint32_t *>(sc + ((w * E + slot) << 2)) = v;
     }
 };
 
@@ -101,7 +92,9 @@ __host__ __device__ __forceinline__ void fetch_word(C &c, uint32_t &opc, uint32_
     lo = (w.x >> 8) & 0xFFu;
     hi = w.x >> 16;
     dec = w.y;
-    const bool slow = !((pc & 0x1000u) && (pc & 0xFFFu) <= 0xFFDu);
+    // the word serves an instruction whose three bytes lie in one bank (E0: one slice)
+    // of the cartridge window, outside the Superchip RAM's page
+    const bool slow = !(pc & 0x1000u) || (pc & c.fetch_mask) > c.fetch_lim || (c.sc && (pc & 0x1F00u) == 0x1000u);
     if (W::any(slow)) {
         if (slow) {
             fetch3(c, opc, lo, hi);
@@ -115,6 +108,11 @@ struct GlobalMem {
     static constexpr bool kRelax = false;
     const uint8_t *rom;
     uint8_t *ram;
+    uint8_t *sc;  // the env's Superchip RAM (NULL: no Superchip image)
+    __host__ __device__ __forceinline__ uint32_t sc_byte(uint32_t cell) const { return sc[cell]; }
+    __host__ __device__ __forceinline__ void sc_set(uint32_t cell, uint32_t v) { sc[cell] = (uint8_t)v; }
+    __host__ __device__ __forceinline__ uint32_t sc_word(uint32_t w) const { return reinterpret_cast<const uint32_t *>(sc)[w]; }
+    __host__ __device__ __forceinline__ void sc_word_set(uint32_t w, uint32_t v) { reinterpret_cast<uint32_t *>(sc)[w] = v; }
     __host__ __device__ __forceinline__ uint32_t rom_byte(uint32_t off) const { return rom[off]; }
     __host__ __device__ __forceinline__ uint32_t ram_byte(uint32_t cell) const { return ram[cell]; }
     __host__ __device__ __forceinline__ void ram_set(uint32_t cell, uint32_t v) { ram[cell] = (uint8_t)v; }
@@ -688,8 +686,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     const int32_t S = P.steps, F = P.frame_skip;
 
     Cpu<Mem, typename X::template Hook<T, W>> c;
-    c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
-    c.f8 = mapper == 2 ? 1u : 0u;
+    c.set_cart(mapper);
     c.mem = mem;
     c.hook.frame = nullptr;
     c.hook.rend_cc = 0;
@@ -709,13 +706,16 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         } else {
             const StateRec &st = src[env];
             c.load(st);
-            c.bank &= c.f8;  // only F8 images have a second bank
             frame = st.frame;
             episode = st.episode;
             ep_step = st.ep_step;
             if constexpr (!kPlain) {
                 const uint32_t *rw = reinterpret_cast<const uint32_t *>(st.ram);
                 for (uint32_t w = sub; w < 32; w += G) c.mem.ram_word_set(w, rw[w]);
+                if (c.sc) {  // Superchip RAM, kept after the state records
+                    const uint32_t *sw = reinterpret_cast<const uint32_t *>(P.sc_state + (size_t)env * 128);
+                    for (uint32_t w = sub; w < 32; w += G) c.mem.sc_word_set(w, sw[w]);
+                }
             }
             if (st.status & 2u) {  // power-on requested by vcs_reset
                 c.power_on();
@@ -733,7 +733,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     bool active = live && S > 0;
     auto set_ports = [&]() {
         const uint32_t act = P.actions ? P.actions[(size_t)env * S + s_idx] : 0u;
-        action_ports(act, &c.swcha, &c.inpt4);
+        action_ports(act, &c.swcha, &c.inpt4, &c.swchb);
     };
     auto start_frame = [&]() {
         c.hook.rend_cc = 0;
@@ -850,6 +850,13 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     c.mem.ram_word_set(2 * w, (uint32_t)v);
                     c.mem.ram_word_set(2 * w + 1, (uint32_t)(v >> 32));
                 }
+                if (c.sc) {  // and the Superchip RAM from its own stream
+                    for (uint32_t w = sub; w < 16; w += G) {
+                        const uint64_t v = reset_ram_word(P.seed ^ kScSeed, (uint64_t)env, episode, w);
+                        c.mem.sc_word_set(2 * w, (uint32_t)v);
+                        c.mem.sc_word_set(2 * w + 1, (uint32_t)(v >> 32));
+                    }
+                }
                 c.power_on();
                 X::init(c, xs);
                 frame = 0;
@@ -878,6 +885,10 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
             if constexpr (!kPlain) {
                 uint32_t *rw = reinterpret_cast<uint32_t *>(st.ram);
                 for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
+                if (c.sc) {
+                    uint32_t *sw = reinterpret_cast<uint32_t *>(P.sc_state + (size_t)env * 128);
+                    for (uint32_t w = sub; w < 32; w += G) sw[w] = c.mem.sc_word(w);
+                }
             }
         }
         if constexpr (kSoft) {
@@ -914,8 +925,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     adj.zero();
 
     Cpu<Mem, TapeHook<W>> c;
-    c.amask = mapper == 0 ? 0x7FFu : 0xFFFu;
-    c.f8 = mapper == 2 ? 1u : 0u;
+    c.set_cart(mapper);  // (never a Superchip format: the soft path rejects them)
     c.mem = mem;
     c.hook.tape = P.tape + (size_t)gslot * (size_t)P.max_rec;  // the env's records, contiguous
     c.hook.max_rec = P.max_rec;
@@ -1042,7 +1052,6 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
         // ---- restore the segment's starting state
         const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + seg];
         c.load(r);
-        c.bank &= c.f8;
         const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
         for (uint32_t w = lane; w < 32; w += NW) c.mem.ram_word_set(w, rw[w]);
         uint32_t frame = r.frame;
@@ -1051,7 +1060,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
         int32_t s_idx = (int32_t)(frame / (uint32_t)F), fstep = (int32_t)(frame % (uint32_t)F);
         c.hook.nrec = 0;
         auto set_ports = [&]() {
-            action_ports(P.actions[(size_t)env * S + s_idx], &c.swcha, &c.inpt4);
+            action_ports(P.actions[(size_t)env * S + s_idx], &c.swcha, &c.inpt4, &c.swchb);
             c.hook.step = (uint32_t)s_idx;
             c.hook.gframe = (s_idx == S - 1 && fstep == F - 1) ? gframe_env : nullptr;
         };

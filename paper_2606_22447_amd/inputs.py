@@ -1628,3 +1628,235 @@ def config_sweep(envs_per_rom: int = 8, steps: int = 4, frame_skip: int = 2, epi
         eps = lens.astype(np.uint32)
     return Workload("sweep", roms, env_rom, initial_ram(5, b), action_stream(5, b, steps), steps=steps,
                     frame_skip=frame_skip, episode_steps=eps, seed=5)
+
+
+# --------------------------------------------------------------------------
+# Further cartridge formats: F6, F4, the Superchip variants and E0
+# --------------------------------------------------------------------------
+
+(MAPPER_F6, MAPPER_F4, MAPPER_F8SC, MAPPER_F6SC, MAPPER_F4SC, MAPPER_E0) = range(3, 9)
+MAPPER_NAMES = {MAPPER_2K: "2K", MAPPER_4K: "4K", MAPPER_F8: "F8", MAPPER_F6: "F6", MAPPER_F4: "F4",
+                MAPPER_F8SC: "F8SC", MAPPER_F6SC: "F6SC", MAPPER_F4SC: "F4SC", MAPPER_E0: "E0"}
+_BANKS = {MAPPER_F8: 2, MAPPER_F6: 4, MAPPER_F4: 8, MAPPER_F8SC: 2, MAPPER_F6SC: 4, MAPPER_F4SC: 8}
+_HOT_LO = {2: 0x1FF8, 4: 0x1FF6, 8: 0x1FF4}
+_SC = (MAPPER_F8SC, MAPPER_F6SC, MAPPER_F4SC)
+ACTION_RESET = 18
+
+
+def _band_line(b: Bank, r: Rng, var, sc: bool, table: int | None, colour_imm: list, img_base: int):
+    """One kernel line's body (<= ~40 cycles) before its STA WSYNC; the image offsets of
+    colour immediates are added to colour_imm (img_base: the bank's offset in the image)."""
+    for _ in range(r.randint(2, 4)):
+        k = r.randint(0, 6 if sc else 4)
+        if k == 0:
+            colour_imm.append(img_base + b.ins("LDA", "imm", r.randint(0, 127) * 2))
+            b.ins("STA", "zp", COLUBK)
+        elif k == 1:
+            b.ins("LDA", "zp", var())
+            b.ins("STA", "zp", COLUPF)
+        elif k == 2:
+            b.ins("INC", "zp", var())
+        elif k == 3:
+            b.ins("LDA", "zp", var())
+            b.ins("AND", "imm", 0xF0)
+            b.ins("STA", "zp", PF1 if r.random() < 0.5 else PF2)
+        elif k == 4:
+            if table is not None:
+                b.ins("LDA", "abs", table + r.randint(0, 255))
+            else:
+                b.ins("LDA", "imm", r.randint(0, 255))
+            b.ins("STA", "zp", PF0 if r.random() < 0.5 else COLUBK)
+        elif k == 5:  # Superchip RAM read port -> a colour
+            b.ins("LDA", "abs", 0x1080 + r.randint(0, 127))
+            b.ins("STA", "zp", COLUPF)
+        else:  # a RAM counter into the Superchip write port
+            b.ins("LDA", "zp", var())
+            b.ins("STA", "abs", 0x1000 + r.randint(0, 127))
+
+
+def generate_mapper_rom(seed: int, mapper: int) -> Rom:
+    """A synthetic cartridge of a bank-switched format whose frames walk all of
+    its banks (F8/F6/F4 and the Superchip variants: the kernel's bands run in
+    banks 0..N-2, each hopping to the next through its hotspot; VSYNC, VBLANK and
+    overscan in bank N-1) or slices (E0: the fixed last quarter maps each band's
+    slice into a quarter of the window and calls it).  Superchip images move RAM
+    counters through their 128-byte RAM into colours.  262 lines per frame."""
+    r = Rng(stream_key(seed, 0x4D4150, mapper))
+    sc = mapper in _SC
+    nvar = [0]
+    colour_imm: list[int] = []
+
+    def var():  # RAM counters $80..$9F
+        nvar[0] = (nvar[0] + 1) % 32
+        return 0x80 + r.randint(0, 31)
+
+    def vsync_vblank(b: Bank):
+        b.ins("LDA", "imm", 0x02)
+        b.ins("STA", "zp", VBLANK)
+        b.ins("STA", "zp", VSYNC)
+        for _ in range(3):
+            b.ins("STA", "zp", WSYNC)
+        b.ins("LDA", "imm", 0x00)
+        b.ins("STA", "zp", VSYNC)
+        b.ins("LDA", "imm", 44)            # ~37 lines of VBLANK on the timer
+        b.ins("STA", "abs", TIM64T)
+        for _ in range(r.randint(2, 5)):
+            b.ins("INC", "zp", var())
+        w = f"w{b.pos}"
+        b.label(w)
+        b.ins("LDA", "abs", INTIM)
+        b.ins("BNE", "rel", w)
+        b.ins("STA", "zp", WSYNC)
+        b.ins("LDA", "imm", 0x00)
+        b.ins("STA", "zp", VBLANK)
+
+    def overscan(b: Bank):
+        b.ins("LDA", "imm", 0x02)
+        b.ins("STA", "zp", VBLANK)
+        b.ins("LDX", "imm", 30)
+        lp = f"os{b.pos}"
+        b.label(lp)
+        b.ins("STA", "zp", WSYNC)
+        b.ins("DEX")
+        b.ins("BNE", "rel", lp)
+
+    def band(b: Bank, lines: int, table, img_base: int):
+        b.ins("LDY", "imm", lines)
+        lp = f"band{b.pos}"
+        b.label(lp)
+        _band_line(b, r, var, sc, table, colour_imm, img_base)
+        b.ins("STA", "zp", WSYNC)
+        b.ins("DEY")
+        b.ins("BNE", "rel", lp)
+
+    if mapper == MAPPER_E0:
+        # slices 0..6 hold band subroutines assembled for the quarter they are mapped to;
+        # slice 7 (the fixed last quarter, $1C00-$1FFF seen at $FC00) holds the frame
+        nb = 7
+        cuts = sorted(r.randint(8, 184) for _ in range(nb - 1))
+        lines = [e1 - e0 for e0, e1 in zip([0] + cuts, cuts + [192])]
+        slices = []
+        order = list(range(nb))
+        for i in range(nb - 1, 0, -1):
+            j = r.randint(0, i)
+            order[i], order[j] = order[j], order[i]
+        plan = []  # (slice, quarter, lines)
+        for i, s in enumerate(order):
+            plan.append((s, i % 3, lines[i]))
+        blobs = {}
+        for s, q, n in plan:
+            b = Bank(1024, 0xF000 + 0x400 * q, bytes([0xEA]) * 1024)
+            b.at(0)
+            if n > 0:
+                band(b, n, 0xF000 + 0x400 * q + 0x300, 1024 * s)
+            b.ins("RTS")
+            b.at(0x300)
+            for i in range(256):  # a data table read by the band
+                b.byte(r.randint(0, 255))
+            b.link()
+            blobs[s] = bytes(b.img)
+        m = Bank(1024, 0xFC00, bytes([0xEA]) * 1024)
+        m.at(0x000)
+        m.label("FRAME")
+        vsync_vblank(m)
+        for s, q, n in plan:
+            m.ins("LDA", "abs", 0x1FE0 + 8 * q + s)   # quarter q <- slice s
+            m.ins("JSR", "abs", 0xF000 + 0x400 * q)
+        overscan(m)
+        m.ins("JMP", "abs", "FRAME")
+        m.at(0x3E0)
+        m.label("RESET")
+        m.ins("SEI")
+        m.ins("CLD")
+        m.ins("LDX", "imm", 0xFF)
+        m.ins("TXS")
+        m.ins("JMP", "abs", "FRAME")
+        m.at(0x3FC)
+        rs = m.labels["RESET"]
+        m.byte(rs & 0xFF, rs >> 8, rs & 0xFF, rs >> 8)
+        m.link()
+        img = b"".join(blobs.get(s, bytes([0xEA]) * 1024) for s in range(7)) + bytes(m.img)
+        return Rom(seed=seed, size=8192, mapper=mapper, image=np.frombuffer(img, np.uint8).copy(),
+                   colour_imm=colour_imm)
+
+    n = _BANKS[mapper]
+    hot = _HOT_LO[n]
+    main = n - 1
+    banks = [Bank(4096, 0xF000, bytes([0xEA]) * 4096) for _ in range(n)]
+    for i, b in enumerate(banks):
+        b.at(0)
+        for _ in range(256):  # the Superchip RAM window holds no code or data; others: a table
+            b.byte(0xFF if sc else r.randint(0, 255))
+        # identical reset stubs: any power-on bank reaches FRAME in the main bank
+        b.at(0xFE0)
+        b.ins("SEI")
+        b.ins("CLD")
+        b.ins("LDX", "imm", 0xFF)
+        b.ins("TXS")
+        b.ins("LDA", "abs", hot + main)
+        b.ins("JMP", "abs", 0xF100)
+        b.at(0xFFC)
+        b.byte(0xE0, 0xFF, 0xE0, 0xFF)
+        # the hop at $F800 selects the next bank, which continues at its own $F803:
+        # its band at $F200, or the main bank's overscan at $F300
+        b.at(0x800)
+        b.ins("LDA", "abs", hot + (i + 1) % n)
+        b.ins("JMP", "abs", 0xF200 if i != main else 0xF300)
+    nbands = n - 1
+    cuts = sorted(r.randint(8, 184) for _ in range(nbands - 1))
+    lines = [e1 - e0 for e0, e1 in zip([0] + cuts, cuts + [192])]
+    for i in range(nbands):  # band i in bank i at $F200, then the hop
+        b = banks[i]
+        b.at(0x200)
+        if lines[i] > 0:
+            band(b, lines[i], 0xFA00, 4096 * i)
+        b.ins("JMP", "abs", 0xF800)
+        b.at(0xA00)
+        for _ in range(256):
+            b.byte(r.randint(0, 255))
+    m = banks[main]
+    m.at(0x100)
+    vsync_vblank(m)
+    m.ins("JMP", "abs", 0xF800)      # -> bank 0's band
+    m.at(0x300)                      # the last band's hop lands here (bank N-1 at $F803 -> $F300)
+    overscan(m)
+    m.ins("JMP", "abs", 0xF100)
+    for b in banks:
+        b.link()
+    img = b"".join(bytes(b.img) for b in banks)
+    return Rom(seed=seed, size=4096 * n, mapper=mapper, image=np.frombuffer(img, np.uint8).copy(),
+               colour_imm=colour_imm)
+
+
+MAPPER_ROMS = ((MAPPER_F6, 1), (MAPPER_F6SC, 2), (MAPPER_F8SC, 3), (MAPPER_E0, 4), (MAPPER_F4, 5), (MAPPER_F4SC, 6))
+
+
+def config_mappers(envs_per_rom: int = 8, steps: int = 3, frame_skip: int = 2, lds_only: bool = False,
+                   episodes: bool = True) -> Workload:
+    """Parity workload over the further cartridge formats (F6, F6SC, F8SC, E0 and,
+    unless lds_only, F4 and F4SC, which only the plain kernel holds), random RAM and
+    joystick inputs, short episodes for every other env (in-run resets reseed RAM
+    and Superchip RAM)."""
+    sel = [(m, s) for m, s in MAPPER_ROMS if not (lds_only and m in (MAPPER_F4, MAPPER_F4SC))]
+    roms = [generate_mapper_rom(s, m) for m, s in sel]
+    b = len(roms) * envs_per_rom
+    env_rom = np.repeat(np.arange(len(roms), dtype=np.int32), envs_per_rom)
+    eps = None
+    if episodes:
+        lens = 1 + int_stream(stream_key(6, 0x455053), b * 8, 2).reshape(b, 8)
+        lens[::2] = 1 << 20
+        eps = lens.astype(np.uint32)
+    return Workload("mappers", roms, env_rom, initial_ram(6, b), action_stream(6, b, steps), steps=steps,
+                    frame_skip=frame_skip, episode_steps=eps, seed=6)
+
+
+def boot_actions(num_envs: int, seed: int, noops: int = 60, resets: int = 4, max_random_noops: int = 30):
+    """The boot sequence of Table s-params as per-frame actions [B][n]: `noops` NOOP
+    frames, `resets` frames with the console RESET switch held, then 0..max random
+    NOOP frames per env (Mnih-style episode-start randomisation), padded with NOOPs
+    to one length; returns (actions, the random counts)."""
+    extra = int_stream(stream_key(seed, 0x424F4F), num_envs, max_random_noops + 1)
+    n = noops + resets + max_random_noops
+    a = np.zeros((num_envs, n), np.uint8)
+    a[:, noops:noops + resets] = ACTION_RESET
+    return a, extra.astype(np.int64)

@@ -41,8 +41,16 @@ extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapp
     st.status = 2;
     st.tim_shift = 10;
     std::memcpy(st.ram, ram0, 128);
+    // Superchip RAM as vcs_reset seeds it (env 0)
+    uint8_t sc_state[128];
+    for (uint32_t w = 0; w < 16; ++w) {
+        const uint64_t v = reset_ram_word(seed ^ kScSeed, 0, 0, w);
+        for (int k = 0; k < 8; ++k) sc_state[8 * w + k] = (uint8_t)(v >> (8 * k));
+    }
+    std::vector<uint32_t> sc_lds(32, 0);
     StepParams P{};
     P.state = &st;
+    P.sc_state = mapper_sc(mapper) ? sc_state : nullptr;
     P.actions = actions;
     P.steps = S;
     P.frame_skip = F;
@@ -55,13 +63,14 @@ extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapp
     P.num_episodes = num_eps;
     P.seed = seed;
     if (plain) {
-        GlobalMem m{rom, st.ram};
+        GlobalMem m{rom, st.ram, P.sc_state};
         step_env<OneLane, 1, false, true>(P, 0, 0, mapper, m, kHostDecode.e);
     } else {
-        std::vector<uint2> words(8192);
+        std::vector<uint2> words(32768);
         for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
         std::vector<uint32_t> ram_lds(32, 0);
         LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+        if (mapper_sc(mapper)) m.sc = reinterpret_cast<uint8_t *>(sc_lds.data());
         step_env<OneLane, 1, false, false>(P, 0, 0, mapper, m, kHostDecode.e);
     }
     // inspection bytes, as vcs_read_regs forms them
@@ -90,7 +99,7 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
                          const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
                          const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
                          float *g_rom, float *g_ram0, float *g_port) {
-    std::vector<uint2> words(8192);
+    std::vector<uint2> words(32768);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 3);
     std::vector<StateRec> ckpt((size_t)max_ckpt);
@@ -181,7 +190,7 @@ extern "C" int host_relaxed(const uint8_t *rom, int rom_size, int mapper, const 
     P.ram_out = ram_out;
     P.frame_out = frame_out;
     P.relax_out = out;
-    std::vector<uint2> words(8192);
+    std::vector<uint2> words(32768);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     std::vector<uint32_t> ram_lds(32, 0);
     RelaxMem<LdsWordMem> m;

@@ -1,0 +1,67 @@
+"""Further cartridge formats on the CPU: the library's machine core built for
+the host (GROUPED interpreter body and PLAIN body) against the oracle on the
+bank-walking F6/F4/Superchip/E0 workload, with in-run resets reseeding RAM and
+Superchip RAM; and the library's content-based format detection."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_22447_amd import binding as Bd
+from paper_2606_22447_amd import inputs as I
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_2606_22447_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
+    so = tmp_path_factory.mktemp("host") / "libhost_machine.so"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC", "-shared",
+                           "-w", "-I", CSRC, os.path.join(HERE, "host_machine.hip"), "-o", str(so)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return C.CDLL(str(so))
+
+
+@pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
+def test_host_core_matches_oracle_on_the_mapper_workload(host_lib, plain):
+    w = I.config_mappers(envs_per_rom=2, steps=4, frame_skip=2)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        ep = np.ascontiguousarray(w.episode_steps[b])
+        # the host harness runs env 0: its reset RAM and Superchip RAM streams are env 0's
+        ref = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, ep_steps=ep,
+                        seed=w.seed, env_index=0)
+        ram = np.zeros((w.steps, 128), np.uint8)
+        fr = np.zeros((w.steps, 210, 160), np.uint8)
+        dn = np.zeros(w.steps, np.uint8)
+        regs = np.zeros(16, np.uint8)
+        host_lib.host_interp(plain, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                             ptr(np.ascontiguousarray(w.ram0[b])), ptr(np.ascontiguousarray(w.actions[b])), w.steps,
+                             w.frame_skip, ptr(ep), ep.size, C.c_ulonglong(w.seed), ptr(ram), ptr(fr), ptr(dn),
+                             ptr(regs))
+        name = I.MAPPER_NAMES[rom.mapper]
+        assert (ram == ref["ram"]).all(), (b, name, plain)
+        assert (fr == ref["frames"]).all(), (b, name, plain)
+        assert (dn == ref["done"]).all(), (b, name, plain)
+        rr = ref["regs"]
+        assert regs.tolist() == [rr[k] for k in O.REG_NAMES[:16]], (b, name, plain)
+
+
+def test_detection_finds_every_generated_format():
+    for mapper, seed in I.MAPPER_ROMS:
+        assert Bd.detect_mapper(I.generate_mapper_rom(seed, mapper).image) == mapper, I.MAPPER_NAMES[mapper]
+    for size, mapper in ((2048, I.MAPPER_2K), (4096, I.MAPPER_4K), (8192, I.MAPPER_F8)):
+        assert Bd.detect_mapper(I.generate_rom(9, size).image) == mapper
+    with pytest.raises(Bd.VcsError):
+        Bd.detect_mapper(np.zeros(1000, np.uint8))
+
+
+def test_boot_sequence_actions():
+    a, extra = I.boot_actions(5, seed=3)
+    assert a.shape == (5, 94) and (a[:, :60] == 0).all() and (a[:, 60:64] == I.ACTION_RESET).all()
+    assert (a[:, 64:] == 0).all() and ((0 <= extra) & (extra <= 30)).all()
