@@ -24,6 +24,11 @@ ACTION_RESET = 18  # the console RESET switch held, joystick idle
 REG_NAMES = ["A", "X", "Y", "S", "P", "PCL", "PCH", "bank", "jammed", "INTIM", "TIMINT", "VBLANK",
              "COLUP0", "COLUP1", "COLUPF", "COLUBK", "CTRLPF", "PF0", "PF1", "PF2", "VSYNC", "cycle",
              "instructions", "episode", "ep_step"]
+# vcs_read_objects layout (32 values): object columns, graphics, enables, shape and
+# delay registers, motion registers, collision latches
+OBJECT_NAMES = ["posP0", "posP1", "posM0", "posM1", "posBL", "GRP0", "GRP1", "GRP0old", "GRP1old", "ENAM0",
+                "ENAM1", "ENABL", "ENABLold", "NUSIZ0", "NUSIZ1", "REFP0", "REFP1", "VDELP0", "VDELP1", "VDELBL",
+                "RESMP0", "RESMP1", "HMP0", "HMP1", "HMM0", "HMM1", "HMBL", "CXlo", "CXhi", "pad0", "pad1", "pad2"]
 
 u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
 f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
@@ -95,7 +100,8 @@ def lib():
         L.orc_soft_env.restype = C.c_int
         L.orc_soft_env_from.argtypes = [u8p, f64p, C.c_int, C.c_int, u8p, f64p, C.c_int, vp, u8p, f64p, f64p,
                                         C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, f64p, f64p,
-                                        f64p, f64p, vp]
+                                        f64p, f64p, f64p, vp]
+        L.orc_get_objects.argtypes = [vp, i64p]
         L.orc_soft_env_from.restype = C.c_int
         _lib = L
     return _lib
@@ -152,6 +158,12 @@ class Machine:
 
     def ram(self) -> np.ndarray:
         return np.ctypeslib.as_array(self.L.orc_ram(self.h), shape=(128,)).copy()
+
+    def objects(self) -> dict:
+        """Object registers now (collisions latched up to the current cycle)."""
+        out = np.zeros(32, np.int64)
+        self.L.orc_get_objects(self.h, out)
+        return dict(zip(OBJECT_NAMES, out.tolist()))
 
     def frame(self) -> np.ndarray:
         return np.ctypeslib.as_array(self.L.orc_frame(self.h), shape=(210 * 160,)).copy().reshape(SCREEN)
@@ -363,8 +375,9 @@ def soft_env(rom_hard, rom_ev, mapper, ram0_hard, ram0_ev, act_hard, swcha_ev, i
     power-on, whose state the soft steps continue (its RAM is then a constant:
     g_ram0 = 0).
 
-    Returns hard outputs, smooth outputs and the leaf gradients g_rom (per ROM
-    byte), g_ram0, g_swcha, g_inpt4 (all float64)."""
+    Returns hard outputs, smooth outputs, the leaf gradients g_rom (per ROM
+    byte), g_ram0, g_swcha, g_inpt4, and g_pos, the position sampler's
+    derivative for the columns of P0, P1, M0, M1, BL (all float64)."""
     L = lib()
     rom_hard = np.ascontiguousarray(rom_hard, np.uint8)
     rom_ev = np.ascontiguousarray(rom_ev, np.float64)
@@ -378,6 +391,7 @@ def soft_env(rom_hard, rom_ev, mapper, ram0_hard, ram0_ev, act_hard, swcha_ev, i
     g_ram0 = np.zeros(128)
     g_sw = np.zeros(steps)
     g_in = np.zeros(steps)
+    g_pos = np.zeros(5)
     nn = np.zeros(1, np.int64)
     pre = None if pre_actions is None else np.ascontiguousarray(pre_actions, np.uint8)
     rc = L.orc_soft_env_from(rom_hard, rom_ev, rom_hard.size, mapper, np.ascontiguousarray(ram0_hard, np.uint8),
@@ -386,8 +400,8 @@ def soft_env(rom_hard, rom_ev, mapper, ram0_hard, ram0_ev, act_hard, swcha_ev, i
                              np.ascontiguousarray(swcha_ev, np.float64), np.ascontiguousarray(inpt4_ev, np.float64),
                              steps, frame_skip, ystart, 1 if mode == "smooth" else 0, _ptr(gf), _ptr(gr),
                              _ptr(ram_out), _ptr(frame_out), _ptr(ram_sm), _ptr(frame_sm), g_rom, g_ram0, g_sw, g_in,
-                             _ptr(nn))
+                             g_pos, _ptr(nn))
     if rc:
         raise ValueError("oracle rejected the configuration")
     return {"ram": ram_out, "frame": frame_out, "ram_smooth": ram_sm, "frame_smooth": frame_sm,
-            "g_rom": g_rom, "g_ram0": g_ram0, "g_swcha": g_sw, "g_inpt4": g_in, "nodes": int(nn[0])}
+            "g_rom": g_rom, "g_ram0": g_ram0, "g_swcha": g_sw, "g_inpt4": g_in, "g_pos": g_pos, "nodes": int(nn[0])}

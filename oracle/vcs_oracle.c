@@ -56,6 +56,46 @@
  *  R12 JMP ($xxFF) wraps within the page; zero-page indexing wraps; BRK pushes
  *     PC+2 and P|0x30; the stack page maps through the 13-bit decode.
  *
+ * The TIA's movable objects (Sec. "Hard and Soft Execution": object priority,
+ * sprite bits and the strobe-timed sprite column; Sec. "Discussion": sub-cycle
+ * object rendering), read from the documented TIA as follows:
+ *  R15 objects P0, P1, M0, M1, BL each have a column pos in [0, 160), the
+ *      visible column of its first pixel, 0 at power-on.  A strobe (RESP0/1,
+ *      RESM0/1, RESBL) whose effect clock (R4) lies at clock h of its line sets
+ *      pos = (h - 68 + 5) mod 160 for a player and (h - 68 + 4) mod 160 for a
+ *      missile or the ball, or 3 / 2 when h < 68 (horizontal blank).
+ *  R16 shapes: NUSIZ bits 0-2 give a player's copies at column offsets
+ *      {0} {0,16} {0,32} {0,16,32} {0,64} {0} {0,32,64} {0} and its pixel width
+ *      1, except 2 (mode 5) and 4 (mode 7); the graphics byte shows bit 7 first,
+ *      bit 0 first when REFP bit 3 is set.  A missile has its player's copies,
+ *      width 2^(NUSIZ bits 4-5), and shows while ENAM bit 1 is set and RESMP bit
+ *      1 is clear; clearing RESMP moves it to its player's column + 4 * width.
+ *      The ball is one copy of width 2^(CTRLPF bits 4-5), shown while ENABL bit
+ *      1 is set.  Vertical delay: a GRP0 write copies GRP1 into GRP1's old
+ *      register; a GRP1 write copies GRP0 and ENABL into their old registers;
+ *      VDELP0/1 and VDELBL bit 0 select the old register for display.
+ *  R17 HMOVE moves every object left by its motion register's signed high
+ *      nibble (pos - m mod 160); HMCLR zeroes the five motion registers.  An
+ *      HMOVE whose effect clock lies in horizontal blank blanks columns 0..7 of
+ *      its line: black, and no collisions there.
+ *  R18 priority: with CTRLPF bit 2 clear, P0/M0 (COLUP0) over P1/M1 (COLUP1)
+ *      over the playfield and ball over the background; with it set, the
+ *      playfield and ball come first.  Score mode colours the playfield's left
+ *      half COLUP0 and right half COLUP1; the ball is always COLUPF.
+ *  R19 collisions latch wherever two objects, or an object and the
+ *      playfield, show at one visible column of any line (VBLANK does not mask
+ *      them); CXCLR clears them; a read in cycle t sees the clocks before
+ *      3t + 3.  Register r = 0..7 (CXM0P, CXM1P, CXP0FB, CXP1FB, CXM0FB, CXM1FB,
+ *      CXBLPF, CXPPMM) reads pair 2r in bit 7 and pair 2r+1 in bit 6, pairs
+ *      M0-P1, M0-P0, M1-P0, M1-P1, P0-PF, P0-BL, P1-PF, P1-BL, M0-PF, M0-BL,
+ *      M1-PF, M1-BL, BL-PF, (none), P0-P1, M0-M1.
+ *  R20 position sampler (soft): the derivative of the returned frame with
+ *      respect to an object's column is that of a triangular (bilinear)
+ *      sampler at zero sub-pixel offset taken from the right: at every visible
+ *      pixel, the colour with the object drawn one column further right minus
+ *      the colour drawn; blanked pixels contribute nothing.  A shift moves the
+ *      object in every span of the frame.
+ *
  * Soft surrogate (reverse sweep) rules, in the paper's "stored switch" reading:
  *  leaves: ROM byte = STE(sum_k k softmax(L_a/tau)_k, argmax_k L_a); RAM0 cell =
  *  STE(sum_k k P0[c,k], argmax_k P0[c,k]); a port read during step s =
@@ -279,6 +319,7 @@ typedef struct Graph {
     const uint8_t *act_hard;
     int32_t *pixel_node;    /* [210*160] */
     int32_t *ramout_node;   /* [steps*128] */
+    int32_t *pos_delta;     /* [5][210*160]: colour with the object one column right minus the colour (R20) */
 } Graph;
 
 static int32_t g_new(Graph *g, int32_t p0, double s0, double m0, int32_t p1, double s1, double m1,
@@ -367,6 +408,7 @@ typedef struct {
 /* ------------------------------------------------------------------------ */
 /* Machine                                                                  */
 /* ------------------------------------------------------------------------ */
+enum { OBJ_P0, OBJ_P1, OBJ_M0, OBJ_M1, OBJ_BL, NOBJ };
 struct Orc {
     /* cartridge */
     uint8_t rom[32768];
@@ -387,6 +429,13 @@ struct Orc {
     /* TIA */
     uint8_t vsync, vblank, colup0, colup1, colupf, colubk, ctrlpf, pf0, pf1, pf2;
     int wsync;
+    /* TIA objects (R15-R19), indexed P0, P1, M0, M1, BL */
+    int pos[NOBJ];
+    uint8_t grp_new[2], grp_old[2], enabl_new, enabl_old, enam[2], nusiz[2], refp[2], vdelp[2], vdelbl, resmp[2];
+    uint8_t hm[NOBJ];
+    uint16_t cx;          /* collision latches, bit k = pair k of R19 */
+    int64_t cx_done;      /* colour clocks since power-on whose collisions are latched */
+    int64_t hmove_line;   /* line since power-on whose columns 0..7 an HMOVE blanked (-1: none) */
     /* time */
     int64_t cycle;      /* CPU cycles since power-on */
     int64_t drawn;      /* colour clocks since power-on already rendered */
@@ -459,13 +508,96 @@ static int playfield_bit(const Orc *m, int x) {
     return (m->pf2 >> (i - 12)) & 1;
 }
 
-/* which colour register owns pixel x: 0 COLUP0, 1 COLUP1, 2 COLUPF, 3 COLUBK */
-static int pixel_owner(const Orc *m, int x) {
-    if (playfield_bit(m, x)) {
-        if (m->ctrlpf & 0x02) return x < 80 ? 0 : 1; /* score mode */
-        return 2;
+/* ---- objects (R15-R19) ---- */
+enum { OCC_P0 = 1, OCC_P1 = 2, OCC_M0 = 4, OCC_M1 = 8, OCC_BL = 16, OCC_PF = 32 };
+
+/* column offsets of the copies of NUSIZ modes 0..7 (-1: no further copy) */
+static const int COPIES[8][3] = {{0, -1, -1}, {0, 16, -1}, {0, 32, -1}, {0, 16, 32},
+                                 {0, 64, -1}, {0, -1, -1}, {0, 32, 64}, {0, -1, -1}};
+
+/* columns from an object's first pixel to column x, going right with wrap-around */
+static int columns_from(int pos, int x) { return ((x - pos) % SCREEN_W + SCREEN_W) % SCREEN_W; }
+
+static int player_pixel(const Orc *m, int i, int x) {
+    const int mode = m->nusiz[i] & 7, scale = mode == 5 ? 2 : mode == 7 ? 4 : 1;
+    const int gfx = (m->vdelp[i] & 1) ? m->grp_old[i] : m->grp_new[i];
+    const int d = columns_from(m->pos[OBJ_P0 + i], x);
+    for (int k = 0; k < 3 && COPIES[mode][k] >= 0; k++) {
+        const int e = d - COPIES[mode][k];
+        if (e >= 0 && e < 8 * scale) {
+            const int b = e / scale; /* graphics bit, counted from the first pixel */
+            return (m->refp[i] & 0x08) ? (gfx >> b) & 1 : (gfx >> (7 - b)) & 1;
+        }
     }
+    return 0;
+}
+
+static int missile_shown(const Orc *m, int i) { return (m->enam[i] & 2) && !(m->resmp[i] & 2); }
+
+static int missile_pixel(const Orc *m, int i, int x) {
+    if (!missile_shown(m, i)) return 0;
+    const int mode = m->nusiz[i] & 7, width = 1 << ((m->nusiz[i] >> 4) & 3);
+    const int d = columns_from(m->pos[OBJ_M0 + i], x);
+    for (int k = 0; k < 3 && COPIES[mode][k] >= 0; k++) {
+        const int e = d - COPIES[mode][k];
+        if (e >= 0 && e < width) return 1;
+    }
+    return 0;
+}
+
+static int ball_shown(const Orc *m) { return (((m->vdelbl & 1) ? m->enabl_old : m->enabl_new) & 2) != 0; }
+
+static int ball_pixel(const Orc *m, int x) {
+    return ball_shown(m) && columns_from(m->pos[OBJ_BL], x) < (1 << ((m->ctrlpf >> 4) & 3));
+}
+
+/* does any object show a pixel anywhere on the line (else nothing can collide) */
+static int objects_shown(const Orc *m) {
+    for (int i = 0; i < 2; i++)
+        if (((m->vdelp[i] & 1) ? m->grp_old[i] : m->grp_new[i]) || missile_shown(m, i)) return 1;
+    return ball_shown(m);
+}
+
+/* which objects and the playfield show at column x (OCC_* bits) */
+static int occupancy(const Orc *m, int x) {
+    return player_pixel(m, 0, x) * OCC_P0 | player_pixel(m, 1, x) * OCC_P1 | missile_pixel(m, 0, x) * OCC_M0 |
+           missile_pixel(m, 1, x) * OCC_M1 | ball_pixel(m, x) * OCC_BL | playfield_bit(m, x) * OCC_PF;
+}
+
+/* which colour register owns pixel x given its occupancy (R18): 0 COLUP0,
+ * 1 COLUP1, 2 COLUPF, 3 COLUBK */
+static int pixel_owner(const Orc *m, int x, int occ) {
+    const int field = (occ & OCC_PF) ? ((m->ctrlpf & 0x02) ? (x < 80 ? 0 : 1) : 2) : (occ & OCC_BL) ? 2 : -1;
+    const int p0 = (occ & (OCC_P0 | OCC_M0)) != 0, p1 = (occ & (OCC_P1 | OCC_M1)) != 0;
+    if ((m->ctrlpf & 0x04) && field >= 0) return field;
+    if (p0) return 0;
+    if (p1) return 1;
+    if (field >= 0) return field;
     return 3;
+}
+
+/* the two occupancy bits of collision latch k (R19); pair 13 is unused */
+static const int CX_PAIRS[16][2] = {
+    {OCC_M0, OCC_P1}, {OCC_M0, OCC_P0}, {OCC_M1, OCC_P0}, {OCC_M1, OCC_P1}, {OCC_P0, OCC_PF}, {OCC_P0, OCC_BL},
+    {OCC_P1, OCC_PF}, {OCC_P1, OCC_BL}, {OCC_M0, OCC_PF}, {OCC_M0, OCC_BL}, {OCC_M1, OCC_PF}, {OCC_M1, OCC_BL},
+    {OCC_BL, OCC_PF}, {0, 0},           {OCC_P0, OCC_P1}, {OCC_M0, OCC_M1}};
+
+/* Latch the collisions of colour clocks [cx_done, until) with the current state. */
+static void tia_collide_until(Orc *m, int64_t until) {
+    if (until <= m->cx_done) return;
+    if (objects_shown(m)) {
+        int occ[SCREEN_W];
+        for (int x = 0; x < SCREEN_W; x++) occ[x] = occupancy(m, x);
+        for (int64_t cc = m->cx_done; cc < until; cc++) {
+            const int h = (int)(cc % CLOCKS_PER_LINE);
+            if (h < HBLANK_CLOCKS) continue;
+            const int x = h - HBLANK_CLOCKS;
+            if (x < 8 && cc / CLOCKS_PER_LINE == m->hmove_line) continue; /* HMOVE blank */
+            for (int k = 0; k < 16; k++)
+                if (CX_PAIRS[k][0] && (occ[x] & CX_PAIRS[k][0]) && (occ[x] & CX_PAIRS[k][1])) m->cx |= 1u << k;
+        }
+    }
+    m->cx_done = until;
 }
 
 static uint8_t colour_reg(const Orc *m, int owner) {
@@ -493,22 +625,85 @@ static void tia_draw_until(Orc *m, int64_t until) {
             if (h < HBLANK_CLOCKS) continue;
             int x = h - HBLANK_CLOCKS;
             int idx = y * SCREEN_W + x;
-            if (m->vblank & 0x02) {
+            if ((m->vblank & 0x02) || (x < 8 && cc / CLOCKS_PER_LINE == m->hmove_line)) {
                 m->frame[idx] = 0;
-                if (m->g) m->g->pixel_node[idx] = -1;
+                if (m->g) {
+                    m->g->pixel_node[idx] = -1;
+                    for (int o = 0; o < NOBJ; o++) m->g->pos_delta[o * SCREEN_H * SCREEN_W + idx] = 0;
+                }
             } else {
-                int owner = pixel_owner(m, x);
-                m->frame[idx] = colour_reg(m, owner) & 0xFE;
-                if (m->g) m->g->pixel_node[idx] = m->g->slot_col[owner];
+                const int owner = pixel_owner(m, x, occupancy(m, x));
+                const int c = colour_reg(m, owner) & 0xFE;
+                m->frame[idx] = (uint8_t)c;
+                if (m->g) {
+                    m->g->pixel_node[idx] = m->g->slot_col[owner];
+                    for (int o = 0; o < NOBJ; o++) { /* R20: the object one column further right */
+                        const int saved = m->pos[o];
+                        m->pos[o] = (saved + 1) % SCREEN_W;
+                        const int c1 = colour_reg(m, pixel_owner(m, x, occupancy(m, x))) & 0xFE;
+                        m->pos[o] = saved;
+                        m->g->pos_delta[o * SCREEN_H * SCREEN_W + idx] = c1 - c;
+                    }
+                }
             }
         }
     }
     if (until > m->drawn) m->drawn = until;
 }
 
+/* Column of an object strobed at colour clock cc (R15): players start 5
+ * columns after the strobe, missiles and the ball 4. */
+static int strobe_column(int64_t cc, int lag) {
+    const int h = (int)(cc % CLOCKS_PER_LINE);
+    return h < HBLANK_CLOCKS ? lag - 2 : (h - HBLANK_CLOCKS + lag) % SCREEN_W;
+}
+
 static void tia_write(Orc *m, int reg, uint8_t v, int64_t w) {
-    tia_draw_until(m, 3 * (w + 1)); /* R4 */
+    const int64_t cc = 3 * (w + 1); /* R4 */
+    tia_draw_until(m, cc);
+    tia_collide_until(m, cc);
     switch (reg & 0x3F) {
+        case 0x04: m->nusiz[0] = v; break;
+        case 0x05: m->nusiz[1] = v; break;
+        case 0x0B: m->refp[0] = v; break;
+        case 0x0C: m->refp[1] = v; break;
+        case 0x10: m->pos[OBJ_P0] = strobe_column(cc, 5); break;
+        case 0x11: m->pos[OBJ_P1] = strobe_column(cc, 5); break;
+        case 0x12: m->pos[OBJ_M0] = strobe_column(cc, 4); break;
+        case 0x13: m->pos[OBJ_M1] = strobe_column(cc, 4); break;
+        case 0x14: m->pos[OBJ_BL] = strobe_column(cc, 4); break;
+        case 0x1B: /* GRP0; GRP1's old register takes GRP1 */
+            m->grp_new[0] = v;
+            m->grp_old[1] = m->grp_new[1];
+            break;
+        case 0x1C: /* GRP1; GRP0's and ENABL's old registers take theirs */
+            m->grp_new[1] = v;
+            m->grp_old[0] = m->grp_new[0];
+            m->enabl_old = m->enabl_new;
+            break;
+        case 0x1D: m->enam[0] = v; break;
+        case 0x1E: m->enam[1] = v; break;
+        case 0x1F: m->enabl_new = v; break;
+        case 0x20: case 0x21: case 0x22: case 0x23: case 0x24: m->hm[(reg & 0x3F) - 0x20] = v; break;
+        case 0x25: m->vdelp[0] = v; break;
+        case 0x26: m->vdelp[1] = v; break;
+        case 0x27: m->vdelbl = v; break;
+        case 0x28: case 0x29: { /* RESMP: released, the missile moves to its player's centre */
+            const int i = (reg & 0x3F) - 0x28, mode = m->nusiz[i] & 7;
+            const int half = 4 * (mode == 5 ? 2 : mode == 7 ? 4 : 1);
+            if ((m->resmp[i] & 2) && !(v & 2)) m->pos[OBJ_M0 + i] = (m->pos[OBJ_P0 + i] + half) % SCREEN_W;
+            m->resmp[i] = v;
+            break;
+        }
+        case 0x2A: /* HMOVE (R17) */
+            for (int o = 0; o < NOBJ; o++) {
+                const int mv = (int8_t)m->hm[o] >> 4;
+                m->pos[o] = ((m->pos[o] - mv) % SCREEN_W + SCREEN_W) % SCREEN_W;
+            }
+            if (cc % CLOCKS_PER_LINE < HBLANK_CLOCKS) m->hmove_line = cc / CLOCKS_PER_LINE;
+            break;
+        case 0x2B: memset(m->hm, 0, sizeof m->hm); break;
+        case 0x2C: m->cx = 0; break;
         case 0x00: m->vsync = v; break;
         case 0x01: m->vblank = v; break;
         case 0x02: m->wsync = 1; break;
@@ -520,15 +715,21 @@ static void tia_write(Orc *m, int reg, uint8_t v, int64_t w) {
         case 0x0D: m->pf0 = v; break;
         case 0x0E: m->pf1 = v; break;
         case 0x0F: m->pf2 = v; break;
-        default: break; /* sprites, audio, HMOVE: outside this subset */
+        default: break; /* audio, RSYNC and the unused addresses */
     }
 }
 
-static uint8_t tia_read(const Orc *m, int reg) {
-    switch (reg & 0x0F) {
+/* TIA read in cycle t (R7, R19) */
+static uint8_t tia_read(Orc *m, int reg, int64_t t) {
+    const int r = reg & 0x0F;
+    if (r < 8) {
+        tia_collide_until(m, 3 * t + 3);
+        return (uint8_t)((((m->cx >> (2 * r)) & 1) << 7) | (((m->cx >> (2 * r + 1)) & 1) << 6));
+    }
+    switch (r) {
         case 0x0C: return m->inpt4;
         case 0x0D: return 0x80;
-        default: return 0x00; /* collisions (no objects), paddles, undriven bits */
+        default: return 0x00; /* paddles and undriven bits */
     }
 }
 
@@ -622,7 +823,7 @@ static uint8_t bus_peek(Orc *m, uint16_t addr, int64_t t) {
     addr &= 0x1FFF;
     if (mapper_sc(m->mapper) && (addr & 0x1F80) == 0x1080) return m->sc_ram[addr & 0x7F];
     if (addr & 0x1000) return rom_value(m, cart_offset(m, addr));
-    if (!(addr & 0x80)) return tia_read(m, addr);
+    if (!(addr & 0x80)) return tia_read(m, addr, t);
     if (!(addr & 0x200)) return ram_value(m, addr & 0x7F);
     return riot_read(m, addr, t, 0);
 }
@@ -647,7 +848,7 @@ static uint8_t bus_read(Orc *m, uint16_t addr, int64_t t) {
         hotspot(m, addr);
         return rom_value(m, cart_offset(m, addr));
     }
-    if (!(addr & 0x80)) return tia_read(m, addr);
+    if (!(addr & 0x80)) return tia_read(m, addr, t);
     if (!(addr & 0x200)) return ram_value(m, addr & 0x7F);
     return riot_read(m, addr, t, 1);
 }
@@ -833,6 +1034,7 @@ int orc_power_on(Orc *m, const uint8_t *rom, int rom_size, int mapper, const uin
     m->swchb = 0x0B;
     m->ystart = ystart;
     m->draw_frame = -1;
+    m->hmove_line = -1;
     uint16_t lo = bus_peek(m, 0x1FFC, 0), hi = bus_peek(m, 0x1FFD, 0);
     m->pc = (uint16_t)(lo | (hi << 8));
     return 0;
@@ -1217,6 +1419,7 @@ static void run_until(Orc *m, int64_t budget) {
         }
     }
     tia_draw_until(m, 3 * m->cycle);
+    tia_collide_until(m, 3 * m->cycle);
 }
 
 /* Actions 0..17: the joystick; ORC_ACTION_RESET: the console's RESET switch held
@@ -1278,6 +1481,37 @@ void orc_get_regs(const Orc *m, int64_t *out) {
     out[20] = m->vsync;
     out[21] = m->cycle;
     out[22] = (int64_t)m->instructions;
+}
+
+/* Object registers (R15-R19) now: columns of P0, P1, M0, M1, BL; GRP0, GRP1;
+ * their old registers; ENAM0, ENAM1, ENABL, its old register; NUSIZ0, NUSIZ1,
+ * REFP0, REFP1, VDELP0, VDELP1, VDELBL, RESMP0, RESMP1; HMP0, HMP1, HMM0,
+ * HMM1, HMBL; the collision latches (low byte, high byte); 0, 0, 0. */
+void orc_get_objects(Orc *m, int64_t *out) {
+    tia_collide_until(m, 3 * m->cycle);
+    int n = 0;
+    for (int o = 0; o < NOBJ; o++) out[n++] = m->pos[o];
+    out[n++] = m->grp_new[0];
+    out[n++] = m->grp_new[1];
+    out[n++] = m->grp_old[0];
+    out[n++] = m->grp_old[1];
+    out[n++] = m->enam[0];
+    out[n++] = m->enam[1];
+    out[n++] = m->enabl_new;
+    out[n++] = m->enabl_old;
+    out[n++] = m->nusiz[0];
+    out[n++] = m->nusiz[1];
+    out[n++] = m->refp[0];
+    out[n++] = m->refp[1];
+    out[n++] = m->vdelp[0];
+    out[n++] = m->vdelp[1];
+    out[n++] = m->vdelbl;
+    out[n++] = m->resmp[0];
+    out[n++] = m->resmp[1];
+    for (int o = 0; o < NOBJ; o++) out[n++] = m->hm[o];
+    out[n++] = m->cx & 0xFF;
+    out[n++] = m->cx >> 8;
+    while (n < 32) out[n++] = 0;
 }
 
 /* FULL relaxed mode on (bit 0 of on; bit 1: also record the float64 pre-cast
@@ -1560,7 +1794,7 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
                       const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev, int steps,
                       int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
                       uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
-                      double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
+                      double *g_ram0, double *g_swcha, double *g_inpt4, double *g_pos, int64_t *n_nodes) {
     /* the soft value graph has no content nodes for Superchip RAM: those formats run hard only */
     if (mapper < 0 || mapper >= ORC_MAPPER_COUNT || mapper_sc(mapper)) return -1;
     Graph *g = (Graph *)calloc(1, sizeof(Graph));
@@ -1577,6 +1811,7 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
     g->act_hard = act_hard;
     g->pixel_node = (int32_t *)malloc(sizeof(int32_t) * SCREEN_H * SCREEN_W);
     for (int i = 0; i < SCREEN_H * SCREEN_W; i++) g->pixel_node[i] = -1;
+    g->pos_delta = (int32_t *)calloc((size_t)NOBJ * SCREEN_H * SCREEN_W, sizeof(int32_t));
     g->ramout_node = (int32_t *)malloc(sizeof(int32_t) * (size_t)steps * 128);
     g->slot_a = g->slot_x = g->slot_y = -1; /* power-on registers are constants */
     for (int i = 0; i < 4; i++) g->slot_col[i] = -1;
@@ -1631,6 +1866,14 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
         g_swcha[s] = adj[g->swcha_leaf[s]];
         g_inpt4[s] = adj[g->inpt4_leaf[s]];
     }
+    if (g_pos) /* R20: the sampler's derivative for each object's column */
+        for (int o = 0; o < NOBJ; o++) {
+            double acc = 0.0;
+            if (grad_frame)
+                for (int i = 0; i < SCREEN_H * SCREEN_W; i++)
+                    acc += grad_frame[i] * (double)g->pos_delta[o * SCREEN_H * SCREEN_W + i];
+            g_pos[o] = acc;
+        }
     if (n_nodes) *n_nodes = g->len;
 
     free(adj);
@@ -1640,6 +1883,7 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
     free(g->swcha_leaf);
     free(g->inpt4_leaf);
     free(g->pixel_node);
+    free(g->pos_delta);
     free(g->ramout_node);
     free(g);
     return 0;
@@ -1652,5 +1896,5 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
                  double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
     return orc_soft_env_from(rom_hard, rom_ev, rom_size, mapper, ram0_hard, ram0_ev, 0, NULL, act_hard, swcha_ev,
                              inpt4_ev, steps, frame_skip, ystart, mode, grad_frame, grad_ram, ram_out, frame_out,
-                             ram_smooth, frame_smooth, g_rom, g_ram0, g_swcha, g_inpt4, n_nodes);
+                             ram_smooth, frame_smooth, g_rom, g_ram0, g_swcha, g_inpt4, NULL, n_nodes);
 }

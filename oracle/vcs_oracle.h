@@ -27,6 +27,7 @@ void orc_set_action(Orc *m, int action);
 void orc_set_draw_frame(Orc *m, int64_t frame);
 void orc_env_step(Orc *m, int action, int frame_skip, int64_t step_index, int store_frame);
 void orc_get_regs(const Orc *m, int64_t *out);
+void orc_get_objects(Orc *m, int64_t *out);
 void orc_op_stats(const Orc *m, uint64_t *out);
 void orc_set_relax(Orc *m, int on, double alpha, double T);
 int64_t orc_relax_ndiv(const Orc *m);
@@ -75,5 +76,5 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
                       const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev, int steps,
                       int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
                       uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
-                      double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes);
+                      double *g_ram0, double *g_swcha, double *g_inpt4, double *g_pos, int64_t *n_nodes);
 #endif
