@@ -99,8 +99,8 @@ def lib():
                                    C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, f64p, f64p, f64p, f64p, vp]
         L.orc_soft_env.restype = C.c_int
         L.orc_soft_env_from.argtypes = [u8p, f64p, C.c_int, C.c_int, u8p, f64p, C.c_int, vp, u8p, f64p, f64p,
-                                        C.c_int, C.c_int, C.c_int, C.c_int, vp, vp, vp, vp, vp, vp, f64p, f64p,
-                                        f64p, f64p, f64p, vp]
+                                        C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, vp, vp,
+                                        f64p, f64p, f64p, f64p, f64p, vp, vp]
         L.orc_get_objects.argtypes = [vp, i64p]
         L.orc_soft_env_from.restype = C.c_int
         _lib = L
@@ -369,15 +369,19 @@ def epilogue_action(logits: np.ndarray, tau: float, g_swcha: np.ndarray, g_inpt4
 
 
 def soft_env(rom_hard, rom_ev, mapper, ram0_hard, ram0_ev, act_hard, swcha_ev, inpt4_ev, steps, frame_skip,
-             mode: str = "ste", grad_frame=None, grad_ram=None, ystart: int = 34, pre_actions=None):
+             mode: str = "ste", grad_frame=None, grad_ram=None, ystart: int = 34, pre_actions=None,
+             read_T: float = 0.0):
     """SOFT-STE (or SMOOTH) rollout of one env with its reverse sweep: from
     power-on, or (pre_actions given) after len(pre_actions) hard env steps from
     power-on, whose state the soft steps continue (its RAM is then a constant:
-    g_ram0 = 0).
+    g_ram0 = 0).  read_T > 0 turns on the address surrogate: indexed reads of ROM
+    or RAM bytes also pass gradient to their index register through Eq. s-read
+    at temperature read_T.
 
     Returns hard outputs, smooth outputs, the leaf gradients g_rom (per ROM
     byte), g_ram0, g_swcha, g_inpt4, and g_pos, the position sampler's
-    derivative for the columns of P0, P1, M0, M1, BL (all float64)."""
+    derivative for the columns of P0, P1, M0, M1, BL, with its per-pixel
+    tangents frame_dpos [5][210][160] (all float64)."""
     L = lib()
     rom_hard = np.ascontiguousarray(rom_hard, np.uint8)
     rom_ev = np.ascontiguousarray(rom_ev, np.float64)
@@ -392,16 +396,19 @@ def soft_env(rom_hard, rom_ev, mapper, ram0_hard, ram0_ev, act_hard, swcha_ev, i
     g_sw = np.zeros(steps)
     g_in = np.zeros(steps)
     g_pos = np.zeros(5)
+    dpos = np.zeros((5, 210, 160))
     nn = np.zeros(1, np.int64)
     pre = None if pre_actions is None else np.ascontiguousarray(pre_actions, np.uint8)
     rc = L.orc_soft_env_from(rom_hard, rom_ev, rom_hard.size, mapper, np.ascontiguousarray(ram0_hard, np.uint8),
                              np.ascontiguousarray(ram0_ev, np.float64), 0 if pre is None else pre.size, _ptr(pre),
                              np.ascontiguousarray(act_hard, np.uint8),
                              np.ascontiguousarray(swcha_ev, np.float64), np.ascontiguousarray(inpt4_ev, np.float64),
-                             steps, frame_skip, ystart, 1 if mode == "smooth" else 0, _ptr(gf), _ptr(gr),
+                             steps, frame_skip, ystart, 1 if mode == "smooth" else 0, float(read_T), _ptr(gf),
+                             _ptr(gr),
                              _ptr(ram_out), _ptr(frame_out), _ptr(ram_sm), _ptr(frame_sm), g_rom, g_ram0, g_sw, g_in,
-                             g_pos, _ptr(nn))
+                             g_pos, _ptr(dpos), _ptr(nn))
     if rc:
         raise ValueError("oracle rejected the configuration")
     return {"ram": ram_out, "frame": frame_out, "ram_smooth": ram_sm, "frame_smooth": frame_sm,
-            "g_rom": g_rom, "g_ram0": g_ram0, "g_swcha": g_sw, "g_inpt4": g_in, "g_pos": g_pos, "nodes": int(nn[0])}
+            "g_rom": g_rom, "g_ram0": g_ram0, "g_swcha": g_sw, "g_inpt4": g_in, "g_pos": g_pos, "frame_dpos": dpos,
+            "nodes": int(nn[0])}

@@ -95,6 +95,14 @@
  *      pixel, the colour with the object drawn one column further right minus
  *      the colour drawn; blanked pixels contribute nothing.  A shift moves the
  *      object in every span of the frame.
+ *  R21 address surrogate (soft, off unless a read temperature T > 0 is given):
+ *      the leaky variant's distance-softmax read (Eq. s-read) taken in the
+ *      backward, so that an indexed read of a ROM or RAM byte passes gradient to
+ *      its index register (X for zp,X and abs,X; Y for zp,Y, abs,Y and (zp),Y);
+ *      the slope is Eq. s-read's at the hard address (see address_node).  The
+ *      paper's other leaky pieces, gradients through branch gates and flags into
+ *      data, need the untaken path's outcome, which a single hard trajectory
+ *      does not have: they are not built.
  *
  * Soft surrogate (reverse sweep) rules, in the paper's "stored switch" reading:
  *  leaves: ROM byte = STE(sum_k k softmax(L_a/tau)_k, argmax_k L_a); RAM0 cell =
@@ -102,8 +110,8 @@
  *  STE(E_softmax(l_s/tau)[port(a)], port(argmax l_s)).  Moves d=1; ADC/SBC d=1
  *  and +/-1; INC/DEC d=1; ASL/ROL d=2, LSR/ROR d=1/2; AND/ORA/EOR/SAX use the
  *  bit-uniform multilinear extension (A&B ~ AB/255, A|B ~ A+B-AB/255,
- *  A^B ~ A+B-2AB/255); flags, compares, PC, S, addresses, opcodes and timer
- *  values carry no gradient; a pixel's adjoint goes to the colour register that
+ *  A^B ~ A+B-2AB/255); flags, compares, PC, S, addresses (unless R21),
+ *  opcodes and timer values carry no gradient; a pixel's adjoint goes to the colour register that
  *  owned it.  STE evaluates coefficients at hard values; SMOOTH re-runs the same
  *  trajectory with real-valued leaves and evaluates them at the smooth values.
  */
@@ -320,6 +328,7 @@ typedef struct Graph {
     int32_t *pixel_node;    /* [210*160] */
     int32_t *ramout_node;   /* [steps*128] */
     int32_t *pos_delta;     /* [5][210*160]: colour with the object one column right minus the colour (R20) */
+    double read_T;          /* R21: the read temperature of the address surrogate (0: off) */
 } Graph;
 
 static int32_t g_new(Graph *g, int32_t p0, double s0, double m0, int32_t p1, double s1, double m1,
@@ -903,6 +912,49 @@ static int32_t read_node(Orc *m, uint16_t addr) {
     return -1; /* SWCHB, direction registers, timer: constants */
 }
 
+/* R21 (the leaky address surrogate): with a read temperature T > 0, an indexed
+ * read of a ROM or RAM byte (zp,X  zp,Y  abs,X  abs,Y  (zp),Y) also depends on
+ * its index register through Eq. s-read: the value at address a is the
+ * distance-softmax blend of the array's bytes j with weights exp(-|j-a|/T)
+ * (|j - a| <= 8, inside the ROM image or the 128 RAM cells), and its slope at the
+ * hard address, taken symmetrically (the j = a term, whose kink has equal and
+ * opposite one-sided slopes, contributes nothing), with the coefficients at
+ * hard values (R[a] for the blend), is
+ *   kappa = (1/T) sum_j w_j sign(j - a) (R[j] - R[a]),  w = the normalised weights.
+ * A new node carries v + kappa (index - its hard value). */
+static double read_slope(const uint8_t *r, int n, int a, double T) {
+    double z = 0.0, acc = 0.0;
+    for (int j = a - RELAX_WINDOW; j <= a + RELAX_WINDOW; j++) {
+        if (j < 0 || j >= n) continue;
+        const double w = exp(-fabs((double)(j - a)) / T);
+        z += w;
+        acc += w * (double)((j > a) - (j < a)) * ((double)r[j] - (double)r[a]);
+    }
+    return acc / (z * T);
+}
+
+static int32_t address_node(Orc *m, int32_t node, uint16_t ea, int mode, int v) {
+    Graph *g = m->g;
+    if (!(g->read_T > 0.0)) return node;
+    int32_t idx_slot;
+    int idx_hard;
+    if (mode == ZPX || mode == ABX) {
+        idx_slot = g->slot_x;
+        idx_hard = m->x;
+    } else if (mode == ZPY || mode == ABY || mode == IZY) {
+        idx_slot = g->slot_y;
+        idx_hard = m->y;
+    } else {
+        return node;
+    }
+    const uint16_t addr = ea & 0x1FFF;
+    double kappa;
+    if (addr & 0x1000) kappa = read_slope(m->rom, m->rom_size, cart_offset(m, addr), g->read_T);
+    else if ((addr & 0x80) && !(addr & 0x200)) kappa = read_slope(m->ram, 128, addr & 0x7F, g->read_T);
+    else return node; /* TIA and RIOT registers: no array to blend over */
+    return g_affine(g, node, 1.0, v, idx_slot, kappa, idx_hard, v);
+}
+
 /* Slot overwritten by a data write at addr (NULL: a sink with no content). */
 static int32_t *write_slot(Orc *m, uint16_t addr) {
     Graph *g = m->g;
@@ -1137,7 +1189,7 @@ int orc_step_instruction(Orc *m) {
             if (g) node = read_node(m, a1);                                     \
         } else {                                                                \
             v = bus_read(m, ea, t0 + n - 1);                                    \
-            if (g) node = read_node(m, ea);                                     \
+            if (g) node = address_node(m, read_node(m, ea), ea, info.mode, v);  \
         }                                                                       \
     } while (0)
 
@@ -1792,13 +1844,15 @@ void orc_epilogue_action(const float *logits, int64_t n, double tau, const doubl
 int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_size, int mapper,
                       const uint8_t *ram0_hard, const double *ram0_ev, int pre_steps, const uint8_t *pre_actions,
                       const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev, int steps,
-                      int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
-                      uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
-                      double *g_ram0, double *g_swcha, double *g_inpt4, double *g_pos, int64_t *n_nodes) {
+                      int frame_skip, int ystart, int mode, double read_T, const double *grad_frame,
+                      const double *grad_ram, uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth,
+                      double *frame_smooth, double *g_rom, double *g_ram0, double *g_swcha, double *g_inpt4,
+                      double *g_pos, double *frame_dpos, int64_t *n_nodes) {
     /* the soft value graph has no content nodes for Superchip RAM: those formats run hard only */
     if (mapper < 0 || mapper >= ORC_MAPPER_COUNT || mapper_sc(mapper)) return -1;
     Graph *g = (Graph *)calloc(1, sizeof(Graph));
     g->rom_size = rom_size;
+    g->read_T = read_T;
     g->rom_hard = rom_hard;
     g->rom_ev = rom_ev;
     g->rom_leaf = (int32_t *)malloc(sizeof(int32_t) * (size_t)rom_size);
@@ -1866,6 +1920,8 @@ int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_siz
         g_swcha[s] = adj[g->swcha_leaf[s]];
         g_inpt4[s] = adj[g->inpt4_leaf[s]];
     }
+    if (frame_dpos) /* R20: the sampler's tangent images of the final frame */
+        for (int i = 0; i < NOBJ * SCREEN_H * SCREEN_W; i++) frame_dpos[i] = (double)g->pos_delta[i];
     if (g_pos) /* R20: the sampler's derivative for each object's column */
         for (int o = 0; o < NOBJ; o++) {
             double acc = 0.0;
@@ -1895,6 +1951,7 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
                  uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
                  double *g_ram0, double *g_swcha, double *g_inpt4, int64_t *n_nodes) {
     return orc_soft_env_from(rom_hard, rom_ev, rom_size, mapper, ram0_hard, ram0_ev, 0, NULL, act_hard, swcha_ev,
-                             inpt4_ev, steps, frame_skip, ystart, mode, grad_frame, grad_ram, ram_out, frame_out,
-                             ram_smooth, frame_smooth, g_rom, g_ram0, g_swcha, g_inpt4, NULL, n_nodes);
+                             inpt4_ev, steps, frame_skip, ystart, mode, 0.0, grad_frame, grad_ram, ram_out,
+                             frame_out, ram_smooth, frame_smooth, g_rom, g_ram0, g_swcha, g_inpt4, NULL, NULL,
+                             n_nodes);
 }

@@ -74,7 +74,8 @@ int orc_soft_env(const uint8_t *rom_hard, const double *rom_ev, int rom_size, in
 int orc_soft_env_from(const uint8_t *rom_hard, const double *rom_ev, int rom_size, int mapper,
                       const uint8_t *ram0_hard, const double *ram0_ev, int pre_steps, const uint8_t *pre_actions,
                       const uint8_t *act_hard, const double *swcha_ev, const double *inpt4_ev, int steps,
-                      int frame_skip, int ystart, int mode, const double *grad_frame, const double *grad_ram,
-                      uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth, double *frame_smooth, double *g_rom,
-                      double *g_ram0, double *g_swcha, double *g_inpt4, double *g_pos, int64_t *n_nodes);
+                      int frame_skip, int ystart, int mode, double read_T, const double *grad_frame,
+                      const double *grad_ram, uint8_t *ram_out, uint8_t *frame_out, double *ram_smooth,
+                      double *frame_smooth, double *g_rom, double *g_ram0, double *g_swcha, double *g_inpt4,
+                      double *g_pos, double *frame_dpos, int64_t *n_nodes);
 #endif
