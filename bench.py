@@ -34,7 +34,8 @@ TRAFFIC_FILE = os.path.join(PROFILES, "vcs_tr_step_c1_hbm_traffic.md")
 HBM_PEAK_GBPS = 8000.0                         # MI355X HBM3E
 SIMDS, CLOCK_HZ = 1024, 2.4e9                  # 256 CUs x 4 SIMDs; a wave64 VALU instruction takes 4 cycles
 KERNEL_SOURCES = ["vcs_core.hpp", "vcs_paths.hpp", "vcs_internal.hpp", "vcs_kernels.hpp", "vcs_kernels.hip",
-                  "vcs_device.hpp", "vcs_jit.hpp", "vcs_jit.cpp"]
+                  "vcs_device.hpp", "vcs_jit.hpp", "vcs_jit.cpp", "vcs_step_kernels.hpp", "vcs_step_hard.hip",
+                  "vcs_step_soft.hip", "vcs_step_relaxed.hip", "vcs_step_hard_obj.hip"]
 
 
 def log(*a):
@@ -126,8 +127,8 @@ def parse():
     ap.add_argument("--kernel", default="translated", help="step kernel of the hard leg: translated, grouped, plain")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--tpb", type=int, default=0)
-    ap.add_argument("--legs", default="hard,grouped,plain,hetero,soft,cpu",
-                    help="comma list of: hard, plain, hetero, soft, cpu")
+    ap.add_argument("--legs", default="hard,grouped,plain,hetero,objects,soft,cpu",
+                    help="comma list of: hard, grouped, plain, hetero, objects, soft, cpu")
     ap.add_argument("--soft-k", default="256,1024,4096")
     ap.add_argument("--soft-passes", type=int, default=2)
     ap.add_argument("--soft-warmup", type=int, default=1)
@@ -136,6 +137,9 @@ def parse():
     ap.add_argument("--hetero-tpb", type=int, default=256)
     ap.add_argument("--hetero-calls", type=int, default=4, help="timed calls of 25 env steps")
     ap.add_argument("--hetero-warmup", type=int, default=1)
+    ap.add_argument("--objects-lanes", type=int, default=0, help="lanes per env of the sprite leg (0 = auto)")
+    ap.add_argument("--objects-tpb", type=int, default=256)
+    ap.add_argument("--objects-calls", type=int, default=4, help="timed calls of 25 env steps")
     ap.add_argument("--cpu-soft-envs", type=int, default=256,
                     help="envs of the small soft workload in the single-core FP64 fwd+bwd oracle sample")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
@@ -456,6 +460,26 @@ def main():
                                         "INTIM) x 256 envs = 16384 envs, frame-skip 4, geometric episodes "
                                         "(mean 1500 frames) with in-run resets")
         log("hetero", result["hetero"])
+    if "objects" in legs:
+        oa = argparse.Namespace(**vars(args))
+        oa.chunk, oa.steps, oa.warmup = 25, args.objects_calls, 1
+        w5 = I.config_objects(envs_per_rom=256, steps=25 * (args.objects_calls + 1), n_roms=16)
+        ol, ot = args.objects_lanes, args.objects_tpb
+        if ol == 0:
+            from paper_2606_22447_amd import autotune
+            t = autotune.tune_hard(w5.roms, w5.env_rom, frame_skip=w5.frame_skip, seed=w5.seed, ram0=w5.ram0,
+                                   actions=w5.actions, trial_steps=2)
+            tuned["objects"] = [(r["lanes_per_env"], r["block_threads"], round(r["env_steps_per_s"]))
+                                for r in t["table"]]
+            log("objects autotune", tuned["objects"])
+            ol, ot = t["lanes_per_env"], t["block_threads"]
+        result["objects"] = hard_leg(oa, "grouped", ol, ot, w5)
+        result["objects"]["instructions_per_env_step"] = instructions_per_step(w5, envs=8, steps=4,
+                                                                               stride=w5.num_envs // 8)
+        result["objects"]["workload"] = ("objects: 16 seed-generated sprite kernels (4x2K, 12x4K: players, "
+                                         "missiles, ball, HMOVE, collisions read every frame, P0 moved by the "
+                                         "joystick) x 256 envs = 4096 envs, frame-skip 4, RAM and frame every step")
+        log("objects", result["objects"])
     if "soft" in legs:
         result["soft"] = soft_leg(args)
         log("soft", result["soft"])
@@ -529,6 +553,19 @@ def main():
             "ops_per_env_step": ops2, "kernel": "k_step (grouped, heterogeneous)",
             "valu_issue": counter_fractions(profile_figures("k_step_c2_hetero_sq_counters.md"), "k_step_hetero",
                                             r2["ms_per_call"] / 1e3)}
+    if "objects" in result:
+        r5 = result["objects"]
+        line["objects"] = {k: r5[k] for k in ("env_steps_per_s", "ms_per_call", "parity_sample", "workload", "launch",
+                                              "instructions_per_env_step")}
+        ips5 = r5["instructions_per_env_step"]
+        ops5 = ips5 * OPS_PER_INSTRUCTION + 33600 * OPS_PER_PIXEL
+        ach5 = r5["env_steps_per_s"] * ops5 / 1e12
+        line["objects"]["instructions_per_s"] = r5["env_steps_per_s"] * ips5
+        line["objects"]["roofline"] = {
+            "bound": "alu", "achieved": ach5, "peak": VALU_PEAK_TOPS, "unit": "Tops/s", "frac": ach5 / VALU_PEAK_TOPS,
+            "ops_per_env_step": ops5, "kernel": "k_step (grouped, sprite workload)",
+            "valu_issue": counter_fractions(profile_figures("k_step_objects_sq_counters.md"), "k_step_objects",
+                                            r5["ms_per_call"] / 1e3)}
     if tuned:
         line["autotune"] = {k: {"trials (lanes_per_env, block_threads, env_steps_per_s)": v}
                             for k, v in tuned.items()}

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define VCS_ABI_VERSION 2  /* 2: vcs_step_soft_fwd takes a starting state */
+#define VCS_ABI_VERSION 3  /* 2: soft forward from a given state; 3: sampler tangents, address surrogate */
 
 typedef enum vcs_status {
     VCS_OK = 0,
@@ -170,11 +170,19 @@ int32_t vcs_reset(vcs_ctx *ctx, void *d_state, const uint8_t *d_mask, const uint
  *                 in episode e < E it is reset in-run (power-on, RAM =
  *                 SplitMix64(seed, env, e+1)) and the next step starts the new
  *                 episode;
- *  d_work         workspace of vcs_workspace_bytes(VCS_OP_HARD).
- * The stream work of a call is one host-to-device copy of the launch tables
- * into d_work and one kernel, so a call can be captured in a HIP graph once the
- * context has made a device call (vcs_reset, or an earlier step); a context's
- * first device call inside a capture returns VCS_UNSUPPORTED. */
+ *  d_work         workspace of vcs_workspace_bytes(VCS_OP_HARD): the launch
+ *                 tables, a copy of the starting states (and Superchip RAM)
+ *                 and one flag byte per env.
+ * A call runs in two passes: every env first runs in kernels without the TIA
+ * object paths (the translated code, or the interpreter), which are exact while
+ * no object shows and flag the envs where one does; those envs are then rerun
+ * from the copied starting states by the interpreter with the object paths
+ * (collisions, object pixels).  The stream work of a call is one
+ * host-to-device copy of the launch tables into d_work, one device-to-device
+ * copy of the states (two with Superchip RAM), and the two kernels, so a call
+ * can be captured in a HIP graph once the context has made a device call
+ * (vcs_reset, or an earlier step); a context's first device call inside a
+ * capture returns VCS_UNSUPPORTED. */
 int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
                       uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
                       const uint32_t *d_episode_steps, int32_t num_episodes, void *d_work, hipStream_t stream);
@@ -185,8 +193,10 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
  * array of the library (1 MiB on each device it runs on, held until the
  * process ends) instead of a caller workspace, and the call allocates
  * nothing: no device, host or pinned memory.
- *  - The context's tables must fit: VCS_WORKSPACE_TOO_SMALL when
- *    vcs_workspace_bytes(VCS_OP_HARD) exceeds 1 MiB (about 80,000 envs).
+ *  - The context's launch tables must fit: VCS_WORKSPACE_TOO_SMALL when
+ *    they exceed 1 MiB (about 80,000 envs).
+ *  - The call is one pass of the interpreter with the object paths (no state
+ *    copy: that would need a workspace), also for a translated context.
  *  - The context must have made its pinned host copy of the tables (vcs_reset
  *    does; so does an earlier vcs_step_hard): VCS_UNSUPPORTED otherwise.
  *  - All calls on one device share the array, and each call rewrites the
@@ -242,6 +252,17 @@ int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
  *  no gradient in this relaxation, so alpha does not change the result);
  *  d_ram_out       float32 [B][S][128] integer-valued RAM after each step;
  *  d_frame_out     float32 [B][210][160] integer-valued final frame;
+ *  d_frame_dpos    float32 [B][5][210][160] (NULL = not written; needs
+ *                  d_frame_out): the differentiable position sampler of Sec.
+ *                  "Hard and Soft Execution" -- for each object (P0, P1, M0, M1,
+ *                  BL) the final frame's derivative with respect to the
+ *                  object's column through a triangular (bilinear) sampler at
+ *                  zero sub-pixel offset, taken from the right: per pixel the
+ *                  colour with the object drawn one column further right
+ *                  (every span of the frame) minus the colour drawn, 0 where
+ *                  VBLANK or an HMOVE blank blacks the pixel out.  A stored
+ *                  switch gives no gradient for a strobe-timed column; this is
+ *                  the paper's remedy for that one index;
  *  d_decode_out    float32 statistics (NULL = not written), in order:
  *                  ROM rows [sum rom_size][3] = (expected byte, softmax max,
  *                  softmax normaliser); tape [B][128] expected byte; actions
@@ -252,8 +273,8 @@ int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
  *  d_work          vcs_workspace_bytes(VCS_OP_SOFT_FWD, S). */
 int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_rom_logits, const float *d_ram_tape,
                           const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
-                          float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
-                          void *d_work, hipStream_t stream);
+                          float *d_frame_out, float *d_frame_dpos, float *d_decode_out, void *d_state_out,
+                          void *d_residual, void *d_work, hipStream_t stream);
 
 /* SOFT-STE backward: surrogate gradients of a loss given dL/d(final frame)
  * (float32 [B][210][160]) and optionally dL/d(RAM out) (float32 [B][S][128],
@@ -266,6 +287,15 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
  * checkpoint segment from its hard-state checkpoint, records a tape and
  * sweeps it in reverse; ROM gradients of envs sharing a ROM are summed in a
  * fixed order (deterministic).
+ *  read_T               0: addresses carry no gradient (the STE surrogate).  > 0:
+ *                       the leaky variant's address surrogate (Eq. s-read taken in
+ *                       the backward): an indexed load or ALU read of a ROM or RAM
+ *                       byte (zp,X zp,Y abs,X abs,Y (zp),Y; not read-modify-write)
+ *                       also passes its value's adjoint to the index register, times
+ *                       the slope of the distance-softmax read at temperature
+ *                       read_T: (1/T) sum_j w_j sign(j - a) (R[j] - R[a]) over
+ *                       |j - a| <= 8 inside the ROM image or the 128 RAM cells,
+ *                       w_j = exp(-|j - a|/T) normalised.  Must be finite, >= 0;
  *  d_ram_tape           unused (may be NULL): dL/dP[c][k] = k dL/dcell[c]
  *  d_grad_rom_logits    float32 [sum rom_size][256]  (overwritten)
  *  d_grad_ram_tape      float32 [B][128][256]         (overwritten; NULL = not
@@ -274,7 +304,7 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
  *  d_work               vcs_workspace_bytes(VCS_OP_SOFT_BWD, S). */
 int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_rom_logits,
                           const float *d_ram_tape, const float *d_action_logits, float tau, float alpha,
-                          int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
+                          float read_T, int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
                           float *d_grad_rom_logits, float *d_grad_ram_tape, float *d_grad_action_logits,
                           void *d_work, hipStream_t stream);
 
@@ -282,6 +312,17 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
  * PCH, bank, status (bit0 jammed), INTIM now, TIMINT now, VBLANK, COLUP0,
  * COLUP1, COLUPF, COLUBK. */
 int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream);
+
+/* Inspect: per-env TIA object registers into d_out uint8 [B][32] (Sec. "Hard
+ * and Soft Execution": object priority, sprite bits, strobe-timed columns) =
+ * the columns of P0, P1, M0, M1, BL (0..159); GRP0, GRP1 and their old
+ * (vertical-delay) registers; ENAM0, ENAM1, ENABL and its old register (bit 1);
+ * NUSIZ0, NUSIZ1; REFP0, REFP1 (bit 3); VDELP0, VDELP1, VDELBL (bit 0);
+ * RESMP0, RESMP1 (bit 1); the motion registers HMP0, HMP1, HMM0, HMM1, HMBL
+ * (high nibble); the collision latches as a 16-bit word (bit 2r: register r's
+ * bit 7, bit 2r+1: its bit 6), low byte first; three zero bytes.  The latches
+ * are those at the state's cycle. */
+int32_t vcs_read_objects(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream);
 
 /* Inspect: a 64-bit fingerprint per env for bulk comparisons (the parity
  * protocol compares them step by step against the reference emulator).

@@ -19,13 +19,13 @@ VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED, VCS_KERNEL_TRANSLATED = 0
 VCS_TRANSLATE_COMPILE_ONLY = 1
 VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
 VCS_OP_HARD, VCS_OP_SOFT_FWD, VCS_OP_SOFT_BWD = 0, 1, 2
-ABI_VERSION = 2
+ABI_VERSION = 3
 STATE_BYTES = 256
 
 EXPORTED = [
     "vcs_create", "vcs_destroy", "vcs_status_string", "vcs_state_bytes", "vcs_rom_bytes",
     "vcs_workspace_bytes", "vcs_residual_bytes", "vcs_decode_bytes", "vcs_reset", "vcs_step_hard",
-    "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_residual_checkpoints",
+    "vcs_step_soft_fwd", "vcs_step_soft_bwd", "vcs_read_regs", "vcs_read_objects", "vcs_residual_checkpoints",
     "vcs_bwd_overflow", "vcs_launch_info", "vcs_decode_table", "vcs_hash", "vcs_translate",
     "vcs_translated_source", "vcs_step_hard_static", "vcs_bwd_overflow_offset", "vcs_step_relaxed",
     "vcs_detect_mapper",
@@ -81,9 +81,10 @@ def lib():
         L.vcs_step_hard.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp, vp]
         L.vcs_step_hard_static.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, vp, vp, i32, vp]
         L.vcs_step_relaxed.argtypes = [vp, vp, vp, vp, i32, vp, i32, vp, C.c_double, C.c_double, vp, vp, vp]
-        L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
-        L.vcs_step_soft_bwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
+        L.vcs_step_soft_fwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.vcs_step_soft_bwd.argtypes = [vp, vp, vp, vp, vp, f32, f32, f32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.vcs_read_regs.argtypes = [vp, vp, vp, vp]
+        L.vcs_read_objects.argtypes = [vp, vp, vp, vp]
         L.vcs_bwd_overflow.argtypes = [vp, vp, i32, vp, C.POINTER(i32)]
         L.vcs_bwd_overflow_offset.argtypes = [vp, i32, C.POINTER(sz)]
         L.vcs_launch_info.argtypes = [vp] + [C.POINTER(i32)] * 5

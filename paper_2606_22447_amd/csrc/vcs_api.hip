@@ -80,6 +80,24 @@ ResidualLayout residual_layout(const vcs_ctx *c, int32_t S) {
 }
 
 // Layout of the soft-backward workspace (after the static region).
+// Workspace of a hard step: the launch tables, then for the two passes the
+// starting states (and Superchip RAM) and the per-env object flags.
+struct HardLayout {
+    size_t states, sc, flags, bytes;
+};
+HardLayout hard_layout(const vcs_ctx *c) {
+    HardLayout L{};
+    size_t o = align_up(c->blob_bytes);
+    L.states = o;
+    o = align_up(o + (size_t)c->B * sizeof(StateRec));
+    L.sc = o;
+    if (c->any_sc) o = align_up(o + (size_t)c->B * 128);
+    L.flags = o;
+    o = align_up(o + (size_t)c->B);
+    L.bytes = o;
+    return L;
+}
+
 struct BwdLayout {
     size_t tape, gpart, gport, g0, overflow, bytes;
     int32_t max_rec;
@@ -150,6 +168,18 @@ int32_t upload_static(vcs_ctx *c, void *d_work, hipStream_t stream) {
 }
 
 int32_t hip_status(hipError_t e) { return e == hipSuccess ? VCS_OK : VCS_HIP_ERROR; }
+
+// Whether the translated kernel fits one CU's LDS: the largest image's words, the
+// block tables (4096 16-bit entries per bank), the envs' RAM, the decode table
+// and a pixel-write log of at least kTrLogCap entries per env.
+bool tr_lds_fits(const vcs_ctx *c) {
+    const size_t E = (size_t)(c->tpb / c->G);
+    bool f8 = false;
+    for (int32_t mp : c->rom_mapper) f8 = f8 || mp == kMapperF8;
+    const size_t need = (size_t)c->max_rom * 8 + (f8 ? 2 : 1) * 4096 * 2 + E * 128 + 1024 +
+                        E * (size_t)kTrLogCap * (size_t)kTrLogEntryBytes;
+    return need <= kLdsBytes;
+}
 
 // Whether the LDS-staged step kernels fit the context's images and launch shape.
 bool lds_fits(const vcs_ctx *c) {
@@ -307,8 +337,8 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
         delete c;
         return VCS_UNSUPPORTED;
     }
-    // translated code keeps a pixel-write log per env in LDS: at most 64 envs per workgroup
-    // (with the largest ROM image staged beside it); its translator handles 2K, 4K and F8
+    // translated code: at most 64 envs per workgroup (vcs_translate checks that its LDS fits);
+    // its translator handles 2K, 4K and F8
     if (c->kernel == VCS_KERNEL_TRANSLATED) {
         bool ok = c->tpb / c->G <= 64;
         for (int32_t mp : c->rom_mapper) ok = ok && (mp == kMapper2K || mp == kMapper4K || mp == kMapperF8);
@@ -405,7 +435,7 @@ int32_t vcs_rom_bytes(const vcs_ctx *ctx, size_t *bytes) {
 int32_t vcs_workspace_bytes(const vcs_ctx *ctx, int32_t op, int32_t steps, size_t *bytes) {
     if (!ctx || !bytes || steps < 1) return VCS_INVALID_ARG;
     switch (op) {
-        case VCS_OP_HARD:
+        case VCS_OP_HARD: *bytes = hard_layout(ctx).bytes; return VCS_OK;
         case VCS_OP_SOFT_FWD: *bytes = align_up(ctx->blob_bytes); return VCS_OK;
         case VCS_OP_SOFT_BWD: *bytes = bwd_layout(ctx, steps).bytes; return VCS_OK;
         default: return VCS_INVALID_ARG;
@@ -456,11 +486,16 @@ int32_t check_step_hard_args(const vcs_ctx *ctx, const uint8_t *d_rom, const voi
     return VCS_OK;
 }
 
-// The hard step's launch: the launch tables are already (in stream order) at d_tables.
+// The hard step's launches: the launch tables are already (in stream order) at
+// d_tables.  With d_two (the rest of a hard workspace) the step runs in two passes:
+// the starting states are copied aside, the kernel without the object paths runs
+// every env and flags those that showed an object, and the kernel with them reruns
+// the flagged envs from the copies; without it (no workspace) the kernel with the
+// object paths runs every env.
 int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const uint8_t *d_actions, int32_t steps,
                          uint8_t *d_ram_out, int32_t frames, uint8_t *d_frame_out, uint8_t *d_done,
                          const uint32_t *d_episode_steps, int32_t num_episodes, const void *d_tables,
-                         hipStream_t stream) {
+                         uint8_t *d_two, hipStream_t stream) {
     StepParams P{};
     P.st = static_ptrs(ctx, d_tables);
     P.rom = d_rom;
@@ -478,16 +513,38 @@ int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
     P.seed = ctx->seed;
     P.sc_state = sc_state(ctx, d_state);
     P.rom_words = ctx->max_rom;
+    const bool plain = ctx->kernel == VCS_KERNEL_PLAIN;
+    if (!d_two)  // one pass with the object paths (the translated code has none: the interpreter runs)
+        return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, plain, step_lds(ctx), stream));
+    const HardLayout L = hard_layout(ctx);
+    uint8_t *work = d_two - align_up(ctx->blob_bytes);  // the workspace's start
+    StateRec *copy = (StateRec *)(work + L.states);
+    uint8_t *sc_copy = ctx->any_sc ? work + L.sc : nullptr;
+    uint8_t *flags = work + L.flags;
+    if (hipMemcpyAsync(copy, d_state, (size_t)ctx->B * sizeof(StateRec), hipMemcpyDeviceToDevice, stream) !=
+            hipSuccess ||
+        (sc_copy && hipMemcpyAsync(sc_copy, P.sc_state, (size_t)ctx->B * 128, hipMemcpyDeviceToDevice, stream) !=
+                        hipSuccess))
+        return VCS_HIP_ERROR;
+    P.obj_flag = flags;
+    int32_t rc;
     if (ctx->kernel == VCS_KERNEL_TRANSLATED) {
         int dev = -1;
         if (!ctx->tr_fn || hipGetDevice(&dev) != hipSuccess || dev != ctx->tr_device) return VCS_UNSUPPORTED;
         void *args[] = {&P};
         const size_t lds = (size_t)ctx->max_rom * sizeof(uint2);
-        return hip_status(hipModuleLaunchKernel(ctx->tr_fn, (unsigned)ctx->main_blocks, 1, 1, (unsigned)ctx->tpb, 1,
-                                                1, (unsigned)lds, stream, args, nullptr));
+        rc = hip_status(hipModuleLaunchKernel(ctx->tr_fn, (unsigned)ctx->main_blocks, 1, 1, (unsigned)ctx->tpb, 1, 1,
+                                              (unsigned)lds, stream, args, nullptr));
+    } else {
+        rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, plain, step_lds(ctx), stream,
+                                    false));
     }
-    return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, ctx->kernel == VCS_KERNEL_PLAIN,
-                                  step_lds(ctx), stream));
+    if (rc) return rc;
+    P.obj_flag = nullptr;
+    P.rerun = flags;
+    P.state_src = copy;
+    P.sc_src = sc_copy;
+    return hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, plain, step_lds(ctx), stream, true));
 }
 
 }  // namespace
@@ -504,7 +561,8 @@ int32_t vcs_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, const u
     rc = upload_static(ctx, d_work, stream);
     if (rc) return rc;
     return launch_step_hard(ctx, d_rom, d_state, d_actions, steps, d_ram_out, frames, d_frame_out, d_done,
-                            d_episode_steps, num_episodes, d_work, stream);
+                            d_episode_steps, num_episodes, d_work, (uint8_t *)d_work + align_up(ctx->blob_bytes),
+                            stream);
 }
 
 // vcs_step_hard with the launch tables in the library's static device array
@@ -525,7 +583,7 @@ int32_t vcs_step_hard_static(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, 
     if (hipMemcpyAsync(tables, ctx->pinned, ctx->blob_bytes, hipMemcpyHostToDevice, stream) != hipSuccess)
         return VCS_HIP_ERROR;
     return launch_step_hard(ctx, d_rom, d_state, d_actions, steps, d_ram_out, frames, d_frame_out, d_done,
-                            d_episode_steps, num_episodes, tables, stream);
+                            d_episode_steps, num_episodes, tables, nullptr, stream);
 }
 
 // FULL relaxed hard steps: the launch of vcs_step_hard with the relaxing kernel.
@@ -583,6 +641,7 @@ int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, 
     if (max_positions < 0 || max_positions > 65536) return VCS_INVALID_ARG;
     const int budget = max_positions ? max_positions : kTranslateBudget;
     if (ctx->kernel != VCS_KERNEL_TRANSLATED) return VCS_UNSUPPORTED;
+    if (!tr_lds_fits(ctx)) return VCS_UNSUPPORTED;  // the pixel logs of this many envs per workgroup do not fit
     if (log && log_size) log[0] = '\0';
     TranslateStats st;
     const std::string src = translated_source(roms, ctx->rom_off, ctx->rom_size, ctx->rom_mapper, ctx->env_rom, ctx->seed,
@@ -624,8 +683,8 @@ int32_t vcs_translate(vcs_ctx *ctx, const uint8_t *roms, int32_t max_positions, 
 
 int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_rom_logits, const float *d_ram_tape,
                           const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
-                          float *d_frame_out, float *d_decode_out, void *d_state_out, void *d_residual,
-                          void *d_work, hipStream_t stream) {
+                          float *d_frame_out, float *d_frame_dpos, float *d_decode_out, void *d_state_out,
+                          void *d_residual, void *d_work, hipStream_t stream) {
     if (!ctx || !d_rom_logits || (!d_ram_tape && !d_state_in) || !d_action_logits || !d_residual || !d_work ||
         steps < 1)
         return VCS_INVALID_ARG;
@@ -633,6 +692,7 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
     if (!aligned16(d_rom_logits) || (d_ram_tape && !aligned16(d_ram_tape)) || ((uintptr_t)d_action_logits & 3u) ||
         !aligned16(d_residual) || !aligned16(d_work) || (d_state_in && !aligned16(d_state_in)))
         return VCS_INVALID_ARG;
+    if (d_frame_dpos && (!d_frame_out || !aligned16(d_frame_dpos))) return VCS_INVALID_ARG;
     if ((d_ram_out && !aligned16(d_ram_out)) || (d_frame_out && !aligned16(d_frame_out)) ||
         (d_state_out && !aligned16(d_state_out)) || (d_decode_out && ((uintptr_t)d_decode_out & 3u)))
         return VCS_INVALID_ARG;
@@ -663,6 +723,7 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
     P.frames_mode = VCS_FRAMES_LAST;
     P.ram_out_f = d_ram_out;
     P.frame_out_f = d_frame_out;
+    P.frame_dpos_f = d_frame_dpos;
     P.ram0 = res + L.ram0_hard;
     P.ckpt = (StateRec *)(res + L.ckpt);
     P.ckpt_count = (int32_t *)(res + L.ckpt_count);
@@ -680,14 +741,14 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
 
 int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_rom_logits,
                           const float *d_ram_tape, const float *d_action_logits, float tau, float alpha,
-                          int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
+                          float read_T, int32_t steps, const float *d_grad_frame, const float *d_grad_ram_out,
                           float *d_grad_rom_logits, float *d_grad_ram_tape, float *d_grad_action_logits,
                           void *d_work, hipStream_t stream) {
     (void)d_ram_tape;  // dL/dP0[c,k] = k g0[c] needs no tape values
     if (!ctx || !d_residual || !d_rom_logits || !d_action_logits || !d_grad_frame || !d_grad_rom_logits ||
         !d_grad_action_logits || !d_work || steps < 1)
         return VCS_INVALID_ARG;
-    if (!(tau > 0.f) || !(alpha > 0.f)) return VCS_INVALID_ARG;
+    if (!(tau > 0.f) || !(alpha > 0.f) || !(read_T >= 0.f) || !std::isfinite(read_T)) return VCS_INVALID_ARG;
     if (!aligned16(d_residual) || !aligned16(d_rom_logits) || !aligned16(d_grad_rom_logits) ||
         (d_grad_ram_tape && !aligned16(d_grad_ram_tape)) || !aligned16(d_work) || ((uintptr_t)d_grad_frame & 3u) ||
         ((uintptr_t)d_action_logits & 3u) || ((uintptr_t)d_grad_action_logits & 3u) ||
@@ -721,6 +782,7 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     P.gport = (float *)(work + W.gport);
     P.g_ram0 = (float *)(work + W.g0);
     P.overflow = (int32_t *)(work + W.overflow);
+    P.read_T = read_T;
     rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, ctx->max_rom, stream));
     if (rc) return rc;
     const StaticPtrs sp = static_ptrs(ctx, d_work);
@@ -734,6 +796,11 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
 int32_t vcs_read_regs(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream) {
     if (!ctx || !d_state || !d_out || !aligned16(d_state)) return VCS_INVALID_ARG;
     return hip_status(launch_read_regs((const StateRec *)d_state, ctx->B, d_out, stream));
+}
+
+int32_t vcs_read_objects(vcs_ctx *ctx, const void *d_state, uint8_t *d_out, hipStream_t stream) {
+    if (!ctx || !d_state || !d_out || !aligned16(d_state)) return VCS_INVALID_ARG;
+    return hip_status(launch_read_objects((const StateRec *)d_state, ctx->B, d_out, stream));
 }
 
 int32_t vcs_hash(vcs_ctx *ctx, const void *d_state, const uint8_t *d_frame, int64_t frame_stride, uint64_t *d_out,

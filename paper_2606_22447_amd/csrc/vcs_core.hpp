@@ -15,6 +15,7 @@
 //  - A TIA write in CPU cycle n shows from colour clock 3n+3; WSYNC resumes the
 //    CPU at cycle 0 of the next line; a pixel is the owning colour register &
 //    0xFE (0 while VBLANK bit 1 is set).
+//  - TIA objects (players, missiles, ball): see the object model below.
 //  - RIOT timer: after writing V with interval 2^shift at cycle w the timer
 //    underflows at u = w + 1 + V*2^shift; before u INTIM = -1 - floor((t-u)/I),
 //    from u on INTIM = (255 - (t - u)) mod 256; TIMINT bit 7 is set from u
@@ -277,13 +278,303 @@ __host__ __device__ __forceinline__ void for_each_group(int32_t from, int32_t to
     }
 }
 
-// Write the pixels of [from, to) for the given TIA state into a frame of T.
+// ---------------------------------------------------------------------------
+// TIA objects (Sec. "Hard and Soft Execution": object priority, sprite bits and
+// the strobe-timed sprite column), as the documented TIA has them:
+//  - P0, P1, M0, M1 and BL each sit at a column (its first pixel), 0 at
+//    power-on.  A strobe (RESP0/1, RESM0/1, RESBL) taking effect at clock h of
+//    its line puts a player at column h - 68 + 5 and a missile or the ball at
+//    h - 68 + 4 (mod 160), or at 3 / 2 when h lies in horizontal blank.
+//  - NUSIZ bits 0-2: a player's copies at column offsets {0} {0,16} {0,32}
+//    {0,16,32} {0,64} {0} {0,32,64} {0}, its pixel width 1, 2 (mode 5) or 4
+//    (mode 7); the graphics byte shows bit 7 first, bit 0 first when REFP bit 3
+//    is set.  A missile has its player's copies, width 2^(NUSIZ bits 4-5), and
+//    shows while ENAM bit 1 is set and RESMP bit 1 clear; releasing RESMP moves
+//    it to its player's column + 4 * pixel width.  The ball is one copy, width
+//    2^(CTRLPF bits 4-5), shown while ENABL bit 1 is set.  A GRP0 write copies
+//    GRP1 to GRP1's old register; a GRP1 write copies GRP0 and ENABL to theirs;
+//    VDELP0/1 and VDELBL bit 0 display the old registers.
+//  - HMOVE moves each object left by the signed high nibble of its motion
+//    register; HMCLR zeroes them.  An HMOVE taking effect in horizontal blank
+//    blacks out columns 0..7 of its line (no collisions there either).
+//  - Priority: P0/M0 (COLUP0) over P1/M1 (COLUP1) over playfield and ball over
+//    the background; CTRLPF bit 2 puts playfield and ball first.  Score mode
+//    colours the playfield only; the ball is COLUPF.
+//  - Collisions latch wherever two objects, or an object and the playfield,
+//    show at one visible column (VBLANK does not mask them); CXCLR clears; a read
+//    in cycle t sees clocks before 3t + 3.  Register r reads pair 2r in bit 7 and
+//    2r + 1 in bit 6: M0-P1, M0-P0, M1-P0, M1-P1, P0-PF, P0-BL, P1-PF, P1-BL,
+//    M0-PF, M0-BL, M1-PF, M1-BL, BL-PF, -, P0-P1, M0-M1.
+// Rows of 160 columns are five 32-bit words (column x = bit x & 31 of word
+// x >> 5), so a row of a span is built once and read a 4-pixel nibble at a time.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kObRefp0 = 1u << 16, kObRefp1 = 1u << 17, kObVdelp0 = 1u << 18, kObVdelp1 = 1u << 19,
+                   kObVdelbl = 1u << 20, kObEnam0 = 1u << 21, kObEnam1 = 1u << 22, kObEnabl = 1u << 23,
+                   kObEnablOld = 1u << 24, kObResmp0 = 1u << 25, kObResmp1 = 1u << 26;
+struct Objs {
+    uint32_t pos;  // columns: P0 | P1 << 8 | M0 << 16 | M1 << 24
+    uint32_t gfx;  // GRP0 | GRP1 << 8 | GRP0 old << 16 | GRP1 old << 24
+    uint32_t ctl;  // NUSIZ0 | NUSIZ1 << 8 | kOb* flags
+    uint32_t bl;   // ball column | (frame-relative line of the last HMOVE blank + 1) << 8 (0: none)
+};
+// The TIA registers the pixel pipeline reads: colours, playfield + CTRLPF,
+// VBLANK | VSYNC << 8, objects.
+struct Tia {
+    uint32_t col, pf, vb;
+    Objs ob;
+};
+enum ObjRow : uint32_t { R_P0 = 0, R_P1, R_M0, R_M1, R_BL, R_PF, kRows };
+
+__host__ __device__ __forceinline__ uint32_t shown_gfx(const Objs &o, uint32_t i) {
+    const bool vdel = (o.ctl & (i ? kObVdelp1 : kObVdelp0)) != 0u;
+    return (o.gfx >> (8u * i + (vdel ? 16u : 0u))) & 0xFFu;
+}
+__host__ __device__ __forceinline__ bool missile_on(const Objs &o, uint32_t i) {
+    return (o.ctl & (i ? kObEnam1 : kObEnam0)) && !(o.ctl & (i ? kObResmp1 : kObResmp0));
+}
+__host__ __device__ __forceinline__ bool ball_on(const Objs &o) {
+    return (o.ctl & ((o.ctl & kObVdelbl) ? kObEnablOld : kObEnabl)) != 0u;
+}
+// does any object show a pixel (else nothing but the playfield is drawn and nothing collides)
+__host__ __device__ __forceinline__ bool objs_shown(const Objs &o) {
+    return (shown_gfx(o, 0) | shown_gfx(o, 1)) != 0u || missile_on(o, 0) || missile_on(o, 1) || ball_on(o);
+}
+// NUSIZ mode m's copies as a set over column offsets 16 j, j = 0..4
+__host__ __device__ __forceinline__ uint32_t copy_set(uint32_t m) {
+    constexpr uint64_t kSets = 1ull | 3ull << 5 | 5ull << 10 | 7ull << 15 | 17ull << 20 | 1ull << 25 | 21ull << 30 |
+                               1ull << 35;
+    return (uint32_t)(kSets >> (5u * (m & 7u))) & 31u;
+}
+// log2 of a player's pixel width in NUSIZ mode m
+__host__ __device__ __forceinline__ uint32_t player_shift(uint32_t m) {
+    m &= 7u;
+    return m == 5u ? 1u : m == 7u ? 2u : 0u;
+}
+__host__ __device__ __forceinline__ uint32_t wrap160(uint32_t c) { return c >= 160u ? c - 160u : c; }
+// column of an object strobed at frame-relative colour clock cc (lag 5: players, 4: missiles and ball)
+__host__ __device__ __forceinline__ uint32_t strobe_column(int32_t cc, uint32_t lag) {
+    const uint32_t h = (uint32_t)(cc % kClocksPerLine);
+    return h < (uint32_t)kHBlank ? lag - 2u : wrap160(h - (uint32_t)kHBlank + lag);
+}
+
+struct Row160 {
+    uint32_t w[5];
+};
+__host__ __device__ __forceinline__ uint32_t row_word(const Row160 &r, uint32_t k) {
+    uint32_t v = r.w[0];
+#pragma unroll
+    for (uint32_t i = 1; i < 5; ++i) v = k == i ? r.w[i] : v;
+    return v;
+}
+// OR a pattern of up to 32 columns (bit e = column c + e, wrapping at 160) into r
+__host__ __device__ __forceinline__ void row_place(Row160 &r, uint32_t pat, uint32_t c) {
+    const uint32_t k = c >> 5, s = c & 31u;
+    const uint32_t lo = pat << s, hi = s ? pat >> (32u - s) : 0u;
+    const uint32_t k1 = k == 4u ? 0u : k + 1u;
+#pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) r.w[i] |= (i == k ? lo : 0u) | (i == k1 ? hi : 0u);
+}
+// the same row one column further right (column 159 goes to 0)
+__host__ __device__ __forceinline__ Row160 row_shift1(const Row160 &r) {
+    Row160 o;
+#pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) o.w[i] = (r.w[i] << 1) | (r.w[i == 0 ? 4 : i - 1] >> 31);
+    return o;
+}
+// each bit of an 8-bit pattern repeated over 2^sh columns
+__host__ __device__ __forceinline__ uint32_t widen(uint32_t p, uint32_t sh) {
+    const uint32_t one = (1u << (1u << sh)) - 1u;
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t b = 0; b < 8; ++b) r |= ((p >> b) & 1u) ? one << (b << sh) : 0u;
+    return r;
+}
+// 8 bits -> 32: bit i fills nibble i
+__host__ __device__ __forceinline__ uint32_t spread4(uint32_t v) {
+    v &= 0xFFu;
+    v = (v | (v << 12)) & 0x000F000Fu;
+    v = (v | (v << 6)) & 0x03030303u;
+    v = (v | (v << 3)) & 0x11111111u;
+    return v * 15u;
+}
+__host__ __device__ __forceinline__ void player_row(Row160 &r, const Objs &o, uint32_t i) {
+    const uint32_t m = (o.ctl >> (8u * i)) & 7u;
+    const uint32_t g = shown_gfx(o, i);
+    const uint32_t p8 = (o.ctl & (i ? kObRefp1 : kObRefp0)) ? g : rev8(g);  // bit e = the e-th pixel
+    const uint32_t pat = widen(p8, player_shift(m));
+    const uint32_t c = (o.pos >> (8u * i)) & 0xFFu, set = copy_set(m);
+#pragma unroll
+    for (uint32_t j = 0; j < 5; ++j)
+        if ((set >> j) & 1u) row_place(r, pat, wrap160(c + 16u * j));
+}
+__host__ __device__ __forceinline__ void missile_row(Row160 &r, const Objs &o, uint32_t i) {
+    if (!missile_on(o, i)) return;
+    const uint32_t nus = (o.ctl >> (8u * i)) & 0xFFu;
+    const uint32_t pat = (1u << (1u << ((nus >> 4) & 3u))) - 1u;
+    const uint32_t c = (o.pos >> (16u + 8u * i)) & 0xFFu, set = copy_set(nus & 7u);
+#pragma unroll
+    for (uint32_t j = 0; j < 5; ++j)
+        if ((set >> j) & 1u) row_place(r, pat, wrap160(c + 16u * j));
+}
+__host__ __device__ __forceinline__ void playfield_row(Row160 &r, uint32_t pf) {
+    const uint32_t m20 = pf_mask20(pf);
+    const uint32_t right = ((pf >> 24) & 1u) ? (__builtin_bitreverse32(m20) >> 12) : m20;
+    const uint64_t g40 = (uint64_t)m20 | ((uint64_t)right << 20);
+#pragma unroll
+    for (uint32_t k = 0; k < 5; ++k) r.w[k] = spread4((uint32_t)(g40 >> (8u * k)));
+}
+// rows of the five objects and the playfield for a TIA state
+__host__ __device__ __forceinline__ void object_rows(Row160 (&r)[kRows], const Tia &t) {
+#pragma unroll
+    for (uint32_t o = 0; o < kRows; ++o)
+#pragma unroll
+        for (uint32_t i = 0; i < 5; ++i) r[o].w[i] = 0u;
+    player_row(r[R_P0], t.ob, 0);
+    player_row(r[R_P1], t.ob, 1);
+    missile_row(r[R_M0], t.ob, 0);
+    missile_row(r[R_M1], t.ob, 1);
+    if (ball_on(t.ob)) row_place(r[R_BL], (1u << (1u << ((t.pf >> 28) & 3u))) - 1u, t.ob.bl & 0xFFu);
+    playfield_row(r[R_PF], t.pf);
+}
+// owning colour register (0 COLUP0, 1 COLUP1, 2 COLUPF, 3 COLUBK) of column x
+// whose occupancy has bit o set for each row o that shows there
+__host__ __device__ __forceinline__ uint32_t owner_of(uint32_t occ, uint32_t x, uint32_t ctrl) {
+    const bool pfb = (occ >> R_PF) & 1u, field = ((occ >> R_BL) & 3u) != 0u;
+    const bool p0 = ((occ >> R_P0) | (occ >> R_M0)) & 1u, p1 = ((occ >> R_P1) | (occ >> R_M1)) & 1u;
+    const uint32_t fo = (pfb && (ctrl & 2u)) ? (x < 80u ? 0u : 1u) : 2u;
+    if (ctrl & 4u) return field ? fo : p0 ? 0u : p1 ? 1u : 3u;
+    return p0 ? 0u : p1 ? 1u : field ? fo : 3u;
+}
+// occupancy nibbles of 4-pixel group g: bit j of nib[o] = row o at column 4g + j
+__host__ __device__ __forceinline__ void group_occupancy(const Row160 (&r)[kRows], uint32_t g, uint32_t (&nib)[kRows]) {
+    const uint32_t k = g >> 3, sh = 4u * (g & 7u);
+#pragma unroll
+    for (uint32_t o = 0; o < kRows; ++o) nib[o] = (row_word(r[o], k) >> sh) & 15u;
+}
+__host__ __device__ __forceinline__ uint32_t pixel_owner(const uint32_t (&nib)[kRows], uint32_t j, uint32_t x,
+                                                        uint32_t ctrl) {
+    uint32_t occ = 0;
+#pragma unroll
+    for (uint32_t o = 0; o < kRows; ++o) occ |= ((nib[o] >> j) & 1u) << o;
+    return owner_of(occ, x, ctrl);
+}
+// the four colours of group g (column 4g in the low byte) with objects shown
+__host__ __device__ __forceinline__ uint32_t group_colours(const Row160 (&r)[kRows], const Tia &t, uint32_t g) {
+    uint32_t nib[kRows];
+    group_occupancy(r, g, nib);
+    uint32_t out = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 4; ++j)
+        out |= ((t.col >> (8u * pixel_owner(nib, j, 4u * g + j, t.pf >> 24))) & 0xFEu) << (8u * j);
+    return out;
+}
+// frame-relative line whose columns 0..7 an HMOVE blanked (-1: none)
+__host__ __device__ __forceinline__ int32_t hmove_line(const Objs &o) { return (int32_t)(o.bl >> 8) - 1; }
+
+// Latch into cx the collisions of frame-relative colour clocks [from, to) (0 <= from < to)
+// drawn with state t.
+__host__ __device__ inline __attribute__((noinline)) uint32_t collide_span(const Tia t, int32_t from, int32_t to) {
+    uint32_t cx = 0;
+    Row160 cov;
+#pragma unroll
+    for (uint32_t i = 0; i < 5; ++i) cov.w[i] = 0u;
+    const int32_t hl = hmove_line(t.ob);
+    for (int32_t c = from; c < to;) {  // the columns the span covers, on any of its lines
+        const int32_t line = c / kClocksPerLine, l0 = line * kClocksPerLine;
+        const int32_t e = to < l0 + kClocksPerLine ? to : l0 + kClocksPerLine;
+        int32_t x0 = c - l0 - kHBlank;
+        const int32_t x1 = e - l0 - kHBlank;
+        x0 = x0 > 0 ? x0 : 0;
+        if (line == hl && x0 < 8) x0 = 8;
+        if (x1 > x0) {
+#pragma unroll
+            for (int32_t i = 0; i < 5; ++i) {
+                const int32_t a = x0 > 32 * i ? x0 - 32 * i : 0, b = x1 < 32 * i + 32 ? x1 - 32 * i : 32;
+                if (b > a) cov.w[i] |= (b - a == 32 ? ~0u : ((1u << (b - a)) - 1u)) << a;
+            }
+        }
+        if ((cov.w[0] & cov.w[1] & cov.w[2] & cov.w[3] & cov.w[4]) == ~0u) break;
+        c = e;
+    }
+    Row160 r[kRows];
+    object_rows(r, t);
+    constexpr uint8_t kPairs[16][2] = {{R_M0, R_P1}, {R_M0, R_P0}, {R_M1, R_P0}, {R_M1, R_P1}, {R_P0, R_PF},
+                                       {R_P0, R_BL}, {R_P1, R_PF}, {R_P1, R_BL}, {R_M0, R_PF}, {R_M0, R_BL},
+                                       {R_M1, R_PF}, {R_M1, R_BL}, {R_BL, R_PF}, {R_BL, R_BL}, {R_P0, R_P1},
+                                       {R_M0, R_M1}};
+#pragma unroll
+    for (uint32_t k = 0; k < 16; ++k) {
+        if (k == 13) continue;  // CXBLPF bit 6: no pair
+        uint32_t any = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < 5; ++i) any |= r[kPairs[k][0]].w[i] & r[kPairs[k][1]].w[i] & cov.w[i];
+        cx |= any ? 1u << k : 0u;
+    }
+    return cx;
+}
+
+// Write the pixels of frame-relative colour clocks [from, to) drawn with TIA
+// state t into a frame of T, where objects show or an HMOVE blank lies in the
+// frame.  With tan (soft frames), also the position sampler's tangents,
+// tan[o][pixel] for o = P0, P1, M0, M1, BL: the colour with object o one column
+// further right minus the colour drawn (0 where blanked) -- the derivative of a
+// triangular (bilinear) sampler over the object's column at zero sub-pixel
+// offset, taken from the right (Sec. "Hard and Soft Execution").
 template <typename T>
-__host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int32_t to, uint32_t col, uint32_t pf,
-                                                     uint32_t vb, int32_t ystart, uint32_t sub, uint32_t G) {
-    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
+__host__ __device__ __attribute__((noinline)) void render_span_objects(T *frame, int32_t from, int32_t to, const Tia t,
+                                                                       int32_t ystart, uint32_t sub, uint32_t G,
+                                                                       float *tan) {
+    const uint32_t mask = pf_mask20(t.pf), ctrl = t.pf >> 24;
+    const bool objs = objs_shown(t.ob);
+    Row160 r[kRows];
+    object_rows(r, t);
+    const int32_t hl = hmove_line(t.ob) - ystart;  // visible row of an HMOVE blank
     for_each_group(from, to, ystart, sub, G, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
-        const uint32_t c = (vb & 2u) ? 0u : ((col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
+        const bool blank = (t.vb & 2u) || (y == hl && g < 2);
+        uint32_t c4;
+        if (blank) c4 = 0u;
+        else if (!objs) c4 = ((t.col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu) * 0x01010101u;
+        else c4 = group_colours(r, t, (uint32_t)g);
+        T *row = frame + y * kScreenW;
+        for (int32_t x = xa; x < xb; ++x) row[x] = (T)((c4 >> (8 * (x - 4 * g))) & 0xFFu);
+        if (tan) {
+            for (uint32_t o = 0; o < 5; ++o) {
+                uint32_t m4 = c4;  // colours with object o one column further right
+                if (!blank && objs) {
+                    Row160 moved[kRows];
+#pragma unroll
+                    for (uint32_t q = 0; q < kRows; ++q) moved[q] = q == o ? row_shift1(r[q]) : r[q];
+                    m4 = group_colours(moved, t, (uint32_t)g);
+                }
+                float *tr = tan + (size_t)o * kPixels + y * kScreenW;
+                for (int32_t x = xa; x < xb; ++x) {
+                    const int32_t sh = 8 * (x - 4 * g);
+                    tr[x] = (float)((int32_t)((m4 >> sh) & 0xFFu) - (int32_t)((c4 >> sh) & 0xFFu));
+                }
+            }
+        }
+    });
+}
+
+// Write the pixels of [from, to) drawn with TIA state t into a frame of T (and
+// with tan the sampler's tangents, see render_span_objects).
+// Without the object paths (kObj false) objects are taken as not shown; the
+// HMOVE blank still blacks out its columns.
+template <bool kObj = true, typename T>
+__host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int32_t to, const Tia &t,
+                                                     int32_t ystart, uint32_t sub, uint32_t G,
+                                                     float *tan = nullptr) {
+    if constexpr (kObj) {
+        if (tan || hmove_line(t.ob) >= 0 || objs_shown(t.ob)) {
+            render_span_objects(frame, from, to, t, ystart, sub, G, tan);
+            return;
+        }
+    }
+    const uint32_t mask = pf_mask20(t.pf), ctrl = t.pf >> 24;
+    const int32_t hl = hmove_line(t.ob) - ystart;
+    for_each_group(from, to, ystart, sub, G, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+        const bool blank = (t.vb & 2u) || (!kObj && y == hl && g < 2);
+        const uint32_t c = blank ? 0u : ((t.col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
         T *row = frame + y * kScreenW;
         if (xb - xa == 4) {
             if constexpr (sizeof(T) == 1) {
@@ -328,12 +619,23 @@ __host__ __device__ __forceinline__ uint32_t write_class(uint32_t addr, uint32_t
 // ---------------------------------------------------------------------------
 // The machine
 // ---------------------------------------------------------------------------
-template <class Mem, class Hook>
+// kObj: the machine with the object paths (collision latching, object pixels).
+// Without them (the fast variant of the hard kernels) the object registers are
+// still kept, and obj_stop is raised once an object shows: from then on the
+// env's results are not the machine's, and the caller reruns the env with the
+// object paths from its starting state.
+template <class Mem, class Hook, bool kObj = true>
 struct Cpu {
+    static constexpr bool kObjects = kObj;
     uint32_t a, x, y, s, p, pc, bank, jam;
     uint32_t rn, rz;              // N = bit 7 of rn, Z = (low byte of rz == 0); p holds the other flags
     int32_t cyc;                  // frame-relative CPU cycle
     uint32_t col, pf, vb;         // colour registers, playfield + CTRLPF, VBLANK | VSYNC << 8
+    Objs ob;                      // TIA objects
+    uint32_t hm;                  // motion nibbles: HMP0 | HMP1 << 4 | HMM0 << 8 | HMM1 << 12 | HMBL << 16
+    uint32_t cx;                  // collision latches, bit k = pair k
+    int32_t cx_cc;                // frame-relative colour clock up to which cx is current
+    bool obj_stop;                // (without the object paths) an object showed
     int32_t tim_u, tim_read;
     uint32_t tim_shift;
     uint32_t swcha, inpt4, swchb;
@@ -385,8 +687,25 @@ struct Cpu {
     __host__ __device__ __forceinline__ uint32_t timint_at(int32_t t) const {
         return (t >= tim_u && tim_read < tim_u) ? 0x80u : 0u;
     }
-    __host__ __device__ __forceinline__ uint32_t tia_in(uint32_t addr) const {
+    __host__ __device__ __forceinline__ Tia tia() const { return Tia{col, pf, vb, ob}; }
+    // latch the collisions of the clocks before k
+    __host__ __device__ __forceinline__ void cx_upto(int32_t k) {
+        if constexpr (kObj) {
+            if (k > cx_cc) {
+                if (objs_shown(ob)) cx |= collide_span(tia(), cx_cc, k);
+                cx_cc = k;
+            }
+        } else if (k > cx_cc) {  // nothing shows, nothing collides
+            cx_cc = k;
+        }
+    }
+    // TIA read in cycle t: collision latches (registers 0..7), INPT4, INPT5
+    __host__ __device__ __forceinline__ uint32_t tia_in(uint32_t addr, int32_t t) {
         const uint32_t r = addr & 0xFu;
+        if (r < 8u) {
+            cx_upto(3 * t + 3);
+            return (((cx >> (2u * r)) & 1u) << 7) | (((cx >> (2u * r + 1u)) & 1u) << 6);
+        }
         return r == 0xCu ? inpt4 : (r == 0xDu ? 0x80u : 0u);
     }
     __host__ __device__ __forceinline__ uint32_t riot_in(uint32_t addr, int32_t t, bool fx) {
@@ -406,7 +725,7 @@ struct Cpu {
         addr &= 0x1FFFu;
         if (sc && (addr & 0x1F80u) == 0x1080u) return mem.sc_byte(addr & 0x7Fu);
         if (addr & 0x1000u) return mem.rom_byte(cart_off(addr));
-        if (!(addr & 0x80u)) return tia_in(addr);
+        if (!(addr & 0x80u)) return tia_in(addr, t);
         if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
         return riot_in(addr, t, false);
     }
@@ -425,20 +744,17 @@ struct Cpu {
             hotspot(addr);
             return mem.rom_byte(cart_off(addr));
         }
-        if (!(addr & 0x80u)) return tia_in(addr);
+        if (!(addr & 0x80u)) return tia_in(addr, t);
         if (!(addr & 0x200u)) return mem.ram_byte(addr & 0x7Fu);
         return riot_in(addr, t, true);
     }
     // Page 0 and the stack page decode alike (A12 = A9 = 0): TIA below $80,
     // RAM from $80.  These are read/write for such addresses (zero-page modes,
-    // zero-page pointers, the stack at $100 | s), with the page bits dropped.
-    __host__ __device__ __forceinline__ uint32_t read_zp(uint32_t a8) {
-        if constexpr (Mem::kRelax) {  // a relaxed RAM read happens only for a RAM address
-            return (a8 & 0x80u) ? mem.ram_byte(a8 & 0x7Fu) : tia_in(a8);
-        } else {
-            const uint32_t r = mem.ram_byte(a8 & 0x7Fu), t = tia_in(a8);  // both, then select: no branch
-            return (a8 & 0x80u) ? r : t;
-        }
+    // zero-page pointers, the stack at $100 | s), with the page bits dropped;
+    // t is the cycle of the read.
+    __host__ __device__ __forceinline__ uint32_t read_zp(uint32_t a8, int32_t t) {
+        if (a8 & 0x80u) return mem.ram_byte(a8 & 0x7Fu);
+        return tia_in(a8, t);
     }
     __host__ __device__ __forceinline__ void write_zp(uint32_t a8, uint32_t v, int32_t w) {
         if (a8 & 0x80u) mem.ram_set(a8 & 0x7Fu, v);
@@ -459,26 +775,98 @@ struct Cpu {
         }
         return (!(addr & 4u) && !(addr & 3u)) ? kClsSwcha : kClsConst;
     }
+    // a write in cycle w to a register that changes what objects or the playfield
+    // show: pixels and collisions before its effect clock keep the old state
+    __host__ __device__ __forceinline__ void before_object_write(int32_t w) {
+        hook.before_pixel_write(*this, w);
+        cx_upto(3 * (w + 1));
+    }
+    __host__ __device__ __forceinline__ void set_ctl(uint32_t flag, bool on) { ob.ctl = on ? (ob.ctl | flag) : (ob.ctl & ~flag); }
+    __host__ __device__ __forceinline__ void set_pos(uint32_t o, uint32_t c) {  // o = 0..3: P0, P1, M0, M1
+        ob.pos = (ob.pos & ~(0xFFu << (8u * o))) | (c << (8u * o));
+    }
     __host__ __device__ __forceinline__ void tia_out(uint32_t reg, uint32_t v, int32_t w) {
+        // registers that change what objects or the playfield show: NUSIZ0/1,
+        // CTRLPF, REFP0/1, PF0-2, the strobes, GRP0/1, ENAM0/1, ENABL, VDELP0/1,
+        // VDELBL, RESMP0/1, HMOVE
+        constexpr uint64_t kObjRegs = (3ull << 0x04) | (7ull << 0x0A) | (7ull << 0x0D) | (0x1Full << 0x10) |
+                                      (0x1Full << 0x1B) | (0x1Full << 0x25) | (1ull << 0x2A);
+        const bool obj_reg = (kObjRegs >> reg) & 1u;
+        if (obj_reg) before_object_write(w);
         switch (reg) {
             case 0x00: vb = (vb & 0xFFu) | (v << 8); break;
             case 0x01: hook.before_pixel_write(*this, w); vb = (vb & 0xFF00u) | v; break;
             case 0x02: wsync = 1; break;
+            case 0x04: case 0x05: {  // NUSIZ0/1
+                const uint32_t sh = (reg - 4u) * 8u;
+                ob.ctl = (ob.ctl & ~(0xFFu << sh)) | (v << sh);
+                break;
+            }
             case 0x06: case 0x07: case 0x08: case 0x09: {
                 hook.before_pixel_write(*this, w);
                 const uint32_t sh = (reg - 6u) * 8u;
                 col = (col & ~(0xFFu << sh)) | (v << sh);
                 break;
             }
-            case 0x0A: hook.before_pixel_write(*this, w); pf = (pf & 0x00FFFFFFu) | (v << 24); break;
+            case 0x0A: pf = (pf & 0x00FFFFFFu) | (v << 24); break;
+            case 0x0B: set_ctl(kObRefp0, v & 8u); break;
+            case 0x0C: set_ctl(kObRefp1, v & 8u); break;
             case 0x0D: case 0x0E: case 0x0F: {
-                hook.before_pixel_write(*this, w);
                 const uint32_t sh = (reg - 0x0Du) * 8u;
                 pf = (pf & ~(0xFFu << sh)) | (v << sh);
                 break;
             }
-            default: break;  // sprites, audio, motion: outside this subset
+            case 0x10: case 0x11: set_pos(reg - 0x10u, strobe_column(3 * (w + 1), 5u)); break;
+            case 0x12: case 0x13: set_pos(reg - 0x10u, strobe_column(3 * (w + 1), 4u)); break;
+            case 0x14: ob.bl = (ob.bl & ~0xFFu) | strobe_column(3 * (w + 1), 4u); break;
+            case 0x1B:  // GRP0; GRP1's old register takes GRP1
+                ob.gfx = (ob.gfx & 0x00FFFF00u) | v | ((ob.gfx & 0xFF00u) << 16);
+                break;
+            case 0x1C:  // GRP1; GRP0's and ENABL's old registers take theirs
+                ob.gfx = (ob.gfx & 0xFF0000FFu) | (v << 8) | ((ob.gfx & 0xFFu) << 16);
+                set_ctl(kObEnablOld, ob.ctl & kObEnabl);
+                break;
+            case 0x1D: set_ctl(kObEnam0, v & 2u); break;
+            case 0x1E: set_ctl(kObEnam1, v & 2u); break;
+            case 0x1F: set_ctl(kObEnabl, v & 2u); break;
+            case 0x20: case 0x21: case 0x22: case 0x23: case 0x24: {  // HMP0 .. HMBL: no effect until HMOVE
+                const uint32_t sh = (reg - 0x20u) * 4u;
+                hm = (hm & ~(0xFu << sh)) | ((v >> 4) << sh);
+                break;
+            }
+            case 0x25: set_ctl(kObVdelp0, v & 1u); break;
+            case 0x26: set_ctl(kObVdelp1, v & 1u); break;
+            case 0x27: set_ctl(kObVdelbl, v & 1u); break;
+            case 0x28: case 0x29: {  // RESMP0/1: on release the missile moves to its player's centre
+                const uint32_t i = reg - 0x28u, flag = i ? kObResmp1 : kObResmp0;
+                if ((ob.ctl & flag) && !(v & 2u)) {
+                    const uint32_t p = (ob.pos >> (8u * i)) & 0xFFu;
+                    set_pos(2u + i, wrap160(p + (4u << player_shift(ob.ctl >> (8u * i)))));
+                }
+                set_ctl(flag, v & 2u);
+                break;
+            }
+            case 0x2A: {  // HMOVE
+                uint32_t np = 0;
+#pragma unroll
+                for (uint32_t o = 0; o < 5; ++o) {
+                    const int32_t m = (int32_t)(hm << (28u - 4u * o)) >> 28;  // signed nibble
+                    const uint32_t c = o < 4 ? (ob.pos >> (8u * o)) & 0xFFu : ob.bl & 0xFFu;
+                    uint32_t q = (uint32_t)((int32_t)c + 160 - m);  // 153..327
+                    q = q >= 320u ? q - 320u : q >= 160u ? q - 160u : q;
+                    if (o < 4) np |= q << (8u * o);
+                    else ob.bl = (ob.bl & ~0xFFu) | q;
+                }
+                ob.pos = np;
+                const int32_t cc = 3 * (w + 1);
+                if (cc % kClocksPerLine < kHBlank) ob.bl = (ob.bl & 0xFFu) | ((uint32_t)(cc / kClocksPerLine + 1) << 8);
+                break;
+            }
+            case 0x2B: hm = 0; break;  // HMCLR
+            case 0x2C: cx_upto(3 * (w + 1)); cx = 0; break;  // CXCLR
+            default: break;  // audio, RSYNC and the unused addresses
         }
+        if constexpr (!kObj) obj_stop = obj_stop || (obj_reg && objs_shown(ob));
     }
     // data write in cycle w
     __host__ __device__ __forceinline__ void write(uint32_t addr, uint32_t v, int32_t w) {
@@ -510,9 +898,9 @@ struct Cpu {
         write_zp(s, v, w);
         s = (s - 1u) & 0xFFu;
     }
-    __host__ __device__ __forceinline__ uint32_t pull() {
+    __host__ __device__ __forceinline__ uint32_t pull(int32_t t) {
         s = (s + 1u) & 0xFFu;
-        return read_zp(s);
+        return read_zp(s, t);
     }
 
     // NMOS ADC, binary and decimal (decimal: B. Clark, "Decimal Mode", App. A).
@@ -628,11 +1016,11 @@ struct Cpu {
                 }
                 case M_IZX: {
                     const uint32_t z = (lo + x) & 0xFFu;
-                    ea = read_zp(z) | (read_zp((z + 1u) & 0xFFu) << 8);
+                    ea = read_zp(z, t0) | (read_zp((z + 1u) & 0xFFu, t0) << 8);
                     break;
                 }
                 case M_IZY: {
-                    const uint32_t base = read_zp(lo) | (read_zp((lo + 1u) & 0xFFu) << 8);
+                    const uint32_t base = read_zp(lo, t0) | (read_zp((lo + 1u) & 0xFFu, t0) << 8);
                     ea = (base + y) & 0xFFFFu;
                     if ((d >> 13) & 1u) n += ((base ^ ea) >> 8) != 0u ? 1 : 0;
                     break;
@@ -646,7 +1034,7 @@ struct Cpu {
             // ---- read (a read-modify-write reads three cycles before its end)
             uint32_t v = lo;
             if (rd) {
-                if (zpt) v = read_zp(ea);
+                if (zpt) v = read_zp(ea, rmw ? t0 + n - 3 : tl);
                 else v = read(ea, rmw ? t0 + n - 3 : tl);
             }
             if constexpr (R) {
@@ -784,8 +1172,8 @@ struct Cpu {
                 break;
             }
             case C_RTS: {
-                const uint32_t l = pull();
-                const uint32_t h = pull();
+                const uint32_t l = pull(tl);
+                const uint32_t h = pull(tl);
                 pc = (((h << 8) | l) + 1u) & 0xFFFFu;
                 break;
             }
@@ -799,9 +1187,9 @@ struct Cpu {
                 break;
             }
             default: {  // RTI
-                set_flags((pull() & ~kFlagB) | kFlagU);
-                const uint32_t l = pull();
-                const uint32_t h = pull();
+                set_flags((pull(tl) & ~kFlagB) | kFlagU);
+                const uint32_t l = pull(tl);
+                const uint32_t h = pull(tl);
                 pc = (h << 8) | l;
                 break;
             }
@@ -820,6 +1208,10 @@ struct Cpu {
         jam = 0;
         cyc = 0;
         col = pf = vb = 0;
+        ob = Objs{0u, 0u, 0u, 0u};
+        hm = cx = 0;
+        cx_cc = 0;
+        obj_stop = false;
         tim_u = 0;
         tim_read = 0;
         tim_shift = 10;
@@ -831,6 +1223,10 @@ struct Cpu {
     // underflowed timers are renormalised by multiples of 256 cycles, which
     // changes no observable value.
     __host__ __device__ __forceinline__ void next_frame() {
+        cx_upto(3 * cyc);  // the frame's remaining collisions (and those of cycles past its end)
+        cx_cc -= kClocksPerFrame;
+        const int32_t hl = hmove_line(ob) - kLinesPerFrame;
+        ob.bl = (ob.bl & 0xFFu) | (hl >= 0 ? (uint32_t)(hl + 1) << 8 : 0u);
         cyc -= kCyclesPerFrame;
         tim_u -= kCyclesPerFrame;
         tim_read -= kCyclesPerFrame;
@@ -847,6 +1243,9 @@ struct Cpu {
         slices = r.slices;
         cyc = r.cyc; col = r.col; pf = r.pf; vb = r.vblank | ((uint32_t)r.vsync << 8);
         tim_u = r.tim_u; tim_read = r.tim_read; tim_shift = r.tim_shift; wsync = 0;
+        ob = Objs{r.ob_pos, r.ob_gfx, r.ob_ctl, r.ob_bl};
+        hm = r.ob_hm; cx = r.cx; cx_cc = r.cx_cc;
+        obj_stop = !kObj && objs_shown(ob);
     }
     __host__ __device__ __forceinline__ void store(StateRec &r) const {
         r.magic = kMagic;
@@ -854,8 +1253,35 @@ struct Cpu {
         r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u); r.slices = (uint16_t)slices;
         r.cyc = cyc; r.col = col; r.pf = pf; r.vblank = (uint8_t)(vb & 0xFFu); r.vsync = (uint8_t)(vb >> 8);
         r.tim_u = tim_u; r.tim_read = tim_read; r.tim_shift = (uint8_t)tim_shift;
+        r.ob_pos = ob.pos; r.ob_gfx = ob.gfx; r.ob_ctl = ob.ctl; r.ob_bl = ob.bl;
+        r.ob_hm = hm; r.cx = cx; r.cx_cc = cx_cc;
     }
 };
+
+// The object registers of a state record in the vcs_read_objects layout.
+__host__ __device__ __forceinline__ void objects32(const StateRec &r, uint8_t o[32]) {
+    const uint32_t c = r.ob_ctl;
+    for (int i = 0; i < 4; ++i) o[i] = (uint8_t)(r.ob_pos >> (8 * i));
+    o[4] = (uint8_t)r.ob_bl;
+    for (int i = 0; i < 4; ++i) o[5 + i] = (uint8_t)(r.ob_gfx >> (8 * i));
+    o[9] = (c & kObEnam0) ? 2 : 0;
+    o[10] = (c & kObEnam1) ? 2 : 0;
+    o[11] = (c & kObEnabl) ? 2 : 0;
+    o[12] = (c & kObEnablOld) ? 2 : 0;
+    o[13] = (uint8_t)c;
+    o[14] = (uint8_t)(c >> 8);
+    o[15] = (c & kObRefp0) ? 8 : 0;
+    o[16] = (c & kObRefp1) ? 8 : 0;
+    o[17] = (c & kObVdelp0) ? 1 : 0;
+    o[18] = (c & kObVdelp1) ? 1 : 0;
+    o[19] = (c & kObVdelbl) ? 1 : 0;
+    o[20] = (c & kObResmp0) ? 2 : 0;
+    o[21] = (c & kObResmp1) ? 2 : 0;
+    for (int i = 0; i < 5; ++i) o[22 + i] = (uint8_t)(((r.ob_hm >> (4 * i)) & 0xFu) << 4);
+    o[27] = (uint8_t)r.cx;
+    o[28] = (uint8_t)(r.cx >> 8);
+    o[29] = o[30] = o[31] = 0;
+}
 
 // ALE joystick action -> port values (SWCHA, INPT4).  Actions 0..17: NOOP FIRE
 // UP RIGHT LEFT DOWN UPRIGHT UPLEFT DOWNRIGHT DOWNLEFT UPFIRE RIGHTFIRE LEFTFIRE

@@ -8,7 +8,7 @@
 
 namespace vcs {
 
-__constant__ DecodeTable kDecodeDev = make_decode_table();
+static __constant__ DecodeTable kDecodeDev = make_decode_table();
 
 // ---------------------------------------------------------------------------
 // Wave policy of the device bodies
@@ -62,7 +62,7 @@ struct DeviceWave {
 // envs, G lanes per env; the ROM image (pre-decoded words), the decode table and
 // the envs' RAM staged in LDS.  state_of(rom) gives the executor state of the
 // workgroup's ROM.
-template <int G, int TPB, bool kSoft, class X, class StateOf>
+template <int G, int TPB, bool kSoft, class X, bool kObj = true, class StateOf>
 __device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds, uint32_t *dec_lds,
                                            StateOf state_of) {
     constexpr int E = TPB / G;
@@ -79,7 +79,7 @@ __device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, 
     LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
     // Superchip RAM: [32 words][E] in LDS after the staged image
     if (mapper_sc(mapper)) m.sc = reinterpret_cast<uint8_t *>(rom_lds + P.rom_words);
-    step_env<DeviceWave, G, kSoft, false, X>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
+    step_env<DeviceWave, G, kSoft, false, X, kObj>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
 }
 
 // Body of the FULL relaxed step kernel: the grouped kernel's layout with the

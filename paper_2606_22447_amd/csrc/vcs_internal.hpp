@@ -24,6 +24,11 @@ constexpr uint32_t kMagic = 0x31534356u;      // "VCS1"
 // length of an env's pixel-write log there (a run writes at most one pixel
 // register per instruction).
 constexpr int kTrMaxRun = 32;
+// Smallest pixel-write log of an env in translated code, in entries: room for
+// one run's writes on top of the entries one row can hold.
+constexpr int kTrLogCap = 2 * kTrMaxRun;
+// Bytes of one entry of that log (the effect clock and the TIA state before the write).
+constexpr int kTrLogEntryBytes = 16;
 
 // Cartridge formats (the numbering of vcs_mapper in include/vcs.h).
 constexpr int32_t kMapper2K = 0, kMapper4K = 1, kMapperF8 = 2, kMapperF6 = 3, kMapperF4 = 4, kMapperF8SC = 5,
@@ -67,7 +72,12 @@ struct alignas(16) StateRec {
     uint32_t from_tape;   // (checkpoint 0) 1: the RAM came from the soft tape at power-on; 0: a given state
     uint16_t slices;      // E0: the slice of each quarter of the cartridge window, 4 bits each
     uint16_t pad16;
-    uint32_t pad[14];
+    // TIA objects (layout of vcs::Objs) and collision latches
+    uint32_t ob_pos, ob_gfx, ob_ctl, ob_bl;
+    uint32_t ob_hm;       // motion registers' high nibbles: HMP0 | HMP1 << 4 | HMM0 << 8 | HMM1 << 12 | HMBL << 16
+    uint32_t cx;          // collision latches, bit k = pair k
+    int32_t cx_cc;        // frame-relative colour clock up to which the latches are current
+    uint32_t pad[7];
     uint8_t ram[128];
 };
 static_assert(sizeof(StateRec) == 256, "state record must be 256 bytes");
@@ -111,6 +121,7 @@ struct StepParams {
     uint8_t *frame_out;        // u8 frames (hard) or NULL
     float *ram_out_f;          // [B][S][128] f32 (soft) or NULL
     float *frame_out_f;        // [B][210][160] f32 (soft) or NULL
+    float *frame_dpos_f;       // [B][5][210][160] f32 position-sampler tangents of frame_out_f, or NULL
     uint8_t *done;             // [B][S] or NULL
     const uint32_t *ep_steps;  // [B][E] or NULL
     int32_t num_episodes;
@@ -122,6 +133,13 @@ struct StepParams {
     int32_t *ckpt_count;       // [B]
     int32_t ckpt_interval;
     int32_t max_ckpt;
+    // hard steps in two passes: the kernel without the object paths writes obj_flag[env]
+    // (1: an object showed, the env's results are void); the kernel with them then runs
+    // only the flagged envs (rerun != NULL) from their starting states state_src/sc_src
+    uint8_t *obj_flag;         // [B] or NULL
+    const uint8_t *rerun;      // [B] or NULL
+    const StateRec *state_src; // [B] starting states of a rerun, or NULL (state)
+    const uint8_t *sc_src;     // [B][128] Superchip RAM at the start of a rerun, or NULL (sc_state)
     // FULL relaxed mode (vcs_step_relaxed)
     float relax_u[9];          // e^{-k/T}, k = 0..8
     float relax_g_taken, relax_g_not;
@@ -130,10 +148,11 @@ struct StepParams {
 
 // One record of the soft backward's recompute tape (32 bytes).
 struct alignas(16) TapeRec {
-    uint32_t w0;  // opcode | rd_class << 8 | wr_class << 12 | kind << 16 | has_pix << 20 | op class << 24
+    uint32_t w0;  // opcode | rd_class << 8 | wr_class << 12 | kind << 16 | has_pix << 20 | index << 21 | op class << 24
     uint32_t w1;  // rd_idx | wr_idx << 16
     uint32_t w2;  // v1 | v2 << 8 | s_before << 16
-    uint32_t w3;  // env step of the instruction / marker
+    uint32_t w3;  // env step of the instruction / marker; with index != 0 (1: X, 2: Y) the address
+                  // surrogate's slope (float bits) of an indexed ROM or RAM read instead
     float pix[4]; // dL/dpixel summed per owning colour register (COLUP0, COLUP1, COLUPF, COLUBK)
 };
 
@@ -158,6 +177,7 @@ struct BwdParams {
     float *gport;                // [B][S][2]
     float *g_ram0;               // [B][128]
     int32_t *overflow;           // set nonzero if a segment needed more than max_rec records
+    float read_T;                // address surrogate's read temperature (0: addresses carry no gradient)
 };
 
 }  // namespace vcs

@@ -147,6 +147,7 @@ Profile profile(const Image &im, uint64_t seed) {
         c.set_cart(im.mapper);  // 2K, 4K or F8 (the formats the translator takes)
         c.mem = GlobalMem{im.img, ram, nullptr};
         c.hook.frame = nullptr;
+        c.hook.tan = nullptr;
         c.hook.rend_cc = c.hook.pix_cc = 0;
         c.hook.ystart = 34;
         c.hook.sub = 0;
@@ -425,7 +426,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "#define VCS_TR_TABLE __device__ const\n#endif\nnamespace vcs {\nnamespace tr {\n";
     {  // the env's pixel-write log: up to 256 entries, 64 KB of LDS per workgroup
         int log_cap = 256;
-        while (log_cap > kTrLogCap && (TPB / G) * log_cap * 16 > 65536) log_cap /= 2;
+        while (log_cap > kTrLogCap && (TPB / G) * log_cap * kTrLogEntryBytes > 65536) log_cap /= 2;
         char cbuf[64];
         std::snprintf(cbuf, sizeof cbuf, "constexpr int kLogCap = %d;\n", log_cap);
         s += cbuf;
@@ -540,7 +541,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
                   "    const uint16_t *src = vcs::tr::kTabAll + vcs::tr::kTabOff[rom];\n"
                   "    for (uint32_t i = threadIdx.x; i < vcs::tr::kTabBanks[rom] * 4096u; i += %d) tab_lds[i] = src[i];\n"
                   "  }\n"
-                  "  vcs::step_group<%d, %d, false, vcs::tr::Exec>(P, rom_lds, ram_lds, dec_lds,\n"
+                  "  vcs::step_group<%d, %d, false, vcs::tr::Exec, false>(P, rom_lds, ram_lds, dec_lds,\n"
                   "      [log](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log, tab_lds}; });\n}\n",
                   TPB, TPB / G, TPB / G, max_banks, G, TPB, G, TPB);
     s += buf;

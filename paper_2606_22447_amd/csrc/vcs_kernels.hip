@@ -1,17 +1,8 @@
 // HIP kernels of libvcs for gfx950 (MI355X).
 //
-//  k_step      hard env steps and the soft forward (paper Sec. "Hard and Soft
-//              Execution"; Theorem "Exact forward equivalence": the soft forward
-//              runs the hard machine on the decoded leaves).
-//              PLAIN   = one env per thread, RAM/ROM in global memory, per-lane
-//                        opcode switch (the baseline kernel).
-//              GROUPED = ROM image and RAM staged in LDS, opcode dispatch made
-//                        wave-uniform by a waterfall over the distinct opcodes
-//                        of the wave (scalar decode), G lanes per env sharing
-//                        the pixel writeback.
-//  k_soft_bwd  surrogate backward: per env, segments from last to first are
-//              recomputed from their hard-state checkpoint into a tape, then
-//              swept in reverse with the straight-through rules.
+//  The step kernels (k_step, k_step_relaxed, k_soft_bwd) are in
+//  vcs_step_kernels.hpp and instantiated by vcs_step_hard.hip,
+//  vcs_step_soft.hip and vcs_step_relaxed.hip (compiled in parallel).
 //  k_decode_*  STE leaves: argmax bytes and softmax statistics (Eq. select).
 //  k_*_grad    epilogue: fixed-order reduction of per-env ROM partials and the
 //              softmax vector-Jacobian products.
@@ -19,70 +10,6 @@
 #include "vcs_kernels.hpp"
 
 namespace vcs {
-
-// ---------------------------------------------------------------------------
-// Step kernel (hard steps, soft forward): one workgroup per ROM group, G lanes
-// per env.
-// ---------------------------------------------------------------------------
-template <int G, int TPB, bool kSoft, bool kPlain>
-__global__ __launch_bounds__(TPB) void k_step(StepParams P) {
-    constexpr int E = TPB / G;
-    extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
-    __shared__ __align__(16) uint32_t ram_lds[kPlain ? 4 : 32 * E];
-    __shared__ uint32_t dec_lds[kPlain ? 1 : 256];
-    if constexpr (kPlain) {
-        const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
-        const int32_t blk = blockIdx.x;
-        const int32_t rom_idx = P.st.main_block_rom[blk];
-        const int32_t env = P.st.main_slot_env[blk * E + slot];
-        GlobalMem m{P.rom + P.st.rom_off[rom_idx], env >= 0 ? P.state[env].ram : nullptr,
-                    (env >= 0 && P.sc_state) ? P.sc_state + (size_t)env * 128 : nullptr};
-        step_env<DeviceWave, G, kSoft, kPlain>(P, env, sub, P.st.rom_mapper[rom_idx], m, kDecodeDev.e);
-    } else {
-        step_group<G, TPB, kSoft, InterpExec>(P, rom_lds, ram_lds, dec_lds, [](int32_t) { return InterpExec::State{}; });
-    }
-}
-
-// FULL relaxed hard steps (vcs_step_relaxed): the grouped layout with every ROM
-// and RAM read and every branch relaxed and cast (Table s-modes).
-template <int G, int TPB>
-__global__ __launch_bounds__(TPB) void k_step_relaxed(StepParams P) {
-    constexpr int E = TPB / G;
-    extern __shared__ __align__(16) uint2 rom_lds[];
-    __shared__ __align__(16) uint32_t ram_lds[32 * E];
-    __shared__ uint32_t dec_lds[256];
-    step_group_relaxed<G, TPB>(P, rom_lds, ram_lds, dec_lds);
-}
-
-// ---------------------------------------------------------------------------
-// Soft backward: one env per wave (all its lanes), kBwdSlots envs of one ROM
-// per workgroup sharing the pre-decoded ROM words in LDS.  The
-// recompute-and-reverse chain of an env is serial, so the envs are spread over
-// as many waves as possible to interleave their latency.
-// ---------------------------------------------------------------------------
-constexpr int kBwdTPB = kBwdSlots * 64;
-
-__global__ __launch_bounds__(kBwdTPB) void k_soft_bwd(BwdParams P) {
-    constexpr int E = kBwdSlots;
-    extern __shared__ __align__(16) uint2 rom_lds[];  // pre-decoded ROM words, sized to the largest image
-    __shared__ uint32_t dec_lds[256];
-    __shared__ __align__(16) uint32_t ram_lds[32 * E];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t slot = __builtin_amdgcn_readfirstlane(tid / 64);  // the wave's env slot (a scalar)
-    const int32_t blk = blockIdx.x;
-    const uint32_t nslots = (uint32_t)gridDim.x * E;
-    const uint32_t gslot = (uint32_t)blk * E + slot;
-    const int32_t rom_idx = P.st.bwd_block_rom[blk];
-    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
-    const int32_t mapper = P.st.rom_mapper[rom_idx];
-    for (int32_t i = (int32_t)tid; i < rom_size; i += kBwdTPB)
-        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
-    for (int32_t i = (int32_t)tid; i < 256; i += kBwdTPB) dec_lds[i] = kDecodeDev.e[i];
-    __syncthreads();
-    const int32_t env = P.st.bwd_slot_env[gslot];
-    LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
-    bwd_env<DeviceWave>(P, env, gslot, nslots, mapper, m, kDecodeDev.e);
-}
 
 // ---------------------------------------------------------------------------
 // Decode: STE leaves (argmax, lowest index on ties) and softmax statistics
@@ -355,6 +282,15 @@ __global__ __launch_bounds__(256) void k_read_regs(const StateRec *state, int32_
     for (int i = 0; i < 16; ++i) out[(size_t)env * 16 + i] = o[i];
 }
 
+// One thread per env: the object registers in the vcs_read_objects layout.
+__global__ __launch_bounds__(256) void k_read_objects(const StateRec *state, int32_t B, uint8_t *out) {
+    const int32_t env = blockIdx.x * 256 + threadIdx.x;
+    if (env >= B) return;
+    uint8_t o[32];
+    objects32(state[env], o);
+    for (int i = 0; i < 32; ++i) out[(size_t)env * 32 + i] = o[i];
+}
+
 // FNV-1a, 64-bit (Fowler, Noll, Vo): offset basis 14695981039346656037, prime 2^40 + 2^8 + 0xb3.
 __device__ __forceinline__ uint64_t fnv1a(uint64_t h, uint32_t byte) {
     return (h ^ (uint64_t)byte) * 0x100000001B3ull;
@@ -393,61 +329,6 @@ __global__ void k_fill_zero(uint32_t *p, int64_t n) {
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
-template <int G, int TPB, bool kSoft, bool kPlain>
-static hipError_t launch_step_t(const StepParams &P, int32_t blocks, size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL((k_step<G, TPB, kSoft, kPlain>), dim3(blocks), dim3(TPB), kPlain ? 0 : lds, stream, P);
-    return hipGetLastError();
-}
-
-hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
-                       size_t lds, hipStream_t stream) {
-    if (plain) {
-        if (soft || lanes != 1) return hipErrorInvalidValue;
-        return tpb == 64 ? launch_step_t<1, 64, false, true>(P, blocks, 0, stream)
-                         : launch_step_t<1, 256, false, true>(P, blocks, 0, stream);
-    }
-#define VCS_STEP_CASE(Gv, Tv)                                                                \
-    if (lanes == Gv && tpb == Tv)                                                            \
-        return soft ? launch_step_t<Gv, Tv, true, false>(P, blocks, lds, stream)             \
-                    : launch_step_t<Gv, Tv, false, false>(P, blocks, lds, stream);
-    VCS_STEP_CASE(1, 64)
-    VCS_STEP_CASE(1, 256)
-    VCS_STEP_CASE(4, 64)
-    VCS_STEP_CASE(4, 256)
-    VCS_STEP_CASE(16, 64)
-    VCS_STEP_CASE(16, 256)
-    VCS_STEP_CASE(64, 64)
-    VCS_STEP_CASE(64, 256)
-    VCS_STEP_CASE(64, 1024)
-#undef VCS_STEP_CASE
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
-                               hipStream_t stream) {
-#define VCS_RELAX_CASE(Gv, Tv)                                                                          \
-    if (lanes == Gv && tpb == Tv) {                                                                     \
-        hipLaunchKernelGGL((k_step_relaxed<Gv, Tv>), dim3(blocks), dim3(Tv), lds, stream, P);           \
-        return hipGetLastError();                                                                       \
-    }
-    VCS_RELAX_CASE(1, 64)
-    VCS_RELAX_CASE(1, 256)
-    VCS_RELAX_CASE(4, 64)
-    VCS_RELAX_CASE(4, 256)
-    VCS_RELAX_CASE(16, 64)
-    VCS_RELAX_CASE(16, 256)
-    VCS_RELAX_CASE(64, 64)
-    VCS_RELAX_CASE(64, 256)
-    VCS_RELAX_CASE(64, 1024)
-#undef VCS_RELAX_CASE
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream) {
-    hipLaunchKernelGGL(k_soft_bwd, dim3(blocks), dim3(kBwdTPB), (size_t)max_rom_size * sizeof(uint2), stream, P);
-    return hipGetLastError();
-}
-
 hipError_t launch_decode(const float *rom_logits, int64_t rom_rows, const float *tape, int64_t tape_rows,
                          const float *act_logits, int64_t act_rows, float tau, uint8_t *rom_hard, float *rom_stats,
                          uint8_t *ram0_hard, float *tape_ev, uint8_t *act_hard, float *act_stats, hipStream_t stream) {
@@ -480,6 +361,11 @@ hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const u
                         uint8_t *sc_state, hipStream_t stream) {
     hipLaunchKernelGGL(k_reset, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, mask, ram0, seed,
                        sc_state);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_objects(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream) {
+    hipLaunchKernelGGL(k_read_objects, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, state, B, out);
     return hipGetLastError();
 }
 

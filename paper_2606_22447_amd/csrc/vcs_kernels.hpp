@@ -6,8 +6,9 @@
 namespace vcs {
 
 // lds: bytes of dynamic LDS (the staged ROM image, then Superchip RAM)
+// objects: the hard kernels with the object paths (soft kernels always have them)
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
-                       size_t lds, hipStream_t stream);
+                       size_t lds, hipStream_t stream, bool objects = true);
 hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
                                hipStream_t stream);
 hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream);
@@ -23,6 +24,7 @@ hipError_t launch_epilogue(const float *rom_logits, const float *rom_stats, cons
 hipError_t launch_reset(StateRec *state, int32_t B, const uint8_t *mask, const uint8_t *ram0, uint64_t seed,
                         uint8_t *sc_state, hipStream_t stream);
 hipError_t launch_read_regs(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream);
+hipError_t launch_read_objects(const StateRec *state, int32_t B, uint8_t *out, hipStream_t stream);
 hipError_t launch_hash(const StateRec *state, int32_t B, const uint8_t *frame, int64_t frame_stride, uint64_t *out,
                        hipStream_t stream);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t stream);

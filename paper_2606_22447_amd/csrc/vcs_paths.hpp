@@ -197,24 +197,30 @@ struct RelaxMem : Base {
 // ---------------------------------------------------------------------------
 // Hooks
 // ---------------------------------------------------------------------------
-// Smallest pixel-write log of an env in translated code, in entries: room for
-// one run's writes on top of the entries one row can hold.
-constexpr int kTrLogCap = 2 * kTrMaxRun;
 
-// Renders the returned frame lazily: before every pixel-register write the
-// pixels up to the write's effect clock are drawn with the old state.  With a
-// wave policy W (translated code) a write only appends (effect clock, colour
-// registers, playfield, VBLANK: the state before it) to the env's log of CAP
-// entries in LDS, a store with no branch, and flush(), called between runs
-// where lanes may branch, draws the visible rows the log covers once it is
-// nearly full: the env's GL lanes share the rows out, each lane writing whole
-// rows, and the entries of the row not yet covered stay in the log.
+// One entry of an env's pixel-write log in translated code (which runs without
+// the object paths): the effect clock of a write, the colour registers, the
+// playfield + CTRLPF, and VBLANK | VSYNC << 8 | (HMOVE-blank line + 1) << 16,
+// all as before the write.
+__host__ __device__ __forceinline__ uint4 log_entry(int32_t clock, const Tia &t) {
+    return make_uint4((uint32_t)clock, t.col, t.pf, (t.vb & 0xFFFFu) | ((t.ob.bl >> 8) << 16));
+}
+
+// Renders the returned frame lazily: before every write that changes pixels
+// the pixels up to the write's effect clock are drawn with the old state.  With
+// a wave policy W (translated code) a write only appends (effect clock, the TIA
+// state before it) to the env's log of CAP entries in LDS, a store with no
+// branch, and flush(), called between runs where lanes may branch, draws the
+// visible rows the log covers once it is nearly full: the env's GL lanes share
+// the rows out, each lane writing whole rows, and the entries of the row not yet
+// covered stay in the log.
 struct NoWave {};
 template <typename T, class W = NoWave, int GL = 1, int CAP = kTrLogCap>
 struct RenderHook {
     static_assert(CAP >= kTrLogCap, "the log holds a row's writes and a run's");
     static constexpr bool kRecord = false;
     T *frame;         // frame being rendered, or nullptr
+    float *tan;       // (soft) the frame's position-sampler tangents [5][210][160], or nullptr
     int32_t rend_cc;  // frame-relative colour clock rendered up to
     int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
     int32_t ystart;
@@ -228,13 +234,14 @@ struct RenderHook {
             if (frame) {
                 const int32_t cc = 3 * (w + 1);
                 if (cc > rend_cc) {
-                    render_span(frame, rend_cc, cc, c.col, c.pf, c.vb, ystart, sub, G);
+                    render_span<C::kObjects>(frame, rend_cc, cc, c.tia(), ystart, sub, G, tan);
                     rend_cc = cc;
                 }
             }
         } else if (W::any(frame != nullptr)) {  // (wave-uniform) only while some lane draws
+            static_assert(!C::kObjects, "translated code runs without the object paths");
             const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
-            log[i] = make_uint4((uint32_t)(3 * (w + 1)), c.col, c.pf, c.vb);
+            log[i] = log_entry(3 * (w + 1), c.tia());
             ++nlog;
         }
     }
@@ -250,6 +257,7 @@ struct RenderHook {
         const int32_t vis0 = ystart * kClocksPerLine + kHBlank;  // clock of pixel (0, 0)
         for (int32_t y = row_lo + (int32_t)sub; y < y_hi; y += GL) {
             const int32_t k_row = vis0 + y * kClocksPerLine;
+            const int32_t line1 = ystart + y + 1;  // the row's line + 1, as entries store an HMOVE blank
             uint32_t lo = 0, hi = n - 1u;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -266,7 +274,8 @@ struct RenderHook {
                 }
             };
             auto colour = [&](uint32_t g) {
-                return (e.w & 2u) ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
+                const bool blank = (e.w & 2u) || (g < 2u && (int32_t)(e.w >> 16) == line1);
+                return blank ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
             };
             T *row = frame + y * kScreenW;
             for (int32_t q = 0; q < kScreenW / 16; ++q) {
@@ -341,12 +350,12 @@ struct RenderHook {
     template <class C>
     __host__ __device__ __forceinline__ void finish_frame(C &c) {
         if constexpr (std::is_same<W, NoWave>::value) {
-            if (frame) render_span(frame, rend_cc, kClocksPerFrame, c.col, c.pf, c.vb, ystart, sub, G);
+            if (frame) render_span<C::kObjects>(frame, rend_cc, kClocksPerFrame, c.tia(), ystart, sub, G, tan);
         } else {
             if (W::any(frame != nullptr)) {  // the rest of the frame with the current state
                 flush(c);
                 const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
-                log[i] = make_uint4((uint32_t)kClocksPerFrame, c.col, c.pf, c.vb);
+                log[i] = log_entry(kClocksPerFrame, c.tia());
                 nlog = i + 1u;
                 flush(c, true);
             }
@@ -356,27 +365,64 @@ struct RenderHook {
     }
 };
 
-// Per-owner sums of dL/dpixel over [from, to) by the lanes of a wave (the soft
-// backward runs one env per wave): lane l takes every kWidth-th 4-pixel group of
-// each line, then the wave sums the four partial sums.  Returns (the same in
-// every lane) whether any visible pixel lies in the span.
+// Per-lane partial sums of dL/dpixel by owner over the groups lane `lane` of
+// `width` takes in [from, to), where objects show or an HMOVE blank falls.
+struct PixelParts {
+    float p[4];
+    bool any;
+};
+__host__ __device__ inline __attribute__((noinline)) PixelParts pixel_parts_objects(const float *gframe, int32_t from,
+                                                                            int32_t to, const Tia t, int32_t ystart,
+                                                                            uint32_t lane, uint32_t width) {
+    PixelParts out{{0.f, 0.f, 0.f, 0.f}, false};
+    const uint32_t mask = pf_mask20(t.pf), ctrl = t.pf >> 24;
+    const bool objs = objs_shown(t.ob);
+    Row160 r[kRows];
+    object_rows(r, t);
+    const int32_t hl = hmove_line(t.ob) - ystart;
+    for_each_group(from, to, ystart, lane, width, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+        out.any = true;
+        if (y == hl && g < 2) return;  // blanked: constant pixels
+        const float *row = gframe + y * kScreenW;
+        uint32_t nib[kRows];
+        group_occupancy(r, (uint32_t)g, nib);
+        for (int32_t x = xa; x < xb; ++x) {
+            const uint32_t o = objs ? pixel_owner(nib, (uint32_t)(x - 4 * g), (uint32_t)x, ctrl)
+                                    : group_owner((uint32_t)g, mask, ctrl);
+            for (uint32_t k = 0; k < 4; ++k) out.p[k] += o == k ? row[x] : 0.f;
+        }
+    });
+    return out;
+}
+
+// Per-owner sums of dL/dpixel over [from, to) drawn with state t by the lanes
+// of a wave (the soft backward runs one env per wave): lane l takes every
+// kWidth-th 4-pixel group of each line, then the wave sums the four partial
+// sums.  Returns (the same in every lane) whether any visible pixel lies in the
+// span.  Blanked pixels are constants and take no gradient.
 template <class W>
-__host__ __device__ __forceinline__ bool pixel_sums_wave(const float *gframe, int32_t from, int32_t to, uint32_t pf,
-                                                         uint32_t vb, int32_t ystart, float sums[4]) {
-    if (vb & 2u) return false;  // blanked pixels are constants
+__host__ __device__ __forceinline__ bool pixel_sums_wave(const float *gframe, int32_t from, int32_t to, const Tia &t,
+                                                         int32_t ystart, float sums[4]) {
+    if (t.vb & 2u) return false;
     const int32_t vis0 = ystart * kClocksPerLine, vis1 = vis0 + kScreenH * kClocksPerLine;
     if (to <= vis0 || from >= vis1) return false;
-    const uint32_t mask = pf_mask20(pf), ctrl = pf >> 24;
     float part[4] = {0.f, 0.f, 0.f, 0.f};
     bool any = false;
-    for_each_group(from, to, ystart, W::lane(), W::kWidth, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
-        const float *row = gframe + y * kScreenW;
-        float acc = 0.f;
-        for (int32_t x = xa; x < xb; ++x) acc += row[x];
-        const uint32_t o = group_owner((uint32_t)g, mask, ctrl);
-        for (uint32_t k = 0; k < 4; ++k) part[k] += o == k ? acc : 0.f;  // constant indices: stays in registers
-        any = true;
-    });
+    if (hmove_line(t.ob) >= 0 || objs_shown(t.ob)) {
+        const PixelParts pp = pixel_parts_objects(gframe, from, to, t, ystart, W::lane(), W::kWidth);
+        for (uint32_t k = 0; k < 4; ++k) part[k] = pp.p[k];
+        any = pp.any;
+    } else {
+        const uint32_t mask = pf_mask20(t.pf), ctrl = t.pf >> 24;
+        for_each_group(from, to, ystart, W::lane(), W::kWidth, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
+            const float *row = gframe + y * kScreenW;
+            float acc = 0.f;
+            for (int32_t x = xa; x < xb; ++x) acc += row[x];
+            const uint32_t o = group_owner((uint32_t)g, mask, ctrl);
+            for (uint32_t k = 0; k < 4; ++k) part[k] += o == k ? acc : 0.f;  // constant indices: stays in registers
+            any = true;
+        });
+    }
     if (!W::any(any)) return false;
     for (uint32_t k = 0; k < 4; ++k) sums[k] += W::sum(part[k]);
     return true;
@@ -395,9 +441,11 @@ struct TapeHook {
     int32_t pix_cc;
     int32_t ystart;
     uint32_t step;
-    uint32_t save_pf, save_vb;
+    Tia save;             // the TIA state before the instruction
     int32_t *overflow;
     bool lead;            // the lane that stores
+    float read_T;         // address surrogate (0: off)
+    uint32_t rom_n;       // bytes of the image (the relaxed read's array bounds)
     __host__ __device__ __forceinline__ void emit(const TapeRec &r) {
         if (nrec < max_rec) {
             if (lead) tape[nrec] = r;
@@ -410,8 +458,7 @@ struct TapeHook {
     __host__ __device__ __forceinline__ void before_pixel_write(C &, int32_t) {}
     template <class C>
     __host__ __device__ __forceinline__ void before_exec(C &c) {
-        save_pf = c.pf;
-        save_vb = c.vb;
+        save = c.tia();
     }
     // Instructions whose reverse-sweep rule is the identity need no record unless
     // pixels are attributed to them: branches, flag changes, compares, BIT, NOPs,
@@ -422,17 +469,55 @@ struct TapeHook {
         (1ull << C_BIT) | (1ull << C_NOP) | (1ull << C_JMP) | (1ull << C_RTS) | (1ull << C_RTI) |
         (1ull << C_PLP) | (1ull << C_TXS);
     static constexpr uint64_t kStores = (1ull << C_STA) | (1ull << C_STX) | (1ull << C_STY) | (1ull << C_SAX);
+    // Slope of Eq. s-read (the distance-softmax read, window |j - a| <= 8 inside the
+    // array) at the hard address a, taken symmetrically with coefficients at hard
+    // values: (1/T) sum_j w_j sign(j - a) (R[j] - R[a]), w_j = exp(-|j - a|/T) / Z.
+    template <class Get>
+    __host__ __device__ __forceinline__ float read_slope(Get get, uint32_t a, uint32_t n) const {
+        const float ra = (float)get(a);
+        float z = 1.f, acc = 0.f;
+        for (uint32_t k = 1; k <= 8; ++k) {
+            const float w = expf(-(float)k / read_T);
+            if (a + k < n) {
+                acc += w * ((float)get(a + k) - ra);
+                z += w;
+            }
+            if (a >= k) {
+                acc -= w * ((float)get(a - k) - ra);
+                z += w;
+            }
+        }
+        return acc / (z * read_T);
+    }
     template <class C>
-    __host__ __device__ __forceinline__ void after_exec(C &, uint32_t opc, int32_t, int32_t wp, ExecInfo &info) {
+    __host__ __device__ __forceinline__ void after_exec(C &c, uint32_t opc, int32_t, int32_t wp, ExecInfo &info) {
         TapeRec r;
         r.w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16) | (info.op_cls << 24);
         r.w1 = info.rd_idx | (info.wr_idx << 16);
         r.w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
         r.w3 = step;
+        // address surrogate: an indexed load or ALU read of a ROM or RAM byte also passes
+        // gradient to its index register (read-modify-write forms do not)
+        constexpr uint64_t kIndexedReads = (1ull << C_LDA) | (1ull << C_LDX) | (1ull << C_LDY) | (1ull << C_LAX) |
+                                           (1ull << C_ADC) | (1ull << C_SBC) | (1ull << C_AND) | (1ull << C_ORA) |
+                                           (1ull << C_EOR);
+        if (read_T > 0.f && ((kIndexedReads >> info.op_cls) & 1u) &&
+            (info.rd_cls == kClsRom || info.rd_cls == kClsRam)) {
+            const uint32_t mode = (c.mem.dec[opc] >> 6) & 15u;
+            const uint32_t ik = (mode == M_ZPX || mode == M_ABX) ? 1u
+                              : (mode == M_ZPY || mode == M_ABY || mode == M_IZY) ? 2u : 0u;
+            if (ik) {
+                const float kappa = info.rd_cls == kClsRom
+                    ? read_slope([&](uint32_t i) { return c.mem.rom_byte(i); }, info.rd_idx, rom_n)
+                    : read_slope([&](uint32_t i) { return c.mem.ram_byte(i); }, info.rd_idx, 128u);
+                r.w0 |= ik << 21;
+                r.w3 = __builtin_bit_cast(uint32_t, kappa);
+            }
+        }
         r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
         bool keep = !(((kNoContent >> info.op_cls) & 1u) ||
                       (((kStores >> info.op_cls) & 1u) && info.wr_cls == kClsConst));
-        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save_pf, save_vb, ystart, r.pix)) {
+        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save, ystart, r.pix)) {
             r.w0 |= 1u << 20;
             keep = true;
         }
@@ -676,19 +761,22 @@ struct InterpExec {
 // empty asm statements, and the ROM image must already be staged in LDS by the
 // whole workgroup.
 // ---------------------------------------------------------------------------
-template <class W, int G, bool kSoft, bool kPlain, class X = InterpExec, class Mem>
+template <class W, int G, bool kSoft, bool kPlain, class X = InterpExec, bool kObj = true, class Mem>
 __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t env, uint32_t sub, int32_t mapper,
                                                   Mem mem, const uint32_t *decode,
                                                   typename X::State xs = typename X::State{}) {
     static_assert(!(kSoft && kPlain), "the soft forward uses the grouped kernel");
+    static_assert(kObj || !kSoft, "the soft forward runs with the object paths");
     using T = typename std::conditional<kSoft, float, uint8_t>::type;
-    const bool live = env >= 0;
+    // a rerun of flagged envs (P.rerun) leaves the others alone
+    const bool live = env >= 0 && (!P.rerun || P.rerun[env]);
     const int32_t S = P.steps, F = P.frame_skip;
 
-    Cpu<Mem, typename X::template Hook<T, W>> c;
+    Cpu<Mem, typename X::template Hook<T, W>, kObj> c;
     c.set_cart(mapper);
     c.mem = mem;
     c.hook.frame = nullptr;
+    c.hook.tan = nullptr;
     c.hook.rend_cc = 0;
     c.hook.pix_cc = 0;
     c.hook.ystart = P.ystart;
@@ -697,7 +785,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     // frame counts frames since power-on (hard) or since the call's start (soft;
     // frame0 then holds the starting state's count)
     uint32_t frame = 0, frame0 = 0, episode = 0, ep_step = 0;
-    const StateRec *src = kSoft ? P.state_in : P.state;
+    const StateRec *src = kSoft ? P.state_in : (P.state_src ? P.state_src : P.state);
+    const uint8_t *sc_src = P.sc_src ? P.sc_src : P.sc_state;
     if (live) {
         if (kSoft && !src) {  // soft forward: power-on with the decoded RAM
             const uint32_t *r0 = reinterpret_cast<const uint32_t *>(P.ram0 + (size_t)env * 128);
@@ -713,7 +802,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                 const uint32_t *rw = reinterpret_cast<const uint32_t *>(st.ram);
                 for (uint32_t w = sub; w < 32; w += G) c.mem.ram_word_set(w, rw[w]);
                 if (c.sc) {  // Superchip RAM, kept after the state records
-                    const uint32_t *sw = reinterpret_cast<const uint32_t *>(P.sc_state + (size_t)env * 128);
+                    const uint32_t *sw = reinterpret_cast<const uint32_t *>(sc_src + (size_t)env * 128);
                     for (uint32_t w = sub; w < 32; w += G) c.mem.sc_word_set(w, sw[w]);
                 }
             }
@@ -731,6 +820,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 
     int32_t s_idx = 0, fstep = 0;
     bool active = live && S > 0;
+    bool stopped = false;  // (without the object paths) the env's results are void
     auto set_ports = [&]() {
         const uint32_t act = P.actions ? P.actions[(size_t)env * S + s_idx] : 0u;
         action_ports(act, &c.swcha, &c.inpt4, &c.swchb);
@@ -740,7 +830,10 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         c.hook.frame = nullptr;
         const bool last_of_step = fstep == F - 1;
         if constexpr (kSoft) {
-            if (P.frame_out_f && last_of_step && s_idx == S - 1) c.hook.frame = P.frame_out_f + (size_t)env * kPixels;
+            if (P.frame_out_f && last_of_step && s_idx == S - 1) {
+                c.hook.frame = P.frame_out_f + (size_t)env * kPixels;
+                if (P.frame_dpos_f) c.hook.tan = P.frame_dpos_f + (size_t)env * 5 * kPixels;
+            }
         } else {
             if (P.frame_out && last_of_step) {
                 if (P.frames_mode == 2) c.hook.frame = P.frame_out + ((size_t)env * S + s_idx) * kPixels;
@@ -814,6 +907,13 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
             if (!W::any(run)) break;
         }
         if (!active) continue;
+        if constexpr (!kObj) {
+            if (c.obj_stop) {  // an object showed: this env is rerun with the object paths
+                stopped = true;
+                active = false;
+                continue;
+            }
+        }
         checkpoint();
         // ---- end of frame
         if (c.cyc < kCyclesPerFrame) c.cyc = kCyclesPerFrame;  // a jammed CPU lets the cycles elapse
@@ -873,9 +973,11 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         if (active) start_frame();
     }
 
-    if (live) {
+    if (live && P.obj_flag && sub == 0) P.obj_flag[env] = stopped ? 1u : 0u;
+    if (live && !stopped) {
         if (P.state) {
             StateRec &st = P.state[env];
+            c.cx_upto(3 * c.cyc);  // collision latches current at the end of the call
             if (sub == 0) {
                 c.store(st);
                 st.frame = frame0 + frame;
@@ -914,7 +1016,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 // lane per address: program order, deterministic).
 template <class W, class Mem>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
-                                                 int32_t mapper, Mem mem, const uint32_t *decode) {
+                                                 int32_t mapper, uint32_t rom_n, Mem mem, const uint32_t *decode) {
     constexpr uint32_t NW = W::kWidth;
     (void)decode;  // the tape records carry the opcode class
     const uint32_t lane = W::lane();
@@ -932,6 +1034,8 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     c.hook.ystart = P.ystart;
     c.hook.overflow = P.overflow;
     c.hook.lead = lead;
+    c.hook.read_T = P.read_T;
+    c.hook.rom_n = rom_n;
 
     float aA = 0.f, aX = 0.f, aY = 0.f;
     float aC[4] = {0.f, 0.f, 0.f, 0.f};
@@ -939,7 +1043,9 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     // segment i starts from checkpoint i (checkpoint 0: the forward's starting state)
     const int32_t nseg = live ? (P.ckpt_count[env] < P.max_ckpt ? P.ckpt_count[env] : P.max_ckpt) : 0;
 
+    float t_rd = 0.f;  // the adjoint the current record delivers to its read value
     auto add_src = [&](uint32_t cls, uint32_t idx, uint32_t step, float t) {
+        t_rd = t;
         switch (cls) {
             case kClsRam: adj.set(idx, adj.get(idx) + t); break;
             case kClsRom: if (lead) W::accumulate(&P.gpart[(size_t)idx * nslots + gslot], t); break;
@@ -991,6 +1097,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
         const float v1 = (float)(w2 & 0xFFu), v2 = (float)((w2 >> 8) & 0xFFu);
         const uint32_t sb = (w2 >> 16) & 0xFFu;
         const uint32_t cls = (w0 >> 24) & 63u;  // the opcode's class, recorded with it
+        t_rd = 0.f;
         switch (cls) {
             case C_LDA: { const float t = aA; aA = 0.f; add_src(rd, rd_idx, step, t); break; }
             case C_LDX: { const float t = aX; aX = 0.f; add_src(rd, rd_idx, step, t); break; }
@@ -1043,6 +1150,12 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             case C_BRK: zero_push(sb); zero_push(sb - 1u); zero_push(sb - 2u); break;
             default: break;  // flags, compares, branches, jumps, pulls into P/PC: no content
         }
+        const uint32_t ik = (w0 >> 21) & 3u;  // address surrogate: the index register's share
+        if (ik) {
+            const float dk = t_rd * __builtin_bit_cast(float, step);
+            aX += ik == 1u ? dk : 0.f;
+            aY += ik == 2u ? dk : 0.f;
+        }
         if (w0 & (1u << 20)) {  // pixels drawn before this instruction's write
             for (uint32_t k = 0; k < 4; ++k) aC[k] += pix(k);
         }
@@ -1094,7 +1207,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                     t.w1 = t.w2 = 0;
                     t.w3 = (uint32_t)s_idx;
                     t.pix[0] = t.pix[1] = t.pix[2] = t.pix[3] = 0.f;
-                    pixel_sums_wave<W>(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.pf, c.vb, c.hook.ystart, t.pix);
+                    pixel_sums_wave<W>(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.tia(), c.hook.ystart, t.pix);
                     c.hook.emit(t);
                 }
                 c.next_frame();

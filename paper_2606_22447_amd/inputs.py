@@ -1860,3 +1860,198 @@ def boot_actions(num_envs: int, seed: int, noops: int = 60, resets: int = 4, max
     a = np.zeros((num_envs, n), np.uint8)
     a[:, noops:noops + resets] = ACTION_RESET
     return a, extra.astype(np.int64)
+
+
+# --------------------------------------------------------------------------
+# Sprite workloads: game-like kernels that use the TIA's movable objects
+# --------------------------------------------------------------------------
+
+NUSIZ0, NUSIZ1, REFP0, REFP1 = 0x04, 0x05, 0x0B, 0x0C
+RESP0, RESP1, RESM0, RESM1, RESBL = 0x10, 0x11, 0x12, 0x13, 0x14
+GRP0, GRP1, ENAM0, ENAM1, ENABL = 0x1B, 0x1C, 0x1D, 0x1E, 0x1F
+HMP0, HMP1, HMM0, HMM1, HMBL = 0x20, 0x21, 0x22, 0x23, 0x24
+VDELP0, VDELP1, VDELBL, RESMP0, RESMP1 = 0x25, 0x26, 0x27, 0x28, 0x29
+HMOVE, HMCLR, CXCLR = 0x2A, 0x2B, 0x2C
+OBJ_X = 0x80          # RAM: columns of P0, P1, M0, M1, BL ($80-$84)
+OBJ_HITS = 0x85       # RAM: P0-P1 hit counter
+OBJ_CX = 0x86         # RAM: the eight collision registers copied each frame ($86-$8D)
+
+
+def generate_object_rom(seed: int, size: int = 4096) -> Rom:
+    """A seed-generated sprite kernel (2K or 4K image), laid out like a game frame:
+    VSYNC, a vertical blank that moves P0 with the joystick (REFP0 follows the
+    direction), positions all five objects from RAM with the divide-by-15 strobe
+    loop and fine motion (HMxx, HMOVE), then 192 lines that load GRP0/GRP1, the
+    missile and ball enables and PF1 from page-aligned tables, and an overscan
+    that copies the collision latches into RAM, counts P0-P1 hits and clears
+    them.  NUSIZ, vertical delay, CTRLPF (reflection, score, priority, ball
+    width), RESMP and the colours are drawn from the seed."""
+    assert size in (2048, 4096)
+    r = Rng(stream_key(seed, 0x4F424A))
+    base = 0xF000 if size == 4096 else 0xF800
+    b = Bank(size, base, bytes([0xEA]) * size)
+    # tables: 5 pages at the top (graphics 0, graphics 1, enables, playfield, colours)
+    tab = {}
+    npages = 5 if size == 4096 else 3
+    tb = byte_stream(stream_key(seed, 0x544F42), 256 * npages)
+    for i, name in enumerate(["gfx0", "gfx1", "en", "pf", "col"][:npages]):
+        off = size - 0x100 * (npages + 1) + 0x100 * i
+        b.at(off)
+        tab[name] = b.addr()
+        for y in range(256):
+            v = int(tb[256 * i + y])
+            if name.startswith("gfx"):
+                band = (y // 16) % 4  # sprites in bands of lines, blank between
+                v = v if band in (1, 2) else 0
+            elif name == "en":
+                v = v & 0x2A  # bits 1, 3, 5: missile 0, missile 1, ball after shifts
+            elif name == "pf":
+                v = v & 0x81
+            elif name == "col":
+                v = v & 0xFE
+            b.byte(v)
+    if npages == 3:
+        tab["pf"] = tab["en"]
+        tab["col"] = tab["gfx0"]
+    b.at(0)
+    b.label("RESET")
+    b.ins("SEI")
+    b.ins("CLD")
+    b.ins("LDX", "imm", 0xFF)
+    b.ins("TXS")
+    # static set-up from the seed
+    settings = [(NUSIZ0, r.randint(0, 7) | (r.randint(0, 3) << 4)), (NUSIZ1, r.randint(0, 7) | (r.randint(0, 3) << 4)),
+                (CTRLPF, r.randint(0, 7) | (r.randint(0, 3) << 4)), (VDELP0, r.randint(0, 1)),
+                (VDELP1, r.randint(0, 1)), (VDELBL, r.randint(0, 1)), (REFP1, 8 * r.randint(0, 1)),
+                (COLUP0, (r.randint(1, 127) * 2) & 0xFE), (COLUP1, (r.randint(1, 127) * 2) & 0xFE),
+                (COLUPF, (r.randint(1, 127) * 2) & 0xFE), (COLUBK, (r.randint(0, 127) * 2) & 0xFE)]
+    for reg, v in settings:
+        b.ins("LDA", "imm", v)
+        b.ins("STA", "zp", reg)
+    b.label("FRAME")
+    b.ins("LDA", "imm", 0x02)
+    b.ins("STA", "zp", VBLANK)
+    b.ins("STA", "zp", VSYNC)
+    for _ in range(3):
+        b.ins("STA", "zp", WSYNC)
+    b.ins("LDA", "imm", 0x00)
+    b.ins("STA", "zp", VSYNC)
+    # line 1: the joystick moves P0 (right: +1, left: -1, reflected while moving left)
+    b.ins("LDA", "abs", SWCHA)
+    b.ins("BMI", "rel", "NR")
+    b.ins("INC", "zp", OBJ_X)
+    b.ins("LDA", "imm", 0x00)
+    b.ins("STA", "zp", REFP0)
+    b.label("NR")
+    b.ins("LDA", "abs", SWCHA)
+    b.ins("AND", "imm", 0x40)
+    b.ins("BNE", "rel", "NL")
+    b.ins("DEC", "zp", OBJ_X)
+    b.ins("LDA", "imm", 0x08)
+    b.ins("STA", "zp", REFP0)
+    b.label("NL")
+    b.ins("STA", "zp", WSYNC)
+    # line 2: every object column kept in 0..151 (a wrapped one restarts at 8)
+    for k in range(5):
+        b.ins("LDA", "zp", OBJ_X + k)
+        b.ins("CMP", "imm", 152)
+        b.ins("BCC", "rel", f"C{k}")
+        b.ins("LDA", "imm", 8)
+        b.ins("STA", "zp", OBJ_X + k)
+        b.label(f"C{k}")
+    b.ins("STA", "zp", WSYNC)
+    # lines 3-7: coarse strobe by the divide-by-15 loop, fine motion into HMxx
+    used = 3
+    for k, (hmr, resr) in enumerate(((HMP0, RESP0), (HMP1, RESP1), (HMM0, RESM0), (HMM1, RESM1), (HMBL, RESBL))):
+        b.ins("STA", "zp", WSYNC)
+        b.ins("LDA", "zp", OBJ_X + k)
+        b.ins("SEC")
+        b.label(f"D{k}")
+        b.ins("SBC", "imm", 15)
+        b.ins("BCS", "rel", f"D{k}")
+        b.ins("EOR", "imm", 7)
+        for _ in range(4):
+            b.ins("ASL", "acc")
+        b.ins("STA", "zp", hmr)
+        b.ins("STA", "zp", resr)
+        used += 1
+    b.ins("STA", "zp", WSYNC)
+    b.ins("STA", "zp", HMOVE)   # in horizontal blank: columns 0..7 of this line go black
+    used += 1
+    if r.random() < 0.5:        # lock missile 1 to player 1's centre for a line
+        b.ins("LDA", "imm", 0x02)
+        b.ins("STA", "zp", RESMP1)
+        b.ins("STA", "zp", WSYNC)
+        b.ins("LDA", "imm", 0x00)
+        b.ins("STA", "zp", RESMP1)
+        used += 1
+    b.ins("STA", "zp", WSYNC)
+    b.ins("STA", "zp", HMCLR)
+    used += 1
+    b.ins("LDX", "imm", 37 - used)
+    b.label("VB")
+    b.ins("STA", "zp", WSYNC)
+    b.ins("DEX")
+    b.ins("BNE", "rel", "VB")
+    # kernel: 192 lines from the tables
+    b.ins("STA", "zp", WSYNC)
+    b.ins("LDA", "imm", 0x00)
+    b.ins("STA", "zp", VBLANK)
+    b.ins("LDY", "imm", 191)
+    b.label("KL")
+    b.ins("STA", "zp", WSYNC)
+    b.ins("LDA", "aby", tab["gfx0"])
+    b.ins("STA", "zp", GRP0)
+    b.ins("LDA", "aby", tab["gfx1"])
+    b.ins("STA", "zp", GRP1)
+    b.ins("LDA", "aby", tab["en"])
+    b.ins("STA", "zp", ENAM0)
+    b.ins("LSR", "acc")
+    b.ins("LSR", "acc")
+    b.ins("STA", "zp", ENAM1)
+    b.ins("LSR", "acc")
+    b.ins("LSR", "acc")
+    b.ins("STA", "zp", ENABL)
+    b.ins("LDA", "aby", tab["pf"])
+    b.ins("STA", "zp", PF1)
+    if r.random() < 0.5:
+        b.ins("LDA", "aby", tab["col"])
+        b.ins("STA", "zp", COLUP1)
+    b.ins("DEY")
+    b.ins("BNE", "rel", "KL")
+    # overscan: collisions into RAM, the P0-P1 hit count, clear
+    b.ins("STA", "zp", WSYNC)
+    b.ins("LDA", "imm", 0x02)
+    b.ins("STA", "zp", VBLANK)
+    b.ins("LDA", "imm", 0x00)
+    b.ins("STA", "zp", GRP0)
+    b.ins("STA", "zp", GRP1)
+    for k in range(8):
+        b.ins("LDA", "zp", k)
+        b.ins("STA", "zp", OBJ_CX + k)
+    b.ins("BIT", "zp", 0x07)      # CXPPMM bit 7: P0-P1
+    b.ins("BPL", "rel", "NH")
+    b.ins("INC", "zp", OBJ_HITS)
+    b.label("NH")
+    b.ins("STA", "zp", CXCLR)
+    b.ins("LDX", "imm", 29)
+    b.label("OS")
+    b.ins("STA", "zp", WSYNC)
+    b.ins("DEX")
+    b.ins("BNE", "rel", "OS")
+    b.ins("JMP", "abs", "FRAME")
+    b.at(size - 4)
+    b.byte(base & 0xFF, base >> 8, base & 0xFF, base >> 8)
+    b.link()
+    img = np.frombuffer(bytes(b.img), dtype=np.uint8).copy()
+    return Rom(seed, size, MAPPER_OF_SIZE[size], img, reads_inputs=True)
+
+
+def config_objects(envs_per_rom: int = 256, steps: int = 200, n_roms: int = 16, frame_skip: int = 4) -> Workload:
+    """Sprite workload: seed-generated object kernels (2K and 4K) x envs_per_rom,
+    random joystick actions (they move player 0), RAM and frames every step."""
+    roms = [generate_object_rom(7000 + i, 4096 if i % 4 else 2048) for i in range(n_roms)]
+    b = n_roms * envs_per_rom
+    env_rom = np.repeat(np.arange(n_roms, dtype=np.int32), envs_per_rom)
+    return Workload("objects", roms, env_rom, initial_ram(5, b), action_stream(5, b, steps), steps=steps,
+                    frame_skip=frame_skip, seed=5)

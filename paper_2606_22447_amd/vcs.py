@@ -212,6 +212,12 @@ class VcsBatch(_Ctx):
         Bd.check(Bd.lib().vcs_read_regs(self.h, Bd.ptr(self.state), Bd.ptr(out), _stream()), "vcs_read_regs")
         return out
 
+    def objects(self) -> torch.Tensor:
+        """uint8 [B][32]: the TIA object registers and collision latches (vcs_read_objects layout)."""
+        out = torch.empty((self.B, 32), dtype=torch.uint8, device=self.device)
+        Bd.check(Bd.lib().vcs_read_objects(self.h, Bd.ptr(self.state), Bd.ptr(out), _stream()), "vcs_read_objects")
+        return out
+
 
 class SoftVcs(_Ctx):
     """B consoles in SOFT-STE mode: differentiable w.r.t. ROM logits, RAM tape and action logits.
@@ -261,11 +267,13 @@ class SoftVcs(_Ctx):
         return S
 
     def forward(self, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0,
-                want_decode: bool = False, want_state: bool = False, state_in=None):
+                want_decode: bool = False, want_state: bool = False, state_in=None, frame_dpos=None):
         """Soft forward of S = action_logits.shape[1] env steps, from power-on with the
         tape's RAM or (state_in: a [B * 256] uint8 state, e.g. VcsBatch.state after hard
         steps) from that state, whose registers and RAM are then constants (ram_tape may
-        be None).  Returns (ram_out, frame, residual, decode stats or None, state or None)."""
+        be None).  frame_dpos: a float32 [B][5][210][160] tensor to receive the position
+        sampler's tangents of the final frame (P0, P1, M0, M1, BL), or None.  Returns
+        (ram_out, frame, residual, decode stats or None, state or None)."""
         S = self._check_leaves(rom_logits, ram_tape, action_logits, state_in)
         B, dev = self.B, self.device
         ram_out = torch.empty((B, S, 128), dtype=torch.float32, device=dev)
@@ -275,19 +283,23 @@ class SoftVcs(_Ctx):
         if want_decode:
             dec = torch.empty(Bd.size_query("vcs_decode_bytes", self.h, S) // 4, dtype=torch.float32, device=dev)
         st = torch.empty(B * Bd.STATE_BYTES, dtype=torch.uint8, device=dev) if want_state else None
+        if frame_dpos is not None:
+            self._check(frame_dpos, (B, 5, 210, 160), "frame_dpos")
         work = self.workspace(Bd.VCS_OP_SOFT_FWD, S)
         rc = Bd.lib().vcs_step_soft_fwd(self.h, Bd.ptr(state_in), Bd.ptr(rom_logits), Bd.ptr(ram_tape),
                                         Bd.ptr(action_logits), float(tau), float(alpha), S, Bd.ptr(ram_out),
-                                        Bd.ptr(frame), Bd.ptr(dec), Bd.ptr(st), Bd.ptr(residual), Bd.ptr(work),
-                                        _stream())
+                                        Bd.ptr(frame), Bd.ptr(frame_dpos), Bd.ptr(dec), Bd.ptr(st),
+                                        Bd.ptr(residual), Bd.ptr(work), _stream())
         Bd.check(rc, "vcs_step_soft_fwd")
         return ram_out, frame, residual, dec, st
 
     def backward(self, residual, rom_logits, ram_tape, action_logits, tau: float, alpha: float, grad_frame,
-                 grad_ram_out=None, check_overflow: bool = False):
+                 grad_ram_out=None, check_overflow: bool = False, read_T: float = 0.0):
         """Surrogate gradients (rom_logits, ram_tape, action_logits) of the forward whose
         residual is given; the RAM-tape gradient is None when ram_tape is None (a forward
-        from a given state, where it would be zero)."""
+        from a given state, where it would be zero).  read_T > 0 adds the address
+        surrogate (indexed reads pass gradient to their index register, Eq. s-read at
+        that temperature)."""
         S = action_logits.shape[1] if torch.is_tensor(action_logits) and action_logits.dim() == 3 else -1
         self._check(rom_logits, (sum(self.rom_sizes), 256), "rom_logits")
         if ram_tape is not None:
@@ -302,7 +314,8 @@ class SoftVcs(_Ctx):
         g_act = torch.empty_like(action_logits)
         work = self.workspace(Bd.VCS_OP_SOFT_BWD, S)
         rc = Bd.lib().vcs_step_soft_bwd(self.h, Bd.ptr(residual), Bd.ptr(rom_logits), Bd.ptr(ram_tape),
-                                        Bd.ptr(action_logits), float(tau), float(alpha), S, Bd.ptr(grad_frame),
+                                        Bd.ptr(action_logits), float(tau), float(alpha), float(read_T), S,
+                                        Bd.ptr(grad_frame),
                                         Bd.ptr(grad_ram_out), Bd.ptr(g_rom), Bd.ptr(g_tape), Bd.ptr(g_act),
                                         Bd.ptr(work), _stream())
         Bd.check(rc, "vcs_step_soft_bwd")
@@ -327,14 +340,15 @@ class VcsSoftFunction(torch.autograd.Function):
     surrogate adjoint (recompute from hard-state checkpoints, reverse sweep)."""
 
     @staticmethod
-    def forward(ctx, rom_logits, ram_tape, action_logits, sim: SoftVcs, tau: float, alpha: float, state_in=None):
+    def forward(ctx, rom_logits, ram_tape, action_logits, sim: SoftVcs, tau: float, alpha: float, state_in=None,
+                read_T: float = 0.0):
         rom_logits = rom_logits.contiguous()
         ram_tape = None if ram_tape is None else ram_tape.contiguous()
         action_logits = action_logits.contiguous()
         ram_out, frame, residual, _, _ = sim.forward(rom_logits, ram_tape, action_logits, tau, alpha,
                                                      state_in=state_in)
         ctx.save_for_backward(rom_logits, ram_tape, action_logits, residual)
-        ctx.sim, ctx.tau, ctx.alpha = sim, tau, alpha
+        ctx.sim, ctx.tau, ctx.alpha, ctx.read_T = sim, tau, alpha, read_T
         return ram_out, frame
 
     @staticmethod
@@ -345,14 +359,17 @@ class VcsSoftFunction(torch.autograd.Function):
             g_frame = torch.zeros((sim.B, 210, 160), dtype=torch.float32, device=sim.device)
         g_rom, g_tape, g_act = sim.backward(residual, rom_logits, ram_tape, action_logits, ctx.tau, ctx.alpha,
                                             g_frame.float().contiguous(),
-                                            None if g_ram is None else g_ram.float().contiguous())
-        return g_rom, g_tape, g_act, None, None, None, None
+                                            None if g_ram is None else g_ram.float().contiguous(),
+                                            read_T=ctx.read_T)
+        return g_rom, g_tape, g_act, None, None, None, None, None
 
 
-def soft_rollout(sim: SoftVcs, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0, state_in=None):
+def soft_rollout(sim: SoftVcs, rom_logits, ram_tape, action_logits, tau: float, alpha: float = 6.0, state_in=None,
+                 read_T: float = 0.0):
     """Differentiable rollout (ram_out, final frame); from power-on with the tape's RAM, or
-    from state_in (then ram_tape may be None and gets no gradient)."""
-    return VcsSoftFunction.apply(rom_logits, ram_tape, action_logits, sim, tau, alpha, state_in)
+    from state_in (then ram_tape may be None and gets no gradient).  read_T > 0: the
+    backward adds the address surrogate."""
+    return VcsSoftFunction.apply(rom_logits, ram_tape, action_logits, sim, tau, alpha, state_in, read_T)
 
 
 def ste_luminance(frame: torch.Tensor) -> torch.Tensor:

@@ -36,7 +36,7 @@ constexpr DecodeTable kHostDecode = make_decode_table();
 extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0,
                            const uint8_t *actions, int S, int F, const uint32_t *ep_steps, int num_eps,
                            unsigned long long seed, uint8_t *ram_out, uint8_t *frame_out, uint8_t *done,
-                           uint8_t *regs) {
+                           uint8_t *regs, uint8_t *objs) {
     StateRec st{};
     st.status = 2;
     st.tim_shift = 10;
@@ -81,6 +81,42 @@ extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapp
     regs[10] = (uint8_t)((t >= st.tim_u && st.tim_read < st.tim_u) ? 0x80 : 0);
     regs[11] = st.vblank;
     for (int i = 0; i < 4; ++i) regs[12 + i] = (uint8_t)(st.col >> (8 * i));
+    if (objs) objects32(st, objs);
+    return 0;
+}
+
+// The first pass of a hard step: the same env run without the object paths
+// (the GROUPED kernel's body, plain = 0, or the PLAIN kernel's, plain = 1).
+// flag = 1 when an object showed (the outputs are then void and the step is
+// rerun with the object paths); otherwise outputs as host_interp.
+extern "C" int host_fast(int plain, const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0,
+                         const uint8_t *actions, int S, int F, unsigned long long seed, uint8_t *ram_out,
+                         uint8_t *frame_out, uint8_t *flag) {
+    StateRec st{};
+    st.status = 2;
+    st.tim_shift = 10;
+    std::memcpy(st.ram, ram0, 128);
+    StepParams P{};
+    P.state = &st;
+    P.actions = actions;
+    P.steps = S;
+    P.frame_skip = F;
+    P.ystart = 34;
+    P.frames_mode = 2;
+    P.ram_out = ram_out;
+    P.frame_out = frame_out;
+    P.seed = seed;
+    P.obj_flag = flag;
+    if (plain) {
+        GlobalMem m{rom, st.ram, nullptr};
+        step_env<OneLane, 1, false, true, InterpExec, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    } else {
+        std::vector<uint2> words(32768);
+        for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
+        std::vector<uint32_t> ram_lds(32, 0);
+        LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
+        step_env<OneLane, 1, false, false, InterpExec, false>(P, 0, 0, mapper, m, kHostDecode.e);
+    }
     return 0;
 }
 
@@ -93,12 +129,13 @@ extern "C" int host_interp(int plain, const uint8_t *rom, int rom_size, int mapp
 // dL/dRAM_out [S][128] (NULL = zero).  Outputs: ram_out [S][128] and frame
 // [210][160] as floats, the per-byte ROM value gradient g_rom [rom_size],
 // g_ram0 [128] and the port gradients g_port [S][2] (SWCHA, INPT4), before the
-// softmax epilogue.  Returns the number of checkpoints, or -1 if the tape
+// softmax epilogue, and (frame_dpos not NULL) the position sampler's tangents
+// of the final frame [5][210][160]; read_T > 0 turns on the address surrogate.  Returns the number of checkpoints, or -1 if the tape
 // overflowed.
 extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
                          const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
                          const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
-                         float *g_rom, float *g_ram0, float *g_port) {
+                         float *g_rom, float *g_ram0, float *g_port, float *frame_dpos, float read_T) {
     std::vector<uint2> words(32768);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 3);
@@ -129,6 +166,7 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
         P.frames_mode = 1;
         P.ram_out_f = ram_out;
         P.frame_out_f = frame_out;
+        P.frame_dpos_f = frame_dpos;
         P.ram0 = ram0;
         P.state_in = pre_steps > 0 ? &st : nullptr;
         P.ckpt = ckpt.data();
@@ -161,9 +199,10 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
     Q.g_ram0 = g_ram0;
     int32_t overflow = 0;
     Q.overflow = &overflow;
+    Q.read_T = read_T;
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-    bwd_env<OneLane>(Q, 0, 0, 1, mapper, m, kHostDecode.e);
+    bwd_env<OneLane>(Q, 0, 0, 1, mapper, (uint32_t)rom_size, m, kHostDecode.e);
     return overflow ? -1 : nck;
 }
 

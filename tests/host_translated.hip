@@ -25,11 +25,13 @@ constexpr DecodeTable kHostDecode = make_decode_table();
 
 // One env from power-on with RAM ram0 for S steps of F frames; outputs per step
 // (RAM [S][128], frame [S][210][160], done [S]) for env index `env`, whose rows
-// of ram_out/frame_out/done are written (they hold env + 1 envs' rows).
+// of ram_out/frame_out/done are written (they hold env + 1 envs' rows).  The
+// translated code runs without the object paths: obj_flag[env] = 1 says an
+// object showed and the outputs are void (the library then reruns the env).
 extern "C" int host_translated(int rom_index, const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0,
                                const uint8_t *actions, int S, int F, const uint32_t *ep_steps, int num_eps,
                                unsigned long long seed, int env, uint8_t *ram_out, uint8_t *frame_out,
-                               uint8_t *done) {
+                               uint8_t *done, uint8_t *obj_flag) {
     std::vector<StateRec> st((size_t)env + 1);
     st[(size_t)env].status = 2;
     std::memcpy(st[(size_t)env].ram, ram0, 128);
@@ -46,12 +48,13 @@ extern "C" int host_translated(int rom_index, const uint8_t *rom, int rom_size, 
     P.ep_steps = ep_steps;
     P.num_episodes = num_eps;
     P.seed = seed;
+    P.obj_flag = obj_flag;  // [env + 1]: 1 when an object showed (the outputs are then void)
     std::vector<uint2> words(8192);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
     std::vector<uint4> log((size_t)tr::kLogCap);
-    step_env<OneLane, 1, false, false, tr::Exec>(
+    step_env<OneLane, 1, false, false, tr::Exec, false>(
         P, env, 0, mapper, m, kHostDecode.e,
         tr::Exec::State{(uint32_t)rom_index, 0u, log.data(), tr::kTabAll + tr::kTabOff[rom_index]});
     return 0;

@@ -68,11 +68,14 @@ def test_create_validates_arguments():
                          None)
     assert rc == -1  # frames requested without a frame buffer
     rc = L.vcs_step_soft_fwd(h, None, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_float(0.0), C.c_float(6.0), 1,
-                             None, None, None, None, C.c_void_p(64), C.c_void_p(80), None)
+                             None, None, None, None, None, C.c_void_p(64), C.c_void_p(80), None)
     assert rc == -1  # tau must be > 0
+    rc = L.vcs_step_soft_fwd(h, None, C.c_void_p(16), C.c_void_p(32), C.c_void_p(48), C.c_float(1.0), C.c_float(6.0), 1,
+                             None, None, C.c_void_p(96), None, None, C.c_void_p(64), C.c_void_p(80), None)
+    assert rc == -1  # sampler tangents need the frame they belong to
     assert L.vcs_status_string(-3).decode() == "workspace too small"
     L.vcs_destroy(h)
-    np.testing.assert_equal(Bd.ABI_VERSION, 2)
+    np.testing.assert_equal(Bd.ABI_VERSION, 3)
 
 
 def test_autotune_candidates_are_valid_launch_shapes():

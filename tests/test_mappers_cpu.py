@@ -43,7 +43,7 @@ def test_host_core_matches_oracle_on_the_mapper_workload(host_lib, plain):
         host_lib.host_interp(plain, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
                              ptr(np.ascontiguousarray(w.ram0[b])), ptr(np.ascontiguousarray(w.actions[b])), w.steps,
                              w.frame_skip, ptr(ep), ep.size, C.c_ulonglong(w.seed), ptr(ram), ptr(fr), ptr(dn),
-                             ptr(regs))
+                             ptr(regs), None)
         name = I.MAPPER_NAMES[rom.mapper]
         assert (ram == ref["ram"]).all(), (b, name, plain)
         assert (fr == ref["frames"]).all(), (b, name, plain)

@@ -1,0 +1,234 @@
+"""The library's machine core, built for the host, against the oracle on the
+TIA objects: the hand-timed programs of the oracle's object pins and the
+seed-generated sprite workload (frames, RAM with the copied collision latches,
+object registers), and the soft forward's position-sampler tangents."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2606_22447_amd import inputs as I
+from tests import asm as A
+from tests import test_oracle_objects as P
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "..", "paper_2606_22447_amd", "csrc")
+ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+
+# vcs_read_objects keeps only the bits the TIA uses of each register
+OBJ_MASK = np.array([0xFF] * 9 + [2, 2, 2, 2, 0xFF, 0xFF, 8, 8, 1, 1, 1, 2, 2] + [0xF0] * 5 + [0xFF, 0xFF, 0, 0, 0],
+                    np.int64)
+
+
+@pytest.fixture(scope="module")
+def host_lib(tmp_path_factory):
+    so = tmp_path_factory.mktemp("host") / "libhost_machine.so"
+    subprocess.check_call(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O1", "-std=c++17", "-fPIC", "-shared",
+                           "-w", "-I", CSRC, os.path.join(HERE, "host_machine.hip"), "-o", str(so)],
+                          stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+    return C.CDLL(str(so))
+
+
+def host_run(H, plain, image, mapper, ram0, actions, S, F, seed=0):
+    ram = np.zeros((S, 128), np.uint8)
+    fr = np.zeros((S, 210, 160), np.uint8)
+    dn = np.zeros(S, np.uint8)
+    regs = np.zeros(16, np.uint8)
+    objs = np.zeros(32, np.uint8)
+    acts = np.ascontiguousarray(np.zeros(S, np.uint8) if actions is None else actions, np.uint8)
+    H.host_interp(plain, ptr(np.ascontiguousarray(image)), image.size, mapper, ptr(np.ascontiguousarray(ram0)),
+                  ptr(acts), S, F, None, 0, C.c_ulonglong(seed), ptr(ram), ptr(fr), ptr(dn), ptr(regs), ptr(objs))
+    return ram, fr, objs
+
+
+def oracle_objects(image, mapper, ram0, actions, S, F):
+    m = O.Machine(image, mapper, ram0)
+    for s in range(S):
+        m.env_step(0 if actions is None else int(actions[s]), F, s, s == S - 1)
+    o = np.array([m.objects()[k] for k in O.OBJECT_NAMES], np.int64)
+    return m.frame(), m.ram(), o & OBJ_MASK
+
+
+PROGRAMS = {
+    "strobe_wrap": P.player_program(0xFF, nops=35),
+    "copies_3": P.player_program(0x81, nusiz=3),
+    "quad_reflect": P.player_program(0x41, nusiz=7, refp=8),
+}
+
+
+def _hand_bodies():
+    """The bodies of the oracle pins, rebuilt here (each returns a ROM image)."""
+    bodies = []
+
+    def moves(b):
+        P.setreg(b, A.COLUP0, 0x44)
+        P.setreg(b, A.GRP0, 0xC3)
+        P.setreg(b, A.NUSIZ0, 0x26)
+        P.setreg(b, A.ENAM0, 0x02)
+        P.setreg(b, A.CTRLPF, 0x25)
+        P.setreg(b, A.PF0, 0x30)
+        P.setreg(b, A.ENABL, 0x02)
+        P.strobe(b, A.RESP0, 10)
+        P.strobe(b, A.RESM0, 17)
+        P.strobe(b, A.RESBL, 3)
+        P.setreg(b, A.HMP0, 0x70)
+        P.setreg(b, A.HMM0, 0x90)
+        P.setreg(b, A.HMBL, 0x30)
+        b.ins("STA", "zp", A.WSYNC)
+        b.ins("STA", "zp", A.HMOVE)
+        b.byte(A.JAM_OPCODE)
+    bodies.append(moves)
+
+    def blank_line(b):
+        P.setreg(b, A.COLUBK, 0x0E)
+        P.setreg(b, A.GRP1, 0xFF)
+        b.ins("LDX", "imm", 100)
+        b.label("W")
+        b.ins("STA", "zp", A.WSYNC)
+        b.ins("DEX")
+        b.ins("BNE", "rel", "W")
+        b.ins("STA", "zp", A.HMOVE)
+        b.byte(A.JAM_OPCODE)
+    bodies.append(blank_line)
+
+    def collide(b):
+        P.setreg(b, A.GRP0, 0xFF)
+        P.setreg(b, A.GRP1, 0xFF)
+        P.setreg(b, A.VDELP1, 0x01)
+        P.setreg(b, A.ENAM1, 0x02)
+        P.setreg(b, A.PF0, 0x30)
+        P.strobe(b, A.RESP0, 10)
+        P.strobe(b, A.RESP1, 11)
+        b.ins("STA", "zp", A.WSYNC)
+        b.ins("STA", "zp", A.WSYNC)
+        for k in range(8):
+            b.ins("LDA", "zp", k)
+            b.ins("STA", "zp", 0x80 + k)
+        b.ins("STA", "zp", A.CXCLR)
+        b.ins("LDA", "zp", A.CXP0FB)
+        b.ins("STA", "zp", 0x88)
+        P.setreg(b, A.RESMP1, 0x02)
+        P.setreg(b, A.RESMP1, 0x00)
+        b.byte(A.JAM_OPCODE)
+    bodies.append(collide)
+    return [A.program(f) for f in bodies]
+
+
+@pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
+def test_host_core_matches_oracle_on_hand_programs(host_lib, plain):
+    images = [A.program(f) for f in PROGRAMS.values()] + _hand_bodies()
+    for i, img in enumerate(images):
+        ram0 = np.zeros(128, np.uint8)
+        ram, fr, objs = host_run(host_lib, plain, img, 1, ram0, None, 2, 1)
+        f, r, o = oracle_objects(img, 1, ram0, None, 2, 1)
+        assert (fr[-1] == f).all(), (i, plain, np.argwhere(fr[-1] != f)[:5])
+        assert (ram[-1] == r).all(), (i, plain)
+        assert (objs.astype(np.int64) == o).all(), (i, plain, objs.tolist(), o.tolist())
+
+
+@pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
+def test_host_core_matches_oracle_on_the_sprite_workload(host_lib, plain):
+    w = I.config_objects(envs_per_rom=1, steps=3, n_roms=8, frame_skip=2)
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        ref = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, seed=w.seed,
+                        env_index=b)
+        ram, fr, objs = host_run(host_lib, plain, rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps,
+                                 w.frame_skip, seed=w.seed)
+        assert (ram == ref["ram"]).all(), (b, plain)
+        assert (fr == ref["frames"]).all(), (b, plain, np.argwhere(fr != ref["frames"])[:5])
+        _, _, o = oracle_objects(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip)
+        assert (objs.astype(np.int64) == o).all(), (b, plain, objs.tolist(), o.tolist())
+
+
+def test_host_soft_tangents_and_gradients_match_oracle(host_lib):
+    w = I.config_objects(envs_per_rom=1, steps=2, n_roms=4, frame_skip=1)
+    rng = np.random.default_rng(5)
+    S = 2
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        act = np.ascontiguousarray(w.actions[b])
+        gf = (rng.standard_normal((210, 160)) * 1e-3).astype(np.float32)
+        sw = np.array([O.action_ports(int(a))[0] for a in act], np.float64)
+        inp = np.array([O.action_ports(int(a))[1] for a in act], np.float64)
+        ref = O.soft_env(rom.image, rom.image.astype(np.float64), rom.mapper, w.ram0[b],
+                         w.ram0[b].astype(np.float64), act, sw, inp, S, 1, grad_frame=gf.astype(np.float64))
+        ram = np.zeros((S, 128), np.float32)
+        fr = np.zeros((210, 160), np.float32)
+        g_rom = np.zeros(rom.size, np.float32)
+        g0 = np.zeros(128, np.float32)
+        gp = np.zeros((S, 2), np.float32)
+        dpos = np.full((5, 210, 160), np.nan, np.float32)
+        n = host_lib.host_soft(ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                               ptr(np.ascontiguousarray(w.ram0[b])), 0, None, ptr(act), S, 1, 1024,
+                               ptr(gf), None, ptr(ram), ptr(fr), ptr(g_rom), ptr(g0), ptr(gp), ptr(dpos),
+                               C.c_float(0.0))
+        assert n >= 0
+        assert (fr == ref["frame"]).all(), b
+        assert (dpos == ref["frame_dpos"]).all(), (b, np.argwhere(dpos != ref["frame_dpos"])[:5])
+        assert np.abs(dpos).sum() > 0, "the workload's frame shows objects"
+        m = np.abs(ref["g_rom"]).max()
+        assert m > 0 and np.abs(g_rom - ref["g_rom"]).max() <= 1e-4 * m, b
+
+
+@pytest.mark.parametrize("read_T", [1.0, 0.3])
+def test_host_address_surrogate_matches_oracle(host_lib, read_T):
+    """The sprite kernels load their graphics with LDA table,Y: with the address
+    surrogate on, those reads pass gradient to Y (and on to the LDY immediates and
+    the RAM the index came from)."""
+    w = I.config_objects(envs_per_rom=1, steps=2, n_roms=8, frame_skip=1)
+    rng = np.random.default_rng(9)
+    S = 2
+    changed = 0
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        act = np.ascontiguousarray(w.actions[b])
+        gf = (rng.standard_normal((210, 160)) * 1e-3).astype(np.float32)
+        gr = (rng.standard_normal((S, 128)) * 1e-2).astype(np.float32)
+        sw = np.array([O.action_ports(int(a))[0] for a in act], np.float64)
+        inp = np.array([O.action_ports(int(a))[1] for a in act], np.float64)
+        kw = dict(grad_frame=gf.astype(np.float64), grad_ram=gr.astype(np.float64))
+        ref = O.soft_env(rom.image, rom.image.astype(np.float64), rom.mapper, w.ram0[b],
+                         w.ram0[b].astype(np.float64), act, sw, inp, S, 1, read_T=read_T, **kw)
+        off = O.soft_env(rom.image, rom.image.astype(np.float64), rom.mapper, w.ram0[b],
+                         w.ram0[b].astype(np.float64), act, sw, inp, S, 1, **kw)
+        changed += np.abs(ref["g_rom"] - off["g_rom"]).max() > 0
+        g_rom = np.zeros(rom.size, np.float32)
+        g0 = np.zeros(128, np.float32)
+        gp = np.zeros((S, 2), np.float32)
+        n = host_lib.host_soft(ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                               ptr(np.ascontiguousarray(w.ram0[b])), 0, None, ptr(act), S, 1, 1024, ptr(gf), ptr(gr),
+                               ptr(np.zeros((S, 128), np.float32)), ptr(np.zeros((210, 160), np.float32)),
+                               ptr(g_rom), ptr(g0), ptr(gp), None, C.c_float(read_T))
+        assert n >= 0
+        for g, r, name in ((g_rom, ref["g_rom"], "rom"), (g0, ref["g_ram0"], "ram0")):
+            m = np.abs(r).max()
+            assert m > 0 and np.abs(g - r).max() <= 1e-4 * m, (b, name, np.abs(g - r).max(), m)
+    assert changed >= 2, "the kernels that colour P1 from a table,Y read get address gradients"
+
+
+@pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
+def test_first_pass_without_object_paths(host_lib, plain):
+    """The hard step's first pass (no object paths) is exact for envs that never show
+    an object (here the batched workload, whose ROM writes only playfield and
+    colours) and flags every env of the sprite workload."""
+    def fast(rom, ram0, acts, S, F, seed):
+        ram = np.zeros((S, 128), np.uint8)
+        fr = np.zeros((S, 210, 160), np.uint8)
+        flag = np.full(1, 7, np.uint8)
+        host_lib.host_fast(plain, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                           ptr(np.ascontiguousarray(ram0)), ptr(np.ascontiguousarray(acts)), S, F,
+                           C.c_ulonglong(seed), ptr(ram), ptr(fr), ptr(flag))
+        return ram, fr, int(flag[0])
+    w = I.config_c1(num_envs=4, steps=4)
+    for b in range(w.num_envs):
+        ram, fr, flag = fast(w.roms[0], w.ram0[b], w.actions[b], w.steps, w.frame_skip, w.seed)
+        ref = O.run_env(w.roms[0].image, w.roms[0].mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip)
+        assert flag == 0 and (ram == ref["ram"]).all() and (fr == ref["frames"]).all(), b
+    w = I.config_objects(envs_per_rom=1, steps=2, n_roms=4, frame_skip=2)
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        assert fast(rom, w.ram0[b], w.actions[b], w.steps, w.frame_skip, w.seed)[2] == 1, b

@@ -62,7 +62,7 @@ def _host_run(H, plain, rom, ram0, actions, S, F, ep, seed, env):
     # the env index only keys the reset RAM: pass it through the seed's stream as the oracle does
     H.host_interp(plain, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper, ptr(np.ascontiguousarray(ram0)),
                   ptr(np.ascontiguousarray(actions)), S, F, ptr(ep), 0 if ep is None else ep.size,
-                  C.c_ulonglong(seed), ptr(ram), ptr(fr), ptr(dn), ptr(regs))
+                  C.c_ulonglong(seed), ptr(ram), ptr(fr), ptr(dn), ptr(regs), None)
     return ram, fr, dn, regs
 
 
@@ -123,7 +123,8 @@ def test_host_soft_backward_matches_oracle_on_the_sweep(host_lib, K, pre):
         gp = np.zeros((S, 2), np.float32)
         n = host_lib.host_soft(ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
                                ptr(np.ascontiguousarray(w.ram0[b])), pre, ptr(pre_act), ptr(act), S, 1, K,
-                               ptr(gf), ptr(gr), ptr(ram), ptr(fr), ptr(g_rom), ptr(g0), ptr(gp))
+                               ptr(gf), ptr(gr), ptr(ram), ptr(fr), ptr(g_rom), ptr(g0), ptr(gp), None,
+                               C.c_float(0.0))
         assert n >= 0, "tape overflow"
         if pre:
             assert (g0 == 0).all()

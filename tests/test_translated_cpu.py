@@ -108,11 +108,12 @@ def playfield_modes_workload(B: int = 3, S: int = 3) -> I.Workload:
                       np.zeros((B, S), np.uint8), S, 2, seed=8)
 
 
-@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes", "playfield_modes", "sweep"])
+@pytest.mark.parametrize("name", ["c1", "hetero", "tia_pushes", "playfield_modes", "sweep", "objects"])
 def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
     w = {"c1": lambda: I.config_c1(num_envs=6, steps=6), "hetero": _hetero, "tia_pushes": tia_pushes_workload,
          "playfield_modes": playfield_modes_workload,
-         "sweep": lambda: I.config_sweep(envs_per_rom=2, steps=3, frame_skip=2)}[name]()
+         "sweep": lambda: I.config_sweep(envs_per_rom=2, steps=3, frame_skip=2),
+         "objects": lambda: I.config_objects(envs_per_rom=1, steps=3, n_roms=6, frame_skip=2)}[name]()
     h = _ctx(w)
     src = Bd.translated_source(h, np.concatenate([r.image for r in w.roms]))
     gen = tmp_path / "translated.hip"
@@ -139,9 +140,15 @@ def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
         ram = np.zeros((n, 128), np.uint8)
         fr = np.zeros((n, 210, 160), np.uint8)
         dn = np.zeros(n, np.uint8)
+        flag = np.full(b + 1, 7, np.uint8)
         H.host_translated(ri, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
                           ptr(np.ascontiguousarray(w.ram0[b])), ptr(acts), w.steps, w.frame_skip, ptr(ep),
-                          0 if ep is None else ep.shape[1], C.c_ulonglong(w.seed), b, ptr(ram), ptr(fr), ptr(dn))
+                          0 if ep is None else ep.shape[1], C.c_ulonglong(w.seed), b, ptr(ram), ptr(fr), ptr(dn),
+                          ptr(flag))
+        if name == "objects":  # sprite kernels show objects: the library reruns them with the object paths
+            assert flag[b] == 1, b
+            continue
+        assert flag[b] == 0, (name, b)
         sl = slice(b * w.steps, None)
         assert (ram[sl] == ref["ram"]).all(), (name, b)
         assert (fr[sl] == ref["frames"]).all(), (name, b)
@@ -176,3 +183,4 @@ def test_translate_arguments_and_budget():
     with pytest.raises(Bd.VcsError):
         Bd.create([r.size for r in w.roms], [r.mapper for r in w.roms], w.env_rom, 4, 34, 0, 0,
                   Bd.VCS_KERNEL_TRANSLATED, 1, 256)
+    assert Bd.translate(_ctx(w, 4, 256), roms, compile_only=True)["positions"] > 100
