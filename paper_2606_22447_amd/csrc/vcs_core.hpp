@@ -558,8 +558,8 @@ __host__ __device__ __attribute__((noinline)) void render_span_objects(T *frame,
 
 // Write the pixels of [from, to) drawn with TIA state t into a frame of T (and
 // with tan the sampler's tangents, see render_span_objects).
-// Without the object paths (kObj false) objects are taken as not shown; the
-// HMOVE blank still blacks out its columns.
+// Without the object paths (kObj false) no object shows and no HMOVE blank
+// falls (the machine stops at the first write that could make either happen).
 template <bool kObj = true, typename T>
 __host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int32_t to, const Tia &t,
                                                      int32_t ystart, uint32_t sub, uint32_t G,
@@ -571,10 +571,8 @@ __host__ __device__ __forceinline__ void render_span(T *frame, int32_t from, int
         }
     }
     const uint32_t mask = pf_mask20(t.pf), ctrl = t.pf >> 24;
-    const int32_t hl = hmove_line(t.ob) - ystart;
     for_each_group(from, to, ystart, sub, G, [&](int32_t y, int32_t g, int32_t xa, int32_t xb) {
-        const bool blank = (t.vb & 2u) || (!kObj && y == hl && g < 2);
-        const uint32_t c = blank ? 0u : ((t.col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
+        const uint32_t c = (t.vb & 2u) ? 0u : ((t.col >> (8 * group_owner((uint32_t)g, mask, ctrl))) & 0xFEu);
         T *row = frame + y * kScreenW;
         if (xb - xa == 4) {
             if constexpr (sizeof(T) == 1) {
@@ -620,10 +618,14 @@ __host__ __device__ __forceinline__ uint32_t write_class(uint32_t addr, uint32_t
 // The machine
 // ---------------------------------------------------------------------------
 // kObj: the machine with the object paths (collision latching, object pixels).
-// Without them (the fast variant of the hard kernels) the object registers are
-// still kept, and obj_stop is raised once an object shows: from then on the
-// env's results are not the machine's, and the caller reruns the env with the
-// object paths from its starting state.
+// Without them (the fast variant of the hard kernels) the machine holds no
+// object state: obj_stop is raised when the loaded state shows an object, and
+// at any write to a register only objects use (NUSIZ, REFP, the strobes, GRP,
+// ENAM/ENABL, HMxx, VDEL, RESMP, HMOVE, HMCLR, CXCLR) or read of a collision
+// latch.  Until then the object state stays as loaded, nothing shows and
+// nothing collides, so the results are the machine's; from then on they are
+// void, and the caller reruns the env with the object paths from its starting
+// state.  The state record's object fields are left as loaded.
 template <class Mem, class Hook, bool kObj = true>
 struct Cpu {
     static constexpr bool kObjects = kObj;
@@ -636,6 +638,7 @@ struct Cpu {
     uint32_t cx;                  // collision latches, bit k = pair k
     int32_t cx_cc;                // frame-relative colour clock up to which cx is current
     bool obj_stop;                // (without the object paths) an object showed
+    bool ob_reset;                // (without the object paths) power-on cleared the object state
     int32_t tim_u, tim_read;
     uint32_t tim_shift;
     uint32_t swcha, inpt4, swchb;
@@ -687,7 +690,10 @@ struct Cpu {
     __host__ __device__ __forceinline__ uint32_t timint_at(int32_t t) const {
         return (t >= tim_u && tim_read < tim_u) ? 0x80u : 0u;
     }
-    __host__ __device__ __forceinline__ Tia tia() const { return Tia{col, pf, vb, ob}; }
+    __host__ __device__ __forceinline__ Tia tia() const {
+        if constexpr (kObj) return Tia{col, pf, vb, ob};
+        else return Tia{col, pf, vb, Objs{0u, 0u, 0u, 0u}};
+    }
     // latch the collisions of the clocks before k
     __host__ __device__ __forceinline__ void cx_upto(int32_t k) {
         if constexpr (kObj) {
@@ -695,14 +701,16 @@ struct Cpu {
                 if (objs_shown(ob)) cx |= collide_span(tia(), cx_cc, k);
                 cx_cc = k;
             }
-        } else if (k > cx_cc) {  // nothing shows, nothing collides
-            cx_cc = k;
         }
     }
     // TIA read in cycle t: collision latches (registers 0..7), INPT4, INPT5
     __host__ __device__ __forceinline__ uint32_t tia_in(uint32_t addr, int32_t t) {
         const uint32_t r = addr & 0xFu;
         if (r < 8u) {
+            if constexpr (!kObj) {
+                obj_stop = true;
+                return 0u;
+            }
             cx_upto(3 * t + 3);
             return (((cx >> (2u * r)) & 1u) << 7) | (((cx >> (2u * r + 1u)) & 1u) << 6);
         }
@@ -786,6 +794,29 @@ struct Cpu {
         ob.pos = (ob.pos & ~(0xFFu << (8u * o))) | (c << (8u * o));
     }
     __host__ __device__ __forceinline__ void tia_out(uint32_t reg, uint32_t v, int32_t w) {
+        if constexpr (!kObj) {
+            switch (reg) {
+                case 0x00: vb = (vb & 0xFFu) | (v << 8); break;
+                case 0x01: hook.before_pixel_write(*this, w); vb = (vb & 0xFF00u) | v; break;
+                case 0x02: wsync = 1; break;
+                case 0x06: case 0x07: case 0x08: case 0x09: {
+                    hook.before_pixel_write(*this, w);
+                    const uint32_t sh = (reg - 6u) * 8u;
+                    col = (col & ~(0xFFu << sh)) | (v << sh);
+                    break;
+                }
+                case 0x0A: hook.before_pixel_write(*this, w); pf = (pf & 0x00FFFFFFu) | (v << 24); break;
+                case 0x0D: case 0x0E: case 0x0F: {
+                    hook.before_pixel_write(*this, w);
+                    const uint32_t sh = (reg - 0x0Du) * 8u;
+                    pf = (pf & ~(0xFFu << sh)) | (v << sh);
+                    break;
+                }
+                case 0x03: case 0x15: case 0x16: case 0x17: case 0x18: case 0x19: case 0x1A: break;  // RSYNC, audio
+                default: obj_stop = obj_stop || reg <= 0x2Cu; break;  // the object registers; unused above
+            }
+            return;
+        }
         // registers that change what objects or the playfield show: NUSIZ0/1,
         // CTRLPF, REFP0/1, PF0-2, the strobes, GRP0/1, ENAM0/1, ENABL, VDELP0/1,
         // VDELBL, RESMP0/1, HMOVE
@@ -866,7 +897,6 @@ struct Cpu {
             case 0x2C: cx_upto(3 * (w + 1)); cx = 0; break;  // CXCLR
             default: break;  // audio, RSYNC and the unused addresses
         }
-        if constexpr (!kObj) obj_stop = obj_stop || (obj_reg && objs_shown(ob));
     }
     // data write in cycle w
     __host__ __device__ __forceinline__ void write(uint32_t addr, uint32_t v, int32_t w) {
@@ -1212,6 +1242,7 @@ struct Cpu {
         hm = cx = 0;
         cx_cc = 0;
         obj_stop = false;
+        ob_reset = true;
         tim_u = 0;
         tim_read = 0;
         tim_shift = 10;
@@ -1223,10 +1254,12 @@ struct Cpu {
     // underflowed timers are renormalised by multiples of 256 cycles, which
     // changes no observable value.
     __host__ __device__ __forceinline__ void next_frame() {
-        cx_upto(3 * cyc);  // the frame's remaining collisions (and those of cycles past its end)
-        cx_cc -= kClocksPerFrame;
-        const int32_t hl = hmove_line(ob) - kLinesPerFrame;
-        ob.bl = (ob.bl & 0xFFu) | (hl >= 0 ? (uint32_t)(hl + 1) << 8 : 0u);
+        if constexpr (kObj) {
+            cx_upto(3 * cyc);  // the frame's remaining collisions (and those of cycles past its end)
+            cx_cc -= kClocksPerFrame;
+            const int32_t hl = hmove_line(ob) - kLinesPerFrame;
+            ob.bl = (ob.bl & 0xFFu) | (hl >= 0 ? (uint32_t)(hl + 1) << 8 : 0u);
+        }
         cyc -= kCyclesPerFrame;
         tim_u -= kCyclesPerFrame;
         tim_read -= kCyclesPerFrame;
@@ -1243,9 +1276,14 @@ struct Cpu {
         slices = r.slices;
         cyc = r.cyc; col = r.col; pf = r.pf; vb = r.vblank | ((uint32_t)r.vsync << 8);
         tim_u = r.tim_u; tim_read = r.tim_read; tim_shift = r.tim_shift; wsync = 0;
-        ob = Objs{r.ob_pos, r.ob_gfx, r.ob_ctl, r.ob_bl};
-        hm = r.ob_hm; cx = r.cx; cx_cc = r.cx_cc;
-        obj_stop = !kObj && objs_shown(ob);
+        if constexpr (kObj) {
+            ob = Objs{r.ob_pos, r.ob_gfx, r.ob_ctl, r.ob_bl};
+            hm = r.ob_hm; cx = r.cx; cx_cc = r.cx_cc;
+            obj_stop = false;
+        } else {
+            obj_stop = objs_shown(Objs{r.ob_pos, r.ob_gfx, r.ob_ctl, r.ob_bl}) || hmove_line(Objs{0u, 0u, 0u, r.ob_bl}) >= 0;
+            ob_reset = false;
+        }
     }
     __host__ __device__ __forceinline__ void store(StateRec &r) const {
         r.magic = kMagic;
@@ -1253,8 +1291,16 @@ struct Cpu {
         r.pc = (uint16_t)pc; r.bank = (uint8_t)bank; r.status = (uint8_t)(jam & 1u); r.slices = (uint16_t)slices;
         r.cyc = cyc; r.col = col; r.pf = pf; r.vblank = (uint8_t)(vb & 0xFFu); r.vsync = (uint8_t)(vb >> 8);
         r.tim_u = tim_u; r.tim_read = tim_read; r.tim_shift = (uint8_t)tim_shift;
-        r.ob_pos = ob.pos; r.ob_gfx = ob.gfx; r.ob_ctl = ob.ctl; r.ob_bl = ob.bl;
-        r.ob_hm = hm; r.cx = cx; r.cx_cc = cx_cc;
+        if constexpr (kObj) {
+            r.ob_pos = ob.pos; r.ob_gfx = ob.gfx; r.ob_ctl = ob.ctl; r.ob_bl = ob.bl;
+            r.ob_hm = hm; r.cx = cx; r.cx_cc = cx_cc;
+        } else {  // the object fields stay as loaded (or cleared by a power-on); nothing collided up to now
+            if (ob_reset) {
+                r.ob_pos = r.ob_gfx = r.ob_ctl = r.ob_bl = 0u;
+                r.ob_hm = r.cx = 0u;
+            }
+            r.cx_cc = 3 * cyc;
+        }
     }
 };
 

@@ -199,11 +199,11 @@ struct RelaxMem : Base {
 // ---------------------------------------------------------------------------
 
 // One entry of an env's pixel-write log in translated code (which runs without
-// the object paths): the effect clock of a write, the colour registers, the
-// playfield + CTRLPF, and VBLANK | VSYNC << 8 | (HMOVE-blank line + 1) << 16,
-// all as before the write.
+// the object paths, so no object shows and no HMOVE blank falls): the effect
+// clock of a write, the colour registers, the playfield + CTRLPF, and VBLANK |
+// VSYNC << 8, all as before the write.
 __host__ __device__ __forceinline__ uint4 log_entry(int32_t clock, const Tia &t) {
-    return make_uint4((uint32_t)clock, t.col, t.pf, (t.vb & 0xFFFFu) | ((t.ob.bl >> 8) << 16));
+    return make_uint4((uint32_t)clock, t.col, t.pf, t.vb);
 }
 
 // Renders the returned frame lazily: before every write that changes pixels
@@ -257,7 +257,6 @@ struct RenderHook {
         const int32_t vis0 = ystart * kClocksPerLine + kHBlank;  // clock of pixel (0, 0)
         for (int32_t y = row_lo + (int32_t)sub; y < y_hi; y += GL) {
             const int32_t k_row = vis0 + y * kClocksPerLine;
-            const int32_t line1 = ystart + y + 1;  // the row's line + 1, as entries store an HMOVE blank
             uint32_t lo = 0, hi = n - 1u;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
@@ -274,8 +273,7 @@ struct RenderHook {
                 }
             };
             auto colour = [&](uint32_t g) {
-                const bool blank = (e.w & 2u) || (g < 2u && (int32_t)(e.w >> 16) == line1);
-                return blank ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
+                return (e.w & 2u) ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
             };
             T *row = frame + y * kScreenW;
             for (int32_t q = 0; q < kScreenW / 16; ++q) {

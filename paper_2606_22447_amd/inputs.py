@@ -1041,9 +1041,12 @@ class _SweepGen:
 
     VAR0, NVAR, PTR, WIN, ACC, RAMCODE = 0x80, 32, 0xA0, 0xA8, 0xC8, 0xD0
 
-    def __init__(self, seed: int, size: int, soft_safe: bool):
+    def __init__(self, seed: int, size: int, soft_safe: bool, objects: bool = True):
         self.r = Rng(stream_key(seed, 0x535750))
         self.seed, self.size, self.soft_safe = seed, size, soft_safe
+        # objects=False: no access reaches a register only the TIA's objects use
+        # (no collision reads, no object-register writes); the same random draws
+        self.objects = objects
         self.bank_size = 2048 if size == 2048 else 4096
         self.base = 0xF800 if size == 2048 else 0xF000
         self.n_label = 0
@@ -1111,7 +1114,20 @@ class _SweepGen:
             return self.var()
         if k == "win":
             return self.WIN + r.randint(0, 31)
-        return r.choice([INPT4, 0x0D, 0x3C, 0x2D, 0x00, 0x07, 0x1C])  # INPT4/5, mirrors, collisions
+        cx = (0x00, 0x07) if self.objects else (0x08, 0x0F)
+        return r.choice([INPT4, 0x0D, 0x3C, 0x2D, cx[0], cx[1], 0x1C])  # INPT4/5, mirrors, collisions
+
+    def wraps_to_tia(self, base: int, span: int) -> bool:
+        """objects=False: base + [0, span) past $FFFF wraps onto page 0, the TIA's
+        collision latches among it."""
+        return not self.objects and base + span - 1 > 0xFFFF
+
+    def rmw_safe(self, a: int, rmw: bool) -> int:
+        """objects=False: a read-modify-write of a TIA address also reads its read
+        register, a collision latch for registers 0-7: use COLUPF/COLUBK instead."""
+        if self.objects or not rmw or (a & 0x1080) or (a & 0xF) >= 8:
+            return a
+        return 0x08 | (a & 1)
 
     def write_target_zp(self) -> int:
         r = self.r
@@ -1120,7 +1136,8 @@ class _SweepGen:
             return self.var()
         if k == "win":
             return self.WIN + r.randint(0, 31)
-        return r.choice([COLUBK, COLUPF, COLUP0, COLUP1, PF0, PF1, PF2, CTRLPF, WSYNC, 0x49, 0x48, 0x03, 0x1F])
+        return r.choice([COLUBK, COLUPF, COLUP0, COLUP1, PF0, PF1, PF2, CTRLPF, WSYNC, 0x49, 0x48, 0x03,
+                         0x1F if self.objects else 0x2D])
 
     def read_target_abs(self, tables) -> int:
         r = self.r
@@ -1130,7 +1147,8 @@ class _SweepGen:
         if k == "mirror":
             return 0x100 | self.var()           # the stack page mirrors RAM
         if k == "tia":
-            return r.choice([0x000C, 0x010C, 0x003D, 0x0105, 0x0040])
+            return r.choice([0x000C, 0x010C, 0x003D, 0x0105 if self.objects else 0x010D,
+                             0x0040 if self.objects else 0x0048])
         if k == "riot":
             return r.choice([SWCHA, 0x281, 0x282, 0x283, INTIM, TIMINT, 0x286, 0x287, 0x2A4, 0x285])
         return tables[r.randint(0, len(tables) - 1)] + r.randint(0, 255)
@@ -1143,7 +1161,8 @@ class _SweepGen:
         if k == "mirror":
             return 0x100 | (self.WIN + r.randint(0, 31))
         if k == "tia":
-            return r.choice([0x0009, 0x0008, 0x0108, 0x004E, 0x000D, 0x000F, 0x0002, 0x0006])
+            return r.choice([0x0009, 0x0008, 0x0108, 0x004E, 0x000D, 0x000F, 0x0002,
+                             0x0006 if self.objects else 0x000A])
         if k == "riot":
             return r.choice([TIM1T, TIM8T, TIM64T, T1024T, 0x29C, 0x29F, 0x280, 0x281])
         return self.base + r.randint(0, 0x7FF)  # cartridge: no effect
@@ -1171,17 +1190,20 @@ class _SweepGen:
         if mode == "imm":
             operand = r.randint(0, 255)
         elif mode == "zp":
-            operand = self.write_target_zp() if (store or rmw) else self.read_target_zp()
+            operand = self.rmw_safe(self.write_target_zp(), rmw) if (store or rmw) else self.read_target_zp()
         elif mode in ("zpx", "zpy"):
             reg = "X" if mode == "zpx" else "Y"
             if r.random() < 0.35:  # wraps inside page 0, onto TIA registers $00-$0F (reads: collisions, INPT4)
-                self.idx_reg(b, reg, 0x10, 16)
+                if self.objects:
+                    self.idx_reg(b, reg, 0x10, 16)
+                else:  # $08-$0F: reads INPT0-5; writes COLUPF/COLUBK
+                    self.idx_reg(b, reg, 0x18, 2 if (store or rmw) else 8)
                 operand = 0xF0
             else:
                 self.idx_reg(b, reg, 0, 32)
                 operand = (self.WIN if (store or rmw) else self.VAR0)
         elif mode == "abs":
-            operand = self.write_target_abs() if (store or rmw) else self.read_target_abs(tables)
+            operand = self.rmw_safe(self.write_target_abs(), rmw) if (store or rmw) else self.read_target_abs(tables)
         elif mode in ("abx", "aby"):
             reg = "X" if mode == "abx" else "Y"
             kinds = [("ram", 3 if cross is not True else 0), ("cross_tia", 2 if cross is not False else 0),
@@ -1194,16 +1216,26 @@ class _SweepGen:
             elif kind == "cross_tia":
                 # $F8 + [0, 16): some envs cross into $0100-$0107 (TIA mirror).  Between
                 # snippets the stack is empty (S = $FF), so $F8-$FF hold nothing live.
-                self.idx_reg(b, reg, 0, 16)
-                operand = 0x00F8
+                if self.objects:
+                    self.idx_reg(b, reg, 0, 16)
+                    operand = 0x00F8
+                else:  # stores cross onto VSYNC/VBLANK only; loads and RMW stay in $F8-$FF
+                    self.idx_reg(b, reg, 0, 8)
+                    operand = 0x00FA if store else 0x00F8
             elif kind == "rom":    # a table near a page end: some envs cross
-                self.idx_reg(b, reg, 0, 64)
-                operand = tables[0] + r.randint(0xE0, 0xF0)
+                if self.wraps_to_tia(tables[0] + 0xF0, 64):  # $FFF8 + [$10, $18): $0008-$000F
+                    self.idx_reg(b, reg, 0x10, 8)
+                    r.randint(0xE0, 0xF0)
+                    operand = 0xFFF8
+                else:
+                    self.idx_reg(b, reg, 0, 64)
+                    operand = tables[0] + r.randint(0xE0, 0xF0)
             else:                  # RIOT registers $0280-$0287 (ports, INTIM, TIMINT) or timer writes
                 self.idx_reg(b, reg, 0, 8)
                 operand = 0x0290 if store else 0x0280
         elif mode in ("izx", "izy"):
-            targets = [self.var(), self.read_target_abs(tables) if not (store or rmw) else self.write_target_abs(),
+            targets = [self.var(), self.read_target_abs(tables) if not (store or rmw)
+                       else self.rmw_safe(self.write_target_abs(), rmw),
                        self.WIN + r.randint(0, 8), r.choice([INTIM, COLUBK, COLUPF, SWCHA])]
             if mode == "izx":
                 for k in range(4):
@@ -1218,14 +1250,22 @@ class _SweepGen:
                 kind = r.weighted([("rom", 3 if not store and cross is not False else 0),
                                    ("win", 2 if cross is not True else 0), ("cross", 1 if cross is not False else 0)])
                 if kind == "rom":
-                    self.set_ptr(b, k, tables[0] + r.randint(0xE0, 0xF0))
-                    self.idx_reg(b, "Y", 0, 64)
+                    base = tables[0] + r.randint(0xE0, 0xF0)
+                    if self.wraps_to_tia(base, 64):  # $FFF8 + [$10, $18): $0008-$000F
+                        self.set_ptr(b, k, 0xFFF8)
+                        self.idx_reg(b, "Y", 0x10, 8)
+                    else:
+                        self.set_ptr(b, k, base)
+                        self.idx_reg(b, "Y", 0, 64)
                 elif kind == "win":
                     self.set_ptr(b, k, self.WIN)
                     self.idx_reg(b, "Y", 0, 32)
-                else:  # $F8 + Y: some envs cross into the TIA mirror $0100-$0107
+                elif self.objects:  # $F8 + Y: some envs cross into the TIA mirror $0100-$0107
                     self.set_ptr(b, k, 0x00F8)
                     self.idx_reg(b, "Y", 0, 16)
+                else:
+                    self.set_ptr(b, k, 0x00FA if store else 0x00F8)
+                    self.idx_reg(b, "Y", 0, 8)
                 operand = self.PTR + 2 * k
         # the accumulator / X operand of the instruction
         if mn in ("STX", "CPX"):
@@ -1590,7 +1630,7 @@ class _SweepGen:
             b.ins("INC", "abs", hs)
 
 
-def generate_sweep_rom(seed: int, size: int = 4096, *, soft_safe: bool = False) -> Rom:
+def generate_sweep_rom(seed: int, size: int = 4096, *, soft_safe: bool = False, objects: bool = True) -> Rom:
     """A seeded program that executes every byte of the 189-opcode set (a 2K
     image holds a seeded 80 of them), in every addressing form, with indexed
     accesses that cross pages for some envs and not for others, read-modify-
@@ -1598,9 +1638,10 @@ def generate_sweep_rom(seed: int, size: int = 4096, *, soft_safe: bool = False) 
     reads, the JMP ($xxFF) page wrap, BRK/RTI, computed RTS/RTI jumps, code run
     from RAM, pushes onto TIA registers and, for F8 images, bank switches on
     every kind of data access (the code is the same in both banks, the data
-    tables differ)."""
+    tables differ).  objects=False keeps every access off the registers only the
+    TIA's objects use (collision reads, object-register writes)."""
     assert size in (2048, 4096, 8192)
-    g = _SweepGen(seed, size, soft_safe)
+    g = _SweepGen(seed, size, soft_safe, objects)
     ops = sorted(instruction_set())
     if size == 2048:
         sel = Rng(stream_key(seed, 0x32304B))
@@ -1614,11 +1655,13 @@ def generate_sweep_rom(seed: int, size: int = 4096, *, soft_safe: bool = False) 
 SWEEP_ROMS = ((4, 4096), (1, 4096), (0, 8192), (7, 8192), (1, 2048), (7, 2048))
 
 
-def config_sweep(envs_per_rom: int = 8, steps: int = 4, frame_skip: int = 2, episodes: bool = True) -> Workload:
+def config_sweep(envs_per_rom: int = 8, steps: int = 4, frame_skip: int = 2, episodes: bool = True,
+                 objects: bool = True) -> Workload:
     """Parity workload over the opcode-sweep family: 4K, F8 and 2K sweep images,
     random RAM and joystick inputs, short geometric-free episodes (1-3 steps)
-    for every other env so that in-run resets land mid-sweep."""
-    roms = [generate_sweep_rom(s, sz) for s, sz in SWEEP_ROMS]
+    for every other env so that in-run resets land mid-sweep.  objects=False:
+    the images that stay off the object registers (see generate_sweep_rom)."""
+    roms = [generate_sweep_rom(s, sz, objects=objects) for s, sz in SWEEP_ROMS]
     b = len(roms) * envs_per_rom
     env_rom = np.repeat(np.arange(len(roms), dtype=np.int32), envs_per_rom)
     eps = None

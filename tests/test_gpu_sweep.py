@@ -17,21 +17,28 @@ pytestmark = pytest.mark.gpu
 _REF = {}
 
 
-def sweep_workload():
-    return I.config_sweep(envs_per_rom=32, steps=4, frame_skip=2, episodes=True)
+def sweep_workload(objects=True):
+    return I.config_sweep(envs_per_rom=32, steps=4, frame_skip=2, episodes=True, objects=objects)
 
 
-def reference(w):
-    if "hard" not in _REF:
-        _REF["hard"] = [oracle_env(w, b) for b in range(w.num_envs)]
-    return _REF["hard"]
+def reference(w, objects=True):
+    if objects not in _REF:
+        _REF[objects] = [oracle_env(w, b) for b in range(w.num_envs)]
+    return _REF[objects]
 
 
-@pytest.mark.parametrize("kernel,G,tpb", KERNELS + [("translated", 4, 256), ("translated", 32, 256), ("translated", 64, 64)])
-def test_sweep_every_byte(kernel, G, tpb):
-    w = sweep_workload()
-    say("sweep", kernel, G, tpb, "envs", w.num_envs)
-    refs = reference(w)
+SHAPES = KERNELS + [("translated", 4, 256), ("translated", 32, 256), ("translated", 64, 64)]
+
+
+# objects=False: images kept off the object registers run wholly in the hard
+# step's first pass (the translated code, or the interpreter without the object
+# paths); the full images mostly in its second pass (the interpreter with them)
+@pytest.mark.parametrize("objects", [True, False], ids=["full", "no_objects"])
+@pytest.mark.parametrize("kernel,G,tpb", SHAPES)
+def test_sweep_every_byte(kernel, G, tpb, objects):
+    w = sweep_workload(objects)
+    say("sweep", kernel, G, tpb, "envs", w.num_envs, "objects", objects)
+    refs = reference(w, objects)
     ram, fr, done, vb = gpu_run(w, kernel, G, tpb, splits=(1,))
     regs = vb.regs().cpu().numpy()
     for b in range(w.num_envs):

@@ -212,9 +212,10 @@ def test_host_address_surrogate_matches_oracle(host_lib, read_T):
 
 @pytest.mark.parametrize("plain", [0, 1], ids=["grouped", "plain"])
 def test_first_pass_without_object_paths(host_lib, plain):
-    """The hard step's first pass (no object paths) is exact for envs that never show
-    an object (here the batched workload, whose ROM writes only playfield and
-    colours) and flags every env of the sprite workload."""
+    """The hard step's first pass (no object paths) is exact for envs that never
+    touch a register only objects use (here the batched workload, whose ROM writes
+    only playfield and colours, and the opcode sweep kept off those registers)
+    and flags every env of the sprite workload."""
     def fast(rom, ram0, acts, S, F, seed):
         ram = np.zeros((S, 128), np.uint8)
         fr = np.zeros((S, 210, 160), np.uint8)
@@ -228,6 +229,13 @@ def test_first_pass_without_object_paths(host_lib, plain):
         ram, fr, flag = fast(w.roms[0], w.ram0[b], w.actions[b], w.steps, w.frame_skip, w.seed)
         ref = O.run_env(w.roms[0].image, w.roms[0].mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip)
         assert flag == 0 and (ram == ref["ram"]).all() and (fr == ref["frames"]).all(), b
+    w = I.config_sweep(envs_per_rom=1, steps=3, frame_skip=2, episodes=False, objects=False)
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        ram, fr, flag = fast(rom, w.ram0[b], w.actions[b], w.steps, w.frame_skip, w.seed)
+        ref = O.run_env(rom.image, rom.mapper, w.ram0[b], w.actions[b], w.steps, w.frame_skip, seed=w.seed,
+                        env_index=b)
+        assert flag == 0 and (ram == ref["ram"]).all() and (fr == ref["frames"]).all(), ("sweep", b)
     w = I.config_objects(envs_per_rom=1, steps=2, n_roms=4, frame_skip=2)
     for b in range(w.num_envs):
         rom = w.roms[int(w.env_rom[b])]
