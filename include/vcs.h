@@ -48,7 +48,8 @@
 extern "C" {
 #endif
 
-#define VCS_ABI_VERSION 3  /* 2: soft forward from a given state; 3: sampler tangents, address surrogate */
+#define VCS_ABI_VERSION 4  /* 2: soft forward from a given state; 3: sampler tangents, address surrogate;
+                              4: the soft forward's tape (tape_records) */
 
 typedef enum vcs_status {
     VCS_OK = 0,
@@ -113,6 +114,13 @@ typedef struct vcs_config {
     int32_t block_threads;      /* threads per workgroup: 64, 256, or 1024 (GROUPED with 64 lanes per
                                    env only); 0 = 1024 for GROUPED with 64 lanes per env, else 256;
                                    TRANSLATED: block_threads / lanes_per_env <= 64 */
+    int32_t tape_records;       /* soft forward's tape, 16-byte records per env kept in the residual:
+                                   0 = none (the backward recomputes every checkpoint segment);
+                                   n > 0 = up to n records; -1 = as many as S steps can need
+                                   ((S F - 1) * 9956 + S + 16).  The forward records each segment
+                                   it completes before the final frame, while the records fit;
+                                   the backward sweeps those from the tape instead of recomputing
+                                   them (not with read_T > 0).  Memory for recompute time. */
 } vcs_config;
 
 typedef struct vcs_ctx vcs_ctx;
@@ -270,7 +278,11 @@ int32_t vcs_step_relaxed(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
  *                  when the forward starts from d_state_in;
  *  d_state_out     [B][256] final hard state (NULL = not written);
  *  d_residual      vcs_residual_bytes(S): saved for the backward;
- *  d_work          vcs_workspace_bytes(VCS_OP_SOFT_FWD, S). */
+ *  d_work          vcs_workspace_bytes(VCS_OP_SOFT_FWD, S).
+ * Like vcs_step_hard, the forward runs every env first in kernels without the
+ * TIA object paths and reruns those in which an object shows with them (the
+ * residual records which); with d_frame_dpos every env runs with them.  With
+ * tape_records != 0 the forward also writes its tape into d_residual. */
 int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_rom_logits, const float *d_ram_tape,
                           const float *d_action_logits, float tau, float alpha, int32_t steps, float *d_ram_out,
                           float *d_frame_out, float *d_frame_dpos, float *d_decode_out, void *d_state_out,
@@ -283,10 +295,12 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
  * relaxation (Sec. "Hard and Soft Execution": stored switches, round and
  * clamp with identity backward, straight-through branches; the Corollary after
  * Theorem "Temperature-limit bound": STE as a surrogate-gradient estimator;
- * softmax Jacobians of Eq. select for the leaves).  Recomputes each
- * checkpoint segment from its hard-state checkpoint, records a tape and
- * sweeps it in reverse; ROM gradients of envs sharing a ROM are summed in a
- * fixed order (deterministic).
+ * softmax Jacobians of Eq. select for the leaves).  Sweeps each checkpoint
+ * segment's tape in reverse: the forward's tape where it kept one
+ * (tape_records), otherwise a tape recorded by recomputing the segment from its
+ * hard-state checkpoint; both give the same records, so the gradients do not
+ * depend on tape_records or K.  ROM gradients of envs sharing a ROM are summed
+ * in a fixed order (deterministic).
  *  read_T               0: addresses carry no gradient (the STE surrogate).  > 0:
  *                       the leaky variant's address surrogate (Eq. s-read taken in
  *                       the backward): an indexed load or ALU read of a ROM or RAM

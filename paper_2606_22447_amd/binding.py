@@ -19,7 +19,7 @@ VCS_KERNEL_AUTO, VCS_KERNEL_PLAIN, VCS_KERNEL_GROUPED, VCS_KERNEL_TRANSLATED = 0
 VCS_TRANSLATE_COMPILE_ONLY = 1
 VCS_FRAMES_NONE, VCS_FRAMES_LAST, VCS_FRAMES_ALL = 0, 1, 2
 VCS_OP_HARD, VCS_OP_SOFT_FWD, VCS_OP_SOFT_BWD = 0, 1, 2
-ABI_VERSION = 3
+ABI_VERSION = 4
 STATE_BYTES = 256
 
 EXPORTED = [
@@ -45,7 +45,7 @@ class VcsConfig(C.Structure):
         ("rom_size", C.POINTER(C.c_int32)), ("rom_mapper", C.POINTER(C.c_int32)),
         ("env_rom", C.POINTER(C.c_int32)), ("frame_skip", C.c_int32), ("ystart", C.c_int32),
         ("seed", C.c_uint64), ("ckpt_interval", C.c_int32), ("kernel", C.c_int32),
-        ("lanes_per_env", C.c_int32), ("block_threads", C.c_int32),
+        ("lanes_per_env", C.c_int32), ("block_threads", C.c_int32), ("tape_records", C.c_int32),
     ]
 
 
@@ -132,13 +132,13 @@ def decode_table():
 
 
 def create(rom_sizes, rom_mappers, env_rom, frame_skip=4, ystart=34, seed=0, ckpt_interval=0,
-           kernel=VCS_KERNEL_AUTO, lanes_per_env=0, block_threads=0):
+           kernel=VCS_KERNEL_AUTO, lanes_per_env=0, block_threads=0, tape_records=0):
     R, B = len(rom_sizes), len(env_rom)
     sizes = (C.c_int32 * R)(*[int(v) for v in rom_sizes])
     maps = (C.c_int32 * R)(*[int(v) for v in rom_mappers])
     envr = (C.c_int32 * B)(*[int(v) for v in env_rom])
     cfg = VcsConfig(ABI_VERSION, B, R, sizes, maps, envr, frame_skip, ystart, seed, ckpt_interval, kernel,
-                    lanes_per_env, block_threads)
+                    lanes_per_env, block_threads, tape_records)
     h = C.c_void_p()
     check(lib().vcs_create(C.byref(cfg), C.byref(h)), "vcs_create")
     return h

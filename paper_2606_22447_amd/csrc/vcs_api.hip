@@ -25,6 +25,7 @@ inline bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 struct vcs_ctx {
     int32_t B = 0, R = 0, F = 1, ystart = 34, K = 1024, kernel = VCS_KERNEL_GROUPED, G = 1, tpb = 256;
+    int32_t tape_records = 0;    // soft forward's tape per env (0: none, -1: the bound for S steps)
     uint64_t seed = 0;
     std::vector<int32_t> rom_size, rom_mapper, env_rom, rom_off;
     int32_t max_rom = 0, total_rom = 0;
@@ -50,10 +51,18 @@ namespace {
 
 // Layout of the soft residual for S steps.
 struct ResidualLayout {
-    size_t rom_hard, ram0_hard, act_hard, stats, rom_stats, tape_ev, act_stats, ckpt_count, ckpt, bytes;
+    size_t rom_hard, ram0_hard, act_hard, stats, rom_stats, tape_ev, act_stats, ckpt_count, obj_env, ckpt, ftape,
+        bytes;
     size_t stats_bytes;
     int32_t max_ckpt;
+    int64_t ftape_cap;  // forward-tape records per env (0: no tape)
 };
+// Records the forward can tape for S steps: every instruction takes at least 2
+// cycles, and the final frame is never taped, so (S F - 1) frames of at most
+// 9956 instruction records each, plus one step-end record per step.
+int64_t ftape_bound(const vcs_ctx *c, int32_t S) {
+    return ((int64_t)S * c->F - 1) * (kCyclesPerFrame / 2) + S + 16;
+}
 ResidualLayout residual_layout(const vcs_ctx *c, int32_t S) {
     ResidualLayout L{};
     size_t o = kAlign;  // header
@@ -71,12 +80,21 @@ ResidualLayout residual_layout(const vcs_ctx *c, int32_t S) {
     o = align_up(L.rom_stats + L.stats_bytes);
     L.ckpt_count = o;
     o = align_up(o + (size_t)c->B * sizeof(int32_t));
+    L.obj_env = o;  // 1 for an env whose forward ran with the object paths
+    o = align_up(o + (size_t)c->B);
     // the starting state, one per K cycles, and slack for a start inside a frame
     L.max_ckpt = (int32_t)(((int64_t)S * c->F * kCyclesPerFrame + 256) / c->K + 3);
     L.ckpt = o;
     o = align_up(o + (size_t)c->B * L.max_ckpt * sizeof(StateRec));
+    L.ftape_cap = c->tape_records < 0 ? ftape_bound(c, S) : c->tape_records;
+    L.ftape = o;
+    o = align_up(o + (size_t)c->B * (size_t)L.ftape_cap * 16u);
     L.bytes = o;
     return L;
+}
+// The forward tape's size is representable (int32 records per env, bytes in 62 bits).
+bool ftape_ok(const vcs_ctx *c, const ResidualLayout &L) {
+    return L.ftape_cap <= INT32_MAX && (L.ftape_cap == 0 || (uint64_t)c->B <= (1ull << 58) / (uint64_t)L.ftape_cap);
 }
 
 // Layout of the soft-backward workspace (after the static region).
@@ -265,6 +283,7 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
     if (cfg->frame_skip < 1 || cfg->frame_skip > 1000) return VCS_INVALID_ARG;
     if (cfg->ystart < 0 || cfg->ystart + kScreenH > kLinesPerFrame) return VCS_INVALID_ARG;
     if (cfg->ckpt_interval != 0 && (cfg->ckpt_interval < 64 || cfg->ckpt_interval > (1 << 24))) return VCS_INVALID_ARG;
+    if (cfg->tape_records < -1) return VCS_INVALID_ARG;
     vcs_ctx *c = new (std::nothrow) vcs_ctx();
     if (!c) return VCS_INVALID_ARG;
     c->B = cfg->num_envs;
@@ -273,6 +292,7 @@ int32_t vcs_create(const vcs_config *cfg, vcs_ctx **out) {
     c->ystart = cfg->ystart;
     c->seed = cfg->seed;
     c->K = cfg->ckpt_interval ? cfg->ckpt_interval : 1024;
+    c->tape_records = cfg->tape_records;
     int64_t total = 0;
     for (int32_t r = 0; r < c->R; ++r) {
         const int32_t sz = cfg->rom_size[r], mp = cfg->rom_mapper[r];
@@ -444,6 +464,7 @@ int32_t vcs_workspace_bytes(const vcs_ctx *ctx, int32_t op, int32_t steps, size_
 
 int32_t vcs_residual_bytes(const vcs_ctx *ctx, int32_t steps, size_t *bytes) {
     if (!ctx || !bytes || steps < 1) return VCS_INVALID_ARG;
+    if (!ftape_ok(ctx, residual_layout(ctx, steps))) return VCS_INVALID_ARG;
     *bytes = residual_layout(ctx, steps).bytes;
     return VCS_OK;
 }
@@ -698,9 +719,10 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
         return VCS_INVALID_ARG;
     if ((int64_t)steps * ctx->F > (1 << 24)) return VCS_INVALID_ARG;
     if (ctx->kernel == VCS_KERNEL_PLAIN || ctx->any_sc) return VCS_UNSUPPORTED;  // no Superchip RAM in the soft graph
+    const ResidualLayout L = residual_layout(ctx, steps);
+    if (!ftape_ok(ctx, L)) return VCS_INVALID_ARG;
     int32_t rc = upload_static(ctx, d_work, stream);
     if (rc) return rc;
-    const ResidualLayout L = residual_layout(ctx, steps);
     uint8_t *res = (uint8_t *)d_residual;
     // (from a given state the tape is not read: its statistics are zero)
     hipError_t e = d_ram_tape ? hipSuccess
@@ -729,8 +751,21 @@ int32_t vcs_step_soft_fwd(vcs_ctx *ctx, const void *d_state_in, const float *d_r
     P.ckpt_count = (int32_t *)(res + L.ckpt_count);
     P.ckpt_interval = ctx->K;
     P.max_ckpt = L.max_ckpt;
+    P.ftape = L.ftape_cap > 0 ? (uint4 *)(res + L.ftape) : nullptr;
+    P.ftape_cap = (int32_t)L.ftape_cap;
     P.rom_words = ctx->max_rom;
-    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, step_lds(ctx), stream));
+    // Two passes, as for the hard steps: every env without the object paths,
+    // flagging those in which an object shows, then those with them from the
+    // same start.  The sampler's tangents need the object paths everywhere.
+    uint8_t *obj_env = res + L.obj_env;
+    P.obj_flag = obj_env;
+    if (!d_frame_dpos) {
+        rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, step_lds(ctx), stream, false));
+        if (rc) return rc;
+        P.obj_flag = nullptr;
+        P.rerun = obj_env;
+    }
+    rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, true, false, step_lds(ctx), stream, true));
     if (rc) return rc;
     if (d_decode_out &&
         hipMemcpyAsync(d_decode_out, res + L.stats, L.stats_bytes, hipMemcpyDeviceToDevice, stream) != hipSuccess)
@@ -759,6 +794,7 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     int32_t rc = upload_static(ctx, d_work, stream);
     if (rc) return rc;
     const ResidualLayout L = residual_layout(ctx, steps);
+    if (!ftape_ok(ctx, L)) return VCS_INVALID_ARG;
     const BwdLayout W = bwd_layout(ctx, steps);
     const uint8_t *res = (const uint8_t *)d_residual;
     uint8_t *work = (uint8_t *)d_work;
@@ -783,7 +819,13 @@ int32_t vcs_step_soft_bwd(vcs_ctx *ctx, const void *d_residual, const float *d_r
     P.g_ram0 = (float *)(work + W.g0);
     P.overflow = (int32_t *)(work + W.overflow);
     P.read_T = read_T;
-    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, ctx->max_rom, stream));
+    P.ftape = L.ftape_cap > 0 ? (const uint4 *)(res + L.ftape) : nullptr;
+    P.ftape_cap = (int32_t)L.ftape_cap;
+    P.obj_env = res + L.obj_env;
+    // the envs whose forward ran without the object paths, then the others
+    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, ctx->max_rom, stream, false));
+    if (rc) return rc;
+    rc = hip_status(launch_soft_bwd(P, ctx->bwd_blocks, ctx->max_rom, stream, true));
     if (rc) return rc;
     const StaticPtrs sp = static_ptrs(ctx, d_work);
     return hip_status(launch_epilogue(d_rom_logits, (const float *)(res + L.rom_stats), P.gpart, ctx->total_rom,

@@ -639,6 +639,7 @@ struct Cpu {
     int32_t cx_cc;                // frame-relative colour clock up to which cx is current
     bool obj_stop;                // (without the object paths) an object showed
     bool ob_reset;                // (without the object paths) power-on cleared the object state
+    const StateRec *ob_src;       // (without the object paths) the record whose object fields hold
     int32_t tim_u, tim_read;
     uint32_t tim_shift;
     uint32_t swcha, inpt4, swchb;
@@ -1243,6 +1244,7 @@ struct Cpu {
         cx_cc = 0;
         obj_stop = false;
         ob_reset = true;
+        ob_src = nullptr;
         tim_u = 0;
         tim_read = 0;
         tim_shift = 10;
@@ -1283,6 +1285,7 @@ struct Cpu {
         } else {
             obj_stop = objs_shown(Objs{r.ob_pos, r.ob_gfx, r.ob_ctl, r.ob_bl}) || hmove_line(Objs{0u, 0u, 0u, r.ob_bl}) >= 0;
             ob_reset = false;
+            ob_src = &r;
         }
     }
     __host__ __device__ __forceinline__ void store(StateRec &r) const {
@@ -1294,10 +1297,13 @@ struct Cpu {
         if constexpr (kObj) {
             r.ob_pos = ob.pos; r.ob_gfx = ob.gfx; r.ob_ctl = ob.ctl; r.ob_bl = ob.bl;
             r.ob_hm = hm; r.cx = cx; r.cx_cc = cx_cc;
-        } else {  // the object fields stay as loaded (or cleared by a power-on); nothing collided up to now
-            if (ob_reset) {
+        } else {  // the object fields as loaded (or cleared by a power-on); nothing collided up to now
+            if (ob_reset || !ob_src) {
                 r.ob_pos = r.ob_gfx = r.ob_ctl = r.ob_bl = 0u;
                 r.ob_hm = r.cx = 0u;
+            } else if (ob_src != &r) {
+                r.ob_pos = ob_src->ob_pos; r.ob_gfx = ob_src->ob_gfx; r.ob_ctl = ob_src->ob_ctl;
+                r.ob_bl = ob_src->ob_bl; r.ob_hm = ob_src->ob_hm; r.cx = ob_src->cx;
             }
             r.cx_cc = 3 * cyc;
         }

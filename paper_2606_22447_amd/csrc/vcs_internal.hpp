@@ -77,7 +77,11 @@ struct alignas(16) StateRec {
     uint32_t ob_hm;       // motion registers' high nibbles: HMP0 | HMP1 << 4 | HMM0 << 8 | HMM1 << 12 | HMBL << 16
     uint32_t cx;          // collision latches, bit k = pair k
     int32_t cx_cc;        // frame-relative colour clock up to which the latches are current
-    uint32_t pad[7];
+    // (soft checkpoints) the forward's tape of the segment that starts here: first
+    // record and count in the env's forward tape, tape_n = -1 when not taped
+    uint32_t tape_off;
+    int32_t tape_n;
+    uint32_t pad[5];
     uint8_t ram[128];
 };
 static_assert(sizeof(StateRec) == 256, "state record must be 256 bytes");
@@ -133,6 +137,8 @@ struct StepParams {
     int32_t *ckpt_count;       // [B]
     int32_t ckpt_interval;
     int32_t max_ckpt;
+    uint4 *ftape;              // [B][ftape_cap] the forward's tape records (w0..w3 of TapeRec), or NULL
+    int32_t ftape_cap;
     // hard steps in two passes: the kernel without the object paths writes obj_flag[env]
     // (1: an object showed, the env's results are void); the kernel with them then runs
     // only the flagged envs (rerun != NULL) from their starting states state_src/sc_src
@@ -178,6 +184,9 @@ struct BwdParams {
     float *g_ram0;               // [B][128]
     int32_t *overflow;           // set nonzero if a segment needed more than max_rec records
     float read_T;                // address surrogate's read temperature (0: addresses carry no gradient)
+    const uint4 *ftape;          // [B][ftape_cap] the forward's tape (segments with tape_n >= 0), or NULL
+    int32_t ftape_cap;
+    const uint8_t *obj_env;      // [B]: 1 for an env whose forward ran with the object paths, or NULL (all)
 };
 
 }  // namespace vcs

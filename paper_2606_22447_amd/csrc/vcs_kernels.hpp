@@ -6,12 +6,13 @@
 namespace vcs {
 
 // lds: bytes of dynamic LDS (the staged ROM image, then Superchip RAM)
-// objects: the hard kernels with the object paths (soft kernels always have them)
+// objects: the kernels with the object paths (TIA objects and collisions)
 hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool soft, bool plain,
                        size_t lds, hipStream_t stream, bool objects = true);
 hipError_t launch_step_relaxed(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
                                hipStream_t stream);
-hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream);
+hipError_t launch_soft_bwd(const BwdParams &P, int32_t blocks, int32_t max_rom_size, hipStream_t stream,
+                           bool objects);
 hipError_t launch_decode(const float *rom_logits, int64_t rom_rows, const float *tape, int64_t tape_rows,
                          const float *act_logits, int64_t act_rows, float tau, uint8_t *rom_hard, float *rom_stats,
                          uint8_t *ram0_hard, float *tape_ev, uint8_t *act_hard, float *act_stats, hipStream_t stream);

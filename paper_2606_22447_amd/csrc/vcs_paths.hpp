@@ -397,8 +397,9 @@ __host__ __device__ inline __attribute__((noinline)) PixelParts pixel_parts_obje
 // of a wave (the soft backward runs one env per wave): lane l takes every
 // kWidth-th 4-pixel group of each line, then the wave sums the four partial
 // sums.  Returns (the same in every lane) whether any visible pixel lies in the
-// span.  Blanked pixels are constants and take no gradient.
-template <class W>
+// span.  Blanked pixels are constants and take no gradient.  kObj false: a
+// machine without the object paths (no object shows, no HMOVE blank falls).
+template <class W, bool kObj>
 __host__ __device__ __forceinline__ bool pixel_sums_wave(const float *gframe, int32_t from, int32_t to, const Tia &t,
                                                          int32_t ystart, float sums[4]) {
     if (t.vb & 2u) return false;
@@ -406,7 +407,7 @@ __host__ __device__ __forceinline__ bool pixel_sums_wave(const float *gframe, in
     if (to <= vis0 || from >= vis1) return false;
     float part[4] = {0.f, 0.f, 0.f, 0.f};
     bool any = false;
-    if (hmove_line(t.ob) >= 0 || objs_shown(t.ob)) {
+    if (kObj && (hmove_line(t.ob) >= 0 || objs_shown(t.ob))) {
         const PixelParts pp = pixel_parts_objects(gframe, from, to, t, ystart, W::lane(), W::kWidth);
         for (uint32_t k = 0; k < 4; ++k) part[k] = pp.p[k];
         any = pp.any;
@@ -487,12 +488,20 @@ struct TapeHook {
         }
         return acc / (z * read_T);
     }
+    // The words of an instruction's record (w3, the step, is the caller's); returns
+    // whether the instruction has content to record.
+    __host__ __device__ __forceinline__ static bool instr_words(uint32_t opc, const ExecInfo &info, uint32_t &w0,
+                                                                uint32_t &w1, uint32_t &w2) {
+        w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16) | (info.op_cls << 24);
+        w1 = info.rd_idx | (info.wr_idx << 16);
+        w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
+        return !(((kNoContent >> info.op_cls) & 1u) ||
+                 (((kStores >> info.op_cls) & 1u) && info.wr_cls == kClsConst));
+    }
     template <class C>
     __host__ __device__ __forceinline__ void after_exec(C &c, uint32_t opc, int32_t, int32_t wp, ExecInfo &info) {
         TapeRec r;
-        r.w0 = opc | (info.rd_cls << 8) | (info.wr_cls << 12) | (kRecInstr << 16) | (info.op_cls << 24);
-        r.w1 = info.rd_idx | (info.wr_idx << 16);
-        r.w2 = (info.v1 & 0xFFu) | ((info.v2 & 0xFFu) << 8) | ((info.s_before & 0xFFu) << 16);
+        bool keep = instr_words(opc, info, r.w0, r.w1, r.w2);
         r.w3 = step;
         // address surrogate: an indexed load or ALU read of a ROM or RAM byte also passes
         // gradient to its index register (read-modify-write forms do not)
@@ -513,14 +522,41 @@ struct TapeHook {
             }
         }
         r.pix[0] = r.pix[1] = r.pix[2] = r.pix[3] = 0.f;
-        bool keep = !(((kNoContent >> info.op_cls) & 1u) ||
-                      (((kStores >> info.op_cls) & 1u) && info.wr_cls == kClsConst));
-        if (gframe && pixel_sums_wave<W>(gframe, pix_cc, 3 * wp, save, ystart, r.pix)) {
+        if (gframe && pixel_sums_wave<W, C::kObjects>(gframe, pix_cc, 3 * wp, save, ystart, r.pix)) {
             r.w0 |= 1u << 20;
             keep = true;
         }
         pix_cc = 3 * wp;
         if (keep) emit(r);
+    }
+};
+
+// Hook of a soft forward that keeps its tape: renders as RenderHook and, while
+// `taping`, appends every instruction record the backward's recompute would
+// make (TapeHook, without the address surrogate) to the env's forward tape, 16
+// bytes each (w0..w3 of TapeRec).  The final frame, whose pixels carry the
+// loss's gradient, is never taped: its records need dL/dframe.
+template <typename T, class W>
+struct TapeFwdHook : RenderHook<T> {
+    static constexpr bool kRecord = true;
+    uint4 *ftape;      // the env's forward tape
+    int32_t fcap, fn;  // capacity; records so far (counted on past the capacity)
+    uint32_t step;
+    bool taping, lead;
+    __host__ __device__ __forceinline__ void put(const uint4 &r) {
+        if (fn < fcap && lead) ftape[fn] = r;
+        ++fn;
+    }
+    template <class C>
+    __host__ __device__ __forceinline__ void after_exec(C &c, uint32_t opc, int32_t x, int32_t wp, ExecInfo &info) {
+        RenderHook<T>::after_exec(c, opc, x, wp, info);
+        if (taping) {
+            uint4 r;
+            if (TapeHook<W>::instr_words(opc, info, r.x, r.y, r.z)) {
+                r.w = step;
+                put(r);
+            }
+        }
     }
 };
 
@@ -750,6 +786,12 @@ struct InterpExec {
     }
 };
 
+// The interpreter with a soft forward that keeps its tape (TapeFwdHook).
+struct TapeFwdExec : InterpExec {
+    template <typename T, class W>
+    using Hook = TapeFwdHook<T, W>;
+};
+
 // ---------------------------------------------------------------------------
 // Per-env bodies of the kernels.  W is the wave policy: any(v) / all(v) (is v
 // true in any / every active lane of the wave), first(v) (v of the first active
@@ -764,7 +806,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                                                   Mem mem, const uint32_t *decode,
                                                   typename X::State xs = typename X::State{}) {
     static_assert(!(kSoft && kPlain), "the soft forward uses the grouped kernel");
-    static_assert(kObj || !kSoft, "the soft forward runs with the object paths");
+    constexpr bool kTapeFwd = std::is_same<X, TapeFwdExec>::value;  // a soft forward that keeps its tape
+    static_assert(kSoft || !kTapeFwd, "only the soft forward keeps a tape");
     using T = typename std::conditional<kSoft, float, uint8_t>::type;
     // a rerun of flagged envs (P.rerun) leaves the others alone
     const bool live = env >= 0 && (!P.rerun || P.rerun[env]);
@@ -815,6 +858,15 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         }
     }
     X::init(c, xs);
+    int32_t seg0 = 0;  // (forward tape) first record of the current segment
+    if constexpr (kTapeFwd) {
+        c.hook.ftape = live ? P.ftape + (size_t)env * (size_t)P.ftape_cap : nullptr;
+        c.hook.fcap = P.ftape_cap;
+        c.hook.fn = 0;
+        c.hook.step = 0;
+        c.hook.taping = live;
+        c.hook.lead = sub == 0;
+    }
 
     int32_t s_idx = 0, fstep = 0;
     bool active = live && S > 0;
@@ -822,11 +874,15 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     auto set_ports = [&]() {
         const uint32_t act = P.actions ? P.actions[(size_t)env * S + s_idx] : 0u;
         action_ports(act, &c.swcha, &c.inpt4, &c.swchb);
+        if constexpr (kTapeFwd) c.hook.step = (uint32_t)s_idx;
     };
     auto start_frame = [&]() {
         c.hook.rend_cc = 0;
         c.hook.frame = nullptr;
         const bool last_of_step = fstep == F - 1;
+        if constexpr (kTapeFwd) {
+            if (last_of_step && s_idx == S - 1) c.hook.taping = false;  // the final frame is recomputed
+        }
         if constexpr (kSoft) {
             if (P.frame_out_f && last_of_step && s_idx == S - 1) {
                 c.hook.frame = P.frame_out_f + (size_t)env * kPixels;
@@ -851,6 +907,14 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
     auto save_checkpoint = [&](int64_t g) {
         if constexpr (kSoft) {
             next_ckpt = (g / P.ckpt_interval + 1) * P.ckpt_interval;
+            if constexpr (kTapeFwd) {  // the segment ending here is taped if all of it fit
+                if (nckpt > 0 && nckpt <= P.max_ckpt && sub == 0 && c.hook.taping && c.hook.fn <= c.hook.fcap) {
+                    StateRec &prev = P.ckpt[(size_t)env * P.max_ckpt + nckpt - 1];
+                    prev.tape_off = (uint32_t)seg0;
+                    prev.tape_n = c.hook.fn - seg0;
+                }
+                seg0 = c.hook.fn;
+            }
             if (nckpt < P.max_ckpt) {
                 StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + nckpt];
                 if (sub == 0) {
@@ -862,6 +926,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                     r.pix_cc = c.hook.pix_cc;
                     r.ckpt_index = (uint32_t)nckpt;
                     r.from_tape = src ? 0u : 1u;
+                    r.tape_off = 0u;
+                    r.tape_n = -1;
                 }
                 uint32_t *rw = reinterpret_cast<uint32_t *>(r.ram);
                 for (uint32_t w = sub; w < 32; w += G) rw[w] = c.mem.ram_word(w);
@@ -921,6 +987,9 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         ++frame;
         if (++fstep == F) {
             // ---- end of env step
+            if constexpr (kTapeFwd) {
+                if (c.hook.taping) c.hook.put(make_uint4(kRecStepEnd << 16, 0u, 0u, (uint32_t)s_idx));
+            }
             if constexpr (kSoft) {
                 if (P.ram_out_f) {
                     float4 *o = reinterpret_cast<float4 *>(P.ram_out_f + ((size_t)env * S + s_idx) * 128);
@@ -971,7 +1040,8 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         if (active) start_frame();
     }
 
-    if (live && P.obj_flag && sub == 0) P.obj_flag[env] = stopped ? 1u : 0u;
+    // obj_flag: 1 for an env that needs (or ran) the object paths
+    if (live && P.obj_flag && sub == 0) P.obj_flag[env] = (kObj || stopped) ? 1u : 0u;
     if (live && !stopped) {
         if (P.state) {
             StateRec &st = P.state[env];
@@ -1012,7 +1082,9 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
 // loop; the RAM adjoint lives in the lanes' registers (RamAdjoint).  ROM and
 // port gradients are accumulated by lane 0 with no-return atomic adds (one
 // lane per address: program order, deterministic).
-template <class W, class Mem>
+// kObj: recompute with the object paths (an env whose forward needed them);
+// without them for the others.
+template <class W, bool kObj = true, class Mem>
 __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env, uint32_t gslot, uint32_t nslots,
                                                  int32_t mapper, uint32_t rom_n, Mem mem, const uint32_t *decode) {
     constexpr uint32_t NW = W::kWidth;
@@ -1024,7 +1096,7 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
     RamAdjoint<W> adj;
     adj.zero();
 
-    Cpu<Mem, TapeHook<W>> c;
+    Cpu<Mem, TapeHook<W>, kObj> c;
     c.set_cart(mapper);  // (never a Superchip format: the soft path rejects them)
     c.mem = mem;
     c.hook.tape = P.tape + (size_t)gslot * (size_t)P.max_rec;  // the env's records, contiguous
@@ -1158,10 +1230,54 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             for (uint32_t k = 0; k < 4; ++k) aC[k] += pix(k);
         }
     };
+    // reverse sweep of records [0, nrec), a batch of NW records at a time (lane l
+    // loads record top - NW + l with load(i, words, pixel sums))
+    auto sweep_tape = [&](int32_t nrec, auto load) {
+        auto load_batch = [&](int32_t top, uint4 &a, float4 &b) {
+            const int32_t i = top - (int32_t)NW + (int32_t)lane;
+            if (i >= 0) {
+                load(i, a, b);
+            } else {
+                a = make_uint4(0u, 0u, 0u, 0u);
+                b = make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        };
+        uint4 ca;
+        float4 cb;
+        load_batch(nrec, ca, cb);
+        for (int32_t top = nrec; top > 0; top -= (int32_t)NW) {
+            const int32_t base = top - (int32_t)NW;  // lane l holds record base + l
+            uint4 na;
+            float4 nb;
+            load_batch(base, na, nb);  // the next batch, in flight during this one
+            const int32_t lo_i = base > 0 ? base : 0;
+            for (int32_t i = top - 1; i >= lo_i; --i) {
+                const uint32_t j = (uint32_t)(i - base);
+                auto pix = [&](uint32_t k) {
+                    return W::readlane(k == 0 ? cb.x : k == 1 ? cb.y : k == 2 ? cb.z : cb.w, j);
+                };
+                sweep_one(W::readlane(ca.x, j), W::readlane(ca.y, j), W::readlane(ca.z, j), W::readlane(ca.w, j),
+                          pix);
+            }
+            ca = na;
+            cb = nb;
+        }
+    };
 
     for (int32_t seg = nseg - 1; seg >= 0; --seg) {
-        // ---- restore the segment's starting state
         const StateRec &r = P.ckpt[(size_t)env * P.max_ckpt + seg];
+        // ---- a segment the forward taped is swept from its tape (not with the
+        // address surrogate, whose slopes need the arrays at the time of each read)
+        const int32_t tape_n = P.ftape && P.read_T == 0.f ? (int32_t)W::first((uint32_t)r.tape_n) : -1;
+        if (tape_n >= 0) {
+            const uint4 *ft = P.ftape + (size_t)env * (size_t)P.ftape_cap + W::first(r.tape_off);
+            sweep_tape(tape_n, [&](int32_t i, uint4 &a, float4 &b) {
+                a = ft[i];
+                b = make_float4(0.f, 0.f, 0.f, 0.f);
+            });
+            continue;
+        }
+        // ---- restore the segment's starting state
         c.load(r);
         const uint32_t *rw = reinterpret_cast<const uint32_t *>(r.ram);
         for (uint32_t w = lane; w < 32; w += NW) c.mem.ram_word_set(w, rw[w]);
@@ -1205,7 +1321,8 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
                     t.w1 = t.w2 = 0;
                     t.w3 = (uint32_t)s_idx;
                     t.pix[0] = t.pix[1] = t.pix[2] = t.pix[3] = 0.f;
-                    pixel_sums_wave<W>(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.tia(), c.hook.ystart, t.pix);
+                    pixel_sums_wave<W, kObj>(c.hook.gframe, c.hook.pix_cc, kClocksPerFrame, c.tia(), c.hook.ystart,
+                                             t.pix);
                     c.hook.emit(t);
                 }
                 c.next_frame();
@@ -1225,39 +1342,13 @@ __host__ __device__ __forceinline__ void bwd_env(const BwdParams &P, int32_t env
             }
         }
 
-        // ---- reverse sweep of the segment's tape, a batch of NW records at a time
+        // ---- reverse sweep of the segment's tape
         const int32_t nrec = c.hook.nrec < c.hook.max_rec ? c.hook.nrec : c.hook.max_rec;
         const TapeRec *tp = c.hook.tape;
-        auto load_batch = [&](int32_t top, uint4 &a, float4 &b) {  // lane l: record top - NW + l
-            const int32_t i = top - (int32_t)NW + (int32_t)lane;
-            if (i >= 0) {
-                a = reinterpret_cast<const uint4 *>(tp + i)[0];
-                b = reinterpret_cast<const float4 *>(tp + i)[1];
-            } else {
-                a = make_uint4(0u, 0u, 0u, 0u);
-                b = make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-        };
-        uint4 ca;
-        float4 cb;
-        load_batch(nrec, ca, cb);
-        for (int32_t top = nrec; top > 0; top -= (int32_t)NW) {
-            const int32_t base = top - (int32_t)NW;  // lane l holds record base + l
-            uint4 na;
-            float4 nb;
-            load_batch(base, na, nb);  // the next batch, in flight during this one
-            const int32_t lo_i = base > 0 ? base : 0;
-            for (int32_t i = top - 1; i >= lo_i; --i) {
-                const uint32_t j = (uint32_t)(i - base);
-                auto pix = [&](uint32_t k) {
-                    return W::readlane(k == 0 ? cb.x : k == 1 ? cb.y : k == 2 ? cb.z : cb.w, j);
-                };
-                sweep_one(W::readlane(ca.x, j), W::readlane(ca.y, j), W::readlane(ca.z, j), W::readlane(ca.w, j),
-                          pix);
-            }
-            ca = na;
-            cb = nb;
-        }
+        sweep_tape(nrec, [&](int32_t i, uint4 &a, float4 &b) {
+            a = reinterpret_cast<const uint4 *>(tp + i)[0];
+            b = reinterpret_cast<const float4 *>(tp + i)[1];
+        });
     }
     // the RAM adjoint at the start reaches the tape only when the forward started
     // from power-on with the tape's RAM; a given starting state is a constant

@@ -5,7 +5,7 @@
 namespace vcs {
 
 hipError_t launch_step_soft(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, size_t lds,
-                            hipStream_t stream);
+                            hipStream_t stream, bool objects);
 hipError_t launch_step_objects(const StepParams &P, int32_t blocks, int32_t lanes, int32_t tpb, bool plain,
                                size_t lds, hipStream_t stream);
 
@@ -13,7 +13,7 @@ hipError_t launch_step(const StepParams &P, int32_t blocks, int32_t lanes, int32
                        size_t lds, hipStream_t stream, bool objects) {
     if (soft) {
         if (plain) return hipErrorInvalidValue;
-        return launch_step_soft(P, blocks, lanes, tpb, lds, stream);
+        return launch_step_soft(P, blocks, lanes, tpb, lds, stream, objects);
     }
     if (objects) return launch_step_objects(P, blocks, lanes, tpb, plain, lds, stream);
     if (plain) {

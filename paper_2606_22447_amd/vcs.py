@@ -37,7 +37,7 @@ def _rom_arrays(roms):
 
 class _Ctx:
     def __init__(self, roms, env_rom, frame_skip, ystart, seed, ckpt_interval, kernel, lanes_per_env,
-                 block_threads, device, max_positions=0):
+                 block_threads, device, max_positions=0, tape_records=0):
         imgs, maps = _rom_arrays(roms)
         self.env_rom = np.asarray(env_rom, np.int32)
         self.B = int(self.env_rom.size)
@@ -45,7 +45,7 @@ class _Ctx:
         self.rom_sizes = [int(i.size) for i in imgs]
         self.h = Bd.create(self.rom_sizes, maps, self.env_rom, frame_skip, ystart, seed, ckpt_interval,
                            _KERNELS[kernel] if isinstance(kernel, str) else int(kernel), lanes_per_env,
-                           block_threads)
+                           block_threads, tape_records)
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:  # "cuda" = the current device
             self.device = torch.device("cuda", torch.cuda.current_device())
@@ -226,12 +226,18 @@ class SoftVcs(_Ctx):
     (a host synchronisation); otherwise the flags are summed on the device and
     raise_if_overflowed() checks them.  The tape is sized so that no segment
     can fill it (every instruction takes at least two cycles), so the flag is a
-    safety net."""
+    safety net.
+
+    tape_records: the forward keeps its tape in the residual for the backward
+    (0: none, every checkpoint segment is recomputed; n > 0: up to n 16-byte
+    records per env; -1: room for every segment before the final frame), which
+    then sweeps those segments without recomputing them: memory for time."""
 
     def __init__(self, roms, env_rom, frame_skip: int = 1, ystart: int = 34, ckpt_interval: int = 1024,
-                 lanes_per_env: int = 0, block_threads: int = 0, device="cuda", strict: bool = False):
+                 lanes_per_env: int = 0, block_threads: int = 0, device="cuda", strict: bool = False,
+                 tape_records: int = 0):
         super().__init__(roms, env_rom, frame_skip, ystart, 0, ckpt_interval, "grouped", lanes_per_env,
-                         block_threads, device)
+                         block_threads, device, tape_records=tape_records)
         self.strict = strict
         self._overflow = torch.zeros(1, dtype=torch.int32, device=self.device)
 

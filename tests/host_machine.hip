@@ -130,18 +130,19 @@ extern "C" int host_fast(int plain, const uint8_t *rom, int rom_size, int mapper
 // [210][160] as floats, the per-byte ROM value gradient g_rom [rom_size],
 // g_ram0 [128] and the port gradients g_port [S][2] (SWCHA, INPT4), before the
 // softmax epilogue, and (frame_dpos not NULL) the position sampler's tangents
-// of the final frame [5][210][160]; read_T > 0 turns on the address surrogate.  Returns the number of checkpoints, or -1 if the tape
-// overflowed.
-extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
-                         const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
-                         const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
-                         float *g_rom, float *g_ram0, float *g_port, float *frame_dpos, float read_T) {
+// of the final frame [5][210][160]; read_T > 0 turns on the address surrogate.
+// Returns the number of checkpoints, or -1 if the tape overflowed.
+static int soft_run(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
+                    const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K, const float *grad_frame,
+                    const float *grad_ram, float *ram_out, float *frame_out, float *g_rom, float *g_ram0,
+                    float *g_port, float *frame_dpos, float read_T, int tape_cap, int *taped, int objects = 1) {
     std::vector<uint2> words(32768);
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     const int max_ckpt = (int)(((int64_t)S * F * kCyclesPerFrame + 256) / K + 3);
     std::vector<StateRec> ckpt((size_t)max_ckpt);
     int32_t nck = 0;
     StateRec st{};
+    std::vector<uint4> ftape((size_t)(tape_cap > 0 ? tape_cap : 1));
     if (pre_steps > 0) {  // hard steps from power-on, through the hard interpreter's body
         st.status = 2;
         st.tim_shift = 10;
@@ -173,10 +174,23 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
         P.ckpt_count = &nck;
         P.ckpt_interval = K;
         P.max_ckpt = max_ckpt;
+        P.ftape = tape_cap > 0 ? ftape.data() : nullptr;
+        P.ftape_cap = tape_cap;
+        uint8_t flag = 7;
+        P.obj_flag = &flag;
         std::vector<uint32_t> ram_lds(32, 0);
         LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-        step_env<OneLane, 1, true, false>(P, 0, 0, mapper, m, kHostDecode.e);
+        if (objects) {
+            if (tape_cap > 0) step_env<OneLane, 1, true, false, TapeFwdExec>(P, 0, 0, mapper, m, kHostDecode.e);
+            else step_env<OneLane, 1, true, false>(P, 0, 0, mapper, m, kHostDecode.e);
+        } else {  // the first pass: an env in which an object shows is flagged (and rerun by the library)
+            if (tape_cap > 0) step_env<OneLane, 1, true, false, TapeFwdExec, false>(P, 0, 0, mapper, m, kHostDecode.e);
+            else step_env<OneLane, 1, true, false, InterpExec, false>(P, 0, 0, mapper, m, kHostDecode.e);
+            if (flag) return -2;
+        }
     }
+    *taped = 0;
+    for (int i = 0; i < nck && i < max_ckpt; ++i) *taped += tape_cap > 0 && ckpt[(size_t)i].tape_n >= 0;
     BwdParams Q{};
     Q.rom = rom;
     Q.actions = actions;
@@ -200,10 +214,36 @@ extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uin
     int32_t overflow = 0;
     Q.overflow = &overflow;
     Q.read_T = read_T;
+    Q.ftape = tape_cap > 0 ? ftape.data() : nullptr;
+    Q.ftape_cap = tape_cap;
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-    bwd_env<OneLane>(Q, 0, 0, 1, mapper, (uint32_t)rom_size, m, kHostDecode.e);
+    if (objects) bwd_env<OneLane>(Q, 0, 0, 1, mapper, (uint32_t)rom_size, m, kHostDecode.e);
+    else bwd_env<OneLane, false>(Q, 0, 0, 1, mapper, (uint32_t)rom_size, m, kHostDecode.e);
     return overflow ? -1 : nck;
+}
+
+extern "C" int host_soft(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
+                         const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
+                         const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
+                         float *g_rom, float *g_ram0, float *g_port, float *frame_dpos, float read_T) {
+    int taped = 0;
+    return soft_run(rom, rom_size, mapper, ram0, pre_steps, pre_actions, actions, S, F, K, grad_frame, grad_ram,
+                    ram_out, frame_out, g_rom, g_ram0, g_port, frame_dpos, read_T, 0, &taped);
+}
+
+// host_soft with the forward keeping its tape (tape_cap records, at most; the
+// segments it completes before the final frame, while they fit; 0 = none):
+// *taped = the number of segments the backward swept from that tape.  objects =
+// 0: the forward and backward without the object paths (the library's first
+// pass); returns -2 when the forward flags the env (an object showed).
+extern "C" int host_soft_tape(const uint8_t *rom, int rom_size, int mapper, const uint8_t *ram0, int pre_steps,
+                              const uint8_t *pre_actions, const uint8_t *actions, int S, int F, int K,
+                              const float *grad_frame, const float *grad_ram, float *ram_out, float *frame_out,
+                              float *g_rom, float *g_ram0, float *g_port, float read_T, int tape_cap, int *taped,
+                              int objects) {
+    return soft_run(rom, rom_size, mapper, ram0, pre_steps, pre_actions, actions, S, F, K, grad_frame, grad_ram,
+                    ram_out, frame_out, g_rom, g_ram0, g_port, nullptr, read_T, tape_cap, taped, objects);
 }
 
 // FULL relaxed rollout of one env from power-on with RAM ram0 (S steps of F

@@ -74,11 +74,12 @@ class Problem:
                 O.epilogue_action(self.act, self.tau, gsw.reshape(-1), gin.reshape(-1)).reshape(B, S, 18))
 
 
-def run_gpu(p: Problem, alpha=6.0, K=1024, G=0, tpb=0, grad_ram=None):
+def run_gpu(p: Problem, alpha=6.0, K=1024, G=0, tpb=0, grad_ram=None, tape=0):
     import torch
     from paper_2606_22447_amd.vcs import SoftVcs
     w = p.w
-    sim = SoftVcs(w.roms, w.env_rom, frame_skip=w.frame_skip, ckpt_interval=K, lanes_per_env=G, block_threads=tpb)
+    sim = SoftVcs(w.roms, w.env_rom, frame_skip=w.frame_skip, ckpt_interval=K, lanes_per_env=G, block_threads=tpb,
+                  tape_records=tape)
     dev = sim.device
     L = torch.from_numpy(p.logits).to(dev)
     T = torch.from_numpy(p.tape).to(dev)
@@ -193,6 +194,38 @@ def test_hetero_roms_with_inputs_and_ram_out_gradient():
             assert (gi == 0).all(), name
             continue
         assert_grad_close(gi, ri, name)
+
+
+@pytest.mark.parametrize("G,tpb,K,tape", [(64, 256, 512, -1), (16, 256, 1024, -1), (4, 64, 256, -1),
+                                           (64, 1024, 512, 3000)])
+def test_forward_tape_gives_the_recompute_gradients(G, tpb, K, tape):
+    """The soft forward that keeps its tape (every segment before the final frame,
+    or a 3000-record tape that runs out): the backward sweeps those segments
+    without recomputing them, with gradients bit-identical to the recomputing
+    backward's, and within the tolerance of the FP64 oracle."""
+    roms = [I.generate_rom(100 + i, sz, reads_inputs=True, timer_vblank=True)
+            for i, sz in enumerate([2048, 8192, 4096])]
+    B, S = 24, 4
+    env_rom = (np.arange(B) % 3).astype(np.int32)
+    w = I.Workload("soft_tape", roms, env_rom, I.initial_ram(23, B), I.action_stream(23, B, S), S, 2, seed=23)
+    p = Problem(w, 1.0)
+    grad_ram = np.random.default_rng(8).standard_normal((B, S, 128)) * 1e-2
+    say("forward tape G", G, "tpb", tpb, "K", K, "tape", tape)
+    r0 = run_gpu(p, K=K, G=G, tpb=tpb, grad_ram=grad_ram)
+    r1 = run_gpu(p, K=K, G=G, tpb=tpb, grad_ram=grad_ram, tape=tape)
+    assert (r0[0] == r1[0]).all() and (r0[1] == r1[1]).all()
+    for a, b, name in zip(r0[4], r1[4], ("rom_logits", "ram_tape", "action_logits")):
+        assert np.array_equal(a, b), (name, np.abs(a - b).max())
+    if tape < 0:  # one env against the oracle (the rest follow from the identity above)
+        r, b = int(env_rom[1]), 1
+        o, n = p.offs[r], roms[r].size
+        res = O.soft_env(p.dec_rom[0][o:o + n], p.dec_rom[1][o:o + n], roms[r].mapper, p.hard_ram0[b],
+                         p.dec_tape[1].reshape(B, 128)[b], p.hard_act[b], p.dec_act[1].reshape(B, S)[b],
+                         p.dec_act[2].reshape(B, S)[b], S, 2, mode="ste",
+                         grad_frame=p.grad_frame[b].astype(np.float64),
+                         grad_ram=grad_ram[b].astype(np.float32).astype(np.float64))
+        g0 = r1[4][1].reshape(B, 128, 256)[b]
+        assert_grad_close(g0, O.epilogue_tape(res["g_ram0"][None]).reshape(128, 256), "ram_tape env 1")
 
 
 def test_autograd_function_end_to_end(c3):

@@ -75,7 +75,20 @@ def test_create_validates_arguments():
     assert rc == -1  # sampler tangents need the frame they belong to
     assert L.vcs_status_string(-3).decode() == "workspace too small"
     L.vcs_destroy(h)
-    np.testing.assert_equal(Bd.ABI_VERSION, 3)
+    np.testing.assert_equal(Bd.ABI_VERSION, 4)
+    # the forward's tape: -1 sizes it for every segment before the final frame
+    with pytest.raises(Bd.VcsError):
+        Bd.create([2048], [0], [0], tape_records=-2)
+    h0 = Bd.create([2048], [0], [0, 0], frame_skip=2)
+    h1 = Bd.create([2048], [0], [0, 0], frame_skip=2, tape_records=-1)
+    h2 = Bd.create([2048], [0], [0, 0], frame_skip=2, tape_records=1000)
+    r0, r1, r2 = (Bd.size_query("vcs_residual_bytes", h, 3) for h in (h0, h1, h2))
+    assert r1 - r0 >= 2 * ((3 * 2 - 1) * 9956 + 3 + 16) * 16 and r2 - r0 >= 2 * 1000 * 16
+    h3 = Bd.create([2048], [0], [0, 0], frame_skip=2, tape_records=-1)
+    with pytest.raises(Bd.VcsError):  # more records per env than an int32 counts
+        Bd.size_query("vcs_residual_bytes", h3, 1 << 20)
+    for h in (h0, h1, h2, h3):
+        L.vcs_destroy(h)
 
 
 def test_autotune_candidates_are_valid_launch_shapes():

@@ -133,3 +133,55 @@ def test_host_soft_backward_matches_oracle_on_the_sweep(host_lib, K, pre):
         _close(g0, ref["g_ram0"], f"ram0 env {b}")
         _close(gp[:, 0], ref["g_swcha"], f"swcha env {b}")
         _close(gp[:, 1], ref["g_inpt4"], f"inpt4 env {b}")
+
+
+@pytest.mark.parametrize("K,cap,pre,objects", [(512, -1, 0, 1), (2048, -1, 1, 1), (512, 900, 0, 1),
+                                               (512, -1, 0, 0), (1024, 900, 1, 0)])
+def test_host_forward_tape_gives_the_recompute_gradients(host_lib, K, cap, pre, objects):
+    """A soft forward that keeps its tape: the backward sweeps the segments the
+    forward completed before the final frame from that tape instead of
+    recomputing them, and its gradients are bit-identical to the recomputing
+    backward's (cap -1: room for every segment; 900 records: the tape runs out
+    and the later segments are recomputed).  With the address surrogate on, the
+    tape is not used.  objects=0: the forward and backward without the object
+    paths, on the sweep images kept off the object registers, against the
+    recomputing backward with them."""
+    w = I.config_sweep(envs_per_rom=1, steps=3 + pre, frame_skip=2, episodes=False, objects=bool(objects))
+    rng = np.random.default_rng(17)
+    ptr = lambda a: None if a is None else a.ctypes.data_as(C.c_void_p)  # noqa: E731
+    S, F = 3, 2
+    bound = (S * F - 1) * 9956 + S + 16
+    for b in range(w.num_envs):
+        rom = w.roms[int(w.env_rom[b])]
+        pre_act, act = np.ascontiguousarray(w.actions[b, :pre]), np.ascontiguousarray(w.actions[b, pre:])
+        gf = (rng.standard_normal((210, 160)) * 1e-3).astype(np.float32)
+        gr = (rng.standard_normal((S, 128)) * 1e-2).astype(np.float32)
+        outs = []
+        for mode, read_T in (("recompute", 0.0), ("tape", 0.0), ("tape", 0.7), ("recompute", 0.7)):
+            ram = np.zeros((S, 128), np.float32)
+            fr = np.zeros((210, 160), np.float32)
+            g_rom = np.zeros(rom.size, np.float32)
+            g0 = np.zeros(128, np.float32)
+            gp = np.zeros((S, 2), np.float32)
+            taped = C.c_int(-1)
+            args = (ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper, ptr(np.ascontiguousarray(w.ram0[b])),
+                    pre, ptr(pre_act), ptr(act), S, F, K, ptr(gf), ptr(gr), ptr(ram), ptr(fr), ptr(g_rom), ptr(g0),
+                    ptr(gp))
+            if mode == "tape":
+                n = host_lib.host_soft_tape(*args, C.c_float(read_T), bound if cap < 0 else cap, C.byref(taped),
+                                            objects)
+            else:
+                n = host_lib.host_soft(*args, None, C.c_float(read_T))
+            assert n > 2, (b, n)
+            outs.append((ram, fr, g_rom, g0, gp, taped.value, n))
+        (r0, f0, a0, b0, p0, _, n0), (r1, f1, a1, b1, p1, t1, n1) = outs[0], outs[1]
+        assert n0 == n1 and (r0 == r1).all() and (f0 == f1).all(), b
+        if cap < 0:
+            assert 0 < t1 < n1, (b, t1, n1)  # all but the segments reaching the final frame
+        else:
+            assert 0 <= t1 < n1 - 1, (b, t1, n1)
+        for x, y, name in ((a0, a1, "rom"), (b0, b1, "ram0"), (p0, p1, "ports")):
+            assert np.array_equal(x, y), (b, name, np.abs(x - y).max())
+        (_, _, a2, b2, p2, _, _), (_, _, a3, b3, p3, _, _) = outs[2], outs[3]
+        for x, y, name in ((a2, a3, "rom"), (b2, b3, "ram0"), (p2, p3, "ports")):
+            assert np.array_equal(x, y), (b, "read_T", name)
