@@ -137,6 +137,7 @@ def parse():
     ap.add_argument("--soft-lanes", type=int, default=0, help="lanes per env of the soft forward (0 = auto)")
     ap.add_argument("--hetero-lanes", type=int, default=0, help="lanes per env of the heterogeneous leg (0 = auto)")
     ap.add_argument("--hetero-tpb", type=int, default=256)
+    ap.add_argument("--hetero-kernel", default="grouped", help="step kernel of the heterogeneous leg")
     ap.add_argument("--hetero-calls", type=int, default=4, help="timed calls of 25 env steps")
     ap.add_argument("--hetero-warmup", type=int, default=1)
     ap.add_argument("--objects-lanes", type=int, default=0, help="lanes per env of the sprite leg (0 = auto)")
@@ -317,7 +318,8 @@ def soft_leg(args):
         "frac": achieved / VALU_PEAK_TOPS, "ops_per_env_step": ops,
         "ops_model": f"{OPS_PER_INSTRUCTION + OPS_PER_SWEEP} integer ops per emulated instruction "
                      "(forward 12, sweep 6; recomputation not counted) + 2 per returned pixel",
-        "kernel": "k_soft_bwd (dominant) and k_step<soft>",
+        "kernel": ("k_step<soft> keeping its tape (dominant) and k_soft_bwd sweeping it" if bk.get("forward_tape")
+                   else "k_soft_bwd (dominant: recompute and sweep) and k_step<soft>"),
         "k_soft_bwd": counter_fractions(fig, "k_soft_bwd", bk["ms_backward"] / 1e3),
         "k_step_soft": counter_fractions(fig, "k_step_soft", bk["ms_forward"] / 1e3),
         "timing": "HIP events on the current stream around the forward (autograd forward + loss) and the "
@@ -459,7 +461,7 @@ def main():
                                for r in t["table"]]
             log("hetero autotune", tuned["hetero"])
             hl, ht = t["lanes_per_env"], t["block_threads"]
-        result["hetero"] = hard_leg(ha, "grouped", hl, ht, w2)
+        result["hetero"] = hard_leg(ha, args.hetero_kernel, hl, ht, w2)
         result["hetero"]["instructions_per_env_step"] = instructions_per_step(w2, envs=8, steps=4,
                                                                               stride=w2.num_envs // 8)
         result["hetero"]["workload"] = ("c2_hetero_persistent: 64 ROMs (21x2K, 22x4K, 21xF8, reading SWCHA/INPT4/"
