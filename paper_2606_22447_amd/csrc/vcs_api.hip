@@ -195,7 +195,7 @@ bool tr_lds_fits(const vcs_ctx *c) {
     bool f8 = false;
     for (int32_t mp : c->rom_mapper) f8 = f8 || mp == kMapperF8;
     const size_t need = (size_t)c->max_rom * 8 + (f8 ? 2 : 1) * 4096 * 2 + E * 128 + 1024 +
-                        E * (size_t)kTrLogCap * (size_t)kTrLogEntryBytes;
+                        E * ((size_t)tr_log_cap((int)E) + 1) * (size_t)kTrLogEntryBytes + E * sizeof(TrCtl);
     return need <= kLdsBytes;
 }
 
@@ -554,8 +554,9 @@ int32_t launch_step_hard(vcs_ctx *ctx, const uint8_t *d_rom, void *d_state, cons
         if (!ctx->tr_fn || hipGetDevice(&dev) != hipSuccess || dev != ctx->tr_device) return VCS_UNSUPPORTED;
         void *args[] = {&P};
         const size_t lds = (size_t)ctx->max_rom * sizeof(uint2);
-        rc = hip_status(hipModuleLaunchKernel(ctx->tr_fn, (unsigned)ctx->main_blocks, 1, 1, (unsigned)ctx->tpb, 1, 1,
-                                              (unsigned)lds, stream, args, nullptr));
+        // the emulating waves and as many drawing waves (the returned frames)
+        rc = hip_status(hipModuleLaunchKernel(ctx->tr_fn, (unsigned)ctx->main_blocks, 1, 1, 2u * (unsigned)ctx->tpb,
+                                              1, 1, (unsigned)lds, stream, args, nullptr));
     } else {
         rc = hip_status(launch_step(P, ctx->main_blocks, ctx->G, ctx->tpb, false, plain, step_lds(ctx), stream,
                                     false));

@@ -42,6 +42,11 @@ struct DeviceWave {
         (void)__hip_atomic_fetch_add(p, t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __device__ static __forceinline__ uint32_t first(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+    // order this wave's LDS and memory accesses before the ones after it, for the
+    // other waves of the workgroup
+    __device__ static __forceinline__ void fence() { __threadfence_block(); }
+    // yield the SIMD for a short while (polling another wave of the workgroup)
+    __device__ static __forceinline__ void sleep() { __builtin_amdgcn_s_sleep(1); }
     // makes v opaque to the optimiser (no instruction): code that uses it cannot be
     // hoisted out of the loop that contains this call
     __device__ static __forceinline__ void opaque(uint32_t &v) { asm volatile("" : "+v"(v)); }
@@ -58,28 +63,46 @@ struct DeviceWave {
     }
 };
 
-// Body of the grouped step kernel: one workgroup per ROM group of E = TPB / G
-// envs, G lanes per env; the ROM image (pre-decoded words), the decode table and
-// the envs' RAM staged in LDS.  state_of(rom) gives the executor state of the
-// workgroup's ROM.
+// Staging of the grouped step kernel by the workgroup's NT threads: the ROM image
+// of the workgroup's ROM group as pre-decoded words and the decode table in LDS.
+template <int NT>
+__device__ __forceinline__ void stage_group(const StepParams &P, uint2 *rom_lds, uint32_t *dec_lds) {
+    const uint32_t tid = threadIdx.x;
+    const int32_t rom_idx = P.st.main_block_rom[blockIdx.x];
+    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
+    const int32_t mapper = P.st.rom_mapper[rom_idx];
+    for (int32_t i = (int32_t)tid; i < rom_size; i += NT)
+        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
+    for (int32_t i = (int32_t)tid; i < 256; i += NT) dec_lds[i] = kDecodeDev.e[i];
+    __syncthreads();
+}
+
+// The envs of a staged grouped step kernel: E = TPB / G envs, G lanes per env,
+// threads [0, TPB) of the workgroup; the envs' RAM in LDS.  state_of(rom) gives
+// the executor state of the workgroup's ROM.
 template <int G, int TPB, bool kSoft, class X, bool kObj = true, class StateOf>
-__device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds, uint32_t *dec_lds,
-                                           StateOf state_of) {
+__device__ __forceinline__ void run_group(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds, uint32_t *dec_lds,
+                                          StateOf state_of) {
     constexpr int E = TPB / G;
     const uint32_t tid = threadIdx.x, slot = tid / G, sub = tid % G;
     const int32_t blk = blockIdx.x;
     const int32_t rom_idx = P.st.main_block_rom[blk];
     const int32_t env = P.st.main_slot_env[blk * E + slot];
-    const int32_t rom_base = P.st.rom_off[rom_idx], rom_size = P.st.rom_size[rom_idx];
     const int32_t mapper = P.st.rom_mapper[rom_idx];
-    for (int32_t i = (int32_t)tid; i < rom_size; i += TPB)
-        rom_lds[i] = rom_word_at(P.rom + rom_base, i, mapper, kDecodeDev.e);
-    for (int32_t i = (int32_t)tid; i < 256; i += TPB) dec_lds[i] = kDecodeDev.e[i];
-    __syncthreads();
     LdsWordMem m{rom_lds, dec_lds, reinterpret_cast<uint8_t *>(ram_lds), (uint32_t)E, slot};
     // Superchip RAM: [32 words][E] in LDS after the staged image
     if (mapper_sc(mapper)) m.sc = reinterpret_cast<uint8_t *>(rom_lds + P.rom_words);
     step_env<DeviceWave, G, kSoft, false, X, kObj>(P, env, sub, mapper, m, kDecodeDev.e, state_of(rom_idx));
+}
+
+// Body of the grouped step kernel: one workgroup per ROM group of E = TPB / G
+// envs, G lanes per env; the ROM image (pre-decoded words), the decode table and
+// the envs' RAM staged in LDS.
+template <int G, int TPB, bool kSoft, class X, bool kObj = true, class StateOf>
+__device__ __forceinline__ void step_group(const StepParams &P, uint2 *rom_lds, uint32_t *ram_lds, uint32_t *dec_lds,
+                                           StateOf state_of) {
+    stage_group<TPB>(P, rom_lds, dec_lds);
+    run_group<G, TPB, kSoft, X, kObj>(P, rom_lds, ram_lds, dec_lds, state_of);
 }
 
 // Body of the FULL relaxed step kernel: the grouped kernel's layout with the

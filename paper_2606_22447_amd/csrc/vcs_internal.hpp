@@ -29,6 +29,30 @@ constexpr int kTrMaxRun = 32;
 constexpr int kTrLogCap = 2 * kTrMaxRun;
 // Bytes of one entry of that log (the effect clock and the TIA state before the write).
 constexpr int kTrLogEntryBytes = 16;
+// Entries of an env's log in translated code with E envs per workgroup: up to
+// 256, halved while the workgroup's logs exceed 64 KB (a power of two, >= kTrLogCap).
+__host__ __device__ constexpr int tr_log_cap(int E) {
+    int cap = 256;
+    while (cap > kTrLogCap && E * cap * kTrLogEntryBytes > 65536) cap /= 2;
+    return cap;
+}
+// Control block of an env's pixel-write log in translated code (in LDS).  The
+// env's emulating lanes append entries to a ring of CAP entries and publish how
+// far the entries reach; the env's drawing lanes, in a wave of their own that
+// runs beside the emulating one, turn the covered rows into pixels and release
+// the entries no later row needs.  Counters run from the start of the drawn
+// frame.
+struct TrCtl {
+    uint32_t head;   // entries appended (emulation)
+    uint32_t ready;  // rows whose pixels the appended entries determine (emulation)
+    uint32_t tail;   // first entry a row not drawn yet may need (drawing)
+    uint32_t done;   // rows drawn (drawing)
+    uint32_t state;  // 0 idle, 1 a frame is being logged, 2 its last entry is in (emulation: 0->1, 1->2; drawing: 2->0)
+    uint32_t fin;    // the env logs no more frames (emulation)
+    uint32_t beat;   // frames the env has ended (emulation): shows the drawing lanes it is alive
+    uint32_t stalls; // waits for the drawing lanes that gave up (emulation; nonzero only after a fault)
+    uint8_t *frame;  // the frame being drawn
+};
 
 // Cartridge formats (the numbering of vcs_mapper in include/vcs.h).
 constexpr int32_t kMapper2K = 0, kMapper4K = 1, kMapperF8 = 2, kMapperF6 = 3, kMapperF4 = 4, kMapperF8SC = 5,

@@ -423,10 +423,10 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     std::string s;
     s.reserve(1 << 20);
     s += "#include \"vcs_device.hpp\"\n#ifndef VCS_TR_FN\n#define VCS_TR_FN __device__ __forceinline__\n"
-         "#define VCS_TR_TABLE __device__ const\n#endif\nnamespace vcs {\nnamespace tr {\n";
-    {  // the env's pixel-write log: up to 256 entries, 64 KB of LDS per workgroup
-        int log_cap = 256;
-        while (log_cap > kTrLogCap && (TPB / G) * log_cap * kTrLogEntryBytes > 65536) log_cap /= 2;
+         "#define VCS_TR_TABLE __device__ const\n#endif\n#ifndef VCS_TR_ASYNC\n#define VCS_TR_ASYNC true\n#endif\n"
+         "namespace vcs {\nnamespace tr {\n";
+    {  // the env's pixel-write ring: up to 256 entries (+ a spare slot), about 64 KB of LDS per workgroup
+        const int log_cap = tr_log_cap(TPB / G);
         char cbuf[64];
         std::snprintf(cbuf, sizeof cbuf, "constexpr int kLogCap = %d;\n", log_cap);
         s += cbuf;
@@ -485,15 +485,16 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
     // interpreter for one instruction (one copy of it, shared by the images)
     char buf[4096];
     std::snprintf(buf, sizeof buf,
-                  "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W, %d, kLogCap>;\n", G);
+                  "struct Exec {\n  template <typename T, class W> using Hook = RenderHook<T, W, %d, kLogCap, VCS_TR_ASYNC>;\n",
+                  G);
     s += buf;
     s += ""
-         "  struct State { uint32_t rom, blk; uint4 *log; const uint16_t *tab; };\n"
+         "  struct State { uint32_t rom, blk; uint4 *log; TrCtl *ctl; const uint16_t *tab; };\n"
          "  template <class C> VCS_TR_FN static void init(C &c, State &s) {\n"
          "    s.blk = lookup(s.tab, c.bank, c.pc);\n"
          "    c.hook.log = s.log;\n"
-         "    c.hook.nlog = 0u;\n"
-         "    c.hook.row_lo = 0;\n"
+         "    c.hook.ctl = s.ctl;\n"
+         "    c.hook.head = c.hook.nlog = c.hook.pub = 0u;\n"
          "  }\n"
          "  template <class W, bool kPlain, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
@@ -528,22 +529,34 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "    }\n"
          "  }\n";
     s += "};\n}  // namespace tr\n}  // namespace vcs\n#ifndef VCS_TR_NO_KERNEL\n";
+    // The workgroup: TPB emulating threads (G lanes per env) and as many drawing
+    // threads, thread TPB + t drawing the rows of thread t's env.
     std::snprintf(buf, sizeof buf,
                   "extern \"C\" __global__ __launch_bounds__(%d) void vcs_tr_step(vcs::StepParams P) {\n"
                   "  extern __shared__ __align__(16) uint2 rom_lds[];\n"
                   "  __shared__ __align__(16) uint32_t ram_lds[32 * %d];\n"
                   "  __shared__ uint32_t dec_lds[256];\n"
-                  "  __shared__ uint4 log_lds[%d * vcs::tr::kLogCap];\n"
+                  "  __shared__ uint4 log_lds[%d * (vcs::tr::kLogCap + 1)];\n"
+                  "  __shared__ vcs::TrCtl ctl_lds[%d];\n"
                   "  __shared__ uint16_t tab_lds[%u * 4096];\n"
-                  "  uint4 *log = log_lds + (threadIdx.x / %d) * vcs::tr::kLogCap;\n"
+                  "  const bool drawer = threadIdx.x >= %du;\n"
+                  "  const uint32_t t = drawer ? threadIdx.x - %du : threadIdx.x;\n"
+                  "  uint4 *log = log_lds + (t / %d) * (vcs::tr::kLogCap + 1);\n"
+                  "  vcs::TrCtl *ctl = ctl_lds + t / %d;\n"
+                  "  if (!drawer && t %% %d == 0u) *ctl = vcs::TrCtl{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, nullptr};\n"
                   "  {\n"
                   "    const int32_t rom = P.st.main_block_rom[blockIdx.x];\n"
                   "    const uint16_t *src = vcs::tr::kTabAll + vcs::tr::kTabOff[rom];\n"
                   "    for (uint32_t i = threadIdx.x; i < vcs::tr::kTabBanks[rom] * 4096u; i += %d) tab_lds[i] = src[i];\n"
                   "  }\n"
-                  "  vcs::step_group<%d, %d, false, vcs::tr::Exec, false>(P, rom_lds, ram_lds, dec_lds,\n"
-                  "      [log](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log, tab_lds}; });\n}\n",
-                  TPB, TPB / G, TPB / G, max_banks, G, TPB, G, TPB);
+                  "  vcs::stage_group<%d>(P, rom_lds, dec_lds);\n"
+                  "  if (drawer) {\n"
+                  "    vcs::draw_loop<vcs::DeviceWave, %d, vcs::tr::kLogCap>(ctl, log, P.ystart, t %% %du);\n"
+                  "  } else {\n"
+                  "    vcs::run_group<%d, %d, false, vcs::tr::Exec, false>(P, rom_lds, ram_lds, dec_lds,\n"
+                  "        [log, ctl](int32_t r) { return vcs::tr::Exec::State{(uint32_t)r, 0u, log, ctl, tab_lds}; });\n"
+                  "  }\n}\n",
+                  2 * TPB, TPB / G, TPB / G, TPB / G, max_banks, TPB, TPB, G, G, G, 2 * TPB, 2 * TPB, G, G, G, TPB);
     s += buf;
     s += "#endif\n";
     return s;

@@ -206,18 +206,154 @@ __host__ __device__ __forceinline__ uint4 log_entry(int32_t clock, const Tia &t)
     return make_uint4((uint32_t)clock, t.col, t.pf, t.vb);
 }
 
+// Upper bound on the polls of a wait between the emulating and the drawing
+// lanes (each poll sleeps ~64 clocks, so ~60 ms) with no sign of progress from
+// the other side: a wait that long can only be a fault, and giving up keeps every
+// wave's exit reachable (the frames are then wrong, not the kernel stuck).
+constexpr uint32_t kTrSpinLimit = 1u << 21;
+__host__ __device__ __forceinline__ uint32_t ld_ctl(const uint32_t *p) { return *(const volatile uint32_t *)p; }
+__host__ __device__ __forceinline__ void st_ctl(uint32_t *p, uint32_t v) { *(volatile uint32_t *)p = v; }
+
+// Draw rows [y0, y1) of a frame from the n entries of a ring starting at entry
+// t0 (entry t0 + i at ring slot (t0 + i) mod CAP), the last of which lies past
+// the last pixel of row y1 - 1: the pixel at colour clock k shows the state of
+// the first entry with an effect clock > k (an entry holds the state before its
+// write).  Lane sub of GL takes rows y0 + sub, y0 + sub + GL, ...; a row's first
+// entry is found by bisection and the row is walked with the entry pointer, a
+// 4-pixel group at a time (one colour unless a write takes effect inside the
+// group), 16 pixels per store.
+template <int GL, int CAP>
+__host__ __device__ __forceinline__ void draw_ring_rows(uint8_t *frame, const uint4 *log, uint32_t t0, uint32_t n,
+                                                        int32_t y0, int32_t y1, int32_t ystart, uint32_t sub) {
+    constexpr uint32_t M = (uint32_t)CAP - 1u;
+    const int32_t vis0 = ystart * kClocksPerLine + kHBlank;  // clock of pixel (0, 0)
+    for (int32_t y = y0 + (int32_t)sub; y < y1; y += GL) {
+        const int32_t k_row = vis0 + y * kClocksPerLine;
+        uint32_t lo = 0, hi = n - 1u;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((int32_t)log[(t0 + mid) & M].x > k_row) hi = mid;
+            else lo = mid + 1u;
+        }
+        uint32_t p = lo;
+        uint4 e = log[(t0 + p) & M];
+        uint32_t mask = pf_mask20(e.z);
+        auto advance_past = [&](int32_t k) {  // to the first entry with clock > k
+            while ((int32_t)e.x <= k && p + 1u < n) {
+                e = log[(t0 + ++p) & M];
+                mask = pf_mask20(e.z);
+            }
+        };
+        auto colour = [&](uint32_t g) {
+            return (e.w & 2u) ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
+        };
+        uint8_t *row = frame + y * kScreenW;
+        for (int32_t q = 0; q < kScreenW / 16; ++q) {
+            uint32_t wd[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t g = (uint32_t)(4 * q + j);
+                const int32_t k0 = k_row + 4 * (int32_t)g;
+                advance_past(k0);
+                if ((int32_t)e.x > k0 + 3) {
+                    wd[j] = colour(g) * 0x01010101u;
+                } else {  // a write takes effect inside the group, at clock e.x
+                    // Effect clocks are multiples of 3, so every entry past those at
+                    // e.x lies beyond the group: the pixels before e.x show e, the
+                    // rest the first entry past e.x (writes at one clock: the last).
+                    const uint32_t c0 = colour(g);
+                    const uint32_t m = (1u << (8 * ((int32_t)e.x - k0))) - 1u;  // 1..3 bytes
+                    advance_past((int32_t)e.x);
+                    wd[j] = ((c0 * 0x01010101u) & m) | ((colour(g) * 0x01010101u) & ~m);
+                }
+            }
+            *reinterpret_cast<uint4 *>(row + 16 * q) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+        }
+    }
+}
+
+// One round of an env's drawing lanes (lane sub of GL): draw the rows the
+// emulation has published and release the entries before the first row not
+// drawn (also with no row to draw, once the ring is half full: writes before the
+// first visible row fill it with no row to show for them).  Returns whether there
+// was anything to do.
+template <class W, int GL, int CAP>
+__host__ __device__ __forceinline__ bool draw_round(TrCtl *ctl, const uint4 *log, int32_t ystart, uint32_t sub) {
+    const uint32_t st = ld_ctl(&ctl->state);
+    if (st == 0u) return false;
+    const uint32_t ready = ld_ctl(&ctl->ready);
+    W::fence();  // the entries and head published with `ready` are visible from here on
+    const uint32_t head = ld_ctl(&ctl->head), tail = ld_ctl(&ctl->tail), done = ld_ctl(&ctl->done);
+    const bool last = st == 2u && ready >= (uint32_t)kScreenH;
+    const uint32_t n = head - tail;
+    const bool rows = ready > done;
+    if (!rows && !last && n <= (uint32_t)(CAP / 2)) return false;
+    const int32_t y1 = ready < (uint32_t)kScreenH ? (int32_t)ready : kScreenH;
+    if (n > 0u && (int32_t)done < y1)
+        draw_ring_rows<GL, CAP>(ctl->frame, log, tail, n, (int32_t)done, y1, ystart, sub);
+    // the first entry past the first pixel of row y1 (earlier ones serve drawn rows only)
+    uint32_t keep = n;
+    if (y1 < kScreenH) {
+        const int32_t cut = ystart * kClocksPerLine + kHBlank + y1 * kClocksPerLine;
+        uint32_t lo = 0u;
+        while (lo < keep) {
+            const uint32_t mid = (lo + keep) >> 1;
+            if ((int32_t)log[(tail + mid) & ((uint32_t)CAP - 1u)].x > cut) keep = mid;
+            else lo = mid + 1u;
+        }
+    }
+    if (!rows && !last && keep == 0u) return false;  // nothing to release yet
+    W::fence();  // this round's reads of the ring are done before the entries are released
+    if (sub == 0u) {
+        st_ctl(&ctl->done, (uint32_t)y1);
+        st_ctl(&ctl->tail, tail + keep);
+        if (last) {
+            W::fence();
+            st_ctl(&ctl->state, 0u);
+        }
+    }
+    W::fence();
+    return true;
+}
+
+// The drawing wave of translated code: rounds for its envs until each has
+// logged its last frame and had it drawn.
+template <class W, int GL, int CAP>
+__host__ __device__ __forceinline__ void draw_loop(TrCtl *ctl, const uint4 *log, int32_t ystart, uint32_t sub) {
+    uint32_t beat = ld_ctl(&ctl->beat);
+    for (uint32_t polls = 0; polls < kTrSpinLimit;) {
+        const bool fin = ld_ctl(&ctl->fin) != 0u;
+        W::fence();
+        const bool idle = ld_ctl(&ctl->state) == 0u;
+        if (W::all(fin && idle)) break;  // (fin is set after the env's last state change)
+        const bool worked = draw_round<W, GL, CAP>(ctl, log, ystart, sub);
+        const uint32_t b = ld_ctl(&ctl->beat);
+        if (W::any(worked || b != beat)) {
+            polls = 0;
+        } else {  // idle: poll less often, leaving the SIMD and the LDS to the emulating wave
+            W::sleep();
+            W::sleep();
+            W::sleep();
+            W::sleep();
+            ++polls;
+        }
+        beat = b;
+    }
+}
+
 // Renders the returned frame lazily: before every write that changes pixels
 // the pixels up to the write's effect clock are drawn with the old state.  With
 // a wave policy W (translated code) a write only appends (effect clock, the TIA
-// state before it) to the env's log of CAP entries in LDS, a store with no
-// branch, and flush(), called between runs where lanes may branch, draws the
-// visible rows the log covers once it is nearly full: the env's GL lanes share
-// the rows out, each lane writing whole rows, and the entries of the row not yet
-// covered stay in the log.
+// state before it) to the env's ring log of CAP entries in LDS (lanes without a
+// frame write a spare slot: a store with no branch), and flush(), called between
+// runs where lanes may branch, publishes how far the entries reach once the ring
+// is half full; the drawing wave (draw_loop) turns the covered rows into pixels.
+// kAsync false (a build for the host, one lane): the hook draws the rows itself
+// at each publish.
 struct NoWave {};
-template <typename T, class W = NoWave, int GL = 1, int CAP = kTrLogCap>
+template <typename T, class W = NoWave, int GL = 1, int CAP = kTrLogCap, bool kAsync = true>
 struct RenderHook {
-    static_assert(CAP >= kTrLogCap, "the log holds a row's writes and a run's");
+    static_assert(CAP >= kTrLogCap && (CAP & (CAP - 1)) == 0, "the log holds a row's writes and a run's");
     static constexpr bool kRecord = false;
     T *frame;         // frame being rendered, or nullptr
     float *tan;       // (soft) the frame's position-sampler tangents [5][210][160], or nullptr
@@ -225,9 +361,11 @@ struct RenderHook {
     int32_t pix_cc;   // write point of the last instruction (soft checkpoints)
     int32_t ystart;
     uint32_t sub, G;
-    uint4 *log;       // (with W) the env's pixel-write log, CAP entries
-    uint32_t nlog;
-    int32_t row_lo;   // (with W) first visible row of the frame not drawn yet
+    uint4 *log;       // (with W) the env's ring of CAP entries and a spare slot
+    TrCtl *ctl;       // (with W) its control block
+    uint32_t head;    // (with W) entries appended in the drawn frame
+    uint32_t nlog;    // (with W) entries in the ring not yet released, as last seen
+    uint32_t pub;     // (with W) head when last published
     template <class C>
     __host__ __device__ __forceinline__ void before_pixel_write(C &c, int32_t w) {
         if constexpr (std::is_same<W, NoWave>::value) {
@@ -240,102 +378,85 @@ struct RenderHook {
             }
         } else if (W::any(frame != nullptr)) {  // (wave-uniform) only while some lane draws
             static_assert(!C::kObjects, "translated code runs without the object paths");
-            const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
-            log[i] = log_entry(3 * (w + 1), c.tia());
-            ++nlog;
+            const bool f = frame != nullptr;
+            log[f ? (head & (uint32_t)(CAP - 1)) : (uint32_t)CAP] = log_entry(3 * (w + 1), c.tia());
+            head += f ? 1u : 0u;
+            nlog += f ? 1u : 0u;
         }
     }
-    // (with W) Draw the visible rows [row_lo, y_hi) from log entries [0, n),
-    // whose last entry lies past the last pixel of row y_hi - 1: the pixel at
-    // colour clock k shows the state of the first entry with an effect clock
-    // > k (an entry holds the state before its write).  Lane sub takes rows
-    // row_lo + sub, row_lo + sub + GL, ...; a row's first entry is found by
-    // bisection and the row is walked with the entry pointer, a 4-pixel group
-    // at a time (one colour unless a write takes effect inside the group),
-    // 16 pixels per store.
-    __host__ __device__ __forceinline__ void draw_rows(int32_t y_hi, uint32_t n) {
-        const int32_t vis0 = ystart * kClocksPerLine + kHBlank;  // clock of pixel (0, 0)
-        for (int32_t y = row_lo + (int32_t)sub; y < y_hi; y += GL) {
-            const int32_t k_row = vis0 + y * kClocksPerLine;
-            uint32_t lo = 0, hi = n - 1u;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if ((int32_t)log[mid].x > k_row) hi = mid;
-                else lo = mid + 1u;
-            }
-            uint32_t p = lo;
-            uint4 e = log[p];
-            uint32_t mask = pf_mask20(e.z);
-            auto advance_past = [&](int32_t k) {  // to the first entry with clock > k
-                while ((int32_t)e.x <= k && p + 1u < n) {
-                    e = log[++p];
-                    mask = pf_mask20(e.z);
+    // (with W) a drawn frame starts: wait until the drawing lanes are done with the
+    // previous one, then reset the ring
+    __host__ __device__ __forceinline__ void begin_frame() {
+        if constexpr (!std::is_same<W, NoWave>::value) {
+            head = nlog = pub = 0u;
+            if (frame) {
+                uint32_t polls = 0;
+                for (; ld_ctl(&ctl->state) != 0u && polls < kTrSpinLimit; ++polls) W::sleep();
+                if (sub == 0u) {
+                    if (polls >= kTrSpinLimit) st_ctl(&ctl->stalls, ld_ctl(&ctl->stalls) + 1u);
+                    ctl->frame = reinterpret_cast<uint8_t *>(frame);
+                    st_ctl(&ctl->head, 0u);
+                    st_ctl(&ctl->ready, 0u);
+                    st_ctl(&ctl->tail, 0u);
+                    st_ctl(&ctl->done, 0u);
+                    W::fence();
+                    st_ctl(&ctl->state, 1u);
                 }
-            };
-            auto colour = [&](uint32_t g) {
-                return (e.w & 2u) ? 0u : ((e.y >> (8 * group_owner(g, mask, e.z >> 24))) & 0xFEu);
-            };
-            T *row = frame + y * kScreenW;
-            for (int32_t q = 0; q < kScreenW / 16; ++q) {
-                uint32_t wd[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t g = (uint32_t)(4 * q + j);
-                    const int32_t k0 = k_row + 4 * (int32_t)g;
-                    advance_past(k0);
-                    if ((int32_t)e.x > k0 + 3) {
-                        wd[j] = colour(g) * 0x01010101u;
-                    } else {  // a write takes effect inside the group, at clock e.x
-                        // Effect clocks are multiples of 3, so every entry past those at
-                        // e.x lies beyond the group: the pixels before e.x show e, the
-                        // rest the first entry past e.x (writes at one clock: the last).
-                        const uint32_t c0 = colour(g);
-                        const uint32_t m = (1u << (8 * ((int32_t)e.x - k0))) - 1u;  // 1..3 bytes
-                        advance_past((int32_t)e.x);
-                        wd[j] = ((c0 * 0x01010101u) & m) | ((colour(g) * 0x01010101u) & ~m);
-                    }
-                }
-                *reinterpret_cast<uint4 *>(row + 16 * q) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+                W::fence();
             }
         }
-        if (y_hi > row_lo) row_lo = y_hi;
     }
-    // (with W) Draw what the log covers once it is nearly full (some run could
-    // not fit) or `all` (frame end, where the caller has appended the state at
-    // the frame's end), then keep only the entries still needed: those past
-    // the first pixel of the first row not drawn.  A row's pixels span 160
-    // clocks and a write takes at least 9, so at most 18 entries stay.
+    // (with W) publish the entries and the rows they determine (rows whose last
+    // pixel lies before the last entry's clock; all of them at the frame's end)
+    __host__ __device__ __forceinline__ void publish(bool all) {
+        const int32_t vis0 = ystart * kClocksPerLine + kHBlank;
+        int32_t y_hi = kScreenH;
+        if (!all) {
+            const int32_t t = (int32_t)log[(head - 1u) & (uint32_t)(CAP - 1)].x - vis0 - (kScreenW - 1);
+            y_hi = t <= 0 ? 0 : (t + kClocksPerLine - 1) / kClocksPerLine;
+            y_hi = y_hi < kScreenH ? y_hi : kScreenH;
+        }
+        W::fence();  // the entries before head and ready
+        if (sub == 0u) st_ctl(&ctl->head, head);
+        W::fence();
+        if (sub == 0u) {
+            st_ctl(&ctl->ready, (uint32_t)y_hi);
+            if (all) {
+                W::fence();
+                st_ctl(&ctl->state, 2u);
+            }
+        }
+        W::fence();
+        pub = head;
+        if constexpr (!kAsync) {  // no drawing wave: draw here
+            while (draw_round<W, GL, CAP>(ctl, log, ystart, sub)) {
+            }
+        }
+    }
+    // (with W) wait until at most `room_left` entries of the ring are unreleased
+    __host__ __device__ __forceinline__ void wait_room(uint32_t limit) {
+        for (uint32_t polls = 0;; ++polls) {
+            nlog = head - ld_ctl(&ctl->tail);
+            if (W::all(!frame || nlog <= limit)) break;
+            if (polls >= kTrSpinLimit) {
+                if (frame && nlog > limit && sub == 0u) st_ctl(&ctl->stalls, ld_ctl(&ctl->stalls) + 1u);
+                break;
+            }
+            W::sleep();
+        }
+    }
+    // (with W) between runs: publish every quarter ring of entries, and make room
+    // for the next run once the ring may not hold it
     template <class C>
-    __host__ __device__ __forceinline__ void flush(C &, bool all = false) {
+    __host__ __device__ __forceinline__ void flush(C &) {
         if constexpr (!std::is_same<W, NoWave>::value) {
             static_assert(sizeof(T) == 1, "translated code returns u8 frames");
-            const uint32_t n = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP;
-            if (!frame) {
-                nlog = 0;
-            } else if (n > 0u && (all || n > (uint32_t)(CAP - kTrMaxRun))) {
-                const int32_t vis0 = ystart * kClocksPerLine + kHBlank;
-                // rows whose last pixel lies before the last entry's clock
-                const int32_t t = (int32_t)log[n - 1u].x - vis0 - (kScreenW - 1);
-                int32_t y_hi = t <= 0 ? 0 : (t + kClocksPerLine - 1) / kClocksPerLine;
-                y_hi = y_hi < kScreenH ? y_hi : kScreenH;
-                draw_rows(y_hi, n);
-                uint32_t keep0 = n;  // first entry past the first pixel of row y_hi (bisection)
-                if (y_hi < kScreenH) {
-                    const int32_t cut = vis0 + y_hi * kClocksPerLine;
-                    uint32_t lo = 0u;
-                    while (lo < keep0) {
-                        const uint32_t mid = (lo + keep0) >> 1;
-                        if ((int32_t)log[mid].x > cut) keep0 = mid;
-                        else lo = mid + 1u;
-                    }
-                }
-                // move the kept entries to the front; the env's lanes run this
-                // loop together, so every read of an iteration precedes its writes
-                for (uint32_t i = sub; i < n - keep0; i += (uint32_t)GL) {
-                    const uint4 e = log[keep0 + i];
-                    log[i] = e;
-                }
-                nlog = n - keep0;
+            const bool f = frame != nullptr;
+            const bool due = f && head - pub >= (uint32_t)(CAP / 4);
+            const bool full = f && nlog > (uint32_t)(CAP - kTrMaxRun);
+            if (W::any(due || full)) {
+                if (f && head != pub) publish(false);
+                if (W::any(full)) wait_room((uint32_t)(CAP - kTrMaxRun));
             }
         }
     }
@@ -351,14 +472,28 @@ struct RenderHook {
             if (frame) render_span<C::kObjects>(frame, rend_cc, kClocksPerFrame, c.tia(), ystart, sub, G, tan);
         } else {
             if (W::any(frame != nullptr)) {  // the rest of the frame with the current state
-                flush(c);
-                const uint32_t i = nlog < (uint32_t)CAP ? nlog : (uint32_t)CAP - 1u;
-                log[i] = log_entry(kClocksPerFrame, c.tia());
-                nlog = i + 1u;
-                flush(c, true);
+                wait_room((uint32_t)CAP - 1u);
+                const bool f = frame != nullptr;
+                log[f ? (head & (uint32_t)(CAP - 1)) : (uint32_t)CAP] = log_entry(kClocksPerFrame, c.tia());
+                head += f ? 1u : 0u;
+                if (f) publish(true);
             }
-            nlog = 0;
-            row_lo = 0;
+            head = nlog = pub = 0u;
+            if (sub == 0u) st_ctl(&ctl->beat, ld_ctl(&ctl->beat) + 1u);
+        }
+    }
+    // (with W) the env logs no more frames: the drawing lanes may stop once it is
+    // drawn.  A frame still being logged (an env stopped by the first pass of a
+    // hard step, whose outputs are void) is abandoned.
+    __host__ __device__ __forceinline__ void end_frames() {
+        if constexpr (!std::is_same<W, NoWave>::value) {
+            W::fence();
+            if (sub == 0u) {
+                if (ld_ctl(&ctl->state) == 1u) st_ctl(&ctl->state, 0u);
+                W::fence();
+                st_ctl(&ctl->fin, 1u);
+            }
+            W::fence();
         }
     }
 };
@@ -894,6 +1029,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                 else if (P.frames_mode == 1 && s_idx == S - 1) c.hook.frame = P.frame_out + (size_t)env * kPixels;
             }
         }
+        c.hook.begin_frame();
     };
     if (active) {
         set_ports();
@@ -1039,6 +1175,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
         }
         if (active) start_frame();
     }
+    c.hook.end_frames();
 
     // obj_flag: 1 for an env that needs (or ran) the object paths
     if (live && P.obj_flag && sub == 0) P.obj_flag[env] = (kObj || stopped) ? 1u : 0u;

@@ -6,6 +6,7 @@
 #define VCS_TR_FN __host__ __device__ __forceinline__
 #define VCS_TR_TABLE static const
 #define VCS_TR_NO_KERNEL
+#define VCS_TR_ASYNC false  // no drawing wave: the hook draws the published rows itself
 #include TR_SOURCE
 
 using namespace vcs;
@@ -18,6 +19,8 @@ struct OneLane {  // wave policy of a one-lane wave
     static void opaque_uniform(uint32_t &) {}
     static void accumulate(float *p, float t) { *p += t; }
     static uint32_t first(uint32_t v) { return v; }
+    static void fence() {}
+    static void sleep() {}
     static uint32_t table(const uint32_t *t, uint32_t u) { return t[u]; }
 };
 constexpr DecodeTable kHostDecode = make_decode_table();
@@ -53,9 +56,12 @@ extern "C" int host_translated(int rom_index, const uint8_t *rom, int rom_size, 
     for (int i = 0; i < rom_size; ++i) words[(size_t)i] = rom_word_at(rom, (uint32_t)i, mapper, kHostDecode.e);
     std::vector<uint32_t> ram_lds(32, 0);
     LdsWordMem m{words.data(), kHostDecode.e, reinterpret_cast<uint8_t *>(ram_lds.data()), 1u, 0u};
-    std::vector<uint4> log((size_t)tr::kLogCap);
+    std::vector<uint4> log((size_t)tr::kLogCap + 1u);
+    TrCtl ctl{0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u, nullptr};
     step_env<OneLane, 1, false, false, tr::Exec, false>(
         P, env, 0, mapper, m, kHostDecode.e,
-        tr::Exec::State{(uint32_t)rom_index, 0u, log.data(), tr::kTabAll + tr::kTabOff[rom_index]});
+        tr::Exec::State{(uint32_t)rom_index, 0u, log.data(), &ctl, tr::kTabAll + tr::kTabOff[rom_index]});
+    if (ctl.state != 0u || !ctl.fin) return -1;  // a frame left undrawn
+    if (ctl.stalls) return -2;                    // a wait for the drawing gave up
     return 0;
 }

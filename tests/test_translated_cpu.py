@@ -143,10 +143,11 @@ def test_translated_code_on_the_host_matches_the_oracle(name, tmp_path):
         fr = np.zeros((n, 210, 160), np.uint8)
         dn = np.zeros(n, np.uint8)
         flag = np.full(b + 1, 7, np.uint8)
-        H.host_translated(ri, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
-                          ptr(np.ascontiguousarray(w.ram0[b])), ptr(acts), w.steps, w.frame_skip, ptr(ep),
-                          0 if ep is None else ep.shape[1], C.c_ulonglong(w.seed), b, ptr(ram), ptr(fr), ptr(dn),
-                          ptr(flag))
+        rc = H.host_translated(ri, ptr(np.ascontiguousarray(rom.image)), rom.size, rom.mapper,
+                               ptr(np.ascontiguousarray(w.ram0[b])), ptr(acts), w.steps, w.frame_skip, ptr(ep),
+                               0 if ep is None else ep.shape[1], C.c_ulonglong(w.seed), b, ptr(ram), ptr(fr),
+                               ptr(dn), ptr(flag))
+        assert rc == 0, (name, b, {-1: "a frame left undrawn", -2: "a wait for the drawing gave up"}.get(rc, rc))
         if name == "objects":  # sprite kernels show objects: the library reruns them with the object paths
             assert flag[b] == 1, b
             continue
