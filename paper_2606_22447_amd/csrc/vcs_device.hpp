@@ -34,6 +34,14 @@ struct DeviceWave {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         return v;
     }
+    // least v over the wave's lanes (every lane gets it; every lane must take part)
+    __device__ static __forceinline__ int32_t min_i32(int32_t v) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const int32_t u = __shfl_xor(v, o, 64);
+            v = u < v ? u : v;
+        }
+        return v;
+    }
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
     __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
     // *p += t without waiting for the result (a no-return atomic add).  Only one lane

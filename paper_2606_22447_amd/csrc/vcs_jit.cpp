@@ -496,7 +496,7 @@ std::string translated_source(const uint8_t *roms, const std::vector<int32_t> &r
          "    c.hook.ctl = s.ctl;\n"
          "    c.hook.head = c.hook.nlog = c.hook.pub = 0u;\n"
          "  }\n"
-         "  template <class W, bool kPlain, class C>\n"
+         "  template <class W, bool kPlain, bool kSync = false, class C>\n"
          "  VCS_TR_FN static void run(C &c, State &s, bool go, int32_t lim, const uint32_t *decode) {\n"
          "    uint32_t fb = 0u;\n"
          "    while (go) {\n"

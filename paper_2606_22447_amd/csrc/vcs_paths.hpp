@@ -902,21 +902,44 @@ __host__ __device__ __forceinline__ void interp_one(C &c, const uint32_t *decode
     }
 }
 
+// Lanes of a wave running several envs through the interpreter that are within
+// this many CPU cycles of the wave's least advanced env run the next instruction
+// together (kSync); the others wait for it.
+constexpr int32_t kSyncWindow = 8;
+
 // Executors of the instruction loop of a frame.  The interpreter runs
 // interp_one until the lane reaches its cycle limit or jams; translated code
 // (generated per ROM image, see the translator) keeps the position of the
 // next instruction in its state and runs straight-line code from there.
+//
+// kSync (a wave of several envs): an env runs its next instruction only while
+// it is at most kSyncWindow cycles ahead of the wave's least advanced env.  Envs
+// of one image whose paths part (joystick, timer, resets) then meet again where
+// their code waits for the same clock (WSYNC, the frame's end) and go on in
+// step, one dispatch for all, instead of drifting apart into a waterfall over
+// their opcodes for the rest of the frame.  Each env still runs its own
+// instructions in order, so the results do not change.
 struct InterpExec {
     template <typename T, class W>
     using Hook = RenderHook<T>;
     struct State {};
     template <class C>
     __host__ __device__ __forceinline__ static void init(C &, State &) {}
-    template <class W, bool kPlain, class C>
+    template <class W, bool kPlain, bool kSync = false, class C>
     __host__ __device__ __forceinline__ static void run(C &c, State &, bool go, int32_t lim, const uint32_t *decode) {
-        while (go) {
-            interp_one<W, kPlain>(c, decode);
-            go = !c.jam && c.cyc < lim;
+        if constexpr (kSync) {
+            while (W::any(go)) {  // (uniform loop: every lane takes part in the reduction)
+                const int32_t least = W::min_i32(go ? c.cyc : 2147483647);
+                if (go && c.cyc <= least + kSyncWindow) {
+                    interp_one<W, kPlain>(c, decode);
+                    go = !c.jam && c.cyc < lim;
+                }
+            }
+        } else {
+            while (go) {
+                interp_one<W, kPlain>(c, decode);
+                go = !c.jam && c.cyc < lim;
+            }
         }
     }
 };
@@ -1101,7 +1124,7 @@ __host__ __device__ __forceinline__ void step_env(const StepParams &P, int32_t e
                 }
             }
             const bool go = run && c.cyc < lim;
-            X::template run<W, kPlain>(c, xs, go, lim, decode);
+            X::template run<W, kPlain, (!kPlain && G < (int)W::kWidth)>(c, xs, go, lim, decode);
             run = active && !c.jam && c.cyc < kCyclesPerFrame;
             if constexpr (!kSoft) break;
             if (!W::any(run)) break;

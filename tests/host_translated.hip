@@ -13,6 +13,7 @@ using namespace vcs;
 
 namespace {
 struct OneLane {  // wave policy of a one-lane wave
+    static constexpr uint32_t kWidth = 1;
     static bool any(bool v) { return v; }
     static bool all(bool v) { return v; }
     static void opaque(uint32_t &) {}
