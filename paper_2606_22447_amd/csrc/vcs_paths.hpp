@@ -905,7 +905,7 @@ __host__ __device__ __forceinline__ void interp_one(C &c, const uint32_t *decode
 // Lanes of a wave running several envs through the interpreter that are within
 // this many CPU cycles of the wave's least advanced env run the next instruction
 // together (kSync); the others wait for it.
-constexpr int32_t kSyncWindow = 8;
+constexpr int32_t kSyncWindow = 4;
 
 // Executors of the instruction loop of a frame.  The interpreter runs
 // interp_one until the lane reaches its cycle limit or jams; translated code
