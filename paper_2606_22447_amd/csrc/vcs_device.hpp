@@ -34,13 +34,19 @@ struct DeviceWave {
         for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
         return v;
     }
-    // least v over the wave's lanes (every lane gets it; every lane must take part)
+    // least v over the active lanes (every lane gets it): start from the first
+    // lane's value and move to the first lane below it until none is, with
+    // scalar ballots and lane reads (no LDS-pipe shuffles, whose dependent chain
+    // costs more than the step it schedules); lanes a few cycles apart take one
+    // or two rounds
     __device__ static __forceinline__ int32_t min_i32(int32_t v) {
-        for (int o = 32; o > 0; o >>= 1) {
-            const int32_t u = __shfl_xor(v, o, 64);
-            v = u < v ? u : v;
+        int32_t m = __builtin_amdgcn_readfirstlane(v);
+        for (;;) {
+            const uint64_t lower = __ballot(v < m);
+            if (lower == 0u) break;
+            m = __builtin_amdgcn_readlane(v, (int)__builtin_ctzll(lower));
         }
-        return v;
+        return m;
     }
     __device__ static __forceinline__ bool any(bool v) { return __ballot(v) != 0; }
     __device__ static __forceinline__ bool all(bool v) { return __ballot(v) == __ballot(true); }
