@@ -113,7 +113,9 @@ typedef struct vcs_config {
                                    0 = auto) */
     int32_t block_threads;      /* threads per workgroup: 64, 256, or 1024 (GROUPED with 64 lanes per
                                    env only); 0 = 1024 for GROUPED with 64 lanes per env, else 256;
-                                   TRANSLATED: block_threads / lanes_per_env <= 64 */
+                                   TRANSLATED: block_threads / lanes_per_env <= 64, and the
+                                   workgroup runs as many drawing threads besides, which turn
+                                   the logged pixel-register writes into the returned frames */
     int32_t tape_records;       /* soft forward's tape, 16-byte records per env kept in the residual:
                                    0 = none (the backward recomputes every checkpoint segment);
                                    n > 0 = up to n records; -1 = as many as S steps can need
